@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of S_N source iteration with heterogeneous DSA on one MI355X.
+
+Workload (default): 2D 256 x 256 Q1-DG, level-symmetric S8 (40 directions),
+16 x 16-cell tiles seeded void / thin / thick 20 / 50 / 30 %, vacuum
+boundaries, q = 1 on thin tiles; thick threshold eta = 1 (19,712 thick cells).
+
+A step is one source iteration through the C ABI: transport sweep of all 40
+directions, FP64 scalar-flux moment, residual, heterogeneous DSA (SIP on the
+thick cells, block-Jacobi PCG to 1e-4) and update.  K steps are timed from
+phi = 0 after W warm-up steps.  `value` is the grind time of one whole step in
+ns per (cell x direction), FP64 sweep.  Also reported: the same for the FP32
+sweep form, sweep-only grind times, time to a 1e-8 residual for both forms,
+the FP32 form's error against the FP64 forms and the CPU oracle, the sweep
+kernel's roofline fraction (HIP events on the library's stream), the CPU
+oracle's time on the same workload, and the 3D 128^3 S12 sweep grind time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sweep grind time ns/(cell·dir) + time-to-1e-8, FP32 vs FP64 sweep, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes_per_call(nc, ndirs, nn, s):
+    """Algorithmic bytes of the sweep kernels of one sweep: psi written once
+    (nc*ndirs*nn*s) plus the per-cell inputs read once (nn source values and
+    sigma_t in the sweep precision)."""
+    return nc * ndirs * nn * s + nc * (nn + 1) * s
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary in
+    profiles/ was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2001_09196_amd", "csrc", "sweep.hip")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        ent = data.get(kernel_key)
+        if not ent:
+            return None
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if ent.get("sweep_hip_sha256") != h:
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 S12 sweep measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import (SN_FP32, SN_FP64, Context, sn_source_iterate, sn_sweep)
+    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = sninputs.config("c2")
+    nc, D, nn = p.ncells, p.ndirs, p.nn
+    cd = nc * D
+    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
+    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
+    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
+    ctx = Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta)
+    log(f"c2: {nc} cells x {D} dirs, {ctx.thick_count} thick cells")
+
+    def run_steps(k, prec, timing=False):
+        phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+        if timing:
+            sn_set_kernel_timing(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=1e-4,
+                              cg_maxit=1000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = None
+        if timing:
+            kt = sn_kernel_timing(ctx)
+            sn_set_kernel_timing(ctx, False)
+        return (t1 - t0), r, kt
+
+    # ---- timed steps, FP64 sweep (the reported value) ----
+    run_steps(max(args.warmup, 1), SN_FP64)
+    dt64, r64, kt64 = run_steps(args.steps, SN_FP64, timing=True)
+    ms_step = dt64 / args.steps * 1e3
+    value = ms_step * 1e6 / cd
+    log(f"fp64 step: {ms_step:.3f} ms = {value:.5f} ns/(cell*dir); CG its {r64['cg_hist'].tolist()}")
+    # ---- same for the FP32 sweep form ----
+    run_steps(max(args.warmup, 1), SN_FP32)
+    dt32, r32, kt32 = run_steps(args.steps, SN_FP32, timing=True)
+    ms_step32 = dt32 / args.steps * 1e3
+    log(f"fp32 step: {ms_step32:.3f} ms")
+
+    # ---- sweep-only grind time (event-timed sweep kernels) ----
+    phi0 = torch.rand((nc, nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
+    grind = {}
+    sweep_ms = {}
+    for name, prec, dt in (("fp64", SN_FP64, torch.float64), ("fp32", SN_FP32, torch.float32)):
+        psi = torch.empty((nc, D, nn), dtype=dt, device=dev)
+        for _ in range(3):
+            sn_sweep(ctx, phi0, q, None, False, prec, psi)
+        reps = 20
+        sn_set_kernel_timing(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sn_sweep(ctx, phi0, q, None, False, prec, psi)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = sn_kernel_timing(ctx)
+        sn_set_kernel_timing(ctx, False)
+        sweep_ms[name] = kt["sweep_ms"] / kt["sweep_count"]
+        grind[name] = {"sweep_kernel_ns": sweep_ms[name] * 1e6 / cd,
+                       "sn_sweep_call_ns": (t1 - t0) / reps * 1e9 / cd}
+        del psi
+        log(f"sweep {name}: kernel {sweep_ms[name]*1e3:.1f} us, grind {grind[name]['sweep_kernel_ns']:.5f} ns")
+
+    # ---- time to 1e-8 ----
+    def solve(prec, tol=1e-8):
+        best = None
+        for _ in range(3):
+            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sn_source_iterate(ctx, q, None, phi, tol=tol, max_it=2000, use_dsa=True, prec=prec, cg_rtol=1e-4,
+                                  cg_maxit=1000)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if best is None or t < best[0]:
+                best = (t, r, phi.clone())
+        return best
+
+    t64, s64, phi64 = solve(SN_FP64)
+    t32, s32, phi32 = solve(SN_FP32)
+    err32_vs64 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
+    log(f"time to 1e-8: fp64 {t64*1e3:.1f} ms ({s64['iters']} it, rc {s64['rc']}), "
+        f"fp32 {t32*1e3:.1f} ms ({s32['iters']} it, rc {s32['rc']}), fp32 vs fp64 {err32_vs64:.2e}")
+
+    # ---- roofline of the dominant kernel (per step) ----
+    sweep_per_step = kt64["sweep_ms"] / max(kt64["sweep_count"], 1)
+    dsa_per_step = kt64["dsa_ms"] / max(kt64["dsa_count"], 1)
+    bytes_sweep = sweep_bytes_per_call(nc, D, nn, 8)
+    roofline = {"kernel": "sweep2d_kernel<double> (one launch per sweep)", "bound": "hbm",
+                "achieved": bytes_sweep / (sweep_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "algorithmic_bytes_per_launch": bytes_sweep, "avg_launch_ms": sweep_per_step,
+                "traffic": traffic_from_profiles("sweep2d_fp64_c2")}
+    roofline["frac"] = roofline["achieved"] / roofline["peak"]
+    log(f"per step: sweep {sweep_per_step:.3f} ms, dsa {dsa_per_step:.3f} ms of {ms_step:.3f} ms")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ns/(cell*dir)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: 2D 256x256 Q1 upwind-DG, S8 (40 dirs), seeded 16x16 tiles void/thin/thick "
+                               "20/50/30%, vacuum; one step = sweep + FP64 moment + residual + thick-only DSA "
+                               "(SIP, block-Jacobi PCG rtol 1e-4) + update",
+                   "cells": nc, "dirs": D, "thick_cells": ctx.thick_count, "eta": p.eta},
+        "roofline": roofline,
+        "step_breakdown_ms": {"sweep": sweep_per_step, "dsa": dsa_per_step,
+                              "cg_iters_per_dsa": float(np.mean(r64["cg_hist"]))},
+        "fp32_form": {"ms_per_step": ms_step32, "value": ms_step32 * 1e6 / cd, "dtype": "f32 sweep, f64 moment/DSA",
+                      "speedup_vs_fp64_step": ms_step / ms_step32},
+        "sweep_grind_ns": grind,
+        "time_to_1e-8": {"fp64": {"seconds": t64, "iters": s64["iters"], "rc": s64["rc"],
+                                  "cg_iters_total": int(np.sum(s64["cg_hist"]))},
+                         "fp32": {"seconds": t32, "iters": s32["iters"], "rc": s32["rc"],
+                                  "cg_iters_total": int(np.sum(s32["cg_hist"]))},
+                         "fp32_speedup": t64 / t32, "fp32_vs_fp64_rel_l2": err32_vs64},
+    }
+    del ctx
+
+    # ---- 3D: 128^3, S12 (168 dirs) sweep grind time and HBM fraction ----
+    if not args.no_3d:
+        try:
+            out["sweep3d_c5"] = bench_3d(log)
+        except Exception as e:  # report, do not hide
+            out["sweep3d_c5"] = {"error": repr(e)}
+
+    # ---- CPU oracle on the same workload (bounded: one solve to 1e-8) ----
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = oracle.num_threads()
+        t0 = time.perf_counter()
+        ro = oracle.source_iterate(p, tol=1e-8, max_it=2000, use_dsa=True, cg_rtol=1e-4)
+        tcpu = time.perf_counter() - t0
+        its = ro["iters"]
+        ref = torch.tensor(ro["phi"], dtype=torch.float64, device=dev)
+        e64 = float(torch.linalg.norm(phi64 - ref) / torch.linalg.norm(ref))
+        e32 = float(torch.linalg.norm(phi32 - ref) / torch.linalg.norm(ref))
+        out["cpu_baseline"] = {"value": tcpu / its * 1e9 / cd, "unit": "ns/(cell*dir)", "cores": nth,
+                               "kind": "oracle",
+                               "sample": f"c2 solve to 1e-8 from phi=0: {its} source iterations "
+                                         f"(+1 sweep for ||b||) in {tcpu:.2f} s; value = time per iteration",
+                               "time_to_1e-8_s": tcpu}
+        out["time_to_1e-8"]["fp64_vs_oracle_rel_l2"] = e64
+        out["time_to_1e-8"]["fp32_vs_oracle_rel_l2"] = e32
+        log(f"oracle: {tcpu:.2f} s for {its} iterations on {nth} threads; gpu fp64 err {e64:.2e}, fp32 {e32:.2e}")
+    print(json.dumps(out), flush=True)
+
+
+def bench_3d(log):
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_sweep
+    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
+    dev = torch.device("cuda:0")
+    p = sninputs.config("c5")
+    nc, D, nn = p.ncells, p.ndirs, p.nn
+    cd = nc * D
+    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
+    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
+    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
+    phi0 = torch.rand((nc, nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
+    res = {"workload": "c5: 3D 128^3 Q1-DG, S12 (168 dirs), seeded 16^3 tiles", "cells": nc, "dirs": D}
+    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
+        for name, prec, dt, s in (("fp32", SN_FP32, torch.float32, 4), ("fp64", SN_FP64, torch.float64, 8)):
+            psi = torch.empty((nc, D, nn), dtype=dt, device=dev)
+            sn_sweep(ctx, phi0, q, None, False, prec, psi)
+            reps = 5
+            sn_set_kernel_timing(ctx, True)
+            for _ in range(reps):
+                sn_sweep(ctx, phi0, q, None, False, prec, psi)
+            kt = sn_kernel_timing(ctx)
+            sn_set_kernel_timing(ctx, False)
+            ms = kt["sweep_ms"] / kt["sweep_count"]
+            b = sweep_bytes_per_call(nc, D, nn, s)
+            res[name] = {"sweep_ms": ms, "grind_ns": ms * 1e6 / cd, "algorithmic_bytes": b,
+                         "achieved_GBs": b / (ms * 1e-3) / 1e9, "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            log(f"c5 sweep {name}: {ms:.3f} ms, grind {ms*1e6/cd:.5f} ns, {res[name]['achieved_GBs']:.0f} GB/s")
+            del psi
+            torch.cuda.empty_cache()
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * sn.h -- C ABI of the MI355X (gfx950) library for discrete-ordinates (S_N)
+ * source iteration with heterogeneous, thick-only diffusion synthetic
+ * acceleration, on uniform Cartesian grids with a Q1 upwind-DG discretisation.
+ *
+ * Problem (Section 1, eq. eq and eq. sntransport of the paper): steady,
+ * mono-energetic transport with isotropic scattering,
+ *     Omega_d . grad psi_d + sigma_t psi_d = sigma_s / (4 pi) phi + q / (4 pi),
+ *     phi = sum_d w_d psi_d,  sum_d w_d = 4 pi,
+ * with psi_d prescribed on the inflow boundary (vacuum when not given).
+ * Discretisation (Section 4.1, eq. Tmat1 at eps = 1): Q1 Lagrange basis on the
+ * cell corners, exact integrals, upwind face coupling.
+ *
+ * Data layout (all arrays are caller-owned; "device" means GPU memory
+ * reachable from the context's device, e.g. a torch tensor's data pointer):
+ *   cell c = (k*ny + j)*nx + i (x fastest); nodes per cell nn = 4 (2D) or 8
+ *   (3D), node n = a + 2b + 4c with a/b/c the low (0) or high (1) corner along
+ *   x/y/z.
+ *   sigma_t, sigma_s, q : [ncells]            FP64, per-cell constants;
+ *                          q is a total isotropic source density.
+ *   phi                 : [ncells][nn]        FP64 nodal scalar flux.
+ *   psi                 : [ncells][ndirs][nn] FP64 or FP32 (sn_precision).
+ *   inflow              : [ndirs][nbf]        FP64, nbf = sn_inflow_size();
+ *     per direction the upwind x face (x = 0 if mu > 0, else x = nx*hx), then
+ *     the upwind y face, then (3D) the upwind z face; node order inside a face:
+ *     x face ((k*ny + j)*F + b + 2c), y face ((k*nx + i)*F + a + 2c),
+ *     z face ((j*nx + i)*4 + a + 2b), F = 2 (2D) or 4 (3D).
+ *   Directions are given by the caller (host arrays); a 2D problem ignores
+ *   the third component.  No direction component may be zero.
+ *
+ * Streams: every entry point enqueues its work on the context's HIP stream
+ * and, except where stated, returns without waiting for it.  One context per
+ * stream; contexts are not thread-safe.
+ *
+ * Errors: every int-returning entry point returns one of the SN_* codes; the
+ * message of the last error on the calling thread is in sn_last_error().
+ * Device buffers are never freed or resized by the library.
+ */
+#ifndef SN_H
+#define SN_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SN_OK = 0,
+    SN_ERR_INVALID = 1,        /* bad argument: null, size, non-finite, sigma < 0, sigma_s > sigma_t */
+    SN_ERR_UNSUPPORTED = 2,    /* valid but not implemented (e.g. a zero direction component) */
+    SN_ERR_NOMEM = 3,          /* device allocation failed */
+    SN_ERR_HIP = 4,            /* a HIP runtime call failed */
+    SN_ERR_NOT_CONVERGED = 5,  /* iteration limit reached; outputs hold the last iterate */
+    SN_ERR_DIVERGED = 6,       /* residual non-finite or above 1e6 x the first residual */
+    SN_ERR_CG_BREAKDOWN = 7    /* p^T D p <= 0 in the diffusion CG */
+};
+
+typedef enum { SN_FP64 = 0, SN_FP32 = 1 } sn_precision;
+
+typedef struct {
+    int dim;                   /* 2 or 3 */
+    int nx, ny, nz;            /* cells per axis; nz = 1 in 2D */
+    double hx, hy, hz;         /* cell widths; hz ignored in 2D */
+} sn_mesh;
+
+typedef struct {
+    int ndirs;
+    const double *omega;       /* host [ndirs][3], unit vectors */
+    const double *w;           /* host [ndirs], positive, sum 4 pi */
+} sn_quad;
+
+typedef struct sn_context sn_context;
+
+/* Create a context for one mesh, quadrature and set of cross sections.
+ * sigma_t, sigma_s: device [ncells] FP64 (copied; the caller may free them
+ * afterwards).  eta: thick threshold, a cell is thick iff sigma_s >= eta
+ * (Section 3.3; the paper uses eta = 1).  Builds the thick-cell list and the
+ * diffusion preconditioner on the GPU.  stream: a hipStream_t (NULL = default
+ * stream).  Synchronises the stream before returning.
+ * Errors: INVALID (bad sizes, sigma_s > sigma_t, negative or non-finite
+ * sigma, weights not summing to 4 pi within 1e-12), UNSUPPORTED (a direction
+ * with a zero component, grid above 1023 tiles per axis), NOMEM, HIP. */
+int sn_context_create(const sn_mesh *mesh, const sn_quad *quad, const double *sigma_t, const double *sigma_s,
+                      double eta, void *stream, sn_context **out);
+
+/* Free the context and its device workspace (waits for its stream). */
+void sn_context_destroy(sn_context *ctx);
+
+/* Number of boundary-face nodes per direction in the inflow layout. */
+long sn_inflow_size(const sn_mesh *mesh);
+
+/* Number of thick cells of the context. */
+int sn_thick_count(const sn_context *ctx);
+
+/* Transport sweep, Section 2.2 eq. psi: for every direction d,
+ *   psi_d = L_d^{-1} ( M (sigma_s phi + q) / 4pi + inflow load )   (transpose = 0)
+ *   psi_d = L_d^{-T} ( same volume load + boundary load )          (transpose = 1).
+ * L_d^T = L_{-d} on this discretisation, so the transposed sweep visits the
+ * cells from the downwind corner; in that mode `inflow` holds the data on the
+ * faces with Omega_d . n > 0, laid out as the inflow of the reversed direction.
+ * phi: device [ncells][nn] or NULL (zero); q: device [ncells] or NULL (zero);
+ * inflow: device [ndirs][nbf] or NULL (vacuum); psi: device output
+ * [ncells][ndirs][nn], FP64 or FP32 per prec (FP32: the local solves and psi
+ * are FP32; the source is formed in FP64 and rounded once). */
+int sn_sweep(sn_context *ctx, const double *phi, const double *q, const double *inflow, int transpose,
+             sn_precision prec, void *psi);
+
+/* Scalar-flux moment, eq. phi: phi_out = sum_d w_d psi_d, accumulated in FP64.
+ * psi: device [ncells][ndirs][nn] in prec; phi_out: device [ncells][nn]. */
+int sn_scalar_flux(sn_context *ctx, const void *psi, sn_precision prec, double *phi_out);
+
+typedef struct {
+    double cg_rtol;            /* stop when ||r|| <= cg_rtol ||b|| (zero initial guess) */
+    int cg_maxit;              /* iteration cap (SN_ERR_NOT_CONVERGED is not raised for it) */
+    int mass_kind;             /* 0: Sigma_f = mass of sigma_s; 1: mass of sigma_t (Sec. 2.2) */
+} sn_dsa_opts;
+
+typedef struct {
+    int cg_iters;              /* CG iterations of this call */
+    double cg_relres;          /* final ||r|| / ||b|| */
+    int n_thick_cells;
+} sn_dsa_stats;
+
+/* Heterogeneous DSA, Alg. 2 applied to the source-iteration residual:
+ *   phi_out = phi_si + P_T D_ff^{-1} Sigma_f R_T (phi_si - phi_old),
+ * D_ff the SIP diffusion operator (eq. SIP) on the thick DOFs only (principal
+ * submatrix, Section 4.2), solved by block-Jacobi preconditioned CG in FP64.
+ * Thin and void DOFs: phi_out = phi_si.  All three arrays device
+ * [ncells][nn]; phi_out may alias phi_si.  stats (host, may be NULL) is filled
+ * after a stream synchronisation.  Returns CG_BREAKDOWN if p^T D p <= 0. */
+int sn_dsa_thick_correct(sn_context *ctx, const double *phi_old, const double *phi_si, double *phi_out,
+                         const sn_dsa_opts *opts, sn_dsa_stats *stats);
+
+typedef struct {
+    double tol;                /* stop when ||phi_SI - phi|| / ||b|| <= tol, b = sweep of q from phi = 0 */
+    int max_it;
+    int use_dsa;
+    sn_precision prec;         /* precision of the sweep; moment, residual and DSA are FP64.  With
+                                  SN_FP32, iterations after the first sweep the increment
+                                  sigma_s (phi_i - phi_{i-1}) and add its FP64 moment to phi_SI;
+                                  when that residual first meets tol, phi_SI is recomputed by one
+                                  FP64 sweep and the iteration stops only if the exact residual
+                                  meets tol as well (FP64 psi workspace allocated on demand) */
+    sn_dsa_opts dsa;
+    int transpose;             /* 1: adjoint iteration with L_d^{-T} sweeps */
+    double *phi_ckpt;          /* device [max_it][ncells][nn] or NULL: phi after every iteration */
+} sn_iter_opts;
+
+typedef struct {
+    int iters;
+    double *res_hist;          /* host [max_it] or NULL: relative residual per iteration */
+    int *cg_hist;              /* host [max_it] or NULL: CG iterations per iteration */
+    double seconds;            /* wall time of the call */
+    int fp64_checks;           /* FP32 form: number of FP64 verification sweeps */
+} sn_iter_stats;
+
+/* Source iteration with optional heterogeneous DSA (eq. DSA_fp):
+ *   phi_SI = sum_d w_d L_d^{-1}( M (sigma_s phi + q)/4pi + inflow load ),
+ *   stop test on ||phi_SI - phi|| / ||b|| before the DSA step,
+ *   phi <- phi_SI + P_T D_ff^{-1} Sigma_f R_T (phi_SI - phi)   (or phi <- phi_SI).
+ * q: device [ncells] or NULL; inflow: device [ndirs][nbf] or NULL;
+ * phi_inout: device [ncells][nn], initial guess in, last iterate out.
+ * Synchronises once per iteration (the residual is read on the host).
+ * Returns OK, NOT_CONVERGED, DIVERGED or CG_BREAKDOWN (phi_inout holds the
+ * last iterate in all three error cases). */
+int sn_source_iterate(sn_context *ctx, const double *q, const double *inflow, double *phi_inout,
+                      const sn_iter_opts *opts, sn_iter_stats *stats);
+
+/* Adjoint gradient contraction (derived from the block system, eq. system):
+ *   g_t[c] = -sigma_t,c sum_d w_d psi_adj_d,c^T M_c psi_d,c       (d J / d log sigma_t,c)
+ *   g_s[c] =  sigma_s,c chi_c^T M_c phi_c / 4pi                    (d J / d log sigma_s,c)
+ * for a response J whose adjoint angular flux psi_adj_d = L_d^{-T}(...) comes
+ * from a transposed sweep at the converged adjoint flux chi.  psi, psi_adj:
+ * device [ncells][ndirs][nn] in prec; phi, chi: device [ncells][nn];
+ * g_t, g_s: device [ncells] FP64 outputs. */
+int sn_gradient(sn_context *ctx, const void *psi, const void *psi_adj, sn_precision prec, const double *phi,
+                const double *chi, double *g_t, double *g_s);
+
+/* Kernel timing for measurement.  When enabled, every subsequent call records
+ * HIP events on the context's stream around the sweep kernels of each sweep
+ * (excluding the source and face-initialisation kernels) and around each DSA
+ * solve.  sn_kernel_timing waits for the stream, returns the summed
+ * durations (ms) and counts since the last query or enable, and resets them.
+ * Enabling or disabling synchronises the stream. */
+int sn_set_kernel_timing(sn_context *ctx, int enable);
+int sn_kernel_timing(sn_context *ctx, double *sweep_ms, int *sweep_count, double *dsa_ms, int *dsa_count);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *sn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SN_H */

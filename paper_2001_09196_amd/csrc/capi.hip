@@ -1,0 +1,651 @@
+// C ABI (include/sn.h): context management, argument validation and the
+// host-side control of source iteration.  Every arithmetic step of the path
+// runs in the kernels of sweep.hip, flux.hip and dsa.hip; the host only
+// launches them, reads the residual scalars once per iteration and the CG
+// status once per batch of CG iterations.
+#include <chrono>
+#include <cstdarg>
+#include <memory>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sn.h"
+#include "sn_kernels.hpp"
+
+using namespace sn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return fail(SN_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // grows only; returns 0 or an SN error code
+    int ensure(size_t count) {
+        if (count <= n && p) return 0;
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(SN_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+        }
+        n = count;
+        return 0;
+    }
+};
+
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+struct sn_context {
+    sn_mesh mesh{};
+    int nn = 4;
+    long nc = 0;
+    int ndirs = 0;
+    long nbf = 0;
+    double eta = 1.0;
+    hipStream_t stream = nullptr;
+    std::vector<DirInfo> hdirs;
+    std::vector<double> hw;
+    DevBuf<DirInfo> dirs;
+    DevBuf<double> w, sigt, sigs;
+    DevBuf<float> sigt32;
+    // thick set and diffusion preconditioner
+    int nthick = 0;
+    DevBuf<int> flags, blocksums, total, slot, thick;
+    DevBuf<double> binv;
+    DsaGeom dg{};
+    int nparts = 1;
+    DevBuf<double> cx, cr, cz, cp, cq, parta, partb;
+    DevBuf<CgScalars> scal;
+    int cg_hint = 8;
+    // sweep
+    SweepGeom sg{};
+    DevBuf<int> tiles;
+    std::vector<int> plane_off;
+    DevBuf<double> xf64, yf64, zf64, src64, sink64;
+    DevBuf<float> xf32, yf32, zf32, src32, sink32;
+    // source iteration workspace
+    DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3;
+    DevBuf<float> psi32;
+    int nrpart = 1;
+    // optional event timing of the sweep kernels and of the DSA solves
+    int timing = 0;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<std::pair<size_t, size_t>> sweep_ev, dsa_ev;
+};
+
+namespace {
+
+// next event of the pool, recorded on the context stream (nullptr if disabled)
+int record_event(sn_context* ctx, size_t* idx) {
+    if (ctx->evused == ctx->evpool.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->evpool.push_back(e);
+    }
+    *idx = ctx->evused++;
+    HIPCHK(hipEventRecord(ctx->evpool[*idx], ctx->stream));
+    return 0;
+}
+
+int check_mesh(const sn_mesh* m) {
+    if (!m) return fail(SN_ERR_INVALID, "mesh is NULL");
+    if (m->dim != 2 && m->dim != 3) return fail(SN_ERR_INVALID, "dim must be 2 or 3 (got %d)", m->dim);
+    if (m->nx <= 0 || m->ny <= 0 || m->nz <= 0) return fail(SN_ERR_INVALID, "cell counts must be positive");
+    if (m->dim == 2 && m->nz != 1) return fail(SN_ERR_INVALID, "2D mesh needs nz = 1");
+    if (!(m->hx > 0) || !(m->hy > 0) || (m->dim == 3 && !(m->hz > 0)) || !std::isfinite(m->hx) ||
+        !std::isfinite(m->hy) || !std::isfinite(m->hz))
+        return fail(SN_ERR_INVALID, "cell widths must be positive and finite");
+    long nc = (long)m->nx * m->ny * m->nz;
+    if (nc > (1L << 31) - 1) return fail(SN_ERR_UNSUPPORTED, "more than 2^31 - 1 cells");
+    return 0;
+}
+
+long inflow_size(const sn_mesh* m) {
+    if (m->dim == 2) return 2L * m->ny + 2L * m->nx;
+    return 4L * ((long)m->ny * m->nz + (long)m->nx * m->nz + (long)m->nx * m->ny);
+}
+
+template <typename T>
+int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
+               int transpose, T* psi, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, DevBuf<T>& sink,
+               const T* sigt) {
+    const SweepGeom& g = ctx->sg;
+    int rc;
+    if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
+    if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
+    if ((rc = zf.ensure((size_t)std::max<long>(g.zstride, 1) * g.ndirs))) return rc;
+    if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
+    if ((rc = sink.ensure((size_t)sink_elems(g)))) return rc;
+    HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
+    HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    size_t e0 = 0, e1 = 0;
+    if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
+                           ctx->plane_off.data(), psi, sink.p, ctx->stream));
+    if (ctx->timing) {
+        if ((rc = record_event(ctx, &e1))) return rc;
+        ctx->sweep_ev.emplace_back(e0, e1);
+    }
+    return 0;
+}
+
+// psi = L^{-1} or L^{-T} of the load of (sigma_s (phi - phi_prev) + q)/4pi plus the inflow
+int do_sweep(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
+             int transpose, sn_precision prec, void* psi) {
+    if (prec == SN_FP64)
+        return sweep_impl<double>(ctx, phi, phi_prev, q, inflow, transpose, (double*)psi, ctx->xf64, ctx->yf64,
+                                  ctx->zf64, ctx->src64, ctx->sink64, ctx->sigt.p);
+    return sweep_impl<float>(ctx, phi, phi_prev, q, inflow, transpose, (float*)psi, ctx->xf32, ctx->yf32, ctx->zf32,
+                             ctx->src32, ctx->sink32, ctx->sigt32.p);
+}
+
+int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, int accumulate = 0) {
+    if (prec == SN_FP64)
+        HIPCHK(launch_moment<double>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, (const double*)psi, phi, accumulate,
+                                     ctx->stream));
+    else
+        HIPCHK(launch_moment<float>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, (const float*)psi, phi, accumulate,
+                                    ctx->stream));
+    return 0;
+}
+
+// phi_out = phi_si + P_T delta; returns an SN code; fills stats
+int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
+           sn_dsa_stats* stats) {
+    const long n = ctx->nc * ctx->nn;
+    if (ctx->nthick == 0) {
+        if (phi_out != phi_si)
+            HIPCHK(hipMemcpyAsync(phi_out, phi_si, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        if (stats) {
+            stats->cg_iters = 0;
+            stats->cg_relres = 0.0;
+            stats->n_thick_cells = 0;
+        }
+        return 0;
+    }
+    const DsaGeom& g = ctx->dg;
+    size_t e0 = 0, e1 = 0;
+    int rc;
+    if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
+                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, ctx->stream));
+    HIPCHK(launch_cg_init(ctx->nparts, ctx->partb.p, ctx->scal.p, o->cg_rtol, ctx->stream));
+    CgScalars hs{};
+    int it = 0;
+    int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit));
+    while (true) {
+        int nb = std::min(batch, o->cg_maxit - it);
+        for (int b = 0; b < nb; ++b)
+            HIPCHK(launch_cg_iteration(g, ctx->thick.p, ctx->slot.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cx.p,
+                                       ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cq.p, ctx->parta.p, ctx->partb.p,
+                                       ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b, ctx->stream));
+        it += nb;
+        HIPCHK(hipMemcpyAsync(&hs, ctx->scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (hs.done || it >= o->cg_maxit) break;
+        batch = 4;
+    }
+    HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+    if (ctx->timing) {
+        if ((rc = record_event(ctx, &e1))) return rc;
+        ctx->dsa_ev.emplace_back(e0, e1);
+    }
+    ctx->cg_hint = hs.iters;
+    if (stats) {
+        stats->cg_iters = hs.iters;
+        stats->cg_relres = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : 0.0;
+        stats->n_thick_cells = ctx->nthick;
+    }
+    if (hs.breakdown) return fail(SN_ERR_CG_BREAKDOWN, "diffusion CG breakdown (p^T D p <= 0)");
+    return 0;
+}
+
+int residual3(sn_context* ctx, const double* a, const double* b, double out[3]) {
+    const long n = ctx->nc * ctx->nn;
+    HIPCHK(launch_residual(n, a, b, ctx->rpart.p, ctx->nrpart, ctx->res3.p, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sn_last_error(void) { return g_err.c_str(); }
+
+long sn_inflow_size(const sn_mesh* mesh) {
+    if (check_mesh(mesh)) return -1;
+    return inflow_size(mesh);
+}
+
+int sn_thick_count(const sn_context* ctx) { return ctx ? ctx->nthick : -1; }
+
+void sn_context_destroy(sn_context* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+    ctx->evpool.clear();
+    ctx->dirs.release();
+    ctx->w.release();
+    ctx->sigt.release();
+    ctx->sigs.release();
+    ctx->sigt32.release();
+    ctx->flags.release();
+    ctx->blocksums.release();
+    ctx->total.release();
+    ctx->slot.release();
+    ctx->thick.release();
+    ctx->binv.release();
+    ctx->cx.release();
+    ctx->cr.release();
+    ctx->cz.release();
+    ctx->cp.release();
+    ctx->cq.release();
+    ctx->parta.release();
+    ctx->partb.release();
+    ctx->scal.release();
+    ctx->tiles.release();
+    ctx->xf64.release();
+    ctx->yf64.release();
+    ctx->zf64.release();
+    ctx->src64.release();
+    ctx->sink64.release();
+    ctx->sink32.release();
+    ctx->xf32.release();
+    ctx->yf32.release();
+    ctx->zf32.release();
+    ctx->src32.release();
+    ctx->psi64.release();
+    ctx->psi32.release();
+    ctx->phisi.release();
+    ctx->phitmp.release();
+    ctx->phiprev.release();
+    ctx->rpart.release();
+    ctx->res3.release();
+    delete ctx;
+}
+
+int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* sigma_t, const double* sigma_s,
+                      double eta, void* stream, sn_context** out) {
+    g_err.clear();
+    if (!out) return fail(SN_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if (!quad || quad->ndirs <= 0 || !quad->omega || !quad->w)
+        return fail(SN_ERR_INVALID, "quadrature missing or empty");
+    if (!sigma_t || !sigma_s) return fail(SN_ERR_INVALID, "sigma_t / sigma_s is NULL");
+    if (std::isnan(eta)) return fail(SN_ERR_INVALID, "eta is NaN");
+    const int dim = mesh->dim;
+    double wsum = 0.0;
+    for (int d = 0; d < quad->ndirs; ++d) {
+        const double* o = quad->omega + 3 * d;
+        if (!(quad->w[d] > 0) || !std::isfinite(quad->w[d])) return fail(SN_ERR_INVALID, "weight %d not positive", d);
+        double nrm = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+        if (!(std::fabs(nrm - 1.0) < 1e-10)) return fail(SN_ERR_INVALID, "direction %d is not a unit vector", d);
+        for (int a = 0; a < dim; ++a)
+            if (o[a] == 0.0) return fail(SN_ERR_UNSUPPORTED, "direction %d has a zero component", d);
+        wsum += quad->w[d];
+    }
+    if (std::fabs(wsum - 4.0 * kPi) > 1e-12 * 4.0 * kPi) return fail(SN_ERR_INVALID, "weights sum to %.17g, not 4 pi", wsum);
+
+    std::unique_ptr<sn_context> c(new sn_context());
+    // owned by unique_ptr until success; sn_context_destroy frees device memory
+    struct Guard {
+        std::unique_ptr<sn_context>& c;
+        ~Guard() {
+            if (c) {
+                sn_context_destroy(c.release());
+            }
+        }
+    } guard{c};
+    c->mesh = *mesh;
+    c->nn = dim == 2 ? 4 : 8;
+    c->nc = (long)mesh->nx * mesh->ny * mesh->nz;
+    c->ndirs = quad->ndirs;
+    c->nbf = inflow_size(mesh);
+    c->eta = eta;
+    c->stream = (hipStream_t)stream;
+    const double h[3] = {mesh->hx, mesh->hy, dim == 3 ? mesh->hz : 1.0};
+    c->hw.assign(quad->w, quad->w + quad->ndirs);
+    c->hdirs.resize(quad->ndirs);
+    for (int d = 0; d < quad->ndirs; ++d) {
+        const double* o = quad->omega + 3 * d;
+        DirInfo& di = c->hdirs[d];
+        di.ax = std::fabs(o[0]) / h[0];
+        di.ay = std::fabs(o[1]) / h[1];
+        di.az = dim == 3 ? std::fabs(o[2]) / h[2] : 0.0;
+        di.w = quad->w[d];
+        di.rx = o[0] < 0;
+        di.ry = o[1] < 0;
+        di.rz = dim == 3 ? (o[2] < 0) : 0;
+        di.pad = 0;
+    }
+    // validate cross sections on the host
+    const long nc = c->nc;
+    std::vector<double> st(nc), ss(nc);
+    HIPCHK(hipMemcpy(st.data(), sigma_t, nc * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ss.data(), sigma_s, nc * sizeof(double), hipMemcpyDeviceToHost));
+    for (long i = 0; i < nc; ++i) {
+        if (!std::isfinite(st[i]) || !std::isfinite(ss[i]) || st[i] < 0 || ss[i] < 0)
+            return fail(SN_ERR_INVALID, "cell %ld: cross sections must be finite and non-negative", i);
+        if (ss[i] > st[i]) return fail(SN_ERR_INVALID, "cell %ld: sigma_s > sigma_t", i);
+    }
+    std::vector<float> st32(st.begin(), st.end());
+    if ((rc = c->dirs.ensure(c->ndirs)) || (rc = c->w.ensure(c->ndirs)) || (rc = c->sigt.ensure(nc)) ||
+        (rc = c->sigs.ensure(nc)) || (rc = c->sigt32.ensure(nc)))
+        return rc;
+    HIPCHK(hipMemcpy(c->dirs.p, c->hdirs.data(), c->ndirs * sizeof(DirInfo), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->w.p, c->hw.data(), c->ndirs * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sigt.p, st.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sigs.p, ss.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sigt32.p, st32.data(), nc * sizeof(float), hipMemcpyHostToDevice));
+
+    // sweep geometry
+    SweepGeom& g = c->sg;
+    g.dim = dim;
+    g.nx = mesh->nx;
+    g.ny = mesh->ny;
+    g.nz = mesh->nz;
+    g.ndirs = c->ndirs;
+    g.nbf = c->nbf;
+    if (dim == 2) {
+        g.nchunk = (mesh->ny + 1023) / 1024;
+        g.xstride = (long)mesh->ny * 2;
+        g.ystride = (long)g.nchunk * mesh->nx * 2;
+        g.zstride = 0;
+        g.TX = 0;
+        g.nTx = g.nTy = g.nTz = 0;
+        g.nplanes = 0;
+        c->plane_off.assign(1, 0);
+        if ((rc = c->tiles.ensure(1))) return rc;
+    } else {
+        int tx = 32;
+        if (const char* e = std::getenv("SN_SWEEP_TX")) tx = std::max(1, std::atoi(e));
+        g.TX = std::min(tx, mesh->nx);
+        g.nTx = (mesh->nx + g.TX - 1) / g.TX;
+        g.nTy = (mesh->ny + 7) / 8;
+        g.nTz = (mesh->nz + 7) / 8;
+        if (g.nTx > 1023 || g.nTy > 1023 || g.nTz > 1023)
+            return fail(SN_ERR_UNSUPPORTED, "more than 1023 sweep tiles along an axis");
+        g.nplanes = g.nTx + g.nTy + g.nTz - 2;
+        g.nchunk = 0;
+        g.xstride = (long)g.nTx * mesh->nz * mesh->ny * 4;
+        g.ystride = (long)g.nTy * mesh->nz * mesh->nx * 4;
+        g.zstride = (long)g.nTz * mesh->ny * mesh->nx * 4;
+        std::vector<int> tl;
+        c->plane_off.assign(1, 0);
+        for (int p = 0; p < g.nplanes; ++p) {
+            for (int I = 0; I < g.nTx; ++I)
+                for (int J = 0; J < g.nTy; ++J) {
+                    int K = p - I - J;
+                    if (K >= 0 && K < g.nTz) tl.push_back(I | (J << 10) | (K << 20));
+                }
+            c->plane_off.push_back((int)tl.size());
+        }
+        if ((rc = c->tiles.ensure(tl.size()))) return rc;
+        HIPCHK(hipMemcpy(c->tiles.p, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+
+    // thick set
+    const int nblk = (int)((nc + 255) / 256);
+    if ((rc = c->flags.ensure(nc)) || (rc = c->blocksums.ensure(nblk)) || (rc = c->total.ensure(1)) ||
+        (rc = c->slot.ensure(nc)) || (rc = c->thick.ensure(nc)))
+        return rc;
+    HIPCHK(launch_thick_flags(nc, c->sigs.p, eta, c->flags.p, c->blocksums.p, nblk, c->stream));
+    HIPCHK(launch_thick_scan(nblk, c->blocksums.p, c->total.p, c->stream));
+    HIPCHK(launch_thick_scatter(nc, c->flags.p, c->blocksums.p, c->slot.p, c->thick.p, c->stream));
+    int nthick = 0;
+    HIPCHK(hipMemcpyAsync(&nthick, c->total.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->nthick = nthick;
+    DsaGeom& dg = c->dg;
+    dg.dim = dim;
+    dg.nx = mesh->nx;
+    dg.ny = mesh->ny;
+    dg.nz = mesh->nz;
+    dg.nn = c->nn;
+    for (int a = 0; a < 3; ++a) {
+        dg.h[a] = h[a];
+        double s = 0.0;
+        for (int d = 0; d < c->ndirs; ++d) s += quad->w[d] * std::fabs(quad->omega[3 * d + a]);
+        dg.kappa0[a] = s / (8.0 * kPi);
+    }
+    dg.nthick = nthick;
+    const long nf = (long)nthick * c->nn;
+    c->nparts = std::max(1, std::min((nthick + 255) / 256, 1024));
+    if ((rc = c->binv.ensure((size_t)std::max(nthick, 1) * c->nn * c->nn)) || (rc = c->cx.ensure(nf)) ||
+        (rc = c->cr.ensure(nf)) || (rc = c->cz.ensure(nf)) || (rc = c->cp.ensure(nf)) || (rc = c->cq.ensure(nf)) ||
+        (rc = c->parta.ensure(2 * c->nparts)) || (rc = c->partb.ensure(2 * c->nparts)) ||
+        (rc = c->scal.ensure(1)))
+        return rc;
+    HIPCHK(launch_block_jacobi(dg, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, c->binv.p, c->stream));
+    c->nrpart = (int)std::max<long>(1, std::min<long>((nc * c->nn + 255) / 256, 1024));
+    if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *out = c.release();
+    return SN_OK;
+}
+
+int sn_set_kernel_timing(sn_context* ctx, int enable) {
+    g_err.clear();
+    if (!ctx) return fail(SN_ERR_INVALID, "context is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->timing = enable ? 1 : 0;
+    ctx->evused = 0;
+    ctx->sweep_ev.clear();
+    ctx->dsa_ev.clear();
+    return 0;
+}
+
+int sn_kernel_timing(sn_context* ctx, double* sweep_ms, int* sweep_count, double* dsa_ms, int* dsa_count) {
+    g_err.clear();
+    if (!ctx) return fail(SN_ERR_INVALID, "context is NULL");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double sw = 0.0, ds = 0.0;
+    for (auto& pr : ctx->sweep_ev) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->evpool[pr.first], ctx->evpool[pr.second]));
+        sw += ms;
+    }
+    for (auto& pr : ctx->dsa_ev) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->evpool[pr.first], ctx->evpool[pr.second]));
+        ds += ms;
+    }
+    if (sweep_ms) *sweep_ms = sw;
+    if (sweep_count) *sweep_count = (int)ctx->sweep_ev.size();
+    if (dsa_ms) *dsa_ms = ds;
+    if (dsa_count) *dsa_count = (int)ctx->dsa_ev.size();
+    ctx->evused = 0;
+    ctx->sweep_ev.clear();
+    ctx->dsa_ev.clear();
+    return 0;
+}
+
+int sn_sweep(sn_context* ctx, const double* phi, const double* q, const double* inflow, int transpose,
+             sn_precision prec, void* psi) {
+    g_err.clear();
+    if (!ctx || !psi) return fail(SN_ERR_INVALID, "context or psi is NULL");
+    if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision %d", (int)prec);
+    return do_sweep(ctx, phi, nullptr, q, inflow, transpose ? 1 : 0, prec, psi);
+}
+
+int sn_scalar_flux(sn_context* ctx, const void* psi, sn_precision prec, double* phi_out) {
+    g_err.clear();
+    if (!ctx || !psi || !phi_out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision %d", (int)prec);
+    return do_moment(ctx, psi, prec, phi_out);
+}
+
+int sn_dsa_thick_correct(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out,
+                         const sn_dsa_opts* opts, sn_dsa_stats* stats) {
+    g_err.clear();
+    if (!ctx || !phi_old || !phi_si || !phi_out || !opts) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!(opts->cg_rtol >= 0) || opts->cg_maxit < 1 || (opts->mass_kind != 0 && opts->mass_kind != 1))
+        return fail(SN_ERR_INVALID, "bad DSA options");
+    return do_dsa(ctx, phi_old, phi_si, phi_out, opts, stats);
+}
+
+int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, double* phi, const sn_iter_opts* o,
+                      sn_iter_stats* stats) {
+    g_err.clear();
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !phi || !o) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
+    if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
+    if (o->use_dsa && (!(o->dsa.cg_rtol >= 0) || o->dsa.cg_maxit < 1 ||
+                       (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1)))
+        return fail(SN_ERR_INVALID, "bad DSA options");
+    const long n = ctx->nc * ctx->nn;
+    const size_t npsi = (size_t)ctx->nc * ctx->ndirs * ctx->nn;
+    int rc;
+    void* psi;
+    if (o->prec == SN_FP64) {
+        if ((rc = ctx->psi64.ensure(npsi))) return rc;
+        psi = ctx->psi64.p;
+    } else {
+        if ((rc = ctx->psi32.ensure(npsi))) return rc;
+        psi = ctx->psi32.p;
+    }
+    if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->phitmp.ensure(n)) || (rc = ctx->phiprev.ensure(n))) return rc;
+    const int tr = o->transpose ? 1 : 0;
+    // FP32 sweeps act on the iterate increment (defect correction): after the
+    // first iteration the sweep source is sigma_s (phi_i - phi_{i-1}) / 4pi
+    // and its moment is added to the FP64 accumulator phi_SI, so the FP32
+    // rounding error scales with the increment instead of with phi.
+    const bool incr = o->prec == SN_FP32;
+    if (stats) stats->fp64_checks = 0;
+    double bnorm = 1.0, first = -1.0;
+    int it = 0;
+    int status = SN_ERR_NOT_CONVERGED;
+    bool verified = false;  // FP32 form: phi_SI last recomputed by an FP64 sweep
+    for (; it < o->max_it; ++it) {
+        if (!incr || it == 0) {
+            if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, o->prec, psi))) return rc;
+            if ((rc = do_moment(ctx, psi, o->prec, ctx->phisi.p))) return rc;
+        } else {
+            if ((rc = do_sweep(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, psi))) return rc;
+            if ((rc = do_moment(ctx, psi, o->prec, ctx->phisi.p, 1))) return rc;
+        }
+        verified = false;
+        double r3[3];
+        if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
+        if (it == 0) {
+            if (r3[2] == 0.0) {
+                bnorm = std::sqrt(r3[1]);
+            } else {
+                // ||b||: the transport update of q alone, from phi = 0
+                if ((rc = do_sweep(ctx, nullptr, nullptr, q, inflow, tr, o->prec, psi))) return rc;
+                if ((rc = do_moment(ctx, psi, o->prec, ctx->phitmp.p))) return rc;
+                double b3[3];
+                if ((rc = residual3(ctx, ctx->phitmp.p, ctx->phitmp.p, b3))) return rc;
+                bnorm = std::sqrt(b3[1]);
+            }
+            if (bnorm == 0.0) bnorm = 1.0;
+        }
+        if (incr && std::sqrt(r3[0]) / bnorm <= o->tol) {
+            // The FP32 form may only stop on an exact residual: recompute
+            // phi_SI from phi with one FP64 sweep and test that instead; the
+            // increments then continue from this FP64 value.
+            if ((rc = ctx->psi64.ensure(npsi))) return rc;
+            if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->psi64.p))) return rc;
+            if ((rc = do_moment(ctx, ctx->psi64.p, SN_FP64, ctx->phisi.p))) return rc;
+            if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
+            verified = true;
+            if (stats) stats->fp64_checks += 1;
+        }
+        if (incr)
+            HIPCHK(hipMemcpyAsync(ctx->phiprev.p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        const double res = std::sqrt(r3[0]) / bnorm;
+        if (stats && stats->res_hist) stats->res_hist[it] = res;
+        if (first < 0) first = res;
+        int cgi = 0;
+        if (o->use_dsa) {
+            sn_dsa_stats ds{};
+            rc = do_dsa(ctx, phi, ctx->phisi.p, phi, &o->dsa, &ds);
+            cgi = ds.cg_iters;
+            if (rc) {
+                status = rc;
+                ++it;
+                break;
+            }
+        } else {
+            HIPCHK(hipMemcpyAsync(phi, ctx->phisi.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        if (stats && stats->cg_hist) stats->cg_hist[it] = cgi;
+        if (o->phi_ckpt)
+            HIPCHK(hipMemcpyAsync(o->phi_ckpt + (size_t)it * n, phi, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+        if (!std::isfinite(res) || res > 1e6 * first) {
+            status = fail(SN_ERR_DIVERGED, "source iteration diverged at iteration %d (residual %g)", it, res);
+            ++it;
+            break;
+        }
+        if (res <= o->tol) {
+            status = SN_OK;
+            ++it;
+            break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (status == SN_ERR_NOT_CONVERGED) fail(status, "not converged in %d iterations", o->max_it);
+    (void)verified;
+    if (stats) {
+        stats->iters = it;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int sn_gradient(sn_context* ctx, const void* psi, const void* psi_adj, sn_precision prec, const double* phi,
+                const double* chi, double* g_t, double* g_s) {
+    g_err.clear();
+    if (!ctx || !psi || !psi_adj || !phi || !chi || !g_t || !g_s) return fail(SN_ERR_INVALID, "NULL argument");
+    const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, ctx->mesh.dim == 3 ? ctx->mesh.hz : 1.0};
+    if (prec == SN_FP64)
+        HIPCHK(launch_gradient<double>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, h, ctx->sigt.p, ctx->sigs.p,
+                                       (const double*)psi, (const double*)psi_adj, phi, chi, g_t, g_s, ctx->stream));
+    else if (prec == SN_FP32)
+        HIPCHK(launch_gradient<float>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, h, ctx->sigt.p, ctx->sigs.p,
+                                      (const float*)psi, (const float*)psi_adj, phi, chi, g_t, g_s, ctx->stream));
+    else
+        return fail(SN_ERR_INVALID, "unknown precision");
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,565 @@
+// Heterogeneous (thick-only) DSA, Alg. 2 of the paper, applied to the source-
+// iteration residual:  phi <- phi_SI + P_T D_ff^{-1} Sigma_f R_T (phi_SI - phi).
+//
+// * Thick set (Sec. 3.3, Sec. 4.2): cell K is thick iff sigma_s,K >= eta; the
+//   thick cells are compacted in increasing cell order by a deterministic scan.
+// * D_ff: the SIP diffusion form (eq. SIP at eps = 1) restricted to the thick
+//   DOFs (principal submatrix, Sec. 4.2), applied matrix-free:
+//     cell:  D_K int grad u . grad v + sigma_a,K int u v,  D_K = 1/(3 sigma_t,K)
+//     face (outward normal n of K, neighbour values zero if it is thin):
+//       -int {D d_n u} v_K - 1/2 int (u_K - u_nb) D_K d_n v_K + kappa int (u_K - u_nb) v_K
+//     domain face: kappa_0 int u v,  kappa_0 = (1/8pi) sum_d w_d |Omega_d . n|,
+//     kappa = max(kappa_0, 8 max(D) / h) on interior faces.
+// * Solver: conjugate gradients preconditioned by the inverse diagonal cell
+//   blocks (block Jacobi), FP64 throughout, zero initial guess, stopping on
+//   ||r|| <= rtol ||b||.  Scalars stay on the device: every dot product is a
+//   fixed-order block reduction whose partials every consumer block re-reduces
+//   in the same order, so results do not depend on scheduling.
+#include "sn_kernels.hpp"
+
+namespace sn {
+
+// ---------------------------------------------------------------------------
+// thick classification and compaction
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) thick_flags_kernel(long nc, const double* __restrict__ sigma_s, double eta,
+                                                          int* __restrict__ flags, int* __restrict__ block_sums) {
+    __shared__ int sh[256];
+    long c = (long)blockIdx.x * 256 + threadIdx.x;
+    int f = (c < nc && sigma_s[c] >= eta) ? 1 : 0;
+    if (c < nc) flags[c] = f;
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of block_sums in place (one block); total -> *total
+__global__ void __launch_bounds__(1024) thick_scan_kernel(int nblk, int* __restrict__ block_sums,
+                                                          int* __restrict__ total) {
+    __shared__ int sh[1024];
+    const int per = (nblk + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    int loc = 0;
+    for (int b = b0; b < min(nblk, b0 + per); ++b) loc += block_sums[b];
+    sh[threadIdx.x] = loc;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over 1024 partials
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? sh[threadIdx.x - 1] : 0;
+    for (int b = b0; b < min(nblk, b0 + per); ++b) {
+        int v = block_sums[b];
+        block_sums[b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) *total = sh[1023];
+}
+
+__global__ void __launch_bounds__(256) thick_scatter_kernel(long nc, const int* __restrict__ flags,
+                                                            const int* __restrict__ block_sums,
+                                                            int* __restrict__ slot_of_cell,
+                                                            int* __restrict__ thick_cell) {
+    __shared__ int sh[256];
+    long c = (long)blockIdx.x * 256 + threadIdx.x;
+    int f = c < nc ? flags[c] : 0;
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (c < nc) {
+        int slot = block_sums[blockIdx.x] + sh[threadIdx.x] - f;
+        slot_of_cell[c] = f ? slot : -1;
+        if (f) thick_cell[slot] = (int)c;
+    }
+}
+
+hipError_t launch_thick_flags(long nc, const double* sigma_s, double eta, int* flags, int* block_sums, int nblk,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(thick_flags_kernel, dim3(nblk), dim3(256), 0, st, nc, sigma_s, eta, flags, block_sums);
+    return hipGetLastError();
+}
+hipError_t launch_thick_scan(int nblk, int* block_sums, int* total, hipStream_t st) {
+    hipLaunchKernelGGL(thick_scan_kernel, dim3(1), dim3(1024), 0, st, nblk, block_sums, total);
+    return hipGetLastError();
+}
+hipError_t launch_thick_scatter(long nc, const int* flags, const int* block_sums, int* slot_of_cell,
+                                int* thick_cell, hipStream_t st) {
+    int nblk = (int)((nc + 255) / 256);
+    hipLaunchKernelGGL(thick_scatter_kernel, dim3(nblk), dim3(256), 0, st, nc, flags, block_sums, slot_of_cell,
+                       thick_cell);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// matrix-free SIP on one thick cell
+// ---------------------------------------------------------------------------
+// 1D mass along `axis` of a tensor-product nodal vector (node bit `axis`)
+template <int NN>
+__device__ __forceinline__ void mass_along(double h, int axis, double t[NN]) {
+    const int st = 1 << axis;
+    const double a = h / 3.0, b = h / 6.0;
+    double o[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) o[n] = a * t[n] + b * t[n ^ st];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) t[n] = o[n];
+}
+template <int NN>
+__device__ __forceinline__ void stiff_along(double h, int axis, double t[NN]) {
+    const int st = 1 << axis;
+    const double a = 1.0 / h;
+    double o[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) o[n] = a * (t[n] - t[n ^ st]);
+#pragma unroll
+    for (int n = 0; n < NN; ++n) t[n] = o[n];
+}
+
+// out = rows of D_ff u belonging to thick cell `cell`, given its own values uK
+// and the global thick vector u (indexed by slot); thin or missing neighbours
+// contribute zero values.  With self_only the neighbour values are taken as
+// zero, which yields the cell's diagonal block.
+template <int NN>
+__device__ void sip_cell_apply(const DsaGeom& g, long cell, const int* __restrict__ slot_of_cell,
+                               const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                               const double uK[NN], const double* __restrict__ u, bool self_only, double out[NN]) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    const int i = (int)(cell % g.nx);
+    const int j = (int)((cell / g.nx) % g.ny);
+    const int k = (int)(cell / ((long)g.nx * g.ny));
+    const double DK = 1.0 / (3.0 * sigma_t[cell]);
+    const double sa = sigma_t[cell] - sigma_s[cell];
+    // volume: D sum_axes (stiff_a (x) mass_others) u + sigma_a M u
+#pragma unroll
+    for (int n = 0; n < NN; ++n) out[n] = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        double t[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = uK[n];
+#pragma unroll
+        for (int o = 0; o < DIM; ++o) {
+            if (o == ax) stiff_along<NN>(g.h[o], o, t);
+            else mass_along<NN>(g.h[o], o, t);
+        }
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = fma(DK, t[n], out[n]);
+    }
+    {
+        double t[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = uK[n];
+#pragma unroll
+        for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = fma(sa, t[n], out[n]);
+    }
+    const int ext[3] = {g.nx, g.ny, g.nz};
+    const int pos[3] = {i, j, k};
+    const long stride[3] = {1, g.nx, (long)g.nx * g.ny};
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const int st = 1 << ax;
+        const double h = g.h[ax];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int npos = pos[ax] + (s ? 1 : -1);
+            double t[NN];
+            if (npos < 0 || npos >= ext[ax]) {
+                // domain boundary: kappa_0 (face mass) u on the face nodes
+#pragma unroll
+                for (int n = 0; n < NN; ++n) t[n] = (((n >> ax) & 1) == s) ? uK[n] : 0.0;
+#pragma unroll
+                for (int o = 0; o < DIM; ++o)
+                    if (o != ax) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+                for (int n = 0; n < NN; ++n)
+                    if (((n >> ax) & 1) == s) out[n] = fma(g.kappa0[ax], t[n], out[n]);
+                continue;
+            }
+            const long nb = cell + (s ? stride[ax] : -stride[ax]);
+            const int nslot = slot_of_cell[nb];
+            double un[NN];
+            double Dn = 0.0;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) un[n] = 0.0;
+            if (nslot >= 0) {
+                Dn = 1.0 / (3.0 * sigma_t[nb]);
+                if (!self_only) {
+#pragma unroll
+                    for (int n = 0; n < NN; ++n) un[n] = u[(long)nslot * NN + n];
+                }
+            }
+            double kap = g.kappa0[ax];
+            const double Dmax = DK > Dn ? DK : Dn;
+            if (8.0 * Dmax / h > kap) kap = 8.0 * Dmax / h;
+            double J[NN], G[NN];
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                if (((n >> ax) & 1) == s) {
+                    J[n] = uK[n] - un[n ^ st];
+                    G[n] = 0.5 * (DK * (uK[n] - uK[n ^ st]) + Dn * (un[n] - un[n ^ st])) / h;
+                } else {
+                    J[n] = 0.0;
+                    G[n] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < DIM; ++o)
+                if (o != ax) {
+                    mass_along<NN>(g.h[o], o, J);
+                    mass_along<NN>(g.h[o], o, G);
+                }
+            const double hd = 0.5 * DK / h;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                if (((n >> ax) & 1) == s) {
+                    out[n] += -G[n] + kap * J[n] - hd * J[n];
+                    out[n ^ st] += hd * J[n];
+                }
+            }
+        }
+    }
+}
+
+// diagonal block of D_ff for each thick cell, inverted (Gauss-Jordan; the
+// block is symmetric positive definite, so no pivoting is needed)
+template <int NN>
+__global__ void block_jacobi_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                    const int* __restrict__ slot_of_cell, const double* __restrict__ sigma_t,
+                                    const double* __restrict__ sigma_s, double* __restrict__ binv) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long cell = thick_cell[s];
+        double B[NN][NN], Inv[NN][NN];
+        for (int c = 0; c < NN; ++c) {
+            double e[NN], col[NN];
+            for (int n = 0; n < NN; ++n) e[n] = (n == c) ? 1.0 : 0.0;
+            sip_cell_apply<NN>(g, cell, slot_of_cell, sigma_t, sigma_s, e, nullptr, true, col);
+            for (int n = 0; n < NN; ++n) B[n][c] = col[n];
+        }
+        for (int r = 0; r < NN; ++r)
+            for (int c = 0; c < NN; ++c) Inv[r][c] = (r == c) ? 1.0 : 0.0;
+        for (int p = 0; p < NN; ++p) {
+            const double ip = 1.0 / B[p][p];
+            for (int c = 0; c < NN; ++c) {
+                B[p][c] *= ip;
+                Inv[p][c] *= ip;
+            }
+            for (int r = 0; r < NN; ++r) {
+                if (r == p) continue;
+                const double f = B[r][p];
+                for (int c = 0; c < NN; ++c) {
+                    B[r][c] -= f * B[p][c];
+                    Inv[r][c] -= f * Inv[p][c];
+                }
+            }
+        }
+        for (int r = 0; r < NN; ++r)
+            for (int c = 0; c < NN; ++c) binv[((long)s * NN + r) * NN + c] = Inv[r][c];
+    }
+}
+
+hipError_t launch_block_jacobi(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                               const double* sigma_t, const double* sigma_s, double* binv, hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    int blocks = std::min((g.nthick + 127) / 128, 65536);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(block_jacobi_kernel<4>, dim3(blocks), dim3(128), 0, st, g, thick_cell, slot_of_cell,
+                           sigma_t, sigma_s, binv);
+    else
+        hipLaunchKernelGGL(block_jacobi_kernel<8>, dim3(blocks), dim3(128), 0, st, g, thick_cell, slot_of_cell,
+                           sigma_t, sigma_s, binv);
+    return hipGetLastError();
+}
+
+template <int NN>
+__global__ void __launch_bounds__(256) sip_apply_kernel(DsaGeom g, const int* __restrict__ thick_cell, const int* __restrict__ slot_of_cell,
+                                 const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                                 const double* __restrict__ u, double* __restrict__ y) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        double uK[NN], o[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) uK[n] = u[(long)s * NN + n];
+        sip_cell_apply<NN>(g, thick_cell[s], slot_of_cell, sigma_t, sigma_s, uK, u, false, o);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) y[(long)s * NN + n] = o[n];
+    }
+}
+
+hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                            const double* sigma_t, const double* sigma_s, const double* u, double* y,
+                            hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    int blocks = std::min((g.nthick + 255) / 256, 65536);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(sip_apply_kernel<4>, dim3(blocks), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
+                           sigma_s, u, y);
+    else
+        hipLaunchKernelGGL(sip_apply_kernel<8>, dim3(blocks), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
+                           sigma_s, u, y);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// preconditioned CG
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// every block re-reduces the same partial array in the same order
+__device__ __forceinline__ double reduce_parts(const double* __restrict__ part, int nparts, double* sh) {
+    double v = 0.0;
+    for (int e = threadIdx.x; e < nparts; e += 256) v += part[e];
+    return block_reduce(v, sh);
+}
+
+template <int NN>
+__device__ __forceinline__ void bj_apply(const double* __restrict__ binv, int s, const double r[NN], double z[NN]) {
+    const double* B = binv + (long)s * NN * NN;
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < NN; ++b) v = fma(B[a * NN + b], r[b], v);
+        z[a] = v;
+    }
+}
+
+// b = coef M (phi_si - phi_old) on thick cells; x = 0, r = b, z = B^{-1} r, p = z;
+// partials: [0..nparts) r.z, [nparts..2 nparts) b.b
+template <int NN>
+__global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                      const double* __restrict__ sigma_t,
+                                                      const double* __restrict__ sigma_s, int mass_kind,
+                                                      const double* __restrict__ phi_old,
+                                                      const double* __restrict__ phi_si,
+                                                      const double* __restrict__ binv, double* __restrict__ x,
+                                                      double* __restrict__ r, double* __restrict__ z,
+                                                      double* __restrict__ p, double* __restrict__ part) {
+    __shared__ double sh[256];
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    double rz = 0.0, bb = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long c = thick_cell[s];
+        const double coef = mass_kind == 1 ? sigma_t[c] : sigma_s[c];
+        double t[NN], zz[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = phi_si[c * NN + n] - phi_old[c * NN + n];
+#pragma unroll
+        for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] *= coef;
+        bj_apply<NN>(binv, s, t, zz);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)s * NN + n;
+            x[e] = 0.0;
+            r[e] = t[n];
+            z[e] = zz[n];
+            p[e] = zz[n];
+            rz = fma(t[n], zz[n], rz);
+            bb = fma(t[n], t[n], bb);
+        }
+    }
+    rz = block_reduce(rz, sh);
+    bb = block_reduce(bb, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[gridDim.x + blockIdx.x] = bb;
+    }
+}
+
+hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
+                          int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
+                          double* x, double* r, double* z, double* p, double* part, int nparts, hipStream_t st) {
+    if (g.nn == 4)
+        hipLaunchKernelGGL(dsa_rhs_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part);
+    else
+        hipLaunchKernelGGL(dsa_rhs_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) cg_init_kernel(int nparts, const double* __restrict__ part, CgScalars* s,
+                                                      double rtol) {
+    __shared__ double sh[256];
+    double rz = reduce_parts(part, nparts, sh);
+    double bb = reduce_parts(part + nparts, nparts, sh);
+    if (threadIdx.x == 0) {
+        s->rz[0] = rz;
+        s->bb = bb;
+        s->rr = bb;
+        s->iters = 0;
+        s->breakdown = 0;
+        s->done = (bb == 0.0) ? 1 : 0;
+    }
+}
+
+hipError_t launch_cg_init(int nparts, const double* part, CgScalars* s, double rtol, hipStream_t st) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(256), 0, st, nparts, part, s, rtol);
+    return hipGetLastError();
+}
+
+// q = A p ; partials p.q
+template <int NN>
+__global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                       const int* __restrict__ slot_of_cell,
+                                                       const double* __restrict__ sigma_t,
+                                                       const double* __restrict__ sigma_s,
+                                                       const double* __restrict__ p, double* __restrict__ q,
+                                                       double* __restrict__ part, const CgScalars* __restrict__ s) {
+    if (s->done) return;
+    __shared__ double sh[256];
+    double pq = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double uK[NN], o[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) uK[n] = p[(long)t * NN + n];
+        sip_cell_apply<NN>(g, thick_cell[t], slot_of_cell, sigma_t, sigma_s, uK, p, false, o);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            q[(long)t * NN + n] = o[n];
+            pq = fma(uK[n], o[n], pq);
+        }
+    }
+    pq = block_reduce(pq, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = pq;
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; z = B^{-1} r; partials r.z, r.r
+template <int NN>
+__global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double* __restrict__ binv,
+                                                        double* __restrict__ x, double* __restrict__ r,
+                                                        double* __restrict__ z, const double* __restrict__ p,
+                                                        const double* __restrict__ q,
+                                                        const double* __restrict__ part_in,
+                                                        double* __restrict__ part_out, int nparts, CgScalars* s,
+                                                        int it) {
+    if (s->done) return;
+    __shared__ double sh[256];
+    const double pq = reduce_parts(part_in, nparts, sh);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            s->breakdown = 1;
+            s->done = 1;
+        }
+        return;
+    }
+    const double alpha = s->rz[it & 1] / pq;
+    double rz = 0.0, rr = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double rv[NN], zv[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)t * NN + n;
+            x[e] = fma(alpha, p[e], x[e]);
+            rv[n] = fma(-alpha, q[e], r[e]);
+            r[e] = rv[n];
+        }
+        bj_apply<NN>(binv, t, rv, zv);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            z[(long)t * NN + n] = zv[n];
+            rz = fma(rv[n], zv[n], rz);
+            rr = fma(rv[n], rv[n], rr);
+        }
+    }
+    rz = block_reduce(rz, sh);
+    rr = block_reduce(rr, sh);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x] = rz;
+        part_out[gridDim.x + blockIdx.x] = rr;
+    }
+}
+
+// beta = rz_new / rz; p = z + beta p.  rz lives in two slots indexed by the
+// iteration parity: this kernel reads slot it&1 and block 0 writes the new
+// value into the other slot, so no block can see a half-updated scalar.
+__global__ void __launch_bounds__(256) cg_direction_kernel(long nf, double* __restrict__ p,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ part, int nparts,
+                                                           CgScalars* s, double rtol, int maxit, int it) {
+    if (s->done) return;
+    __shared__ double sh[256];
+    const double rz_new = reduce_parts(part, nparts, sh);
+    const double rr = reduce_parts(part + nparts, nparts, sh);
+    const bool conv = sqrt(rr) <= rtol * sqrt(s->bb);
+    const bool stop = conv || it + 1 >= maxit;
+    if (!stop) {
+        const double beta = rz_new / s->rz[it & 1];
+        for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += (long)gridDim.x * blockDim.x)
+            p[e] = fma(beta, p[e], z[e]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rz[(it + 1) & 1] = rz_new;
+        s->rr = rr;
+        s->iters = it + 1;
+        if (stop) s->done = 1;
+    }
+}
+
+hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                               const double* sigma_t, const double* sigma_s, const double* binv, double* x,
+                               double* r, double* z, double* p, double* q, double* part_a, double* part_b,
+                               int nparts, CgScalars* s, double rtol, int maxit, int it, hipStream_t st) {
+    const long nf = (long)g.nthick * g.nn;
+    if (g.nn == 4) {
+        hipLaunchKernelGGL(cg_apply_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
+                           sigma_s, p, q, part_a, s);
+        hipLaunchKernelGGL(cg_update_kernel<4>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p, q, part_a,
+                           part_b, nparts, s, it);
+    } else {
+        hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
+                           sigma_s, p, q, part_a, s);
+        hipLaunchKernelGGL(cg_update_kernel<8>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p, q, part_a,
+                           part_b, nparts, s, it);
+    }
+    hipLaunchKernelGGL(cg_direction_kernel, dim3(nparts), dim3(256), 0, st, nf, p, z, part_b, nparts, s, rtol, maxit,
+                       it);
+    return hipGetLastError();
+}
+
+__global__ void dsa_scatter_kernel(long n, int nn, const int* __restrict__ slot_of_cell,
+                                   const double* __restrict__ phi_si, const double* __restrict__ x,
+                                   double* __restrict__ phi_out) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const long c = e / nn;
+        const int s = slot_of_cell ? slot_of_cell[c] : -1;
+        double v = phi_si[e];
+        if (s >= 0) v += x[(long)s * nn + (e - c * nn)];
+        phi_out[e] = v;
+    }
+}
+
+hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
+                              double* phi_out, hipStream_t st) {
+    long n = nc * nn;
+    int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(dsa_scatter_kernel, dim3(blocks), dim3(256), 0, st, n, nn, slot_of_cell, phi_si, x, phi_out);
+    return hipGetLastError();
+}
+
+}  // namespace sn

@@ -1,0 +1,223 @@
+// Scalar-flux side of one source iteration (Section 2.2, eq. psi / eq. phi):
+//   source   s = (sigma_s phi + q) / 4pi per node (the M^{-1}-scaled volume load),
+//   moment   phi = sum_d w_d psi_d, always accumulated in FP64,
+//   residual ||phi_SI - phi||^2, ||phi_SI||^2, ||phi||^2 (eq. source0),
+//   gradient contraction of the adjoint (derived from eq. system).
+#include "sn_kernels.hpp"
+
+namespace sn {
+
+constexpr double kInv4Pi = 0.079577471545947667884;  // 1 / (4 pi)
+
+// s = (sigma_s (phi - phi_prev) + q) / 4pi, formed in FP64 and rounded once
+// to the sweep precision; phi_prev, phi and q may be NULL (zero).
+template <typename T>
+__global__ void source_kernel(long n, int nn, const double* __restrict__ sigma_s, const double* __restrict__ phi,
+                              const double* __restrict__ phi_prev, const double* __restrict__ q,
+                              T* __restrict__ src) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        long c = e / nn;
+        double f = phi ? phi[e] : 0.0;
+        if (phi_prev) f -= phi_prev[e];
+        double v = sigma_s[c] * f + (q ? q[c] : 0.0);
+        src[e] = T(v * kInv4Pi);
+    }
+}
+
+template <typename T>
+hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* phi, const double* phi_prev,
+                         const double* q, T* src, hipStream_t st) {
+    long n = nc * nn;
+    int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(source_kernel<T>, dim3(blocks), dim3(256), 0, st, n, nn, sigma_s, phi, phi_prev, q, src);
+    return hipGetLastError();
+}
+
+// One thread per cell: reads the cell's contiguous [ndirs][NN] block of psi.
+template <typename T, int NN>
+__global__ void moment_kernel(long nc, int ndirs, const double* __restrict__ w, const T* __restrict__ psi,
+                              double* __restrict__ phi, int accumulate) {
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        double acc[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) acc[n] = 0.0;
+        const T* p = psi + c * ndirs * NN;
+        for (int d = 0; d < ndirs; ++d) {
+            const double wd = w[d];
+#pragma unroll
+            for (int n = 0; n < NN; ++n) acc[n] = fma(wd, double(p[d * NN + n]), acc[n]);
+        }
+        if (accumulate) {
+#pragma unroll
+            for (int n = 0; n < NN; ++n) phi[c * NN + n] += acc[n];
+        } else {
+#pragma unroll
+            for (int n = 0; n < NN; ++n) phi[c * NN + n] = acc[n];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* psi, double* phi, int accumulate,
+                         hipStream_t st) {
+    int blocks = (int)std::min<long>((nc + 255) / 256, 1 << 16);
+    if (nn == 4)
+        hipLaunchKernelGGL((moment_kernel<T, 4>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, psi, phi, accumulate);
+    else
+        hipLaunchKernelGGL((moment_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, psi, phi, accumulate);
+    return hipGetLastError();
+}
+
+// deterministic block reduction of three sums
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = a;
+    sh[256 + tid] = b;
+    sh[512 + tid] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sh[tid] += sh[tid + s];
+            sh[256 + tid] += sh[256 + tid + s];
+            sh[512 + tid] += sh[512 + tid + s];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[256];
+    c = sh[512];
+}
+
+__global__ void __launch_bounds__(256) residual_part_kernel(long n, const double* __restrict__ a,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ part) {
+    __shared__ double sh[768];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        double x = a[e], y = b[e], d = x - y;
+        s0 = fma(d, d, s0);
+        s1 = fma(x, x, s1);
+        s2 = fma(y, y, s2);
+    }
+    block_sum3(s0, s1, s2, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[gridDim.x + blockIdx.x] = s1;
+        part[2 * gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+__global__ void __launch_bounds__(256) residual_final_kernel(int nparts, const double* __restrict__ part,
+                                                             double* __restrict__ out) {
+    __shared__ double sh[768];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int e = threadIdx.x; e < nparts; e += 256) {
+        s0 += part[e];
+        s1 += part[nparts + e];
+        s2 += part[2 * nparts + e];
+    }
+    block_sum3(s0, s1, s2, sh);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+    }
+}
+
+hipError_t launch_residual(long n, const double* a, const double* b, double* partials, int nparts, double* out,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(residual_part_kernel, dim3(nparts), dim3(256), 0, st, n, a, b, partials);
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, partials, out);
+    return hipGetLastError();
+}
+
+// dJ/dlog sigma_t,K = -sigma_t,K sum_d w_d psia_d,K^T M_K psi_d,K
+// dJ/dlog sigma_s,K =  sigma_s,K chi_K^T M_K phi_K / 4pi
+// M_K = (x) of 1D masses h/6 [[2,1],[1,2]]; applied as a tensor product.
+template <int NN>
+__device__ __forceinline__ void apply_mass(const double* h, const double in[NN], double out[NN]) {
+    double t[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) t[n] = in[n];
+    const int naxes = NN == 4 ? 2 : 3;
+#pragma unroll
+    for (int ax = 0; ax < naxes; ++ax) {
+        const int st = 1 << ax;
+        const double a = h[ax] / 3.0, b = h[ax] / 6.0;
+        double o[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const int m = n ^ st;
+            o[n] = a * t[n] + b * t[m];
+        }
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = o[n];
+    }
+#pragma unroll
+    for (int n = 0; n < NN; ++n) out[n] = t[n];
+}
+
+template <typename T, int NN>
+__global__ void gradient_kernel(long nc, int ndirs, const double* __restrict__ w, double hx, double hy, double hz,
+                                const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                                const T* __restrict__ psi, const T* __restrict__ psia,
+                                const double* __restrict__ phi, const double* __restrict__ chi,
+                                double* __restrict__ gt, double* __restrict__ gs) {
+    const double h[3] = {hx, hy, hz};
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int d = 0; d < ndirs; ++d) {
+            double a[NN], b[NN], mb[NN];
+            const T* pa = psia + (c * ndirs + d) * NN;
+            const T* pb = psi + (c * ndirs + d) * NN;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                a[n] = double(pa[n]);
+                b[n] = double(pb[n]);
+            }
+            apply_mass<NN>(h, b, mb);
+            double v = 0.0;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) v = fma(a[n], mb[n], v);
+            acc = fma(w[d], v, acc);
+        }
+        gt[c] = -sigma_t[c] * acc;
+        double x[NN], mx[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) x[n] = phi[c * NN + n];
+        apply_mass<NN>(h, x, mx);
+        double v = 0.0;
+#pragma unroll
+        for (int n = 0; n < NN; ++n) v = fma(chi[c * NN + n], mx[n], v);
+        gs[c] = sigma_s[c] * v * kInv4Pi;
+    }
+}
+
+template <typename T>
+hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const double* h, const double* sigma_t,
+                           const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
+                           const double* chi, double* g_t, double* g_s, hipStream_t st) {
+    int blocks = (int)std::min<long>((nc + 255) / 256, 1 << 16);
+    if (nn == 4)
+        hipLaunchKernelGGL((gradient_kernel<T, 4>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, h[0], h[1], h[2],
+                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s);
+    else
+        hipLaunchKernelGGL((gradient_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, h[0], h[1], h[2],
+                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s);
+    return hipGetLastError();
+}
+
+template hipError_t launch_source<double>(long, int, const double*, const double*, const double*, const double*,
+                                          double*, hipStream_t);
+template hipError_t launch_source<float>(long, int, const double*, const double*, const double*, const double*,
+                                         float*, hipStream_t);
+template hipError_t launch_moment<double>(long, int, int, const double*, const double*, double*, int, hipStream_t);
+template hipError_t launch_moment<float>(long, int, int, const double*, const float*, double*, int, hipStream_t);
+template hipError_t launch_gradient<double>(long, int, int, const double*, const double*, const double*,
+                                            const double*, const double*, const double*, const double*,
+                                            const double*, double*, double*, hipStream_t);
+template hipError_t launch_gradient<float>(long, int, int, const double*, const double*, const double*,
+                                           const double*, const float*, const float*, const double*,
+                                           const double*, double*, double*, hipStream_t);
+
+}  // namespace sn

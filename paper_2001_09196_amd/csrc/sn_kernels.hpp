@@ -1,0 +1,85 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "sn_device.hpp"
+
+namespace sn {
+
+// Geometry of one sweep: mesh, direction count and the tiling / chunking the
+// sweep kernels use (see sweep.hip).
+struct SweepGeom {
+    int dim, nx, ny, nz, ndirs;
+    long nbf;          // boundary-face nodes per direction in the inflow layout
+    int TX;            // 3D tile length along x
+    int nTx, nTy, nTz; // 3D tile counts (tiles are TX x 8 x 8)
+    int nplanes;       // 3D tile-diagonal planes
+    int nchunk;        // 2D row chunks of at most 1024 rows
+    long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements)
+};
+
+template <typename T>
+hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transpose, const double* inflow, T* xf,
+                             T* yf, T* zf, hipStream_t st);
+// sink: scratch of sink_elems(g) elements that absorbs the stores of lanes
+// without a cell at a given step
+template <typename T>
+hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
+                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st);
+inline long sink_elems(const SweepGeom& g) { return g.dim == 2 ? (long)g.ndirs * 1024 * 4 : 1; }
+
+// scalar-flux kernels (flux.hip)
+template <typename T>
+hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* phi, const double* phi_prev,
+                         const double* q, T* src, hipStream_t st);
+template <typename T>
+hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* psi, double* phi, int accumulate,
+                         hipStream_t st);
+// partial sums of (a-b)^2, a^2, b^2 over n doubles; out[3] on device
+hipError_t launch_residual(long n, const double* a, const double* b, double* partials, int nparts, double* out,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const double* h, const double* sigma_t,
+                           const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
+                           const double* chi, double* g_t, double* g_s, hipStream_t st);
+
+// heterogeneous DSA (dsa.hip)
+struct DsaGeom {
+    int dim, nx, ny, nz, nn;
+    double h[3];
+    double kappa0[3];  // (1/8pi) sum_d w_d |Omega_d,axis|
+    int nthick;
+};
+
+hipError_t launch_thick_flags(long nc, const double* sigma_s, double eta, int* flags, int* block_sums, int nblk,
+                              hipStream_t st);
+hipError_t launch_thick_scan(int nblk, int* block_sums, int* total, hipStream_t st);
+hipError_t launch_thick_scatter(long nc, const int* flags, const int* block_sums, int* slot_of_cell,
+                                int* thick_cell, hipStream_t st);
+hipError_t launch_block_jacobi(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                               const double* sigma_t, const double* sigma_s, double* binv, hipStream_t st);
+
+struct CgScalars {
+    double rz[2];   // r.z of the current iterate, slot = iteration parity
+    double bb, rr;  // ||b||^2 and the latest ||r||^2
+    int done, iters, breakdown, pad;
+};
+
+hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
+                          int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
+                          double* x, double* r, double* z, double* p, double* part, int nparts, hipStream_t st);
+hipError_t launch_cg_init(int nparts, const double* part, CgScalars* s, double rtol, hipStream_t st);
+hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                               const double* sigma_t, const double* sigma_s, const double* binv, double* x,
+                               double* r, double* z, double* p, double* q, double* part_a, double* part_b,
+                               int nparts, CgScalars* s, double rtol, int maxit, int it, hipStream_t st);
+hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
+                              double* phi_out, hipStream_t st);
+hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                            const double* sigma_t, const double* sigma_s, const double* u, double* y,
+                            hipStream_t st);
+
+}  // namespace sn

@@ -1,0 +1,474 @@
+// Transport sweeps (Section 1 and Section 2.2, eq. psi): for every direction d
+// and every cell in upwind order, solve the upwind-DG cell problem with the
+// already-computed upwind face values.  The local solve is sn::cell_solve2/3.
+//
+// 2D (latency bound: the dependency chain is nx + ny - 1 cells long):
+//   one workgroup per direction; lane r of wave w owns local row 64 w + r and
+//   walks along x, skewed by its row index, so that at step t it works on
+//   column t - row.  The x inflow of a cell is the previous cell of the same
+//   lane (registers); the y inflow is the top face of the row below, taken
+//   from lane r - 1 by a lane shuffle, or from the previous wave through LDS
+//   (one barrier per step).  Rows beyond 1024 are processed in chunks, one
+//   launch per chunk, chained through a y-face buffer.
+//
+// 3D (throughput bound): tiles of TX x 8 x 8 cells in the reflected frame of
+//   each direction; one wave per (tile, direction); lane (jy, kz) owns the
+//   x-pencil (jy, kz) of the tile and walks along x skewed by jy + kz, taking
+//   its y inflow from lane - 1 and its z inflow from lane - 8 by lane
+//   shuffles.  Tiles on one diagonal plane I + J + K = p are independent, so
+//   each plane is one launch; tile faces travel through face buffers in the
+//   reflected frame (slot 0 of each buffer holds the domain inflow).
+//
+// Node order in memory is global (a + 2b + 4c); in the reflected frame node
+// n_local = n_global ^ M with M = rx + 2 ry + 4 rz, a compile-time constant
+// of each kernel body.
+#include "sn_kernels.hpp"
+
+namespace sn {
+
+template <typename T>
+__device__ __forceinline__ T shfl_up_t(T v, int delta) {
+    return __shfl_up(v, delta, 64);
+}
+
+// ---------------------------------------------------------------------------
+// face-buffer initialisation from the domain inflow (or zero)
+// ---------------------------------------------------------------------------
+// inflow layout per direction (global frame): x face ((k*ny + j)*F + b + 2c),
+// y face ((k*nx + i)*F + a + 2c), z face ((j*nx + i)*F + a + 2b).
+template <typename T>
+__global__ void init_faces_kernel(int dim, int nx, int ny, int nz, int ndirs, const DirInfo* __restrict__ dirs,
+                                  int transpose, const double* __restrict__ inflow, long nbf, T* __restrict__ xf,
+                                  long xstride, T* __restrict__ yf, long ystride, T* __restrict__ zf,
+                                  long zstride) {
+    const int F = dim == 2 ? 2 : 4;
+    const long nxf = (long)ny * nz, nyf = (long)nx * nz, nzf = (long)nx * ny;
+    const long per = (nxf + nyf + (dim == 3 ? nzf : 0));
+    long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long total = per * ndirs;
+    for (; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        int d = (int)(idx / per);
+        long f = idx % per;
+        DirInfo di = dirs[d];
+        int rx = di.rx ^ transpose, ry = di.ry ^ transpose, rz = (dim == 3) ? (di.rz ^ transpose) : 0;
+        const double* in = inflow ? inflow + (long)d * nbf : nullptr;
+        if (f < nxf) {  // x face, local (kl, jl)
+            int jl = (int)(f % ny), kl = (int)(f / ny);
+            int j = ry ? ny - 1 - jl : jl, k = rz ? nz - 1 - kl : kl;
+            for (int t = 0; t < F; ++t) {
+                int b = (t & 1) ^ ry, c = ((t >> 1) & 1) ^ rz;
+                double v = in ? in[((long)k * ny + j) * F + b + 2 * c] : 0.0;
+                xf[d * xstride + f * F + t] = T(v);
+            }
+        } else if (f < nxf + nyf) {  // y face, local (kl, il)
+            long g = f - nxf;
+            int il = (int)(g % nx), kl = (int)(g / nx);
+            int i = rx ? nx - 1 - il : il, k = rz ? nz - 1 - kl : kl;
+            for (int t = 0; t < F; ++t) {
+                int a = (t & 1) ^ rx, c = ((t >> 1) & 1) ^ rz;
+                double v = in ? in[nxf * F + ((long)k * nx + i) * F + a + 2 * c] : 0.0;
+                yf[d * ystride + g * F + t] = T(v);
+            }
+        } else {  // z face, local (jl, il)
+            long g = f - nxf - nyf;
+            int il = (int)(g % nx), jl = (int)(g / nx);
+            int i = rx ? nx - 1 - il : il, j = ry ? ny - 1 - jl : jl;
+            for (int t = 0; t < 4; ++t) {
+                int a = (t & 1) ^ rx, b = ((t >> 1) & 1) ^ ry;
+                double v = in ? in[(nxf + nyf) * 4 + ((long)j * nx + i) * 4 + a + 2 * b] : 0.0;
+                zf[d * zstride + g * 4 + t] = T(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D pipelined sweep
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> load4(const T* p) {
+    Vec4<T> r;
+    if constexpr (sizeof(T) == 8) {
+        const double2* q = reinterpret_cast<const double2*>(p);
+        double2 a = q[0], b = q[1];
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+    } else {
+        float4 a = *reinterpret_cast<const float4*>(p);
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(T* p, T a0, T a1, T a2, T a3) {
+    if constexpr (sizeof(T) == 8) {
+        double2* q = reinterpret_cast<double2*>(p);
+        q[0] = make_double2(a0, a1);
+        q[1] = make_double2(a2, a3);
+    } else {
+        *reinterpret_cast<float4*>(p) = make_float4(a0, a1, a2, a3);
+    }
+}
+
+// Inputs of one cell for one lane, loaded ahead of use.
+template <typename T>
+struct In2 {
+    Vec4<T> s;
+    T sig, yb0, yb1;
+};
+
+// The loop body is branch-free: every lane loads from a valid (clamped)
+// address, solves, and stores either to psi or, when it has no cell at this
+// step, to a per-workgroup sink.  Straight-line code lets the compiler count
+// outstanding memory operations exactly, so a step waits only for loads
+// issued two steps earlier and never for the psi stores (loads and stores
+// retire in order on this hardware).
+template <typename T, int M>
+__device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T ax, T ay,
+                                             const T* __restrict__ sigt, const T* __restrict__ src,
+                                             const T* __restrict__ xf, const T* __restrict__ yin_buf,
+                                             T* __restrict__ yout_buf, int row0, int nrows,
+                                             T* __restrict__ psi, T* __restrict__ sink, T (*lds)[16][2]) {
+    constexpr int rx = M & 1, ry = (M >> 1) & 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = wave * 64 + lane;
+    const bool rowok = r < nrows;
+    const int jl = row0 + min(r, nrows - 1);
+    const int j = ry ? ny - 1 - jl : jl;
+    const long rowbase = (long)j * nx;
+    T* my_sink = sink + (long)threadIdx.x * 4;
+    T* yout = yout_buf ? yout_buf : sink;
+    const bool top = yout_buf && r == nrows - 1;
+    T xin0 = xf[(long)jl * 2 + 0];
+    T xin1 = xf[(long)jl * 2 + 1];
+    T yo0 = T(0), yo1 = T(0);
+    auto fetch = [&](int il, In2<T>& v) {
+        const int ilc = min(max(il, 0), nx - 1);
+        const int i = rx ? nx - 1 - ilc : ilc;
+        const long c = rowbase + i;
+        v.s = load4(src + c * 4);
+        v.sig = sigt[c];
+        v.yb0 = yin_buf[(long)ilc * 2 + 0];
+        v.yb1 = yin_buf[(long)ilc * 2 + 1];
+    };
+    const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay;
+    const int nsteps = nx + nrows - 1;
+    const int pw = wave > 0 ? wave - 1 : 0;
+    // one pipeline step: solve with the inputs in `use`, fetch the inputs of
+    // step t + 2 into `fill`.  The loop below is unrolled by three so that the
+    // three input slots keep fixed registers (no copies of in-flight loads).
+    auto step = [&](int t, In2<T>& use, In2<T>& fill) {
+        const int il = t - r;
+        fetch(il + 2, fill);
+        T yi0 = shfl_up_t(yo0, 1), yi1 = shfl_up_t(yo1, 1);
+        const T l0 = lds[(t - 1) & 1][pw][0], l1 = lds[(t - 1) & 1][pw][1];
+        if (lane == 0) {
+            yi0 = wave == 0 ? use.yb0 : l0;
+            yi1 = wave == 0 ? use.yb1 : l1;
+        }
+        const bool active = rowok && il >= 0 && il < nx;
+        const int ilc = min(max(il, 0), nx - 1);
+        const int i = rx ? nx - 1 - ilc : ilc;
+        const long c = rowbase + i;
+        T g[4], u[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) g[n] = use.s.v[n ^ M];
+        // x inflow face (a' = 0), y inflow face (b' = 0)
+        g[0] = fma(ax4, xin0, g[0]);
+        g[1] = fma(-ax2, xin0, g[1]);
+        g[2] = fma(ax4, xin1, g[2]);
+        g[3] = fma(-ax2, xin1, g[3]);
+        g[0] = fma(ay4, yi0, g[0]);
+        g[2] = fma(-ay2, yi0, g[2]);
+        g[1] = fma(ay4, yi1, g[1]);
+        g[3] = fma(-ay2, yi1, g[3]);
+        cell_solve2(g, ax, ay, use.sig, u);
+        xin0 = active ? u[1] : xin0;
+        xin1 = active ? u[3] : xin1;
+        yo0 = active ? u[2] : yo0;
+        yo1 = active ? u[3] : yo1;
+        T o[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) o[n] = u[n ^ M];
+        store4(active ? psi + (c * ndirs + d) * 4 : my_sink, o[0], o[1], o[2], o[3]);
+        if (yout_buf) {
+            T* ya = (active && top) ? yout + (long)il * 2 : my_sink;
+            ya[0] = yo0;
+            ya[1] = yo1;
+        }
+        if (lane == 63) {
+            lds[t & 1][wave][0] = yo0;
+            lds[t & 1][wave][1] = yo1;
+        }
+        __syncthreads();
+    };
+    In2<T> s0, s1, s2;
+    fetch(-r, s0);
+    fetch(1 - r, s1);
+    for (int t = 0; t < nsteps; t += 3) {
+        step(t, s0, s2);
+        if (t + 1 < nsteps) step(t + 1, s1, s0);
+        if (t + 2 < nsteps) step(t + 2, s2, s1);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) sweep2d_kernel(int nx, int ny, int ndirs, const DirInfo* __restrict__ dirs,
+                                                       int transpose, const T* __restrict__ sigt,
+                                                       const T* __restrict__ src, const T* __restrict__ xf,
+                                                       long xstride, T* __restrict__ ybuf, long ystride, int chunk,
+                                                       int nchunk, int row0, int nrows, T* __restrict__ psi,
+                                                       T* __restrict__ sink) {
+    __shared__ T lds[2][16][2];
+    const int d = blockIdx.x;
+    const DirInfo di = dirs[d];
+    const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
+    const T ax = T(di.ax), ay = T(di.ay);
+    const T* xfd = xf + d * xstride;
+    const T* yin = ybuf + d * ystride + (long)chunk * nx * 2;
+    T* yout = (chunk + 1 < nchunk) ? ybuf + d * ystride + (long)(chunk + 1) * nx * 2 : nullptr;
+    T* snk = sink + (long)blockIdx.x * 1024 * 4;
+    switch (m) {
+        case 0: sweep2d_body<T, 0>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
+        case 1: sweep2d_body<T, 1>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
+        case 2: sweep2d_body<T, 2>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
+        default: sweep2d_body<T, 3>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D tile-plane sweep
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec8 {
+    T v[8];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec8<T> load8(const T* p) {
+    Vec8<T> r;
+    Vec4<T> a = load4(p), b = load4(p + 4);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        r.v[n] = a.v[n];
+        r.v[n + 4] = b.v[n];
+    }
+    return r;
+}
+
+template <typename T>
+struct In3 {
+    Vec8<T> s;
+    T sig;
+    Vec4<T> yb, zb;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, T ax, T ay, T az, int I,
+                                             int J, int K, int TX, int nTx, int nTy, int nTz,
+                                             const T* __restrict__ sigt, const T* __restrict__ src,
+                                             T* __restrict__ xf, T* __restrict__ yf, T* __restrict__ zf,
+                                             T* __restrict__ psi) {
+    constexpr int rx = M & 1, ry = (M >> 1) & 1, rz = (M >> 2) & 1;
+    const int lane = threadIdx.x & 63;
+    const int jy = lane & 7, kz = lane >> 3;
+    const int jl = J * 8 + jy, kl = K * 8 + kz;
+    const bool pen = jl < ny && kl < nz;
+    const int j = ry ? ny - 1 - jl : jl, k = rz ? nz - 1 - kl : kl;
+    const int i0 = I * TX;
+    const int len = min(TX, nx - i0);
+    T xin[4], yo[4], zo[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        xin[t] = T(0);
+        yo[t] = T(0);
+        zo[t] = T(0);
+    }
+    if (pen) {
+        Vec4<T> x = load4(xf + (((long)I * nz + kl) * ny + jl) * 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xin[t] = x.v[t];
+    }
+    const long rowbase = ((long)k * ny + j) * nx;
+    // inputs of the cell two steps ahead are loaded before the current solve
+    // (loads and stores retire in order; see sweep2d_body)
+    auto fetch = [&](int ir, In3<T>& v) {
+        if (pen && ir >= 0 && ir < len) {
+            const int il = i0 + ir;
+            const int i = rx ? nx - 1 - il : il;
+            const long c = rowbase + i;
+            v.s = load8(src + c * 8);
+            v.sig = sigt[c];
+            if (jy == 0) v.yb = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
+            if (kz == 0) v.zb = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
+        }
+    };
+    const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay, az4 = T(4) * az, az2 = T(2) * az;
+    const int skew = jy + kz;
+    const int nsteps = len + 14;
+    // one step: solve with `use`, fetch the inputs of step s + 1 into `fill`;
+    // unrolled by two so that the two slots keep fixed registers
+    auto step = [&](int s, In3<T>& use, In3<T>& fill) {
+        const int ir = s - skew;
+        fetch(ir + 1, fill);
+        T yi[4], zi[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            yi[t] = shfl_up_t(yo[t], 1);
+            zi[t] = shfl_up_t(zo[t], 8);
+        }
+        const bool active = pen && ir >= 0 && ir < len;
+        if (active) {
+            const int il = i0 + ir;
+            if (jy == 0) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) yi[t] = use.yb.v[t];
+            }
+            if (kz == 0) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zi[t] = use.zb.v[t];
+            }
+            const int i = rx ? nx - 1 - il : il;
+            const long c = rowbase + i;
+            T g[8], u[8];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g[n] = use.s.v[n ^ M];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                // x face: local nodes (0, t) += 4 ax xin, (1, t) -= 2 ax xin ; t = b + 2c
+                const int nx0 = 2 * t;
+                g[nx0] = fma(ax4, xin[t], g[nx0]);
+                g[nx0 + 1] = fma(-ax2, xin[t], g[nx0 + 1]);
+                // y face: t = a + 2c -> nodes a + 4c (b = 0) and a + 2 + 4c (b = 1)
+                const int ny0 = (t & 1) + 4 * (t >> 1);
+                g[ny0] = fma(ay4, yi[t], g[ny0]);
+                g[ny0 + 2] = fma(-ay2, yi[t], g[ny0 + 2]);
+                // z face: t = a + 2b -> nodes t (c = 0) and t + 4 (c = 1)
+                g[t] = fma(az4, zi[t], g[t]);
+                g[t + 4] = fma(-az2, zi[t], g[t + 4]);
+            }
+            cell_solve3(g, ax, ay, az, use.sig, u);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                xin[t] = u[2 * t + 1];
+                yo[t] = u[(t & 1) + 2 + 4 * (t >> 1)];
+                zo[t] = u[t + 4];
+            }
+            T o[8];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) o[n] = u[n ^ M];
+            T* pp = psi + (c * ndirs + d) * 8;
+            store4(pp, o[0], o[1], o[2], o[3]);
+            store4(pp + 4, o[4], o[5], o[6], o[7]);
+            if (jy == 7 && J + 1 < nTy)
+                store4(yf + (((long)(J + 1) * nz + kl) * nx + il) * 4, yo[0], yo[1], yo[2], yo[3]);
+            if (kz == 7 && K + 1 < nTz)
+                store4(zf + (((long)(K + 1) * ny + jl) * nx + il) * 4, zo[0], zo[1], zo[2], zo[3]);
+            if (ir == len - 1 && I + 1 < nTx)
+                store4(xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4, xin[0], xin[1], xin[2], xin[3]);
+        }
+    };
+    In3<T> s0{}, s1{};
+    fetch(-skew, s0);
+    for (int s = 0; s < nsteps; s += 2) {
+        step(s, s0, s1);
+        if (s + 1 < nsteps) step(s + 1, s1, s0);
+    }
+}
+
+template <typename T, int WPB>
+__global__ void __launch_bounds__(64 * WPB) sweep3d_kernel(int nx, int ny, int nz, int ndirs,
+                                                           const DirInfo* __restrict__ dirs, int transpose,
+                                                           const T* __restrict__ sigt, const T* __restrict__ src,
+                                                           T* __restrict__ xf, long xstride, T* __restrict__ yf,
+                                                           long ystride, T* __restrict__ zf, long zstride, int TX,
+                                                           int nTx, int nTy, int nTz, const int* __restrict__ tiles,
+                                                           T* __restrict__ psi) {
+    const int wave = threadIdx.x >> 6;
+    const int d = blockIdx.y * WPB + wave;
+    if (d >= ndirs) return;
+    const int tile = tiles[blockIdx.x];
+    const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
+    const DirInfo di = dirs[d];
+    const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1) | ((di.rz ^ transpose) << 2);
+    const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
+    T* xd = xf + d * xstride;
+    T* yd = yf + d * ystride;
+    T* zd = zf + d * zstride;
+#define SN_CASE(MM)                                                                                                \
+    case MM:                                                                                                       \
+        sweep3d_body<T, MM>(nx, ny, nz, ndirs, d, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, xd, yd, zd, \
+                            psi);                                                                                  \
+        break;
+    switch (m) {
+        SN_CASE(0)
+        SN_CASE(1)
+        SN_CASE(2)
+        SN_CASE(3)
+        SN_CASE(4)
+        SN_CASE(5)
+        SN_CASE(6)
+        SN_CASE(7)
+    }
+#undef SN_CASE
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transpose, const double* inflow,
+                             T* xf, T* yf, T* zf, hipStream_t st) {
+    long per = (long)g.ny * g.nz + (long)g.nx * g.nz + (g.dim == 3 ? (long)g.nx * g.ny : 0);
+    long total = per * g.ndirs;
+    int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(init_faces_kernel<T>, dim3(blocks), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz, g.ndirs, dirs,
+                       transpose, inflow, g.nbf, xf, g.xstride, yf, g.ystride, zf, g.zstride);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
+                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st) {
+    if (g.dim == 2) {
+        for (int ch = 0; ch < g.nchunk; ++ch) {
+            int row0 = ch * 1024;
+            int nrows = std::min(1024, g.ny - row0);
+            int nw = (nrows + 63) / 64;
+            hipLaunchKernelGGL(sweep2d_kernel<T>, dim3(g.ndirs), dim3(64 * nw), 0, st, g.nx, g.ny, g.ndirs, dirs,
+                               transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows, psi,
+                               sink);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    constexpr int WPB = 4;
+    int gy = (g.ndirs + WPB - 1) / WPB;
+    for (int p = 0; p < g.nplanes; ++p) {
+        int nt = plane_off[p + 1] - plane_off[p];
+        hipLaunchKernelGGL((sweep3d_kernel<T, WPB>), dim3(nt, gy), dim3(64 * WPB), 0, st, g.nx, g.ny, g.nz, g.ndirs,
+                           dirs, transpose, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx,
+                           g.nTy, g.nTz, tiles + plane_off[p], psi);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_init_faces<double>(const SweepGeom&, const DirInfo*, int, const double*, double*, double*,
+                                              double*, hipStream_t);
+template hipError_t launch_init_faces<float>(const SweepGeom&, const DirInfo*, int, const double*, float*, float*,
+                                             float*, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepGeom&, const DirInfo*, int, const double*, const double*,
+                                         double*, double*, double*, const int*, const int*, double*, double*,
+                                         hipStream_t);
+template hipError_t launch_sweep<float>(const SweepGeom&, const DirInfo*, int, const float*, const float*, float*,
+                                        float*, float*, const int*, const int*, float*, float*, hipStream_t);
+
+}  // namespace sn

@@ -1,0 +1,190 @@
+"""GPU (gfx950) path against the CPU oracle, through the C ABI.
+
+Tolerances: FP64 entry points agree with the oracle to 1e-12 (max-norm
+relative) per call, source-iteration iterates to 1e-10 (the spec parity
+bar); the FP32-sweep form is compared with the FP64 oracle in its own tests.
+Sizes span several sweep tiles / waves and a ragged tail in every axis.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import sninputs
+from gpu_util import context, dev, rel_l2, rel_max, random_problem, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _sweep_case(p, transpose, with_inflow, prec=0, seed=1):
+    from paper_2001_09196_amd import sn_sweep
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0, 1, (p.ncells, p.nn))
+    inflow = rng.uniform(0, 1, (p.ndirs, sninputs.inflow_size(p.dim, p.nx, p.ny, p.nz))) if with_inflow else None
+    ref = oracle.sweep(p, phi, p.q, inflow=inflow, transpose=transpose)
+    say(f"sweep {p.name} transpose={transpose} inflow={with_inflow} prec={prec}")
+    with context(p) as ctx:
+        dt = torch.float64 if prec == 0 else torch.float32
+        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=dt, device="cuda")
+        sn_sweep(ctx, dev(phi), dev(p.q), dev(inflow) if inflow is not None else None, transpose, prec, psi)
+        torch.cuda.synchronize()
+        got = psi.double().cpu().numpy()
+    return got, ref
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (37, 150), (5, 1100)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sweep2d_fp64(shape, transpose):
+    p = random_problem(2, shape[0], shape[1], 1, order=4, seed=shape[1])
+    got, ref = _sweep_case(p, transpose, with_inflow=True)
+    assert rel_max(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,order", [((70, 19, 11), 4), ((9, 17, 23), 8), ((33, 8, 8), 4)])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sweep3d_fp64(shape, order, transpose):
+    p = random_problem(3, *shape, order=order, seed=sum(shape))
+    got, ref = _sweep_case(p, transpose, with_inflow=True)
+    assert rel_max(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (37, 150, 1)), (3, (70, 19, 11))])
+def test_sweep_fp32_close(dim, shape):
+    p = random_problem(dim, *shape, order=4, seed=3)
+    got, ref = _sweep_case(p, False, with_inflow=True, prec=1)
+    assert rel_max(got, ref) <= 2e-5
+
+
+def test_sweep_vacuum_null_inputs():
+    from paper_2001_09196_amd import sn_sweep
+    p = random_problem(2, 20, 70, 1, seed=4)
+    say("sweep null inputs")
+    ref = oracle.sweep(p, None, None)
+    assert np.all(ref == 0)
+    p2 = random_problem(3, 10, 9, 9, seed=4)
+    ref2 = oracle.sweep(p2, None, p2.q)
+    for pp, rr, q in ((p, ref, None), (p2, ref2, p2.q)):
+        with context(pp) as ctx:
+            psi = torch.full((pp.ncells, pp.ndirs, pp.nn), 7.0, dtype=torch.float64, device="cuda")
+            sn_sweep(ctx, None, dev(q) if q is not None else None, None, False, 0, psi)
+            assert rel_max(psi.cpu().numpy(), rr) <= 1e-12 if np.any(rr) else np.all(psi.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_scalar_flux(prec):
+    from paper_2001_09196_amd import sn_scalar_flux
+    p = random_problem(3, 12, 10, 9, order=8, seed=5)
+    rng = np.random.default_rng(6)
+    psi = rng.standard_normal((p.ncells, p.ndirs, p.nn))
+    if prec == 1:
+        psi = psi.astype(np.float32).astype(np.float64)
+    ref = oracle.moment(p, psi)
+    say(f"moment prec={prec}")
+    with context(p) as ctx:
+        phi = torch.empty((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        sn_scalar_flux(ctx, dev(psi, torch.float64 if prec == 0 else torch.float32), prec, phi)
+        assert rel_max(phi.cpu().numpy(), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (16, 16, 1)), (2, (45, 70, 1)), (3, (14, 11, 9))])
+@pytest.mark.parametrize("mass_kind", [0, 1])
+def test_dsa_parity(dim, shape, mass_kind):
+    from paper_2001_09196_amd import sn_dsa_thick_correct
+    p = random_problem(dim, *shape, order=4, seed=7 + shape[0])
+    rng = np.random.default_rng(8)
+    phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    ref, it_o, _ = oracle.dsa_correct(p, phi_old, phi_si, mass_kind=mass_kind, cg_rtol=1e-14)
+    say(f"dsa {p.name} mass_kind={mass_kind}")
+    with context(p) as ctx:
+        assert ctx.thick_count == int(np.count_nonzero(p.sigma_s >= p.eta))
+        out = torch.empty((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        st = sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out, cg_rtol=1e-14, cg_maxit=5000,
+                                  mass_kind=mass_kind)
+        got = out.cpu().numpy()
+    assert st["cg_relres"] <= 1e-14
+    assert rel_max(got, ref) <= 1e-11
+    thin = p.sigma_s < p.eta
+    assert np.array_equal(got[thin], phi_si[thin])
+
+
+def test_dsa_aliasing_and_no_thick():
+    from paper_2001_09196_amd import sn_dsa_thick_correct
+    p = random_problem(2, 30, 20, 1, seed=9)
+    rng = np.random.default_rng(1)
+    phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    ref, _, _ = oracle.dsa_correct(p, phi_old, phi_si, cg_rtol=1e-14)
+    say("dsa aliasing")
+    with context(p) as ctx:
+        a = dev(phi_si)
+        sn_dsa_thick_correct(ctx, dev(phi_old), a, a, cg_rtol=1e-14, cg_maxit=5000)
+        assert rel_max(a.cpu().numpy(), ref) <= 1e-11
+    with context(p, eta=math.inf) as ctx:
+        assert ctx.thick_count == 0
+        out = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        st = sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out)
+        assert st["cg_iters"] == 0
+        assert np.array_equal(out.cpu().numpy(), phi_si)
+
+
+def _si_gpu(p, **kw):
+    from paper_2001_09196_amd import sn_source_iterate
+    with context(p, eta=kw.pop("eta", None)) as ctx:
+        phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        r = sn_source_iterate(ctx, dev(p.q), None, phi, **kw)
+        r["phi"] = phi.cpu().numpy()
+    return r
+
+
+def test_si_per_iterate_c1():
+    """Fixed number of iterations, inner CG at 1e-13: every iterate agrees."""
+    p = sninputs.config("c1")
+    for k in (1, 2, 5, 12):
+        say(f"SI c1 k={k}")
+        ref = oracle.source_iterate(p, tol=0.0, max_it=k, use_dsa=True, cg_rtol=1e-13)
+        got = _si_gpu(p, tol=0.0, max_it=k, use_dsa=True, cg_rtol=1e-13, cg_maxit=5000)
+        assert got["iters"] == ref["iters"] == k
+        assert rel_l2(got["phi"], ref["phi"]) <= 1e-10
+        assert np.allclose(got["res_hist"], ref["res_hist"], rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("use_dsa", [True, False])
+def test_si_converged_c1(use_dsa):
+    p = sninputs.config("c1")
+    max_it = 400 if use_dsa else 60000
+    tol = 1e-12 if use_dsa else 1e-13
+    say(f"SI c1 converged dsa={use_dsa}")
+    ref = oracle.source_iterate(p, tol=1e-13, max_it=2000, use_dsa=True, cg_rtol=1e-13)
+    got = _si_gpu(p, tol=tol, max_it=max_it, use_dsa=use_dsa, cg_rtol=1e-13, cg_maxit=5000)
+    assert got["rc"] == 0
+    assert rel_l2(got["phi"], ref["phi"]) <= (1e-10 if use_dsa else 3e-10)
+
+
+def test_si_per_iterate_3d():
+    p = random_problem(3, 20, 11, 9, order=4, seed=11)
+    say("SI 3d per-iterate")
+    ref = oracle.source_iterate(p, tol=0.0, max_it=6, use_dsa=True, cg_rtol=1e-13)
+    got = _si_gpu(p, tol=0.0, max_it=6, use_dsa=True, cg_rtol=1e-13, cg_maxit=5000)
+    assert rel_l2(got["phi"], ref["phi"]) <= 1e-10
+    assert np.allclose(got["res_hist"], ref["res_hist"], rtol=1e-9, atol=0)
+
+
+def test_si_eta_inf_equals_plain():
+    p = sninputs.config("c1")
+    say("SI eta=inf")
+    a = _si_gpu(p, tol=0.0, max_it=8, use_dsa=True, eta=math.inf)
+    b = _si_gpu(p, tol=0.0, max_it=8, use_dsa=False)
+    assert np.array_equal(a["phi"], b["phi"])
+
+
+def test_si_fp32_form_c1():
+    p = sninputs.config("c1")
+    say("SI fp32 c1")
+    ref = oracle.source_iterate(p, tol=1e-13, max_it=2000, use_dsa=True, cg_rtol=1e-13)
+    got = _si_gpu(p, tol=1e-8, max_it=2000, use_dsa=True, prec=1, cg_rtol=1e-10, cg_maxit=5000)
+    assert got["rc"] == 0
+    assert rel_l2(got["phi"], ref["phi"]) <= 1e-5
