@@ -137,9 +137,10 @@ typedef struct {
     sn_precision prec;         /* precision of the sweep; moment, residual and DSA are FP64.  With
                                   SN_FP32, iterations after the first sweep the increment
                                   sigma_s (phi_i - phi_{i-1}) and add its FP64 moment to phi_SI;
-                                  when that residual first meets tol, phi_SI is recomputed by one
-                                  FP64 sweep and the iteration stops only if the exact residual
-                                  meets tol as well (FP64 psi workspace allocated on demand) */
+                                  phi_SI is recomputed by one FP64 sweep when that residual first
+                                  drops below 1e-4 and whenever it meets tol, and the iteration
+                                  stops only on the exact residual (FP64 psi workspace allocated
+                                  on demand) */
     sn_dsa_opts dsa;
     int transpose;             /* 1: adjoint iteration with L_d^{-T} sweeps */
     double *phi_ckpt;          /* device [max_it][ncells][nn] or NULL: phi after every iteration */
@@ -174,6 +175,17 @@ int sn_source_iterate(sn_context *ctx, const double *q, const double *inflow, do
  * g_t, g_s: device [ncells] FP64 outputs. */
 int sn_gradient(sn_context *ctx, const void *psi, const void *psi_adj, sn_precision prec, const double *phi,
                 const double *chi, double *g_t, double *g_s);
+
+/* Linear response of a solution (the detector functionals of the adjoint):
+ *   J = sum_c r_c int_c phi                                        (r != NULL)
+ *     + sum_{d: Omega_d.n > 0} w_d (Omega_d.n) int_face psi_d       (face >= 0)
+ * r: device [ncells] FP64 detector density or NULL (then phi must be NULL);
+ * face: -1 (none) or domain face 2*axis + side (side 1 = high end of the
+ * axis); psi: device [ncells][ndirs][nn] in prec (needed when face >= 0).
+ * The sum is reduced in a fixed order on the device; *out (host) is written
+ * after a stream synchronisation. */
+int sn_response(sn_context *ctx, const double *r, const double *phi, int face, const void *psi,
+                sn_precision prec, double *out);
 
 /* Kernel timing for measurement.  When enabled, every subsequent call records
  * HIP events on the context's stream around the sweep kernels of each sweep

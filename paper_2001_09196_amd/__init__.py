@@ -1,9 +1,11 @@
 """MI355X (gfx950) S_N source iteration with heterogeneous (thick-only) DSA.
 
 The compute path is libsn.so (HIP kernels behind the C ABI of include/sn.h);
-`binding` marshals torch device tensors into it.  Nothing here falls back to
+`binding` marshals torch device tensors into it and `adjoint` wraps the
+adjoint gradient in a torch.autograd.Function.  Nothing here falls back to
 the CPU: without the built library the binding raises.
 """
 from . import binding  # noqa: F401
 from .binding import (SN_FP32, SN_FP64, Context, SnError, sn_dsa_thick_correct,  # noqa: F401
-                      sn_gradient, sn_scalar_flux, sn_source_iterate, sn_sweep)
+                      sn_gradient, sn_kernel_timing, sn_response, sn_scalar_flux, sn_set_kernel_timing,
+                      sn_source_iterate, sn_sweep)

@@ -23,7 +23,8 @@ SN_FP64, SN_FP32 = 0, 1
 
 # every symbol declared in include/sn.h
 EXPORTED = ("sn_context_create", "sn_context_destroy", "sn_inflow_size", "sn_thick_count", "sn_sweep",
-            "sn_scalar_flux", "sn_dsa_thick_correct", "sn_source_iterate", "sn_gradient", "sn_set_kernel_timing",
+            "sn_scalar_flux", "sn_dsa_thick_correct", "sn_source_iterate", "sn_gradient", "sn_response",
+            "sn_set_kernel_timing",
             "sn_kernel_timing", "sn_last_error")
 
 
@@ -94,6 +95,8 @@ def lib():
         L.sn_source_iterate.restype = ip
         L.sn_gradient.argtypes = [vp, vp, vp, ip, vp, vp, vp, vp]
         L.sn_gradient.restype = ip
+        L.sn_response.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(ctypes.c_double)]
+        L.sn_response.restype = ip
         L.sn_set_kernel_timing.argtypes = [vp, ip]
         L.sn_set_kernel_timing.restype = ip
         dp = ctypes.POINTER(ctypes.c_double)
@@ -219,6 +222,12 @@ def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_d
 def sn_gradient(ctx: Context, psi, psi_adj, prec: int, phi, chi, g_t, g_s):
     _check(lib().sn_gradient(ctx.handle, _ptr(psi), _ptr(psi_adj), int(prec), _ptr(phi), _ptr(chi), _ptr(g_t),
                              _ptr(g_s)))
+
+
+def sn_response(ctx: Context, r=None, phi=None, face: int = -1, psi=None, prec: int = SN_FP64) -> float:
+    out = ctypes.c_double()
+    _check(lib().sn_response(ctx.handle, _ptr(r), _ptr(phi), int(face), _ptr(psi), int(prec), ctypes.byref(out)))
+    return out.value
 
 
 def sn_set_kernel_timing(ctx: Context, enable: bool):

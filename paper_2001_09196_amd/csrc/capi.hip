@@ -76,7 +76,8 @@ struct sn_context {
     double eta = 1.0;
     hipStream_t stream = nullptr;
     std::vector<DirInfo> hdirs;
-    std::vector<double> hw;
+    std::vector<double> hw, omega;
+    DevBuf<double> wn;
     DevBuf<DirInfo> dirs;
     DevBuf<double> w, sigt, sigs;
     DevBuf<float> sigt32;
@@ -86,12 +87,13 @@ struct sn_context {
     DevBuf<double> binv;
     DsaGeom dg{};
     int nparts = 1;
-    DevBuf<double> cx, cr, cz, cp, cq, parta, partb;
+    DevBuf<double> cx, cr, cz, cp, cp1, cq, parta, partb;
+    DevBuf<int> nbr;
     DevBuf<CgScalars> scal;
     int cg_hint = 8;
     // sweep
     SweepGeom sg{};
-    DevBuf<int> tiles;
+    DevBuf<int> tiles, groups;
     std::vector<int> plane_off;
     DevBuf<double> xf64, yf64, zf64, src64, sink64;
     DevBuf<float> xf32, yf32, zf32, src32, sink32;
@@ -200,22 +202,25 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     size_t e0 = 0, e1 = 0;
     int rc;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    HIPCHK(launch_cg_init(ctx->scal.p, ctx->stream));
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
                           ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, ctx->stream));
-    HIPCHK(launch_cg_init(ctx->nparts, ctx->partb.p, ctx->scal.p, o->cg_rtol, ctx->stream));
     CgScalars hs{};
     int it = 0;
-    int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit));
+    // launch batches of iterations and poll the device-side stop flag; the
+    // first batch is sized by the previous call's iteration count
+    int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit + 1));
     while (true) {
-        int nb = std::min(batch, o->cg_maxit - it);
+        int nb = std::min(batch, o->cg_maxit + 1 - it);
         for (int b = 0; b < nb; ++b)
-            HIPCHK(launch_cg_iteration(g, ctx->thick.p, ctx->slot.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cx.p,
-                                       ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cq.p, ctx->parta.p, ctx->partb.p,
-                                       ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b, ctx->stream));
+            HIPCHK(launch_cg_iteration(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cx.p,
+                                       ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cp1.p, ctx->cq.p, ctx->parta.p,
+                                       ctx->partb.p, ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b,
+                                       ctx->stream));
         it += nb;
         HIPCHK(hipMemcpyAsync(&hs, ctx->scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
-        if (hs.done || it >= o->cg_maxit) break;
+        if (hs.done || it > o->cg_maxit) break;
         batch = 4;
     }
     HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
@@ -261,6 +266,7 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->evpool.clear();
     ctx->dirs.release();
     ctx->w.release();
+    ctx->wn.release();
     ctx->sigt.release();
     ctx->sigs.release();
     ctx->sigt32.release();
@@ -274,11 +280,14 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->cr.release();
     ctx->cz.release();
     ctx->cp.release();
+    ctx->cp1.release();
+    ctx->nbr.release();
     ctx->cq.release();
     ctx->parta.release();
     ctx->partb.release();
     ctx->scal.release();
     ctx->tiles.release();
+    ctx->groups.release();
     ctx->xf64.release();
     ctx->yf64.release();
     ctx->zf64.release();
@@ -342,6 +351,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     c->stream = (hipStream_t)stream;
     const double h[3] = {mesh->hx, mesh->hy, dim == 3 ? mesh->hz : 1.0};
     c->hw.assign(quad->w, quad->w + quad->ndirs);
+    c->omega.assign(quad->omega, quad->omega + 3 * quad->ndirs);
     c->hdirs.resize(quad->ndirs);
     for (int d = 0; d < quad->ndirs; ++d) {
         const double* o = quad->omega + 3 * d;
@@ -398,8 +408,8 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         if (const char* e = std::getenv("SN_SWEEP_TX")) tx = std::max(1, std::atoi(e));
         g.TX = std::min(tx, mesh->nx);
         g.nTx = (mesh->nx + g.TX - 1) / g.TX;
-        g.nTy = (mesh->ny + 7) / 8;
-        g.nTz = (mesh->nz + 7) / 8;
+        g.nTy = (mesh->ny + 3) / 4;
+        g.nTz = (mesh->nz + 3) / 4;
         if (g.nTx > 1023 || g.nTy > 1023 || g.nTz > 1023)
             return fail(SN_ERR_UNSUPPORTED, "more than 1023 sweep tiles along an axis");
         g.nplanes = g.nTx + g.nTy + g.nTz - 2;
@@ -419,6 +429,46 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         }
         if ((rc = c->tiles.ensure(tl.size()))) return rc;
         HIPCHK(hipMemcpy(c->tiles.p, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice));
+        // direction groups: directions with the same reflection (octant), in
+        // index order, four per group
+        std::vector<std::vector<int>> cls(8);
+        for (int d = 0; d < c->ndirs; ++d) {
+            const DirInfo& di = c->hdirs[d];
+            cls[di.rx | (di.ry << 1) | (di.rz << 2)].push_back(d);
+        }
+        int ncls = 0, gpc = 1;
+        for (auto& v : cls)
+            if (!v.empty()) {
+                ++ncls;
+                gpc = std::max(gpc, (int)((v.size() + 3) / 4));
+            }
+        if (gpc > 6) return fail(SN_ERR_UNSUPPORTED, "more than 24 directions per octant");
+        // per group: four direction ids (-1 = empty), the first id if the
+        // valid ones are consecutive (else -1), the number of valid ids
+        std::vector<int> gr((size_t)ncls * gpc * 6, -1);
+        int ci = 0;
+        for (auto& v : cls) {
+            if (v.empty()) continue;
+            for (size_t e = 0; e < v.size(); ++e) gr[((size_t)ci * gpc + e / 4) * 6 + e % 4] = v[e];
+            for (int gidx = 0; gidx < gpc; ++gidx) {
+                int* gg = &gr[((size_t)ci * gpc + gidx) * 6];
+                int nv = 0;
+                bool consec = true;
+                for (int k = 0; k < 4; ++k)
+                    if (gg[k] >= 0) {
+                        if (gg[k] != gg[0] + k) consec = false;
+                        ++nv;
+                    }
+                gg[5] = nv;
+                gg[4] = (nv > 0 && consec) ? gg[0] : -1;
+            }
+            ++ci;
+        }
+        if ((rc = c->groups.ensure(gr.size()))) return rc;
+        HIPCHK(hipMemcpy(c->groups.p, gr.data(), gr.size() * sizeof(int), hipMemcpyHostToDevice));
+        g.nclasses = ncls;
+        g.groups_per_class = gpc;
+        g.groups = c->groups.p;
     }
 
     // thick set
@@ -449,11 +499,13 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     const long nf = (long)nthick * c->nn;
     c->nparts = std::max(1, std::min((nthick + 255) / 256, 1024));
     if ((rc = c->binv.ensure((size_t)std::max(nthick, 1) * c->nn * c->nn)) || (rc = c->cx.ensure(nf)) ||
-        (rc = c->cr.ensure(nf)) || (rc = c->cz.ensure(nf)) || (rc = c->cp.ensure(nf)) || (rc = c->cq.ensure(nf)) ||
+        (rc = c->cr.ensure(nf)) || (rc = c->cz.ensure(nf)) || (rc = c->cp.ensure(nf)) || (rc = c->cp1.ensure(nf)) ||
+        (rc = c->cq.ensure(nf)) || (rc = c->nbr.ensure((size_t)std::max(nthick, 1) * 2 * dim)) ||
         (rc = c->parta.ensure(2 * c->nparts)) || (rc = c->partb.ensure(2 * c->nparts)) ||
         (rc = c->scal.ensure(1)))
         return rc;
     HIPCHK(launch_block_jacobi(dg, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, c->binv.p, c->stream));
+    HIPCHK(launch_neighbour_table(dg, c->thick.p, c->slot.p, c->nbr.p, c->stream));
     c->nrpart = (int)std::max<long>(1, std::min<long>((nc * c->nn + 255) / 256, 1024));
     if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -553,7 +605,8 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     double bnorm = 1.0, first = -1.0;
     int it = 0;
     int status = SN_ERR_NOT_CONVERGED;
-    bool verified = false;  // FP32 form: phi_SI last recomputed by an FP64 sweep
+    bool verified = false;   // FP32 form: phi_SI last recomputed by an FP64 sweep
+    bool refreshed = false;  // FP32 form: the 1e-4 refresh sweep has been done
     for (; it < o->max_it; ++it) {
         if (!incr || it == 0) {
             if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, o->prec, psi))) return rc;
@@ -578,10 +631,15 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
             }
             if (bnorm == 0.0) bnorm = 1.0;
         }
-        if (incr && std::sqrt(r3[0]) / bnorm <= o->tol) {
-            // The FP32 form may only stop on an exact residual: recompute
-            // phi_SI from phi with one FP64 sweep and test that instead; the
-            // increments then continue from this FP64 value.
+        const double res32 = std::sqrt(r3[0]) / bnorm;
+        const double refresh_at = 1e-4;
+        if (incr && (res32 <= o->tol || (!refreshed && res32 <= refresh_at && o->tol < refresh_at))) {
+            // FP64 sweeps in the FP32 form: once when the residual first
+            // drops below 1e-4 (this discards the FP32 rounding accumulated
+            // while the increments were large) and whenever it meets tol (the
+            // form may only stop on an exact residual).  phi_SI is recomputed
+            // from phi with one FP64 sweep and the increments continue from it.
+            refreshed = true;
             if ((rc = ctx->psi64.ensure(npsi))) return rc;
             if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->psi64.p))) return rc;
             if ((rc = do_moment(ctx, ctx->psi64.p, SN_FP64, ctx->phisi.p))) return rc;
@@ -630,6 +688,43 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+int sn_response(sn_context* ctx, const double* r, const double* phi, int face, const void* psi, sn_precision prec,
+                double* out) {
+    g_err.clear();
+    if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    const int dim = ctx->mesh.dim;
+    if (face < -1 || face >= 2 * dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * dim - 1);
+    if (face >= 0 && !psi) return fail(SN_ERR_INVALID, "psi is needed for a face functional");
+    if ((r == nullptr) != (phi == nullptr)) return fail(SN_ERR_INVALID, "r and phi must be given together");
+    if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
+    int rc;
+    if ((rc = ctx->wn.ensure(ctx->ndirs))) return rc;
+    std::vector<double> wn(ctx->ndirs, 0.0);
+    if (face >= 0) {
+        const int ax = face >> 1;
+        const double sgn = (face & 1) ? 1.0 : -1.0;
+        for (int d = 0; d < ctx->ndirs; ++d) {
+            double on = sgn * ctx->omega[3 * d + ax];
+            wn[d] = on > 0 ? ctx->hw[d] * on : 0.0;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->wn.p, wn.data(), ctx->ndirs * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, dim == 3 ? ctx->mesh.hz : 1.0};
+    double res[3];
+    if (prec == SN_FP64)
+        HIPCHK(launch_response<double>(ctx->nc, ctx->nn, ctx->mesh.nx, ctx->mesh.ny, ctx->mesh.nz, h, r, phi, face,
+                                       ctx->ndirs, ctx->wn.p, (const double*)psi, ctx->rpart.p, ctx->nrpart,
+                                       ctx->res3.p, ctx->stream));
+    else
+        HIPCHK(launch_response<float>(ctx->nc, ctx->nn, ctx->mesh.nx, ctx->mesh.ny, ctx->mesh.nz, h, r, phi, face,
+                                      ctx->ndirs, ctx->wn.p, (const float*)psi, ctx->rpart.p, ctx->nrpart,
+                                      ctx->res3.p, ctx->stream));
+    HIPCHK(hipMemcpyAsync(res, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = res[0] + res[1];
+    return 0;
 }
 
 int sn_gradient(sn_context* ctx, const void* psi, const void* psi_adj, sn_precision prec, const double* phi,

@@ -234,6 +234,133 @@ __device__ void sip_cell_apply(const DsaGeom& g, long cell, const int* __restric
     }
 }
 
+// neighbour table of each thick cell: for face f = 2*axis + side, the slot of
+// the neighbour across that face, -1 for a thin neighbour, -2 at the domain
+// boundary
+template <int NN>
+__global__ void neighbour_table_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                       const int* __restrict__ slot_of_cell, int* __restrict__ nbr) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long cell = thick_cell[s];
+        const int pos[3] = {(int)(cell % g.nx), (int)((cell / g.nx) % g.ny), (int)(cell / ((long)g.nx * g.ny))};
+        const int ext[3] = {g.nx, g.ny, g.nz};
+        const long stride[3] = {1, g.nx, (long)g.nx * g.ny};
+        for (int ax = 0; ax < DIM; ++ax)
+            for (int sd = 0; sd < 2; ++sd) {
+                const int np = pos[ax] + (sd ? 1 : -1);
+                int v = -2;
+                if (np >= 0 && np < ext[ax]) v = slot_of_cell[cell + (sd ? stride[ax] : -stride[ax])];
+                nbr[s * 2 * DIM + 2 * ax + sd] = v < 0 ? (np >= 0 && np < ext[ax] ? -1 : -2) : v;
+            }
+    }
+}
+
+hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
+                                  hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    int blocks = std::min((g.nthick + 255) / 256, 65536);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(neighbour_table_kernel<4>, dim3(blocks), dim3(256), 0, st, g, thick_cell, slot_of_cell, nbr);
+    else
+        hipLaunchKernelGGL(neighbour_table_kernel<8>, dim3(blocks), dim3(256), 0, st, g, thick_cell, slot_of_cell, nbr);
+    return hipGetLastError();
+}
+
+// Rows of D_ff u for thick cell `cell` (slot s) with the neighbour values
+// supplied by get(nslot, un) -- the same bilinear form as sip_cell_apply,
+// reading neighbours through the neighbour table.
+template <int NN, typename Get>
+__device__ __forceinline__ void sip_rows(const DsaGeom& g, int s, long cell, const int* __restrict__ nbr,
+                                         const int* __restrict__ thick_cell, const double* __restrict__ sigma_t,
+                                         const double* __restrict__ sigma_s, const double uK[NN], Get get,
+                                         double out[NN]) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    const double DK = 1.0 / (3.0 * sigma_t[cell]);
+    const double sa = sigma_t[cell] - sigma_s[cell];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) out[n] = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        double t[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = uK[n];
+#pragma unroll
+        for (int o = 0; o < DIM; ++o) {
+            if (o == ax) stiff_along<NN>(g.h[o], o, t);
+            else mass_along<NN>(g.h[o], o, t);
+        }
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = fma(DK, t[n], out[n]);
+    }
+    {
+        double t[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) t[n] = uK[n];
+#pragma unroll
+        for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = fma(sa, t[n], out[n]);
+    }
+#pragma unroll
+    for (int ax = 0; ax < DIM; ++ax) {
+        const int st = 1 << ax;
+        const double h = g.h[ax];
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const int ns = nbr[s * 2 * DIM + 2 * ax + sd];
+            double t[NN];
+            if (ns == -2) {
+#pragma unroll
+                for (int n = 0; n < NN; ++n) t[n] = (((n >> ax) & 1) == sd) ? uK[n] : 0.0;
+#pragma unroll
+                for (int o = 0; o < DIM; ++o)
+                    if (o != ax) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+                for (int n = 0; n < NN; ++n)
+                    if (((n >> ax) & 1) == sd) out[n] = fma(g.kappa0[ax], t[n], out[n]);
+                continue;
+            }
+            double un[NN];
+            double Dn = 0.0;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) un[n] = 0.0;
+            if (ns >= 0) {
+                Dn = 1.0 / (3.0 * sigma_t[thick_cell[ns]]);
+                get(ns, un);
+            }
+            double kap = g.kappa0[ax];
+            const double Dmax = DK > Dn ? DK : Dn;
+            if (8.0 * Dmax / h > kap) kap = 8.0 * Dmax / h;
+            double J[NN], G[NN];
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                if (((n >> ax) & 1) == sd) {
+                    J[n] = uK[n] - un[n ^ st];
+                    G[n] = 0.5 * (DK * (uK[n] - uK[n ^ st]) + Dn * (un[n] - un[n ^ st])) / h;
+                } else {
+                    J[n] = 0.0;
+                    G[n] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < DIM; ++o)
+                if (o != ax) {
+                    mass_along<NN>(g.h[o], o, J);
+                    mass_along<NN>(g.h[o], o, G);
+                }
+            const double hd = 0.5 * DK / h;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                if (((n >> ax) & 1) == sd) {
+                    out[n] += -G[n] + kap * J[n] - hd * J[n];
+                    out[n ^ st] += hd * J[n];
+                }
+            }
+        }
+    }
+}
+
 // diagonal block of D_ff for each thick cell, inverted (Gauss-Jordan; the
 // block is symmetric positive definite, so no pivoting is needed)
 template <int NN>
@@ -378,7 +505,7 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
             x[e] = 0.0;
             r[e] = t[n];
             z[e] = zz[n];
-            p[e] = zz[n];
+            p[e] = 0.0;
             rz = fma(t[n], zz[n], rz);
             bb = fma(t[n], t[n], bb);
         }
@@ -403,44 +530,74 @@ hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double*
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) cg_init_kernel(int nparts, const double* __restrict__ part, CgScalars* s,
-                                                      double rtol) {
-    __shared__ double sh[256];
-    double rz = reduce_parts(part, nparts, sh);
-    double bb = reduce_parts(part + nparts, nparts, sh);
+__global__ void cg_init_kernel(CgScalars* s) {
     if (threadIdx.x == 0) {
-        s->rz[0] = rz;
-        s->bb = bb;
-        s->rr = bb;
+        s->rz[0] = s->rz[1] = 0.0;
+        s->bb = s->rr = 0.0;
         s->iters = 0;
         s->breakdown = 0;
-        s->done = (bb == 0.0) ? 1 : 0;
+        s->done = 0;
     }
 }
 
-hipError_t launch_cg_init(int nparts, const double* part, CgScalars* s, double rtol, hipStream_t st) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(256), 0, st, nparts, part, s, rtol);
+hipError_t launch_cg_init(CgScalars* s, hipStream_t st) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(64), 0, st, s);
     return hipGetLastError();
 }
 
-// q = A p ; partials p.q
+// Two kernels per CG iteration `it`:
+//   apply:  every block reduces the r.z / r.r partials of the previous update
+//           (of the right-hand-side kernel at it = 0) and stops the solve when
+//           ||r|| <= rtol ||b|| or it = maxit; otherwise
+//           beta = rz_it / rz_{it-1} (0 at it = 0), p = z + beta p_old for its
+//           own and its neighbours' DOFs (on the fly: z and p_old are complete
+//           from the previous iteration), q = A p, partials p.q.
+//   update: alpha = rz_it / p.q; x += alpha p; r -= alpha q; z = B^{-1} r;
+//           partials r.z, r.r.
+// p alternates between two buffers (read p_old, write p) so that neighbours
+// never see a half-updated direction.  Block 0 of the apply kernel stores
+// rz_it in slot it&1 while the other blocks read slot (it-1)&1.
 template <int NN>
 __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __restrict__ thick_cell,
-                                                       const int* __restrict__ slot_of_cell,
+                                                       const int* __restrict__ nbr,
                                                        const double* __restrict__ sigma_t,
                                                        const double* __restrict__ sigma_s,
-                                                       const double* __restrict__ p, double* __restrict__ q,
-                                                       double* __restrict__ part, const CgScalars* __restrict__ s) {
+                                                       const double* __restrict__ z, const double* __restrict__ p_old,
+                                                       double* __restrict__ p_new, double* __restrict__ q,
+                                                       const double* __restrict__ part_rz, double* __restrict__ part,
+                                                       int nparts, CgScalars* s, double rtol, int maxit, int it) {
     if (s->done) return;
     __shared__ double sh[256];
+    const double rz = reduce_parts(part_rz, nparts, sh);
+    const double rr = reduce_parts(part_rz + nparts, nparts, sh);
+    const double bb = it == 0 ? rr : s->bb;
+    if (sqrt(rr) <= rtol * sqrt(bb) || it >= maxit || bb == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            s->bb = bb;
+            s->rr = rr;
+            s->iters = it;
+            s->done = 1;
+        }
+        return;
+    }
+    const double beta = it == 0 ? 0.0 : rz / s->rz[(it + 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rz[it & 1] = rz;
+        s->rr = rr;
+        if (it == 0) s->bb = bb;
+    }
+    auto pdir = [&](int slot, double out[NN]) {
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = fma(beta, p_old[(long)slot * NN + n], z[(long)slot * NN + n]);
+    };
     double pq = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
         double uK[NN], o[NN];
-#pragma unroll
-        for (int n = 0; n < NN; ++n) uK[n] = p[(long)t * NN + n];
-        sip_cell_apply<NN>(g, thick_cell[t], slot_of_cell, sigma_t, sigma_s, uK, p, false, o);
+        pdir(t, uK);
+        sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, pdir, o);
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
+            p_new[(long)t * NN + n] = uK[n];
             q[(long)t * NN + n] = o[n];
             pq = fma(uK[n], o[n], pq);
         }
@@ -449,21 +606,21 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
     if (threadIdx.x == 0) part[blockIdx.x] = pq;
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; z = B^{-1} r; partials r.z, r.r
 template <int NN>
 __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double* __restrict__ binv,
                                                         double* __restrict__ x, double* __restrict__ r,
                                                         double* __restrict__ z, const double* __restrict__ p,
                                                         const double* __restrict__ q,
-                                                        const double* __restrict__ part_in,
+                                                        const double* __restrict__ part_pq,
                                                         double* __restrict__ part_out, int nparts, CgScalars* s,
                                                         int it) {
     if (s->done) return;
     __shared__ double sh[256];
-    const double pq = reduce_parts(part_in, nparts, sh);
+    const double pq = reduce_parts(part_pq, nparts, sh);
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             s->breakdown = 1;
+            s->iters = it;
             s->done = 1;
         }
         return;
@@ -495,50 +652,26 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
     }
 }
 
-// beta = rz_new / rz; p = z + beta p.  rz lives in two slots indexed by the
-// iteration parity: this kernel reads slot it&1 and block 0 writes the new
-// value into the other slot, so no block can see a half-updated scalar.
-__global__ void __launch_bounds__(256) cg_direction_kernel(long nf, double* __restrict__ p,
-                                                           const double* __restrict__ z,
-                                                           const double* __restrict__ part, int nparts,
-                                                           CgScalars* s, double rtol, int maxit, int it) {
-    if (s->done) return;
-    __shared__ double sh[256];
-    const double rz_new = reduce_parts(part, nparts, sh);
-    const double rr = reduce_parts(part + nparts, nparts, sh);
-    const bool conv = sqrt(rr) <= rtol * sqrt(s->bb);
-    const bool stop = conv || it + 1 >= maxit;
-    if (!stop) {
-        const double beta = rz_new / s->rz[it & 1];
-        for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += (long)gridDim.x * blockDim.x)
-            p[e] = fma(beta, p[e], z[e]);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        s->rz[(it + 1) & 1] = rz_new;
-        s->rr = rr;
-        s->iters = it + 1;
-        if (stop) s->done = 1;
-    }
-}
-
-hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
-                               const double* sigma_t, const double* sigma_s, const double* binv, double* x,
-                               double* r, double* z, double* p, double* q, double* part_a, double* part_b,
-                               int nparts, CgScalars* s, double rtol, int maxit, int it, hipStream_t st) {
-    const long nf = (long)g.nthick * g.nn;
+// iteration `it`; with check_only only the apply kernel's stop test runs
+hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                               const double* sigma_s, const double* binv, double* x, double* r, double* z,
+                               double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
+                               CgScalars* s, double rtol, int maxit, int it, hipStream_t st) {
+    double* p_old = (it & 1) ? p1 : p0;
+    double* p_new = (it & 1) ? p0 : p1;
     if (g.nn == 4) {
-        hipLaunchKernelGGL(cg_apply_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
-                           sigma_s, p, q, part_a, s);
-        hipLaunchKernelGGL(cg_update_kernel<4>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p, q, part_a,
-                           part_b, nparts, s, it);
+        hipLaunchKernelGGL(cg_apply_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
+        if (it < maxit)
+            hipLaunchKernelGGL(cg_update_kernel<4>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
+                               part_a, part_b, nparts, s, it);
     } else {
-        hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, slot_of_cell, sigma_t,
-                           sigma_s, p, q, part_a, s);
-        hipLaunchKernelGGL(cg_update_kernel<8>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p, q, part_a,
-                           part_b, nparts, s, it);
+        hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
+        if (it < maxit)
+            hipLaunchKernelGGL(cg_update_kernel<8>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
+                               part_a, part_b, nparts, s, it);
     }
-    hipLaunchKernelGGL(cg_direction_kernel, dim3(nparts), dim3(256), 0, st, nf, p, z, part_b, nparts, s, rtol, maxit,
-                       it);
     return hipGetLastError();
 }
 

@@ -207,6 +207,84 @@ hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const do
     return hipGetLastError();
 }
 
+// Linear functionals of the solution, reduced deterministically:
+//   out[0] = sum_c r_c int_c phi            (volume detector, r per cell)
+//   out[1] = sum_{d: Omega_d.n > 0} w_d (Omega_d.n) int_face psi_d
+//            (partial outflow current through one domain face)
+template <typename T, int NN>
+__global__ void __launch_bounds__(256) response_part_kernel(long nc, int nx, int ny, int nz, double hx, double hy,
+                                                            double hz, const double* __restrict__ r,
+                                                            const double* __restrict__ phi, int face, int ndirs,
+                                                            const double* __restrict__ wn, const T* __restrict__ psi,
+                                                            double* __restrict__ part) {
+    __shared__ double sh[256];
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    const double h[3] = {hx, hy, hz};
+    double vol = DIM == 2 ? hx * hy : hx * hy * hz;
+    double a = 0.0, b = 0.0;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        if (r && phi) {
+            // int_c phi = vol / NN * sum of nodal values (Q1, exact)
+            double s = 0.0;
+#pragma unroll
+            for (int n = 0; n < NN; ++n) s += phi[c * NN + n];
+            a = fma(r[c] * vol / NN, s, a);
+        }
+        if (face >= 0 && psi) {
+            const int ax = face >> 1, side = face & 1;
+            const int pos[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long)nx * ny))};
+            const int ext[3] = {nx, ny, nz};
+            if (pos[ax] == (side ? ext[ax] - 1 : 0)) {
+                double area = 1.0;
+                for (int o = 0; o < DIM; ++o)
+                    if (o != ax) area *= h[o];
+                for (int d = 0; d < ndirs; ++d) {
+                    const double wd = wn[d];
+                    if (wd <= 0.0) continue;
+                    double s = 0.0;
+#pragma unroll
+                    for (int n = 0; n < NN; ++n)
+                        if (((n >> ax) & 1) == side) s += double(psi[(c * ndirs + d) * NN + n]);
+                    b = fma(wd * area / (NN / 2), s, b);
+                }
+            }
+        }
+    }
+    double t[2] = {a, b};
+    for (int k = 0; k < 2; ++k) {
+        sh[threadIdx.x] = t[k];
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[k * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_response(long nc, int nn, int nx, int ny, int nz, const double* h, const double* r,
+                           const double* phi, int face, int ndirs, const double* wn, const T* psi, double* part,
+                           int nparts, double* out, hipStream_t st) {
+    if (nn == 4)
+        hipLaunchKernelGGL((response_part_kernel<T, 4>), dim3(nparts), dim3(256), 0, st, nc, nx, ny, nz, h[0], h[1],
+                           h[2], r, phi, face, ndirs, wn, psi, part);
+    else
+        hipLaunchKernelGGL((response_part_kernel<T, 8>), dim3(nparts), dim3(256), 0, st, nc, nx, ny, nz, h[0], h[1],
+                           h[2], r, phi, face, ndirs, wn, psi, part);
+    // final fixed-order sum of the two partial arrays (third slot unused)
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, part, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_response<double>(long, int, int, int, int, const double*, const double*, const double*,
+                                            int, int, const double*, const double*, double*, int, double*,
+                                            hipStream_t);
+template hipError_t launch_response<float>(long, int, int, int, int, const double*, const double*, const double*,
+                                           int, int, const double*, const float*, double*, int, double*,
+                                           hipStream_t);
+
 template hipError_t launch_source<double>(long, int, const double*, const double*, const double*, const double*,
                                           double*, hipStream_t);
 template hipError_t launch_source<float>(long, int, const double*, const double*, const double*, const double*,

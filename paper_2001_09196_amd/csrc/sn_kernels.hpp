@@ -15,7 +15,11 @@ struct SweepGeom {
     int dim, nx, ny, nz, ndirs;
     long nbf;          // boundary-face nodes per direction in the inflow layout
     int TX;            // 3D tile length along x
-    int nTx, nTy, nTz; // 3D tile counts (tiles are TX x 8 x 8)
+    int nTx, nTy, nTz; // 3D tile counts (tiles are TX x 4 x 4 cells)
+    int nclasses;      // 3D: reflection classes with at least one direction
+    int groups_per_class;  // 3D: direction groups of four per class (max over classes)
+    const int* groups; // 3D: device [nclasses * groups_per_class][6]: four direction ids (-1 = empty),
+                       //     the first id if the valid ids are consecutive (else -1), the valid count
     int nplanes;       // 3D tile-diagonal planes
     int nchunk;        // 2D row chunks of at most 1024 rows
     long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements)
@@ -46,6 +50,13 @@ hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const do
                            const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
                            const double* chi, double* g_t, double* g_s, hipStream_t st);
 
+// out[0] = sum_c r_c int_c phi; out[1] = outflow partial current through `face`
+// (wn[d] = w_d Omega_d.n for outgoing directions, else 0); part: 3*nparts scratch
+template <typename T>
+hipError_t launch_response(long nc, int nn, int nx, int ny, int nz, const double* h, const double* r,
+                           const double* phi, int face, int ndirs, const double* wn, const T* psi, double* part,
+                           int nparts, double* out, hipStream_t st);
+
 // heterogeneous DSA (dsa.hip)
 struct DsaGeom {
     int dim, nx, ny, nz, nn;
@@ -71,11 +82,14 @@ struct CgScalars {
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, hipStream_t st);
-hipError_t launch_cg_init(int nparts, const double* part, CgScalars* s, double rtol, hipStream_t st);
-hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
-                               const double* sigma_t, const double* sigma_s, const double* binv, double* x,
-                               double* r, double* z, double* p, double* q, double* part_a, double* part_b,
-                               int nparts, CgScalars* s, double rtol, int maxit, int it, hipStream_t st);
+hipError_t launch_cg_init(CgScalars* s, hipStream_t st);
+hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
+                                  hipStream_t st);
+// CG iteration `it` (it = maxit only runs the stop test); p0/p1 alternate
+hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                               const double* sigma_s, const double* binv, double* x, double* r, double* z,
+                               double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
+                               CgScalars* s, double rtol, int maxit, int it, hipStream_t st);
 hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
                               double* phi_out, hipStream_t st);
 hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,

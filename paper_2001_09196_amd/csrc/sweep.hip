@@ -7,15 +7,16 @@
 //   walks along x, skewed by its row index, so that at step t it works on
 //   column t - row.  The x inflow of a cell is the previous cell of the same
 //   lane (registers); the y inflow is the top face of the row below, taken
-//   from lane r - 1 by a lane shuffle, or from the previous wave through LDS
-//   (one barrier per step).  Rows beyond 1024 are processed in chunks, one
+//   from lane r - 1 by a DPP wave shift, or from the previous wave through
+//   LDS (one barrier per step).  Rows beyond 1024 are processed in chunks, one
 //   launch per chunk, chained through a y-face buffer.
 //
-// 3D (throughput bound): tiles of TX x 8 x 8 cells in the reflected frame of
-//   each direction; one wave per (tile, direction); lane (jy, kz) owns the
-//   x-pencil (jy, kz) of the tile and walks along x skewed by jy + kz, taking
-//   its y inflow from lane - 1 and its z inflow from lane - 8 by lane
-//   shuffles.  Tiles on one diagonal plane I + J + K = p are independent, so
+// 3D (throughput bound): tiles of TX x 4 x 4 cells in the reflected frame of
+//   each direction; one wave per (tile, group of four directions with the
+//   same reflection); lane (jy, kz, k) owns the
+//   x-pencil (jy, kz) of a 4 x 4 pencil block for four directions and walks
+//   along x skewed by jy + kz, taking its y inflow from lane - 1 and its z
+//   inflow from lane - 4 by DPP row shifts.  Tiles on one diagonal plane I + J + K = p are independent, so
 //   each plane is one launch; tile faces travel through face buffers in the
 //   reflected frame (slot 0 of each buffer holds the domain inflow).
 //
@@ -26,9 +27,16 @@
 
 namespace sn {
 
-template <typename T>
-__device__ __forceinline__ T shfl_up_t(T v, int delta) {
-    return __shfl_up(v, delta, 64);
+// v of lane - 1 across the whole wave (DPP wave_shr:1); lane 0 receives 0
+__device__ __forceinline__ double wave_shr1(double v) {
+    const long long x = __double_as_longlong(v);
+    int lo = (int)(x & 0xffffffffLL), hi = (int)(x >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float wave_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
 // ---------------------------------------------------------------------------
@@ -165,7 +173,7 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     auto step = [&](int t, In2<T>& use, In2<T>& fill) {
         const int il = t - r;
         fetch(il + 2, fill);
-        T yi0 = shfl_up_t(yo0, 1), yi1 = shfl_up_t(yo1, 1);
+        T yi0 = wave_shr1(yo0), yi1 = wave_shr1(yo1);
         const T l0 = lds[(t - 1) & 1][pw][0], l1 = lds[(t - 1) & 1][pw][1];
         if (lane == 0) {
             yi0 = wave == 0 ? use.yb0 : l0;
@@ -244,6 +252,12 @@ __global__ void __launch_bounds__(1024) sweep2d_kernel(int nx, int ny, int ndirs
 // ---------------------------------------------------------------------------
 // 3D tile-plane sweep
 // ---------------------------------------------------------------------------
+// Lane layout: lane = p + 16 k, pencil p = jy + 4 kz of a 4 x 4 block of
+// x-pencils, k = one of four directions that share the reflection M.  The
+// y-upwind pencil is lane - 1 and the z-upwind pencil lane - 4, both inside
+// the same 16-lane DPP row, so the face values move with row_shr DPP moves.
+// The four lanes of one pencil read the same cell (one cache line serves four
+// directions) and write its four consecutive directions of psi (contiguous).
 template <typename T>
 struct Vec8 {
     T v[8];
@@ -261,25 +275,40 @@ __device__ __forceinline__ Vec8<T> load8(const T* p) {
     return r;
 }
 
+// v of lane - SHIFT within the 16-lane row (row_shr DPP); lanes without a
+// source inside the row receive 0 and take their value from a face buffer
+template <int SHIFT>
+__device__ __forceinline__ double row_shr(double v) {
+    const long long x = __double_as_longlong(v);
+    int lo = (int)(x & 0xffffffffLL), hi = (int)(x >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x110 + SHIFT, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x110 + SHIFT, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int SHIFT>
+__device__ __forceinline__ float row_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + SHIFT, 0xF, 0xF, true));
+}
+
 template <typename T>
 struct In3 {
     Vec8<T> s;
     T sig;
-    Vec4<T> yb, zb;
 };
 
 template <typename T, int M>
-__device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, T ax, T ay, T az, int I,
-                                             int J, int K, int TX, int nTx, int nTy, int nTz,
+__device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, bool dok, T ax, T ay, T az,
+                                             int I, int J, int K, int TX, int nTx, int nTy, int nTz,
                                              const T* __restrict__ sigt, const T* __restrict__ src,
                                              T* __restrict__ xf, T* __restrict__ yf, T* __restrict__ zf,
-                                             T* __restrict__ psi) {
+                                             T* __restrict__ psi, int d0, int nvalid, T* __restrict__ stg) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1, rz = (M >> 2) & 1;
     const int lane = threadIdx.x & 63;
-    const int jy = lane & 7, kz = lane >> 3;
-    const int jl = J * 8 + jy, kl = K * 8 + kz;
-    const bool pen = jl < ny && kl < nz;
-    const int j = ry ? ny - 1 - jl : jl, k = rz ? nz - 1 - kl : kl;
+    const int jy = lane & 3, kz = (lane >> 2) & 3;
+    const int jl = J * 4 + jy, kl = K * 4 + kz;
+    const bool pen = dok && jl < ny && kl < nz;
+    const int jc = min(jl, ny - 1), kc = min(kl, nz - 1);
+    const int j = ry ? ny - 1 - jc : jc, k = rz ? nz - 1 - kc : kc;
     const int i0 = I * TX;
     const int len = min(TX, nx - i0);
     T xin[4], yo[4], zo[4];
@@ -295,43 +324,39 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         for (int t = 0; t < 4; ++t) xin[t] = x.v[t];
     }
     const long rowbase = ((long)k * ny + j) * nx;
-    // inputs of the cell two steps ahead are loaded before the current solve
-    // (loads and stores retire in order; see sweep2d_body)
+    // the source and sigma_t of the next cell are loaded one step ahead
     auto fetch = [&](int ir, In3<T>& v) {
-        if (pen && ir >= 0 && ir < len) {
-            const int il = i0 + ir;
-            const int i = rx ? nx - 1 - il : il;
-            const long c = rowbase + i;
-            v.s = load8(src + c * 8);
-            v.sig = sigt[c];
-            if (jy == 0) v.yb = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
-            if (kz == 0) v.zb = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
-        }
+        const int irc = min(max(ir, 0), len - 1);
+        const int il = i0 + irc;
+        const int i = rx ? nx - 1 - il : il;
+        const long c = rowbase + i;
+        v.s = load8(src + c * 8);
+        v.sig = sigt[c];
     };
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay, az4 = T(4) * az, az2 = T(2) * az;
     const int skew = jy + kz;
-    const int nsteps = len + 14;
-    // one step: solve with `use`, fetch the inputs of step s + 1 into `fill`;
-    // unrolled by two so that the two slots keep fixed registers
+    const int nsteps = len + 6;
     auto step = [&](int s, In3<T>& use, In3<T>& fill) {
         const int ir = s - skew;
         fetch(ir + 1, fill);
         T yi[4], zi[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            yi[t] = shfl_up_t(yo[t], 1);
-            zi[t] = shfl_up_t(zo[t], 8);
+            yi[t] = row_shr<1>(yo[t]);
+            zi[t] = row_shr<4>(zo[t]);
         }
         const bool active = pen && ir >= 0 && ir < len;
         if (active) {
             const int il = i0 + ir;
             if (jy == 0) {
+                Vec4<T> y = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) yi[t] = use.yb.v[t];
+                for (int t = 0; t < 4; ++t) yi[t] = y.v[t];
             }
             if (kz == 0) {
+                Vec4<T> z = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) zi[t] = use.zb.v[t];
+                for (int t = 0; t < 4; ++t) zi[t] = z.v[t];
             }
             const int i = rx ? nx - 1 - il : il;
             const long c = rowbase + i;
@@ -362,18 +387,60 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             T o[8];
 #pragma unroll
             for (int n = 0; n < 8; ++n) o[n] = u[n ^ M];
-            T* pp = psi + (c * ndirs + d) * 8;
-            store4(pp, o[0], o[1], o[2], o[3]);
-            store4(pp + 4, o[4], o[5], o[6], o[7]);
-            if (jy == 7 && J + 1 < nTy)
+            if (nvalid > 0) {
+                // staged: this lane's eight values go to LDS slot (pencil, k)
+                T* sp = stg + ((lane & 15) * 4 + (lane >> 4)) * 8;
+                store4(sp, o[0], o[1], o[2], o[3]);
+                store4(sp + 4, o[4], o[5], o[6], o[7]);
+            } else {
+                T* pp = psi + (c * ndirs + d) * 8;
+                store4(pp, o[0], o[1], o[2], o[3]);
+                store4(pp + 4, o[4], o[5], o[6], o[7]);
+            }
+            if (jy == 3 && J + 1 < nTy)
                 store4(yf + (((long)(J + 1) * nz + kl) * nx + il) * 4, yo[0], yo[1], yo[2], yo[3]);
-            if (kz == 7 && K + 1 < nTz)
+            if (kz == 3 && K + 1 < nTz)
                 store4(zf + (((long)(K + 1) * ny + jl) * nx + il) * 4, zo[0], zo[1], zo[2], zo[3]);
             if (ir == len - 1 && I + 1 < nTx)
                 store4(xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4, xin[0], xin[1], xin[2], xin[3]);
         }
+        if (nvalid > 0) {
+            // Write the staged psi of the 16 pencils: pencil q's block is the
+            // nvalid consecutive directions d0.. of its current cell, nvalid*8
+            // contiguous values, and consecutive lanes write consecutive
+            // 16-byte pieces of it, so neighbouring lanes store neighbouring
+            // bytes.  LDS operations of one wave execute in order, so the
+            // reads below see this step's writes.
+            __builtin_amdgcn_wave_barrier();
+            constexpr int CH = 16 / sizeof(T);          // values per 16-byte piece
+            const int per = nvalid * 8 / CH;            // pieces per pencil block
+            const int total = 16 * per;
+            for (int base = 0; base < total; base += 64) {
+                const int id = base + lane;
+                const int q = id / per, o = id - q * per;
+                const int qy = q & 3, qz = q >> 2;
+                const int qjl = J * 4 + qy, qkl = K * 4 + qz;
+                const int qir = s - (qy + qz);
+                const bool qact = id < total && qjl < ny && qkl < nz && qir >= 0 && qir < len;
+                if (qact) {
+                    const int qil = i0 + qir;
+                    const int qi = rx ? nx - 1 - qil : qil;
+                    const int qj = ry ? ny - 1 - qjl : qjl;
+                    const int qk = rz ? nz - 1 - qkl : qkl;
+                    const long qc = ((long)qk * ny + qj) * nx + qi;
+                    const T* sp = stg + q * 32 + o * CH;
+                    T* gp = psi + (qc * ndirs + d0) * 8 + o * CH;
+                    if constexpr (sizeof(T) == 8) {
+                        *reinterpret_cast<double2*>(gp) = *reinterpret_cast<const double2*>(sp);
+                    } else {
+                        *reinterpret_cast<float4*>(gp) = *reinterpret_cast<const float4*>(sp);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
     };
-    In3<T> s0{}, s1{};
+    In3<T> s0, s1;
     fetch(-skew, s0);
     for (int s = 0; s < nsteps; s += 2) {
         step(s, s0, s1);
@@ -381,29 +448,43 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     }
 }
 
-template <typename T, int WPB>
-__global__ void __launch_bounds__(64 * WPB) sweep3d_kernel(int nx, int ny, int nz, int ndirs,
-                                                           const DirInfo* __restrict__ dirs, int transpose,
-                                                           const T* __restrict__ sigt, const T* __restrict__ src,
-                                                           T* __restrict__ xf, long xstride, T* __restrict__ yf,
-                                                           long ystride, T* __restrict__ zf, long zstride, int TX,
-                                                           int nTx, int nTy, int nTz, const int* __restrict__ tiles,
-                                                           T* __restrict__ psi) {
+// blockIdx.x: tile of the plane; blockIdx.y: reflection class; wave w of the
+// block: direction group w of that class (four directions, -1 = unused slot)
+template <typename T>
+__global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, int ndirs,
+                                                      const DirInfo* __restrict__ dirs, int transpose,
+                                                      const int* __restrict__ groups, int groups_per_class,
+                                                      const T* __restrict__ sigt, const T* __restrict__ src,
+                                                      T* __restrict__ xf, long xstride, T* __restrict__ yf,
+                                                      long ystride, T* __restrict__ zf, long zstride, int TX,
+                                                      int nTx, int nTy, int nTz, const int* __restrict__ tiles,
+                                                      T* __restrict__ psi) {
+    __shared__ __align__(16) T stage[6][16 * 4 * 8];
     const int wave = threadIdx.x >> 6;
-    const int d = blockIdx.y * WPB + wave;
-    if (d >= ndirs) return;
+    const int lane = threadIdx.x & 63;
+    const int grp = blockIdx.y * groups_per_class + wave;
+    const int* gi = groups + 6 * grp;
+    const int d = gi[lane >> 4];
+    const int m0 = gi[0];            // first direction of the group (always valid)
+    if (m0 < 0) return;              // empty group slot: the whole wave leaves
+    // consecutive directions d0 .. d0 + nvalid - 1: psi goes out through the
+    // LDS stage; otherwise (nvalid = 0) every lane stores its own values
+    const int d0 = gi[4], nvalid = gi[4] >= 0 ? gi[5] : 0;
+    const bool dok = d >= 0;
+    const int dd = dok ? d : m0;
     const int tile = tiles[blockIdx.x];
     const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
-    const DirInfo di = dirs[d];
-    const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1) | ((di.rz ^ transpose) << 2);
+    const DirInfo dm = dirs[m0];
+    const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
+    const DirInfo di = dirs[dd];
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
-    T* xd = xf + d * xstride;
-    T* yd = yf + d * ystride;
-    T* zd = zf + d * zstride;
-#define SN_CASE(MM)                                                                                                \
-    case MM:                                                                                                       \
-        sweep3d_body<T, MM>(nx, ny, nz, ndirs, d, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, xd, yd, zd, \
-                            psi);                                                                                  \
+    T* xd = xf + dd * xstride;
+    T* yd = yf + dd * ystride;
+    T* zd = zf + dd * zstride;
+#define SN_CASE(MM)                                                                                               \
+    case MM:                                                                                                      \
+        sweep3d_body<T, MM>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, xd, yd, \
+                            zd, psi, d0, nvalid, stage[wave]);                                                    \
         break;
     switch (m) {
         SN_CASE(0)
@@ -448,13 +529,12 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
         }
         return hipSuccess;
     }
-    constexpr int WPB = 4;
-    int gy = (g.ndirs + WPB - 1) / WPB;
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
-        hipLaunchKernelGGL((sweep3d_kernel<T, WPB>), dim3(nt, gy), dim3(64 * WPB), 0, st, g.nx, g.ny, g.nz, g.ndirs,
-                           dirs, transpose, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx,
-                           g.nTy, g.nTz, tiles + plane_off[p], psi);
+        hipLaunchKernelGGL((sweep3d_kernel<T>), dim3(nt, g.nclasses), dim3(64 * g.groups_per_class), 0, st, g.nx,
+                           g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, sigt, src, xf,
+                           g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
+                           tiles + plane_off[p], psi);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -1,0 +1,194 @@
+"""Adjoint gradients on the GPU against the oracle's adjoint, central finite
+differences of converged GPU forward solves, and reciprocity.
+
+FD protocol: central differences in log sigma with step 1e-4 and forward
+solves to 6e-14 relative residual (the FP64 floor of C4 is about 2.6e-14, so
+a 1e-6 step would leave ~1e-5 relative round-off in the quotient; at 1e-4 the
+truncation, about step^2/6, and the round-off are both near 1e-8); metric
+|g_adj - g_FD| <= 1e-6 max(|g_FD,i|, 1e-3 max_j |g_FD,j|).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import sninputs
+from gpu_util import dev, random_problem, rel_max, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _solver(p, tol=1e-14, cg_rtol=1e-13, max_it=5000):
+    from paper_2001_09196_amd.adjoint import Solver
+    return Solver(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, dev(p.q), eta=p.eta, tol=tol, max_it=max_it,
+                  cg_rtol=cg_rtol, cg_maxit=20000)
+
+
+def _logs(p):
+    with np.errstate(divide="ignore"):
+        lt = torch.tensor(np.log(p.sigma_t), dtype=torch.float64, device="cuda", requires_grad=True)
+        ls = torch.tensor(np.log(p.sigma_s), dtype=torch.float64, device="cuda", requires_grad=True)
+    return lt, ls
+
+
+def _oracle_gradient(p, qadj, inflow=None):
+    fwd = oracle.source_iterate(p, tol=1e-14, max_it=5000, use_dsa=True, cg_rtol=1e-13)
+    adj = oracle.source_iterate(p, tol=1e-14, max_it=5000, use_dsa=True, cg_rtol=1e-13, transpose=True, q=qadj,
+                                inflow=inflow)
+    psi = oracle.sweep(p, fwd["phi"], p.q)
+    psia = oracle.sweep(p, adj["phi"], qadj, inflow=inflow, transpose=True)
+    return oracle.gradient(p, psi, psia, fwd["phi"], adj["phi"])
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (13, 9, 1)), (3, (9, 7, 6))])
+def test_adjoint_vs_oracle_small(dim, shape):
+    from paper_2001_09196_amd.adjoint import detector_response
+    p = random_problem(dim, *shape, order=4, seed=21 + dim)
+    r = np.zeros(p.ncells)
+    r[-3:] = 1.0
+    say(f"adjoint small {p.name}")
+    gt_o, gs_o = _oracle_gradient(p, 4 * math.pi * r)
+    lt, ls = _logs(p)
+    J = detector_response(lt, ls, _solver(p), r=dev(r))
+    J.backward()
+    assert rel_max(lt.grad.cpu().numpy(), gt_o) <= 1e-9
+    assert rel_max(ls.grad.cpu().numpy(), gs_o) <= 1e-9
+
+
+def test_adjoint_outflow_vs_oracle_small():
+    from paper_2001_09196_amd.adjoint import detector_response, outgoing_face_inflow
+    p = random_problem(3, 8, 6, 5, order=4, seed=31)
+    face = 1  # x = high face
+    inflow = outgoing_face_inflow(p.dim, p.nx, p.ny, p.nz, p.omega, face)
+    say("adjoint outflow small")
+    gt_o, gs_o = _oracle_gradient(p, np.zeros(p.ncells), inflow=inflow)
+    lt, ls = _logs(p)
+    J = detector_response(lt, ls, _solver(p), face=face)
+    J.backward()
+    assert rel_max(lt.grad.cpu().numpy(), gt_o) <= 1e-9
+    assert rel_max(ls.grad.cpu().numpy(), gs_o) <= 1e-9
+
+
+def _c4_patch(p):
+    r = np.zeros(p.ncells)
+    for j in range(120, 128):
+        for i in range(120, 128):
+            r[j * p.nx + i] = 1.0
+    return r
+
+
+GOLD_C4 = os.path.join(os.path.dirname(__file__), "golden", "c4_adjoint.json")
+
+
+def test_adjoint_c4_vs_fd_and_oracle():
+    """C4 (128^2, S8, jittered): patch detector on [120,128)^2; 20 seeded cells.
+    Forward solves stop at 6e-14, just above the FP64 residual floor of this
+    problem (about 2.6e-14 in the oracle)."""
+    from paper_2001_09196_amd import Context, sn_response, sn_source_iterate
+    from paper_2001_09196_amd.adjoint import detector_response
+    p = sninputs.config("c4")
+    r = _c4_patch(p)
+    solver = _solver(p, tol=6e-14, cg_rtol=1e-6, max_it=600)
+    lt, ls = _logs(p)
+    say("adjoint c4")
+    J = detector_response(lt, ls, solver, r=dev(r))
+    J.backward()
+    g_t, g_s = lt.grad.cpu().numpy(), ls.grad.cpu().numpy()
+    cells = sninputs.fd_cells(p, 20, seed=2)
+    rr = dev(r)
+    q = dev(p.q)
+
+    def J_of(st, ss):
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, dev(st), dev(ss), eta=p.eta) as ctx:
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+            res = sn_source_iterate(ctx, q, None, phi, tol=6e-14, max_it=600, use_dsa=True, cg_rtol=1e-6,
+                                    cg_maxit=20000)
+            assert res["rc"] == 0
+            return sn_response(ctx, rr, phi)
+
+    eps = 1e-4
+    fd = {0: [], 1: []}
+    for c in cells:
+        for which in (0, 1):
+            st, ss = p.sigma_t.copy(), p.sigma_s.copy()
+            arr = st if which == 0 else ss
+            base = arr[c]
+            arr[c] = base * math.exp(eps)
+            jp = J_of(st, ss)
+            arr[c] = base * math.exp(-eps)
+            jm = J_of(st, ss)
+            fd[which].append((jp - jm) / (2 * eps))
+    for which, g in ((0, g_t), (1, g_s)):
+        f = np.array(fd[which])
+        ga = g[cells]
+        floor = 1e-3 * np.max(np.abs(f))
+        err = np.abs(ga - f) / np.maximum(np.abs(f), floor)
+        say(f"  FD which={which}: max scaled error {err.max():.2e}")
+        assert err.max() <= 1e-6
+    # against the oracle's adjoint (fixture written by tests/golden/make_golden.py)
+    if not os.path.exists(GOLD_C4):
+        pytest.skip("oracle fixture c4_adjoint.json not generated")
+    gold = json.load(open(GOLD_C4))
+    for key, g in (("t", g_t), ("s", g_s)):
+        for cells_key in ("fd_cells", "sample_cells"):
+            idx = np.array(gold[cells_key])
+            ref = np.array(gold[f"g_{key}_{cells_key}" if cells_key == "fd_cells" else f"g_{key}_sample"])
+            err = np.max(np.abs(g[idx] - ref)) / gold[f"g_{key}_maxabs"]
+            say(f"  vs oracle g_{key} at {cells_key}: {err:.2e}")
+            assert err <= 1e-8
+        assert abs(np.linalg.norm(g) - gold[f"g_{key}_norm"]) <= 1e-8 * gold[f"g_{key}_norm"]
+
+
+def test_adjoint_c5_outflow_reciprocity_and_fd():
+    """C5 (128^3, S12): outflow partial current through x = 128 with flux
+    checkpoints; reciprocity J = sum_c (q_c/4pi) int_c chi and sampled FD."""
+    from paper_2001_09196_amd import Context, sn_response, sn_source_iterate, sn_sweep
+    from paper_2001_09196_amd.adjoint import Solver, SnDetector, detector_response, outgoing_face_inflow
+    p = sninputs.config("c5")
+    face = 1
+    solver = _solver(p, tol=1e-13, cg_rtol=1e-12, max_it=2000)
+    lt, ls = _logs(p)
+    say("adjoint c5: forward + adjoint")
+    J = detector_response(lt, ls, solver, face=face)
+    J.backward()
+    g_t, g_s = lt.grad.cpu().numpy(), ls.grad.cpu().numpy()
+    Jv = float(J)
+    # reciprocity with a fresh adjoint solve
+    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, dev(p.sigma_t), dev(p.sigma_s), eta=p.eta) as ctx:
+        inflow = dev(outgoing_face_inflow(p.dim, p.nx, p.ny, p.nz, p.omega, face))
+        chi, _, _ = solver.solve(ctx, q=None, inflow=inflow, transpose=True)
+        Jr = sn_response(ctx, dev(p.q / (4 * math.pi)), chi)
+    say(f"  J = {Jv:.12e}, reciprocity {Jr:.12e}")
+    assert abs(Jv - Jr) <= 1e-10 * abs(Jv)
+    # sampled central differences on 3 cells near the outflow face
+    rng = np.random.default_rng(5)
+    cand = [c for c in range(p.ncells) if (c % p.nx) >= p.nx - 4 and p.sigma_t[c] > 0]
+    cells = rng.choice(cand, size=3, replace=False)
+
+    def J_of(st, ss):
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, dev(st), dev(ss), eta=p.eta) as ctx:
+            phi, _, _ = solver.solve(ctx, q=dev(p.q))
+            psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device="cuda")
+            sn_sweep(ctx, phi, dev(p.q), None, False, 0, psi)
+            v = sn_response(ctx, None, None, face, psi)
+            del psi
+            return v
+
+    eps = 1e-4
+    scale = max(np.max(np.abs(g_t)), np.max(np.abs(g_s)))
+    for c in cells:
+        for which, g in ((0, g_t), (1, g_s)):
+            st, ss = p.sigma_t.copy(), p.sigma_s.copy()
+            arr = st if which == 0 else ss
+            base = arr[c]
+            arr[c] = base * math.exp(eps)
+            jp = J_of(st, ss)
+            arr[c] = base * math.exp(-eps)
+            jm = J_of(st, ss)
+            f = (jp - jm) / (2 * eps)
+            say(f"  cell {c} which={which}: adj {g[c]:.10e} fd {f:.10e}")
+            assert abs(g[c] - f) <= 1e-5 * max(abs(f), 1e-3 * scale)
