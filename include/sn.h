@@ -143,7 +143,9 @@ typedef struct {
                                   on demand) */
     sn_dsa_opts dsa;
     int transpose;             /* 1: adjoint iteration with L_d^{-T} sweeps */
-    double *phi_ckpt;          /* device [max_it][ncells][nn] or NULL: phi after every iteration */
+    double *phi_ckpt;          /* device [ckpt_cap][ncells][nn] or NULL: phi after iteration it goes
+                                  to slot it % ckpt_cap, so the last ckpt_cap iterates are kept */
+    int ckpt_cap;              /* slots in phi_ckpt; must be >= 1 when phi_ckpt is not NULL */
 } sn_iter_opts;
 
 typedef struct {

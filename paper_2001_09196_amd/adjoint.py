@@ -55,7 +55,7 @@ class Solver:
     """Problem description shared by forward and adjoint solves."""
 
     def __init__(self, dim, nx, ny, nz, h, omega, w, q, eta=1.0, tol=1e-12, max_it=5000, cg_rtol=1e-12,
-                 cg_maxit=10000, checkpoint=True):
+                 cg_maxit=10000, checkpoint=True, ckpt_bytes=8 << 30):
         self.dim, self.nx, self.ny, self.nz = dim, nx, ny, nz
         self.h = tuple(h)
         self.omega = np.ascontiguousarray(omega, dtype=np.float64)
@@ -64,6 +64,7 @@ class Solver:
         self.eta = eta
         self.tol, self.max_it, self.cg_rtol, self.cg_maxit = tol, max_it, cg_rtol, cg_maxit
         self.checkpoint = checkpoint
+        self.ckpt_bytes = int(ckpt_bytes)    # device memory for flux checkpoints (last iterates kept)
         self.nn = 4 if dim == 2 else 8
         self.ncells = nx * ny * nz
 
@@ -76,13 +77,16 @@ class Solver:
         phi = torch.zeros((self.ncells, self.nn), dtype=torch.float64, device=dev)
         ck = None
         if checkpoint:
-            ck = torch.empty((self.max_it, self.ncells, self.nn), dtype=torch.float64, device=dev)
+            cap = max(1, min(self.max_it, self.ckpt_bytes // (self.ncells * self.nn * 8)))
+            ck = torch.empty((cap, self.ncells, self.nn), dtype=torch.float64, device=dev)
         r = sn_source_iterate(ctx, q, inflow, phi, tol=self.tol, max_it=self.max_it, use_dsa=True, prec=SN_FP64,
                               cg_rtol=self.cg_rtol, cg_maxit=self.cg_maxit, transpose=transpose, phi_ckpt=ck)
         if r["rc"] != 0:
             raise RuntimeError(f"source iteration did not converge (rc {r['rc']}, {r['iters']} iterations)")
         if ck is not None:
-            ck = ck[: r["iters"]]
+            # oldest first: the ring holds iterates max(0, iters - cap) .. iters - 1
+            n, cap = r["iters"], ck.shape[0]
+            ck = ck[:n] if n <= cap else torch.roll(ck, -(n % cap), dims=0)
         return phi, r, ck
 
 

@@ -55,7 +55,7 @@ class sn_dsa_stats(ctypes.Structure):
 class sn_iter_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("use_dsa", ctypes.c_int),
                 ("prec", ctypes.c_int), ("dsa", sn_dsa_opts), ("transpose", ctypes.c_int),
-                ("phi_ckpt", ctypes.c_void_p)]
+                ("phi_ckpt", ctypes.c_void_p), ("ckpt_cap", ctypes.c_int)]
 
 
 class sn_iter_stats(ctypes.Structure):
@@ -204,10 +204,12 @@ def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, c
 def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_dsa=True, prec=SN_FP64,
                       cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None):
     """Returns dict(rc, iters, res_hist, cg_hist, seconds); raises on errors
-    other than NOT_CONVERGED / DIVERGED (which are reported in rc)."""
+    other than NOT_CONVERGED / DIVERGED (which are reported in rc).
+    phi_ckpt: optional device tensor [cap, ncells, nn]; iterate it is kept in
+    slot it % cap."""
     o = sn_iter_opts(float(tol), int(max_it), int(bool(use_dsa)), int(prec),
                      sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind)), int(bool(transpose)),
-                     _ptr(phi_ckpt))
+                     _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0)
     res = np.zeros(max_it, dtype=np.float64)
     cgh = np.zeros(max_it, dtype=np.int32)
     st = sn_iter_stats(0, res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

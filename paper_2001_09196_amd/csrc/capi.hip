@@ -95,8 +95,8 @@ struct sn_context {
     SweepGeom sg{};
     DevBuf<int> tiles, groups;
     std::vector<int> plane_off;
-    DevBuf<double> xf64, yf64, zf64, src64, sink64;
-    DevBuf<float> xf32, yf32, zf32, src32, sink32;
+    DevBuf<double> xf64, yf64, zf64, src64, sink64, sigskew64, srcskew64;
+    DevBuf<float> xf32, yf32, zf32, src32, sink32, sigskew32, srcskew32;
     // source iteration workspace
     DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3;
     DevBuf<float> psi32;
@@ -143,7 +143,7 @@ long inflow_size(const sn_mesh* m) {
 template <typename T>
 int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
                int transpose, T* psi, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, DevBuf<T>& sink,
-               const T* sigt) {
+               const T* sigt, DevBuf<T>& srcskew, const T* sigskew) {
     const SweepGeom& g = ctx->sg;
     int rc;
     if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
@@ -152,10 +152,18 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
     if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
     if ((rc = sink.ensure((size_t)sink_elems(g)))) return rc;
     HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
+    const T* sweep_src = src.p;
+    const T* sweep_sig = sigt;
+    if (g.dim == 2) {
+        if ((rc = srcskew.ensure((size_t)skew2d_elems(g.nx, g.ny, 4)))) return rc;
+        HIPCHK(launch_skew2d<T>(g.nx, g.ny, 4, src.p, srcskew.p, ctx->stream));
+        sweep_src = srcskew.p;
+        sweep_sig = sigskew;
+    }
     HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
-    HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
+    HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, xf.p, yf.p, zf.p, ctx->tiles.p,
                            ctx->plane_off.data(), psi, sink.p, ctx->stream));
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
@@ -169,9 +177,9 @@ int do_sweep(sn_context* ctx, const double* phi, const double* phi_prev, const d
              int transpose, sn_precision prec, void* psi) {
     if (prec == SN_FP64)
         return sweep_impl<double>(ctx, phi, phi_prev, q, inflow, transpose, (double*)psi, ctx->xf64, ctx->yf64,
-                                  ctx->zf64, ctx->src64, ctx->sink64, ctx->sigt.p);
+                                  ctx->zf64, ctx->src64, ctx->sink64, ctx->sigt.p, ctx->srcskew64, ctx->sigskew64.p);
     return sweep_impl<float>(ctx, phi, phi_prev, q, inflow, transpose, (float*)psi, ctx->xf32, ctx->yf32, ctx->zf32,
-                             ctx->src32, ctx->sink32, ctx->sigt32.p);
+                             ctx->src32, ctx->sink32, ctx->sigt32.p, ctx->srcskew32, ctx->sigskew32.p);
 }
 
 int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, int accumulate = 0) {
@@ -298,6 +306,10 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->yf32.release();
     ctx->zf32.release();
     ctx->src32.release();
+    ctx->sigskew64.release();
+    ctx->sigskew32.release();
+    ctx->srcskew64.release();
+    ctx->srcskew32.release();
     ctx->psi64.release();
     ctx->psi32.release();
     ctx->phisi.release();
@@ -394,7 +406,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     g.ndirs = c->ndirs;
     g.nbf = c->nbf;
     if (dim == 2) {
-        g.nchunk = (mesh->ny + 1023) / 1024;
+        g.nchunk = (mesh->ny + ROWS2D - 1) / ROWS2D;
         g.xstride = (long)mesh->ny * 2;
         g.ystride = (long)g.nchunk * mesh->nx * 2;
         g.zstride = 0;
@@ -403,6 +415,13 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.nplanes = 0;
         c->plane_off.assign(1, 0);
         if ((rc = c->tiles.ensure(1))) return rc;
+        g.groups = nullptr;
+        g.nclasses = g.groups_per_class = 0;
+        // sigma_t in the diagonal-major layout of the 2D sweep
+        const size_t ns = (size_t)skew2d_elems(mesh->nx, mesh->ny, 1);
+        if ((rc = c->sigskew64.ensure(ns)) || (rc = c->sigskew32.ensure(ns))) return rc;
+        HIPCHK(launch_skew2d<double>(mesh->nx, mesh->ny, 1, c->sigt.p, c->sigskew64.p, c->stream));
+        HIPCHK(launch_skew2d<float>(mesh->nx, mesh->ny, 1, c->sigt32.p, c->sigskew32.p, c->stream));
     } else {
         int tx = 32;
         if (const char* e = std::getenv("SN_SWEEP_TX")) tx = std::max(1, std::atoi(e));
@@ -579,6 +598,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !phi || !o) return fail(SN_ERR_INVALID, "NULL argument");
     if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
+    if (o->phi_ckpt && o->ckpt_cap < 1) return fail(SN_ERR_INVALID, "ckpt_cap must be >= 1 with phi_ckpt");
     if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
     if (o->use_dsa && (!(o->dsa.cg_rtol >= 0) || o->dsa.cg_maxit < 1 ||
                        (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1)))
@@ -667,7 +687,8 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         }
         if (stats && stats->cg_hist) stats->cg_hist[it] = cgi;
         if (o->phi_ckpt)
-            HIPCHK(hipMemcpyAsync(o->phi_ckpt + (size_t)it * n, phi, n * sizeof(double), hipMemcpyDeviceToDevice,
+            HIPCHK(hipMemcpyAsync(o->phi_ckpt + (size_t)(it % o->ckpt_cap) * n, phi, n * sizeof(double),
+                                  hipMemcpyDeviceToDevice,
                                   ctx->stream));
         if (!std::isfinite(res) || res > 1e6 * first) {
             status = fail(SN_ERR_DIVERGED, "source iteration diverged at iteration %d (residual %g)", it, res);

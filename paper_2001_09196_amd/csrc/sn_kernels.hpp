@@ -11,6 +11,9 @@ namespace sn {
 
 // Geometry of one sweep: mesh, direction count and the tiling / chunking the
 // sweep kernels use (see sweep.hip).
+// rows per 2D sweep workgroup (one lane per row, 8 waves)
+constexpr int ROWS2D = 512;
+
 struct SweepGeom {
     int dim, nx, ny, nz, ndirs;
     long nbf;          // boundary-face nodes per direction in the inflow layout
@@ -21,19 +24,24 @@ struct SweepGeom {
     const int* groups; // 3D: device [nclasses * groups_per_class][6]: four direction ids (-1 = empty),
                        //     the first id if the valid ids are consecutive (else -1), the valid count
     int nplanes;       // 3D tile-diagonal planes
-    int nchunk;        // 2D row chunks of at most 1024 rows
+    int nchunk;        // 2D row chunks of at most ROWS2D rows
     long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements)
 };
 
 template <typename T>
 hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transpose, const double* inflow, T* xf,
                              T* yf, T* zf, hipStream_t st);
-// sink: scratch of sink_elems(g) elements that absorbs the stores of lanes
-// without a cell at a given step
+// 2D: sigt and src are the diagonal-major arrays of launch_skew2d; 3D: per cell.
+// sink: scratch of sink_elems(g) elements (unused)
 template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st);
-inline long sink_elems(const SweepGeom& g) { return g.dim == 2 ? (long)g.ndirs * 1024 * 4 : 1; }
+inline long sink_elems(const SweepGeom&) { return 1; }
+// per-cell array [ncells][nn] -> four quadrant diagonal-major arrays
+// [4][nx + ny - 1][ny][nn] (2D sweep input layout)
+template <typename T>
+hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_t st);
+inline long skew2d_elems(int nx, int ny, int nn) { return 4L * (nx + ny - 1) * ny * nn; }
 
 // scalar-flux kernels (flux.hip)
 template <typename T>

@@ -8,7 +8,7 @@
 //   column t - row.  The x inflow of a cell is the previous cell of the same
 //   lane (registers); the y inflow is the top face of the row below, taken
 //   from lane r - 1 by a DPP wave shift, or from the previous wave through
-//   LDS (one barrier per step).  Rows beyond 1024 are processed in chunks, one
+//   LDS (one barrier per step).  Rows beyond ROWS2D are processed in chunks, one
 //   launch per chunk, chained through a y-face buffer.
 //
 // 3D (throughput bound): tiles of TX x 4 x 4 cells in the reflected frame of
@@ -91,7 +91,7 @@ __global__ void init_faces_kernel(int dim, int nx, int ny, int nz, int ndirs, co
 }
 
 // ---------------------------------------------------------------------------
-// 2D pipelined sweep
+// vector loads and stores
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Vec4 {
@@ -123,6 +123,41 @@ __device__ __forceinline__ void store4(T* p, T a0, T a1, T a2, T a3) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D diagonal-major input layout
+// ---------------------------------------------------------------------------
+// For the quadrant with reflection (rx, ry), local cell (il, jl) of the
+// reflected frame lies on diagonal D = il + jl.  At a given step the lanes
+// of a wave own consecutive rows jl on one diagonal, so an array stored as
+// [D][jl] (D in [0, nx + ny - 1), entries off the mesh zero) turns each
+// wave's cell loads into one contiguous run instead of one cache line per
+// lane.  out: [4 quadrants][nx + ny - 1][ny][nn].
+template <typename T>
+__global__ void skew2d_kernel(int nx, int ny, int nn, const T* __restrict__ in, T* __restrict__ out) {
+    const long nd = (long)nx + ny - 1;
+    const long per = nd * ny;
+    const long total = 4 * per;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        const int q = (int)(idx / per);
+        const long e = idx - q * per;
+        const int D = (int)(e / ny), jl = (int)(e - (long)D * ny);
+        const int il = D - jl;
+        T* o = out + idx * nn;
+        if (il >= 0 && il < nx) {
+            const int i = (q & 1) ? nx - 1 - il : il;
+            const int j = (q & 2) ? ny - 1 - jl : jl;
+            const T* src = in + ((long)j * nx + i) * nn;
+            for (int n = 0; n < nn; ++n) o[n] = src[n];
+        } else {
+            for (int n = 0; n < nn; ++n) o[n] = T(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D pipelined sweep
+// ---------------------------------------------------------------------------
 // Inputs of one cell for one lane, loaded ahead of use.
 template <typename T>
 struct In2 {
@@ -130,18 +165,26 @@ struct In2 {
     T sig, yb0, yb1;
 };
 
-// The loop body is branch-free: every lane loads from a valid (clamped)
-// address, solves, and stores either to psi or, when it has no cell at this
-// step, to a per-workgroup sink.  Straight-line code lets the compiler count
-// outstanding memory operations exactly, so a step waits only for loads
-// issued two steps earlier and never for the psi stores (loads and stores
-// retire in order on this hardware).
+// Pipeline constants of the 2D sweep: the input prefetch ring depth, and the
+// number of steps between workgroup barriers.  Wave w runs (B2D - 1) w steps
+// behind the plain diagonal schedule, so the top row of wave w - 1 produces
+// the value that the bottom row of wave w needs B2D steps before it is
+// needed; the values travel through a ring of 2 B2D LDS slots and one
+// barrier per B2D steps orders writers and readers.
+constexpr int R2D = 4;
+constexpr int B2D = 8;
+
+// Per step a wave reads its cells' source and sigma_t as contiguous runs of
+// the diagonal-major arrays.  In FP64 the four psi values of a lane (32
+// bytes) go through LDS so that two lanes write the two 16-byte halves of
+// one cell's block: one cache line per cell per store instruction instead
+// of one per lane.
 template <typename T, int M>
 __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T ax, T ay,
-                                             const T* __restrict__ sigt, const T* __restrict__ src,
+                                             const T* __restrict__ sigq, const T* __restrict__ srcq,
                                              const T* __restrict__ xf, const T* __restrict__ yin_buf,
-                                             T* __restrict__ yout_buf, int row0, int nrows,
-                                             T* __restrict__ psi, T* __restrict__ sink, T (*lds)[16][2]) {
+                                             T* __restrict__ yout_buf, int row0, int nrows, T* __restrict__ psi,
+                                             T (*lds)[ROWS2D / 64][2], T (*stage)[4]) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = wave * 64 + lane;
@@ -149,40 +192,46 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     const int jl = row0 + min(r, nrows - 1);
     const int j = ry ? ny - 1 - jl : jl;
     const long rowbase = (long)j * nx;
-    T* my_sink = sink + (long)threadIdx.x * 4;
-    T* yout = yout_buf ? yout_buf : sink;
-    const bool top = yout_buf && r == nrows - 1;
+    const bool top = yout_buf != nullptr && r == nrows - 1;
+    const int nd = nx + ny - 1;
     T xin0 = xf[(long)jl * 2 + 0];
     T xin1 = xf[(long)jl * 2 + 1];
     T yo0 = T(0), yo1 = T(0);
-    auto fetch = [&](int il, In2<T>& v) {
-        const int ilc = min(max(il, 0), nx - 1);
-        const int i = rx ? nx - 1 - ilc : ilc;
-        const long c = rowbase + i;
-        v.s = load4(src + c * 4);
-        v.sig = sigt[c];
-        v.yb0 = yin_buf[(long)ilc * 2 + 0];
-        v.yb1 = yin_buf[(long)ilc * 2 + 1];
+    const int nw = (nrows + 63) / 64;
+    const int lag = wave * (B2D - 1);
+    const int nsteps = nx + nrows - 1 + (nw - 1) * (B2D - 1);
+    // inputs of step t: diagonal D = t - lag + row0 (the same for the whole wave)
+    auto fetch = [&](int t, In2<T>& v) {
+        const int D = min(max(t - lag + row0, 0), nd - 1);
+        const long e = (long)D * ny + jl;
+        v.s = load4(srcq + e * 4);
+        v.sig = sigq[e];
+        if (r == 0) {
+            const int ilc = min(max(t - lag, 0), nx - 1);
+            v.yb0 = yin_buf[(long)ilc * 2 + 0];
+            v.yb1 = yin_buf[(long)ilc * 2 + 1];
+        } else {
+            v.yb0 = v.yb1 = T(0);
+        }
     };
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay;
-    const int nsteps = nx + nrows - 1;
-    const int pw = wave > 0 ? wave - 1 : 0;
-    // one pipeline step: solve with the inputs in `use`, fetch the inputs of
-    // step t + 2 into `fill`.  The loop below is unrolled by three so that the
-    // three input slots keep fixed registers (no copies of in-flight loads).
     auto step = [&](int t, In2<T>& use, In2<T>& fill) {
-        const int il = t - r;
-        fetch(il + 2, fill);
+        const int il = t - r - lag;
+        fetch(t + R2D - 1, fill);
+        // y inflow: the lane below (DPP), the wave below (LDS ring, written
+        // B2D steps ago), or the inflow row of the chunk
         T yi0 = wave_shr1(yo0), yi1 = wave_shr1(yo1);
-        const T l0 = lds[(t - 1) & 1][pw][0], l1 = lds[(t - 1) & 1][pw][1];
         if (lane == 0) {
-            yi0 = wave == 0 ? use.yb0 : l0;
-            yi1 = wave == 0 ? use.yb1 : l1;
+            if (wave == 0) {
+                yi0 = use.yb0;
+                yi1 = use.yb1;
+            } else {
+                const int sl = (t - B2D) & (2 * B2D - 1);
+                yi0 = lds[sl][wave - 1][0];
+                yi1 = lds[sl][wave - 1][1];
+            }
         }
         const bool active = rowok && il >= 0 && il < nx;
-        const int ilc = min(max(il, 0), nx - 1);
-        const int i = rx ? nx - 1 - ilc : ilc;
-        const long c = rowbase + i;
         T g[4], u[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) g[n] = use.s.v[n ^ M];
@@ -200,53 +249,83 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
         xin1 = active ? u[3] : xin1;
         yo0 = active ? u[2] : yo0;
         yo1 = active ? u[3] : yo1;
-        T o[4];
+        if constexpr (sizeof(T) == 8) {
+            // stage, then lane pair (2 q, 2 q + 1) writes the halves of cell q
+            store4(stage[lane], u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int n = 0; n < 4; ++n) o[n] = u[n ^ M];
-        store4(active ? psi + (c * ndirs + d) * 4 : my_sink, o[0], o[1], o[2], o[3]);
-        if (yout_buf) {
-            T* ya = (active && top) ? yout + (long)il * 2 : my_sink;
-            ya[0] = yo0;
-            ya[1] = yo1;
+            for (int h = 0; h < 2; ++h) {
+                const int q = h * 32 + (lane >> 1), o = lane & 1;
+                const int rq = wave * 64 + q;
+                const int ilq = t - rq - lag;
+                if (rq < nrows && ilq >= 0 && ilq < nx) {
+                    const int jq = ry ? ny - 1 - (row0 + rq) : row0 + rq;
+                    const int iq = rx ? nx - 1 - ilq : ilq;
+                    const long cq = (long)jq * nx + iq;
+                    *reinterpret_cast<double2*>(psi + (cq * ndirs + d) * 4 + 2 * o) =
+                        *reinterpret_cast<const double2*>(&stage[q][2 * o]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            if (active) {
+                const int i = rx ? nx - 1 - il : il;
+                store4(psi + ((rowbase + i) * ndirs + d) * 4, u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            }
+        }
+        if (top && active) {
+            yout_buf[(long)il * 2 + 0] = yo0;
+            yout_buf[(long)il * 2 + 1] = yo1;
         }
         if (lane == 63) {
-            lds[t & 1][wave][0] = yo0;
-            lds[t & 1][wave][1] = yo1;
+            const int sl = t & (2 * B2D - 1);
+            lds[sl][wave][0] = yo0;
+            lds[sl][wave][1] = yo1;
         }
-        __syncthreads();
+        if ((t + 1) % B2D == 0) __syncthreads();
     };
-    In2<T> s0, s1, s2;
-    fetch(-r, s0);
-    fetch(1 - r, s1);
-    for (int t = 0; t < nsteps; t += 3) {
-        step(t, s0, s2);
-        if (t + 1 < nsteps) step(t + 1, s1, s0);
-        if (t + 2 < nsteps) step(t + 2, s2, s1);
+    In2<T> sl[R2D];
+#pragma unroll
+    for (int k = 0; k + 1 < R2D; ++k) fetch(k, sl[k]);
+    for (int t = 0; t < nsteps; t += R2D) {
+#pragma unroll
+        for (int k = 0; k < R2D; ++k)
+            if (t + k < nsteps) step(t + k, sl[k], sl[(k + R2D - 1) % R2D]);
     }
 }
 
+// blockIdx.x: direction; one launch per row chunk.  sigskew / srcskew: the
+// diagonal-major arrays of the four quadrants ([4][nx + ny - 1][ny][nn]).
 template <typename T>
-__global__ void __launch_bounds__(1024) sweep2d_kernel(int nx, int ny, int ndirs, const DirInfo* __restrict__ dirs,
-                                                       int transpose, const T* __restrict__ sigt,
-                                                       const T* __restrict__ src, const T* __restrict__ xf,
+__global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndirs, const DirInfo* __restrict__ dirs,
+                                                       int transpose, const T* __restrict__ sigskew,
+                                                       const T* __restrict__ srcskew, const T* __restrict__ xf,
                                                        long xstride, T* __restrict__ ybuf, long ystride, int chunk,
-                                                       int nchunk, int row0, int nrows, T* __restrict__ psi,
-                                                       T* __restrict__ sink) {
-    __shared__ T lds[2][16][2];
+                                                       int nchunk, int row0, int nrows, T* __restrict__ psi) {
+    __shared__ T lds[2 * B2D][ROWS2D / 64][2];
+    __shared__ __align__(16) T stage[ROWS2D][4];
     const int d = blockIdx.x;
     const DirInfo di = dirs[d];
     const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
     const T ax = T(di.ax), ay = T(di.ay);
+    const long per = (long)(nx + ny - 1) * ny;
+    const T* sq = sigskew + m * per;
+    const T* cq = srcskew + m * per * 4;
     const T* xfd = xf + d * xstride;
     const T* yin = ybuf + d * ystride + (long)chunk * nx * 2;
     T* yout = (chunk + 1 < nchunk) ? ybuf + d * ystride + (long)(chunk + 1) * nx * 2 : nullptr;
-    T* snk = sink + (long)blockIdx.x * 1024 * 4;
+    T (*stg)[4] = stage + (threadIdx.x & ~63);
+#define SN_CASE2(MM)                                                                                         \
+    case MM:                                                                                                 \
+        sweep2d_body<T, MM>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, lds, stg); \
+        break;
     switch (m) {
-        case 0: sweep2d_body<T, 0>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
-        case 1: sweep2d_body<T, 1>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
-        case 2: sweep2d_body<T, 2>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
-        default: sweep2d_body<T, 3>(nx, ny, ndirs, d, ax, ay, sigt, src, xfd, yin, yout, row0, nrows, psi, snk, lds); break;
+        SN_CASE2(0)
+        SN_CASE2(1)
+        SN_CASE2(2)
+        SN_CASE2(3)
     }
+#undef SN_CASE2
 }
 
 // ---------------------------------------------------------------------------
@@ -294,6 +373,7 @@ template <typename T>
 struct In3 {
     Vec8<T> s;
     T sig;
+    Vec4<T> y, z;  // y- and z-face inflow (lanes on the tile's y = 0 / z = 0 side)
 };
 
 template <typename T, int M>
@@ -324,7 +404,10 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         for (int t = 0; t < 4; ++t) xin[t] = x.v[t];
     }
     const long rowbase = ((long)k * ny + j) * nx;
-    // the source and sigma_t of the next cell are loaded one step ahead
+    // The source, sigma_t and the y/z face inflow of the next cell are loaded
+    // one step ahead.  The face values of this tile were written by earlier
+    // launches (the upwind tiles) and no tile of this launch writes them, so
+    // they can be read at any time.
     auto fetch = [&](int ir, In3<T>& v) {
         const int irc = min(max(ir, 0), len - 1);
         const int il = i0 + irc;
@@ -332,6 +415,14 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         const long c = rowbase + i;
         v.s = load8(src + c * 8);
         v.sig = sigt[c];
+        if (pen && jy == 0)
+            v.y = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
+        else
+            v.y = Vec4<T>{};
+        if (pen && kz == 0)
+            v.z = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
+        else
+            v.z = Vec4<T>{};
     };
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay, az4 = T(4) * az, az2 = T(2) * az;
     const int skew = jy + kz;
@@ -349,14 +440,12 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         if (active) {
             const int il = i0 + ir;
             if (jy == 0) {
-                Vec4<T> y = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) yi[t] = y.v[t];
+                for (int t = 0; t < 4; ++t) yi[t] = use.y.v[t];
             }
             if (kz == 0) {
-                Vec4<T> z = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) zi[t] = z.v[t];
+                for (int t = 0; t < 4; ++t) zi[t] = use.z.v[t];
             }
             const int i = rx ? nx - 1 - il : il;
             const long c = rowbase + i;
@@ -518,12 +607,11 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st) {
     if (g.dim == 2) {
         for (int ch = 0; ch < g.nchunk; ++ch) {
-            int row0 = ch * 1024;
-            int nrows = std::min(1024, g.ny - row0);
+            int row0 = ch * ROWS2D;
+            int nrows = std::min(ROWS2D, g.ny - row0);
             int nw = (nrows + 63) / 64;
             hipLaunchKernelGGL(sweep2d_kernel<T>, dim3(g.ndirs), dim3(64 * nw), 0, st, g.nx, g.ny, g.ndirs, dirs,
-                               transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows, psi,
-                               sink);
+                               transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows, psi);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -540,6 +628,16 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
     }
     return hipSuccess;
 }
+
+template <typename T>
+hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_t st) {
+    const long total = 4L * (nx + ny - 1) * ny;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(skew2d_kernel<T>, dim3(blocks), dim3(256), 0, st, nx, ny, nn, in, out);
+    return hipGetLastError();
+}
+template hipError_t launch_skew2d<double>(int, int, int, const double*, double*, hipStream_t);
+template hipError_t launch_skew2d<float>(int, int, int, const float*, float*, hipStream_t);
 
 template hipError_t launch_init_faces<double>(const SweepGeom&, const DirInfo*, int, const double*, double*, double*,
                                               double*, hipStream_t);

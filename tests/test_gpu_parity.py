@@ -35,7 +35,7 @@ def _sweep_case(p, transpose, with_inflow, prec=0, seed=1):
     return got, ref
 
 
-@pytest.mark.parametrize("shape", [(16, 16), (37, 150), (5, 1100)])
+@pytest.mark.parametrize("shape", [(16, 16), (37, 150), (9, 513), (5, 1100)])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sweep2d_fp64(shape, transpose):
     p = random_problem(2, shape[0], shape[1], 1, order=4, seed=shape[1])
@@ -188,3 +188,25 @@ def test_si_fp32_form_c1():
     got = _si_gpu(p, tol=1e-8, max_it=2000, use_dsa=True, prec=1, cg_rtol=1e-10, cg_maxit=5000)
     assert got["rc"] == 0
     assert rel_l2(got["phi"], ref["phi"]) <= 1e-5
+
+
+def test_si_checkpoint_ring():
+    """phi checkpoints: with a 3-slot ring over 7 iterations the slots hold
+    iterates 7, 5, 6 (slot it % 3), each equal to the oracle's iterate."""
+    from paper_2001_09196_amd import sn_source_iterate
+    p = random_problem(2, 17, 12, 1, order=4, seed=41)
+    say("SI checkpoint ring")
+    refs = {k: oracle.source_iterate(p, tol=0.0, max_it=k, use_dsa=True, cg_rtol=1e-13)["phi"] for k in (5, 6, 7)}
+    with context(p) as ctx:
+        phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        ck = torch.full((3, p.ncells, p.nn), float("nan"), dtype=torch.float64, device="cuda")
+        r = sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=7, use_dsa=True, cg_rtol=1e-13,
+                              cg_maxit=5000, phi_ckpt=ck)
+        ck = ck.cpu().numpy()
+        phi = phi.cpu().numpy()
+    assert r["iters"] == 7
+    # iteration index it (0-based) is stored in slot it % 3; iterate k = it + 1
+    for k in (5, 6, 7):
+        slot = (k - 1) % 3
+        assert rel_l2(ck[slot], refs[k]) <= 1e-10
+    assert np.array_equal(ck[(7 - 1) % 3], phi)
