@@ -166,25 +166,29 @@ struct In2 {
 };
 
 // Pipeline constants of the 2D sweep: the input prefetch ring depth, and the
-// number of steps between workgroup barriers.  Wave w runs (B2D - 1) w steps
+// number of steps between workgroup barriers.  Wave w runs B2D w steps
 // behind the plain diagonal schedule, so the top row of wave w - 1 produces
-// the value that the bottom row of wave w needs B2D steps before it is
-// needed; the values travel through a ring of 2 B2D LDS slots and one
-// barrier per B2D steps orders writers and readers.
+// the value that the bottom row of wave w needs B2D + 1 steps before it is
+// needed.  The values travel through a ring of 2 B2D LDS slots; with one
+// barrier per B2D steps, every window of B2D consecutive steps holds exactly
+// one barrier, which orders each write before its read (done one step
+// early, to hide the LDS latency) and each read before the slot is
+// rewritten.
 constexpr int R2D = 4;
 constexpr int B2D = 8;
 
 // Per step a wave reads its cells' source and sigma_t as contiguous runs of
 // the diagonal-major arrays.  In FP64 the four psi values of a lane (32
-// bytes) go through LDS so that two lanes write the two 16-byte halves of
-// one cell's block: one cache line per cell per store instruction instead
-// of one per lane.
+// bytes) go through a double-buffered LDS stage so that two lanes write the
+// two 16-byte halves of one cell's block (one cache line per cell per store
+// instruction instead of one per lane); the write-out of step t happens
+// during step t + 1, behind its arithmetic.
 template <typename T, int M>
 __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T ax, T ay,
                                              const T* __restrict__ sigq, const T* __restrict__ srcq,
                                              const T* __restrict__ xf, const T* __restrict__ yin_buf,
                                              T* __restrict__ yout_buf, int row0, int nrows, T* __restrict__ psi,
-                                             T (*lds)[ROWS2D / 64][2], T (*stage)[4]) {
+                                             T (*lds)[ROWS2D / 64][2], T (*stage)[ROWS2D][4]) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = wave * 64 + lane;
@@ -197,39 +201,59 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     T xin0 = xf[(long)jl * 2 + 0];
     T xin1 = xf[(long)jl * 2 + 1];
     T yo0 = T(0), yo1 = T(0);
+    T rin0 = T(0), rin1 = T(0);  // y inflow of the bottom lane from the wave below, read one step early
     const int nw = (nrows + 63) / 64;
-    const int lag = wave * (B2D - 1);
-    const int nsteps = nx + nrows - 1 + (nw - 1) * (B2D - 1);
-    // inputs of step t: diagonal D = t - lag + row0 (the same for the whole wave)
+    const int lag = wave * B2D;
+    const int nsteps = nx + nrows - 1 + (nw - 1) * B2D;
+    // inputs of step t: diagonal D = t - lag + row0 (the same for the whole
+    // wave); the chunk's inflow row is read at one address by all lanes
     auto fetch = [&](int t, In2<T>& v) {
+        const int ilc = min(max(t - lag, 0), nx - 1);
+        v.yb0 = yin_buf[(long)ilc * 2 + 0];
+        v.yb1 = yin_buf[(long)ilc * 2 + 1];
         const int D = min(max(t - lag + row0, 0), nd - 1);
         const long e = (long)D * ny + jl;
         v.s = load4(srcq + e * 4);
         v.sig = sigq[e];
-        if (r == 0) {
-            const int ilc = min(max(t - lag, 0), nx - 1);
-            v.yb0 = yin_buf[(long)ilc * 2 + 0];
-            v.yb1 = yin_buf[(long)ilc * 2 + 1];
-        } else {
-            v.yb0 = v.yb1 = T(0);
+    };
+    // psi write-out of step t from stage buffer t & 1 (FP64): lane pair
+    // (2 q, 2 q + 1) stores the two halves of cell q, q = 32 h + lane / 2
+    auto write_half = [&](int t, int h, double2 v) {
+        const int q = h * 32 + (lane >> 1), o = lane & 1;
+        const int rq = wave * 64 + q;
+        const int ilq = t - rq - lag;
+        if (rq < nrows && ilq >= 0 && ilq < nx) {
+            const int jq = ry ? ny - 1 - (row0 + rq) : row0 + rq;
+            const int iq = rx ? nx - 1 - ilq : ilq;
+            const long cq = (long)jq * nx + iq;
+            *reinterpret_cast<double2*>(psi + (cq * ndirs + d) * 4 + 2 * o) = v;
         }
+    };
+    auto read_half = [&](int t, int h) {
+        const int q = h * 32 + (lane >> 1), o = lane & 1;
+        return *reinterpret_cast<const double2*>(&stage[t & 1][wave * 64 + q][2 * o]);
     };
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay;
     auto step = [&](int t, In2<T>& use, In2<T>& fill) {
         const int il = t - r - lag;
         fetch(t + R2D - 1, fill);
-        // y inflow: the lane below (DPP), the wave below (LDS ring, written
-        // B2D steps ago), or the inflow row of the chunk
+        double2 prev0{}, prev1{};
+        if constexpr (sizeof(T) == 8) {
+            prev0 = read_half(max(t - 1, 0), 0);
+            prev1 = read_half(max(t - 1, 0), 1);
+        }
+        // y inflow: the lane below (DPP), the wave below (LDS ring), or the
+        // inflow row of the chunk
         T yi0 = wave_shr1(yo0), yi1 = wave_shr1(yo1);
         if (lane == 0) {
-            if (wave == 0) {
-                yi0 = use.yb0;
-                yi1 = use.yb1;
-            } else {
-                const int sl = (t - B2D) & (2 * B2D - 1);
-                yi0 = lds[sl][wave - 1][0];
-                yi1 = lds[sl][wave - 1][1];
-            }
+            yi0 = wave == 0 ? use.yb0 : rin0;
+            yi1 = wave == 0 ? use.yb1 : rin1;
+        }
+        if (lane == 0 && wave > 0) {
+            // value for step t + 1, written by wave - 1 at step t - B2D
+            const int sl = (t - B2D) & (2 * B2D - 1);
+            rin0 = lds[sl][wave - 1][0];
+            rin1 = lds[sl][wave - 1][1];
         }
         const bool active = rowok && il >= 0 && il < nx;
         T g[4], u[4];
@@ -250,23 +274,14 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
         yo0 = active ? u[2] : yo0;
         yo1 = active ? u[3] : yo1;
         if constexpr (sizeof(T) == 8) {
-            // stage, then lane pair (2 q, 2 q + 1) writes the halves of cell q
-            store4(stage[lane], u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int q = h * 32 + (lane >> 1), o = lane & 1;
-                const int rq = wave * 64 + q;
-                const int ilq = t - rq - lag;
-                if (rq < nrows && ilq >= 0 && ilq < nx) {
-                    const int jq = ry ? ny - 1 - (row0 + rq) : row0 + rq;
-                    const int iq = rx ? nx - 1 - ilq : ilq;
-                    const long cq = (long)jq * nx + iq;
-                    *reinterpret_cast<double2*>(psi + (cq * ndirs + d) * 4 + 2 * o) =
-                        *reinterpret_cast<const double2*>(&stage[q][2 * o]);
-                }
+            // the unconditional stage write consumes the solve, so the solve
+            // stays ahead of the (branchy) write-out of the previous step and
+            // the stage reads of that step complete behind the arithmetic
+            store4(stage[t & 1][r], u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            if (t > 0) {
+                write_half(t - 1, 0, prev0);
+                write_half(t - 1, 1, prev1);
             }
-            __builtin_amdgcn_wave_barrier();
         } else {
             if (active) {
                 const int i = rx ? nx - 1 - il : il;
@@ -292,6 +307,10 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
         for (int k = 0; k < R2D; ++k)
             if (t + k < nsteps) step(t + k, sl[k], sl[(k + R2D - 1) % R2D]);
     }
+    if constexpr (sizeof(T) == 8) {
+        write_half(nsteps - 1, 0, read_half(nsteps - 1, 0));
+        write_half(nsteps - 1, 1, read_half(nsteps - 1, 1));
+    }
 }
 
 // blockIdx.x: direction; one launch per row chunk.  sigskew / srcskew: the
@@ -303,7 +322,7 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
                                                        long xstride, T* __restrict__ ybuf, long ystride, int chunk,
                                                        int nchunk, int row0, int nrows, T* __restrict__ psi) {
     __shared__ T lds[2 * B2D][ROWS2D / 64][2];
-    __shared__ __align__(16) T stage[ROWS2D][4];
+    __shared__ __align__(16) T stage[sizeof(T) == 8 ? 2 : 1][ROWS2D][4];
     const int d = blockIdx.x;
     const DirInfo di = dirs[d];
     const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
@@ -314,10 +333,9 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
     const T* xfd = xf + d * xstride;
     const T* yin = ybuf + d * ystride + (long)chunk * nx * 2;
     T* yout = (chunk + 1 < nchunk) ? ybuf + d * ystride + (long)(chunk + 1) * nx * 2 : nullptr;
-    T (*stg)[4] = stage + (threadIdx.x & ~63);
-#define SN_CASE2(MM)                                                                                         \
-    case MM:                                                                                                 \
-        sweep2d_body<T, MM>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, lds, stg); \
+#define SN_CASE2(MM)                                                                                           \
+    case MM:                                                                                                   \
+        sweep2d_body<T, MM>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, lds, stage); \
         break;
     switch (m) {
         SN_CASE2(0)
