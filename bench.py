@@ -64,6 +64,44 @@ def traffic_from_profiles(kernel_key):
         return None
 
 
+COPY_PROBE_BYTES = 1 << 31
+
+
+def copy_probe():
+    """Three copies of a 2 GiB FP64 buffer: each reads and writes exactly
+    COPY_PROBE_BYTES, which scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 x {COPY_PROBE_BYTES} bytes")
+
+
+def sweeps_only(name, prec_name, n):
+    """n sweeps of one workload from a seeded random phi (counter passes)."""
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_sweep
+    dev = torch.device("cuda:0")
+    p = sninputs.config(name)
+    prec, dt = (SN_FP64, torch.float64) if prec_name == "fp64" else (SN_FP32, torch.float32)
+    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
+    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
+    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
+    phi = torch.rand((p.ncells, p.nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
+    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
+        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=dt, device=dev)
+        for _ in range(n):
+            sn_sweep(ctx, phi, q, None, False, prec, psi)
+        torch.cuda.synchronize()
+    log(f"{n} sweeps of {name} in {prec_name}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,11 +109,23 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 S12 sweep measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 2 GiB device copy three times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--sweeps-only", type=int, default=0, metavar="N",
+                    help="only run N sweeps of --config in --prec (for rocprofv3 counter passes)")
+    ap.add_argument("--config", default="c2", help="workload of --sweeps-only (c1..c5)")
+    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"), help="sweep precision of --sweeps-only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.sweeps_only:
+        sweeps_only(args.config, args.prec, args.sweeps_only)
+        return
 
     import numpy as np
     import torch

@@ -1,0 +1,89 @@
+"""Summaries of rocprofv3 output for the sweep kernels.
+
+  python -m paper_2001_09196_amd.profile_summary stats <dir> <out.txt> <command...>
+      per-kernel table (calls, average and total duration) from the
+      *_kernel_stats.csv of a `rocprofv3 --kernel-trace --stats --output-format csv` run
+  python -m paper_2001_09196_amd.profile_summary traffic <key> <kernel-substring> <fetch_dir> <write_dir>
+      <copy_fetch_dir> <copy_write_dir> <copy_bytes> <out.txt> <traffic.json>
+      HBM bytes per dispatch of one kernel from FETCH_SIZE and WRITE_SIZE runs (KiB per
+      dispatch), each scaled so that a plain copy of copy_bytes reads as copy_bytes; the entry
+      of traffic.json records the sha256 of sweep.hip the counters were taken on.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _one(pattern):
+    fs = sorted(glob.glob(pattern, recursive=True))
+    if not fs:
+        raise SystemExit(f"no file matches {pattern}")
+    return fs[0]
+
+
+def stats(d, out, command):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*kernel_stats.csv")))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+             f"{'kernel':70s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in rows[:25]:
+        name = r["Name"]
+        if len(name) > 70:
+            name = name[:67] + "..."
+        lines.append(f"{name:70s} {int(r['Calls']):7d} {float(r['AverageNs'])/1e3:10.2f} "
+                     f"{float(r['TotalDurationNs'])/1e6:10.3f} {float(r['Percentage']):6.2f}")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _per_dispatch(d, counter, kernel):
+    vals = {}
+    for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
+        if r["Counter_Name"] == counter and kernel in r["Kernel_Name"]:
+            vals.setdefault(r["Dispatch_Id"], 0.0)
+            vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel} in {d}")
+    v = sorted(vals.values())
+    return v[len(v) // 2], len(v)   # median over dispatches, KiB
+
+
+def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, command):
+    copy_bytes = float(copy_bytes)
+    cf, _ = _per_dispatch(cfdir, "FETCH_SIZE", "copy")
+    cw, _ = _per_dispatch(cwdir, "WRITE_SIZE", "copy")
+    sf, sw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    f, nf = _per_dispatch(fdir, "FETCH_SIZE", kernel)
+    w, nw = _per_dispatch(wdir, "WRITE_SIZE", kernel)
+    fb, wb = f * 1024 * sf, w * 1024 * sw
+    src = os.path.join(HERE, "csrc", "sweep.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    lines = [f"# HBM traffic of {kernel} ({key})", f"# commands: {command}", "",
+             f"copy probe: FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB per {copy_bytes:.0f}-byte copy -> "
+             f"scale fetch {sf:.3f}, write {sw:.3f}",
+             f"kernel: FETCH_SIZE {f:.0f} KiB (median of {nf} dispatches), WRITE_SIZE {w:.0f} KiB ({nw})",
+             f"scaled bytes per dispatch: read {fb:.4e}, write {wb:.4e}, total {fb + wb:.4e}",
+             f"sweep.hip sha256 {sha}"]
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    data = json.load(open(jpath)) if os.path.exists(jpath) else {}
+    data[key] = {"bytes_per_launch": fb + wb, "read_bytes": fb, "write_bytes": wb, "kernel": kernel,
+                 "sweep_hip_sha256": sha, "fetch_scale": sf, "write_scale": sw}
+    json.dump(data, open(jpath, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    a = sys.argv[1:]
+    if a and a[0] == "stats":
+        stats(a[1], a[2], " ".join(a[3:]))
+    elif a and a[0] == "traffic":
+        traffic(*a[1:10], " ".join(a[10:]))
+    else:
+        raise SystemExit(__doc__)
