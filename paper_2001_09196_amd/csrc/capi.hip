@@ -415,7 +415,35 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.nplanes = 0;
         c->plane_off.assign(1, 0);
         if ((rc = c->tiles.ensure(1))) return rc;
-        g.groups = nullptr;
+        // Workgroup order: workgroups are dealt to the eight XCDs round robin
+        // (workgroup i on XCD i % 8) and every XCD has its own L2, so the
+        // directions of one quadrant, which read the same input arrays, go
+        // to XCDs 2q and 2q + 1; leftovers fill the remaining positions.
+        {
+            std::vector<std::vector<int>> cls(4);
+            for (int d = 0; d < c->ndirs; ++d) {
+                const DirInfo& di = c->hdirs[d];
+                cls[di.rx | (di.ry << 1)].push_back(d);
+            }
+            std::vector<std::vector<int>> xq(8);
+            for (int q = 0; q < 4; ++q)
+                for (size_t e = 0; e < cls[q].size(); ++e) xq[2 * q + (e & 1)].push_back(cls[q][e]);
+            std::vector<int> order, rest;
+            std::vector<size_t> pos(8, 0);
+            for (int i = 0; i < c->ndirs; ++i) {
+                auto& v = xq[i % 8];
+                if (pos[i % 8] < v.size()) order.push_back(v[pos[i % 8]++]);
+                else order.push_back(-1);
+            }
+            for (int x = 0; x < 8; ++x)
+                for (size_t e = pos[x]; e < xq[x].size(); ++e) rest.push_back(xq[x][e]);
+            size_t ri = 0;
+            for (auto& o : order)
+                if (o < 0) o = rest[ri++];
+            if ((rc = c->groups.ensure(order.size()))) return rc;
+            HIPCHK(hipMemcpy(c->groups.p, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+            g.groups = c->groups.p;
+        }
         g.nclasses = g.groups_per_class = 0;
         // sigma_t in the diagonal-major layout of the 2D sweep
         const size_t ns = (size_t)skew2d_elems(mesh->nx, mesh->ny, 1);

@@ -22,7 +22,8 @@ struct SweepGeom {
     int nclasses;      // 3D: reflection classes with at least one direction
     int groups_per_class;  // 3D: direction groups of four per class (max over classes)
     const int* groups; // 3D: device [nclasses * groups_per_class][6]: four direction ids (-1 = empty),
-                       //     the first id if the valid ids are consecutive (else -1), the valid count
+                       //     the first id if the valid ids are consecutive (else -1), the valid count;
+                       // 2D: device [ndirs] direction of each workgroup (XCD-aware order)
     int nplanes;       // 3D tile-diagonal planes
     int nchunk;        // 2D row chunks of at most ROWS2D rows
     long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements)
@@ -38,10 +39,10 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st);
 inline long sink_elems(const SweepGeom&) { return 1; }
 // per-cell array [ncells][nn] -> four quadrant diagonal-major arrays
-// [4][nx + ny - 1][ny][nn] (2D sweep input layout)
+// [4][ceil(ny / 64)][nx + 63][64][nn] (2D sweep input layout)
 template <typename T>
 hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_t st);
-inline long skew2d_elems(int nx, int ny, int nn) { return 4L * (nx + ny - 1) * ny * nn; }
+inline long skew2d_elems(int nx, int ny, int nn) { return 4L * ((ny + 63) / 64) * (nx + 63) * 64 * nn; }
 
 // scalar-flux kernels (flux.hip)
 template <typename T>

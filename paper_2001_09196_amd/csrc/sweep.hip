@@ -127,24 +127,29 @@ __device__ __forceinline__ void store4(T* p, T a0, T a1, T a2, T a3) {
 // 2D diagonal-major input layout
 // ---------------------------------------------------------------------------
 // For the quadrant with reflection (rx, ry), local cell (il, jl) of the
-// reflected frame lies on diagonal D = il + jl.  At a given step the lanes
-// of a wave own consecutive rows jl on one diagonal, so an array stored as
-// [D][jl] (D in [0, nx + ny - 1), entries off the mesh zero) turns each
-// wave's cell loads into one contiguous run instead of one cache line per
-// lane.  out: [4 quadrants][nx + ny - 1][ny][nn].
+// reflected frame lies on diagonal il + jl.  A wave owns the 64 rows
+// jl = 64 b + l (l = lane) of one row block b and at a given step works on
+// one diagonal of it, so each block is stored as a parallelogram
+// [s][l], s = il + l in [0, nx + 63): every load of a wave is one contiguous
+// run instead of one cache line per lane, and only the two 64 x 64 ramp
+// triangles are padding (entries off the mesh are zero).
+// out: [4 quadrants][ceil(ny / 64) blocks][nx + 63][64][nn].
 template <typename T>
 __global__ void skew2d_kernel(int nx, int ny, int nn, const T* __restrict__ in, T* __restrict__ out) {
-    const long nd = (long)nx + ny - 1;
-    const long per = nd * ny;
+    const long ns = (long)nx + 63;
+    const long nb = (ny + 63) / 64;
+    const long per = nb * ns * 64;
     const long total = 4 * per;
     for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
         const int q = (int)(idx / per);
         const long e = idx - q * per;
-        const int D = (int)(e / ny), jl = (int)(e - (long)D * ny);
-        const int il = D - jl;
+        const int l = (int)(e & 63);
+        const long bs = e >> 6;
+        const int b = (int)(bs / ns), sd = (int)(bs - (long)b * ns);
+        const int il = sd - l, jl = 64 * b + l;
         T* o = out + idx * nn;
-        if (il >= 0 && il < nx) {
+        if (il >= 0 && il < nx && jl < ny) {
             const int i = (q & 1) ? nx - 1 - il : il;
             const int j = (q & 2) ? ny - 1 - jl : jl;
             const T* src = in + ((long)j * nx + i) * nn;
@@ -197,7 +202,9 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     const int j = ry ? ny - 1 - jl : jl;
     const long rowbase = (long)j * nx;
     const bool top = yout_buf != nullptr && r == nrows - 1;
-    const int nd = nx + ny - 1;
+    const int ns = nx + 63;
+    // this wave's row block in the diagonal-major arrays
+    const long blk = (long)((row0 >> 6) + wave) * ns;
     T xin0 = xf[(long)jl * 2 + 0];
     T xin1 = xf[(long)jl * 2 + 1];
     T yo0 = T(0), yo1 = T(0);
@@ -205,14 +212,15 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     const int nw = (nrows + 63) / 64;
     const int lag = wave * B2D;
     const int nsteps = nx + nrows - 1 + (nw - 1) * B2D;
-    // inputs of step t: diagonal D = t - lag + row0 (the same for the whole
-    // wave); the chunk's inflow row is read at one address by all lanes
+    // inputs of step t: diagonal s = t - lag - 64 wave of the row block (the
+    // same for the whole wave); the chunk's inflow row is read at one address
+    // by all lanes
     auto fetch = [&](int t, In2<T>& v) {
         const int ilc = min(max(t - lag, 0), nx - 1);
         v.yb0 = yin_buf[(long)ilc * 2 + 0];
         v.yb1 = yin_buf[(long)ilc * 2 + 1];
-        const int D = min(max(t - lag + row0, 0), nd - 1);
-        const long e = (long)D * ny + jl;
+        const int sd = min(max(t - lag - 64 * wave, 0), ns - 1);
+        const long e = (blk + sd) * 64 + lane;
         v.s = load4(srcq + e * 4);
         v.sig = sigq[e];
     };
@@ -313,21 +321,24 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
     }
 }
 
-// blockIdx.x: direction; one launch per row chunk.  sigskew / srcskew: the
-// diagonal-major arrays of the four quadrants ([4][nx + ny - 1][ny][nn]).
+// blockIdx.x: position in dir_order (directions of one quadrant are placed
+// on the same XCDs, whose L2 then holds that quadrant's arrays); one launch
+// per row chunk.  sigskew / srcskew: the diagonal-major arrays of the four
+// quadrants (skew2d_kernel layout).
 template <typename T>
 __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndirs, const DirInfo* __restrict__ dirs,
+                                                       const int* __restrict__ dir_order,
                                                        int transpose, const T* __restrict__ sigskew,
                                                        const T* __restrict__ srcskew, const T* __restrict__ xf,
                                                        long xstride, T* __restrict__ ybuf, long ystride, int chunk,
                                                        int nchunk, int row0, int nrows, T* __restrict__ psi) {
     __shared__ T lds[2 * B2D][ROWS2D / 64][2];
     __shared__ __align__(16) T stage[sizeof(T) == 8 ? 2 : 1][ROWS2D][4];
-    const int d = blockIdx.x;
+    const int d = dir_order[blockIdx.x];
     const DirInfo di = dirs[d];
     const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
     const T ax = T(di.ax), ay = T(di.ay);
-    const long per = (long)(nx + ny - 1) * ny;
+    const long per = (long)((ny + 63) / 64) * (nx + 63) * 64;
     const T* sq = sigskew + m * per;
     const T* cq = srcskew + m * per * 4;
     const T* xfd = xf + d * xstride;
@@ -629,7 +640,8 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
             int nrows = std::min(ROWS2D, g.ny - row0);
             int nw = (nrows + 63) / 64;
             hipLaunchKernelGGL(sweep2d_kernel<T>, dim3(g.ndirs), dim3(64 * nw), 0, st, g.nx, g.ny, g.ndirs, dirs,
-                               transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows, psi);
+                               g.groups, transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows,
+                               psi);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -649,7 +661,7 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
 
 template <typename T>
 hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_t st) {
-    const long total = 4L * (nx + ny - 1) * ny;
+    const long total = 4L * ((ny + 63) / 64) * (nx + 63) * 64;
     const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
     hipLaunchKernelGGL(skew2d_kernel<T>, dim3(blocks), dim3(256), 0, st, nx, ny, nn, in, out);
     return hipGetLastError();
