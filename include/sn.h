@@ -8,7 +8,7 @@
  *     Omega_d . grad psi_d + sigma_t psi_d = sigma_s / (4 pi) phi + q / (4 pi),
  *     phi = sum_d w_d psi_d,  sum_d w_d = 4 pi,
  * with psi_d prescribed on the inflow boundary (vacuum when not given).
- * Discretisation (Section 4.1, eq. Tmat1 at eps = 1): Q1 Lagrange basis on the
+ * Discretisation (Section 3.1, eq. Tmat1 at eps = 1): Q1 Lagrange basis on the
  * cell corners, exact integrals, upwind face coupling.
  *
  * Data layout (all arrays are caller-owned; "device" means GPU memory
@@ -73,7 +73,7 @@ typedef struct sn_context sn_context;
 /* Create a context for one mesh, quadrature and set of cross sections.
  * sigma_t, sigma_s: device [ncells] FP64 (copied; the caller may free them
  * afterwards).  eta: thick threshold, a cell is thick iff sigma_s >= eta
- * (Section 3.3; the paper uses eta = 1).  Builds the thick-cell list and the
+ * (Sections 2.3 and 3.2; the paper uses eta = 1).  Builds the thick-cell list and the
  * diffusion preconditioner on the GPU.  stream: a hipStream_t (NULL = default
  * stream).  Synchronises the stream before returning.
  * Errors: INVALID (bad sizes, sigma_s > sigma_t, negative or non-finite
@@ -123,7 +123,7 @@ typedef struct {
 /* Heterogeneous DSA, Alg. 2 applied to the source-iteration residual:
  *   phi_out = phi_si + P_T D_ff^{-1} Sigma_f R_T (phi_si - phi_old),
  * D_ff the SIP diffusion operator (eq. SIP) on the thick DOFs only (principal
- * submatrix, Section 4.2), solved by block-Jacobi preconditioned CG in FP64.
+ * submatrix, Section 3.2), solved by block-Jacobi preconditioned CG in FP64.
  * Thin and void DOFs: phi_out = phi_si.  All three arrays device
  * [ncells][nn]; phi_out may alias phi_si.  stats (host, may be NULL) is filled
  * after a stream synchronisation.  Returns CG_BREAKDOWN if p^T D p <= 0. */

@@ -23,11 +23,11 @@
  *   (2) Q1 Lagrange basis on the cell corners, exact integrals, no lumping.
  *   (3) upwind coupling: on an inflow face (Omega.n < 0) the load
  *       int |Omega.n| v psi_upwind is added; outflow faces carry nothing.
- *   (4) thick iff sigma_s >= eta (Sec. 3.3, Sec. 4.2), all DOFs of a thick
+ *   (4) thick iff sigma_s >= eta (Sec. 2.3, Sec. 3.2), all DOFs of a thick
  *       cell thick.
  *   (5) diffusion operator: SIP form (eq. SIP) with D = 1/(3 sigma_t),
  *       penalty kappa = max((1/8pi) sum_d w_d |Omega_d.n|, 8 D/h), principal
- *       submatrix on thick DOFs (Sec. 4.2): thick-thin faces keep the thick
+ *       submatrix on thick DOFs (Sec. 3.2): thick-thin faces keep the thick
  *       side's terms only, domain faces get kappa int u v.
  *   (6) Alg. 2 acts on the source-iteration residual: phi <- phi_SI +
  *       P_T D_ff^{-1} Sigma_f (phi_SI - phi) with Sigma_f the mass matrix of

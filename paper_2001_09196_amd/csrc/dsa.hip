@@ -1,10 +1,10 @@
 // Heterogeneous (thick-only) DSA, Alg. 2 of the paper, applied to the source-
 // iteration residual:  phi <- phi_SI + P_T D_ff^{-1} Sigma_f R_T (phi_SI - phi).
 //
-// * Thick set (Sec. 3.3, Sec. 4.2): cell K is thick iff sigma_s,K >= eta; the
+// * Thick set (Sec. 2.3, Sec. 3.2): cell K is thick iff sigma_s,K >= eta; the
 //   thick cells are compacted in increasing cell order by a deterministic scan.
 // * D_ff: the SIP diffusion form (eq. SIP at eps = 1) restricted to the thick
-//   DOFs (principal submatrix, Sec. 4.2), applied matrix-free:
+//   DOFs (principal submatrix, Sec. 3.2), applied matrix-free:
 //     cell:  D_K int grad u . grad v + sigma_a,K int u v,  D_K = 1/(3 sigma_t,K)
 //     face (outward normal n of K, neighbour values zero if it is thin):
 //       -int {D d_n u} v_K - 1/2 int (u_K - u_nb) D_K d_n v_K + kappa int (u_K - u_nb) v_K

@@ -1,7 +1,7 @@
 // Device-side building blocks shared by the sweep kernels: per-direction
 // constants and the local upwind-DG cell solve.
 //
-// Cell problem (Section 4.1, eq. Tmat1 at eps = 1, one Cartesian Q1 cell):
+// Cell problem (Section 3.1, eq. Tmat1 at eps = 1, one Cartesian Q1 cell):
 //   A u = f,  A = sum_axes |Omega_a| (mass of the other axes) (x) G_a + sigma_t M,
 // with the 1D upwind block G = [[1/2, 1/2], [-1/2, 1/2]] in a frame where
 // every direction component is positive.  Every direction is mapped to that

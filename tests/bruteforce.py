@@ -7,7 +7,7 @@ cell and face by face, and the resulting global matrices are solved densely
 with numpy.  Nothing here uses the oracle's 1D/Kronecker formulas.
 
 Weak forms (uniform Cartesian grid, Q1 Lagrange basis on cell corners):
-* transport (Section 4.1, eq. Tmat1 at eps = 1), direction Omega, cell K:
+* transport (Section 3.1, eq. Tmat1 at eps = 1), direction Omega, cell K:
     int_K (Omega.grad u) v + sigma_t u v
     + sum_{faces F of K, Omega.n < 0} int_F |Omega.n| (u_K - u_upwind) v
   with u_upwind the neighbour's trace or the boundary inflow;

@@ -1,11 +1,11 @@
-"""Pins of the oracle's thick-region diffusion operator (eq. SIP; Sec. 4.2).
+"""Pins of the oracle's thick-region diffusion operator (eq. SIP, Sec. 3.1; Sec. 3.2).
 
 P13 the assembled D_ff equals a pointwise-quadrature evaluation of the SIP
     bilinear form (principal submatrix semantics), is symmetric and SPD, and
     satisfies D 1 = sigma_a M 1 on thick cells whose faces are all thick.
 P14 the CG correction equals a dense solve.
 P15 heterogeneous DSA is not a global DSA solve restricted to the thick DOFs
-    (Section 3.3).
+    (Section 2.3).
 """
 import math
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's transport sweep (Section 2.2, eq. psi; Section 4.1, eq. Tmat1).
+"""Pins of the oracle's transport sweep (Section 2.2, eq. psi; Section 3.1, eq. Tmat1).
 
 P1 brute force: dense L_d^{-1} (and L_d^{-T}) from the quadrature-assembled weak form.
 P2 closed form: pure absorber, outflow factor of the upwind Q1 scheme per cell.
