@@ -321,6 +321,32 @@ def bench_3d(log):
             log(f"c5 sweep {name}: {ms:.3f} ms, grind {ms*1e6/cd:.5f} ns, {res[name]['achieved_GBs']:.0f} GB/s")
             del psi
             torch.cuda.empty_cache()
+        # source iterations: fused sweep + moment (psi never stored) and DSA
+        from paper_2001_09196_amd import sn_source_iterate
+        for name, prec in (("fp32", SN_FP32), ("fp64", SN_FP64)):
+            k = 4
+            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=1e-4,
+                              cg_maxit=2000)
+            phi.zero_()
+            sn_set_kernel_timing(ctx, True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=1e-4,
+                                  cg_maxit=2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            kt = sn_kernel_timing(ctx)
+            sn_set_kernel_timing(ctx, False)
+            fused = kt["sweep_ms"] / max(kt["sweep_count"], 1)
+            res[name]["si_step_ms"] = (t1 - t0) / k * 1e3
+            res[name]["fused_sweep_moment_ms"] = fused
+            res[name]["fused_grind_ns"] = fused * 1e6 / cd
+            res[name]["dsa_ms"] = kt["dsa_ms"] / max(kt["dsa_count"], 1)
+            res[name]["cg_iters"] = r["cg_hist"].tolist()
+            log(f"c5 SI {name}: step {res[name]['si_step_ms']:.2f} ms, fused sweep+moment {fused:.3f} ms, "
+                f"dsa {res[name]['dsa_ms']:.3f} ms, CG {r['cg_hist'].tolist()}")
+            del phi
     return res
 
 

@@ -98,7 +98,7 @@ struct sn_context {
     DevBuf<double> xf64, yf64, zf64, src64, sink64, sigskew64, srcskew64;
     DevBuf<float> xf32, yf32, zf32, src32, sink32, sigskew32, srcskew32;
     // source iteration workspace
-    DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3;
+    DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3, phioct;
     DevBuf<float> psi32;
     int nrpart = 1;
     // optional event timing of the sweep kernels and of the DSA solves
@@ -190,6 +190,57 @@ int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, 
         HIPCHK(launch_moment<float>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, (const float*)psi, phi, accumulate,
                                     ctx->stream));
     return 0;
+}
+
+// 3D fused sweep + moment in precision T: phi_out (+)= sum_d w_d psi_d, psi not stored
+template <typename T>
+int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q,
+                      const double* inflow, int transpose, double* phi_out, int accumulate, DevBuf<T>& xf,
+                      DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, const T* sigt) {
+    const SweepGeom& g = ctx->sg;
+    int rc;
+    if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
+    if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
+    if ((rc = zf.ensure((size_t)std::max<long>(g.zstride, 1) * g.ndirs))) return rc;
+    if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
+    if ((rc = ctx->phioct.ensure((size_t)g.nclasses * ctx->nc * 8))) return rc;
+    HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
+    HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    size_t e0 = 0, e1 = 0;
+    if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
+                                  ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, ctx->stream));
+    if (ctx->timing) {
+        if ((rc = record_event(ctx, &e1))) return rc;
+        ctx->sweep_ev.emplace_back(e0, e1);
+    }
+    return 0;
+}
+
+// phi_out (+)= sum_d w_d L_d^{-1}(...) for source iteration: in 3D the fused
+// kernels (psi never reaches memory); in 2D a psi-writing sweep into the
+// context's psi workspace followed by the moment
+int do_sweep_flux(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
+                  int transpose, sn_precision prec, double* phi_out, int accumulate) {
+    int rc;
+    if (ctx->mesh.dim == 3) {
+        if (prec == SN_FP64)
+            return sweep_flux3d_impl<double>(ctx, phi, phi_prev, q, inflow, transpose, phi_out, accumulate,
+                                             ctx->xf64, ctx->yf64, ctx->zf64, ctx->src64, ctx->sigt.p);
+        return sweep_flux3d_impl<float>(ctx, phi, phi_prev, q, inflow, transpose, phi_out, accumulate, ctx->xf32,
+                                        ctx->yf32, ctx->zf32, ctx->src32, ctx->sigt32.p);
+    }
+    const size_t npsi = (size_t)ctx->nc * ctx->ndirs * ctx->nn;
+    void* psi;
+    if (prec == SN_FP64) {
+        if ((rc = ctx->psi64.ensure(npsi))) return rc;
+        psi = ctx->psi64.p;
+    } else {
+        if ((rc = ctx->psi32.ensure(npsi))) return rc;
+        psi = ctx->psi32.p;
+    }
+    if ((rc = do_sweep(ctx, phi, phi_prev, q, inflow, transpose, prec, psi))) return rc;
+    return do_moment(ctx, psi, prec, phi_out, accumulate);
 }
 
 // phi_out = phi_si + P_T delta; returns an SN code; fills stats
@@ -317,6 +368,7 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->phiprev.release();
     ctx->rpart.release();
     ctx->res3.release();
+    ctx->phioct.release();
     delete ctx;
 }
 
@@ -632,16 +684,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
                        (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1)))
         return fail(SN_ERR_INVALID, "bad DSA options");
     const long n = ctx->nc * ctx->nn;
-    const size_t npsi = (size_t)ctx->nc * ctx->ndirs * ctx->nn;
     int rc;
-    void* psi;
-    if (o->prec == SN_FP64) {
-        if ((rc = ctx->psi64.ensure(npsi))) return rc;
-        psi = ctx->psi64.p;
-    } else {
-        if ((rc = ctx->psi32.ensure(npsi))) return rc;
-        psi = ctx->psi32.p;
-    }
     if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->phitmp.ensure(n)) || (rc = ctx->phiprev.ensure(n))) return rc;
     const int tr = o->transpose ? 1 : 0;
     // FP32 sweeps act on the iterate increment (defect correction): after the
@@ -657,11 +700,10 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     bool refreshed = false;  // FP32 form: the 1e-4 refresh sweep has been done
     for (; it < o->max_it; ++it) {
         if (!incr || it == 0) {
-            if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, o->prec, psi))) return rc;
-            if ((rc = do_moment(ctx, psi, o->prec, ctx->phisi.p))) return rc;
+            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, o->prec, ctx->phisi.p, 0))) return rc;
         } else {
-            if ((rc = do_sweep(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, psi))) return rc;
-            if ((rc = do_moment(ctx, psi, o->prec, ctx->phisi.p, 1))) return rc;
+            if ((rc = do_sweep_flux(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, ctx->phisi.p, 1)))
+                return rc;
         }
         verified = false;
         double r3[3];
@@ -671,8 +713,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
                 bnorm = std::sqrt(r3[1]);
             } else {
                 // ||b||: the transport update of q alone, from phi = 0
-                if ((rc = do_sweep(ctx, nullptr, nullptr, q, inflow, tr, o->prec, psi))) return rc;
-                if ((rc = do_moment(ctx, psi, o->prec, ctx->phitmp.p))) return rc;
+                if ((rc = do_sweep_flux(ctx, nullptr, nullptr, q, inflow, tr, o->prec, ctx->phitmp.p, 0))) return rc;
                 double b3[3];
                 if ((rc = residual3(ctx, ctx->phitmp.p, ctx->phitmp.p, b3))) return rc;
                 bnorm = std::sqrt(b3[1]);
@@ -688,9 +729,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
             // form may only stop on an exact residual).  phi_SI is recomputed
             // from phi with one FP64 sweep and the increments continue from it.
             refreshed = true;
-            if ((rc = ctx->psi64.ensure(npsi))) return rc;
-            if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->psi64.p))) return rc;
-            if ((rc = do_moment(ctx, ctx->psi64.p, SN_FP64, ctx->phisi.p))) return rc;
+            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->phisi.p, 0))) return rc;
             if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
             verified = true;
             if (stats) stats->fp64_checks += 1;

@@ -38,6 +38,13 @@ template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st);
 inline long sink_elems(const SweepGeom&) { return 1; }
+// 3D fused sweep + moment (source iteration): psi is not stored; phioct
+// (workspace [nclasses][ncells][8]) receives each octant's share of phi, then
+// phi = (accumulate ? phi : 0) + sum over the octants in a fixed order.
+template <typename T>
+hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
+                               const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
+                               const int* plane_off, double* phioct, double* phi, int accumulate, hipStream_t st);
 // per-cell array [ncells][nn] -> four quadrant diagonal-major arrays
 // [4][ceil(ny / 64)][nx + 63][64][nn] (2D sweep input layout)
 template <typename T>

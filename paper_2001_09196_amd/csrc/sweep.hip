@@ -405,12 +405,43 @@ struct In3 {
     Vec4<T> y, z;  // y- and z-face inflow (lanes on the tile's y = 0 / z = 0 side)
 };
 
-template <typename T, int M>
+// Sum over the four direction rows (k = lane / 16) of a 16-lane pencil,
+// returned in every row: the gfx950 permlane swaps exchange rows 0 <-> 1 and
+// 2 <-> 3, then the two 32-lane halves; the order of the additions is fixed,
+// (v0 + v1) + (v2 + v3), and the same in every row.
+__device__ __forceinline__ double rows_sum(double v) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double s = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0])) +
+                     __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
+    const unsigned long long y = (unsigned long long)__double_as_longlong(s);
+    const unsigned lo2 = (unsigned)y, hi2 = (unsigned)(y >> 32);
+    const auto c = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
+    const auto e = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
+    return __longlong_as_double((long long)(((unsigned long long)e[0] << 32) | c[0])) +
+           __longlong_as_double((long long)(((unsigned long long)e[1] << 32) | c[1]));
+}
+
+// fused sweep + moment: steps per workgroup barrier
+constexpr int RF = 4;
+
+// FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
+// stored; every step the lanes' w_d psi (FP64) is summed over the four
+// directions of a pencil (rows_sum), the 16 pencil sums of each wave go to an
+// LDS ring red[2 RF][waves][16][8], and every RF steps, after a workgroup
+// barrier, the workgroup adds the waves' sums in wave order and stores the
+// octant's share of phi for those cells (each cell is visited once per
+// octant, so plain stores suffice and the result does not depend on timing).
+template <typename T, int M, bool FUSED = false>
 __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, bool dok, T ax, T ay, T az,
                                              int I, int J, int K, int TX, int nTx, int nTy, int nTz,
                                              const T* __restrict__ sigt, const T* __restrict__ src,
                                              T* __restrict__ xf, T* __restrict__ yf, T* __restrict__ zf,
-                                             T* __restrict__ psi, int d0, int nvalid, T* __restrict__ stg) {
+                                             T* __restrict__ psi, int d0, int nvalid, T* __restrict__ stg,
+                                             double wgt = 0.0, double* __restrict__ red = nullptr,
+                                             double* __restrict__ phio = nullptr, int nwaves = 0) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1, rz = (M >> 2) & 1;
     const int lane = threadIdx.x & 63;
     const int jy = lane & 3, kz = (lane >> 2) & 3;
@@ -466,6 +497,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             zi[t] = row_shr<4>(zo[t]);
         }
         const bool active = pen && ir >= 0 && ir < len;
+        double acc[8];
+        if constexpr (FUSED) {
+#pragma unroll
+            for (int n = 0; n < 8; ++n) acc[n] = 0.0;
+        }
         if (active) {
             const int il = i0 + ir;
             if (jy == 0) {
@@ -505,7 +541,10 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             T o[8];
 #pragma unroll
             for (int n = 0; n < 8; ++n) o[n] = u[n ^ M];
-            if (nvalid > 0) {
+            if constexpr (FUSED) {
+#pragma unroll
+                for (int n = 0; n < 8; ++n) acc[n] = wgt * (double)o[n];
+            } else if (nvalid > 0) {
                 // staged: this lane's eight values go to LDS slot (pencil, k)
                 T* sp = stg + ((lane & 15) * 4 + (lane >> 4)) * 8;
                 store4(sp, o[0], o[1], o[2], o[3]);
@@ -522,7 +561,39 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             if (ir == len - 1 && I + 1 < nTx)
                 store4(xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4, xin[0], xin[1], xin[2], xin[3]);
         }
-        if (nvalid > 0) {
+        if constexpr (FUSED) {
+            const int wave = threadIdx.x >> 6;
+            double* rs = red + ((s % (2 * RF)) * nwaves + wave) * 128;
+#pragma unroll
+            for (int n = 0; n < 8; ++n) acc[n] = rows_sum(acc[n]);
+            if (lane < 16) {
+                double2* r2 = reinterpret_cast<double2*>(rs + lane * 8);
+#pragma unroll
+                for (int n = 0; n < 4; ++n) r2[n] = make_double2(acc[2 * n], acc[2 * n + 1]);
+            }
+            if ((s + 1) % RF == 0 || s == nsteps - 1) {
+                __syncthreads();
+                // the steps sb .. s of this batch: 128 (pencil, node) sums each
+                const int sb = s - s % RF;
+                const int nwork = (s - sb + 1) * 128;
+                for (int id = threadIdx.x; id < nwork; id += blockDim.x) {
+                    const int sj = sb + (id >> 7), q = (id >> 3) & 15, n = id & 7;
+                    const double* rq = red + (sj % (2 * RF)) * nwaves * 128 + q * 8 + n;
+                    double sum = 0.0;
+                    for (int w = 0; w < nwaves; ++w) sum += rq[w * 128];
+                    const int qy = q & 3, qz = q >> 2;
+                    const int qjl = J * 4 + qy, qkl = K * 4 + qz;
+                    const int qir = sj - (qy + qz);
+                    if (qjl < ny && qkl < nz && qir >= 0 && qir < len) {
+                        const int qil = i0 + qir;
+                        const int qi = rx ? nx - 1 - qil : qil;
+                        const int qj = ry ? ny - 1 - qjl : qjl;
+                        const int qk = rz ? nz - 1 - qkl : qkl;
+                        phio[(((long)qk * ny + qj) * nx + qi) * 8 + n] = sum;
+                    }
+                }
+            }
+        } else if (nvalid > 0) {
             // Write the staged psi of the 16 pencils: pencil q's block is the
             // nvalid consecutive directions d0.. of its current cell, nvalid*8
             // contiguous values, and consecutive lanes write consecutive
@@ -617,6 +688,68 @@ __global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, in
 #undef SN_CASE
 }
 
+// Fused sweep + moment (source iteration): as sweep3d_kernel, but psi is not
+// stored; phio receives, per reflection class (octant) blockIdx.y, that
+// octant's share sum_d w_d psi_d of phi ([class][cell][8], FP64).  Every wave
+// of the block takes part in the block-wide reductions, including waves of
+// empty direction groups (their lanes contribute zero).
+template <typename T>
+__global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int nz, int ndirs,
+                                                           const DirInfo* __restrict__ dirs, const double* __restrict__ w,
+                                                           int transpose, const int* __restrict__ groups,
+                                                           int groups_per_class, const T* __restrict__ sigt,
+                                                           const T* __restrict__ src, T* __restrict__ xf, long xstride,
+                                                           T* __restrict__ yf, long ystride, T* __restrict__ zf,
+                                                           long zstride, int TX, int nTx, int nTy, int nTz,
+                                                           const int* __restrict__ tiles, double* __restrict__ phioct) {
+    __shared__ __align__(16) double red[2 * RF * 6 * 128];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int grp = blockIdx.y * groups_per_class + wave;
+    const int* gi = groups + 6 * grp;
+    const int d = gi[lane >> 4];
+    const int mc = groups[6 * blockIdx.y * groups_per_class];  // first direction of the class (valid)
+    const bool dok = d >= 0;
+    const int dd = dok ? d : mc;
+    const int tile = tiles[blockIdx.x];
+    const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
+    const DirInfo dm = dirs[mc];
+    const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
+    const DirInfo di = dirs[dd];
+    const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
+    const double wgt = dok ? w[dd] : 0.0;
+    T* xd = xf + dd * xstride;
+    T* yd = yf + dd * ystride;
+    T* zd = zf + dd * zstride;
+    double* po = phioct + (long)blockIdx.y * nx * ny * nz * 8;
+#define SN_CASEF(MM)                                                                                             \
+    case MM:                                                                                                     \
+        sweep3d_body<T, MM, true>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, \
+                                  xd, yd, zd, nullptr, -1, 0, nullptr, wgt, red, po, groups_per_class);          \
+        break;
+    switch (m) {
+        SN_CASEF(0)
+        SN_CASEF(1)
+        SN_CASEF(2)
+        SN_CASEF(3)
+        SN_CASEF(4)
+        SN_CASEF(5)
+        SN_CASEF(6)
+        SN_CASEF(7)
+    }
+#undef SN_CASEF
+}
+
+// phi = sum over the classes of phioct (fixed order), or phi += that sum
+__global__ void octant_sum_kernel(long n, int ncls, const double* __restrict__ phioct, double* __restrict__ phi,
+                                  int accumulate) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < ncls; ++c) s += phioct[c * n + i];
+        phi[i] = accumulate ? phi[i] + s : s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -668,6 +801,31 @@ hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_
 }
 template hipError_t launch_skew2d<double>(int, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_skew2d<float>(int, int, int, const float*, float*, hipStream_t);
+
+template <typename T>
+hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
+                               const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
+                               const int* plane_off, double* phioct, double* phi, int accumulate, hipStream_t st) {
+    for (int p = 0; p < g.nplanes; ++p) {
+        int nt = plane_off[p + 1] - plane_off[p];
+        hipLaunchKernelGGL((sweep3d_flux_kernel<T>), dim3(nt, g.nclasses), dim3(64 * g.groups_per_class), 0, st,
+                           g.nx, g.ny, g.nz, g.ndirs, dirs, w, transpose, g.groups, g.groups_per_class, sigt, src,
+                           xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
+                           tiles + plane_off[p], phioct);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const long n = (long)g.nx * g.ny * g.nz * 8;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(octant_sum_kernel, dim3(blocks), dim3(256), 0, st, n, g.nclasses, phioct, phi, accumulate);
+    return hipGetLastError();
+}
+template hipError_t launch_sweep_flux3d<double>(const SweepGeom&, const DirInfo*, const double*, int, const double*,
+                                                const double*, double*, double*, double*, const int*, const int*,
+                                                double*, double*, int, hipStream_t);
+template hipError_t launch_sweep_flux3d<float>(const SweepGeom&, const DirInfo*, const double*, int, const float*,
+                                               const float*, float*, float*, float*, const int*, const int*,
+                                               double*, double*, int, hipStream_t);
 
 template hipError_t launch_init_faces<double>(const SweepGeom&, const DirInfo*, int, const double*, double*, double*,
                                               double*, hipStream_t);
