@@ -112,7 +112,15 @@ typedef struct {
     double cg_rtol;            /* stop when ||r|| <= cg_rtol ||b|| (zero initial guess) */
     int cg_maxit;              /* iteration cap (SN_ERR_NOT_CONVERGED is not raised for it) */
     int mass_kind;             /* 0: Sigma_f = mass of sigma_s; 1: mass of sigma_t (Sec. 2.2) */
+    int precond;               /* SN_PRECOND_BLOCK_JACOBI (inverse diagonal cell blocks) or SN_PRECOND_MG
+                                  (one symmetric geometric-multigrid V-cycle: damped block Jacobi on the
+                                  DG level, Galerkin piecewise-constant levels with 2x aggregation of the
+                                  cell grid and Jacobi smoothing, dense solve on <= 512 unknowns; the
+                                  hierarchy is built on the first use in a context) */
 } sn_dsa_opts;
+
+#define SN_PRECOND_BLOCK_JACOBI 0
+#define SN_PRECOND_MG 1
 
 typedef struct {
     int cg_iters;              /* CG iterations of this call */
@@ -123,7 +131,7 @@ typedef struct {
 /* Heterogeneous DSA, Alg. 2 applied to the source-iteration residual:
  *   phi_out = phi_si + P_T D_ff^{-1} Sigma_f R_T (phi_si - phi_old),
  * D_ff the SIP diffusion operator (eq. SIP) on the thick DOFs only (principal
- * submatrix, Section 3.2), solved by block-Jacobi preconditioned CG in FP64.
+ * submatrix, Section 3.2), solved by preconditioned CG in FP64 (opts->precond).
  * Thin and void DOFs: phi_out = phi_si.  All three arrays device
  * [ncells][nn]; phi_out may alias phi_si.  stats (host, may be NULL) is filled
  * after a stream synchronisation.  Returns CG_BREAKDOWN if p^T D p <= 0. */

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsn.so")
 SN_OK, SN_ERR_INVALID, SN_ERR_UNSUPPORTED, SN_ERR_NOMEM, SN_ERR_HIP = 0, 1, 2, 3, 4
 SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED, SN_ERR_CG_BREAKDOWN = 5, 6, 7
 SN_FP64, SN_FP32 = 0, 1
+SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG = 0, 1
 
 # every symbol declared in include/sn.h
 EXPORTED = ("sn_context_create", "sn_context_destroy", "sn_inflow_size", "sn_thick_count", "sn_sweep",
@@ -45,7 +46,8 @@ class sn_quad(ctypes.Structure):
 
 
 class sn_dsa_opts(ctypes.Structure):
-    _fields_ = [("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int), ("mass_kind", ctypes.c_int)]
+    _fields_ = [("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int), ("mass_kind", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class sn_dsa_stats(ctypes.Structure):
@@ -193,8 +195,10 @@ def sn_scalar_flux(ctx: Context, psi, prec: int, phi_out):
     _check(lib().sn_scalar_flux(ctx.handle, _ptr(psi), int(prec), _ptr(phi_out)))
 
 
-def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0):
-    o = sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind))
+def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0,
+                         precond=0):
+    """precond: SN_PRECOND_BLOCK_JACOBI (0) or SN_PRECOND_MG (1)."""
+    o = sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond))
     st = sn_dsa_stats()
     rc = _check(lib().sn_dsa_thick_correct(ctx.handle, _ptr(phi_old), _ptr(phi_si), _ptr(phi_out), ctypes.byref(o),
                                            ctypes.byref(st)))
@@ -202,13 +206,13 @@ def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, c
 
 
 def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_dsa=True, prec=SN_FP64,
-                      cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None):
+                      cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None, precond=0):
     """Returns dict(rc, iters, res_hist, cg_hist, seconds); raises on errors
     other than NOT_CONVERGED / DIVERGED (which are reported in rc).
     phi_ckpt: optional device tensor [cap, ncells, nn]; iterate it is kept in
     slot it % cap."""
     o = sn_iter_opts(float(tol), int(max_it), int(bool(use_dsa)), int(prec),
-                     sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind)), int(bool(transpose)),
+                     sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond)), int(bool(transpose)),
                      _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0)
     res = np.zeros(max_it, dtype=np.float64)
     cgh = np.zeros(max_it, dtype=np.int32)

@@ -91,6 +91,13 @@ struct sn_context {
     DevBuf<int> nbr;
     DevBuf<CgScalars> scal;
     int cg_hint = 8;
+    // geometric multigrid hierarchy (built on first use)
+    bool mg_ready = false;
+    int mg_lc = 1;
+    double mg_omega0 = 0.7;
+    MgDev mg{};
+    DevBuf<double> mg_diag, mg_offc, mg_b, mg_x, mg_y, mg_ainv, cz0;
+    DevBuf<int> mg_nbr, mg_parent, mg_child;
     // sweep
     SweepGeom sg{};
     DevBuf<int> tiles, groups;
@@ -244,6 +251,206 @@ int do_sweep_flux(sn_context* ctx, const double* phi, const double* phi_prev, co
 }
 
 // phi_out = phi_si + P_T delta; returns an SN code; fills stats
+double env_double(const char* name, double dflt) {
+    const char* e = std::getenv(name);
+    return e ? std::atof(e) : dflt;
+}
+
+// Inverse of a symmetric positive definite matrix (row-major, n x n) by
+// Cholesky factorisation; returns false if a pivot is not positive.
+bool spd_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
+    for (int j = 0; j < n; ++j) {
+        double d = a[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        a[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = a[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            a[(size_t)i * n + j] = v / d;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {  // L y = e_c
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= a[(size_t)i * n + k] * y[k];
+            y[i] = v / a[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+            double v = y[i];
+            for (int k = i + 1; k < n; ++k) v -= a[(size_t)k * n + i] * inv[(size_t)k * n + c];
+            inv[(size_t)i * n + c] = v / a[(size_t)i * n + i];
+        }
+    }
+    return true;
+}
+
+// Multigrid hierarchy for the thick-region operator: level-1 Galerkin
+// coefficients from the device, then 2 x 2 (x 2) aggregation of the cell
+// grid on the host (sums in a fixed order) until at most 512 unknowns
+// remain, whose operator is inverted densely.
+int mg_setup(sn_context* c) {
+    const DsaGeom& g = c->dg;
+    const int nt = g.nthick, dim = g.dim, nf = 2 * dim, nch = 1 << dim;
+    int rc;
+    DevBuf<double> d1, o1;
+    if ((rc = d1.ensure(nt)) || (rc = o1.ensure((size_t)nt * nf))) return rc;
+    HIPCHK(launch_mg_level1(g, c->thick.p, c->nbr.p, c->sigt.p, c->sigs.p, d1.p, o1.p, c->stream));
+    struct Lv {
+        int nx, ny, nz;
+        std::vector<long> pos;
+        std::vector<double> diag, off;
+        std::vector<int> nbr, parent, child;
+    };
+    std::vector<Lv> lv(2);
+    Lv& l1 = lv[1];
+    l1.nx = g.nx;
+    l1.ny = g.ny;
+    l1.nz = g.nz;
+    l1.diag.resize(nt);
+    l1.off.resize((size_t)nt * nf);
+    l1.nbr.resize((size_t)nt * nf);
+    std::vector<int> tc(nt);
+    HIPCHK(hipMemcpyAsync(l1.diag.data(), d1.p, nt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(l1.off.data(), o1.p, (size_t)nt * nf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(l1.nbr.data(), c->nbr.p, (size_t)nt * nf * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(tc.data(), c->thick.p, nt * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    l1.pos.assign(tc.begin(), tc.end());
+    for (auto& v : l1.nbr) v = v >= 0 ? v : -1;
+    while (lv.back().diag.size() > 512 && (int)lv.size() < MG_MAXL) {
+        Lv cl;
+        {
+            const Lv& f = lv.back();
+            cl.nx = (f.nx + 1) / 2;
+            cl.ny = (f.ny + 1) / 2;
+            cl.nz = (f.nz + 1) / 2;
+        }
+        Lv& f = lv.back();
+        const long ncg = (long)cl.nx * cl.ny * cl.nz;
+        std::vector<int> slot(ncg, -1);
+        const int nfine = (int)f.diag.size();
+        std::vector<long> key(nfine);
+        std::vector<int> q(nfine);
+        for (int e = 0; e < nfine; ++e) {
+            const long p = f.pos[e];
+            const int i = (int)(p % f.nx), j = (int)((p / f.nx) % f.ny), k = (int)(p / ((long)f.nx * f.ny));
+            key[e] = ((long)(k / 2) * cl.ny + j / 2) * cl.nx + i / 2;
+            q[e] = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+            slot[key[e]] = 0;
+        }
+        int n = 0;
+        for (long kk = 0; kk < ncg; ++kk)
+            if (slot[kk] == 0) {
+                slot[kk] = n++;
+                cl.pos.push_back(kk);
+            }
+        f.parent.resize(nfine);
+        cl.child.assign((size_t)n * nch, -1);
+        for (int e = 0; e < nfine; ++e) {
+            f.parent[e] = slot[key[e]];
+            cl.child[(size_t)f.parent[e] * nch + q[e]] = e;
+        }
+        cl.diag.assign(n, 0.0);
+        cl.off.assign((size_t)n * nf, 0.0);
+        cl.nbr.assign((size_t)n * nf, -1);
+        const int ext[3] = {cl.nx, cl.ny, cl.nz};
+        for (int S = 0; S < n; ++S) {
+            double d = 0.0;
+            for (int qq = 0; qq < nch; ++qq) {
+                const int e = cl.child[(size_t)S * nch + qq];
+                if (e < 0) continue;
+                d += f.diag[e];
+                for (int ff = 0; ff < nf; ++ff) {
+                    const int ne = f.nbr[(size_t)e * nf + ff];
+                    if (ne < 0) continue;
+                    if (f.parent[ne] == S) d += f.off[(size_t)e * nf + ff];
+                    else cl.off[(size_t)S * nf + ff] += f.off[(size_t)e * nf + ff];
+                }
+            }
+            cl.diag[S] = d;
+            const long p = cl.pos[S];
+            const int pos[3] = {(int)(p % cl.nx), (int)((p / cl.nx) % cl.ny), (int)(p / ((long)cl.nx * cl.ny))};
+            const long stride[3] = {1, cl.nx, (long)cl.nx * cl.ny};
+            for (int ff = 0; ff < nf; ++ff) {
+                const int ax = ff >> 1, sd = ff & 1;
+                const int np = pos[ax] + (sd ? 1 : -1);
+                if (np >= 0 && np < ext[ax]) cl.nbr[(size_t)S * nf + ff] = slot[p + (sd ? stride[ax] : -stride[ax])];
+            }
+        }
+        lv.push_back(std::move(cl));
+    }
+    const int L = (int)lv.size() - 1;
+    lv[L].parent.assign(lv[L].diag.size(), -1);
+    // dense inverse of the coarsest operator
+    const int nL = (int)lv[L].diag.size();
+    std::vector<double> A((size_t)nL * nL, 0.0), Ainv;
+    for (int i = 0; i < nL; ++i) {
+        A[(size_t)i * nL + i] = lv[L].diag[i];
+        for (int ff = 0; ff < nf; ++ff) {
+            const int j = lv[L].nbr[(size_t)i * nf + ff];
+            if (j >= 0) A[(size_t)i * nL + j] += lv[L].off[(size_t)i * nf + ff];
+        }
+    }
+    if (!spd_inverse(nL, A, Ainv)) return fail(SN_ERR_CG_BREAKDOWN, "coarsest multigrid operator is not SPD");
+    // flatten
+    MgDev& m = c->mg;
+    m = MgDev{};
+    m.L = L;
+    m.dim = dim;
+    long nv = 0, ncl = 0;
+    for (int l = 1; l <= L; ++l) {
+        m.n[l] = (int)lv[l].diag.size();
+        m.vo[l] = nv;
+        m.fo[l] = nv * nf;
+        m.co[l] = ncl;
+        nv += m.n[l];
+        if (l >= 2) ncl += (long)m.n[l] * nch;
+    }
+    std::vector<double> diag(nv), offc((size_t)nv * nf);
+    std::vector<int> nbr((size_t)nv * nf), par(nv), chl(std::max<long>(ncl, 1), -1);
+    for (int l = 1; l <= L; ++l) {
+        std::copy(lv[l].diag.begin(), lv[l].diag.end(), diag.begin() + m.vo[l]);
+        std::copy(lv[l].off.begin(), lv[l].off.end(), offc.begin() + m.fo[l]);
+        std::copy(lv[l].nbr.begin(), lv[l].nbr.end(), nbr.begin() + m.fo[l]);
+        std::copy(lv[l].parent.begin(), lv[l].parent.end(), par.begin() + m.vo[l]);
+        if (l >= 2) std::copy(lv[l].child.begin(), lv[l].child.end(), chl.begin() + m.co[l]);
+    }
+    if ((rc = c->mg_diag.ensure(nv)) || (rc = c->mg_offc.ensure((size_t)nv * nf)) ||
+        (rc = c->mg_nbr.ensure((size_t)nv * nf)) || (rc = c->mg_parent.ensure(nv)) ||
+        (rc = c->mg_child.ensure(chl.size())) || (rc = c->mg_b.ensure(nv)) || (rc = c->mg_x.ensure(nv)) ||
+        (rc = c->mg_y.ensure(nv)) || (rc = c->mg_ainv.ensure(Ainv.size())) ||
+        (rc = c->cz0.ensure((size_t)nt * c->nn)))
+        return rc;
+    HIPCHK(hipMemcpy(c->mg_diag.p, diag.data(), nv * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_offc.p, offc.data(), offc.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_nbr.p, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_parent.p, par.data(), par.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_child.p, chl.data(), chl.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_ainv.p, Ainv.data(), Ainv.size() * sizeof(double), hipMemcpyHostToDevice));
+    m.diag = c->mg_diag.p;
+    m.offc = c->mg_offc.p;
+    m.nbr = c->mg_nbr.p;
+    m.parent = c->mg_parent.p;
+    m.child = c->mg_child.p;
+    m.b = c->mg_b.p;
+    m.x = c->mg_x.p;
+    m.y = c->mg_y.p;
+    m.ainv = c->mg_ainv.p;
+    m.omega = env_double("SN_MG_OMEGA", 0.7);
+    m.alpha = env_double("SN_MG_ALPHA", 1.0);
+    c->mg_omega0 = env_double("SN_MG_OMEGA0", 0.7);
+    // levels with at most 8192 unknowns run in the single-workgroup kernel
+    int lc = L;
+    while (lc > 1 && m.n[lc - 1] <= 8192) --lc;
+    c->mg_lc = lc;
+    c->mg_ready = true;
+    return 0;
+}
+
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
            sn_dsa_stats* stats) {
     const long n = ctx->nc * ctx->nn;
@@ -260,10 +467,19 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     const DsaGeom& g = ctx->dg;
     size_t e0 = 0, e1 = 0;
     int rc;
+    const int bj = o->precond == SN_PRECOND_MG ? 0 : 1;
+    if (!bj && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
+    auto vcycle = [&]() -> int {
+        HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cr.p,
+                                ctx->cz0.p, ctx->cz.p, ctx->mg, ctx->mg_lc, ctx->mg_omega0, ctx->partb.p,
+                                ctx->nparts, ctx->scal.p, ctx->stream));
+        return 0;
+    };
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_cg_init(ctx->scal.p, ctx->stream));
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
-                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, ctx->stream));
+                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->stream));
+    if (!bj && (rc = vcycle())) return rc;
     CgScalars hs{};
     int it = 0;
     // launch batches of iterations and poll the device-side stop flag; the
@@ -271,11 +487,13 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit + 1));
     while (true) {
         int nb = std::min(batch, o->cg_maxit + 1 - it);
-        for (int b = 0; b < nb; ++b)
+        for (int b = 0; b < nb; ++b) {
             HIPCHK(launch_cg_iteration(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cx.p,
                                        ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cp1.p, ctx->cq.p, ctx->parta.p,
-                                       ctx->partb.p, ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b,
+                                       ctx->partb.p, ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b, bj,
                                        ctx->stream));
+            if (!bj && it + b < o->cg_maxit && (rc = vcycle())) return rc;
+        }
         it += nb;
         HIPCHK(hipMemcpyAsync(&hs, ctx->scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -369,6 +587,16 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->rpart.release();
     ctx->res3.release();
     ctx->phioct.release();
+    ctx->mg_diag.release();
+    ctx->mg_offc.release();
+    ctx->mg_b.release();
+    ctx->mg_x.release();
+    ctx->mg_y.release();
+    ctx->mg_ainv.release();
+    ctx->cz0.release();
+    ctx->mg_nbr.release();
+    ctx->mg_parent.release();
+    ctx->mg_child.release();
     delete ctx;
 }
 
@@ -667,7 +895,8 @@ int sn_dsa_thick_correct(sn_context* ctx, const double* phi_old, const double* p
                          const sn_dsa_opts* opts, sn_dsa_stats* stats) {
     g_err.clear();
     if (!ctx || !phi_old || !phi_si || !phi_out || !opts) return fail(SN_ERR_INVALID, "NULL argument");
-    if (!(opts->cg_rtol >= 0) || opts->cg_maxit < 1 || (opts->mass_kind != 0 && opts->mass_kind != 1))
+    if (!(opts->cg_rtol >= 0) || opts->cg_maxit < 1 || (opts->mass_kind != 0 && opts->mass_kind != 1) ||
+        (opts->precond != SN_PRECOND_BLOCK_JACOBI && opts->precond != SN_PRECOND_MG))
         return fail(SN_ERR_INVALID, "bad DSA options");
     return do_dsa(ctx, phi_old, phi_si, phi_out, opts, stats);
 }
@@ -681,7 +910,8 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     if (o->phi_ckpt && o->ckpt_cap < 1) return fail(SN_ERR_INVALID, "ckpt_cap must be >= 1 with phi_ckpt");
     if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
     if (o->use_dsa && (!(o->dsa.cg_rtol >= 0) || o->dsa.cg_maxit < 1 ||
-                       (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1)))
+                       (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1) ||
+                       (o->dsa.precond != SN_PRECOND_BLOCK_JACOBI && o->dsa.precond != SN_PRECOND_MG)))
         return fail(SN_ERR_INVALID, "bad DSA options");
     const long n = ctx->nc * ctx->nn;
     int rc;

@@ -474,8 +474,10 @@ __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, int s,
     }
 }
 
-// b = coef M (phi_si - phi_old) on thick cells; x = 0, r = b, z = B^{-1} r, p = z;
-// partials: [0..nparts) r.z, [nparts..2 nparts) b.b
+// b = coef M (phi_si - phi_old) on thick cells; x = 0, r = b, p = 0; with the
+// block-Jacobi preconditioner (bj = 1) also z = B^{-1} r and the r.z partials
+// [0..nparts); the b.b partials go to [nparts..2 nparts).  With the multigrid
+// preconditioner the V-cycle produces z and the r.z partials.
 template <int NN>
 __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __restrict__ thick_cell,
                                                       const double* __restrict__ sigma_t,
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       const double* __restrict__ phi_si,
                                                       const double* __restrict__ binv, double* __restrict__ x,
                                                       double* __restrict__ r, double* __restrict__ z,
-                                                      double* __restrict__ p, double* __restrict__ part) {
+                                                      double* __restrict__ p, double* __restrict__ part, int bj) {
     __shared__ double sh[256];
     constexpr int DIM = NN == 4 ? 2 : 3;
     double rz = 0.0, bb = 0.0;
@@ -498,35 +500,38 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
         for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
 #pragma unroll
         for (int n = 0; n < NN; ++n) t[n] *= coef;
-        bj_apply<NN>(binv, s, t, zz);
+        if (bj) bj_apply<NN>(binv, s, t, zz);
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const long e = (long)s * NN + n;
             x[e] = 0.0;
             r[e] = t[n];
-            z[e] = zz[n];
             p[e] = 0.0;
-            rz = fma(t[n], zz[n], rz);
+            if (bj) {
+                z[e] = zz[n];
+                rz = fma(t[n], zz[n], rz);
+            }
             bb = fma(t[n], t[n], bb);
         }
     }
     rz = block_reduce(rz, sh);
     bb = block_reduce(bb, sh);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = rz;
+        if (bj) part[blockIdx.x] = rz;
         part[gridDim.x + blockIdx.x] = bb;
     }
 }
 
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
-                          double* x, double* r, double* z, double* p, double* part, int nparts, hipStream_t st) {
+                          double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
+                          hipStream_t st) {
     if (g.nn == 4)
         hipLaunchKernelGGL(dsa_rhs_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
-                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part);
+                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part, bj);
     else
         hipLaunchKernelGGL(dsa_rhs_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
-                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part);
+                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part, bj);
     return hipGetLastError();
 }
 
@@ -613,7 +618,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
                                                         const double* __restrict__ q,
                                                         const double* __restrict__ part_pq,
                                                         double* __restrict__ part_out, int nparts, CgScalars* s,
-                                                        int it) {
+                                                        int it, int bj) {
     if (s->done) return;
     __shared__ double sh[256];
     const double pq = reduce_parts(part_pq, nparts, sh);
@@ -635,19 +640,21 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
             x[e] = fma(alpha, p[e], x[e]);
             rv[n] = fma(-alpha, q[e], r[e]);
             r[e] = rv[n];
-        }
-        bj_apply<NN>(binv, t, rv, zv);
-#pragma unroll
-        for (int n = 0; n < NN; ++n) {
-            z[(long)t * NN + n] = zv[n];
-            rz = fma(rv[n], zv[n], rz);
             rr = fma(rv[n], rv[n], rr);
+        }
+        if (bj) {
+            bj_apply<NN>(binv, t, rv, zv);
+#pragma unroll
+            for (int n = 0; n < NN; ++n) {
+                z[(long)t * NN + n] = zv[n];
+                rz = fma(rv[n], zv[n], rz);
+            }
         }
     }
     rz = block_reduce(rz, sh);
     rr = block_reduce(rr, sh);
     if (threadIdx.x == 0) {
-        part_out[blockIdx.x] = rz;
+        if (bj) part_out[blockIdx.x] = rz;
         part_out[gridDim.x + blockIdx.x] = rr;
     }
 }
@@ -656,7 +663,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
 hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
                                const double* sigma_s, const double* binv, double* x, double* r, double* z,
                                double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
-                               CgScalars* s, double rtol, int maxit, int it, hipStream_t st) {
+                               CgScalars* s, double rtol, int maxit, int it, int bj, hipStream_t st) {
     double* p_old = (it & 1) ? p1 : p0;
     double* p_new = (it & 1) ? p0 : p1;
     if (g.nn == 4) {
@@ -664,13 +671,13 @@ hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const in
                            z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
         if (it < maxit)
             hipLaunchKernelGGL(cg_update_kernel<4>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
-                               part_a, part_b, nparts, s, it);
+                               part_a, part_b, nparts, s, it, bj);
     } else {
         hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
                            z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
         if (it < maxit)
             hipLaunchKernelGGL(cg_update_kernel<8>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
-                               part_a, part_b, nparts, s, it);
+                               part_a, part_b, nparts, s, it, bj);
     }
     return hipGetLastError();
 }
@@ -692,6 +699,273 @@ hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const do
     long n = nc * nn;
     int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
     hipLaunchKernelGGL(dsa_scatter_kernel, dim3(blocks), dim3(256), 0, st, n, nn, slot_of_cell, phi_si, x, phi_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// geometric multigrid preconditioner for D_ff
+// ---------------------------------------------------------------------------
+// Level 0 is the Q1-DG SIP system on the thick cells.  Level 1 holds one
+// unknown per thick cell (piecewise constants, prolongation P = copy of the
+// cell value to its nodes); its operator is the Galerkin product P^T D_ff P,
+// a face-neighbour stencil whose coefficients are evaluated below with the
+// same bilinear form as D_ff.  Levels 2.. aggregate 2 x 2 (x 2) cells of the
+// previous level (built on the host), the last one is solved with a dense
+// inverse.  One symmetric V-cycle: damped block-Jacobi (level 0) or Jacobi
+// (levels >= 1) once before and once after the coarse-grid correction, which
+// is scaled by alpha; with equal pre- and post-smoothers the cycle is a
+// symmetric preconditioner for CG.
+
+// level-1 coefficients: diag[s] = 1^T D_ss 1, offc[s][f] = 1^T D_{s,nbr(s,f)} 1
+template <int NN>
+__global__ void __launch_bounds__(128) mg_level1_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                        const int* __restrict__ nbr,
+                                                        const double* __restrict__ sigma_t,
+                                                        const double* __restrict__ sigma_s,
+                                                        double* __restrict__ diag, double* __restrict__ offc) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long cell = thick_cell[s];
+        double ones[NN], zeros[NN], out[NN];
+        for (int n = 0; n < NN; ++n) {
+            ones[n] = 1.0;
+            zeros[n] = 0.0;
+        }
+        sip_rows<NN>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, ones,
+                     [](int, double un[NN]) {
+                         for (int n = 0; n < NN; ++n) un[n] = 0.0;
+                     },
+                     out);
+        double d = 0.0;
+        for (int n = 0; n < NN; ++n) d += out[n];
+        diag[s] = d;
+        for (int f = 0; f < 2 * DIM; ++f) {
+            const int target = nbr[s * 2 * DIM + f];
+            double o = 0.0;
+            if (target >= 0) {
+                sip_rows<NN>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, zeros,
+                             [target](int ns, double un[NN]) {
+                                 for (int n = 0; n < NN; ++n) un[n] = ns == target ? 1.0 : 0.0;
+                             },
+                             out);
+                for (int n = 0; n < NN; ++n) o += out[n];
+            }
+            offc[s * 2 * DIM + f] = o;
+        }
+    }
+}
+
+hipError_t launch_mg_level1(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, double* diag, double* offc, hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    int blocks = std::min((g.nthick + 127) / 128, 65536);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(mg_level1_kernel<4>, dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           diag, offc);
+    else
+        hipLaunchKernelGGL(mg_level1_kernel<8>, dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           diag, offc);
+    return hipGetLastError();
+}
+
+// residual of cell c at P0 level l for the vector xv of that level
+__device__ __forceinline__ double mg_res(const MgDev& m, int l, int c, const double* __restrict__ xv) {
+    const int nf = 2 * m.dim;
+    const double* off = m.offc + m.fo[l] + (long)c * nf;
+    const int* nb = m.nbr + m.fo[l] + (long)c * nf;
+    double a = m.diag[m.vo[l] + c] * xv[c];
+    for (int f = 0; f < nf; ++f)
+        if (nb[f] >= 0) a = fma(off[f], xv[nb[f]], a);
+    return m.b[m.vo[l] + c] - a;
+}
+
+// the post-smoothed vector of level l (the coarsest level has no post-smoother)
+__device__ __forceinline__ const double* mg_post_vec(const MgDev& m, int l) {
+    return l == m.L ? m.x + m.vo[l] : m.y + m.vo[l];
+}
+
+// pre-smoothing from zero: x_l = omega b_l / diag_l
+__device__ __forceinline__ void mg_pre_at(const MgDev& m, int l, int i) {
+    m.x[m.vo[l] + i] = m.omega * m.b[m.vo[l] + i] / m.diag[m.vo[l] + i];
+}
+// restriction: b_{l+1}[S] = sum over the children c of S (fixed order) of the level-l residual
+__device__ __forceinline__ void mg_restrict_at(const MgDev& m, int l, int S) {
+    const int nch = 1 << m.dim;
+    const int* ch = m.child + m.co[l + 1] + (long)S * nch;
+    const double* xv = m.x + m.vo[l];
+    double v = 0.0;
+    for (int q = 0; q < nch; ++q)
+        if (ch[q] >= 0) v += mg_res(m, l, ch[q], xv);
+    m.b[m.vo[l + 1] + S] = v;
+}
+// post-smoothing after the prolongated correction: xp = x_l + alpha P x_{l+1},
+// y_l = xp + omega (b_l - A_l xp) / diag_l (xp evaluated on the fly)
+__device__ __forceinline__ void mg_post_at(const MgDev& m, int l, int c) {
+    const int nf = 2 * m.dim;
+    const double* xl = m.x + m.vo[l];
+    const double* xc = mg_post_vec(m, l + 1);
+    const int* par = m.parent + m.vo[l];
+    auto xp = [&](int e) { return fma(m.alpha, xc[par[e]], xl[e]); };
+    const double* off = m.offc + m.fo[l] + (long)c * nf;
+    const int* nb = m.nbr + m.fo[l] + (long)c * nf;
+    const double dg = m.diag[m.vo[l] + c];
+    const double xs = xp(c);
+    double a = dg * xs;
+    for (int f = 0; f < nf; ++f)
+        if (nb[f] >= 0) a = fma(off[f], xp(nb[f]), a);
+    m.y[m.vo[l] + c] = xs + m.omega * (m.b[m.vo[l] + c] - a) / dg;
+}
+
+__global__ void __launch_bounds__(256) mg_pre_kernel(MgDev m, int l, const CgScalars* s) {
+    if (s->done) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.n[l]; i += gridDim.x * blockDim.x) mg_pre_at(m, l, i);
+}
+__global__ void __launch_bounds__(256) mg_restrict_kernel(MgDev m, int l, const CgScalars* s) {
+    if (s->done) return;
+    for (int S = blockIdx.x * blockDim.x + threadIdx.x; S < m.n[l + 1]; S += gridDim.x * blockDim.x)
+        mg_restrict_at(m, l, S);
+}
+__global__ void __launch_bounds__(256) mg_post_kernel(MgDev m, int l, const CgScalars* s) {
+    if (s->done) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.n[l]; c += gridDim.x * blockDim.x) mg_post_at(m, l, c);
+}
+
+// levels lc .. L in one workgroup (their sizes are small): pre-smoothing and
+// restriction down, dense solve on level L, prolongation and post-smoothing up
+__global__ void __launch_bounds__(1024) mg_coarse_kernel(MgDev m, int lc, const CgScalars* s) {
+    if (s->done) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int l = lc; l < m.L; ++l) {
+        for (int i = tid; i < m.n[l]; i += nt) mg_pre_at(m, l, i);
+        __syncthreads();
+        for (int S = tid; S < m.n[l + 1]; S += nt) mg_restrict_at(m, l, S);
+        __syncthreads();
+    }
+    const int nL = m.n[m.L];
+    const double* bL = m.b + m.vo[m.L];
+    for (int i = tid; i < nL; i += nt) {
+        const double* row = m.ainv + (long)i * nL;
+        double v = 0.0;
+        for (int j = 0; j < nL; ++j) v = fma(row[j], bL[j], v);
+        m.x[m.vo[m.L] + i] = v;
+    }
+    __syncthreads();
+    for (int l = m.L - 1; l >= lc; --l) {
+        for (int c = tid; c < m.n[l]; c += nt) mg_post_at(m, l, c);
+        __syncthreads();
+    }
+}
+
+// level 0 pre-smoothing from zero: z0 = omega0 B^{-1} r
+template <int NN>
+__global__ void __launch_bounds__(256) mg_l0_pre_kernel(DsaGeom g, const double* __restrict__ binv,
+                                                        const double* __restrict__ r, double* __restrict__ z0,
+                                                        double omega0, const CgScalars* s) {
+    if (s->done) return;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double rv[NN], zv[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) rv[n] = r[(long)t * NN + n];
+        bj_apply<NN>(binv, t, rv, zv);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) z0[(long)t * NN + n] = omega0 * zv[n];
+    }
+}
+
+// level 0 residual restricted to level 1: b1[t] = sum_n (r - D_ff z0)[t, n]
+template <int NN>
+__global__ void __launch_bounds__(256) mg_l0_restrict_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                             const int* __restrict__ nbr,
+                                                             const double* __restrict__ sigma_t,
+                                                             const double* __restrict__ sigma_s,
+                                                             const double* __restrict__ r,
+                                                             const double* __restrict__ z0, MgDev m,
+                                                             const CgScalars* s) {
+    if (s->done) return;
+    auto get = [&](int slot, double out[NN]) {
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = z0[(long)slot * NN + n];
+    };
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double uK[NN], o[NN];
+        get(t, uK);
+        sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, get, o);
+        double v = 0.0;
+#pragma unroll
+        for (int n = 0; n < NN; ++n) v += r[(long)t * NN + n] - o[n];
+        m.b[m.vo[1] + t] = v;
+    }
+}
+
+// level 0 post-smoothing: zp = z0 + alpha P x1, z = zp + omega0 B^{-1} (r - D_ff zp)
+// (zp on the fly for the cell and its neighbours); partials r.z -> part[block]
+template <int NN>
+__global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                         const int* __restrict__ nbr,
+                                                         const double* __restrict__ sigma_t,
+                                                         const double* __restrict__ sigma_s,
+                                                         const double* __restrict__ binv,
+                                                         const double* __restrict__ r, const double* __restrict__ z0,
+                                                         MgDev m, double omega0, double* __restrict__ z,
+                                                         double* __restrict__ part, const CgScalars* s) {
+    if (s->done) return;
+    __shared__ double sh[256];
+    const double* x1 = mg_post_vec(m, 1);
+    auto get = [&](int slot, double out[NN]) {
+        const double c = m.alpha * x1[slot];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = z0[(long)slot * NN + n] + c;
+    };
+    double rz = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double uK[NN], o[NN], rv[NN], zv[NN];
+        get(t, uK);
+        sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, get, o);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) rv[n] = r[(long)t * NN + n] - o[n];
+        bj_apply<NN>(binv, t, rv, zv);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const double zz = fma(omega0, zv[n], uK[n]);
+            z[(long)t * NN + n] = zz;
+            rz = fma(r[(long)t * NN + n], zz, rz);
+        }
+    }
+    rz = block_reduce(rz, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = rz;
+}
+
+// One V-cycle z = M^{-1} r; levels 1 .. lc-1 run as separate grid-wide
+// kernels, levels lc .. L in the single-workgroup kernel.  part: r.z partials
+// ([0..nparts)).
+hipError_t launch_mg_vcycle(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, const double* binv, const double* r, double* z0, double* z,
+                            const MgDev& m, int lc, double omega0, double* part, int nparts, const CgScalars* s,
+                            hipStream_t st) {
+    const int gb = nparts;
+    auto blocks = [](int n) { return std::max(1, std::min((n + 255) / 256, 4096)); };
+    if (g.nn == 4) {
+        hipLaunchKernelGGL(mg_l0_pre_kernel<4>, dim3(gb), dim3(256), 0, st, g, binv, r, z0, omega0, s);
+        hipLaunchKernelGGL(mg_l0_restrict_kernel<4>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t,
+                           sigma_s, r, z0, m, s);
+    } else {
+        hipLaunchKernelGGL(mg_l0_pre_kernel<8>, dim3(gb), dim3(256), 0, st, g, binv, r, z0, omega0, s);
+        hipLaunchKernelGGL(mg_l0_restrict_kernel<8>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t,
+                           sigma_s, r, z0, m, s);
+    }
+    for (int l = 1; l < lc; ++l) {
+        hipLaunchKernelGGL(mg_pre_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+        hipLaunchKernelGGL(mg_restrict_kernel, dim3(blocks(m.n[l + 1])), dim3(256), 0, st, m, l, s);
+    }
+    hipLaunchKernelGGL(mg_coarse_kernel, dim3(1), dim3(1024), 0, st, m, lc, s);
+    for (int l = lc - 1; l >= 1; --l)
+        hipLaunchKernelGGL(mg_post_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(mg_l0_post_kernel<4>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           binv, r, z0, m, omega0, z, part, s);
+    else
+        hipLaunchKernelGGL(mg_l0_post_kernel<8>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           binv, r, z0, m, omega0, z, part, s);
     return hipGetLastError();
 }
 

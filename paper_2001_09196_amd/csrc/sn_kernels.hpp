@@ -97,15 +97,45 @@ struct CgScalars {
 
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
-                          double* x, double* r, double* z, double* p, double* part, int nparts, hipStream_t st);
+                          double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
+                          hipStream_t st);
 hipError_t launch_cg_init(CgScalars* s, hipStream_t st);
 hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
                                   hipStream_t st);
-// CG iteration `it` (it = maxit only runs the stop test); p0/p1 alternate
+// CG iteration `it` (it = maxit only runs the stop test); p0/p1 alternate.
+// bj = 1: z = B^{-1} r inside the update; bj = 0: the caller computes z and
+// the r.z partials (multigrid V-cycle) after the update.
 hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
                                const double* sigma_s, const double* binv, double* x, double* r, double* z,
                                double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
-                               CgScalars* s, double rtol, int maxit, int it, hipStream_t st);
+                               CgScalars* s, double rtol, int maxit, int it, int bj, hipStream_t st);
+
+// geometric multigrid hierarchy on the device (levels 1 .. L hold one value
+// per active cell; level 1 = the thick cells in slot order)
+constexpr int MG_MAXL = 20;
+struct MgDev {
+    int L, dim;
+    int n[MG_MAXL];        // unknowns of each level
+    long vo[MG_MAXL];      // offset of level l in diag, b, x, y, parent
+    long fo[MG_MAXL];      // offset of level l in offc, nbr (2 dim per unknown)
+    long co[MG_MAXL];      // offset of level l in child (2^dim per unknown, children at level l - 1)
+    const double* diag;    // Galerkin diagonal
+    const double* offc;    // Galerkin face couplings [unknown][face]
+    const int* nbr;        // face neighbour [unknown][face] or -1
+    const int* parent;     // unknown of level l + 1 containing it (levels < L)
+    const int* child;      // children at level l - 1 (or -1), fixed order
+    double* b;
+    double* x;
+    double* y;
+    const double* ainv;    // dense inverse of the level-L operator [n_L][n_L]
+    double omega, alpha;   // Jacobi damping (levels >= 1), coarse-correction scale
+};
+hipError_t launch_mg_level1(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, double* diag, double* offc, hipStream_t st);
+hipError_t launch_mg_vcycle(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, const double* binv, const double* r, double* z0, double* z,
+                            const MgDev& m, int lc, double omega0, double* part, int nparts, const CgScalars* s,
+                            hipStream_t st);
 hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
                               double* phi_out, hipStream_t st);
 hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,

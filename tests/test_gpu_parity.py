@@ -91,19 +91,23 @@ def test_scalar_flux(prec):
 
 @pytest.mark.parametrize("dim,shape", [(2, (16, 16, 1)), (2, (45, 70, 1)), (3, (14, 11, 9))])
 @pytest.mark.parametrize("mass_kind", [0, 1])
-def test_dsa_parity(dim, shape, mass_kind):
+@pytest.mark.parametrize("precond", [0, 1])
+def test_dsa_parity(dim, shape, mass_kind, precond):
+    """Both preconditioners (block Jacobi, geometric multigrid) reach the
+    oracle's thick-region correction."""
     from paper_2001_09196_amd import sn_dsa_thick_correct
     p = random_problem(dim, *shape, order=4, seed=7 + shape[0])
     rng = np.random.default_rng(8)
     phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
     phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
     ref, it_o, _ = oracle.dsa_correct(p, phi_old, phi_si, mass_kind=mass_kind, cg_rtol=1e-14)
-    say(f"dsa {p.name} mass_kind={mass_kind}")
+    say(f"dsa {p.name} mass_kind={mass_kind} precond={precond}")
     with context(p) as ctx:
         assert ctx.thick_count == int(np.count_nonzero(p.sigma_s >= p.eta))
         out = torch.empty((p.ncells, p.nn), dtype=torch.float64, device="cuda")
         st = sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out, cg_rtol=1e-14, cg_maxit=5000,
-                                  mass_kind=mass_kind)
+                                  mass_kind=mass_kind, precond=precond)
+        say(f"  CG iterations {st['cg_iters']}")
         got = out.cpu().numpy()
     assert st["cg_relres"] <= 1e-14
     assert rel_max(got, ref) <= 1e-11
