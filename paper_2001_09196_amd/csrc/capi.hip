@@ -15,6 +15,7 @@
 
 #include "../../include/sn.h"
 #include "sn_kernels.hpp"
+#include "mg_host.hpp"
 
 using namespace sn;
 
@@ -93,11 +94,11 @@ struct sn_context {
     int cg_hint = 8;
     // geometric multigrid hierarchy (built on first use)
     bool mg_ready = false;
-    int mg_lc = 1;
-    double mg_omega0 = 0.7;
+    int mg_lc = 1, mg_levels = 0;
+    double mg_omega0 = 0.8;
     MgDev mg{};
-    DevBuf<double> mg_diag, mg_offc, mg_b, mg_x, mg_y, mg_ainv, cz0;
-    DevBuf<int> mg_nbr, mg_parent, mg_child;
+    DevBuf<double> mg_coef, mg_pw, mg_b, mg_x, mg_y, mg_r, mg_ainv, cz0, cres;
+    DevBuf<int> mg_nbr, mg_chl, mg_par, mg_vnodes, mg_nodev;
     // sweep
     SweepGeom sg{};
     DevBuf<int> tiles, groups;
@@ -288,165 +289,128 @@ bool spd_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
     return true;
 }
 
-// Multigrid hierarchy for the thick-region operator: level-1 Galerkin
-// coefficients from the device, then 2 x 2 (x 2) aggregation of the cell
-// grid on the host (sums in a fixed order) until at most 512 unknowns
-// remain, whose operator is inverted densely.
+// Multigrid hierarchy for the thick-region operator.  Level 1: the vertices
+// of the thick cells (continuous Q1), stencil P^T D_ff P by probing on the
+// device.  Coarser levels (host, sums in a fixed order): every other vertex,
+// (bi/tri)linear interpolation, Galerkin stencils, until at most 512 unknowns
+// remain; that operator is inverted densely.
 int mg_setup(sn_context* c) {
     const DsaGeom& g = c->dg;
-    const int nt = g.nthick, dim = g.dim, nf = 2 * dim, nch = 1 << dim;
+    const int nt = g.nthick, dim = g.dim, nn = c->nn, nch = 1 << dim, ns = dim == 2 ? 9 : 27;
     int rc;
-    DevBuf<double> d1, o1;
-    if ((rc = d1.ensure(nt)) || (rc = o1.ensure((size_t)nt * nf))) return rc;
-    HIPCHK(launch_mg_level1(g, c->thick.p, c->nbr.p, c->sigt.p, c->sigs.p, d1.p, o1.p, c->stream));
-    struct Lv {
-        int nx, ny, nz;
-        std::vector<long> pos;
-        std::vector<double> diag, off;
-        std::vector<int> nbr, parent, child;
-    };
-    std::vector<Lv> lv(2);
-    Lv& l1 = lv[1];
-    l1.nx = g.nx;
-    l1.ny = g.ny;
-    l1.nz = g.nz;
-    l1.diag.resize(nt);
-    l1.off.resize((size_t)nt * nf);
-    l1.nbr.resize((size_t)nt * nf);
+    std::vector<MgLevelHost> lv(2);
+    MgLevelHost& l1 = lv[1];
+    l1.nvx = g.nx + 1;
+    l1.nvy = g.ny + 1;
+    l1.nvz = dim == 3 ? g.nz + 1 : 1;
     std::vector<int> tc(nt);
-    HIPCHK(hipMemcpyAsync(l1.diag.data(), d1.p, nt * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(l1.off.data(), o1.p, (size_t)nt * nf * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(l1.nbr.data(), c->nbr.p, (size_t)nt * nf * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(tc.data(), c->thick.p, nt * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    l1.pos.assign(tc.begin(), tc.end());
-    for (auto& v : l1.nbr) v = v >= 0 ? v : -1;
-    while (lv.back().diag.size() > 512 && (int)lv.size() < MG_MAXL) {
-        Lv cl;
-        {
-            const Lv& f = lv.back();
-            cl.nx = (f.nx + 1) / 2;
-            cl.ny = (f.ny + 1) / 2;
-            cl.nz = (f.nz + 1) / 2;
+    l1.slot.assign((size_t)l1.nvx * l1.nvy * l1.nvz, -1);
+    auto vtx = [&](int s, int q) {
+        const long cell = tc[s];
+        const int i = (int)(cell % g.nx), j = (int)((cell / g.nx) % g.ny), k = (int)(cell / ((long)g.nx * g.ny));
+        return ((long)(k + ((q >> 2) & 1)) * l1.nvy + j + ((q >> 1) & 1)) * l1.nvx + i + (q & 1);
+    };
+    for (int s = 0; s < nt; ++s)
+        for (int q = 0; q < nch; ++q) l1.slot[vtx(s, q)] = 0;
+    for (long v = 0; v < (long)l1.slot.size(); ++v)
+        if (l1.slot[v] == 0) {
+            l1.slot[v] = (int)l1.pos.size();
+            l1.pos.push_back(v);
         }
-        Lv& f = lv.back();
-        const long ncg = (long)cl.nx * cl.ny * cl.nz;
-        std::vector<int> slot(ncg, -1);
-        const int nfine = (int)f.diag.size();
-        std::vector<long> key(nfine);
-        std::vector<int> q(nfine);
-        for (int e = 0; e < nfine; ++e) {
-            const long p = f.pos[e];
-            const int i = (int)(p % f.nx), j = (int)((p / f.nx) % f.ny), k = (int)(p / ((long)f.nx * f.ny));
-            key[e] = ((long)(k / 2) * cl.ny + j / 2) * cl.nx + i / 2;
-            q[e] = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
-            slot[key[e]] = 0;
+    const int n1 = (int)l1.pos.size();
+    std::vector<int> vnodes((size_t)n1 * nch, -1), nodev((size_t)nt * nn);
+    for (int s = 0; s < nt; ++s)
+        for (int q = 0; q < nch; ++q) {
+            const int w = l1.slot[vtx(s, q)];
+            vnodes[(size_t)w * nch + q] = s * nn + q;
+            nodev[(size_t)s * nn + q] = w;
         }
-        int n = 0;
-        for (long kk = 0; kk < ncg; ++kk)
-            if (slot[kk] == 0) {
-                slot[kk] = n++;
-                cl.pos.push_back(kk);
-            }
-        f.parent.resize(nfine);
-        cl.child.assign((size_t)n * nch, -1);
-        for (int e = 0; e < nfine; ++e) {
-            f.parent[e] = slot[key[e]];
-            cl.child[(size_t)f.parent[e] * nch + q[e]] = e;
-        }
-        cl.diag.assign(n, 0.0);
-        cl.off.assign((size_t)n * nf, 0.0);
-        cl.nbr.assign((size_t)n * nf, -1);
-        const int ext[3] = {cl.nx, cl.ny, cl.nz};
-        for (int S = 0; S < n; ++S) {
-            double d = 0.0;
-            for (int qq = 0; qq < nch; ++qq) {
-                const int e = cl.child[(size_t)S * nch + qq];
-                if (e < 0) continue;
-                d += f.diag[e];
-                for (int ff = 0; ff < nf; ++ff) {
-                    const int ne = f.nbr[(size_t)e * nf + ff];
-                    if (ne < 0) continue;
-                    if (f.parent[ne] == S) d += f.off[(size_t)e * nf + ff];
-                    else cl.off[(size_t)S * nf + ff] += f.off[(size_t)e * nf + ff];
-                }
-            }
-            cl.diag[S] = d;
-            const long p = cl.pos[S];
-            const int pos[3] = {(int)(p % cl.nx), (int)((p / cl.nx) % cl.ny), (int)(p / ((long)cl.nx * cl.ny))};
-            const long stride[3] = {1, cl.nx, (long)cl.nx * cl.ny};
-            for (int ff = 0; ff < nf; ++ff) {
-                const int ax = ff >> 1, sd = ff & 1;
-                const int np = pos[ax] + (sd ? 1 : -1);
-                if (np >= 0 && np < ext[ax]) cl.nbr[(size_t)S * nf + ff] = slot[p + (sd ? stride[ax] : -stride[ax])];
-            }
-        }
-        lv.push_back(std::move(cl));
-    }
-    const int L = (int)lv.size() - 1;
-    lv[L].parent.assign(lv[L].diag.size(), -1);
-    // dense inverse of the coarsest operator
-    const int nL = (int)lv[L].diag.size();
-    std::vector<double> A((size_t)nL * nL, 0.0), Ainv;
-    for (int i = 0; i < nL; ++i) {
-        A[(size_t)i * nL + i] = lv[L].diag[i];
-        for (int ff = 0; ff < nf; ++ff) {
-            const int j = lv[L].nbr[(size_t)i * nf + ff];
-            if (j >= 0) A[(size_t)i * nL + j] += lv[L].off[(size_t)i * nf + ff];
-        }
-    }
-    if (!spd_inverse(nL, A, Ainv)) return fail(SN_ERR_CG_BREAKDOWN, "coarsest multigrid operator is not SPD");
-    // flatten
+    DevBuf<long> vpos;
+    DevBuf<double> coef1;
+    if ((rc = vpos.ensure(n1)) || (rc = coef1.ensure((size_t)n1 * ns)) || (rc = c->mg_vnodes.ensure(vnodes.size())) ||
+        (rc = c->mg_nodev.ensure(nodev.size())) || (rc = c->cz0.ensure((size_t)nt * nn)) ||
+        (rc = c->cres.ensure((size_t)nt * nn)))
+        return rc;
+    HIPCHK(hipMemcpy(vpos.p, l1.pos.data(), n1 * sizeof(long), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_vnodes.p, vnodes.data(), vnodes.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_nodev.p, nodev.data(), nodev.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(coef1.p, 0, (size_t)n1 * ns * sizeof(double)));
     MgDev& m = c->mg;
     m = MgDev{};
-    m.L = L;
     m.dim = dim;
-    long nv = 0, ncl = 0;
+    m.ns = ns;
+    m.n[1] = n1;
+    m.vnodes = c->mg_vnodes.p;
+    m.nodev = c->mg_nodev.p;
+    HIPCHK(launch_vmg_probe(g, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, m, l1.nvx, l1.nvy, vpos.p, c->cz0.p,
+                            c->cres.p, coef1.p, c->stream));
+    l1.coef.resize((size_t)n1 * ns);
+    HIPCHK(hipMemcpyAsync(l1.coef.data(), coef1.p, l1.coef.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    mg_coarsen(lv, dim, 512, MG_MAXL);
+    const int L = (int)lv.size() - 1;
+    // dense inverse of the coarsest operator
+    const int nL = (int)lv[L].pos.size();
+    std::vector<double> A((size_t)nL * nL, 0.0), Ainv;
+    for (int i = 0; i < nL; ++i)
+        for (int o = 0; o < ns; ++o) {
+            const int j = lv[L].nbr[(size_t)i * ns + o];
+            if (j >= 0) A[(size_t)i * nL + j] += lv[L].coef[(size_t)i * ns + o];
+        }
+    if (!spd_inverse(nL, A, Ainv)) return fail(SN_ERR_CG_BREAKDOWN, "coarsest multigrid operator is not SPD");
+    // flatten
+    m.L = L;
+    long nv = 0, np = 0;
     for (int l = 1; l <= L; ++l) {
-        m.n[l] = (int)lv[l].diag.size();
+        m.n[l] = (int)lv[l].pos.size();
         m.vo[l] = nv;
-        m.fo[l] = nv * nf;
-        m.co[l] = ncl;
+        m.so[l] = nv * ns;
+        m.po[l] = np;
         nv += m.n[l];
-        if (l >= 2) ncl += (long)m.n[l] * nch;
+        if (l < L) np += (long)m.n[l] * nch;
     }
-    std::vector<double> diag(nv), offc((size_t)nv * nf);
-    std::vector<int> nbr((size_t)nv * nf), par(nv), chl(std::max<long>(ncl, 1), -1);
+    std::vector<double> coef((size_t)nv * ns), pw(std::max<long>(np, 1), 0.0);
+    std::vector<int> nbr((size_t)nv * ns), chl((size_t)nv * ns, -1), par(std::max<long>(np, 1), -1);
     for (int l = 1; l <= L; ++l) {
-        std::copy(lv[l].diag.begin(), lv[l].diag.end(), diag.begin() + m.vo[l]);
-        std::copy(lv[l].off.begin(), lv[l].off.end(), offc.begin() + m.fo[l]);
-        std::copy(lv[l].nbr.begin(), lv[l].nbr.end(), nbr.begin() + m.fo[l]);
-        std::copy(lv[l].parent.begin(), lv[l].parent.end(), par.begin() + m.vo[l]);
-        if (l >= 2) std::copy(lv[l].child.begin(), lv[l].child.end(), chl.begin() + m.co[l]);
+        std::copy(lv[l].coef.begin(), lv[l].coef.end(), coef.begin() + m.so[l]);
+        std::copy(lv[l].nbr.begin(), lv[l].nbr.end(), nbr.begin() + m.so[l]);
+        if (l >= 2) std::copy(lv[l].chl.begin(), lv[l].chl.end(), chl.begin() + m.so[l]);
+        if (l < L) {
+            std::copy(lv[l].par.begin(), lv[l].par.end(), par.begin() + m.po[l]);
+            std::copy(lv[l].pw.begin(), lv[l].pw.end(), pw.begin() + m.po[l]);
+        }
     }
-    if ((rc = c->mg_diag.ensure(nv)) || (rc = c->mg_offc.ensure((size_t)nv * nf)) ||
-        (rc = c->mg_nbr.ensure((size_t)nv * nf)) || (rc = c->mg_parent.ensure(nv)) ||
-        (rc = c->mg_child.ensure(chl.size())) || (rc = c->mg_b.ensure(nv)) || (rc = c->mg_x.ensure(nv)) ||
-        (rc = c->mg_y.ensure(nv)) || (rc = c->mg_ainv.ensure(Ainv.size())) ||
-        (rc = c->cz0.ensure((size_t)nt * c->nn)))
+    if ((rc = c->mg_coef.ensure(coef.size())) || (rc = c->mg_nbr.ensure(nbr.size())) ||
+        (rc = c->mg_chl.ensure(chl.size())) || (rc = c->mg_par.ensure(par.size())) ||
+        (rc = c->mg_pw.ensure(pw.size())) || (rc = c->mg_b.ensure(nv)) || (rc = c->mg_x.ensure(nv)) ||
+        (rc = c->mg_y.ensure(nv)) || (rc = c->mg_r.ensure(nv)) || (rc = c->mg_ainv.ensure(Ainv.size())))
         return rc;
-    HIPCHK(hipMemcpy(c->mg_diag.p, diag.data(), nv * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->mg_offc.p, offc.data(), offc.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_coef.p, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->mg_nbr.p, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->mg_parent.p, par.data(), par.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->mg_child.p, chl.data(), chl.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_chl.p, chl.data(), chl.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_par.p, par.data(), par.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->mg_pw.p, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->mg_ainv.p, Ainv.data(), Ainv.size() * sizeof(double), hipMemcpyHostToDevice));
-    m.diag = c->mg_diag.p;
-    m.offc = c->mg_offc.p;
+    m.coef = c->mg_coef.p;
     m.nbr = c->mg_nbr.p;
-    m.parent = c->mg_parent.p;
-    m.child = c->mg_child.p;
+    m.chl = c->mg_chl.p;
+    m.par = c->mg_par.p;
+    m.pw = c->mg_pw.p;
     m.b = c->mg_b.p;
     m.x = c->mg_x.p;
     m.y = c->mg_y.p;
+    m.r = c->mg_r.p;
     m.ainv = c->mg_ainv.p;
     m.omega = env_double("SN_MG_OMEGA", 0.7);
-    m.alpha = env_double("SN_MG_ALPHA", 1.0);
-    c->mg_omega0 = env_double("SN_MG_OMEGA0", 0.7);
+    c->mg_omega0 = env_double("SN_MG_OMEGA0", 0.8);
     // levels with at most 8192 unknowns run in the single-workgroup kernel
     int lc = L;
     while (lc > 1 && m.n[lc - 1] <= 8192) --lc;
     c->mg_lc = lc;
+    c->mg_levels = L;
     c->mg_ready = true;
     return 0;
 }
@@ -471,8 +435,8 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     if (!bj && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
     auto vcycle = [&]() -> int {
         HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cr.p,
-                                ctx->cz0.p, ctx->cz.p, ctx->mg, ctx->mg_lc, ctx->mg_omega0, ctx->partb.p,
-                                ctx->nparts, ctx->scal.p, ctx->stream));
+                                ctx->cz0.p, ctx->cres.p, ctx->cz.p, ctx->mg, ctx->mg_lc, ctx->mg_omega0,
+                                ctx->partb.p, ctx->nparts, ctx->scal.p, ctx->stream));
         return 0;
     };
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
@@ -587,16 +551,20 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->rpart.release();
     ctx->res3.release();
     ctx->phioct.release();
-    ctx->mg_diag.release();
-    ctx->mg_offc.release();
+    ctx->mg_coef.release();
+    ctx->mg_pw.release();
     ctx->mg_b.release();
     ctx->mg_x.release();
     ctx->mg_y.release();
+    ctx->mg_r.release();
     ctx->mg_ainv.release();
     ctx->cz0.release();
+    ctx->cres.release();
     ctx->mg_nbr.release();
-    ctx->mg_parent.release();
-    ctx->mg_child.release();
+    ctx->mg_chl.release();
+    ctx->mg_par.release();
+    ctx->mg_vnodes.release();
+    ctx->mg_nodev.release();
     delete ctx;
 }
 

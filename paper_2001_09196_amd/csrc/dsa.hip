@@ -705,140 +705,157 @@ hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const do
 // ---------------------------------------------------------------------------
 // geometric multigrid preconditioner for D_ff
 // ---------------------------------------------------------------------------
-// Level 0 is the Q1-DG SIP system on the thick cells.  Level 1 holds one
-// unknown per thick cell (piecewise constants, prolongation P = copy of the
-// cell value to its nodes); its operator is the Galerkin product P^T D_ff P,
-// a face-neighbour stencil whose coefficients are evaluated below with the
-// same bilinear form as D_ff.  Levels 2.. aggregate 2 x 2 (x 2) cells of the
-// previous level (built on the host), the last one is solved with a dense
-// inverse.  One symmetric V-cycle: damped block-Jacobi (level 0) or Jacobi
-// (levels >= 1) once before and once after the coarse-grid correction, which
-// is scaled by alpha; with equal pre- and post-smoothers the cycle is a
-// symmetric preconditioner for CG.
+// Level 0 is the Q1-DG SIP system on the thick cells.  In thick cells the
+// face penalty (kappa_0 ~ 1/4) is far larger than D/h, so the low-energy
+// functions of D_ff are continuous: level 1 is the continuous Q1 space on the
+// vertices of the thick cells (prolongation = the vertex value copied to the
+// DG nodes at that vertex), and its operator is the Galerkin product
+// P^T D_ff P, a 3^dim-point vertex stencil, evaluated by applying D_ff to
+// colourings of the vertices (mod 3 per axis).  Levels 2.. coarsen the vertex
+// grid by two with (bi/tri)linear interpolation and Galerkin operators (built
+// on the host); the last level is solved with a dense inverse.  One
+// symmetric V-cycle: damped block Jacobi on level 0 and damped Jacobi on the
+// vertex levels, once before and once after the coarse-grid correction.
 
-// level-1 coefficients: diag[s] = 1^T D_ss 1, offc[s][f] = 1^T D_{s,nbr(s,f)} 1
+// colour of a vertex: (i mod 3) + 3 (j mod 3) + 9 (k mod 3)
+__device__ __forceinline__ int vtx_colour(int i, int j, int k) { return i % 3 + 3 * (j % 3) + 9 * (k % 3); }
+
+// x0 = P (indicator of the vertices of colour col) on the DG nodes
 template <int NN>
-__global__ void __launch_bounds__(128) mg_level1_kernel(DsaGeom g, const int* __restrict__ thick_cell,
-                                                        const int* __restrict__ nbr,
-                                                        const double* __restrict__ sigma_t,
-                                                        const double* __restrict__ sigma_s,
-                                                        double* __restrict__ diag, double* __restrict__ offc) {
-    constexpr int DIM = NN == 4 ? 2 : 3;
+__global__ void vmg_probe_fill_kernel(DsaGeom g, const int* __restrict__ thick_cell, int col,
+                                      double* __restrict__ x0) {
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
         const long cell = thick_cell[s];
-        double ones[NN], zeros[NN], out[NN];
-        for (int n = 0; n < NN; ++n) {
-            ones[n] = 1.0;
-            zeros[n] = 0.0;
-        }
-        sip_rows<NN>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, ones,
-                     [](int, double un[NN]) {
-                         for (int n = 0; n < NN; ++n) un[n] = 0.0;
-                     },
-                     out);
-        double d = 0.0;
-        for (int n = 0; n < NN; ++n) d += out[n];
-        diag[s] = d;
-        for (int f = 0; f < 2 * DIM; ++f) {
-            const int target = nbr[s * 2 * DIM + f];
-            double o = 0.0;
-            if (target >= 0) {
-                sip_rows<NN>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, zeros,
-                             [target](int ns, double un[NN]) {
-                                 for (int n = 0; n < NN; ++n) un[n] = ns == target ? 1.0 : 0.0;
-                             },
-                             out);
-                for (int n = 0; n < NN; ++n) o += out[n];
-            }
-            offc[s * 2 * DIM + f] = o;
-        }
+        const int i = (int)(cell % g.nx), j = (int)((cell / g.nx) % g.ny), k = (int)(cell / ((long)g.nx * g.ny));
+        for (int n = 0; n < NN; ++n)
+            x0[(long)s * NN + n] = vtx_colour(i + (n & 1), j + ((n >> 1) & 1), k + ((n >> 2) & 1)) == col ? 1.0 : 0.0;
     }
 }
 
-hipError_t launch_mg_level1(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                            const double* sigma_s, double* diag, double* offc, hipStream_t st) {
+// coef1[w][o] = (P^T D_ff P)(w, w + o) for the neighbour w + o of colour col:
+// the sum of y0 = D_ff x0 over the DG nodes at vertex w
+__global__ void vmg_probe_gather_kernel(MgDev m, int nvx, int nvy, const long* __restrict__ vpos, int col,
+                                        const double* __restrict__ y0, double* __restrict__ coef) {
+    const int nch = 1 << m.dim;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < m.n[1]; w += gridDim.x * blockDim.x) {
+        const long p = vpos[w];
+        const int c[3] = {(int)(p % nvx), (int)((p / nvx) % nvy), (int)(p / ((long)nvx * nvy))};
+        const int cc[3] = {col % 3, (col / 3) % 3, col / 9};
+        int idx = 0, mul = 1;
+        for (int d = 0; d < m.dim; ++d) {
+            const int delta = (cc[d] - c[d] % 3 + 3) % 3;   // 0 -> 0, 1 -> +1, 2 -> -1
+            const int o = delta == 2 ? -1 : delta;
+            idx += (o + 1) * mul;
+            mul *= 3;
+        }
+        double v = 0.0;
+        for (int q = 0; q < nch; ++q) {
+            const int e = m.vnodes[(long)w * nch + q];
+            if (e >= 0) v += y0[e];
+        }
+        coef[(long)w * m.ns + idx] = v;
+    }
+}
+
+hipError_t launch_vmg_probe(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                            const double* sigma_t, const double* sigma_s, const MgDev& m, int nvx, int nvy,
+                            const long* vpos, double* x0, double* y0, double* coef, hipStream_t st) {
     if (g.nthick == 0) return hipSuccess;
-    int blocks = std::min((g.nthick + 127) / 128, 65536);
-    if (g.nn == 4)
-        hipLaunchKernelGGL(mg_level1_kernel<4>, dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
-                           diag, offc);
-    else
-        hipLaunchKernelGGL(mg_level1_kernel<8>, dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
-                           diag, offc);
+    const int ncol = g.dim == 2 ? 9 : 27;
+    const int bt = std::min((g.nthick + 255) / 256, 65536), bv = std::min((m.n[1] + 255) / 256, 65536);
+    for (int col = 0; col < ncol; ++col) {
+        if (g.nn == 4)
+            hipLaunchKernelGGL(vmg_probe_fill_kernel<4>, dim3(bt), dim3(256), 0, st, g, thick_cell, col, x0);
+        else
+            hipLaunchKernelGGL(vmg_probe_fill_kernel<8>, dim3(bt), dim3(256), 0, st, g, thick_cell, col, x0);
+        hipError_t e = launch_sip_apply(g, thick_cell, slot_of_cell, sigma_t, sigma_s, x0, y0, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(vmg_probe_gather_kernel, dim3(bv), dim3(256), 0, st, m, nvx, nvy, vpos, col, y0, coef);
+    }
     return hipGetLastError();
 }
 
-// residual of cell c at P0 level l for the vector xv of that level
-__device__ __forceinline__ double mg_res(const MgDev& m, int l, int c, const double* __restrict__ xv) {
-    const int nf = 2 * m.dim;
-    const double* off = m.offc + m.fo[l] + (long)c * nf;
-    const int* nb = m.nbr + m.fo[l] + (long)c * nf;
-    double a = m.diag[m.vo[l] + c] * xv[c];
-    for (int f = 0; f < nf; ++f)
-        if (nb[f] >= 0) a = fma(off[f], xv[nb[f]], a);
-    return m.b[m.vo[l] + c] - a;
+// (A_l v)[f] for vertex level l
+__device__ __forceinline__ double vmg_apply_at(const MgDev& m, int l, int f, const double* __restrict__ v) {
+    const double* c = m.coef + m.so[l] + (long)f * m.ns;
+    const int* nb = m.nbr + m.so[l] + (long)f * m.ns;
+    double a = 0.0;
+    for (int o = 0; o < m.ns; ++o) {
+        const int g = nb[o];
+        if (g >= 0) a = fma(c[o], v[g], a);
+    }
+    return a;
 }
-
-// the post-smoothed vector of level l (the coarsest level has no post-smoother)
-__device__ __forceinline__ const double* mg_post_vec(const MgDev& m, int l) {
+__device__ __forceinline__ double vmg_diag(const MgDev& m, int l, int f) {
+    return m.coef[m.so[l] + (long)f * m.ns + m.ns / 2];
+}
+// the post-smoothed vector of level l (the coarsest level has no smoother)
+__device__ __forceinline__ const double* vmg_post_vec(const MgDev& m, int l) {
     return l == m.L ? m.x + m.vo[l] : m.y + m.vo[l];
 }
-
-// pre-smoothing from zero: x_l = omega b_l / diag_l
-__device__ __forceinline__ void mg_pre_at(const MgDev& m, int l, int i) {
-    m.x[m.vo[l] + i] = m.omega * m.b[m.vo[l] + i] / m.diag[m.vo[l] + i];
+__device__ __forceinline__ void vmg_pre_at(const MgDev& m, int l, int f) {
+    m.x[m.vo[l] + f] = m.omega * m.b[m.vo[l] + f] / vmg_diag(m, l, f);
 }
-// restriction: b_{l+1}[S] = sum over the children c of S (fixed order) of the level-l residual
-__device__ __forceinline__ void mg_restrict_at(const MgDev& m, int l, int S) {
-    const int nch = 1 << m.dim;
-    const int* ch = m.child + m.co[l + 1] + (long)S * nch;
-    const double* xv = m.x + m.vo[l];
+__device__ __forceinline__ void vmg_res_at(const MgDev& m, int l, int f) {
+    m.r[m.vo[l] + f] = m.b[m.vo[l] + f] - vmg_apply_at(m, l, f, m.x + m.vo[l]);
+}
+// full-weighting restriction (transpose of the interpolation): children of C
+// at 2C + o with weight prod_d (o_d == 0 ? 1 : 1/2)
+__device__ __forceinline__ void vmg_restrict_at(const MgDev& m, int l, int C) {
+    const int* ch = m.chl + m.so[l + 1] + (long)C * m.ns;
+    const double* rl = m.r + m.vo[l];
     double v = 0.0;
+    for (int o = 0; o < m.ns; ++o) {
+        const int f = ch[o];
+        if (f < 0) continue;
+        double w = 1.0;
+        int t = o;
+        for (int d = 0; d < m.dim; ++d) {
+            if (t % 3 != 1) w *= 0.5;
+            t /= 3;
+        }
+        v = fma(w, rl[f], v);
+    }
+    m.b[m.vo[l + 1] + C] = v;
+}
+// x_l += P x_{l+1}
+__device__ __forceinline__ void vmg_prolong_at(const MgDev& m, int l, int f) {
+    const int nch = 1 << m.dim;
+    const double* xc = vmg_post_vec(m, l + 1);
+    const int* pa = m.par + m.po[l] + (long)f * nch;
+    const double* pw = m.pw + m.po[l] + (long)f * nch;
+    double v = m.x[m.vo[l] + f];
     for (int q = 0; q < nch; ++q)
-        if (ch[q] >= 0) v += mg_res(m, l, ch[q], xv);
-    m.b[m.vo[l + 1] + S] = v;
+        if (pa[q] >= 0) v = fma(pw[q], xc[pa[q]], v);
+    m.x[m.vo[l] + f] = v;
 }
-// post-smoothing after the prolongated correction: xp = x_l + alpha P x_{l+1},
-// y_l = xp + omega (b_l - A_l xp) / diag_l (xp evaluated on the fly)
-__device__ __forceinline__ void mg_post_at(const MgDev& m, int l, int c) {
-    const int nf = 2 * m.dim;
+__device__ __forceinline__ void vmg_post_at(const MgDev& m, int l, int f) {
     const double* xl = m.x + m.vo[l];
-    const double* xc = mg_post_vec(m, l + 1);
-    const int* par = m.parent + m.vo[l];
-    auto xp = [&](int e) { return fma(m.alpha, xc[par[e]], xl[e]); };
-    const double* off = m.offc + m.fo[l] + (long)c * nf;
-    const int* nb = m.nbr + m.fo[l] + (long)c * nf;
-    const double dg = m.diag[m.vo[l] + c];
-    const double xs = xp(c);
-    double a = dg * xs;
-    for (int f = 0; f < nf; ++f)
-        if (nb[f] >= 0) a = fma(off[f], xp(nb[f]), a);
-    m.y[m.vo[l] + c] = xs + m.omega * (m.b[m.vo[l] + c] - a) / dg;
+    m.y[m.vo[l] + f] = xl[f] + m.omega * (m.b[m.vo[l] + f] - vmg_apply_at(m, l, f, xl)) / vmg_diag(m, l, f);
 }
 
-__global__ void __launch_bounds__(256) mg_pre_kernel(MgDev m, int l, const CgScalars* s) {
-    if (s->done) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m.n[l]; i += gridDim.x * blockDim.x) mg_pre_at(m, l, i);
-}
-__global__ void __launch_bounds__(256) mg_restrict_kernel(MgDev m, int l, const CgScalars* s) {
-    if (s->done) return;
-    for (int S = blockIdx.x * blockDim.x + threadIdx.x; S < m.n[l + 1]; S += gridDim.x * blockDim.x)
-        mg_restrict_at(m, l, S);
-}
-__global__ void __launch_bounds__(256) mg_post_kernel(MgDev m, int l, const CgScalars* s) {
-    if (s->done) return;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.n[l]; c += gridDim.x * blockDim.x) mg_post_at(m, l, c);
-}
+#define VMG_GRID_KERNEL(NAME, N, BODY)                                                                 \
+    __global__ void __launch_bounds__(256) NAME(MgDev m, int l, const CgScalars* s) {                  \
+        if (s->done) return;                                                                           \
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (N); i += gridDim.x * blockDim.x) BODY; \
+    }
+VMG_GRID_KERNEL(vmg_pre_kernel, m.n[l], vmg_pre_at(m, l, i))
+VMG_GRID_KERNEL(vmg_res_kernel, m.n[l], vmg_res_at(m, l, i))
+VMG_GRID_KERNEL(vmg_restrict_kernel, m.n[l + 1], vmg_restrict_at(m, l, i))
+VMG_GRID_KERNEL(vmg_prolong_kernel, m.n[l], vmg_prolong_at(m, l, i))
+VMG_GRID_KERNEL(vmg_post_kernel, m.n[l], vmg_post_at(m, l, i))
+#undef VMG_GRID_KERNEL
 
-// levels lc .. L in one workgroup (their sizes are small): pre-smoothing and
-// restriction down, dense solve on level L, prolongation and post-smoothing up
-__global__ void __launch_bounds__(1024) mg_coarse_kernel(MgDev m, int lc, const CgScalars* s) {
+// levels lc .. L in one workgroup (their sizes are small)
+__global__ void __launch_bounds__(1024) vmg_coarse_kernel(MgDev m, int lc, const CgScalars* s) {
     if (s->done) return;
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int l = lc; l < m.L; ++l) {
-        for (int i = tid; i < m.n[l]; i += nt) mg_pre_at(m, l, i);
+        for (int i = tid; i < m.n[l]; i += nt) vmg_pre_at(m, l, i);
         __syncthreads();
-        for (int S = tid; S < m.n[l + 1]; S += nt) mg_restrict_at(m, l, S);
+        for (int i = tid; i < m.n[l]; i += nt) vmg_res_at(m, l, i);
+        __syncthreads();
+        for (int i = tid; i < m.n[l + 1]; i += nt) vmg_restrict_at(m, l, i);
         __syncthreads();
     }
     const int nL = m.n[m.L];
@@ -851,7 +868,9 @@ __global__ void __launch_bounds__(1024) mg_coarse_kernel(MgDev m, int lc, const 
     }
     __syncthreads();
     for (int l = m.L - 1; l >= lc; --l) {
-        for (int c = tid; c < m.n[l]; c += nt) mg_post_at(m, l, c);
+        for (int i = tid; i < m.n[l]; i += nt) vmg_prolong_at(m, l, i);
+        __syncthreads();
+        for (int i = tid; i < m.n[l]; i += nt) vmg_post_at(m, l, i);
         __syncthreads();
     }
 }
@@ -872,15 +891,15 @@ __global__ void __launch_bounds__(256) mg_l0_pre_kernel(DsaGeom g, const double*
     }
 }
 
-// level 0 residual restricted to level 1: b1[t] = sum_n (r - D_ff z0)[t, n]
+// level 0 residual res0 = r - D_ff z0
 template <int NN>
-__global__ void __launch_bounds__(256) mg_l0_restrict_kernel(DsaGeom g, const int* __restrict__ thick_cell,
-                                                             const int* __restrict__ nbr,
-                                                             const double* __restrict__ sigma_t,
-                                                             const double* __restrict__ sigma_s,
-                                                             const double* __restrict__ r,
-                                                             const double* __restrict__ z0, MgDev m,
-                                                             const CgScalars* s) {
+__global__ void __launch_bounds__(256) mg_l0_res_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                        const int* __restrict__ nbr,
+                                                        const double* __restrict__ sigma_t,
+                                                        const double* __restrict__ sigma_s,
+                                                        const double* __restrict__ r,
+                                                        const double* __restrict__ z0, double* __restrict__ res0,
+                                                        const CgScalars* s) {
     if (s->done) return;
     auto get = [&](int slot, double out[NN]) {
 #pragma unroll
@@ -890,14 +909,27 @@ __global__ void __launch_bounds__(256) mg_l0_restrict_kernel(DsaGeom g, const in
         double uK[NN], o[NN];
         get(t, uK);
         sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, get, o);
-        double v = 0.0;
 #pragma unroll
-        for (int n = 0; n < NN; ++n) v += r[(long)t * NN + n] - o[n];
-        m.b[m.vo[1] + t] = v;
+        for (int n = 0; n < NN; ++n) res0[(long)t * NN + n] = r[(long)t * NN + n] - o[n];
     }
 }
 
-// level 0 post-smoothing: zp = z0 + alpha P x1, z = zp + omega0 B^{-1} (r - D_ff zp)
+// b1[w] = sum of res0 over the DG nodes at vertex w (fixed order)
+__global__ void __launch_bounds__(256) mg_restrict1_kernel(MgDev m, const double* __restrict__ res0,
+                                                           const CgScalars* s) {
+    if (s->done) return;
+    const int nch = 1 << m.dim;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < m.n[1]; w += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int q = 0; q < nch; ++q) {
+            const int e = m.vnodes[(long)w * nch + q];
+            if (e >= 0) v += res0[e];
+        }
+        m.b[m.vo[1] + w] = v;
+    }
+}
+
+// level 0 post-smoothing: zp = z0 + P x1, z = zp + omega0 B^{-1} (r - D_ff zp)
 // (zp on the fly for the cell and its neighbours); partials r.z -> part[block]
 template <int NN>
 __global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* __restrict__ thick_cell,
@@ -910,11 +942,10 @@ __global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* _
                                                          double* __restrict__ part, const CgScalars* s) {
     if (s->done) return;
     __shared__ double sh[256];
-    const double* x1 = mg_post_vec(m, 1);
+    const double* x1 = vmg_post_vec(m, 1);
     auto get = [&](int slot, double out[NN]) {
-        const double c = m.alpha * x1[slot];
 #pragma unroll
-        for (int n = 0; n < NN; ++n) out[n] = z0[(long)slot * NN + n] + c;
+        for (int n = 0; n < NN; ++n) out[n] = z0[(long)slot * NN + n] + x1[m.nodev[(long)slot * NN + n]];
     };
     double rz = 0.0;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
@@ -935,31 +966,35 @@ __global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* _
     if (threadIdx.x == 0) part[blockIdx.x] = rz;
 }
 
-// One V-cycle z = M^{-1} r; levels 1 .. lc-1 run as separate grid-wide
-// kernels, levels lc .. L in the single-workgroup kernel.  part: r.z partials
-// ([0..nparts)).
+// One V-cycle z = M^{-1} r; vertex levels 1 .. lc-1 run as grid-wide kernels,
+// levels lc .. L in the single-workgroup kernel.  res0: DG scratch.
+// part: r.z partials ([0..nparts)).
 hipError_t launch_mg_vcycle(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                            const double* sigma_s, const double* binv, const double* r, double* z0, double* z,
-                            const MgDev& m, int lc, double omega0, double* part, int nparts, const CgScalars* s,
-                            hipStream_t st) {
+                            const double* sigma_s, const double* binv, const double* r, double* z0, double* res0,
+                            double* z, const MgDev& m, int lc, double omega0, double* part, int nparts,
+                            const CgScalars* s, hipStream_t st) {
     const int gb = nparts;
     auto blocks = [](int n) { return std::max(1, std::min((n + 255) / 256, 4096)); };
     if (g.nn == 4) {
         hipLaunchKernelGGL(mg_l0_pre_kernel<4>, dim3(gb), dim3(256), 0, st, g, binv, r, z0, omega0, s);
-        hipLaunchKernelGGL(mg_l0_restrict_kernel<4>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t,
-                           sigma_s, r, z0, m, s);
+        hipLaunchKernelGGL(mg_l0_res_kernel<4>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           r, z0, res0, s);
     } else {
         hipLaunchKernelGGL(mg_l0_pre_kernel<8>, dim3(gb), dim3(256), 0, st, g, binv, r, z0, omega0, s);
-        hipLaunchKernelGGL(mg_l0_restrict_kernel<8>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t,
-                           sigma_s, r, z0, m, s);
+        hipLaunchKernelGGL(mg_l0_res_kernel<8>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           r, z0, res0, s);
     }
+    hipLaunchKernelGGL(mg_restrict1_kernel, dim3(blocks(m.n[1])), dim3(256), 0, st, m, res0, s);
     for (int l = 1; l < lc; ++l) {
-        hipLaunchKernelGGL(mg_pre_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
-        hipLaunchKernelGGL(mg_restrict_kernel, dim3(blocks(m.n[l + 1])), dim3(256), 0, st, m, l, s);
+        hipLaunchKernelGGL(vmg_pre_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+        hipLaunchKernelGGL(vmg_res_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+        hipLaunchKernelGGL(vmg_restrict_kernel, dim3(blocks(m.n[l + 1])), dim3(256), 0, st, m, l, s);
     }
-    hipLaunchKernelGGL(mg_coarse_kernel, dim3(1), dim3(1024), 0, st, m, lc, s);
-    for (int l = lc - 1; l >= 1; --l)
-        hipLaunchKernelGGL(mg_post_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+    hipLaunchKernelGGL(vmg_coarse_kernel, dim3(1), dim3(1024), 0, st, m, lc, s);
+    for (int l = lc - 1; l >= 1; --l) {
+        hipLaunchKernelGGL(vmg_prolong_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+        hipLaunchKernelGGL(vmg_post_kernel, dim3(blocks(m.n[l])), dim3(256), 0, st, m, l, s);
+    }
     if (g.nn == 4)
         hipLaunchKernelGGL(mg_l0_post_kernel<4>, dim3(gb), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
                            binv, r, z0, m, omega0, z, part, s);

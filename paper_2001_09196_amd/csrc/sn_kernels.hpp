@@ -110,36 +110,44 @@ hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const in
                                double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
                                CgScalars* s, double rtol, int maxit, int it, int bj, hipStream_t st);
 
-// geometric multigrid hierarchy on the device (levels 1 .. L hold one value
-// per active cell; level 1 = the thick cells in slot order)
-constexpr int MG_MAXL = 20;
-struct MgDev {
-    int L, dim;
-    int n[MG_MAXL];        // unknowns of each level
-    long vo[MG_MAXL];      // offset of level l in diag, b, x, y, parent
-    long fo[MG_MAXL];      // offset of level l in offc, nbr (2 dim per unknown)
-    long co[MG_MAXL];      // offset of level l in child (2^dim per unknown, children at level l - 1)
-    const double* diag;    // Galerkin diagonal
-    const double* offc;    // Galerkin face couplings [unknown][face]
-    const int* nbr;        // face neighbour [unknown][face] or -1
-    const int* parent;     // unknown of level l + 1 containing it (levels < L)
-    const int* child;      // children at level l - 1 (or -1), fixed order
-    double* b;
-    double* x;
-    double* y;
-    const double* ainv;    // dense inverse of the level-L operator [n_L][n_L]
-    double omega, alpha;   // Jacobi damping (levels >= 1), coarse-correction scale
-};
-hipError_t launch_mg_level1(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                            const double* sigma_s, double* diag, double* offc, hipStream_t st);
-hipError_t launch_mg_vcycle(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                            const double* sigma_s, const double* binv, const double* r, double* z0, double* z,
-                            const MgDev& m, int lc, double omega0, double* part, int nparts, const CgScalars* s,
-                            hipStream_t st);
 hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
                               double* phi_out, hipStream_t st);
 hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
                             const double* sigma_t, const double* sigma_s, const double* u, double* y,
                             hipStream_t st);
+
+// geometric multigrid hierarchy on the device: level 0 is the DG system;
+// vertex levels 1 .. L hold one value per active vertex (level 1 = the
+// vertices of the thick cells in increasing vertex order) with a 3^dim-point
+// stencil (offset index o = sum_d (o_d + 1) 3^d)
+constexpr int MG_MAXL = 20;
+struct MgDev {
+    int L, dim, ns;        // coarsest level, dimension, stencil size 3^dim
+    int n[MG_MAXL];        // unknowns of each level
+    long vo[MG_MAXL];      // offset of level l in the per-unknown arrays (b, x, y, r)
+    long so[MG_MAXL];      // offset of level l in coef, nbr, chl (ns per unknown)
+    long po[MG_MAXL];      // offset of level l in par, pw (2^dim per unknown; levels < L)
+    const double* coef;    // stencil coefficients [unknown][ns]
+    const int* nbr;        // stencil neighbours [unknown][ns] or -1
+    const int* chl;        // level l >= 2: fine unknowns at 2C + o of level l - 1, [unknown][ns] or -1
+    const int* par;        // coarse parents (level l + 1) of each unknown [unknown][2^dim] or -1
+    const double* pw;      // interpolation weights of the parents
+    const int* vnodes;     // level 1: DG indices (slot * nn + node) at each vertex [n1][2^dim] or -1
+    const int* nodev;      // level-1 vertex of each DG node [nthick * nn]
+    double* b;
+    double* x;
+    double* y;
+    double* r;
+    const double* ainv;    // dense inverse of the level-L operator [n_L][n_L]
+    double omega;          // Jacobi damping on the vertex levels
+};
+// level-1 stencil by probing: coef[w][o] of P^T D_ff P (x0, y0: DG scratch)
+hipError_t launch_vmg_probe(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
+                            const double* sigma_t, const double* sigma_s, const MgDev& m, int nvx, int nvy,
+                            const long* vpos, double* x0, double* y0, double* coef, hipStream_t st);
+hipError_t launch_mg_vcycle(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, const double* binv, const double* r, double* z0, double* res0,
+                            double* z, const MgDev& m, int lc, double omega0, double* part, int nparts,
+                            const CgScalars* s, hipStream_t st);
 
 }  // namespace sn

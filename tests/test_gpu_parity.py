@@ -238,3 +238,14 @@ def test_si_3d_fused_moment_inflow(transpose):
         assert r["iters"] == k
         assert rel_l2(got, ref["phi"]) <= 1e-10
         assert np.allclose(r["res_hist"], ref["res_hist"], rtol=1e-9, atol=0)
+
+
+def test_si_converged_c1_multigrid():
+    """Source iteration with the multigrid-preconditioned thick-region CG
+    converges to the oracle's fixed point."""
+    p = sninputs.config("c1")
+    say("SI c1 converged, multigrid DSA")
+    ref = oracle.source_iterate(p, tol=1e-13, max_it=2000, use_dsa=True, cg_rtol=1e-13)
+    got = _si_gpu(p, tol=1e-12, max_it=400, use_dsa=True, cg_rtol=1e-13, cg_maxit=5000, precond=1)
+    assert got["rc"] == 0
+    assert rel_l2(got["phi"], ref["phi"]) <= 1e-10
