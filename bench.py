@@ -212,6 +212,29 @@ def main():
                 best = (t, r, phi.clone())
         return best
 
+    # ---- thick-region preconditioners: block Jacobi against multigrid ----
+    def dsa_compare(precond, k=6):
+        phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+                          cg_maxit=1000, precond=precond)     # first use builds the hierarchy
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        phi.zero_()
+        sn_set_kernel_timing(ctx, True)
+        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+                              cg_maxit=1000, precond=precond)
+        kt = sn_kernel_timing(ctx)
+        sn_set_kernel_timing(ctx, False)
+        return {"dsa_ms": kt["dsa_ms"] / max(kt["dsa_count"], 1), "cg_iters": r["cg_hist"].tolist(),
+                "first_call_s": first}
+
+    precond_cmp = {"block_jacobi": dsa_compare(0), "multigrid": dsa_compare(1)}
+    log(f"c2 DSA: block Jacobi {precond_cmp['block_jacobi']['dsa_ms']:.3f} ms "
+        f"{precond_cmp['block_jacobi']['cg_iters']}, multigrid {precond_cmp['multigrid']['dsa_ms']:.3f} ms "
+        f"{precond_cmp['multigrid']['cg_iters']}")
+
     t64, s64, phi64 = solve(SN_FP64)
     t32, s32, phi32 = solve(SN_FP32)
     err32_vs64 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
@@ -257,8 +280,15 @@ def main():
                          "fp32": {"seconds": t32, "iters": s32["iters"], "rc": s32["rc"],
                                   "cg_iters_total": int(np.sum(s32["cg_hist"]))},
                          "fp32_speedup": t64 / t32, "fp32_vs_fp64_rel_l2": err32_vs64},
+        "dsa_preconditioners_c2": precond_cmp,
     }
     del ctx
+
+    # ---- pure-scatterer thick tiles (sigma_a = 0): where multigrid matters ----
+    try:
+        out["dsa_preconditioners_c2s"] = pure_scatterer_compare(log)
+    except Exception as e:  # report, do not hide
+        out["dsa_preconditioners_c2s"] = {"error": repr(e)}
 
     # ---- 3D: 128^3, S12 (168 dirs) sweep grind time and HBM fraction ----
     if not args.no_3d:
@@ -287,6 +317,39 @@ def main():
         out["time_to_1e-8"]["fp32_vs_oracle_rel_l2"] = e32
         log(f"oracle: {tcpu:.2f} s for {its} iterations on {nth} threads; gpu fp64 err {e64:.2e}, fp32 {e32:.2e}")
     print(json.dumps(out), flush=True)
+
+
+def pure_scatterer_compare(log):
+    """c2s (c2 with sigma_s = sigma_t in the thick tiles): FP64 source iteration
+    to 1e-8 with each thick-region preconditioner."""
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import SN_FP64, Context, sn_source_iterate
+    dev = torch.device("cuda:0")
+    p = sninputs.config("c2s")
+    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
+    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
+    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
+    res = {"workload": "c2s: c2 with pure-scatterer thick tiles (sigma_t = sigma_s = 1e3)"}
+    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
+        for name, pc in (("block_jacobi", 0), ("multigrid", 1)):
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+                              cg_maxit=5000, precond=pc)      # builds the hierarchy on first use
+            phi.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=2000, use_dsa=True, prec=SN_FP64,
+                                  cg_rtol=1e-4, cg_maxit=5000, precond=pc)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            res[name] = {"time_to_1e-8_s": t, "iters": r["iters"], "rc": r["rc"],
+                         "cg_iters_total": int(r["cg_hist"].sum()),
+                         "cg_iters_mean": float(r["cg_hist"].mean())}
+            log(f"c2s {name}: {t*1e3:.1f} ms to 1e-8, {r['iters']} SI iterations, "
+                f"CG {int(r['cg_hist'].sum())} total")
+    return res
 
 
 def bench_3d(log):
@@ -323,6 +386,25 @@ def bench_3d(log):
             torch.cuda.empty_cache()
         # source iterations: fused sweep + moment (psi never stored) and DSA
         from paper_2001_09196_amd import sn_source_iterate
+        for pc_name, pc in (("block_jacobi", 0), ("multigrid", 1)):
+            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+            t0 = time.perf_counter()
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+                              cg_maxit=2000, precond=pc)
+            torch.cuda.synchronize()
+            first = time.perf_counter() - t0
+            phi.zero_()
+            sn_set_kernel_timing(ctx, True)
+            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=4, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+                                  cg_maxit=2000, precond=pc)
+            kt = sn_kernel_timing(ctx)
+            sn_set_kernel_timing(ctx, False)
+            res.setdefault("dsa_preconditioners", {})[pc_name] = {
+                "dsa_ms": kt["dsa_ms"] / max(kt["dsa_count"], 1), "cg_iters": r["cg_hist"].tolist(),
+                "first_call_s": first}
+            log(f"c5 DSA {pc_name}: {res['dsa_preconditioners'][pc_name]['dsa_ms']:.3f} ms, CG {r['cg_hist'].tolist()}, "
+                f"first call {first:.2f} s")
+            del phi
         for name, prec in (("fp32", SN_FP32), ("fp64", SN_FP64)):
             k = 4
             phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)

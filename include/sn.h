@@ -112,11 +112,12 @@ typedef struct {
     double cg_rtol;            /* stop when ||r|| <= cg_rtol ||b|| (zero initial guess) */
     int cg_maxit;              /* iteration cap (SN_ERR_NOT_CONVERGED is not raised for it) */
     int mass_kind;             /* 0: Sigma_f = mass of sigma_s; 1: mass of sigma_t (Sec. 2.2) */
-    int precond;               /* SN_PRECOND_BLOCK_JACOBI (inverse diagonal cell blocks) or SN_PRECOND_MG
-                                  (one symmetric geometric-multigrid V-cycle: damped block Jacobi on the
-                                  DG level, Galerkin piecewise-constant levels with 2x aggregation of the
-                                  cell grid and Jacobi smoothing, dense solve on <= 512 unknowns; the
-                                  hierarchy is built on the first use in a context) */
+    int precond;               /* SN_PRECOND_BLOCK_JACOBI: inverse diagonal cell blocks.
+                                  SN_PRECOND_MG: one symmetric geometric-multigrid V-cycle -- damped block
+                                  Jacobi on the DG level, the continuous Q1 space on the vertices of the
+                                  thick cells (Galerkin operator), vertex-grid coarsening by two with
+                                  (bi/tri)linear interpolation and damped Jacobi, a dense solve on <= 256
+                                  unknowns.  The hierarchy is built on the first use in a context. */
 } sn_dsa_opts;
 
 #define SN_PRECOND_BLOCK_JACOBI 0

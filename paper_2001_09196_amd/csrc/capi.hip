@@ -292,7 +292,7 @@ bool spd_inverse(int n, std::vector<double>& a, std::vector<double>& inv) {
 // Multigrid hierarchy for the thick-region operator.  Level 1: the vertices
 // of the thick cells (continuous Q1), stencil P^T D_ff P by probing on the
 // device.  Coarser levels (host, sums in a fixed order): every other vertex,
-// (bi/tri)linear interpolation, Galerkin stencils, until at most 512 unknowns
+// (bi/tri)linear interpolation, Galerkin stencils, until at most 256 unknowns
 // remain; that operator is inverted densely.
 int mg_setup(sn_context* c) {
     const DsaGeom& g = c->dg;
@@ -334,7 +334,12 @@ int mg_setup(sn_context* c) {
         (rc = c->cres.ensure((size_t)nt * nn)))
         return rc;
     HIPCHK(hipMemcpy(vpos.p, l1.pos.data(), n1 * sizeof(long), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->mg_vnodes.p, vnodes.data(), vnodes.size() * sizeof(int), hipMemcpyHostToDevice));
+    {
+        std::vector<int> vt(vnodes.size());   // offset-major on the device
+        for (int w = 0; w < n1; ++w)
+            for (int q = 0; q < nch; ++q) vt[(size_t)q * n1 + w] = vnodes[(size_t)w * nch + q];
+        HIPCHK(hipMemcpy(c->mg_vnodes.p, vt.data(), vt.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(c->mg_nodev.p, nodev.data(), nodev.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHK(hipMemset(coef1.p, 0, (size_t)n1 * ns * sizeof(double)));
     MgDev& m = c->mg;
@@ -350,7 +355,7 @@ int mg_setup(sn_context* c) {
     HIPCHK(hipMemcpyAsync(l1.coef.data(), coef1.p, l1.coef.size() * sizeof(double), hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    mg_coarsen(lv, dim, 512, MG_MAXL);
+    mg_coarsen(lv, dim, 256, MG_MAXL);
     const int L = (int)lv.size() - 1;
     // dense inverse of the coarsest operator
     const int nL = (int)lv[L].pos.size();
@@ -374,13 +379,20 @@ int mg_setup(sn_context* c) {
     }
     std::vector<double> coef((size_t)nv * ns), pw(std::max<long>(np, 1), 0.0);
     std::vector<int> nbr((size_t)nv * ns), chl((size_t)nv * ns, -1), par(std::max<long>(np, 1), -1);
+    // device tables are offset-major within each level
     for (int l = 1; l <= L; ++l) {
-        std::copy(lv[l].coef.begin(), lv[l].coef.end(), coef.begin() + m.so[l]);
-        std::copy(lv[l].nbr.begin(), lv[l].nbr.end(), nbr.begin() + m.so[l]);
-        if (l >= 2) std::copy(lv[l].chl.begin(), lv[l].chl.end(), chl.begin() + m.so[l]);
-        if (l < L) {
-            std::copy(lv[l].par.begin(), lv[l].par.end(), par.begin() + m.po[l]);
-            std::copy(lv[l].pw.begin(), lv[l].pw.end(), pw.begin() + m.po[l]);
+        const long n = m.n[l];
+        for (long f = 0; f < n; ++f) {
+            for (int o = 0; o < ns; ++o) {
+                coef[m.so[l] + o * n + f] = lv[l].coef[(size_t)f * ns + o];
+                nbr[m.so[l] + o * n + f] = lv[l].nbr[(size_t)f * ns + o];
+                if (l >= 2) chl[m.so[l] + o * n + f] = lv[l].chl[(size_t)f * ns + o];
+            }
+            if (l < L)
+                for (int q = 0; q < nch; ++q) {
+                    par[m.po[l] + q * n + f] = lv[l].par[(size_t)f * nch + q];
+                    pw[m.po[l] + q * n + f] = lv[l].pw[(size_t)f * nch + q];
+                }
         }
     }
     if ((rc = c->mg_coef.ensure(coef.size())) || (rc = c->mg_nbr.ensure(nbr.size())) ||
@@ -406,9 +418,11 @@ int mg_setup(sn_context* c) {
     m.ainv = c->mg_ainv.p;
     m.omega = env_double("SN_MG_OMEGA", 0.7);
     c->mg_omega0 = env_double("SN_MG_OMEGA0", 0.8);
-    // levels with at most 8192 unknowns run in the single-workgroup kernel
+    // the smallest levels (at most SN_MG_COARSE unknowns, default 2048) run
+    // in the single-workgroup kernel, the others as grid-wide kernels
+    const int small = (int)env_double("SN_MG_COARSE", 2048);
     int lc = L;
-    while (lc > 1 && m.n[lc - 1] <= 8192) --lc;
+    while (lc > 1 && m.n[lc - 1] <= small) --lc;
     c->mg_lc = lc;
     c->mg_levels = L;
     c->mg_ready = true;

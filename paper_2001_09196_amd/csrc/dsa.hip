@@ -394,7 +394,7 @@ __global__ void block_jacobi_kernel(DsaGeom g, const int* __restrict__ thick_cel
             }
         }
         for (int r = 0; r < NN; ++r)
-            for (int c = 0; c < NN; ++c) binv[((long)s * NN + r) * NN + c] = Inv[r][c];
+            for (int c = 0; c < NN; ++c) binv[(long)(r * NN + c) * g.nthick + s] = Inv[r][c];
     }
 }
 
@@ -463,13 +463,16 @@ __device__ __forceinline__ double reduce_parts(const double* __restrict__ part, 
 }
 
 template <int NN>
-__device__ __forceinline__ void bj_apply(const double* __restrict__ binv, int s, const double r[NN], double z[NN]) {
-    const double* B = binv + (long)s * NN * NN;
+__device__ __forceinline__ void bj_apply(const double* __restrict__ binv, long bj_stride, int s, const double r[NN],
+                                         double z[NN]) {
+    // element-major storage: entry (a, b) of the blocks of all thick cells is
+    // contiguous, so consecutive lanes (cells) read consecutive words
+    const long n = bj_stride;
 #pragma unroll
     for (int a = 0; a < NN; ++a) {
         double v = 0.0;
 #pragma unroll
-        for (int b = 0; b < NN; ++b) v = fma(B[a * NN + b], r[b], v);
+        for (int b = 0; b < NN; ++b) v = fma(binv[(long)(a * NN + b) * n + s], r[b], v);
         z[a] = v;
     }
 }
@@ -478,7 +481,7 @@ __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, int s,
 // block-Jacobi preconditioner (bj = 1) also z = B^{-1} r and the r.z partials
 // [0..nparts); the b.b partials go to [nparts..2 nparts).  With the multigrid
 // preconditioner the V-cycle produces z and the r.z partials.
-template <int NN>
+template <int NN, bool BJ>
 __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __restrict__ thick_cell,
                                                       const double* __restrict__ sigma_t,
                                                       const double* __restrict__ sigma_s, int mass_kind,
@@ -486,7 +489,7 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       const double* __restrict__ phi_si,
                                                       const double* __restrict__ binv, double* __restrict__ x,
                                                       double* __restrict__ r, double* __restrict__ z,
-                                                      double* __restrict__ p, double* __restrict__ part, int bj) {
+                                                      double* __restrict__ p, double* __restrict__ part) {
     __shared__ double sh[256];
     constexpr int DIM = NN == 4 ? 2 : 3;
     double rz = 0.0, bb = 0.0;
@@ -500,14 +503,14 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
         for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
 #pragma unroll
         for (int n = 0; n < NN; ++n) t[n] *= coef;
-        if (bj) bj_apply<NN>(binv, s, t, zz);
+        if constexpr (BJ) bj_apply<NN>(binv, g.nthick, s, t, zz);
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const long e = (long)s * NN + n;
             x[e] = 0.0;
             r[e] = t[n];
             p[e] = 0.0;
-            if (bj) {
+            if constexpr (BJ) {
                 z[e] = zz[n];
                 rz = fma(t[n], zz[n], rz);
             }
@@ -517,7 +520,7 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
     rz = block_reduce(rz, sh);
     bb = block_reduce(bb, sh);
     if (threadIdx.x == 0) {
-        if (bj) part[blockIdx.x] = rz;
+        if constexpr (BJ) part[blockIdx.x] = rz;
         part[gridDim.x + blockIdx.x] = bb;
     }
 }
@@ -526,12 +529,17 @@ hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double*
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
                           hipStream_t st) {
-    if (g.nn == 4)
-        hipLaunchKernelGGL(dsa_rhs_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
-                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part, bj);
-    else
-        hipLaunchKernelGGL(dsa_rhs_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
-                           mass_kind, phi_old, phi_si, binv, x, r, z, p, part, bj);
+#define SN_RHS(NN, BJ)                                                                                        \
+    hipLaunchKernelGGL((dsa_rhs_kernel<NN, BJ>), dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s, \
+                       mass_kind, phi_old, phi_si, binv, x, r, z, p, part)
+    if (g.nn == 4) {
+        if (bj) SN_RHS(4, true);
+        else SN_RHS(4, false);
+    } else {
+        if (bj) SN_RHS(8, true);
+        else SN_RHS(8, false);
+    }
+#undef SN_RHS
     return hipGetLastError();
 }
 
@@ -611,14 +619,14 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
     if (threadIdx.x == 0) part[blockIdx.x] = pq;
 }
 
-template <int NN>
+template <int NN, bool BJ>
 __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double* __restrict__ binv,
                                                         double* __restrict__ x, double* __restrict__ r,
                                                         double* __restrict__ z, const double* __restrict__ p,
                                                         const double* __restrict__ q,
                                                         const double* __restrict__ part_pq,
                                                         double* __restrict__ part_out, int nparts, CgScalars* s,
-                                                        int it, int bj) {
+                                                        int it) {
     if (s->done) return;
     __shared__ double sh[256];
     const double pq = reduce_parts(part_pq, nparts, sh);
@@ -640,21 +648,24 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
             x[e] = fma(alpha, p[e], x[e]);
             rv[n] = fma(-alpha, q[e], r[e]);
             r[e] = rv[n];
-            rr = fma(rv[n], rv[n], rr);
         }
-        if (bj) {
-            bj_apply<NN>(binv, t, rv, zv);
+        if constexpr (BJ) {
+            bj_apply<NN>(binv, g.nthick, t, rv, zv);
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
                 z[(long)t * NN + n] = zv[n];
                 rz = fma(rv[n], zv[n], rz);
+                rr = fma(rv[n], rv[n], rr);
             }
+        } else {
+#pragma unroll
+            for (int n = 0; n < NN; ++n) rr = fma(rv[n], rv[n], rr);
         }
     }
     rz = block_reduce(rz, sh);
     rr = block_reduce(rr, sh);
     if (threadIdx.x == 0) {
-        if (bj) part_out[blockIdx.x] = rz;
+        if constexpr (BJ) part_out[blockIdx.x] = rz;
         part_out[gridDim.x + blockIdx.x] = rr;
     }
 }
@@ -669,15 +680,25 @@ hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const in
     if (g.nn == 4) {
         hipLaunchKernelGGL(cg_apply_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
                            z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
-        if (it < maxit)
-            hipLaunchKernelGGL(cg_update_kernel<4>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
-                               part_a, part_b, nparts, s, it, bj);
+        if (it < maxit) {
+            if (bj)
+                hipLaunchKernelGGL((cg_update_kernel<4, true>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
+                                   p_new, q, part_a, part_b, nparts, s, it);
+            else
+                hipLaunchKernelGGL((cg_update_kernel<4, false>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
+                                   p_new, q, part_a, part_b, nparts, s, it);
+        }
     } else {
         hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
                            z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
-        if (it < maxit)
-            hipLaunchKernelGGL(cg_update_kernel<8>, dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q,
-                               part_a, part_b, nparts, s, it, bj);
+        if (it < maxit) {
+            if (bj)
+                hipLaunchKernelGGL((cg_update_kernel<8, true>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
+                                   p_new, q, part_a, part_b, nparts, s, it);
+            else
+                hipLaunchKernelGGL((cg_update_kernel<8, false>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
+                                   p_new, q, part_a, part_b, nparts, s, it);
+        }
     }
     return hipGetLastError();
 }
@@ -750,7 +771,7 @@ __global__ void vmg_probe_gather_kernel(MgDev m, int nvx, int nvy, const long* _
         }
         double v = 0.0;
         for (int q = 0; q < nch; ++q) {
-            const int e = m.vnodes[(long)w * nch + q];
+            const int e = m.vnodes[(long)q * m.n[1] + w];
             if (e >= 0) v += y0[e];
         }
         coef[(long)w * m.ns + idx] = v;
@@ -777,17 +798,20 @@ hipError_t launch_vmg_probe(const DsaGeom& g, const int* thick_cell, const int* 
 
 // (A_l v)[f] for vertex level l
 __device__ __forceinline__ double vmg_apply_at(const MgDev& m, int l, int f, const double* __restrict__ v) {
-    const double* c = m.coef + m.so[l] + (long)f * m.ns;
-    const int* nb = m.nbr + m.so[l] + (long)f * m.ns;
+    // per-level arrays are offset-major ([o][unknown]): for a fixed offset,
+    // consecutive lanes read consecutive words
+    const long n = m.n[l];
+    const double* c = m.coef + m.so[l] + f;
+    const int* nb = m.nbr + m.so[l] + f;
     double a = 0.0;
     for (int o = 0; o < m.ns; ++o) {
-        const int g = nb[o];
-        if (g >= 0) a = fma(c[o], v[g], a);
+        const int g = nb[o * n];
+        if (g >= 0) a = fma(c[o * n], v[g], a);
     }
     return a;
 }
 __device__ __forceinline__ double vmg_diag(const MgDev& m, int l, int f) {
-    return m.coef[m.so[l] + (long)f * m.ns + m.ns / 2];
+    return m.coef[m.so[l] + (long)(m.ns / 2) * m.n[l] + f];
 }
 // the post-smoothed vector of level l (the coarsest level has no smoother)
 __device__ __forceinline__ const double* vmg_post_vec(const MgDev& m, int l) {
@@ -802,11 +826,12 @@ __device__ __forceinline__ void vmg_res_at(const MgDev& m, int l, int f) {
 // full-weighting restriction (transpose of the interpolation): children of C
 // at 2C + o with weight prod_d (o_d == 0 ? 1 : 1/2)
 __device__ __forceinline__ void vmg_restrict_at(const MgDev& m, int l, int C) {
-    const int* ch = m.chl + m.so[l + 1] + (long)C * m.ns;
+    const long nc = m.n[l + 1];
+    const int* ch = m.chl + m.so[l + 1] + C;
     const double* rl = m.r + m.vo[l];
     double v = 0.0;
     for (int o = 0; o < m.ns; ++o) {
-        const int f = ch[o];
+        const int f = ch[o * nc];
         if (f < 0) continue;
         double w = 1.0;
         int t = o;
@@ -822,11 +847,12 @@ __device__ __forceinline__ void vmg_restrict_at(const MgDev& m, int l, int C) {
 __device__ __forceinline__ void vmg_prolong_at(const MgDev& m, int l, int f) {
     const int nch = 1 << m.dim;
     const double* xc = vmg_post_vec(m, l + 1);
-    const int* pa = m.par + m.po[l] + (long)f * nch;
-    const double* pw = m.pw + m.po[l] + (long)f * nch;
+    const long n = m.n[l];
+    const int* pa = m.par + m.po[l] + f;
+    const double* pw = m.pw + m.po[l] + f;
     double v = m.x[m.vo[l] + f];
     for (int q = 0; q < nch; ++q)
-        if (pa[q] >= 0) v = fma(pw[q], xc[pa[q]], v);
+        if (pa[q * n] >= 0) v = fma(pw[q * n], xc[pa[q * n]], v);
     m.x[m.vo[l] + f] = v;
 }
 __device__ __forceinline__ void vmg_post_at(const MgDev& m, int l, int f) {
@@ -858,13 +884,17 @@ __global__ void __launch_bounds__(1024) vmg_coarse_kernel(MgDev m, int lc, const
         for (int i = tid; i < m.n[l + 1]; i += nt) vmg_restrict_at(m, l, i);
         __syncthreads();
     }
+    // dense solve: one wave per row at a time, lanes over the columns
+    // (coalesced row reads), then a fixed-order butterfly sum across the wave
     const int nL = m.n[m.L];
     const double* bL = m.b + m.vo[m.L];
-    for (int i = tid; i < nL; i += nt) {
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    for (int i = wv; i < nL; i += nw) {
         const double* row = m.ainv + (long)i * nL;
         double v = 0.0;
-        for (int j = 0; j < nL; ++j) v = fma(row[j], bL[j], v);
-        m.x[m.vo[m.L] + i] = v;
+        for (int j = lane; j < nL; j += 64) v = fma(row[j], bL[j], v);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) m.x[m.vo[m.L] + i] = v;
     }
     __syncthreads();
     for (int l = m.L - 1; l >= lc; --l) {
@@ -885,7 +915,7 @@ __global__ void __launch_bounds__(256) mg_l0_pre_kernel(DsaGeom g, const double*
         double rv[NN], zv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) rv[n] = r[(long)t * NN + n];
-        bj_apply<NN>(binv, t, rv, zv);
+        bj_apply<NN>(binv, g.nthick, t, rv, zv);
 #pragma unroll
         for (int n = 0; n < NN; ++n) z0[(long)t * NN + n] = omega0 * zv[n];
     }
@@ -922,7 +952,7 @@ __global__ void __launch_bounds__(256) mg_restrict1_kernel(MgDev m, const double
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < m.n[1]; w += gridDim.x * blockDim.x) {
         double v = 0.0;
         for (int q = 0; q < nch; ++q) {
-            const int e = m.vnodes[(long)w * nch + q];
+            const int e = m.vnodes[(long)q * m.n[1] + w];
             if (e >= 0) v += res0[e];
         }
         m.b[m.vo[1] + w] = v;
@@ -954,7 +984,7 @@ __global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* _
         sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, get, o);
 #pragma unroll
         for (int n = 0; n < NN; ++n) rv[n] = r[(long)t * NN + n] - o[n];
-        bj_apply<NN>(binv, t, rv, zv);
+        bj_apply<NN>(binv, g.nthick, t, rv, zv);
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const double zz = fma(omega0, zv[n], uK[n]);

@@ -119,7 +119,9 @@ hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* 
 // geometric multigrid hierarchy on the device: level 0 is the DG system;
 // vertex levels 1 .. L hold one value per active vertex (level 1 = the
 // vertices of the thick cells in increasing vertex order) with a 3^dim-point
-// stencil (offset index o = sum_d (o_d + 1) 3^d)
+// stencil (offset index o = sum_d (o_d + 1) 3^d); the per-unknown tables of a level
+// are stored offset-major ([o][unknown], [q][unknown]) so that consecutive
+// lanes read consecutive words
 constexpr int MG_MAXL = 20;
 struct MgDev {
     int L, dim, ns;        // coarsest level, dimension, stencil size 3^dim
@@ -127,12 +129,12 @@ struct MgDev {
     long vo[MG_MAXL];      // offset of level l in the per-unknown arrays (b, x, y, r)
     long so[MG_MAXL];      // offset of level l in coef, nbr, chl (ns per unknown)
     long po[MG_MAXL];      // offset of level l in par, pw (2^dim per unknown; levels < L)
-    const double* coef;    // stencil coefficients [unknown][ns]
-    const int* nbr;        // stencil neighbours [unknown][ns] or -1
-    const int* chl;        // level l >= 2: fine unknowns at 2C + o of level l - 1, [unknown][ns] or -1
-    const int* par;        // coarse parents (level l + 1) of each unknown [unknown][2^dim] or -1
+    const double* coef;    // stencil coefficients [ns][unknown]
+    const int* nbr;        // stencil neighbours [ns][unknown] or -1
+    const int* chl;        // level l >= 2: fine unknowns at 2C + o of level l - 1, [ns][unknown] or -1
+    const int* par;        // coarse parents (level l + 1) of each unknown [2^dim][unknown] or -1
     const double* pw;      // interpolation weights of the parents
-    const int* vnodes;     // level 1: DG indices (slot * nn + node) at each vertex [n1][2^dim] or -1
+    const int* vnodes;     // level 1: DG indices (slot * nn + node) at each vertex [2^dim][n1] or -1
     const int* nodev;      // level-1 vertex of each DG node [nthick * nn]
     double* b;
     double* x;

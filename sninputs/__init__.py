@@ -178,8 +178,15 @@ def config(name: str) -> Problem:
         on sigma_t and sigma_s, then sigma_s clipped to sigma_t.
     c5  3D 128^3, S12, 16^3 tiles, same mix.
     Thin tiles carry q = 1; thick tiles (1e3, 999.9); thin (1, 0.5); void (0, 0).
+    c2s c2 with pure-scatterer thick tiles (1e3, 1e3): sigma_a = 0 there, so the
+        thick-region diffusion operator has no absorption (the regime of the
+        sigma_a = 0 rows of the paper's crooked-pipe table).
     """
     name = name.lower()
+    if name == "c2s":
+        p = config("c2")
+        ss = np.where(p.meta["kind"] == 2, p.sigma_t, p.sigma_s)
+        return Problem("c2s", 2, p.nx, p.ny, 1, p.h, p.sigma_t, ss, p.q, p.omega, p.w, meta=p.meta)
     if name == "c1":
         n = 16
         om, w = level_symmetric(4, 2)
