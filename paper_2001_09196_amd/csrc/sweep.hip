@@ -619,10 +619,15 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                     const long qc = ((long)qk * ny + qj) * nx + qi;
                     const T* sp = stg + q * 32 + o * CH;
                     T* gp = psi + (qc * ndirs + d0) * 8 + o * CH;
+                    // psi is written once per sweep and not read back by this
+                    // kernel: nontemporal stores keep it from displacing the
+                    // face and source data in the caches
                     if constexpr (sizeof(T) == 8) {
-                        *reinterpret_cast<double2*>(gp) = *reinterpret_cast<const double2*>(sp);
+                        typedef double d2v __attribute__((ext_vector_type(2)));
+                        __builtin_nontemporal_store(*reinterpret_cast<const d2v*>(sp), reinterpret_cast<d2v*>(gp));
                     } else {
-                        *reinterpret_cast<float4*>(gp) = *reinterpret_cast<const float4*>(sp);
+                        typedef float f4v __attribute__((ext_vector_type(4)));
+                        __builtin_nontemporal_store(*reinterpret_cast<const f4v*>(sp), reinterpret_cast<f4v*>(gp));
                     }
                 }
             }
@@ -638,7 +643,9 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
 }
 
 // blockIdx.x: tile of the plane; blockIdx.y: reflection class; wave w of the
-// block: direction group w of that class (four directions, -1 = unused slot)
+// block: direction group w of that class (four directions, -1 = unused slot).
+// The waves of a block read the same cells' source and sigma_t, which one
+// compute unit's L1 then serves to all of them.
 template <typename T>
 __global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const DirInfo* __restrict__ dirs, int transpose,
