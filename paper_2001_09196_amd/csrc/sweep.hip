@@ -427,6 +427,17 @@ __device__ __forceinline__ double rows_sum(double v) {
 // fused sweep + moment: steps per workgroup barrier
 constexpr int RF = 4;
 
+// The LDS buffers reach the sweep bodies as plain pointers; these casts give
+// them back the LDS address space, so that the compiler emits LDS
+// instructions (ds_read / ds_write) rather than flat ones, which wait on both
+// the memory and the LDS counters.
+template <typename T>
+using lds_t = __attribute__((address_space(3))) T;
+template <typename T>
+__device__ __forceinline__ lds_t<T>* as_lds(T* p) {
+    return (lds_t<T>*)p;
+}
+
 // FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
 // stored; every step the lanes' w_d psi (FP64) is summed over the four
 // directions of a pencil (rows_sum), the 16 pencil sums of each wave go to an
@@ -546,9 +557,9 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 for (int n = 0; n < 8; ++n) acc[n] = wgt * (double)o[n];
             } else if (nvalid > 0) {
                 // staged: this lane's eight values go to LDS slot (pencil, k)
-                T* sp = stg + ((lane & 15) * 4 + (lane >> 4)) * 8;
-                store4(sp, o[0], o[1], o[2], o[3]);
-                store4(sp + 4, o[4], o[5], o[6], o[7]);
+                lds_t<T>* sp = as_lds(stg) + ((lane & 15) * 4 + (lane >> 4)) * 8;
+#pragma unroll
+                for (int n = 0; n < 8; ++n) sp[n] = o[n];
             } else {
                 T* pp = psi + (c * ndirs + d) * 8;
                 store4(pp, o[0], o[1], o[2], o[3]);
@@ -563,13 +574,12 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         }
         if constexpr (FUSED) {
             const int wave = threadIdx.x >> 6;
-            double* rs = red + ((s % (2 * RF)) * nwaves + wave) * 128;
+            lds_t<double>* rs = as_lds(red) + ((s % (2 * RF)) * nwaves + wave) * 128;
 #pragma unroll
             for (int n = 0; n < 8; ++n) acc[n] = rows_sum(acc[n]);
             if (lane < 16) {
-                double2* r2 = reinterpret_cast<double2*>(rs + lane * 8);
 #pragma unroll
-                for (int n = 0; n < 4; ++n) r2[n] = make_double2(acc[2 * n], acc[2 * n + 1]);
+                for (int n = 0; n < 8; ++n) rs[lane * 8 + n] = acc[n];
             }
             if ((s + 1) % RF == 0 || s == nsteps - 1) {
                 __syncthreads();
@@ -578,7 +588,7 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 const int nwork = (s - sb + 1) * 128;
                 for (int id = threadIdx.x; id < nwork; id += blockDim.x) {
                     const int sj = sb + (id >> 7), q = (id >> 3) & 15, n = id & 7;
-                    const double* rq = red + (sj % (2 * RF)) * nwaves * 128 + q * 8 + n;
+                    const lds_t<double>* rq = as_lds(red) + (sj % (2 * RF)) * nwaves * 128 + q * 8 + n;
                     double sum = 0.0;
                     for (int w = 0; w < nwaves; ++w) sum += rq[w * 128];
                     const int qy = q & 3, qz = q >> 2;
@@ -617,17 +627,19 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                     const int qj = ry ? ny - 1 - qjl : qjl;
                     const int qk = rz ? nz - 1 - qkl : qkl;
                     const long qc = ((long)qk * ny + qj) * nx + qi;
-                    const T* sp = stg + q * 32 + o * CH;
+                    const lds_t<T>* sp = as_lds(stg) + q * 32 + o * CH;
                     T* gp = psi + (qc * ndirs + d0) * 8 + o * CH;
                     // psi is written once per sweep and not read back by this
                     // kernel: nontemporal stores keep it from displacing the
                     // face and source data in the caches
                     if constexpr (sizeof(T) == 8) {
                         typedef double d2v __attribute__((ext_vector_type(2)));
-                        __builtin_nontemporal_store(*reinterpret_cast<const d2v*>(sp), reinterpret_cast<d2v*>(gp));
+                        typedef __attribute__((address_space(3))) d2v lds_d2v;
+                        __builtin_nontemporal_store(*reinterpret_cast<const lds_d2v*>(sp), reinterpret_cast<d2v*>(gp));
                     } else {
                         typedef float f4v __attribute__((ext_vector_type(4)));
-                        __builtin_nontemporal_store(*reinterpret_cast<const f4v*>(sp), reinterpret_cast<f4v*>(gp));
+                        typedef __attribute__((address_space(3))) f4v lds_f4v;
+                        __builtin_nontemporal_store(*reinterpret_cast<const lds_f4v*>(sp), reinterpret_cast<f4v*>(gp));
                     }
                 }
             }
