@@ -380,7 +380,8 @@ def bench_3d(log):
             ms = kt["sweep_ms"] / kt["sweep_count"]
             b = sweep_bytes_per_call(nc, D, nn, s)
             res[name] = {"sweep_ms": ms, "grind_ns": ms * 1e6 / cd, "algorithmic_bytes": b,
-                         "achieved_GBs": b / (ms * 1e-3) / 1e9, "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                         "achieved_GBs": b / (ms * 1e-3) / 1e9, "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic_from_profiles(f"sweep3d_{name}_c5")}
             log(f"c5 sweep {name}: {ms:.3f} ms, grind {ms*1e6/cd:.5f} ns, {res[name]['achieved_GBs']:.0f} GB/s")
             del psi
             torch.cuda.empty_cache()

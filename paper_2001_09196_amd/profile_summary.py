@@ -8,6 +8,9 @@
       HBM bytes per dispatch of one kernel from FETCH_SIZE and WRITE_SIZE runs (KiB per
       dispatch), each scaled so that a plain copy of copy_bytes reads as copy_bytes; the entry
       of traffic.json records the sha256 of sweep.hip the counters were taken on.
+  python -m paper_2001_09196_amd.profile_summary traffic_per_call <calls> <key> ... (as traffic)
+      the same for kernels launched several times per call: the counters of all
+      dispatches summed and divided by the number of calls.
 """
 from __future__ import annotations
 
@@ -43,7 +46,9 @@ def stats(d, out, command):
     print("\n".join(lines))
 
 
-def _per_dispatch(d, counter, kernel):
+def _per_dispatch(d, counter, kernel, per_call=0):
+    """Median over dispatches (KiB), or, with per_call = k > 0, the sum over all
+    dispatches divided by k (kernels launched k times per call)."""
     vals = {}
     for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
         if r["Counter_Name"] == counter and kernel in r["Kernel_Name"]:
@@ -51,25 +56,30 @@ def _per_dispatch(d, counter, kernel):
             vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
     if not vals:
         raise SystemExit(f"no {counter} rows for {kernel} in {d}")
+    if per_call > 0:
+        return sum(vals.values()) / per_call, len(vals)
     v = sorted(vals.values())
     return v[len(v) // 2], len(v)   # median over dispatches, KiB
 
 
-def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, command):
+def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, command, per_call=0):
     copy_bytes = float(copy_bytes)
     cf, _ = _per_dispatch(cfdir, "FETCH_SIZE", "copy")
     cw, _ = _per_dispatch(cwdir, "WRITE_SIZE", "copy")
     sf, sw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
-    f, nf = _per_dispatch(fdir, "FETCH_SIZE", kernel)
-    w, nw = _per_dispatch(wdir, "WRITE_SIZE", kernel)
+    f, nf = _per_dispatch(fdir, "FETCH_SIZE", kernel, per_call)
+    w, nw = _per_dispatch(wdir, "WRITE_SIZE", kernel, per_call)
     fb, wb = f * 1024 * sf, w * 1024 * sw
     src = os.path.join(HERE, "csrc", "sweep.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     lines = [f"# HBM traffic of {kernel} ({key})", f"# commands: {command}", "",
              f"copy probe: FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB per {copy_bytes:.0f}-byte copy -> "
              f"scale fetch {sf:.3f}, write {sw:.3f}",
-             f"kernel: FETCH_SIZE {f:.0f} KiB (median of {nf} dispatches), WRITE_SIZE {w:.0f} KiB ({nw})",
-             f"scaled bytes per dispatch: read {fb:.4e}, write {wb:.4e}, total {fb + wb:.4e}",
+             (f"kernel: FETCH_SIZE {f:.0f} KiB, WRITE_SIZE {w:.0f} KiB per call "
+              f"({nf} dispatches summed over {per_call} calls)" if per_call > 0 else
+              f"kernel: FETCH_SIZE {f:.0f} KiB (median of {nf} dispatches), WRITE_SIZE {w:.0f} KiB ({nw})"),
+             f"scaled bytes per {'call' if per_call > 0 else 'dispatch'}: read {fb:.4e}, write {wb:.4e}, "
+             f"total {fb + wb:.4e}",
              f"sweep.hip sha256 {sha}"]
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -85,5 +95,8 @@ if __name__ == "__main__":
         stats(a[1], a[2], " ".join(a[3:]))
     elif a and a[0] == "traffic":
         traffic(*a[1:10], " ".join(a[10:]))
+    elif a and a[0] == "traffic_per_call":
+        # traffic_per_call <calls> <key> <kernel> ... (as traffic)
+        traffic(*a[2:11], " ".join(a[11:]), per_call=int(a[1]))
     else:
         raise SystemExit(__doc__)
