@@ -7,7 +7,7 @@ boundaries, q = 1 on thin tiles; thick threshold eta = 1 (19,712 thick cells).
 
 A step is one source iteration through the C ABI: transport sweep of all 40
 directions, FP64 scalar-flux moment, residual, heterogeneous DSA (SIP on the
-thick cells, block-Jacobi PCG to 1e-4) and update.  K steps are timed from
+thick cells, block-Jacobi PCG to 1e-2) and update.  K steps are timed from
 phi = 0 after W warm-up steps.  `value` is the grind time of one whole step in
 ns per (cell x direction), FP64 sweep.  Also reported: the same for the FP32
 sweep form, sweep-only grind times, time to a 1e-8 residual for both forms,
@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sweep grind time ns/(cell·dir) + time-to-1e-8, FP32 vs FP64 sweep, 1 MI355X"
+# relative tolerance of the thick-region CG inside source iteration: on c2 the
+# source-iteration count (45 to 1e-8) is the same for 1e-1 .. 1e-4, so the
+# diffusion correction is solved to 1e-2 rather than over-solved
+CG_RTOL = 1e-2
 HBM_PEAK_GBS = 8000.0
 
 
@@ -151,7 +155,7 @@ def main():
             sn_set_kernel_timing(ctx, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=1e-4,
+        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
                               cg_maxit=1000)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -204,7 +208,7 @@ def main():
             phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = sn_source_iterate(ctx, q, None, phi, tol=tol, max_it=2000, use_dsa=True, prec=prec, cg_rtol=1e-4,
+            r = sn_source_iterate(ctx, q, None, phi, tol=tol, max_it=2000, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
                                   cg_maxit=1000)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
@@ -217,13 +221,13 @@ def main():
         phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+        sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
                           cg_maxit=1000, precond=precond)     # first use builds the hierarchy
         torch.cuda.synchronize()
         first = time.perf_counter() - t0
         phi.zero_()
         sn_set_kernel_timing(ctx, True)
-        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
                               cg_maxit=1000, precond=precond)
         kt = sn_kernel_timing(ctx)
         sn_set_kernel_timing(ctx, False)
@@ -267,7 +271,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 2D 256x256 Q1 upwind-DG, S8 (40 dirs), seeded 16x16 tiles void/thin/thick "
                                "20/50/30%, vacuum; one step = sweep + FP64 moment + residual + thick-only DSA "
-                               "(SIP, block-Jacobi PCG rtol 1e-4) + update",
+                               "(SIP, block-Jacobi PCG rtol 1e-2) + update",
                    "cells": nc, "dirs": D, "thick_cells": ctx.thick_count, "eta": p.eta},
         "roofline": roofline,
         "step_breakdown_ms": {"sweep": sweep_per_step, "dsa": dsa_per_step,
@@ -302,7 +306,7 @@ def main():
         import oracle
         nth = oracle.num_threads()
         t0 = time.perf_counter()
-        ro = oracle.source_iterate(p, tol=1e-8, max_it=2000, use_dsa=True, cg_rtol=1e-4)
+        ro = oracle.source_iterate(p, tol=1e-8, max_it=2000, use_dsa=True, cg_rtol=CG_RTOL)
         tcpu = time.perf_counter() - t0
         its = ro["iters"]
         ref = torch.tensor(ro["phi"], dtype=torch.float64, device=dev)
@@ -335,13 +339,13 @@ def pure_scatterer_compare(log):
     with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
         for name, pc in (("block_jacobi", 0), ("multigrid", 1)):
             phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
                               cg_maxit=5000, precond=pc)      # builds the hierarchy on first use
             phi.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=2000, use_dsa=True, prec=SN_FP64,
-                                  cg_rtol=1e-4, cg_maxit=5000, precond=pc)
+                                  cg_rtol=CG_RTOL, cg_maxit=5000, precond=pc)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             res[name] = {"time_to_1e-8_s": t, "iters": r["iters"], "rc": r["rc"],
@@ -390,13 +394,13 @@ def bench_3d(log):
         for pc_name, pc in (("block_jacobi", 0), ("multigrid", 1)):
             phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
             t0 = time.perf_counter()
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
                               cg_maxit=2000, precond=pc)
             torch.cuda.synchronize()
             first = time.perf_counter() - t0
             phi.zero_()
             sn_set_kernel_timing(ctx, True)
-            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=4, use_dsa=True, prec=SN_FP64, cg_rtol=1e-4,
+            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=4, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
                                   cg_maxit=2000, precond=pc)
             kt = sn_kernel_timing(ctx)
             sn_set_kernel_timing(ctx, False)
@@ -409,13 +413,13 @@ def bench_3d(log):
         for name, prec in (("fp32", SN_FP32), ("fp64", SN_FP64)):
             k = 4
             phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=1e-4,
+            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
                               cg_maxit=2000)
             phi.zero_()
             sn_set_kernel_timing(ctx, True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=1e-4,
+            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
                                   cg_maxit=2000)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

@@ -157,16 +157,21 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
     if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
     if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
     if ((rc = zf.ensure((size_t)std::max<long>(g.zstride, 1) * g.ndirs))) return rc;
-    if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
     if ((rc = sink.ensure((size_t)sink_elems(g)))) return rc;
-    HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
-    const T* sweep_src = src.p;
+    const T* sweep_src;
     const T* sweep_sig = sigt;
     if (g.dim == 2) {
-        if ((rc = srcskew.ensure((size_t)skew2d_elems(g.nx, g.ny, 4)))) return rc;
-        HIPCHK(launch_skew2d<T>(g.nx, g.ny, 4, src.p, srcskew.p, ctx->stream));
+        const size_t ne = (size_t)skew2d_elems(g.nx, g.ny, 4);
+        const bool fresh = srcskew.n < ne || !srcskew.p;
+        if ((rc = srcskew.ensure(ne))) return rc;
+        if (fresh) HIPCHK(hipMemsetAsync(srcskew.p, 0, ne * sizeof(T), ctx->stream));  // padding stays zero
+        HIPCHK(launch_source_skew2d<T>(g.nx, g.ny, ctx->sigs.p, phi, phi_prev, q, srcskew.p, ctx->stream));
         sweep_src = srcskew.p;
         sweep_sig = sigskew;
+    } else {
+        if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
+        HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
+        sweep_src = src.p;
     }
     HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
     size_t e0 = 0, e1 = 0;

@@ -49,6 +49,11 @@ hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const do
 // [4][ceil(ny / 64)][nx + 63][64][nn] (2D sweep input layout)
 template <typename T>
 hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_t st);
+// the 2D sweep source (sigma_s (phi - phi_prev) + q) / 4pi written straight
+// into the diagonal-major layout (only on-mesh entries; padding stays zero)
+template <typename T>
+hipError_t launch_source_skew2d(int nx, int ny, const double* sigma_s, const double* phi, const double* phi_prev,
+                                const double* q, T* out, hipStream_t st);
 inline long skew2d_elems(int nx, int ny, int nn) { return 4L * ((ny + 63) / 64) * (nx + 63) * 64 * nn; }
 
 // scalar-flux kernels (flux.hip)

@@ -160,6 +160,36 @@ __global__ void skew2d_kernel(int nx, int ny, int nn, const T* __restrict__ in, 
     }
 }
 
+// Source of the 2D sweep written straight into the diagonal-major arrays:
+// s = (sigma_s (phi - phi_prev) + q) / 4pi per node (one thread per cell),
+// stored at the cell's position in each quadrant's layout.  Only on-mesh
+// entries are written; the padding of the arrays is zeroed once when they
+// are allocated.
+template <typename T>
+__global__ void source_skew2d_kernel(int nx, int ny, const double* __restrict__ sigma_s,
+                                     const double* __restrict__ phi, const double* __restrict__ phi_prev,
+                                     const double* __restrict__ q, T* __restrict__ out) {
+    const long ns = (long)nx + 63;
+    const long per = (long)((ny + 63) / 64) * ns * 64;
+    const long nc = (long)nx * ny;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)(c / nx);
+        T v[4];
+        for (int n = 0; n < 4; ++n) {
+            double f = phi ? phi[c * 4 + n] : 0.0;
+            if (phi_prev) f -= phi_prev[c * 4 + n];
+            v[n] = T((sigma_s[c] * f + (q ? q[c] : 0.0)) * 0.07957747154594766788);  // 1 / 4pi
+        }
+        for (int qd = 0; qd < 4; ++qd) {
+            const int il = (qd & 1) ? nx - 1 - i : i;
+            const int jl = (qd & 2) ? ny - 1 - j : j;
+            const int l = jl & 63;
+            T* o = out + (qd * per + ((long)(jl >> 6) * ns + il + l) * 64 + l) * 4;
+            for (int n = 0; n < 4; ++n) o[n] = v[n];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 2D pipelined sweep
 // ---------------------------------------------------------------------------
@@ -818,6 +848,19 @@ hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_
     hipLaunchKernelGGL(skew2d_kernel<T>, dim3(blocks), dim3(256), 0, st, nx, ny, nn, in, out);
     return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_source_skew2d(int nx, int ny, const double* sigma_s, const double* phi, const double* phi_prev,
+                                const double* q, T* out, hipStream_t st) {
+    const long nc = (long)nx * ny;
+    const int blocks = (int)std::min<long>((nc + 255) / 256, 65536);
+    hipLaunchKernelGGL(source_skew2d_kernel<T>, dim3(blocks), dim3(256), 0, st, nx, ny, sigma_s, phi, phi_prev, q,
+                       out);
+    return hipGetLastError();
+}
+template hipError_t launch_source_skew2d<double>(int, int, const double*, const double*, const double*,
+                                                 const double*, double*, hipStream_t);
+template hipError_t launch_source_skew2d<float>(int, int, const double*, const double*, const double*, const double*,
+                                                float*, hipStream_t);
 template hipError_t launch_skew2d<double>(int, int, int, const double*, double*, hipStream_t);
 template hipError_t launch_skew2d<float>(int, int, int, const float*, float*, hipStream_t);
 
