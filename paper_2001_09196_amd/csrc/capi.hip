@@ -92,6 +92,14 @@ struct sn_context {
     DevBuf<int> nbr;
     DevBuf<CgScalars> scal;
     int cg_hint = 8;
+    // pinned host copies of the device scalars (async read-back) and the
+    // event that marks the latest residual copy
+    struct HostScalars {
+        double r3[4];
+        CgScalars cs;
+    };
+    HostScalars* hpin = nullptr;
+    hipEvent_t res_ev = nullptr;
     // geometric multigrid hierarchy (built on first use)
     bool mg_ready = false;
     int mg_lc = 1, mg_levels = 0;
@@ -434,6 +442,11 @@ int mg_setup(sn_context* c) {
     return 0;
 }
 
+bool bad_dsa_opts(const sn_dsa_opts& o) {
+    return !(o.cg_rtol >= 0) || o.cg_maxit < 1 || (o.mass_kind != 0 && o.mass_kind != 1) ||
+           (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG);
+}
+
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
            sn_dsa_stats* stats) {
     const long n = ctx->nc * ctx->nn;
@@ -463,10 +476,12 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
                           ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->stream));
     if (!bj && (rc = vcycle())) return rc;
-    CgScalars hs{};
+    CgScalars& hs = ctx->hpin->cs;
     int it = 0;
-    // launch batches of iterations and poll the device-side stop flag; the
-    // first batch is sized by the previous call's iteration count
+    // launch batches of iterations and poll the device-side stop flag (one
+    // stream synchronisation when the batch suffices, which also completes
+    // any residual read-back queued before the solve); the first batch is
+    // sized by the previous call's iteration count
     int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit + 1));
     while (true) {
         int nb = std::min(batch, o->cg_maxit + 1 - it);
@@ -498,6 +513,23 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     return 0;
 }
 
+// residual partial sums queued with an asynchronous read-back into pinned
+// host memory; residual_wait completes it (the DSA solve's stream
+// synchronisation usually has already)
+int residual3_async(sn_context* ctx, const double* a, const double* b) {
+    const long n = ctx->nc * ctx->nn;
+    HIPCHK(launch_residual(n, a, b, ctx->rpart.p, ctx->nrpart, ctx->res3.p, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->hpin->r3, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->res_ev, ctx->stream));
+    return 0;
+}
+
+int residual_wait(sn_context* ctx, double out[3]) {
+    HIPCHK(hipEventSynchronize(ctx->res_ev));
+    for (int k = 0; k < 3; ++k) out[k] = ctx->hpin->r3[k];
+    return 0;
+}
+
 int residual3(sn_context* ctx, const double* a, const double* b, double out[3]) {
     const long n = ctx->nc * ctx->nn;
     HIPCHK(launch_residual(n, a, b, ctx->rpart.p, ctx->nrpart, ctx->res3.p, ctx->stream));
@@ -523,6 +555,8 @@ void sn_context_destroy(sn_context* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
+    if (ctx->res_ev) (void)hipEventDestroy(ctx->res_ev);
+    if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     ctx->evpool.clear();
     ctx->dirs.release();
     ctx->w.release();
@@ -715,6 +749,8 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         // sigma_t in the diagonal-major layout of the 2D sweep
         const size_t ns = (size_t)skew2d_elems(mesh->nx, mesh->ny, 1);
         if ((rc = c->sigskew64.ensure(ns)) || (rc = c->sigskew32.ensure(ns))) return rc;
+        HIPCHK(hipMemsetAsync(c->sigskew64.p, 0, ns * sizeof(double), c->stream));
+        HIPCHK(hipMemsetAsync(c->sigskew32.p, 0, ns * sizeof(float), c->stream));
         HIPCHK(launch_skew2d<double>(mesh->nx, mesh->ny, 1, c->sigt.p, c->sigskew64.p, c->stream));
         HIPCHK(launch_skew2d<float>(mesh->nx, mesh->ny, 1, c->sigt32.p, c->sigskew32.p, c->stream));
     } else {
@@ -822,6 +858,8 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     HIPCHK(launch_neighbour_table(dg, c->thick.p, c->slot.p, c->nbr.p, c->stream));
     c->nrpart = (int)std::max<long>(1, std::min<long>((nc * c->nn + 255) / 256, 1024));
     if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
+    HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(sn_context::HostScalars), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&c->res_ev, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(c->stream));
     *out = c.release();
     return SN_OK;
@@ -882,9 +920,7 @@ int sn_dsa_thick_correct(sn_context* ctx, const double* phi_old, const double* p
                          const sn_dsa_opts* opts, sn_dsa_stats* stats) {
     g_err.clear();
     if (!ctx || !phi_old || !phi_si || !phi_out || !opts) return fail(SN_ERR_INVALID, "NULL argument");
-    if (!(opts->cg_rtol >= 0) || opts->cg_maxit < 1 || (opts->mass_kind != 0 && opts->mass_kind != 1) ||
-        (opts->precond != SN_PRECOND_BLOCK_JACOBI && opts->precond != SN_PRECOND_MG))
-        return fail(SN_ERR_INVALID, "bad DSA options");
+    if (bad_dsa_opts(*opts)) return fail(SN_ERR_INVALID, "bad DSA options");
     return do_dsa(ctx, phi_old, phi_si, phi_out, opts, stats);
 }
 
@@ -896,10 +932,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
     if (o->phi_ckpt && o->ckpt_cap < 1) return fail(SN_ERR_INVALID, "ckpt_cap must be >= 1 with phi_ckpt");
     if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
-    if (o->use_dsa && (!(o->dsa.cg_rtol >= 0) || o->dsa.cg_maxit < 1 ||
-                       (o->dsa.mass_kind != 0 && o->dsa.mass_kind != 1) ||
-                       (o->dsa.precond != SN_PRECOND_BLOCK_JACOBI && o->dsa.precond != SN_PRECOND_MG)))
-        return fail(SN_ERR_INVALID, "bad DSA options");
+    if (o->use_dsa && bad_dsa_opts(o->dsa)) return fail(SN_ERR_INVALID, "bad DSA options");
     const long n = ctx->nc * ctx->nn;
     int rc;
     if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->phitmp.ensure(n)) || (rc = ctx->phiprev.ensure(n))) return rc;
@@ -924,7 +957,15 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         }
         verified = false;
         double r3[3];
-        if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
+        // FP64 form after the first iteration: the residual is read back
+        // asynchronously and picked up after the DSA solve, which does not
+        // depend on it (one host synchronisation per iteration)
+        const bool defer = !incr && it > 0;
+        if (defer) {
+            if ((rc = residual3_async(ctx, ctx->phisi.p, phi))) return rc;
+        } else {
+            if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
+        }
         if (it == 0) {
             if (r3[2] == 0.0) {
                 bnorm = std::sqrt(r3[1]);
@@ -937,25 +978,23 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
             }
             if (bnorm == 0.0) bnorm = 1.0;
         }
-        const double res32 = std::sqrt(r3[0]) / bnorm;
-        const double refresh_at = 1e-4;
-        if (incr && (res32 <= o->tol || (!refreshed && res32 <= refresh_at && o->tol < refresh_at))) {
-            // FP64 sweeps in the FP32 form: once when the residual first
-            // drops below 1e-4 (this discards the FP32 rounding accumulated
-            // while the increments were large) and whenever it meets tol (the
-            // form may only stop on an exact residual).  phi_SI is recomputed
-            // from phi with one FP64 sweep and the increments continue from it.
-            refreshed = true;
-            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->phisi.p, 0))) return rc;
-            if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
-            verified = true;
-            if (stats) stats->fp64_checks += 1;
-        }
-        if (incr)
+        if (incr) {
+            const double res32 = std::sqrt(r3[0]) / bnorm;
+            const double refresh_at = 1e-4;
+            if (res32 <= o->tol || (!refreshed && res32 <= refresh_at && o->tol < refresh_at)) {
+                // FP64 sweeps in the FP32 form: once when the residual first
+                // drops below 1e-4 (this discards the FP32 rounding accumulated
+                // while the increments were large) and whenever it meets tol (the
+                // form may only stop on an exact residual).  phi_SI is recomputed
+                // from phi with one FP64 sweep and the increments continue from it.
+                refreshed = true;
+                if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->phisi.p, 0))) return rc;
+                if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
+                verified = true;
+                if (stats) stats->fp64_checks += 1;
+            }
             HIPCHK(hipMemcpyAsync(ctx->phiprev.p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-        const double res = std::sqrt(r3[0]) / bnorm;
-        if (stats && stats->res_hist) stats->res_hist[it] = res;
-        if (first < 0) first = res;
+        }
         int cgi = 0;
         if (o->use_dsa) {
             sn_dsa_stats ds{};
@@ -969,6 +1008,10 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         } else {
             HIPCHK(hipMemcpyAsync(phi, ctx->phisi.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         }
+        if (defer && (rc = residual_wait(ctx, r3))) return rc;
+        const double res = std::sqrt(r3[0]) / bnorm;
+        if (stats && stats->res_hist) stats->res_hist[it] = res;
+        if (first < 0) first = res;
         if (stats && stats->cg_hist) stats->cg_hist[it] = cgi;
         if (o->phi_ckpt)
             HIPCHK(hipMemcpyAsync(o->phi_ckpt + (size_t)(it % o->ckpt_cap) * n, phi, n * sizeof(double),

@@ -54,7 +54,12 @@ hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_
 template <typename T>
 hipError_t launch_source_skew2d(int nx, int ny, const double* sigma_s, const double* phi, const double* phi_prev,
                                 const double* q, T* out, hipStream_t st);
-inline long skew2d_elems(int nx, int ny, int nn) { return 4L * ((ny + 63) / 64) * (nx + 63) * 64 * nn; }
+// (plus SKEW2D_TAIL zero diagonals after the last block: the sweep's
+// prefetch runs up to that far past a block's last diagonal)
+constexpr int SKEW2D_TAIL = 16;
+inline long skew2d_elems(int nx, int ny, int nn) {
+    return (4L * ((ny + 63) / 64) * (nx + 63) + SKEW2D_TAIL) * 64 * nn;
+}
 
 // scalar-flux kernels (flux.hip)
 template <typename T>

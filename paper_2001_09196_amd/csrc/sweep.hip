@@ -8,8 +8,8 @@
 //   column t - row.  The x inflow of a cell is the previous cell of the same
 //   lane (registers); the y inflow is the top face of the row below, taken
 //   from lane r - 1 by a DPP wave shift, or from the previous wave through
-//   LDS (one barrier per step).  Rows beyond ROWS2D are processed in chunks, one
-//   launch per chunk, chained through a y-face buffer.
+//   an LDS ring (one barrier per B2D steps).  Rows beyond ROWS2D are processed
+//   in chunks, one launch per chunk, chained through a y-face buffer.
 //
 // 3D (throughput bound): tiles of TX x 4 x 4 cells in the reflected frame of
 //   each direction; one wave per (tile, group of four directions with the
@@ -23,20 +23,23 @@
 // Node order in memory is global (a + 2b + 4c); in the reflected frame node
 // n_local = n_global ^ M with M = rx + 2 ry + 4 rz, a compile-time constant
 // of each kernel body.
+#include <type_traits>
+
 #include "sn_kernels.hpp"
 
 namespace sn {
 
-// v of lane - 1 across the whole wave (DPP wave_shr:1); lane 0 receives 0
-__device__ __forceinline__ double wave_shr1(double v) {
-    const long long x = __double_as_longlong(v);
+// v of lane - 1 across the wave; lane 0 receives `old`
+__device__ __forceinline__ double wave_shr1_old(double v, double old) {
+    const long long x = __double_as_longlong(v), y = __double_as_longlong(old);
     int lo = (int)(x & 0xffffffffLL), hi = (int)(x >> 32);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, true);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, true);
+    int olo = (int)(y & 0xffffffffLL), ohi = (int)(y >> 32);
+    lo = __builtin_amdgcn_update_dpp(olo, lo, 0x138, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(ohi, hi, 0x138, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ float wave_shr1(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+__device__ __forceinline__ float wave_shr1_old(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 
 // ---------------------------------------------------------------------------
@@ -200,100 +203,161 @@ struct In2 {
     T sig, yb0, yb1;
 };
 
+// The LDS buffers reach the sweep bodies as plain pointers; these casts give
+// them back the LDS address space, so that the compiler emits LDS
+// instructions (ds_read / ds_write) rather than flat ones, which wait on both
+// the memory and the LDS counters.
+template <typename T>
+using lds_t = __attribute__((address_space(3))) T;
+using dvec2 = double __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ lds_t<T>* as_lds(T* p) {
+    return (lds_t<T>*)p;
+}
+
 // Pipeline constants of the 2D sweep: the input prefetch ring depth, and the
-// number of steps between workgroup barriers.  Wave w runs B2D w steps
-// behind the plain diagonal schedule, so the top row of wave w - 1 produces
-// the value that the bottom row of wave w needs B2D + 1 steps before it is
-// needed.  The values travel through a ring of 2 B2D LDS slots; with one
-// barrier per B2D steps, every window of B2D consecutive steps holds exactly
-// one barrier, which orders each write before its read (done one step
-// early, to hide the LDS latency) and each read before the slot is
-// rewritten.
+// number of steps between workgroup barriers (also the unroll of the step
+// loop).  Wave w runs B2D w steps behind the plain diagonal schedule, so the
+// top row of wave w - 1 produces the value that the bottom row of wave w
+// needs B2D + 1 steps before it is needed.  The values travel through a ring
+// of 2 B2D LDS slots; with one barrier per B2D steps, every window of B2D
+// consecutive steps holds exactly one barrier, which orders each write before
+// its read (done one step early, to hide the LDS latency) and each read
+// before the slot is rewritten.
 constexpr int R2D = 4;
 constexpr int B2D = 8;
 
-// Per step a wave reads its cells' source and sigma_t as contiguous runs of
-// the diagonal-major arrays.  In FP64 the four psi values of a lane (32
-// bytes) go through a double-buffered LDS stage so that two lanes write the
-// two 16-byte halves of one cell's block (one cache line per cell per store
-// instruction instead of one per lane); the write-out of step t happens
-// during step t + 1, behind its arithmetic.
-template <typename T, int M>
-__device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T ax, T ay,
+// LDS of one 2D sweep workgroup.
+template <typename T>
+struct Lds2 {
+    // FP64: double-buffered psi stage, see sweep2d_wave
+    T stage[sizeof(T) == 8 ? 2 : 1][ROWS2D][4];
+    // y outflow of the top row of each wave, one slot per step
+    T ring[2 * B2D][ROWS2D / 64][2];
+    // every lane writes the ring; the lanes below the top one write here (one
+    // pair per lane, moved by the same slot offset), so the write needs no
+    // lane mask
+    T discard[64 + (2 * B2D - 1) * (ROWS2D / 64)][2];
+};
+
+// Roles of a wave in the 2D sweep: the bottom wave takes its y inflow from
+// the chunk's inflow row in memory, the others from the wave below through
+// the LDS ring; the top wave of a chunk that has a chunk above also writes
+// the y outflow of its top row to memory.
+enum { W2_FIRST = 0, W2_MID = 1, W2_TOPOUT = 2 };
+
+// One wave of the 2D sweep.  Lane l owns row r = 64 w + l of the chunk and,
+// at step t, cell il = t - r - B2D w of it.  The wave is busy only in its
+// window of LEN steps starting at ts = (64 + B2D) w, in which it reads
+// diagonal k = t - ts of its row block, a contiguous run of the
+// diagonal-major arrays; outside the window it only takes part in the
+// barriers.  Cells outside the row (il < 0 or il >= nx) are computed on
+// padding and discarded: their y outflow reaches only lanes that are outside
+// their row as well, their x outflow is not kept before the row starts, and
+// their psi stores are masked.
+// In FP64 the four psi values of a lane (32 bytes) go through a
+// double-buffered LDS stage so that two lanes write the two 16-byte halves
+// of one cell's block (one cache line per cell per store instruction instead
+// of one per lane); the write-out of step k happens during step k + 1,
+// behind its arithmetic.  Store addresses move by a fixed stride per step.
+template <typename T, int M, int ROLE>
+__device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T ax, T ay,
                                              const T* __restrict__ sigq, const T* __restrict__ srcq,
                                              const T* __restrict__ xf, const T* __restrict__ yin_buf,
                                              T* __restrict__ yout_buf, int row0, int nrows, T* __restrict__ psi,
-                                             T (*lds)[ROWS2D / 64][2], T (*stage)[ROWS2D][4]) {
+                                             Lds2<T>* L, int wave, int nw) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int PR = ROWS2D / 64;  // ring pairs per slot
+    const int lane = threadIdx.x & 63;
     const int r = wave * 64 + lane;
     const bool rowok = r < nrows;
     const int jl = row0 + min(r, nrows - 1);
     const int j = ry ? ny - 1 - jl : jl;
-    const long rowbase = (long)j * nx;
-    const bool top = yout_buf != nullptr && r == nrows - 1;
     const int ns = nx + 63;
-    // this wave's row block in the diagonal-major arrays
+    const int LEN = (ns + 1 + B2D - 1) / B2D * B2D;  // >= ns + 1: the last step writes out psi
+    const int ts = wave * (64 + B2D);
+    const int NT = (nw - 1) * (64 + B2D) + LEN;
+    // this wave's row block in the diagonal-major arrays (uniform) and the lane's column
     const long blk = (long)((row0 >> 6) + wave) * ns;
+    const T* sbase = srcq + blk * 256;
+    const T* gbase = sigq + blk * 64;
     T xin0 = xf[(long)jl * 2 + 0];
     T xin1 = xf[(long)jl * 2 + 1];
     T yo0 = T(0), yo1 = T(0);
-    T rin0 = T(0), rin1 = T(0);  // y inflow of the bottom lane from the wave below, read one step early
-    const int nw = (nrows + 63) / 64;
-    const int lag = wave * B2D;
-    const int nsteps = nx + nrows - 1 + (nw - 1) * B2D;
-    // inputs of step t: diagonal s = t - lag - 64 wave of the row block (the
-    // same for the whole wave); the chunk's inflow row is read at one address
-    // by all lanes
-    auto fetch = [&](int t, In2<T>& v) {
-        const int ilc = min(max(t - lag, 0), nx - 1);
-        v.yb0 = yin_buf[(long)ilc * 2 + 0];
-        v.yb1 = yin_buf[(long)ilc * 2 + 1];
-        const int sd = min(max(t - lag - 64 * wave, 0), ns - 1);
-        const long e = (blk + sd) * 64 + lane;
-        v.s = load4(srcq + e * 4);
-        v.sig = sigq[e];
-    };
-    // psi write-out of step t from stage buffer t & 1 (FP64): lane pair
-    // (2 q, 2 q + 1) stores the two halves of cell q, q = 32 h + lane / 2
-    auto write_half = [&](int t, int h, double2 v) {
-        const int q = h * 32 + (lane >> 1), o = lane & 1;
-        const int rq = wave * 64 + q;
-        const int ilq = t - rq - lag;
-        if (rq < nrows && ilq >= 0 && ilq < nx) {
-            const int jq = ry ? ny - 1 - (row0 + rq) : row0 + rq;
-            const int iq = rx ? nx - 1 - ilq : ilq;
-            const long cq = (long)jq * nx + iq;
-            *reinterpret_cast<double2*>(psi + (cq * ndirs + d) * 4 + 2 * o) = v;
+    T rin0 = T(0), rin1 = T(0);  // y inflow of lane 0 from the wave below, read one step early
+    const lds_t<T>* rd = as_lds(&L->ring[0][max(wave - 1, 0)][0]);
+    lds_t<T>* wr = lane == 63 ? as_lds(&L->ring[0][wave][0]) : as_lds(&L->discard[lane][0]);
+    if constexpr (ROLE != W2_FIRST) {
+        for (int b = 0; b + 1 < ts / B2D; ++b) __syncthreads();
+        // the value for step ts, written by wave - 1 at step ts - 1 - B2D
+        const int sl = (ts - 1 - B2D) & (2 * B2D - 1);
+        rin0 = rd[sl * PR * 2 + 0];
+        rin1 = rd[sl * PR * 2 + 1];
+        __syncthreads();
+    }
+    auto fetch = [&](int k, In2<T>& v) {
+        v.s = load4(sbase + (long)k * 256 + lane * 4);
+        v.sig = gbase[(long)k * 64 + lane];
+        if constexpr (ROLE == W2_FIRST) {
+            const int c = min(k, nx - 1);
+            v.yb0 = yin_buf[(long)c * 2 + 0];
+            v.yb1 = yin_buf[(long)c * 2 + 1];
         }
     };
-    auto read_half = [&](int t, int h) {
-        const int q = h * 32 + (lane >> 1), o = lane & 1;
-        return *reinterpret_cast<const double2*>(&stage[t & 1][wave * 64 + q][2 * o]);
-    };
+    // psi store addresses at k = 0, moved by sgn_step per step; a store is
+    // done when (unsigned)(k - v) < nx (v = a huge negative for rows past nrows)
+    const long dstep = (long)ndirs * 4;
+    const long sgn_step = rx ? -dstep : dstep;
+    constexpr int OFF = -(1 << 30);
+    T* wp0;
+    T* wp1;
+    int v0, v1;
+    const lds_t<T>* st0 = nullptr;
+    const lds_t<T>* st1 = nullptr;
+    if constexpr (sizeof(T) == 8) {
+        // lane pair (2 q, 2 q + 1) stores the halves o = lane & 1 of cell q =
+        // 32 h + lane / 2 of the wave (step k writes out the cells of step k - 1)
+        auto half = [&](int h, T*& wp, int& v, const lds_t<T>*& sp) {
+            const int q = 32 * h + (lane >> 1), o = lane & 1, rq = wave * 64 + q;
+            const int jq0 = row0 + min(rq, nrows - 1);
+            const int jq = ry ? ny - 1 - jq0 : jq0;
+            const long i0 = rx ? (long)(nx + q) : (long)(-1 - q);
+            wp = psi + ((long)jq * nx * ndirs + d) * 4 + 2 * o + i0 * dstep;
+            v = rq < nrows ? 1 + q : OFF;
+            sp = as_lds(&L->stage[0][rq][2 * o]);
+        };
+        half(0, wp0, v0, st0);
+        half(1, wp1, v1, st1);
+    } else {
+        const long i0 = rx ? (long)(nx - 1 + lane) : (long)(-lane);
+        wp0 = psi + ((long)j * nx * ndirs + d) * 4 + i0 * dstep;
+        v0 = rowok ? lane : OFF;
+        wp1 = nullptr;
+        v1 = OFF;
+    }
+    lds_t<T>* stw = as_lds(&L->stage[0][r][0]);
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay;
-    auto step = [&](int t, In2<T>& use, In2<T>& fill) {
-        const int il = t - r - lag;
-        fetch(t + R2D - 1, fill);
-        double2 prev0{}, prev1{};
+    // step k of the window (slot base sb = (ts + k - kk) & B2D, kk = k mod B2D)
+    auto step = [&](int k, int sb, auto kkc, In2<T>& use, In2<T>& fill) {
+        constexpr int kk = decltype(kkc)::value;
+        fetch(k + R2D - 1, fill);
+        dvec2 prev0{}, prev1{};
         if constexpr (sizeof(T) == 8) {
-            prev0 = read_half(max(t - 1, 0), 0);
-            prev1 = read_half(max(t - 1, 0), 1);
+            constexpr int par = (kk + 1) & 1;  // stage buffer of step k - 1
+            prev0 = *reinterpret_cast<const lds_t<dvec2>*>(st0 + par * ROWS2D * 4);
+            prev1 = *reinterpret_cast<const lds_t<dvec2>*>(st1 + par * ROWS2D * 4);
         }
-        // y inflow: the lane below (DPP), the wave below (LDS ring), or the
-        // inflow row of the chunk
-        T yi0 = wave_shr1(yo0), yi1 = wave_shr1(yo1);
-        if (lane == 0) {
-            yi0 = wave == 0 ? use.yb0 : rin0;
-            yi1 = wave == 0 ? use.yb1 : rin1;
+        // y inflow: the lane below (DPP); lane 0 keeps the DPP's old value,
+        // the wave below's top row (ring) or the chunk's inflow row
+        const T old0 = ROLE == W2_FIRST ? use.yb0 : rin0;
+        const T old1 = ROLE == W2_FIRST ? use.yb1 : rin1;
+        const T yi0 = wave_shr1_old(yo0, old0), yi1 = wave_shr1_old(yo1, old1);
+        if constexpr (ROLE != W2_FIRST) {
+            // the value for step k + 1, written by wave - 1 B2D steps ago
+            const int sl = (sb ^ B2D) + kk;
+            rin0 = rd[sl * PR * 2 + 0];
+            rin1 = rd[sl * PR * 2 + 1];
         }
-        if (lane == 0 && wave > 0) {
-            // value for step t + 1, written by wave - 1 at step t - B2D
-            const int sl = (t - B2D) & (2 * B2D - 1);
-            rin0 = lds[sl][wave - 1][0];
-            rin1 = lds[sl][wave - 1][1];
-        }
-        const bool active = rowok && il >= 0 && il < nx;
         T g[4], u[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) g[n] = use.s.v[n ^ M];
@@ -307,48 +371,53 @@ __device__ __forceinline__ void sweep2d_body(int nx, int ny, int ndirs, int d, T
         g[1] = fma(ay4, yi1, g[1]);
         g[3] = fma(-ay2, yi1, g[3]);
         cell_solve2(g, ax, ay, use.sig, u);
-        xin0 = active ? u[1] : xin0;
-        xin1 = active ? u[3] : xin1;
-        yo0 = active ? u[2] : yo0;
-        yo1 = active ? u[3] : yo1;
+        const bool started = k >= lane;  // il >= 0: keep the row's x inflow until then
+        xin0 = started ? u[1] : xin0;
+        xin1 = started ? u[3] : xin1;
+        yo0 = u[2];
+        yo1 = u[3];
         if constexpr (sizeof(T) == 8) {
             // the unconditional stage write consumes the solve, so the solve
-            // stays ahead of the (branchy) write-out of the previous step and
-            // the stage reads of that step complete behind the arithmetic
-            store4(stage[t & 1][r], u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
-            if (t > 0) {
-                write_half(t - 1, 0, prev0);
-                write_half(t - 1, 1, prev1);
-            }
+            // stays ahead of the write-out of the previous step
+            constexpr int par = kk & 1;
+            lds_t<dvec2>* sw = reinterpret_cast<lds_t<dvec2>*>(stw + par * ROWS2D * 4);
+            sw[0] = dvec2{u[0 ^ M], u[1 ^ M]};
+            sw[1] = dvec2{u[2 ^ M], u[3 ^ M]};
+            if ((unsigned)(k - v0) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp0) = prev0;
+            if ((unsigned)(k - v1) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp1) = prev1;
+            wp0 += sgn_step;
+            wp1 += sgn_step;
         } else {
-            if (active) {
-                const int i = rx ? nx - 1 - il : il;
-                store4(psi + ((rowbase + i) * ndirs + d) * 4, u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            if ((unsigned)(k - v0) < (unsigned)nx) store4(wp0, u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            wp0 += sgn_step;
+        }
+        if constexpr (ROLE == W2_TOPOUT) {
+            // lane 63 of the top wave is the chunk's top row (the chunk is full)
+            if (lane == 63 && (unsigned)(k - 63) < (unsigned)nx) {
+                yout_buf[(long)(k - 63) * 2 + 0] = yo0;
+                yout_buf[(long)(k - 63) * 2 + 1] = yo1;
             }
         }
-        if (top && active) {
-            yout_buf[(long)il * 2 + 0] = yo0;
-            yout_buf[(long)il * 2 + 1] = yo1;
-        }
-        if (lane == 63) {
-            const int sl = t & (2 * B2D - 1);
-            lds[sl][wave][0] = yo0;
-            lds[sl][wave][1] = yo1;
-        }
-        if ((t + 1) % B2D == 0) __syncthreads();
+        const int slw = sb + kk;
+        wr[slw * PR * 2 + 0] = yo0;
+        wr[slw * PR * 2 + 1] = yo1;
     };
     In2<T> sl[R2D];
 #pragma unroll
     for (int k = 0; k + 1 < R2D; ++k) fetch(k, sl[k]);
-    for (int t = 0; t < nsteps; t += R2D) {
-#pragma unroll
-        for (int k = 0; k < R2D; ++k)
-            if (t + k < nsteps) step(t + k, sl[k], sl[(k + R2D - 1) % R2D]);
+    for (int k0 = 0; k0 < LEN; k0 += B2D) {
+        const int sb = (ts + k0) & B2D;
+        step(k0 + 0, sb, std::integral_constant<int, 0>{}, sl[0], sl[3]);
+        step(k0 + 1, sb, std::integral_constant<int, 1>{}, sl[1], sl[0]);
+        step(k0 + 2, sb, std::integral_constant<int, 2>{}, sl[2], sl[1]);
+        step(k0 + 3, sb, std::integral_constant<int, 3>{}, sl[3], sl[2]);
+        step(k0 + 4, sb, std::integral_constant<int, 4>{}, sl[0], sl[3]);
+        step(k0 + 5, sb, std::integral_constant<int, 5>{}, sl[1], sl[0]);
+        step(k0 + 6, sb, std::integral_constant<int, 6>{}, sl[2], sl[1]);
+        step(k0 + 7, sb, std::integral_constant<int, 7>{}, sl[3], sl[2]);
+        __syncthreads();
     }
-    if constexpr (sizeof(T) == 8) {
-        write_half(nsteps - 1, 0, read_half(nsteps - 1, 0));
-        write_half(nsteps - 1, 1, read_half(nsteps - 1, 1));
-    }
+    for (int t = ts + LEN; t < NT; t += B2D) __syncthreads();
 }
 
 // blockIdx.x: position in dir_order (directions of one quadrant are placed
@@ -362,8 +431,7 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
                                                        const T* __restrict__ srcskew, const T* __restrict__ xf,
                                                        long xstride, T* __restrict__ ybuf, long ystride, int chunk,
                                                        int nchunk, int row0, int nrows, T* __restrict__ psi) {
-    __shared__ T lds[2 * B2D][ROWS2D / 64][2];
-    __shared__ __align__(16) T stage[sizeof(T) == 8 ? 2 : 1][ROWS2D][4];
+    __shared__ __align__(16) Lds2<T> L;
     const int d = dir_order[blockIdx.x];
     const DirInfo di = dirs[d];
     const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
@@ -374,9 +442,15 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
     const T* xfd = xf + d * xstride;
     const T* yin = ybuf + d * ystride + (long)chunk * nx * 2;
     T* yout = (chunk + 1 < nchunk) ? ybuf + d * ystride + (long)(chunk + 1) * nx * 2 : nullptr;
-#define SN_CASE2(MM)                                                                                           \
-    case MM:                                                                                                   \
-        sweep2d_body<T, MM>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, lds, stage); \
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = (nrows + 63) / 64;
+#define SN_WAVE2(MM, RR) \
+    sweep2d_wave<T, MM, RR>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, &L, wave, nw)
+#define SN_CASE2(MM)                                      \
+    case MM:                                              \
+        if (wave == 0) SN_WAVE2(MM, W2_FIRST);            \
+        else if (yout && wave == nw - 1) SN_WAVE2(MM, W2_TOPOUT); \
+        else SN_WAVE2(MM, W2_MID);                        \
         break;
     switch (m) {
         SN_CASE2(0)
@@ -385,6 +459,7 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
         SN_CASE2(3)
     }
 #undef SN_CASE2
+#undef SN_WAVE2
 }
 
 // ---------------------------------------------------------------------------
@@ -457,16 +532,7 @@ __device__ __forceinline__ double rows_sum(double v) {
 // fused sweep + moment: steps per workgroup barrier
 constexpr int RF = 4;
 
-// The LDS buffers reach the sweep bodies as plain pointers; these casts give
-// them back the LDS address space, so that the compiler emits LDS
-// instructions (ds_read / ds_write) rather than flat ones, which wait on both
-// the memory and the LDS counters.
-template <typename T>
-using lds_t = __attribute__((address_space(3))) T;
-template <typename T>
-__device__ __forceinline__ lds_t<T>* as_lds(T* p) {
-    return (lds_t<T>*)p;
-}
+
 
 // FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
 // stored; every step the lanes' w_d psi (FP64) is summed over the four
