@@ -114,9 +114,21 @@ struct sn_context {
     DevBuf<double> xf64, yf64, zf64, src64, sink64, sigskew64, srcskew64;
     DevBuf<float> xf32, yf32, zf32, src32, sink32, sigskew32, srcskew32;
     // source iteration workspace
-    DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3, phioct;
+    DevBuf<double> psi64, phisi, phitmp, phiprev, rpart, res3, phioct, fpart;
     DevBuf<float> psi32;
     int nrpart = 1;
+    // Face buffers of each precision hold the inflow of the last
+    // initialisation (slot 0 is never overwritten by a sweep).  Within one
+    // source-iteration call, where the inflow array does not change, a sweep
+    // with the same inflow pointer and transpose flag skips the
+    // initialisation.
+    struct FaceKey {
+        const double* inflow = nullptr;
+        int transpose = 0;
+        bool valid = false;
+    };
+    FaceKey fkey[2];  // [FP64, FP32]
+    bool face_reuse = false;
     // optional event timing of the sweep kernels and of the DSA solves
     int timing = 0;
     std::vector<hipEvent_t> evpool;
@@ -157,6 +169,17 @@ long inflow_size(const sn_mesh* m) {
 }
 
 template <typename T>
+int init_faces(sn_context* ctx, const double* inflow, int transpose, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf) {
+    sn_context::FaceKey& k = ctx->fkey[sizeof(T) == 8 ? 0 : 1];
+    if (ctx->face_reuse && k.valid && k.inflow == inflow && k.transpose == transpose) return 0;
+    HIPCHK(launch_init_faces<T>(ctx->sg, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    k.inflow = inflow;
+    k.transpose = transpose;
+    k.valid = true;
+    return 0;
+}
+
+template <typename T>
 int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
                int transpose, T* psi, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, DevBuf<T>& sink,
                const T* sigt, DevBuf<T>& srcskew, const T* sigskew) {
@@ -181,7 +204,7 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
         HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
         sweep_src = src.p;
     }
-    HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    if ((rc = init_faces<T>(ctx, inflow, transpose, xf, yf, zf))) return rc;
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, xf.p, yf.p, zf.p, ctx->tiles.p,
@@ -203,13 +226,16 @@ int do_sweep(sn_context* ctx, const double* phi, const double* phi_prev, const d
                              ctx->src32, ctx->sink32, ctx->sigt32.p, ctx->srcskew32, ctx->sigskew32.p);
 }
 
-int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, int accumulate = 0) {
+// res_ref != nullptr: also the residual partial sums against res_ref into
+// ctx->fpart (moment_blocks(nc) blocks)
+int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, int accumulate = 0,
+              const double* res_ref = nullptr) {
     if (prec == SN_FP64)
         HIPCHK(launch_moment<double>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, (const double*)psi, phi, accumulate,
-                                     ctx->stream));
+                                     res_ref, ctx->fpart.p, ctx->stream));
     else
         HIPCHK(launch_moment<float>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, (const float*)psi, phi, accumulate,
-                                    ctx->stream));
+                                    res_ref, ctx->fpart.p, ctx->stream));
     return 0;
 }
 
@@ -217,7 +243,7 @@ int do_moment(sn_context* ctx, const void* psi, sn_precision prec, double* phi, 
 template <typename T>
 int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q,
                       const double* inflow, int transpose, double* phi_out, int accumulate, DevBuf<T>& xf,
-                      DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, const T* sigt) {
+                      DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, const T* sigt, const double* res_ref) {
     const SweepGeom& g = ctx->sg;
     int rc;
     if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
@@ -226,11 +252,12 @@ int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev
     if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
     if ((rc = ctx->phioct.ensure((size_t)g.nclasses * ctx->nc * 8))) return rc;
     HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
-    HIPCHK(launch_init_faces<T>(g, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    if ((rc = init_faces<T>(ctx, inflow, transpose, xf, yf, zf))) return rc;
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
-                                  ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, ctx->stream));
+                                  ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, res_ref, ctx->fpart.p,
+                                  ctx->stream));
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->sweep_ev.emplace_back(e0, e1);
@@ -240,16 +267,24 @@ int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev
 
 // phi_out (+)= sum_d w_d L_d^{-1}(...) for source iteration: in 3D the fused
 // kernels (psi never reaches memory); in 2D a psi-writing sweep into the
-// context's psi workspace followed by the moment
+// context's psi workspace followed by the moment.  res_ref != nullptr: the
+// last kernel also writes the residual partial sums of phi_out against
+// res_ref into ctx->fpart; returns their block count in *res_nparts.
 int do_sweep_flux(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
-                  int transpose, sn_precision prec, double* phi_out, int accumulate) {
+                  int transpose, sn_precision prec, double* phi_out, int accumulate, const double* res_ref = nullptr,
+                  int* res_nparts = nullptr) {
     int rc;
+    if (res_ref) {
+        const int nb = std::max(moment_blocks(ctx->nc), octant_sum_blocks(ctx->nc));
+        if ((rc = ctx->fpart.ensure(3 * (size_t)nb))) return rc;
+        *res_nparts = ctx->mesh.dim == 3 ? octant_sum_blocks(ctx->nc) : moment_blocks(ctx->nc);
+    }
     if (ctx->mesh.dim == 3) {
         if (prec == SN_FP64)
             return sweep_flux3d_impl<double>(ctx, phi, phi_prev, q, inflow, transpose, phi_out, accumulate,
-                                             ctx->xf64, ctx->yf64, ctx->zf64, ctx->src64, ctx->sigt.p);
+                                             ctx->xf64, ctx->yf64, ctx->zf64, ctx->src64, ctx->sigt.p, res_ref);
         return sweep_flux3d_impl<float>(ctx, phi, phi_prev, q, inflow, transpose, phi_out, accumulate, ctx->xf32,
-                                        ctx->yf32, ctx->zf32, ctx->src32, ctx->sigt32.p);
+                                        ctx->yf32, ctx->zf32, ctx->src32, ctx->sigt32.p, res_ref);
     }
     const size_t npsi = (size_t)ctx->nc * ctx->ndirs * ctx->nn;
     void* psi;
@@ -261,7 +296,7 @@ int do_sweep_flux(sn_context* ctx, const double* phi, const double* phi_prev, co
         psi = ctx->psi32.p;
     }
     if ((rc = do_sweep(ctx, phi, phi_prev, q, inflow, transpose, prec, psi))) return rc;
-    return do_moment(ctx, psi, prec, phi_out, accumulate);
+    return do_moment(ctx, psi, prec, phi_out, accumulate, res_ref);
 }
 
 // phi_out = phi_si + P_T delta; returns an SN code; fills stats
@@ -447,12 +482,18 @@ bool bad_dsa_opts(const sn_dsa_opts& o) {
            (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG);
 }
 
+// res_part / res_nparts: source-iteration residual partial sums to reduce in
+// the solve's first kernel into ctx->res3 and the pinned ctx->hpin->r3 (the
+// solve's stream synchronisation then also completes that read-back)
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
-           sn_dsa_stats* stats) {
+           sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0) {
     const long n = ctx->nc * ctx->nn;
     if (ctx->nthick == 0) {
+        if (res_part)
+            HIPCHK(launch_residual_final(res_nparts, res_part, ctx->res3.p, ctx->hpin->r3, ctx->stream));
         if (phi_out != phi_si)
             HIPCHK(hipMemcpyAsync(phi_out, phi_si, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        if (res_part) HIPCHK(hipStreamSynchronize(ctx->stream));
         if (stats) {
             stats->cg_iters = 0;
             stats->cg_relres = 0.0;
@@ -465,35 +506,47 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     int rc;
     const int bj = o->precond == SN_PRECOND_MG ? 0 : 1;
     if (!bj && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
+    CgScalars& hs = ctx->hpin->cs;
     auto vcycle = [&]() -> int {
         HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cr.p,
                                 ctx->cz0.p, ctx->cres.p, ctx->cz.p, ctx->mg, ctx->mg_lc, ctx->mg_omega0,
                                 ctx->partb.p, ctx->nparts, ctx->scal.p, ctx->stream));
         return 0;
     };
+    auto apply = [&](int it) -> int {
+        HIPCHK(launch_cg_apply(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->cz.p, ctx->cp.p,
+                               ctx->cp1.p, ctx->cq.p, ctx->parta.p, ctx->partb.p, ctx->nparts, ctx->scal.p, &hs,
+                               o->cg_rtol, o->cg_maxit, it, ctx->stream));
+        return 0;
+    };
+    auto update = [&](int it) -> int {
+        HIPCHK(launch_cg_update(g, ctx->binv.p, ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cp1.p, ctx->cq.p,
+                                ctx->parta.p, ctx->partb.p, ctx->nparts, ctx->scal.p, &hs, it, bj, ctx->stream));
+        if (!bj) return vcycle();
+        return 0;
+    };
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
-    HIPCHK(launch_cg_init(ctx->scal.p, ctx->stream));
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
-                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->stream));
+                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->scal.p, &hs,
+                          res_part, res_nparts, ctx->res3.p, ctx->hpin->r3, ctx->stream));
     if (!bj && (rc = vcycle())) return rc;
-    CgScalars& hs = ctx->hpin->cs;
-    int it = 0;
-    // launch batches of iterations and poll the device-side stop flag (one
-    // stream synchronisation when the batch suffices, which also completes
-    // any residual read-back queued before the solve); the first batch is
-    // sized by the previous call's iteration count
-    int batch = std::max(1, std::min(ctx->cg_hint + 1, o->cg_maxit + 1));
+    // Batches of iterations, each ended by the stop test of the next
+    // iteration (its apply kernel), then one stream synchronisation and a look
+    // at the stop flags, which the kernels also write to pinned host memory.
+    // The first batch is sized by the previous call's iteration count; when
+    // a batch does not suffice, the next one starts with the update that the
+    // last test left pending.
+    int it = 0;  // iteration whose apply kernel runs next
+    bool pending = false;
+    int batch = std::max(0, std::min(ctx->cg_hint, o->cg_maxit));
     while (true) {
-        int nb = std::min(batch, o->cg_maxit + 1 - it);
-        for (int b = 0; b < nb; ++b) {
-            HIPCHK(launch_cg_iteration(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, ctx->cx.p,
-                                       ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cp1.p, ctx->cq.p, ctx->parta.p,
-                                       ctx->partb.p, ctx->nparts, ctx->scal.p, o->cg_rtol, o->cg_maxit, it + b, bj,
-                                       ctx->stream));
-            if (!bj && it + b < o->cg_maxit && (rc = vcycle())) return rc;
-        }
-        it += nb;
-        HIPCHK(hipMemcpyAsync(&hs, ctx->scal.p, sizeof(CgScalars), hipMemcpyDeviceToHost, ctx->stream));
+        if (pending && (rc = update(it - 1))) return rc;
+        const int nb = std::min(batch, o->cg_maxit - it);
+        for (int b = 0; b < nb; ++b, ++it)
+            if ((rc = apply(it)) || (rc = update(it))) return rc;
+        if ((rc = apply(it))) return rc;
+        ++it;
+        pending = true;
         HIPCHK(hipStreamSynchronize(ctx->stream));
         if (hs.done || it > o->cg_maxit) break;
         batch = 4;
@@ -510,23 +563,6 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         stats->n_thick_cells = ctx->nthick;
     }
     if (hs.breakdown) return fail(SN_ERR_CG_BREAKDOWN, "diffusion CG breakdown (p^T D p <= 0)");
-    return 0;
-}
-
-// residual partial sums queued with an asynchronous read-back into pinned
-// host memory; residual_wait completes it (the DSA solve's stream
-// synchronisation usually has already)
-int residual3_async(sn_context* ctx, const double* a, const double* b) {
-    const long n = ctx->nc * ctx->nn;
-    HIPCHK(launch_residual(n, a, b, ctx->rpart.p, ctx->nrpart, ctx->res3.p, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->hpin->r3, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipEventRecord(ctx->res_ev, ctx->stream));
-    return 0;
-}
-
-int residual_wait(sn_context* ctx, double out[3]) {
-    HIPCHK(hipEventSynchronize(ctx->res_ev));
-    for (int k = 0; k < 3; ++k) out[k] = ctx->hpin->r3[k];
     return 0;
 }
 
@@ -557,6 +593,7 @@ void sn_context_destroy(sn_context* ctx) {
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->res_ev) (void)hipEventDestroy(ctx->res_ev);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+    ctx->fpart.release();
     ctx->evpool.clear();
     ctx->dirs.release();
     ctx->w.release();
@@ -933,6 +970,16 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     if (o->phi_ckpt && o->ckpt_cap < 1) return fail(SN_ERR_INVALID, "ckpt_cap must be >= 1 with phi_ckpt");
     if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
     if (o->use_dsa && bad_dsa_opts(o->dsa)) return fail(SN_ERR_INVALID, "bad DSA options");
+    // the inflow array is fixed for the whole call: face buffers are filled
+    // once per precision (and transpose flag) and reused by later sweeps
+    struct FaceReuse {
+        sn_context* c;
+        explicit FaceReuse(sn_context* c_) : c(c_) {
+            c->fkey[0].valid = c->fkey[1].valid = false;
+            c->face_reuse = true;
+        }
+        ~FaceReuse() { c->face_reuse = false; }
+    } face_reuse(ctx);
     const long n = ctx->nc * ctx->nn;
     int rc;
     if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->phitmp.ensure(n)) || (rc = ctx->phiprev.ensure(n))) return rc;
@@ -949,23 +996,24 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     bool verified = false;   // FP32 form: phi_SI last recomputed by an FP64 sweep
     bool refreshed = false;  // FP32 form: the 1e-4 refresh sweep has been done
     for (; it < o->max_it; ++it) {
+        // FP64 form after the first iteration: the last kernel of the sweep
+        // writes the residual's partial sums, the DSA solve's first kernel
+        // reduces them into pinned host memory, and the value is read after
+        // the solve, which does not depend on it (one host synchronisation
+        // per iteration)
+        const bool defer = !incr && it > 0;
+        int res_n = 0;
         if (!incr || it == 0) {
-            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, o->prec, ctx->phisi.p, 0))) return rc;
+            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, o->prec, ctx->phisi.p, 0,
+                                    defer ? phi : nullptr, &res_n)))
+                return rc;
         } else {
             if ((rc = do_sweep_flux(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, ctx->phisi.p, 1)))
                 return rc;
         }
         verified = false;
         double r3[3];
-        // FP64 form after the first iteration: the residual is read back
-        // asynchronously and picked up after the DSA solve, which does not
-        // depend on it (one host synchronisation per iteration)
-        const bool defer = !incr && it > 0;
-        if (defer) {
-            if ((rc = residual3_async(ctx, ctx->phisi.p, phi))) return rc;
-        } else {
-            if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
-        }
+        if (!defer && (rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
         if (it == 0) {
             if (r3[2] == 0.0) {
                 bnorm = std::sqrt(r3[1]);
@@ -998,7 +1046,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         int cgi = 0;
         if (o->use_dsa) {
             sn_dsa_stats ds{};
-            rc = do_dsa(ctx, phi, ctx->phisi.p, phi, &o->dsa, &ds);
+            rc = do_dsa(ctx, phi, ctx->phisi.p, phi, &o->dsa, &ds, defer ? ctx->fpart.p : nullptr, res_n);
             cgi = ds.cg_iters;
             if (rc) {
                 status = rc;
@@ -1006,9 +1054,15 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
                 break;
             }
         } else {
+            if (defer) {
+                HIPCHK(launch_residual_final(res_n, ctx->fpart.p, ctx->res3.p, ctx->hpin->r3, ctx->stream));
+                HIPCHK(hipEventRecord(ctx->res_ev, ctx->stream));
+            }
             HIPCHK(hipMemcpyAsync(phi, ctx->phisi.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+            if (defer) HIPCHK(hipEventSynchronize(ctx->res_ev));
         }
-        if (defer && (rc = residual_wait(ctx, r3))) return rc;
+        if (defer)
+            for (int k = 0; k < 3; ++k) r3[k] = ctx->hpin->r3[k];
         const double res = std::sqrt(r3[0]) / bnorm;
         if (stats && stats->res_hist) stats->res_hist[it] = res;
         if (first < 0) first = res;

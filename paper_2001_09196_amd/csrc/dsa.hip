@@ -481,6 +481,9 @@ __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, long b
 // block-Jacobi preconditioner (bj = 1) also z = B^{-1} r and the r.z partials
 // [0..nparts); the b.b partials go to [nparts..2 nparts).  With the multigrid
 // preconditioner the V-cycle produces z and the r.z partials.
+// Block 0 also resets the CG scalars (and the stop fields of their pinned
+// host copy) and, given res_part, reduces the source-iteration residual
+// partials into res_out (device) and res_host (pinned host memory).
 template <int NN, bool BJ>
 __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __restrict__ thick_cell,
                                                       const double* __restrict__ sigma_t,
@@ -489,9 +492,44 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       const double* __restrict__ phi_si,
                                                       const double* __restrict__ binv, double* __restrict__ x,
                                                       double* __restrict__ r, double* __restrict__ z,
-                                                      double* __restrict__ p, double* __restrict__ part) {
-    __shared__ double sh[256];
+                                                      double* __restrict__ p, double* __restrict__ part,
+                                                      CgScalars* sc, CgScalars* sc_host,
+                                                      const double* __restrict__ res_part, int res_nparts,
+                                                      double* __restrict__ res_out, double* __restrict__ res_host) {
+    __shared__ double sh[768];
     constexpr int DIM = NN == 4 ? 2 : 3;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            sc->rz[0] = sc->rz[1] = 0.0;
+            sc->bb = sc->rr = 0.0;
+            sc->iters = 0;
+            sc->breakdown = 0;
+            sc->done = 0;
+            if (sc_host) {
+                sc_host->iters = 0;
+                sc_host->breakdown = 0;
+                sc_host->done = 0;
+            }
+        }
+        if (res_part) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int e = threadIdx.x; e < res_nparts; e += 256) {
+                s0 += res_part[e];
+                s1 += res_part[res_nparts + e];
+                s2 += res_part[2 * res_nparts + e];
+            }
+            block_sum3(s0, s1, s2, sh);
+            if (threadIdx.x == 0) {
+                res_out[0] = s0;
+                res_out[1] = s1;
+                res_out[2] = s2;
+                res_host[0] = s0;
+                res_host[1] = s1;
+                res_host[2] = s2;
+            }
+            __syncthreads();
+        }
+    }
     double rz = 0.0, bb = 0.0;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
         const long c = thick_cell[s];
@@ -528,10 +566,12 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
-                          hipStream_t st) {
+                          CgScalars* s, CgScalars* s_host, const double* res_part, int res_nparts, double* res_out,
+                          double* res_host, hipStream_t st) {
 #define SN_RHS(NN, BJ)                                                                                        \
     hipLaunchKernelGGL((dsa_rhs_kernel<NN, BJ>), dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s, \
-                       mass_kind, phi_old, phi_si, binv, x, r, z, p, part)
+                       mass_kind, phi_old, phi_si, binv, x, r, z, p, part, s, s_host, res_part, res_nparts,      \
+                       res_out, res_host)
     if (g.nn == 4) {
         if (bj) SN_RHS(4, true);
         else SN_RHS(4, false);
@@ -540,21 +580,6 @@ hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double*
         else SN_RHS(8, false);
     }
 #undef SN_RHS
-    return hipGetLastError();
-}
-
-__global__ void cg_init_kernel(CgScalars* s) {
-    if (threadIdx.x == 0) {
-        s->rz[0] = s->rz[1] = 0.0;
-        s->bb = s->rr = 0.0;
-        s->iters = 0;
-        s->breakdown = 0;
-        s->done = 0;
-    }
-}
-
-hipError_t launch_cg_init(CgScalars* s, hipStream_t st) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3(1), dim3(64), 0, st, s);
     return hipGetLastError();
 }
 
@@ -578,7 +603,8 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
                                                        const double* __restrict__ z, const double* __restrict__ p_old,
                                                        double* __restrict__ p_new, double* __restrict__ q,
                                                        const double* __restrict__ part_rz, double* __restrict__ part,
-                                                       int nparts, CgScalars* s, double rtol, int maxit, int it) {
+                                                       int nparts, CgScalars* s, CgScalars* s_host, double rtol,
+                                                       int maxit, int it) {
     if (s->done) return;
     __shared__ double sh[256];
     const double rz = reduce_parts(part_rz, nparts, sh);
@@ -590,6 +616,12 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
             s->rr = rr;
             s->iters = it;
             s->done = 1;
+            if (s_host) {
+                s_host->bb = bb;
+                s_host->rr = rr;
+                s_host->iters = it;
+                s_host->done = 1;
+            }
         }
         return;
     }
@@ -626,7 +658,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
                                                         const double* __restrict__ q,
                                                         const double* __restrict__ part_pq,
                                                         double* __restrict__ part_out, int nparts, CgScalars* s,
-                                                        int it) {
+                                                        CgScalars* s_host, int it) {
     if (s->done) return;
     __shared__ double sh[256];
     const double pq = reduce_parts(part_pq, nparts, sh);
@@ -635,6 +667,13 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
             s->breakdown = 1;
             s->iters = it;
             s->done = 1;
+            if (s_host) {
+                s_host->bb = s->bb;
+                s_host->rr = s->rr;
+                s_host->breakdown = 1;
+                s_host->iters = it;
+                s_host->done = 1;
+            }
         }
         return;
     }
@@ -670,36 +709,39 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
     }
 }
 
-// iteration `it`; with check_only only the apply kernel's stop test runs
-hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                               const double* sigma_s, const double* binv, double* x, double* r, double* z,
-                               double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
-                               CgScalars* s, double rtol, int maxit, int it, int bj, hipStream_t st) {
+// apply kernel of iteration it (its stop test first; with it = maxit only the
+// test); p alternates between p0 and p1 by iteration parity
+hipError_t launch_cg_apply(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                           const double* sigma_s, const double* z, double* p0, double* p1, double* q,
+                           double* part_a, double* part_b, int nparts, CgScalars* s, CgScalars* s_host, double rtol,
+                           int maxit, int it, hipStream_t st) {
     double* p_old = (it & 1) ? p1 : p0;
     double* p_new = (it & 1) ? p0 : p1;
-    if (g.nn == 4) {
+    if (g.nn == 4)
         hipLaunchKernelGGL(cg_apply_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
-                           z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
-        if (it < maxit) {
-            if (bj)
-                hipLaunchKernelGGL((cg_update_kernel<4, true>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
-                                   p_new, q, part_a, part_b, nparts, s, it);
-            else
-                hipLaunchKernelGGL((cg_update_kernel<4, false>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
-                                   p_new, q, part_a, part_b, nparts, s, it);
-        }
-    } else {
+                           z, p_old, p_new, q, part_b, part_a, nparts, s, s_host, rtol, maxit, it);
+    else
         hipLaunchKernelGGL(cg_apply_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
-                           z, p_old, p_new, q, part_b, part_a, nparts, s, rtol, maxit, it);
-        if (it < maxit) {
-            if (bj)
-                hipLaunchKernelGGL((cg_update_kernel<8, true>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
-                                   p_new, q, part_a, part_b, nparts, s, it);
-            else
-                hipLaunchKernelGGL((cg_update_kernel<8, false>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z,
-                                   p_new, q, part_a, part_b, nparts, s, it);
-        }
+                           z, p_old, p_new, q, part_b, part_a, nparts, s, s_host, rtol, maxit, it);
+    return hipGetLastError();
+}
+
+// update kernel of iteration it (< maxit)
+hipError_t launch_cg_update(const DsaGeom& g, const double* binv, double* x, double* r, double* z, double* p0,
+                            double* p1, const double* q, double* part_a, double* part_b, int nparts, CgScalars* s,
+                            CgScalars* s_host, int it, int bj, hipStream_t st) {
+    double* p_new = (it & 1) ? p0 : p1;
+#define SN_UPD(NN, BJ)                                                                                       \
+    hipLaunchKernelGGL((cg_update_kernel<NN, BJ>), dim3(nparts), dim3(256), 0, st, g, binv, x, r, z, p_new, q, \
+                       part_a, part_b, nparts, s, s_host, it)
+    if (g.nn == 4) {
+        if (bj) SN_UPD(4, true);
+        else SN_UPD(4, false);
+    } else {
+        if (bj) SN_UPD(8, true);
+        else SN_UPD(8, false);
     }
+#undef SN_UPD
     return hipGetLastError();
 }
 

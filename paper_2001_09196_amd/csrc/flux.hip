@@ -34,9 +34,14 @@ hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* p
 }
 
 // One thread per cell: reads the cell's contiguous [ndirs][NN] block of psi.
-template <typename T, int NN>
-__global__ void moment_kernel(long nc, int ndirs, const double* __restrict__ w, const T* __restrict__ psi,
-                              double* __restrict__ phi, int accumulate) {
+// RES: also the block partial sums of (phi - ref)^2, phi^2, ref^2 over the
+// written phi (part[3][gridDim.x]), the residual of source iteration.
+template <typename T, int NN, bool RES>
+__global__ void __launch_bounds__(256) moment_kernel(long nc, int ndirs, const double* __restrict__ w,
+                                                     const T* __restrict__ psi, double* __restrict__ phi,
+                                                     int accumulate, const double* __restrict__ ref,
+                                                     double* __restrict__ part) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
         double acc[NN];
 #pragma unroll
@@ -47,45 +52,45 @@ __global__ void moment_kernel(long nc, int ndirs, const double* __restrict__ w, 
 #pragma unroll
             for (int n = 0; n < NN; ++n) acc[n] = fma(wd, double(p[d * NN + n]), acc[n]);
         }
-        if (accumulate) {
 #pragma unroll
-            for (int n = 0; n < NN; ++n) phi[c * NN + n] += acc[n];
-        } else {
-#pragma unroll
-            for (int n = 0; n < NN; ++n) phi[c * NN + n] = acc[n];
+        for (int n = 0; n < NN; ++n) {
+            const double v = accumulate ? phi[c * NN + n] + acc[n] : acc[n];
+            phi[c * NN + n] = v;
+            if constexpr (RES) {
+                const double y = ref[c * NN + n], e = v - y;
+                s0 = fma(e, e, s0);
+                s1 = fma(v, v, s1);
+                s2 = fma(y, y, s2);
+            }
+        }
+    }
+    if constexpr (RES) {
+        __shared__ double sh[768];
+        block_sum3(s0, s1, s2, sh);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = s0;
+            part[gridDim.x + blockIdx.x] = s1;
+            part[2 * gridDim.x + blockIdx.x] = s2;
         }
     }
 }
 
 template <typename T>
 hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* psi, double* phi, int accumulate,
-                         hipStream_t st) {
-    int blocks = (int)std::min<long>((nc + 255) / 256, 1 << 16);
-    if (nn == 4)
-        hipLaunchKernelGGL((moment_kernel<T, 4>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, psi, phi, accumulate);
-    else
-        hipLaunchKernelGGL((moment_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, psi, phi, accumulate);
-    return hipGetLastError();
-}
-
-// deterministic block reduction of three sums
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = a;
-    sh[256 + tid] = b;
-    sh[512 + tid] = c;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            sh[tid] += sh[tid + s];
-            sh[256 + tid] += sh[256 + tid + s];
-            sh[512 + tid] += sh[512 + tid + s];
-        }
-        __syncthreads();
+                         const double* ref, double* part, hipStream_t st) {
+    const int blocks = moment_blocks(nc);
+#define SN_MOM(NN, RES)                                                                                          \
+    hipLaunchKernelGGL((moment_kernel<T, NN, RES>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, psi, phi,     \
+                       accumulate, ref, part)
+    if (nn == 4) {
+        if (ref) SN_MOM(4, true);
+        else SN_MOM(4, false);
+    } else {
+        if (ref) SN_MOM(8, true);
+        else SN_MOM(8, false);
     }
-    a = sh[0];
-    b = sh[256];
-    c = sh[512];
+#undef SN_MOM
+    return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(256) residual_part_kernel(long n, const double* __restrict__ a,
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(256) residual_part_kernel(long n, const double
 }
 
 __global__ void __launch_bounds__(256) residual_final_kernel(int nparts, const double* __restrict__ part,
-                                                             double* __restrict__ out) {
+                                                             double* __restrict__ out, double* __restrict__ out_host) {
     __shared__ double sh[768];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int e = threadIdx.x; e < nparts; e += 256) {
@@ -121,13 +126,24 @@ __global__ void __launch_bounds__(256) residual_final_kernel(int nparts, const d
         out[0] = s0;
         out[1] = s1;
         out[2] = s2;
+        if (out_host) {
+            out_host[0] = s0;
+            out_host[1] = s1;
+            out_host[2] = s2;
+        }
     }
 }
 
 hipError_t launch_residual(long n, const double* a, const double* b, double* partials, int nparts, double* out,
                            hipStream_t st) {
     hipLaunchKernelGGL(residual_part_kernel, dim3(nparts), dim3(256), 0, st, n, a, b, partials);
-    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, partials, out);
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, partials, out, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_final(int nparts, const double* partials, double* out, double* out_host,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, partials, out, out_host);
     return hipGetLastError();
 }
 
@@ -274,7 +290,7 @@ hipError_t launch_response(long nc, int nn, int nx, int ny, int nz, const double
         hipLaunchKernelGGL((response_part_kernel<T, 8>), dim3(nparts), dim3(256), 0, st, nc, nx, ny, nz, h[0], h[1],
                            h[2], r, phi, face, ndirs, wn, psi, part);
     // final fixed-order sum of the two partial arrays (third slot unused)
-    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, part, out);
+    hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, nparts, part, out, nullptr);
     return hipGetLastError();
 }
 
@@ -289,8 +305,10 @@ template hipError_t launch_source<double>(long, int, const double*, const double
                                           double*, hipStream_t);
 template hipError_t launch_source<float>(long, int, const double*, const double*, const double*, const double*,
                                          float*, hipStream_t);
-template hipError_t launch_moment<double>(long, int, int, const double*, const double*, double*, int, hipStream_t);
-template hipError_t launch_moment<float>(long, int, int, const double*, const float*, double*, int, hipStream_t);
+template hipError_t launch_moment<double>(long, int, int, const double*, const double*, double*, int, const double*,
+                                          double*, hipStream_t);
+template hipError_t launch_moment<float>(long, int, int, const double*, const float*, double*, int, const double*,
+                                         double*, hipStream_t);
 template hipError_t launch_gradient<double>(long, int, int, const double*, const double*, const double*,
                                             const double*, const double*, const double*, const double*,
                                             const double*, double*, double*, hipStream_t);

@@ -158,4 +158,25 @@ __device__ __forceinline__ void cell_solve3(const T g[8], T ax, T ay, T az, T si
     }
 }
 
+// deterministic block reduction of three sums
+// (256 threads; sh: 768 doubles)
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = a;
+    sh[256 + tid] = b;
+    sh[512 + tid] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sh[tid] += sh[tid + s];
+            sh[256 + tid] += sh[256 + tid + s];
+            sh[512 + tid] += sh[512 + tid + s];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[256];
+    c = sh[512];
+}
+
 }  // namespace sn

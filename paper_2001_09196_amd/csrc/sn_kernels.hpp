@@ -41,10 +41,13 @@ inline long sink_elems(const SweepGeom&) { return 1; }
 // 3D fused sweep + moment (source iteration): psi is not stored; phioct
 // (workspace [nclasses][ncells][8]) receives each octant's share of phi, then
 // phi = (accumulate ? phi : 0) + sum over the octants in a fixed order.
+// ref != nullptr: residual partial sums as in launch_moment, part[3][octant_sum_blocks(ncells)]
+inline int octant_sum_blocks(long nc) { return (int)std::min<long>((nc * 8 + 255) / 256, 65536); }
 template <typename T>
 hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
                                const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
-                               const int* plane_off, double* phioct, double* phi, int accumulate, hipStream_t st);
+                               const int* plane_off, double* phioct, double* phi, int accumulate,
+                               const double* ref, double* part, hipStream_t st);
 // per-cell array [ncells][nn] -> four quadrant diagonal-major arrays
 // [4][ceil(ny / 64)][nx + 63][64][nn] (2D sweep input layout)
 template <typename T>
@@ -65,12 +68,19 @@ inline long skew2d_elems(int nx, int ny, int nn) {
 template <typename T>
 hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* phi, const double* phi_prev,
                          const double* q, T* src, hipStream_t st);
+// ref != nullptr: also the residual partial sums of (phi - ref)^2, phi^2,
+// ref^2 over the written phi, part[3][moment_blocks(nc)]
+inline int moment_blocks(long nc) { return (int)std::min<long>((nc + 255) / 256, 1 << 16); }
 template <typename T>
 hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* psi, double* phi, int accumulate,
-                         hipStream_t st);
+                         const double* ref, double* part, hipStream_t st);
 // partial sums of (a-b)^2, a^2, b^2 over n doubles; out[3] on device
 hipError_t launch_residual(long n, const double* a, const double* b, double* partials, int nparts, double* out,
                            hipStream_t st);
+// the final reduction of nparts such partial sums into out[3] (device) and,
+// if out_host != nullptr, into pinned host memory
+hipError_t launch_residual_final(int nparts, const double* partials, double* out, double* out_host,
+                                 hipStream_t st);
 template <typename T>
 hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const double* h, const double* sigma_t,
                            const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
@@ -105,20 +115,30 @@ struct CgScalars {
     int done, iters, breakdown, pad;
 };
 
+// right-hand side and CG start; also resets s (and the stop fields of its
+// pinned host copy s_host) and, given res_part, reduces res_nparts
+// source-iteration residual partials into res_out (device) and res_host
+// (pinned host memory)
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
-                          hipStream_t st);
-hipError_t launch_cg_init(CgScalars* s, hipStream_t st);
+                          CgScalars* s, CgScalars* s_host, const double* res_part, int res_nparts, double* res_out,
+                          double* res_host, hipStream_t st);
 hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
                                   hipStream_t st);
-// CG iteration `it` (it = maxit only runs the stop test); p0/p1 alternate.
-// bj = 1: z = B^{-1} r inside the update; bj = 0: the caller computes z and
-// the r.z partials (multigrid V-cycle) after the update.
-hipError_t launch_cg_iteration(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
-                               const double* sigma_s, const double* binv, double* x, double* r, double* z,
-                               double* p0, double* p1, double* q, double* part_a, double* part_b, int nparts,
-                               CgScalars* s, double rtol, int maxit, int it, int bj, hipStream_t st);
+// CG iteration `it` in two kernels.  apply: the stop test (at it = maxit
+// only the test), then p = z + beta p_old and q = D p; update (it < maxit):
+// x, r and, with bj = 1, z = B^{-1} r (bj = 0: the caller computes z and the
+// r.z partials, multigrid V-cycle, after the update).  p0/p1 alternate by
+// parity.  When the solve stops or breaks down, block 0 also writes the
+// stop fields into s_host (pinned host memory, may be nullptr).
+hipError_t launch_cg_apply(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                           const double* sigma_s, const double* z, double* p0, double* p1, double* q,
+                           double* part_a, double* part_b, int nparts, CgScalars* s, CgScalars* s_host, double rtol,
+                           int maxit, int it, hipStream_t st);
+hipError_t launch_cg_update(const DsaGeom& g, const double* binv, double* x, double* r, double* z, double* p0,
+                            double* p1, const double* q, double* part_a, double* part_b, int nparts, CgScalars* s,
+                            CgScalars* s_host, int it, int bj, hipStream_t st);
 
 hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
                               double* phi_out, hipStream_t st);

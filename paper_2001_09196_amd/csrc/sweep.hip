@@ -24,6 +24,7 @@
 // n_local = n_global ^ M with M = rx + 2 ry + 4 rz, a compile-time constant
 // of each kernel body.
 #include <type_traits>
+#include <utility>
 
 #include "sn_kernels.hpp"
 
@@ -226,6 +227,13 @@ __device__ __forceinline__ lds_t<T>* as_lds(T* p) {
 // before the slot is rewritten.
 constexpr int R2D = 4;
 constexpr int B2D = 8;
+static_assert(B2D % R2D == 0, "the prefetch ring must wrap at chunk boundaries");
+
+// f(integral_constant<int, K>) for K = 0, 1, ... in order
+template <typename F, int... K>
+__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, K...>) {
+    (f(std::integral_constant<int, K>{}), ...);
+}
 
 // LDS of one 2D sweep workgroup.
 template <typename T>
@@ -337,9 +345,12 @@ __device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T
     }
     lds_t<T>* stw = as_lds(&L->stage[0][r][0]);
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay;
-    // step k of the window (slot base sb = (ts + k - kk) & B2D, kk = k mod B2D)
-    auto step = [&](int k, int sb, auto kkc, In2<T>& use, In2<T>& fill) {
+    // step k of the window (slot base sb = (ts + k - kk) & B2D, kk = k mod B2D);
+    // FULL: every lane of the wave is inside its row at this step and at the
+    // previous one (no store masks, no hold of the x inflow)
+    auto step = [&](int k, int sb, auto kkc, auto fullc, In2<T>& use, In2<T>& fill) {
         constexpr int kk = decltype(kkc)::value;
+        constexpr bool FULL = decltype(fullc)::value;
         fetch(k + R2D - 1, fill);
         dvec2 prev0{}, prev1{};
         if constexpr (sizeof(T) == 8) {
@@ -371,9 +382,14 @@ __device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T
         g[1] = fma(ay4, yi1, g[1]);
         g[3] = fma(-ay2, yi1, g[3]);
         cell_solve2(g, ax, ay, use.sig, u);
-        const bool started = k >= lane;  // il >= 0: keep the row's x inflow until then
-        xin0 = started ? u[1] : xin0;
-        xin1 = started ? u[3] : xin1;
+        if constexpr (FULL) {
+            xin0 = u[1];
+            xin1 = u[3];
+        } else {
+            const bool started = k >= lane;  // il >= 0: keep the row's x inflow until then
+            xin0 = started ? u[1] : xin0;
+            xin1 = started ? u[3] : xin1;
+        }
         yo0 = u[2];
         yo1 = u[3];
         if constexpr (sizeof(T) == 8) {
@@ -383,12 +399,12 @@ __device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T
             lds_t<dvec2>* sw = reinterpret_cast<lds_t<dvec2>*>(stw + par * ROWS2D * 4);
             sw[0] = dvec2{u[0 ^ M], u[1 ^ M]};
             sw[1] = dvec2{u[2 ^ M], u[3 ^ M]};
-            if ((unsigned)(k - v0) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp0) = prev0;
-            if ((unsigned)(k - v1) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp1) = prev1;
+            if (FULL || (unsigned)(k - v0) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp0) = prev0;
+            if (FULL || (unsigned)(k - v1) < (unsigned)nx) *reinterpret_cast<dvec2*>(wp1) = prev1;
             wp0 += sgn_step;
             wp1 += sgn_step;
         } else {
-            if ((unsigned)(k - v0) < (unsigned)nx) store4(wp0, u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
+            if (FULL || (unsigned)(k - v0) < (unsigned)nx) store4(wp0, u[0 ^ M], u[1 ^ M], u[2 ^ M], u[3 ^ M]);
             wp0 += sgn_step;
         }
         if constexpr (ROLE == W2_TOPOUT) {
@@ -405,17 +421,24 @@ __device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T
     In2<T> sl[R2D];
 #pragma unroll
     for (int k = 0; k + 1 < R2D; ++k) fetch(k, sl[k]);
-    for (int k0 = 0; k0 < LEN; k0 += B2D) {
+    // one chunk of B2D steps; step k uses ring slot k % R2D and refills the
+    // slot of step k + R2D - 1 (B2D is a multiple of R2D)
+    auto chunk = [&](int k0, auto fullc) {
         const int sb = (ts + k0) & B2D;
-        step(k0 + 0, sb, std::integral_constant<int, 0>{}, sl[0], sl[3]);
-        step(k0 + 1, sb, std::integral_constant<int, 1>{}, sl[1], sl[0]);
-        step(k0 + 2, sb, std::integral_constant<int, 2>{}, sl[2], sl[1]);
-        step(k0 + 3, sb, std::integral_constant<int, 3>{}, sl[3], sl[2]);
-        step(k0 + 4, sb, std::integral_constant<int, 4>{}, sl[0], sl[3]);
-        step(k0 + 5, sb, std::integral_constant<int, 5>{}, sl[1], sl[0]);
-        step(k0 + 6, sb, std::integral_constant<int, 6>{}, sl[2], sl[1]);
-        step(k0 + 7, sb, std::integral_constant<int, 7>{}, sl[3], sl[2]);
+        unroll_seq(
+            [&](auto kc) {
+                constexpr int kk = decltype(kc)::value;
+                step(k0 + kk, sb, kc, fullc, sl[kk % R2D], sl[(kk + R2D - 1) % R2D]);
+            },
+            std::make_integer_sequence<int, B2D>{});
         __syncthreads();
+    };
+    // chunks [64, kf) have every lane inside its row (il = k - lane in
+    // [0, nx) at k and at k - 1) when the wave's rows are all in the chunk
+    const int kf = (wave + 1) * 64 <= nrows ? max(64, nx / B2D * B2D) : 0;
+    for (int k0 = 0; k0 < LEN; k0 += B2D) {
+        if (k0 >= 64 && k0 < kf) chunk(k0, std::true_type{});
+        else chunk(k0, std::false_type{});
     }
     for (int t = ts + LEN; t < NT; t += B2D) __syncthreads();
 }
@@ -856,12 +879,33 @@ __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int n
 }
 
 // phi = sum over the classes of phioct (fixed order), or phi += that sum
-__global__ void octant_sum_kernel(long n, int ncls, const double* __restrict__ phioct, double* __restrict__ phi,
-                                  int accumulate) {
+// RES: also the residual partial sums (phi - ref)^2, phi^2, ref^2 per block
+template <bool RES>
+__global__ void __launch_bounds__(256) octant_sum_kernel(long n, int ncls, const double* __restrict__ phioct,
+                                                         double* __restrict__ phi, int accumulate,
+                                                         const double* __restrict__ ref,
+                                                         double* __restrict__ part) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int c = 0; c < ncls; ++c) s += phioct[c * n + i];
-        phi[i] = accumulate ? phi[i] + s : s;
+        const double v = accumulate ? phi[i] + s : s;
+        phi[i] = v;
+        if constexpr (RES) {
+            const double y = ref[i], e = v - y;
+            s0 = fma(e, e, s0);
+            s1 = fma(v, v, s1);
+            s2 = fma(y, y, s2);
+        }
+    }
+    if constexpr (RES) {
+        __shared__ double sh[768];
+        block_sum3(s0, s1, s2, sh);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x] = s0;
+            part[gridDim.x + blockIdx.x] = s1;
+            part[2 * gridDim.x + blockIdx.x] = s2;
+        }
     }
 }
 
@@ -933,7 +977,8 @@ template hipError_t launch_skew2d<float>(int, int, int, const float*, float*, hi
 template <typename T>
 hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
                                const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
-                               const int* plane_off, double* phioct, double* phi, int accumulate, hipStream_t st) {
+                               const int* plane_off, double* phioct, double* phi, int accumulate,
+                               const double* ref, double* part, hipStream_t st) {
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
         hipLaunchKernelGGL((sweep3d_flux_kernel<T>), dim3(nt, g.nclasses), dim3(64 * g.groups_per_class), 0, st,
@@ -943,17 +988,22 @@ hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const do
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const long n = (long)g.nx * g.ny * g.nz * 8;
-    const int blocks = (int)std::min<long>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(octant_sum_kernel, dim3(blocks), dim3(256), 0, st, n, g.nclasses, phioct, phi, accumulate);
+    const long nc = (long)g.nx * g.ny * g.nz, n = nc * 8;
+    const int blocks = octant_sum_blocks(nc);
+    if (ref)
+        hipLaunchKernelGGL(octant_sum_kernel<true>, dim3(blocks), dim3(256), 0, st, n, g.nclasses, phioct, phi,
+                           accumulate, ref, part);
+    else
+        hipLaunchKernelGGL(octant_sum_kernel<false>, dim3(blocks), dim3(256), 0, st, n, g.nclasses, phioct, phi,
+                           accumulate, ref, part);
     return hipGetLastError();
 }
 template hipError_t launch_sweep_flux3d<double>(const SweepGeom&, const DirInfo*, const double*, int, const double*,
                                                 const double*, double*, double*, double*, const int*, const int*,
-                                                double*, double*, int, hipStream_t);
+                                                double*, double*, int, const double*, double*, hipStream_t);
 template hipError_t launch_sweep_flux3d<float>(const SweepGeom&, const DirInfo*, const double*, int, const float*,
                                                const float*, float*, float*, float*, const int*, const int*,
-                                               double*, double*, int, hipStream_t);
+                                               double*, double*, int, const double*, double*, hipStream_t);
 
 template hipError_t launch_init_faces<double>(const SweepGeom&, const DirInfo*, int, const double*, double*, double*,
                                               double*, hipStream_t);
