@@ -134,8 +134,11 @@ typedef struct {
  * D_ff the SIP diffusion operator (eq. SIP) on the thick DOFs only (principal
  * submatrix, Section 3.2), solved by preconditioned CG in FP64 (opts->precond).
  * Thin and void DOFs: phi_out = phi_si.  All three arrays device
- * [ncells][nn]; phi_out may alias phi_si.  stats (host, may be NULL) is filled
- * after a stream synchronisation.  Returns CG_BREAKDOWN if p^T D p <= 0. */
+ * [ncells][nn]; phi_out may alias phi_si.  The call waits until the CG stop
+ * test has passed on the device (the kernels post the stop flags to pinned
+ * host memory), fills stats (host, may be NULL) and returns with the final
+ * update of phi_out enqueued on the stream.  Returns CG_BREAKDOWN if
+ * p^T D p <= 0. */
 int sn_dsa_thick_correct(sn_context *ctx, const double *phi_old, const double *phi_si, double *phi_out,
                          const sn_dsa_opts *opts, sn_dsa_stats *stats);
 
@@ -171,7 +174,8 @@ typedef struct {
  *   phi <- phi_SI + P_T D_ff^{-1} Sigma_f R_T (phi_SI - phi)   (or phi <- phi_SI).
  * q: device [ncells] or NULL; inflow: device [ndirs][nbf] or NULL;
  * phi_inout: device [ncells][nn], initial guess in, last iterate out.
- * Synchronises once per iteration (the residual is read on the host).
+ * Waits on the host once per iteration (the residual and the CG stop flags
+ * are read from pinned host memory).
  * Returns OK, NOT_CONVERGED, DIVERGED or CG_BREAKDOWN (phi_inout holds the
  * last iterate in all three error cases). */
 int sn_source_iterate(sn_context *ctx, const double *q, const double *inflow, double *phi_inout,

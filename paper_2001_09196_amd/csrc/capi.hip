@@ -99,7 +99,7 @@ struct sn_context {
         CgScalars cs;
     };
     HostScalars* hpin = nullptr;
-    hipEvent_t res_ev = nullptr;
+    hipEvent_t res_ev = nullptr, cg_ev = nullptr;
     // geometric multigrid hierarchy (built on first use)
     bool mg_ready = false;
     int mg_lc = 1, mg_levels = 0;
@@ -484,7 +484,8 @@ bool bad_dsa_opts(const sn_dsa_opts& o) {
 
 // res_part / res_nparts: source-iteration residual partial sums to reduce in
 // the solve's first kernel into ctx->res3 and the pinned ctx->hpin->r3 (the
-// solve's stream synchronisation then also completes that read-back)
+// host's wait for the solve's stop flag, which a later kernel writes, then
+// also covers that read-back)
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
            sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0) {
     const long n = ctx->nc * ctx->nn;
@@ -525,9 +526,16 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if (!bj) return vcycle();
         return 0;
     };
+    // The stop fields of the pinned copy are cleared here, before the solve
+    // is enqueued: the host may get here while earlier work is still
+    // running, and the previous solve wrote them for the last time when its
+    // stop test passed (the host saw that write before returning).
+    hs.done = 0;
+    hs.breakdown = 0;
+    hs.iters = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
-                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->scal.p, &hs,
+                          ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->scal.p,
                           res_part, res_nparts, ctx->res3.p, ctx->hpin->r3, ctx->stream));
     if (!bj && (rc = vcycle())) return rc;
     // Batches of iterations, each ended by the stop test of the next
@@ -547,7 +555,15 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if ((rc = apply(it))) return rc;
         ++it;
         pending = true;
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        // wait for the stop flag in pinned memory (written as soon as the
+        // test passes, ahead of the kernel's end) or for the batch to finish
+        HIPCHK(hipEventRecord(ctx->cg_ev, ctx->stream));
+        volatile int* flag = &hs.done;
+        while (!*flag) {
+            const hipError_t e = hipEventQuery(ctx->cg_ev);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) HIPCHK(e);
+        }
         if (hs.done || it > o->cg_maxit) break;
         batch = 4;
     }
@@ -592,6 +608,7 @@ void sn_context_destroy(sn_context* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->res_ev) (void)hipEventDestroy(ctx->res_ev);
+    if (ctx->cg_ev) (void)hipEventDestroy(ctx->cg_ev);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     ctx->fpart.release();
     ctx->evpool.clear();
@@ -897,6 +914,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
     HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(sn_context::HostScalars), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&c->res_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->cg_ev, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(c->stream));
     *out = c.release();
     return SN_OK;

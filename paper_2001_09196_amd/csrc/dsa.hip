@@ -481,9 +481,9 @@ __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, long b
 // block-Jacobi preconditioner (bj = 1) also z = B^{-1} r and the r.z partials
 // [0..nparts); the b.b partials go to [nparts..2 nparts).  With the multigrid
 // preconditioner the V-cycle produces z and the r.z partials.
-// Block 0 also resets the CG scalars (and the stop fields of their pinned
-// host copy) and, given res_part, reduces the source-iteration residual
-// partials into res_out (device) and res_host (pinned host memory).
+// Block 0 also resets the CG scalars and, given res_part, reduces the
+// source-iteration residual partials into res_out (device) and res_host
+// (pinned host memory).
 template <int NN, bool BJ>
 __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __restrict__ thick_cell,
                                                       const double* __restrict__ sigma_t,
@@ -493,8 +493,8 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       const double* __restrict__ binv, double* __restrict__ x,
                                                       double* __restrict__ r, double* __restrict__ z,
                                                       double* __restrict__ p, double* __restrict__ part,
-                                                      CgScalars* sc, CgScalars* sc_host,
-                                                      const double* __restrict__ res_part, int res_nparts,
+                                                      CgScalars* sc, const double* __restrict__ res_part,
+                                                      int res_nparts,
                                                       double* __restrict__ res_out, double* __restrict__ res_host) {
     __shared__ double sh[768];
     constexpr int DIM = NN == 4 ? 2 : 3;
@@ -505,11 +505,6 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
             sc->iters = 0;
             sc->breakdown = 0;
             sc->done = 0;
-            if (sc_host) {
-                sc_host->iters = 0;
-                sc_host->breakdown = 0;
-                sc_host->done = 0;
-            }
         }
         if (res_part) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -566,11 +561,11 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
-                          CgScalars* s, CgScalars* s_host, const double* res_part, int res_nparts, double* res_out,
-                          double* res_host, hipStream_t st) {
+                          CgScalars* s, const double* res_part, int res_nparts, double* res_out, double* res_host,
+                          hipStream_t st) {
 #define SN_RHS(NN, BJ)                                                                                        \
     hipLaunchKernelGGL((dsa_rhs_kernel<NN, BJ>), dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s, \
-                       mass_kind, phi_old, phi_si, binv, x, r, z, p, part, s, s_host, res_part, res_nparts,      \
+                       mass_kind, phi_old, phi_si, binv, x, r, z, p, part, s, res_part, res_nparts,              \
                        res_out, res_host)
     if (g.nn == 4) {
         if (bj) SN_RHS(4, true);
@@ -620,6 +615,7 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
                 s_host->bb = bb;
                 s_host->rr = rr;
                 s_host->iters = it;
+                __threadfence_system();  // the fields reach the host before the flag
                 s_host->done = 1;
             }
         }
@@ -672,6 +668,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
                 s_host->rr = s->rr;
                 s_host->breakdown = 1;
                 s_host->iters = it;
+                __threadfence_system();
                 s_host->done = 1;
             }
         }

@@ -115,15 +115,14 @@ struct CgScalars {
     int done, iters, breakdown, pad;
 };
 
-// right-hand side and CG start; also resets s (and the stop fields of its
-// pinned host copy s_host) and, given res_part, reduces res_nparts
-// source-iteration residual partials into res_out (device) and res_host
-// (pinned host memory)
+// right-hand side and CG start; also resets s and, given res_part, reduces
+// res_nparts source-iteration residual partials into res_out (device) and
+// res_host (pinned host memory)
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
-                          CgScalars* s, CgScalars* s_host, const double* res_part, int res_nparts, double* res_out,
-                          double* res_host, hipStream_t st);
+                          CgScalars* s, const double* res_part, int res_nparts, double* res_out, double* res_host,
+                          hipStream_t st);
 hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
                                   hipStream_t st);
 // CG iteration `it` in two kernels.  apply: the stop test (at it = maxit
