@@ -533,23 +533,38 @@ struct In3 {
     Vec4<T> y, z;  // y- and z-face inflow (lanes on the tile's y = 0 / z = 0 side)
 };
 
-// Sum over the four direction rows (k = lane / 16) of a 16-lane pencil,
-// returned in every row: the gfx950 permlane swaps exchange rows 0 <-> 1 and
-// 2 <-> 3, then the two 32-lane halves; the order of the additions is fixed,
-// (v0 + v1) + (v2 + v3), and the same in every row.
-__device__ __forceinline__ double rows_sum(double v) {
-    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
-    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    const double s = __longlong_as_double((long long)(((unsigned long long)b[0] << 32) | a[0])) +
-                     __longlong_as_double((long long)(((unsigned long long)b[1] << 32) | a[1]));
-    const unsigned long long y = (unsigned long long)__double_as_longlong(s);
-    const unsigned lo2 = (unsigned)y, hi2 = (unsigned)(y >> 32);
-    const auto c = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
-    const auto e = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
-    return __longlong_as_double((long long)(((unsigned long long)e[0] << 32) | c[0])) +
-           __longlong_as_double((long long)(((unsigned long long)e[1] << 32) | c[1]));
+// Sums over the four direction rows of a pencil of eight values v[0..7],
+// reduce-scattered: lane (p, k) receives the sums of nodes nb and nb + 1,
+// nb = 2 (k >> 1) + 4 (k & 1).  The first permlane16 swap pairs rows 0-1 and
+// 2-3, exchanging nodes 4..7 of the even row for nodes 0..3 of the odd row,
+// so an even row keeps partial sums of nodes 0..3 and an odd row of 4..7;
+// the permlane32 swap then pairs the two halves the same way.  Every sum is
+// (v0 + v1) + (v2 + v3) over the rows, in a fixed order.  (The gfx950
+// permlane swaps exchange the odd rows of their first operand with the even
+// rows of the second, and the upper half of the first with the lower half of
+// the second.)
+__device__ __forceinline__ double swap_sum16(double a, double b) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long y = (unsigned long long)__double_as_longlong(b);
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0])) +
+           __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+}
+__device__ __forceinline__ double swap_sum32(double a, double b) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long y = (unsigned long long)__double_as_longlong(b);
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+    return __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0])) +
+           __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+}
+__device__ __forceinline__ void rows_sum8(const double v[8], double& r0, double& r1) {
+    double c[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) c[n] = swap_sum16(v[n], v[n + 4]);
+    r0 = swap_sum32(c[0], c[2]);
+    r1 = swap_sum32(c[1], c[3]);
 }
 
 // fused sweep + moment: steps per workgroup barrier
@@ -559,7 +574,7 @@ constexpr int RF = 4;
 
 // FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
 // stored; every step the lanes' w_d psi (FP64) is summed over the four
-// directions of a pencil (rows_sum), the 16 pencil sums of each wave go to an
+// directions of a pencil (rows_sum8), the 16 pencil sums of each wave go to an
 // LDS ring red[2 RF][waves][16][8], and every RF steps, after a workgroup
 // barrier, the workgroup adds the waves' sums in wave order and stores the
 // octant's share of phi for those cells (each cell is visited once per
@@ -594,28 +609,76 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         for (int t = 0; t < 4; ++t) xin[t] = x.v[t];
     }
     const long rowbase = ((long)k * ny + j) * nx;
+    // Addresses are formed from per-lane bases at the tile's first cell
+    // (position ir = 0 along the pencil) plus a multiple of the step, so the
+    // step loop does no 64-bit index arithmetic.  cdir: cells per step in
+    // memory along x.
+    constexpr int cdir = rx ? -1 : 1;
+    const int skew = jy + kz;  // lane's pencil lags the tile's first pencil by skew steps
+    const long c0 = rowbase + (rx ? nx - 1 - i0 : i0);
+    const T* src0 = src + c0 * 8;
+    const T* sig0 = sigt + c0;
+    const T* yin0 = yf + (((long)J * nz + kl) * nx + i0) * 4;
+    const T* zin0 = zf + (((long)K * ny + jl) * nx + i0) * 4;
     // The source, sigma_t and the y/z face inflow of the next cell are loaded
     // one step ahead.  The face values of this tile were written by earlier
     // launches (the upwind tiles) and no tile of this launch writes them, so
     // they can be read at any time.
     auto fetch = [&](int ir, In3<T>& v) {
         const int irc = min(max(ir, 0), len - 1);
-        const int il = i0 + irc;
-        const int i = rx ? nx - 1 - il : il;
-        const long c = rowbase + i;
-        v.s = load8(src + c * 8);
-        v.sig = sigt[c];
+        v.s = load8(src0 + cdir * irc * 8);
+        v.sig = sig0[cdir * irc];
         if (pen && jy == 0)
-            v.y = load4(yf + (((long)J * nz + kl) * nx + il) * 4);
+            v.y = load4(yin0 + irc * 4);
         else
             v.y = Vec4<T>{};
         if (pen && kz == 0)
-            v.z = load4(zf + (((long)K * ny + jl) * nx + il) * 4);
+            v.z = load4(zin0 + irc * 4);
         else
             v.z = Vec4<T>{};
     };
+    // face outflow of the tile's top pencils (position il = i0 + s - skew at
+    // step s) and of the last cell of each pencil
+    const bool ystore = pen && jy == 3 && J + 1 < nTy;
+    const bool zstore = pen && kz == 3 && K + 1 < nTz;
+    const bool xstore = pen && I + 1 < nTx;
+    T* yout0 = yf + (((long)(J + 1) * nz + kl) * nx + i0 - skew) * 4;
+    T* zout0 = zf + (((long)(K + 1) * ny + jl) * nx + i0 - skew) * 4;
+    T* xout = xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4;
+    // psi write-out through the LDS stage (nvalid > 0): pass it of the wave
+    // covers the 64 consecutive 16-byte pieces it * 64 + lane of the 16
+    // pencils' blocks of nvalid * 8 values; wsk: the pencil's skew (a huge
+    // value where the lane has no piece), woff: the piece's LDS offset, wp:
+    // its address at the current step, moved by wstride per step
+    constexpr int CH = 16 / sizeof(T);  // values per 16-byte piece
+    constexpr int NIT = 8 / CH;         // passes for four directions
+    const long wstride = (long)cdir * ndirs * 8;
+    int wsk[NIT], woff[NIT];
+    T* wp[NIT];
+    if constexpr (!FUSED) {
+        const int per = nvalid * 8 / CH;  // pieces per pencil block
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int id = it * 64 + lane;
+            wsk[it] = 1 << 29;
+            woff[it] = 0;
+            wp[it] = psi;
+            if (nvalid > 0 && id < 16 * per) {
+                const int q = id / per, o = id - q * per;
+                const int qy = q & 3, qz = q >> 2;
+                const int qjl = J * 4 + qy, qkl = K * 4 + qz;
+                if (qjl < ny && qkl < nz) {
+                    const int qj = ry ? ny - 1 - qjl : qjl;
+                    const int qk = rz ? nz - 1 - qkl : qkl;
+                    const long qc0 = ((long)qk * ny + qj) * nx + (rx ? nx - 1 - i0 : i0);
+                    wsk[it] = qy + qz;
+                    woff[it] = q * 32 + o * CH;
+                    wp[it] = psi + (qc0 * ndirs + d0) * 8 + o * CH - (long)(qy + qz) * wstride;
+                }
+            }
+        }
+    }
     const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay, az4 = T(4) * az, az2 = T(2) * az;
-    const int skew = jy + kz;
     const int nsteps = len + 6;
     auto step = [&](int s, In3<T>& use, In3<T>& fill) {
         const int ir = s - skew;
@@ -684,21 +747,19 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 store4(pp, o[0], o[1], o[2], o[3]);
                 store4(pp + 4, o[4], o[5], o[6], o[7]);
             }
-            if (jy == 3 && J + 1 < nTy)
-                store4(yf + (((long)(J + 1) * nz + kl) * nx + il) * 4, yo[0], yo[1], yo[2], yo[3]);
-            if (kz == 3 && K + 1 < nTz)
-                store4(zf + (((long)(K + 1) * ny + jl) * nx + il) * 4, zo[0], zo[1], zo[2], zo[3]);
-            if (ir == len - 1 && I + 1 < nTx)
-                store4(xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4, xin[0], xin[1], xin[2], xin[3]);
+            if (ystore) store4(yout0 + s * 4, yo[0], yo[1], yo[2], yo[3]);
+            if (zstore) store4(zout0 + s * 4, zo[0], zo[1], zo[2], zo[3]);
+            if (xstore && ir == len - 1) store4(xout, xin[0], xin[1], xin[2], xin[3]);
         }
         if constexpr (FUSED) {
             const int wave = threadIdx.x >> 6;
             lds_t<double>* rs = as_lds(red) + ((s % (2 * RF)) * nwaves + wave) * 128;
-#pragma unroll
-            for (int n = 0; n < 8; ++n) acc[n] = rows_sum(acc[n]);
-            if (lane < 16) {
-#pragma unroll
-                for (int n = 0; n < 8; ++n) rs[lane * 8 + n] = acc[n];
+            double r0, r1;
+            rows_sum8(acc, r0, r1);
+            {
+                const int kr = lane >> 4;
+                *reinterpret_cast<lds_t<dvec2>*>(rs + (lane & 15) * 8 + 2 * (kr >> 1) + 4 * (kr & 1)) =
+                    dvec2{r0, r1};
             }
             if ((s + 1) % RF == 0 || s == nsteps - 1) {
                 __syncthreads();
@@ -730,37 +791,26 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             // bytes.  LDS operations of one wave execute in order, so the
             // reads below see this step's writes.
             __builtin_amdgcn_wave_barrier();
-            constexpr int CH = 16 / sizeof(T);          // values per 16-byte piece
-            const int per = nvalid * 8 / CH;            // pieces per pencil block
-            const int total = 16 * per;
-            for (int base = 0; base < total; base += 64) {
-                const int id = base + lane;
-                const int q = id / per, o = id - q * per;
-                const int qy = q & 3, qz = q >> 2;
-                const int qjl = J * 4 + qy, qkl = K * 4 + qz;
-                const int qir = s - (qy + qz);
-                const bool qact = id < total && qjl < ny && qkl < nz && qir >= 0 && qir < len;
-                if (qact) {
-                    const int qil = i0 + qir;
-                    const int qi = rx ? nx - 1 - qil : qil;
-                    const int qj = ry ? ny - 1 - qjl : qjl;
-                    const int qk = rz ? nz - 1 - qkl : qkl;
-                    const long qc = ((long)qk * ny + qj) * nx + qi;
-                    const lds_t<T>* sp = as_lds(stg) + q * 32 + o * CH;
-                    T* gp = psi + (qc * ndirs + d0) * 8 + o * CH;
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                if ((unsigned)(s - wsk[it]) < (unsigned)len) {
+                    const lds_t<T>* sp = as_lds(stg) + woff[it];
                     // psi is written once per sweep and not read back by this
                     // kernel: nontemporal stores keep it from displacing the
                     // face and source data in the caches
                     if constexpr (sizeof(T) == 8) {
                         typedef double d2v __attribute__((ext_vector_type(2)));
                         typedef __attribute__((address_space(3))) d2v lds_d2v;
-                        __builtin_nontemporal_store(*reinterpret_cast<const lds_d2v*>(sp), reinterpret_cast<d2v*>(gp));
+                        __builtin_nontemporal_store(*reinterpret_cast<const lds_d2v*>(sp),
+                                                    reinterpret_cast<d2v*>(wp[it]));
                     } else {
                         typedef float f4v __attribute__((ext_vector_type(4)));
                         typedef __attribute__((address_space(3))) f4v lds_f4v;
-                        __builtin_nontemporal_store(*reinterpret_cast<const lds_f4v*>(sp), reinterpret_cast<f4v*>(gp));
+                        __builtin_nontemporal_store(*reinterpret_cast<const lds_f4v*>(sp),
+                                                    reinterpret_cast<f4v*>(wp[it]));
                     }
                 }
+                wp[it] += wstride;
             }
             __builtin_amdgcn_wave_barrier();
         }
