@@ -442,15 +442,15 @@ hipError_t launch_sip_apply(const DsaGeom& g, const int* thick_cell, const int* 
 // ---------------------------------------------------------------------------
 // preconditioned CG
 // ---------------------------------------------------------------------------
+// deterministic block sum (sh: at least 16 doubles): the wave sums, then the
+// waves in wave order
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
     double r = sh[0];
+    for (int k = 1; k < nw; ++k) r += sh[k];
     __syncthreads();
     return r;
 }
@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       CgScalars* sc, const double* __restrict__ res_part,
                                                       int res_nparts,
                                                       double* __restrict__ res_out, double* __restrict__ res_host) {
-    __shared__ double sh[768];
+    __shared__ double sh[48];
     constexpr int DIM = NN == 4 ? 2 : 3;
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
                                                        int nparts, CgScalars* s, CgScalars* s_host, double rtol,
                                                        int maxit, int it) {
     if (s->done) return;
-    __shared__ double sh[256];
+    __shared__ double sh[16];
     const double rz = reduce_parts(part_rz, nparts, sh);
     const double rr = reduce_parts(part_rz + nparts, nparts, sh);
     const double bb = it == 0 ? rr : s->bb;
@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
                                                         double* __restrict__ part_out, int nparts, CgScalars* s,
                                                         CgScalars* s_host, int it) {
     if (s->done) return;
-    __shared__ double sh[256];
+    __shared__ double sh[16];
     const double pq = reduce_parts(part_pq, nparts, sh);
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1010,7 +1010,7 @@ __global__ void __launch_bounds__(256) mg_l0_post_kernel(DsaGeom g, const int* _
                                                          MgDev m, double omega0, double* __restrict__ z,
                                                          double* __restrict__ part, const CgScalars* s) {
     if (s->done) return;
-    __shared__ double sh[256];
+    __shared__ double sh[16];
     const double* x1 = vmg_post_vec(m, 1);
     auto get = [&](int slot, double out[NN]) {
 #pragma unroll

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256) moment_kernel(long nc, int ndirs, const d
         }
     }
     if constexpr (RES) {
-        __shared__ double sh[768];
+        __shared__ double sh[48];
         block_sum3(s0, s1, s2, sh);
         if (threadIdx.x == 0) {
             part[blockIdx.x] = s0;
@@ -96,7 +96,7 @@ hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* p
 __global__ void __launch_bounds__(256) residual_part_kernel(long n, const double* __restrict__ a,
                                                             const double* __restrict__ b,
                                                             double* __restrict__ part) {
-    __shared__ double sh[768];
+    __shared__ double sh[48];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         double x = a[e], y = b[e], d = x - y;
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) residual_part_kernel(long n, const double
 
 __global__ void __launch_bounds__(256) residual_final_kernel(int nparts, const double* __restrict__ part,
                                                              double* __restrict__ out, double* __restrict__ out_host) {
-    __shared__ double sh[768];
+    __shared__ double sh[48];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int e = threadIdx.x; e < nparts; e += 256) {
         s0 += part[e];

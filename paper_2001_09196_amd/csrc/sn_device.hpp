@@ -158,25 +158,37 @@ __device__ __forceinline__ void cell_solve3(const T g[8], T ax, T ay, T az, T si
     }
 }
 
-// deterministic block reduction of three sums
-// (256 threads; sh: 768 doubles)
+// Sum over a 64-lane wave by an xor butterfly: every lane receives the same
+// sum, added in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// deterministic block reduction of three sums (blockDim.x a multiple of 64,
+// at most 1024; sh: at least 48 doubles): the wave sums, then the waves in
+// wave order
 __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
-    const int tid = threadIdx.x;
-    sh[tid] = a;
-    sh[256 + tid] = b;
-    sh[512 + tid] = c;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            sh[tid] += sh[tid + s];
-            sh[256 + tid] += sh[256 + tid + s];
-            sh[512 + tid] += sh[512 + tid + s];
-        }
-        __syncthreads();
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[16 + w] = b;
+        sh[32 + w] = c;
     }
+    __syncthreads();
     a = sh[0];
-    b = sh[256];
-    c = sh[512];
+    b = sh[16];
+    c = sh[32];
+    for (int k = 1; k < nw; ++k) {
+        a += sh[k];
+        b += sh[16 + k];
+        c += sh[32 + k];
+    }
+    __syncthreads();
 }
 
 }  // namespace sn
