@@ -44,6 +44,19 @@ def test_sweep2d_fp64(shape, transpose):
     assert rel_max(got, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(1, 600), (300, 1), (72, 128), (200, 64), (256, 520)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep2d_window_edges(shape, prec):
+    """Edge shapes of the 2D windowed sweep: a single column (the window
+    is all ramp) and a single row (one partly filled wave), widths with and
+    without interior chunks that have every lane inside its row, and a
+    chunked height whose first chunk is full (its top wave writes the
+    chunk boundary faces)."""
+    p = random_problem(2, shape[0], shape[1], 1, order=4, seed=shape[0] + 7 * shape[1])
+    got, ref = _sweep_case(p, False, with_inflow=True, prec=prec, seed=shape[0])
+    assert rel_max(got, ref) <= (1e-12 if prec == 0 else 2e-5)
+
+
 @pytest.mark.parametrize("shape,order", [((70, 19, 11), 4), ((9, 17, 23), 8), ((33, 8, 8), 4)])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sweep3d_fp64(shape, order, transpose):
@@ -184,6 +197,27 @@ def test_si_eta_inf_equals_plain():
     a = _si_gpu(p, tol=0.0, max_it=8, use_dsa=True, eta=math.inf)
     b = _si_gpu(p, tol=0.0, max_it=8, use_dsa=False)
     assert np.array_equal(a["phi"], b["phi"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_si_2d_inflow_faces_reused(prec):
+    """Source iteration with a seeded inflow: the face buffers are filled once
+    per precision within the call (the FP32 form alternates between zero-inflow
+    increment sweeps and FP64 sweeps with the inflow), and the converged
+    solution matches the oracle's."""
+    from paper_2001_09196_amd import sn_source_iterate
+    p = random_problem(2, 41, 77, 1, order=4, seed=61)
+    rng = np.random.default_rng(62)
+    inflow = rng.uniform(0, 1, (p.ndirs, sninputs.inflow_size(p.dim, p.nx, p.ny, p.nz)))
+    ref = oracle.source_iterate(p, tol=1e-13, max_it=3000, use_dsa=True, cg_rtol=1e-13, inflow=inflow)
+    say(f"SI 2d inflow prec={prec}")
+    with context(p) as ctx:
+        phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        r = sn_source_iterate(ctx, dev(p.q), dev(inflow), phi, tol=1e-11 if prec == 0 else 1e-8, max_it=3000,
+                              use_dsa=True, prec=prec, cg_rtol=1e-12, cg_maxit=5000)
+        got = phi.cpu().numpy()
+    assert r["rc"] == 0
+    assert rel_l2(got, ref["phi"]) <= (1e-9 if prec == 0 else 1e-5)
 
 
 def test_si_fp32_form_c1():
