@@ -546,6 +546,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     // last test left pending.
     int it = 0;  // iteration whose apply kernel runs next
     bool pending = false;
+    const bool speculate = phi_out != phi_si;
     int batch = std::max(0, std::min(ctx->cg_hint, o->cg_maxit));
     while (true) {
         if (pending && (rc = update(it - 1))) return rc;
@@ -555,8 +556,17 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if ((rc = apply(it))) return rc;
         ++it;
         pending = true;
+        // Without aliasing the final update phi_out = phi_si + P x can be
+        // enqueued ahead of the stop decision: the CG kernels never read
+        // phi_out (phi_old is read by the right-hand side only), and if the
+        // solve goes on the update is enqueued again after the next batch.
+        if (speculate)
+            HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
         // wait for the stop flag in pinned memory (written as soon as the
-        // test passes, ahead of the kernel's end) or for the batch to finish
+        // test passes, ahead of the kernel's end) or for the batch to finish.
+        // The event is queried on every turn of the loop: the query also
+        // makes the runtime hand the enqueued kernels to the device (with
+        // sparser queries the kernels were measured to start late)
         HIPCHK(hipEventRecord(ctx->cg_ev, ctx->stream));
         volatile int* flag = &hs.done;
         while (!*flag) {
@@ -567,7 +577,8 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if (hs.done || it > o->cg_maxit) break;
         batch = 4;
     }
-    HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+    if (!speculate)
+        HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->dsa_ev.emplace_back(e0, e1);

@@ -33,7 +33,11 @@ hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* p
     return hipGetLastError();
 }
 
-// One thread per cell: reads the cell's contiguous [ndirs][NN] block of psi.
+// Four lanes per cell: lane j of the cell sums directions j, j + 4, j + 8, ...
+// (the four lanes read four consecutive direction blocks of the cell's
+// contiguous [ndirs][NN] block of psi), then the lanes' sums are combined by
+// an xor butterfly, (s0 + s1) + (s2 + s3), and lane j writes nodes j (and
+// j + 4 when NN = 8).
 // RES: also the block partial sums of (phi - ref)^2, phi^2, ref^2 over the
 // written phi (part[3][gridDim.x]), the residual of source iteration.
 template <typename T, int NN, bool RES>
@@ -42,23 +46,32 @@ __global__ void __launch_bounds__(256) moment_kernel(long nc, int ndirs, const d
                                                      int accumulate, const double* __restrict__ ref,
                                                      double* __restrict__ part) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+    const int j = threadIdx.x & 3;
+    const long stride = ((long)gridDim.x * blockDim.x) >> 2;
+    for (long c = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2; c < nc; c += stride) {
         double acc[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) acc[n] = 0.0;
         const T* p = psi + c * ndirs * NN;
-        for (int d = 0; d < ndirs; ++d) {
+        for (int d = j; d < ndirs; d += 4) {
             const double wd = w[d];
 #pragma unroll
             for (int n = 0; n < NN; ++n) acc[n] = fma(wd, double(p[d * NN + n]), acc[n]);
         }
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
-            const double v = accumulate ? phi[c * NN + n] + acc[n] : acc[n];
-            phi[c * NN + n] = v;
+            acc[n] += __shfl_xor(acc[n], 1, 4);
+            acc[n] += __shfl_xor(acc[n], 2, 4);
+        }
+#pragma unroll
+        for (int h = 0; h < NN / 4; ++h) {
+            const int n = j + 4 * h;
+            const long e = c * NN + n;
+            const double v = accumulate ? phi[e] + acc[n] : acc[n];
+            phi[e] = v;
             if constexpr (RES) {
-                const double y = ref[c * NN + n], e = v - y;
-                s0 = fma(e, e, s0);
+                const double y = ref[e], d = v - y;
+                s0 = fma(d, d, s0);
                 s1 = fma(v, v, s1);
                 s2 = fma(y, y, s2);
             }

@@ -70,7 +70,7 @@ hipError_t launch_source(long nc, int nn, const double* sigma_s, const double* p
                          const double* q, T* src, hipStream_t st);
 // ref != nullptr: also the residual partial sums of (phi - ref)^2, phi^2,
 // ref^2 over the written phi, part[3][moment_blocks(nc)]
-inline int moment_blocks(long nc) { return (int)std::min<long>((nc + 255) / 256, 1 << 16); }
+inline int moment_blocks(long nc) { return (int)std::min<long>((4 * nc + 255) / 256, 1 << 16); }
 template <typename T>
 hipError_t launch_moment(long nc, int nn, int ndirs, const double* w, const T* psi, double* phi, int accumulate,
                          const double* ref, double* part, hipStream_t st);
