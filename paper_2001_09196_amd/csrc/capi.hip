@@ -1024,20 +1024,21 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     int status = SN_ERR_NOT_CONVERGED;
     bool verified = false;   // FP32 form: phi_SI last recomputed by an FP64 sweep
     bool refreshed = false;  // FP32 form: the 1e-4 refresh sweep has been done
+    const double refresh_at = 1e-4;
     for (; it < o->max_it; ++it) {
-        // FP64 form after the first iteration: the last kernel of the sweep
-        // writes the residual's partial sums, the DSA solve's first kernel
-        // reduces them into pinned host memory, and the value is read after
-        // the solve, which does not depend on it (one host synchronisation
-        // per iteration)
-        const bool defer = !incr && it > 0;
+        // After the first iteration the last kernel of the sweep writes the
+        // residual's partial sums, the DSA solve's first kernel reduces them
+        // into pinned host memory, and the value is read after the solve,
+        // which does not depend on it (one host wait per iteration).
+        const bool defer = it > 0;
         int res_n = 0;
+        const double* res_ref = defer ? phi : nullptr;
         if (!incr || it == 0) {
-            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, o->prec, ctx->phisi.p, 0,
-                                    defer ? phi : nullptr, &res_n)))
+            if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, o->prec, ctx->phisi.p, 0, res_ref, &res_n)))
                 return rc;
         } else {
-            if ((rc = do_sweep_flux(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, ctx->phisi.p, 1)))
+            if ((rc = do_sweep_flux(ctx, phi, ctx->phiprev.p, nullptr, nullptr, tr, o->prec, ctx->phisi.p, 1,
+                                    res_ref, &res_n)))
                 return rc;
         }
         verified = false;
@@ -1055,43 +1056,65 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
             }
             if (bnorm == 0.0) bnorm = 1.0;
         }
+        // FP64 sweeps in the FP32 form: once when the residual first drops
+        // below 1e-4 (this discards the FP32 rounding accumulated while the
+        // increments were large) and whenever it meets tol (the form may only
+        // stop on an exact residual).  phi_SI is recomputed from the iterate
+        // with one FP64 sweep and the increments continue from it.
+        auto wants_fp64 = [&](const double* r) {
+            const double res32 = std::sqrt(r[0]) / bnorm;
+            return res32 <= o->tol || (!refreshed && res32 <= refresh_at && o->tol < refresh_at);
+        };
+        auto refresh = [&](const double* iterate) -> int {
+            refreshed = true;
+            int e;
+            if ((e = do_sweep_flux(ctx, iterate, nullptr, q, inflow, tr, SN_FP64, ctx->phisi.p, 0))) return e;
+            if ((e = residual3(ctx, ctx->phisi.p, iterate, r3))) return e;
+            verified = true;
+            if (stats) stats->fp64_checks += 1;
+            return 0;
+        };
         if (incr) {
-            const double res32 = std::sqrt(r3[0]) / bnorm;
-            const double refresh_at = 1e-4;
-            if (res32 <= o->tol || (!refreshed && res32 <= refresh_at && o->tol < refresh_at)) {
-                // FP64 sweeps in the FP32 form: once when the residual first
-                // drops below 1e-4 (this discards the FP32 rounding accumulated
-                // while the increments were large) and whenever it meets tol (the
-                // form may only stop on an exact residual).  phi_SI is recomputed
-                // from phi with one FP64 sweep and the increments continue from it.
-                refreshed = true;
-                if ((rc = do_sweep_flux(ctx, phi, nullptr, q, inflow, tr, SN_FP64, ctx->phisi.p, 0))) return rc;
-                if ((rc = residual3(ctx, ctx->phisi.p, phi, r3))) return rc;
-                verified = true;
-                if (stats) stats->fp64_checks += 1;
-            }
+            if (!defer && wants_fp64(r3) && (rc = refresh(phi))) return rc;
+            // the iterate, for the next increment (and for a redo below)
             HIPCHK(hipMemcpyAsync(ctx->phiprev.p, phi, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         }
+        // phi <- phi_SI, corrected by the DSA solve from the iterate phi_old
         int cgi = 0;
-        if (o->use_dsa) {
-            sn_dsa_stats ds{};
-            rc = do_dsa(ctx, phi, ctx->phisi.p, phi, &o->dsa, &ds, defer ? ctx->fpart.p : nullptr, res_n);
-            cgi = ds.cg_iters;
-            if (rc) {
-                status = rc;
-                ++it;
-                break;
+        auto update = [&](const double* phi_old, bool with_res) -> int {
+            if (o->use_dsa) {
+                sn_dsa_stats ds{};
+                const int e =
+                    do_dsa(ctx, phi_old, ctx->phisi.p, phi, &o->dsa, &ds, with_res ? ctx->fpart.p : nullptr, res_n);
+                cgi = ds.cg_iters;
+                return e;
             }
-        } else {
-            if (defer) {
+            if (with_res) {
                 HIPCHK(launch_residual_final(res_n, ctx->fpart.p, ctx->res3.p, ctx->hpin->r3, ctx->stream));
                 HIPCHK(hipEventRecord(ctx->res_ev, ctx->stream));
             }
             HIPCHK(hipMemcpyAsync(phi, ctx->phisi.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-            if (defer) HIPCHK(hipEventSynchronize(ctx->res_ev));
+            if (with_res) HIPCHK(hipEventSynchronize(ctx->res_ev));
+            return 0;
+        };
+        if ((rc = update(phi, defer))) {
+            status = rc;
+            ++it;
+            break;
         }
-        if (defer)
+        if (defer) {
             for (int k = 0; k < 3; ++k) r3[k] = ctx->hpin->r3[k];
+            if (incr && wants_fp64(r3)) {
+                // the FP32 residual, known only now, asks for an FP64 sweep:
+                // this iteration is redone from its iterate, kept in phiprev
+                if ((rc = refresh(ctx->phiprev.p))) return rc;
+                if ((rc = update(ctx->phiprev.p, false))) {
+                    status = rc;
+                    ++it;
+                    break;
+                }
+            }
+        }
         const double res = std::sqrt(r3[0]) / bnorm;
         if (stats && stats->res_hist) stats->res_hist[it] = res;
         if (first < 0) first = res;
