@@ -819,9 +819,11 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         HIPCHK(launch_skew2d<double>(mesh->nx, mesh->ny, 1, c->sigt.p, c->sigskew64.p, c->stream));
         HIPCHK(launch_skew2d<float>(mesh->nx, mesh->ny, 1, c->sigt32.p, c->sigskew32.p, c->stream));
     } else {
+        // tile length along x: 32 (SN_SWEEP_TX in the environment, at most
+        // 32, the length of the sweep kernels' LDS tile)
         int tx = 32;
         if (const char* e = std::getenv("SN_SWEEP_TX")) tx = std::max(1, std::atoi(e));
-        g.TX = std::min(tx, mesh->nx);
+        g.TX = std::min(std::min(tx, 32), mesh->nx);
         g.nTx = (mesh->nx + g.TX - 1) / g.TX;
         g.nTy = (mesh->ny + 3) / 4;
         g.nTz = (mesh->nz + 3) / 4;

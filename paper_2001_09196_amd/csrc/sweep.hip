@@ -570,6 +570,69 @@ __device__ __forceinline__ void rows_sum8(const double v[8], double& r0, double&
 // fused sweep + moment: steps per workgroup barrier
 constexpr int RF = 4;
 
+// The tile's source and sigma_t, staged in LDS once per workgroup: every wave
+// of a block sweeps the same cells (one reflection class, different
+// directions), so the per-step loads of the waves become LDS reads of one
+// copy, loaded with contiguous runs (a pencil's cells are consecutive in
+// memory).  Layout [x][pencil][SRCP] in the reflected frame, nodes in memory
+// order; the pencil stride is padded by 16 bytes so that the 16 pencils of
+// one x fall on different LDS bank groups.
+// Only the FP64 kernels stage (measured: FP64 -4% psi sweep, -5% fused; the
+// FP32 fused sweep was 6% slower, so FP32 loads its inputs directly).
+constexpr int TXMAX = 32;  // longest tile along x
+template <typename T>
+constexpr bool staged_tile() {
+    return sizeof(T) == 8;
+}
+template <typename T>
+constexpr int src_pencil() {
+    return 8 + 16 / (int)sizeof(T);
+}
+template <typename T>
+struct TileIn {
+    static constexpr int NX = staged_tile<T>() ? TXMAX : 1;
+    T s[NX][16][src_pencil<T>()];
+    T sig[NX][16];
+};
+template <typename T>
+__device__ __forceinline__ const lds_t<T>* as_lds(const T* p) {
+    return (const lds_t<T>*)p;
+}
+// all threads of the block take part; the caller synchronises afterwards
+template <typename T>
+__device__ __forceinline__ void stage_tile(int nx, int ny, int nz, int m, int I, int J, int K, int TX,
+                                           const T* __restrict__ sigt, const T* __restrict__ src, TileIn<T>* t) {
+    const int rx = m & 1, ry = (m >> 1) & 1, rz = (m >> 2) & 1;
+    const int i0 = I * TX, len = min(TX, nx - i0);
+    const int ilo = rx ? nx - i0 - len : i0;  // lowest x of the tile's cells in memory
+    lds_t<T>* ts = as_lds(&t->s[0][0][0]);
+    lds_t<T>* tg = as_lds(&t->sig[0][0]);
+    const int per = len * 8;
+    for (int e = threadIdx.x; e < 16 * per; e += blockDim.x) {
+        const int q = e / per, r = e - q * per;
+        const int xm = r >> 3, n = r & 7;  // position in the pencil's memory run
+        const int qjl = J * 4 + (q & 3), qkl = K * 4 + (q >> 2);
+        T v = T(0);
+        if (qjl < ny && qkl < nz) {
+            const int qj = ry ? ny - 1 - qjl : qjl, qk = rz ? nz - 1 - qkl : qkl;
+            v = src[(((long)qk * ny + qj) * nx + ilo + xm) * 8 + n];
+        }
+        const int ir = rx ? len - 1 - xm : xm;
+        ts[(ir * 16 + q) * src_pencil<T>() + n] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * len; e += blockDim.x) {
+        const int q = e / len, xm = e - q * len;
+        const int qjl = J * 4 + (q & 3), qkl = K * 4 + (q >> 2);
+        T v = T(0);
+        if (qjl < ny && qkl < nz) {
+            const int qj = ry ? ny - 1 - qjl : qjl, qk = rz ? nz - 1 - qkl : qkl;
+            v = sigt[((long)qk * ny + qj) * nx + ilo + xm];
+        }
+        const int ir = rx ? len - 1 - xm : xm;
+        tg[ir * 16 + q] = v;
+    }
+}
+
 
 
 // FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
@@ -582,8 +645,9 @@ constexpr int RF = 4;
 template <typename T, int M, bool FUSED = false>
 __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, bool dok, T ax, T ay, T az,
                                              int I, int J, int K, int TX, int nTx, int nTy, int nTz,
-                                             const T* __restrict__ sigt, const T* __restrict__ src,
-                                             T* __restrict__ xf, T* __restrict__ yf, T* __restrict__ zf,
+                                             const TileIn<T>* tin, const T* __restrict__ sigt,
+                                             const T* __restrict__ src, T* __restrict__ xf, T* __restrict__ yf,
+                                             T* __restrict__ zf,
                                              T* __restrict__ psi, int d0, int nvalid, T* __restrict__ stg,
                                              double wgt = 0.0, double* __restrict__ red = nullptr,
                                              double* __restrict__ phio = nullptr, int nwaves = 0) {
@@ -615,6 +679,9 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     // memory along x.
     constexpr int cdir = rx ? -1 : 1;
     const int skew = jy + kz;  // lane's pencil lags the tile's first pencil by skew steps
+    // this lane's pencil in the LDS tile (FP64), or its cells in memory (FP32)
+    const lds_t<T>* tsrc = as_lds(&tin->s[0][lane & 15][0]);
+    const lds_t<T>* tsig = as_lds(&tin->sig[0][lane & 15]);
     const long c0 = rowbase + (rx ? nx - 1 - i0 : i0);
     const T* src0 = src + c0 * 8;
     const T* sig0 = sigt + c0;
@@ -626,8 +693,15 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     // they can be read at any time.
     auto fetch = [&](int ir, In3<T>& v) {
         const int irc = min(max(ir, 0), len - 1);
-        v.s = load8(src0 + cdir * irc * 8);
-        v.sig = sig0[cdir * irc];
+        if constexpr (staged_tile<T>()) {
+            const lds_t<T>* sp = tsrc + irc * (16 * src_pencil<T>());
+#pragma unroll
+            for (int n = 0; n < 8; ++n) v.s.v[n] = sp[n];
+            v.sig = tsig[irc * 16];
+        } else {
+            v.s = load8(src0 + cdir * irc * 8);
+            v.sig = sig0[cdir * irc];
+        }
         if (pen && jy == 0)
             v.y = load4(yin0 + irc * 4);
         else
@@ -837,22 +911,29 @@ __global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, in
                                                       int nTx, int nTy, int nTz, const int* __restrict__ tiles,
                                                       T* __restrict__ psi) {
     __shared__ __align__(16) T stage[6][16 * 4 * 8];
+    __shared__ __align__(16) TileIn<T> tin;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const int tile = tiles[blockIdx.x];
+    const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
+    // reflection of the class, from its first direction (always valid)
+    const int mc = groups[6 * blockIdx.y * groups_per_class];
+    const DirInfo dm = dirs[mc];
+    const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
+    if constexpr (staged_tile<T>()) {
+        stage_tile<T>(nx, ny, nz, m, I, J, K, TX, sigt, src, &tin);
+        __syncthreads();
+    }
     const int grp = blockIdx.y * groups_per_class + wave;
     const int* gi = groups + 6 * grp;
     const int d = gi[lane >> 4];
-    const int m0 = gi[0];            // first direction of the group (always valid)
+    const int m0 = gi[0];            // first direction of the group (-1: empty slot)
     if (m0 < 0) return;              // empty group slot: the whole wave leaves
     // consecutive directions d0 .. d0 + nvalid - 1: psi goes out through the
     // LDS stage; otherwise (nvalid = 0) every lane stores its own values
     const int d0 = gi[4], nvalid = gi[4] >= 0 ? gi[5] : 0;
     const bool dok = d >= 0;
     const int dd = dok ? d : m0;
-    const int tile = tiles[blockIdx.x];
-    const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
-    const DirInfo dm = dirs[m0];
-    const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
     const DirInfo di = dirs[dd];
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
     T* xd = xf + dd * xstride;
@@ -860,8 +941,8 @@ __global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, in
     T* zd = zf + dd * zstride;
 #define SN_CASE(MM)                                                                                               \
     case MM:                                                                                                      \
-        sweep3d_body<T, MM>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, xd, yd, \
-                            zd, psi, d0, nvalid, stage[wave]);                                                    \
+        sweep3d_body<T, MM>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, src, \
+                            xd, yd, zd, psi, d0, nvalid, stage[wave]);                                            \
         break;
     switch (m) {
         SN_CASE(0)
@@ -891,6 +972,7 @@ __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int n
                                                            long zstride, int TX, int nTx, int nTy, int nTz,
                                                            const int* __restrict__ tiles, double* __restrict__ phioct) {
     __shared__ __align__(16) double red[2 * RF * 6 * 128];
+    __shared__ __align__(16) TileIn<T> tin;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int grp = blockIdx.y * groups_per_class + wave;
@@ -903,6 +985,10 @@ __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int n
     const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
     const DirInfo dm = dirs[mc];
     const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
+    if constexpr (staged_tile<T>()) {
+        stage_tile<T>(nx, ny, nz, m, I, J, K, TX, sigt, src, &tin);
+        __syncthreads();
+    }
     const DirInfo di = dirs[dd];
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
     const double wgt = dok ? w[dd] : 0.0;
@@ -912,8 +998,8 @@ __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int n
     double* po = phioct + (long)blockIdx.y * nx * ny * nz * 8;
 #define SN_CASEF(MM)                                                                                             \
     case MM:                                                                                                     \
-        sweep3d_body<T, MM, true>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, sigt, src, \
-                                  xd, yd, zd, nullptr, -1, 0, nullptr, wgt, red, po, groups_per_class);          \
+        sweep3d_body<T, MM, true>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, \
+                                  src, xd, yd, zd, nullptr, -1, 0, nullptr, wgt, red, po, groups_per_class);     \
         break;
     switch (m) {
         SN_CASEF(0)
