@@ -175,7 +175,10 @@ typedef struct {
  * q: device [ncells] or NULL; inflow: device [ndirs][nbf] or NULL;
  * phi_inout: device [ncells][nn], initial guess in, last iterate out.
  * Waits on the host once per iteration (the residual and the CG stop flags
- * are read from pinned host memory).
+ * are read from pinned host memory).  With DSA, every CG solve after the
+ * first of a call starts from the previous solve's correction, scaled by a
+ * one-dimensional Galerkin projection onto the new right-hand side (the stop
+ * test stays ||r|| <= cg_rtol ||b||).
  * Returns OK, NOT_CONVERGED, DIVERGED or CG_BREAKDOWN (phi_inout holds the
  * last iterate in all three error cases). */
 int sn_source_iterate(sn_context *ctx, const double *q, const double *inflow, double *phi_inout,

@@ -486,8 +486,10 @@ bool bad_dsa_opts(const sn_dsa_opts& o) {
 // the solve's first kernel into ctx->res3 and the pinned ctx->hpin->r3 (the
 // host's wait for the solve's stop flag, which a later kernel writes, then
 // also covers that read-back)
+// warm: start the CG from the previous call's solution (within one
+// source-iteration call), projected onto the new right-hand side
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
-           sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0) {
+           sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0, bool warm = false) {
     const long n = ctx->nc * ctx->nn;
     if (ctx->nthick == 0) {
         if (res_part)
@@ -534,9 +536,13 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     hs.breakdown = 0;
     hs.iters = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    if (warm)
+        HIPCHK(launch_dsa_warm(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si,
+                               ctx->cx.p, ctx->cq.p, ctx->parta.p, ctx->nparts, ctx->stream));
     HIPCHK(launch_dsa_rhs(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->binv.p,
                           ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->partb.p, ctx->nparts, bj, ctx->scal.p,
-                          res_part, res_nparts, ctx->res3.p, ctx->hpin->r3, ctx->stream));
+                          res_part, res_nparts, ctx->res3.p, ctx->hpin->r3, warm ? ctx->cq.p : nullptr,
+                          warm ? ctx->parta.p : nullptr, ctx->stream));
     if (!bj && (rc = vcycle())) return rc;
     // Batches of iterations, each ended by the stop test of the next
     // iteration (its apply kernel), then one stream synchronisation and a look
@@ -918,7 +924,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     if ((rc = c->binv.ensure((size_t)std::max(nthick, 1) * c->nn * c->nn)) || (rc = c->cx.ensure(nf)) ||
         (rc = c->cr.ensure(nf)) || (rc = c->cz.ensure(nf)) || (rc = c->cp.ensure(nf)) || (rc = c->cp1.ensure(nf)) ||
         (rc = c->cq.ensure(nf)) || (rc = c->nbr.ensure((size_t)std::max(nthick, 1) * 2 * dim)) ||
-        (rc = c->parta.ensure(2 * c->nparts)) || (rc = c->partb.ensure(2 * c->nparts)) ||
+        (rc = c->parta.ensure(3 * c->nparts)) || (rc = c->partb.ensure(3 * c->nparts)) ||
         (rc = c->scal.ensure(1)))
         return rc;
     HIPCHK(launch_block_jacobi(dg, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, c->binv.p, c->stream));
@@ -1027,6 +1033,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     bool verified = false;   // FP32 form: phi_SI last recomputed by an FP64 sweep
     bool refreshed = false;  // FP32 form: the 1e-4 refresh sweep has been done
     const double refresh_at = 1e-4;
+    int dsa_done = 0;  // DSA solves of this call
     for (; it < o->max_it; ++it) {
         // After the first iteration the last kernel of the sweep writes the
         // residual's partial sums, the DSA solve's first kernel reduces them
@@ -1083,11 +1090,13 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         }
         // phi <- phi_SI, corrected by the DSA solve from the iterate phi_old
         int cgi = 0;
+        // (the CG warm-starts from the previous iteration's correction)
         auto update = [&](const double* phi_old, bool with_res) -> int {
             if (o->use_dsa) {
                 sn_dsa_stats ds{};
-                const int e =
-                    do_dsa(ctx, phi_old, ctx->phisi.p, phi, &o->dsa, &ds, with_res ? ctx->fpart.p : nullptr, res_n);
+                const int e = do_dsa(ctx, phi_old, ctx->phisi.p, phi, &o->dsa, &ds,
+                                     with_res ? ctx->fpart.p : nullptr, res_n, dsa_done > 0);
+                ++dsa_done;
                 cgi = ds.cg_iters;
                 return e;
             }

@@ -477,10 +477,68 @@ __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, long b
     }
 }
 
-// b = coef M (phi_si - phi_old) on thick cells; x = 0, r = b, p = 0; with the
-// block-Jacobi preconditioner (bj = 1) also z = B^{-1} r and the r.z partials
-// [0..nparts); the b.b partials go to [nparts..2 nparts).  With the multigrid
-// preconditioner the V-cycle produces z and the r.z partials.
+// right-hand side of thick slot s: b = coef M (phi_si - phi_old)
+template <int NN>
+__device__ __forceinline__ void dsa_rhs_at(const DsaGeom& g, const int* __restrict__ thick_cell,
+                                           const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
+                                           int mass_kind, const double* __restrict__ phi_old,
+                                           const double* __restrict__ phi_si, int s, double t[NN]) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    const long c = thick_cell[s];
+    const double coef = mass_kind == 1 ? sigma_t[c] : sigma_s[c];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) t[n] = phi_si[c * NN + n] - phi_old[c * NN + n];
+#pragma unroll
+    for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
+#pragma unroll
+    for (int n = 0; n < NN; ++n) t[n] *= coef;
+}
+
+// Warm start of the CG from the previous solution x_p (one-dimensional
+// Galerkin projection: x0 = alpha x_p with alpha = x_p.b / x_p.D x_p, which
+// never increases the D-norm error of the zero start): w = D x_p and the
+// partials x_p.b [0..nparts), x_p.w [nparts..2 nparts).
+template <int NN>
+__global__ void __launch_bounds__(256) dsa_warm_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                       const int* __restrict__ nbr,
+                                                       const double* __restrict__ sigma_t,
+                                                       const double* __restrict__ sigma_s, int mass_kind,
+                                                       const double* __restrict__ phi_old,
+                                                       const double* __restrict__ phi_si,
+                                                       const double* __restrict__ xp, double* __restrict__ w,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[16];
+    auto get = [&](int slot, double out[NN]) {
+#pragma unroll
+        for (int n = 0; n < NN; ++n) out[n] = xp[(long)slot * NN + n];
+    };
+    double xb = 0.0, xw = 0.0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double b[NN], xK[NN], o[NN];
+        dsa_rhs_at<NN>(g, thick_cell, sigma_t, sigma_s, mass_kind, phi_old, phi_si, t, b);
+        get(t, xK);
+        sip_rows<NN>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, xK, get, o);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            w[(long)t * NN + n] = o[n];
+            xb = fma(xK[n], b[n], xb);
+            xw = fma(xK[n], o[n], xw);
+        }
+    }
+    xb = block_reduce(xb, sh);
+    xw = block_reduce(xw, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = xb;
+        part[gridDim.x + blockIdx.x] = xw;
+    }
+}
+
+// b = coef M (phi_si - phi_old) on thick cells; x = 0 and r = b, or with a
+// warm start (wpart != nullptr, partials of dsa_warm_kernel) x = alpha x and
+// r = b - alpha w; p = 0.  With the block-Jacobi preconditioner (bj = 1) also
+// z = B^{-1} r and the r.z partials [0..nparts); r.r partials go to
+// [nparts..2 nparts), b.b partials to [2 nparts..3 nparts).  With the
+// multigrid preconditioner the V-cycle produces z and the r.z partials.
 // Block 0 also resets the CG scalars and, given res_part, reduces the
 // source-iteration residual partials into res_out (device) and res_host
 // (pinned host memory).
@@ -495,9 +553,16 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
                                                       double* __restrict__ p, double* __restrict__ part,
                                                       CgScalars* sc, const double* __restrict__ res_part,
                                                       int res_nparts,
-                                                      double* __restrict__ res_out, double* __restrict__ res_host) {
+                                                      double* __restrict__ res_out, double* __restrict__ res_host,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ wpart) {
     __shared__ double sh[48];
-    constexpr int DIM = NN == 4 ? 2 : 3;
+    double alpha = 0.0;
+    if (wpart) {
+        const double xb = reduce_parts(wpart, gridDim.x, sh);
+        const double xw = reduce_parts(wpart + gridDim.x, gridDim.x, sh);
+        alpha = xw > 0.0 ? xb / xw : 0.0;
+    }
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             sc->rz[0] = sc->rz[1] = 0.0;
@@ -525,48 +590,66 @@ __global__ void __launch_bounds__(256) dsa_rhs_kernel(DsaGeom g, const int* __re
             __syncthreads();
         }
     }
-    double rz = 0.0, bb = 0.0;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
-        const long c = thick_cell[s];
-        const double coef = mass_kind == 1 ? sigma_t[c] : sigma_s[c];
-        double t[NN], zz[NN];
+        double b[NN], t[NN], zz[NN];
+        dsa_rhs_at<NN>(g, thick_cell, sigma_t, sigma_s, mass_kind, phi_old, phi_si, s, b);
 #pragma unroll
-        for (int n = 0; n < NN; ++n) t[n] = phi_si[c * NN + n] - phi_old[c * NN + n];
-#pragma unroll
-        for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
-#pragma unroll
-        for (int n = 0; n < NN; ++n) t[n] *= coef;
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)s * NN + n;
+            if (wpart) {
+                t[n] = fma(-alpha, w[e], b[n]);
+                x[e] = alpha * x[e];
+            } else {
+                t[n] = b[n];
+                x[e] = 0.0;
+            }
+        }
         if constexpr (BJ) bj_apply<NN>(binv, g.nthick, s, t, zz);
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const long e = (long)s * NN + n;
-            x[e] = 0.0;
             r[e] = t[n];
             p[e] = 0.0;
             if constexpr (BJ) {
                 z[e] = zz[n];
                 rz = fma(t[n], zz[n], rz);
             }
-            bb = fma(t[n], t[n], bb);
+            rr = fma(t[n], t[n], rr);
+            bb = fma(b[n], b[n], bb);
         }
     }
     rz = block_reduce(rz, sh);
+    rr = block_reduce(rr, sh);
     bb = block_reduce(bb, sh);
     if (threadIdx.x == 0) {
         if constexpr (BJ) part[blockIdx.x] = rz;
-        part[gridDim.x + blockIdx.x] = bb;
+        part[gridDim.x + blockIdx.x] = rr;
+        part[2 * gridDim.x + blockIdx.x] = bb;
     }
+}
+
+hipError_t launch_dsa_warm(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                           const double* sigma_s, int mass_kind, const double* phi_old, const double* phi_si,
+                           const double* xp, double* w, double* part, int nparts, hipStream_t st) {
+    if (g.nn == 4)
+        hipLaunchKernelGGL(dsa_warm_kernel<4>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, xp, w, part);
+    else
+        hipLaunchKernelGGL(dsa_warm_kernel<8>, dim3(nparts), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, xp, w, part);
+    return hipGetLastError();
 }
 
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
                           CgScalars* s, const double* res_part, int res_nparts, double* res_out, double* res_host,
-                          hipStream_t st) {
+                          const double* w, const double* wpart, hipStream_t st) {
 #define SN_RHS(NN, BJ)                                                                                        \
     hipLaunchKernelGGL((dsa_rhs_kernel<NN, BJ>), dim3(nparts), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s, \
                        mass_kind, phi_old, phi_si, binv, x, r, z, p, part, s, res_part, res_nparts,              \
-                       res_out, res_host)
+                       res_out, res_host, w, wpart)
     if (g.nn == 4) {
         if (bj) SN_RHS(4, true);
         else SN_RHS(4, false);
@@ -604,7 +687,7 @@ __global__ void __launch_bounds__(256) cg_apply_kernel(DsaGeom g, const int* __r
     __shared__ double sh[16];
     const double rz = reduce_parts(part_rz, nparts, sh);
     const double rr = reduce_parts(part_rz + nparts, nparts, sh);
-    const double bb = it == 0 ? rr : s->bb;
+    const double bb = it == 0 ? reduce_parts(part_rz + 2 * nparts, nparts, sh) : s->bb;
     if (sqrt(rr) <= rtol * sqrt(bb) || it >= maxit || bb == 0.0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             s->bb = bb;

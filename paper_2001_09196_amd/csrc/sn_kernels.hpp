@@ -115,14 +115,20 @@ struct CgScalars {
     int done, iters, breakdown, pad;
 };
 
-// right-hand side and CG start; also resets s and, given res_part, reduces
-// res_nparts source-iteration residual partials into res_out (device) and
-// res_host (pinned host memory)
+// warm start of the CG from its previous solution xp: w = D xp and the
+// partials of xp.b, xp.w (part: 2 * nparts)
+hipError_t launch_dsa_warm(const DsaGeom& g, const int* thick_cell, const int* nbr, const double* sigma_t,
+                           const double* sigma_s, int mass_kind, const double* phi_old, const double* phi_si,
+                           const double* xp, double* w, double* part, int nparts, hipStream_t st);
+// right-hand side and CG start (x = 0, or x = alpha x with the warm-start
+// partials wpart and w = D x); partials r.z, r.r, b.b in part (3 * nparts);
+// also resets s and, given res_part, reduces res_nparts source-iteration
+// residual partials into res_out (device) and res_host (pinned host memory)
 hipError_t launch_dsa_rhs(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                           int mass_kind, const double* phi_old, const double* phi_si, const double* binv,
                           double* x, double* r, double* z, double* p, double* part, int nparts, int bj,
                           CgScalars* s, const double* res_part, int res_nparts, double* res_out, double* res_host,
-                          hipStream_t st);
+                          const double* w, const double* wpart, hipStream_t st);
 hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell, int* nbr,
                                   hipStream_t st);
 // CG iteration `it` in two kernels.  apply: the stop test (at it = maxit
