@@ -901,8 +901,16 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
 // block: direction group w of that class (four directions, -1 = unused slot).
 // The waves of a block read the same cells' source and sigma_t, which one
 // compute unit's L1 then serves to all of them.
+// The compiler is told how many waves per SIMD to schedule for: FP64 runs two
+// (its register use allows no more), FP32 three (measured at C5: 11.0 ->
+// 9.4 ms against the default schedule for four or more).
 template <typename T>
-__global__ void __launch_bounds__(384) sweep3d_kernel(int nx, int ny, int nz, int ndirs,
+constexpr int psi3d_waves() {
+    return sizeof(T) == 8 ? 2 : 3;
+}
+template <typename T>
+__global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(psi3d_waves<T>(), psi3d_waves<T>())))
+sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const DirInfo* __restrict__ dirs, int transpose,
                                                       const int* __restrict__ groups, int groups_per_class,
                                                       const T* __restrict__ sigt, const T* __restrict__ src,
