@@ -301,6 +301,13 @@ def main():
         except Exception as e:  # report, do not hide
             out["sweep3d_c5"] = {"error": repr(e)}
 
+    # ---- 3D solves to 1e-8 in both forms (C3, C5) ----
+    if not args.no_3d:
+        try:
+            out["time_to_1e-8_3d"] = bench_to_tolerance_3d(log)
+        except Exception as e:  # report, do not hide
+            out["time_to_1e-8_3d"] = {"error": repr(e)}
+
     # ---- CPU oracle on the same workload (bounded: one solve to 1e-8) ----
     if not args.no_cpu_baseline:
         import oracle
@@ -435,6 +442,60 @@ def bench_3d(log):
                 f"dsa {res[name]['dsa_ms']:.3f} ms, CG {r['cg_hist'].tolist()}")
             del phi
     return res
+
+
+def bench_to_tolerance_3d(log):
+    """C3 and C5 solved to 1e-8 from phi = 0 in both forms (one timed solve
+    each, after a first call that builds the context's workspace): seconds,
+    source iterations, FP32 form against FP64, and for C3 both against the
+    oracle's converged flux at its stored sample points."""
+    import numpy as np
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_source_iterate
+    dev = torch.device("cuda:0")
+    gold_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c3_phi.json")
+    out = {}
+    for name in ("c3", "c5"):
+        p = sninputs.config(name)
+        nc, nn = p.ncells, p.nn
+        st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
+        ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
+        q = torch.tensor(p.q, dtype=torch.float64, device=dev)
+        res = {"workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.ndirs} dirs", "cg_rtol": CG_RTOL}
+        phis = {}
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
+            for form, prec in (("fp64", SN_FP64), ("fp32", SN_FP32)):
+                phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
+                sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
+                                  cg_maxit=2000)
+                phi.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=2000, use_dsa=True, prec=prec,
+                                      cg_rtol=CG_RTOL, cg_maxit=2000)
+                torch.cuda.synchronize()
+                res[form] = {"seconds": time.perf_counter() - t0, "iters": r["iters"], "rc": r["rc"],
+                             "cg_iters_total": int(r["cg_hist"][:r["iters"]].sum())}
+                phis[form] = phi
+                log(f"{name} to 1e-8 {form}: {res[form]['seconds']:.3f} s, {r['iters']} iterations")
+        res["fp32_speedup"] = res["fp64"]["seconds"] / res["fp32"]["seconds"]
+        res["fp32_vs_fp64_rel_l2"] = float(torch.linalg.norm(phis["fp32"] - phis["fp64"]) /
+                                           torch.linalg.norm(phis["fp64"]))
+        if name == "c3" and os.path.exists(gold_path):
+            gold = json.load(open(gold_path))
+            res["oracle_samples"] = (f"{len(gold['sample_index'])} values of the oracle's flux solved to residual "
+                                     f"{gold['res_last']:.1e}; the gap below is the 1e-8 stop of these solves")
+            idx = torch.tensor(gold["sample_index"], dtype=torch.long, device=dev)
+            ref = torch.tensor(gold["sample_value"], dtype=torch.float64, device=dev)
+            for form in ("fp64", "fp32"):
+                got = phis[form].reshape(-1)[idx]
+                res[form]["vs_oracle_samples_rel_l2"] = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+        out[name] = res
+        del phis
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
