@@ -91,7 +91,7 @@ struct sn_context {
     DevBuf<double> cx, cr, cz, cp, cp1, cq, parta, partb;
     DevBuf<int> nbr;
     DevBuf<CgScalars> scal;
-    int cg_hint = 8;
+    int cg_hint = 8, cg_hint2 = 8;  // CG iterations of the last two solves
     // pinned host copies of the device scalars (async read-back) and the
     // event that marks the latest residual copy
     struct HostScalars {
@@ -545,15 +545,18 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
                           warm ? ctx->parta.p : nullptr, ctx->stream));
     if (!bj && (rc = vcycle())) return rc;
     // Batches of iterations, each ended by the stop test of the next
-    // iteration (its apply kernel), then one stream synchronisation and a look
+    // iteration (its apply kernel), then one host wait and a look
     // at the stop flags, which the kernels also write to pinned host memory.
-    // The first batch is sized by the previous call's iteration count; when
+    // The first batch is sized by the last two calls' iteration counts; when
     // a batch does not suffice, the next one starts with the update that the
     // last test left pending.
     int it = 0;  // iteration whose apply kernel runs next
     bool pending = false;
     const bool speculate = phi_out != phi_si;
-    int batch = std::max(0, std::min(ctx->cg_hint, o->cg_maxit));
+    // (one more than the larger of the last two counts: a batch that falls
+    // short costs a host round trip and a trickle of late launches, surplus
+    // iterations only early-exit kernels)
+    int batch = std::max(0, std::min(std::max(ctx->cg_hint, ctx->cg_hint2) + 1, o->cg_maxit));
     while (true) {
         if (pending && (rc = update(it - 1))) return rc;
         const int nb = std::min(batch, o->cg_maxit - it);
@@ -589,6 +592,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->dsa_ev.emplace_back(e0, e1);
     }
+    ctx->cg_hint2 = ctx->cg_hint;
     ctx->cg_hint = hs.iters;
     if (stats) {
         stats->cg_iters = hs.iters;
