@@ -740,6 +740,28 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
                                                         CgScalars* s_host, int it) {
     if (s->done) return;
     __shared__ double sh[16];
+    // The first cell's operands are loaded before the reduction of the
+    // partials, whose barriers also order memory accesses, so that the loads
+    // overlap it (the C2 thick set has one cell per thread); in 2D the
+    // block inverse too.
+    constexpr int NB = NN == 4 ? NN * NN : 1;
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    double x0[NN], p0[NN], q0[NN], r0[NN], b0[NB];
+    if (t0 < g.nthick) {
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)t0 * NN + n;
+            x0[n] = x[e];
+            p0[n] = p[e];
+            q0[n] = q[e];
+            r0[n] = r[e];
+        }
+        if constexpr (BJ && NN == 4) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) b0[k] = binv[(long)k * g.nthick + t0];
+        }
+    }
     const double pq = reduce_parts(part_pq, nparts, sh);
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -759,17 +781,32 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
     }
     const double alpha = s->rz[it & 1] / pq;
     double rz = 0.0, rr = 0.0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+    auto cell = [&](int t, const double xv[NN], const double pv[NN], const double qv[NN], const double rin[NN],
+                    bool pre) {
         double rv[NN], zv[NN];
 #pragma unroll
         for (int n = 0; n < NN; ++n) {
             const long e = (long)t * NN + n;
-            x[e] = fma(alpha, p[e], x[e]);
-            rv[n] = fma(-alpha, q[e], r[e]);
+            x[e] = fma(alpha, pv[n], xv[n]);
+            rv[n] = fma(-alpha, qv[n], rin[n]);
             r[e] = rv[n];
         }
         if constexpr (BJ) {
-            bj_apply<NN>(binv, g.nthick, t, rv, zv);
+            if constexpr (NN == 4) {
+                if (pre) {
+#pragma unroll
+                    for (int i = 0; i < NN; ++i) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NN; ++j) v = fma(b0[i * NN + j], rv[j], v);
+                        zv[i] = v;
+                    }
+                } else {
+                    bj_apply<NN>(binv, g.nthick, t, rv, zv);
+                }
+            } else {
+                bj_apply<NN>(binv, g.nthick, t, rv, zv);
+            }
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
                 z[(long)t * NN + n] = zv[n];
@@ -780,6 +817,19 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
 #pragma unroll
             for (int n = 0; n < NN; ++n) rr = fma(rv[n], rv[n], rr);
         }
+    };
+    if (t0 < g.nthick) cell(t0, x0, p0, q0, r0, true);
+    for (int t = t0 + stride; t < g.nthick; t += stride) {
+        double xv[NN], pv[NN], qv[NN], rin[NN];
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)t * NN + n;
+            xv[n] = x[e];
+            pv[n] = p[e];
+            qv[n] = q[e];
+            rin[n] = r[e];
+        }
+        cell(t, xv, pv, qv, rin, false);
     }
     rz = block_reduce(rz, sh);
     rr = block_reduce(rr, sh);
