@@ -693,14 +693,14 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     // they can be read at any time.
     auto fetch = [&](int ir, In3<T>& v) {
         const int irc = min(max(ir, 0), len - 1);
-        if constexpr (staged_tile<T>()) {
+        if constexpr (!staged_tile<T>()) {
+            v.s = load8(src0 + cdir * irc * 8);
+            v.sig = sig0[cdir * irc];
+        } else if constexpr (FUSED) {
             const lds_t<T>* sp = tsrc + irc * (16 * src_pencil<T>());
 #pragma unroll
             for (int n = 0; n < 8; ++n) v.s.v[n] = sp[n];
             v.sig = tsig[irc * 16];
-        } else {
-            v.s = load8(src0 + cdir * irc * 8);
-            v.sig = sig0[cdir * irc];
         }
         if (pen && jy == 0)
             v.y = load4(yin0 + irc * 4);
@@ -781,9 +781,20 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             }
             const int i = rx ? nx - 1 - il : il;
             const long c = rowbase + i;
-            T g[8], u[8];
+            T g[8], u[8], sg;
+            if constexpr (staged_tile<T>() && !FUSED) {
+                // psi kernel: read from the LDS tile when used, not a step
+                // ahead, which keeps the source out of the prefetch registers
+                // (three waves per SIMD fit, so two workgroups per CU)
+                const lds_t<T>* sp = tsrc + ir * (16 * src_pencil<T>());
 #pragma unroll
-            for (int n = 0; n < 8; ++n) g[n] = use.s.v[n ^ M];
+                for (int n = 0; n < 8; ++n) g[n] = sp[n ^ M];
+                sg = tsig[ir * 16];
+            } else {
+#pragma unroll
+                for (int n = 0; n < 8; ++n) g[n] = use.s.v[n ^ M];
+                sg = use.sig;
+            }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 // x face: local nodes (0, t) += 4 ax xin, (1, t) -= 2 ax xin ; t = b + 2c
@@ -798,7 +809,7 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 g[t] = fma(az4, zi[t], g[t]);
                 g[t + 4] = fma(-az2, zi[t], g[t + 4]);
             }
-            cell_solve3(g, ax, ay, az, use.sig, u);
+            cell_solve3(g, ax, ay, az, sg, u);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 xin[t] = u[2 * t + 1];
@@ -901,15 +912,13 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
 // block: direction group w of that class (four directions, -1 = unused slot).
 // The waves of a block read the same cells' source and sigma_t, which one
 // compute unit's L1 then serves to all of them.
-// The compiler is told how many waves per SIMD to schedule for: FP64 runs two
-// (its register use allows no more), FP32 three (measured at C5: 11.0 ->
-// 9.4 ms against the default schedule for four or more).
+// The compiler is told to schedule for three waves per SIMD, so that two
+// six-wave workgroups share a CU.  Measured at C5: FP32 11.0 -> 9.4 ms against
+// the default schedule for four or more waves; FP64 16.0 -> 15.7 ms against
+// two waves per SIMD.
+constexpr int PSI3D_WAVES = 3;
 template <typename T>
-constexpr int psi3d_waves() {
-    return sizeof(T) == 8 ? 2 : 3;
-}
-template <typename T>
-__global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(psi3d_waves<T>(), psi3d_waves<T>())))
+__global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(PSI3D_WAVES, PSI3D_WAVES)))
 sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const DirInfo* __restrict__ dirs, int transpose,
                                                       const int* __restrict__ groups, int groups_per_class,
