@@ -17,6 +17,11 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsn.so")
 SOURCES = ["sweep.hip", "flux.hip", "dsa.hip", "capi.hip"]
 HOST_ONLY = {"capi.hip"}  # host code only: no device compilation pass
+# The sweeps issue from one or two waves per SIMD, so their speed depends on how
+# well independent instructions are interleaved in the in-order stream; the
+# iterative ILP machine scheduler measured 167 -> 161 us (FP64) and 119 -> 116
+# us (FP32) on the 256^2 S8 2D sweep, and no change on the 3D sweeps.
+EXTRA = {"sweep.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -26,6 +31,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-u
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
     extra = ["--cuda-host-only"] if src in HOST_ONLY else []
+    extra += EXTRA.get(src, [])
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
