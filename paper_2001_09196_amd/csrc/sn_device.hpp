@@ -25,6 +25,7 @@
 // |Omega_a| (face mass) psi_up on the a = 0 face becomes
 //   +4 a_axis psi_up on node 0 and -2 a_axis psi_up on node 1 of that axis.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 namespace sn {
@@ -47,6 +48,32 @@ __device__ __forceinline__ float rcp(float d) {
     float r = __builtin_amdgcn_rcpf(d);
     r = fmaf(r, fmaf(-d, r, 1.0f), r);
     return r;
+}
+
+// Reciprocals of two or four denominators P^2 + Q^2 of the cell solves.  In
+// FP64 they come from one reciprocal of their product (one v_rcp_f64 and its
+// Newton steps instead of two or four): the product of four such factors
+// stays inside the double range for any cross sections and cell sizes below
+// about 1e38 in magnitude.  FP32 takes each reciprocal on its own, since the
+// product could leave the float range.
+__device__ __forceinline__ void rcp_each(const double d[2], double r[2], std::integral_constant<int, 2>) {
+    const double R = rcp(d[0] * d[1]);
+    r[0] = R * d[1];
+    r[1] = R * d[0];
+}
+__device__ __forceinline__ void rcp_each(const double d[4], double r[4], std::integral_constant<int, 4>) {
+    const double d01 = d[0] * d[1], d23 = d[2] * d[3];
+    const double R = rcp(d01 * d23);
+    const double a = R * d23, b = R * d01;
+    r[0] = a * d[1];
+    r[1] = a * d[0];
+    r[2] = b * d[3];
+    r[3] = b * d[2];
+}
+template <int N>
+__device__ __forceinline__ void rcp_each(const float d[N], float r[N], std::integral_constant<int, N>) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) r[e] = rcp(d[e]);
 }
 
 template <typename T>
@@ -106,8 +133,11 @@ __device__ __forceinline__ void cell_solve2(const T g[4], T ax, T ay, T sig, T u
     T P = fma(T(2), ax + ay, sig);
     T Qp = r2 * (ax + ay), Qm = r2 * (ax - ay);
     T P2 = P * P;
-    cpx<T> hp = cdiv(fp, P, Qp, rcp(fma(Qp, Qp, P2)));
-    cpx<T> hm = cdiv(fm, P, Qm, rcp(fma(Qm, Qm, P2)));
+    const T den[2] = {fma(Qp, Qp, P2), fma(Qm, Qm, P2)};
+    T inv[2];
+    rcp_each(den, inv, std::integral_constant<int, 2>{});
+    cpx<T> hp = cdiv(fp, P, Qp, inv[0]);
+    cpx<T> hm = cdiv(fm, P, Qm, inv[1]);
     cpx<T> d0, d1;
     inv_pair(hp, hm, d0, d1);
     const T tr2 = T(2) * r2;
@@ -139,8 +169,12 @@ __device__ __forceinline__ void cell_solve3(const T g[8], T ax, T ay, T az, T si
     T P = fma(T(2), ax + ay + az, sig);
     T P2 = P * P;
     T Q[4] = {r2 * (ax + ay + az), r2 * (ax + ay - az), r2 * (ax - ay + az), r2 * (ax - ay - az)};
+    T den[4], inv[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) h[e] = cdiv(h[e], P, Q[e], rcp(fma(Q[e], Q[e], P2)));
+    for (int e = 0; e < 4; ++e) den[e] = fma(Q[e], Q[e], P2);
+    rcp_each(den, inv, std::integral_constant<int, 4>{});
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = cdiv(h[e], P, Q[e], inv[e]);
     // inverse z: for e_y = +, - -> nodes c = 0, 1
     cpx<T> dp[2], dm[2];
     inv_pair(h[0], h[1], dp[0], dp[1]);
