@@ -125,9 +125,10 @@ __device__ __forceinline__ cpx<T> cdiv(cpx<T> f, T P, T Q, T inv) {
 // 2D cell solve in the reflected frame. g, u: nodes a + 2b.
 template <typename T>
 __device__ __forceinline__ void cell_solve2(const T g[4], T ax, T ay, T sig, T u[4]) {
-    const T k = Consts<T>::k, r2 = Consts<T>::r2;
-    cpx<T> c0{T(0.5) * g[0], -k * (g[0] + g[1])};   // row b = 0, x-transform
-    cpx<T> c1{T(0.5) * g[2], -k * (g[2] + g[3])};   // row b = 1
+    const T k2 = T(2) * Consts<T>::k, r2 = Consts<T>::r2;
+    // twice the x-transform (see cell_solve3)
+    cpx<T> c0{g[0], -k2 * (g[0] + g[1])};   // row b = 0
+    cpx<T> c1{g[2], -k2 * (g[2] + g[3])};   // row b = 1
     cpx<T> fp, fm;
     fwd_pair(c0, c1, fp, fm);
     T P = fma(T(2), ax + ay, sig);
@@ -140,23 +141,26 @@ __device__ __forceinline__ void cell_solve2(const T g[4], T ax, T ay, T sig, T u
     cpx<T> hm = cdiv(fm, P, Qm, inv[1]);
     cpx<T> d0, d1;
     inv_pair(hp, hm, d0, d1);
-    const T tr2 = T(2) * r2;
-    u[0] = T(2) * d0.re;
-    u[1] = fma(-tr2, d0.im, -T(2) * d0.re);
-    u[2] = T(2) * d1.re;
-    u[3] = fma(-tr2, d1.im, -T(2) * d1.re);
+    u[0] = d0.re;
+    u[1] = fma(-r2, d0.im, -d0.re);
+    u[2] = d1.re;
+    u[3] = fma(-r2, d1.im, -d1.re);
 }
 
 // 3D cell solve in the reflected frame. g, u: nodes a + 2b + 4c.
 template <typename T>
 __device__ __forceinline__ void cell_solve3(const T g[8], T ax, T ay, T az, T sig, T u[8]) {
-    const T k = Consts<T>::k, r2 = Consts<T>::r2;
-    // x-transform of the four (b, c) pencils
+    const T k2 = T(2) * Consts<T>::k, r2 = Consts<T>::r2;
+    // Twice the x-transform of the four (b, c) pencils: every later stage is
+    // linear, so the coefficients stay doubled up to the back-transform, whose
+    // real part of a conjugate pair (2 Re) then needs no factor 2.  Doubling
+    // is exact in binary floating point, so the values are those of the plain
+    // transform; it saves the multiplications by 1/2 and by 2.
     cpx<T> c1[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-        c1[p].re = T(0.5) * g[2 * p];
-        c1[p].im = -k * (g[2 * p] + g[2 * p + 1]);
+        c1[p].re = g[2 * p];
+        c1[p].im = -k2 * (g[2 * p] + g[2 * p + 1]);
     }
     // y-transform: for c = 0, 1 -> (e_y = +, e_y = -)
     cpx<T> yp[2], ym[2];
@@ -180,15 +184,15 @@ __device__ __forceinline__ void cell_solve3(const T g[8], T ax, T ay, T az, T si
     inv_pair(h[0], h[1], dp[0], dp[1]);
     inv_pair(h[2], h[3], dm[0], dm[1]);
     // inverse y for each c -> nodes b = 0, 1 ; inverse x -> real nodes a = 0, 1
-    const T tr2 = T(2) * r2;
+    // (node 0 = 2 Re e, node 1 = 2 Re((-1 + i r2) e); e here is already 2 e)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         cpx<T> e0, e1;
         inv_pair(dp[c], dm[c], e0, e1);
-        u[4 * c + 0] = T(2) * e0.re;
-        u[4 * c + 1] = fma(-tr2, e0.im, -T(2) * e0.re);
-        u[4 * c + 2] = T(2) * e1.re;
-        u[4 * c + 3] = fma(-tr2, e1.im, -T(2) * e1.re);
+        u[4 * c + 0] = e0.re;
+        u[4 * c + 1] = fma(-r2, e0.im, -e0.re);
+        u[4 * c + 2] = e1.re;
+        u[4 * c + 3] = fma(-r2, e1.im, -e1.re);
     }
 }
 
