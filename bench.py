@@ -49,9 +49,8 @@ def sweep_bytes_per_call(nc, ndirs, nn, s):
 def traffic_from_profiles(kernel_key):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary in
     profiles/ was taken on the current kernel source (else None)."""
-    import hashlib
+    from paper_2001_09196_amd.profile_summary import kernel_source_sha
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2001_09196_amd", "csrc", "sweep.hip")
     if not os.path.exists(path):
         return None
     try:
@@ -60,8 +59,7 @@ def traffic_from_profiles(kernel_key):
         ent = data.get(kernel_key)
         if not ent:
             return None
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if ent.get("sweep_hip_sha256") != h:
+        if ent.get("kernel_src_sha256") != kernel_source_sha():
             return None
         return float(ent["bytes_per_launch"])
     except Exception:

@@ -7,7 +7,8 @@
       <copy_fetch_dir> <copy_write_dir> <copy_bytes> <out.txt> <traffic.json>
       HBM bytes per dispatch of one kernel from FETCH_SIZE and WRITE_SIZE runs (KiB per
       dispatch), each scaled so that a plain copy of copy_bytes reads as copy_bytes; the entry
-      of traffic.json records the sha256 of sweep.hip the counters were taken on.
+      of traffic.json records a sha256 of the sweep kernels' source and build flags
+      (kernel_source_sha) the counters were taken on.
   python -m paper_2001_09196_amd.profile_summary traffic_per_call <calls> <key> ... (as traffic)
       the same for kernels launched several times per call: the counters of all
       dispatches summed and divided by the number of calls.
@@ -62,6 +63,15 @@ def _per_dispatch(d, counter, kernel, per_call=0):
     return v[len(v) // 2], len(v)   # median over dispatches, KiB
 
 
+def kernel_source_sha() -> str:
+    """sha256 over the files that decide the sweep kernels' code: their
+    source, the device header, the launch header and the build flags."""
+    h = hashlib.sha256()
+    for rel in ("csrc/sweep.hip", "csrc/sn_device.hpp", "csrc/sn_kernels.hpp", "build.py"):
+        h.update(open(os.path.join(HERE, rel), "rb").read())
+    return h.hexdigest()
+
+
 def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, command, per_call=0):
     copy_bytes = float(copy_bytes)
     cf, _ = _per_dispatch(cfdir, "FETCH_SIZE", "copy")
@@ -70,8 +80,7 @@ def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, comma
     f, nf = _per_dispatch(fdir, "FETCH_SIZE", kernel, per_call)
     w, nw = _per_dispatch(wdir, "WRITE_SIZE", kernel, per_call)
     fb, wb = f * 1024 * sf, w * 1024 * sw
-    src = os.path.join(HERE, "csrc", "sweep.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha()
     lines = [f"# HBM traffic of {kernel} ({key})", f"# commands: {command}", "",
              f"copy probe: FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB per {copy_bytes:.0f}-byte copy -> "
              f"scale fetch {sf:.3f}, write {sw:.3f}",
@@ -80,12 +89,12 @@ def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, comma
               f"kernel: FETCH_SIZE {f:.0f} KiB (median of {nf} dispatches), WRITE_SIZE {w:.0f} KiB ({nw})"),
              f"scaled bytes per {'call' if per_call > 0 else 'dispatch'}: read {fb:.4e}, write {wb:.4e}, "
              f"total {fb + wb:.4e}",
-             f"sweep.hip sha256 {sha}"]
+             f"kernel source sha256 {sha} (sweep.hip, sn_device.hpp, sn_kernels.hpp, build.py)"]
     open(out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
     data = json.load(open(jpath)) if os.path.exists(jpath) else {}
     data[key] = {"bytes_per_launch": fb + wb, "read_bytes": fb, "write_bytes": wb, "kernel": kernel,
-                 "sweep_hip_sha256": sha, "fetch_scale": sf, "write_scale": sw}
+                 "kernel_src_sha256": sha, "fetch_scale": sf, "write_scale": sw}
     json.dump(data, open(jpath, "w"), indent=1)
 
 
