@@ -553,10 +553,12 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     int it = 0;  // iteration whose apply kernel runs next
     bool pending = false;
     const bool speculate = phi_out != phi_si;
-    // (one more than the larger of the last two counts: a batch that falls
-    // short costs a host round trip and a trickle of late launches, surplus
+    // (the larger of the last two counts, which alternate under the warm
+    // start: a batch of b iterations ends with the stop test of iteration b,
+    // so it covers a solve of up to b iterations; a batch that falls short
+    // costs a host round trip and a trickle of late launches, surplus
     // iterations only early-exit kernels)
-    int batch = std::max(0, std::min(std::max(ctx->cg_hint, ctx->cg_hint2) + 1, o->cg_maxit));
+    int batch = std::max(0, std::min(std::max(ctx->cg_hint, ctx->cg_hint2), o->cg_maxit));
     while (true) {
         if (pending && (rc = update(it - 1))) return rc;
         const int nb = std::min(batch, o->cg_maxit - it);
