@@ -205,12 +205,14 @@ int sn_gradient(sn_context *ctx, const void *psi, const void *psi_adj, sn_precis
 int sn_response(sn_context *ctx, const double *r, const double *phi, int face, const void *psi,
                 sn_precision prec, double *out);
 
-/* Kernel timing for measurement.  When enabled, every subsequent call records
+/* Kernel timing for measurement.  enable = 1: every subsequent call records
  * HIP events on the context's stream around the sweep kernels of each sweep
  * (excluding the source and face-initialisation kernels) and around each DSA
- * solve.  sn_kernel_timing waits for the stream, returns the summed
- * durations (ms) and counts since the last query or enable, and resets them.
- * Enabling or disabling synchronises the stream. */
+ * solve; enable = 2: around the sweep kernels only (each recorded event holds
+ * the next kernel back by a few microseconds, so fewer events perturb a timed
+ * run less); enable = 0: off.  sn_kernel_timing waits for the stream, returns
+ * the summed durations (ms) and counts since the last query or enable, and
+ * resets them.  Enabling or disabling synchronises the stream. */
 int sn_set_kernel_timing(sn_context *ctx, int enable);
 int sn_kernel_timing(sn_context *ctx, double *sweep_ms, int *sweep_count, double *dsa_ms, int *dsa_count);
 

@@ -236,8 +236,10 @@ def sn_response(ctx: Context, r=None, phi=None, face: int = -1, psi=None, prec: 
     return out.value
 
 
-def sn_set_kernel_timing(ctx: Context, enable: bool):
-    _check(lib().sn_set_kernel_timing(ctx.handle, int(bool(enable))))
+def sn_set_kernel_timing(ctx: Context, enable: bool, sweeps_only: bool = False):
+    """enable: record HIP events around the sweep kernels and (unless
+    sweeps_only) around each DSA solve."""
+    _check(lib().sn_set_kernel_timing(ctx.handle, (2 if sweeps_only else 1) if enable else 0))
 
 
 def sn_kernel_timing(ctx: Context):

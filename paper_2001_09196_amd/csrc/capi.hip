@@ -535,7 +535,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     hs.done = 0;
     hs.breakdown = 0;
     hs.iters = 0;
-    if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
+    if (ctx->timing == 1 && (rc = record_event(ctx, &e0))) return rc;
     if (warm)
         HIPCHK(launch_dsa_warm(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si,
                                ctx->cx.p, ctx->cq.p, ctx->parta.p, ctx->nparts, ctx->stream));
@@ -590,7 +590,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     }
     if (!speculate)
         HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
-    if (ctx->timing) {
+    if (ctx->timing == 1) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->dsa_ev.emplace_back(e0, e1);
     }
@@ -969,7 +969,8 @@ int sn_set_kernel_timing(sn_context* ctx, int enable) {
     g_err.clear();
     if (!ctx) return fail(SN_ERR_INVALID, "context is NULL");
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    ctx->timing = enable ? 1 : 0;
+    if (enable < 0 || enable > 2) return fail(SN_ERR_INVALID, "kernel timing mode %d (0, 1 or 2)", enable);
+    ctx->timing = enable;
     ctx->evused = 0;
     ctx->sweep_ev.clear();
     ctx->dsa_ev.clear();

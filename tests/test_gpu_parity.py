@@ -335,3 +335,22 @@ def test_dsa_multigrid_pure_scatterer():
             assert rel_max(out.cpu().numpy(), ref) <= 1e-6
     say(f"pure scatterer: CG iterations block Jacobi {its[0]}, multigrid {its[1]}")
     assert its[1] * 3 <= its[0]
+
+
+def test_kernel_timing_modes():
+    """Timing mode 1 records events around the sweeps and the DSA solves,
+    mode 2 around the sweeps only; other modes are rejected."""
+    from paper_2001_09196_amd import sn_source_iterate
+    from paper_2001_09196_amd.binding import lib, sn_kernel_timing, sn_set_kernel_timing
+    p = sninputs.config("c1")
+    say("kernel timing modes")
+    with context(p) as ctx:
+        for sweeps_only in (False, True):
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+            sn_set_kernel_timing(ctx, True, sweeps_only=sweeps_only)
+            sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=3, use_dsa=True)
+            kt = sn_kernel_timing(ctx)
+            sn_set_kernel_timing(ctx, False)
+            assert kt["sweep_count"] >= 3 and kt["sweep_ms"] > 0.0
+            assert (kt["dsa_count"] == 0) == sweeps_only
+        assert lib().sn_set_kernel_timing(ctx.handle, 3) != 0
