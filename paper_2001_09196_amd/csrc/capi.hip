@@ -92,6 +92,12 @@ struct sn_context {
     DevBuf<int> nbr;
     DevBuf<CgScalars> scal;
     int cg_hint = 8, cg_hint2 = 8;  // CG iterations of the last two solves
+    // 2D source iteration, FP64 form: the DSA's final update also wrote the
+    // next sweep's source (srcskew64) from phi = src_tok_phi and
+    // q = src_tok_q; the next sweep then skips its source kernel
+    bool src_tok = false;
+    const double* src_tok_phi = nullptr;
+    const double* src_tok_q = nullptr;
     // pinned host copies of the device scalars (async read-back) and the
     // event that marks the latest residual copy
     struct HostScalars {
@@ -179,6 +185,17 @@ int init_faces(sn_context* ctx, const double* inflow, int transpose, DevBuf<T>& 
     return 0;
 }
 
+// the 2D diagonal-major source array, allocated with zero padding
+template <typename T>
+int ensure_skew(sn_context* ctx, DevBuf<T>& srcskew) {
+    const size_t ne = (size_t)skew2d_elems(ctx->sg.nx, ctx->sg.ny, 4);
+    const bool fresh = srcskew.n < ne || !srcskew.p;
+    int rc;
+    if ((rc = srcskew.ensure(ne))) return rc;
+    if (fresh) HIPCHK(hipMemsetAsync(srcskew.p, 0, ne * sizeof(T), ctx->stream));  // padding stays zero
+    return 0;
+}
+
 template <typename T>
 int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
                int transpose, T* psi, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, DevBuf<T>& sink,
@@ -192,11 +209,12 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
     const T* sweep_src;
     const T* sweep_sig = sigt;
     if (g.dim == 2) {
-        const size_t ne = (size_t)skew2d_elems(g.nx, g.ny, 4);
-        const bool fresh = srcskew.n < ne || !srcskew.p;
-        if ((rc = srcskew.ensure(ne))) return rc;
-        if (fresh) HIPCHK(hipMemsetAsync(srcskew.p, 0, ne * sizeof(T), ctx->stream));  // padding stays zero
-        HIPCHK(launch_source_skew2d<T>(g.nx, g.ny, ctx->sigs.p, phi, phi_prev, q, srcskew.p, ctx->stream));
+        if ((rc = ensure_skew(ctx, srcskew))) return rc;
+        const bool ready = std::is_same<T, double>::value && ctx->src_tok && ctx->src_tok_phi == phi &&
+                           ctx->src_tok_q == q && !phi_prev;
+        ctx->src_tok = false;
+        if (!ready)
+            HIPCHK(launch_source_skew2d<T>(g.nx, g.ny, ctx->sigs.p, phi, phi_prev, q, srcskew.p, ctx->stream));
         sweep_src = srcskew.p;
         sweep_sig = sigskew;
     } else {
@@ -488,8 +506,11 @@ bool bad_dsa_opts(const sn_dsa_opts& o) {
 // also covers that read-back)
 // warm: start the CG from the previous call's solution (within one
 // source-iteration call), projected onto the new right-hand side
+// next_src (2D source iteration, FP64 form): the final update also writes the
+// next sweep's source from phi_out and next_q
 int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
-           sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0, bool warm = false) {
+           sn_dsa_stats* stats, const double* res_part = nullptr, int res_nparts = 0, bool warm = false,
+           bool next_src = false, const double* next_q = nullptr) {
     const long n = ctx->nc * ctx->nn;
     if (ctx->nthick == 0) {
         if (res_part)
@@ -508,6 +529,20 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     size_t e0 = 0, e1 = 0;
     int rc;
     const int bj = o->precond == SN_PRECOND_MG ? 0 : 1;
+    const bool fuse_src = next_src && ctx->mesh.dim == 2;
+    if (fuse_src && (rc = ensure_skew(ctx, ctx->srcskew64))) return rc;
+    auto scatter = [&]() -> int {
+        if (fuse_src) {
+            HIPCHK(launch_scatter_source_skew2d(ctx->sg.nx, ctx->sg.ny, ctx->slot.p, phi_si, ctx->cx.p,
+                                                ctx->sigs.p, next_q, phi_out, ctx->srcskew64.p, ctx->stream));
+            ctx->src_tok = true;
+            ctx->src_tok_phi = phi_out;
+            ctx->src_tok_q = next_q;
+        } else {
+            HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+        }
+        return 0;
+    };
     if (!bj && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
     CgScalars& hs = ctx->hpin->cs;
     auto vcycle = [&]() -> int {
@@ -571,8 +606,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         // enqueued ahead of the stop decision: the CG kernels never read
         // phi_out (phi_old is read by the right-hand side only), and if the
         // solve goes on the update is enqueued again after the next batch.
-        if (speculate)
-            HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+        if (speculate && (rc = scatter())) return rc;
         // wait for the stop flag in pinned memory (written as soon as the
         // test passes, ahead of the kernel's end) or for the batch to finish.
         // The event is queried on every turn of the loop: the query also
@@ -588,8 +622,7 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         if (hs.done || it > o->cg_maxit) break;
         batch = 4;
     }
-    if (!speculate)
-        HIPCHK(launch_dsa_scatter(ctx->nc, ctx->nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+    if (!speculate && (rc = scatter())) return rc;
     if (ctx->timing == 1) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->dsa_ev.emplace_back(e0, e1);
@@ -1041,8 +1074,12 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         explicit FaceReuse(sn_context* c_) : c(c_) {
             c->fkey[0].valid = c->fkey[1].valid = false;
             c->face_reuse = true;
+            c->src_tok = false;
         }
-        ~FaceReuse() { c->face_reuse = false; }
+        ~FaceReuse() {
+            c->face_reuse = false;
+            c->src_tok = false;  // the caller may change phi before the next call
+        }
     } face_reuse(ctx);
     const long n = ctx->nc * ctx->nn;
     int rc;
@@ -1122,7 +1159,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
             if (o->use_dsa) {
                 sn_dsa_stats ds{};
                 const int e = do_dsa(ctx, phi_old, ctx->phisi.p, phi, &o->dsa, &ds,
-                                     with_res ? ctx->fpart.p : nullptr, res_n, dsa_done > 0);
+                                     with_res ? ctx->fpart.p : nullptr, res_n, dsa_done > 0, !incr, q);
                 ++dsa_done;
                 cgi = ds.cg_iters;
                 return e;

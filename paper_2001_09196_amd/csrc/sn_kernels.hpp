@@ -57,6 +57,11 @@ hipError_t launch_skew2d(int nx, int ny, int nn, const T* in, T* out, hipStream_
 template <typename T>
 hipError_t launch_source_skew2d(int nx, int ny, const double* sigma_s, const double* phi, const double* phi_prev,
                                 const double* q, T* out, hipStream_t st);
+// phi_out = phi_si + P x (x: thick-slot values, slot_of_cell -1 for others)
+// and the FP64 diagonal-major sweep source of phi_out (2D, four quadrants)
+hipError_t launch_scatter_source_skew2d(int nx, int ny, const int* slot_of_cell, const double* phi_si,
+                                       const double* x, const double* sigma_s, const double* q, double* phi_out,
+                                       double* out, hipStream_t st);
 // (plus SKEW2D_TAIL zero diagonals after the last block: the sweep's
 // prefetch runs up to that far past a block's last diagonal)
 constexpr int SKEW2D_TAIL = 16;

@@ -165,6 +165,26 @@ __global__ void skew2d_kernel(int nx, int ny, int nn, const T* __restrict__ in, 
 }
 
 // Source of the 2D sweep written straight into the diagonal-major arrays:
+// the source (sigma_s f + q) / 4pi of cell c from its four flux values f,
+// written to the cell's place in the diagonal-major arrays of all four
+// quadrants
+template <typename T>
+__device__ __forceinline__ void put_source_skew2d(int nx, int ny, long c, double sigs, double qc, const double f[4],
+                                                  T* __restrict__ out) {
+    const long ns = (long)nx + 63;
+    const long per = (long)((ny + 63) / 64) * ns * 64;
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    T v[4];
+    for (int n = 0; n < 4; ++n) v[n] = T((sigs * f[n] + qc) * 0.07957747154594766788);  // 1 / 4pi
+    for (int qd = 0; qd < 4; ++qd) {
+        const int il = (qd & 1) ? nx - 1 - i : i;
+        const int jl = (qd & 2) ? ny - 1 - j : j;
+        const int l = jl & 63;
+        T* o = out + (qd * per + ((long)(jl >> 6) * ns + il + l) * 64 + l) * 4;
+        for (int n = 0; n < 4; ++n) o[n] = v[n];
+    }
+}
+
 // s = (sigma_s (phi - phi_prev) + q) / 4pi per node (one thread per cell),
 // stored at the cell's position in each quadrant's layout.  Only on-mesh
 // entries are written; the padding of the arrays is zeroed once when they
@@ -173,24 +193,34 @@ template <typename T>
 __global__ void source_skew2d_kernel(int nx, int ny, const double* __restrict__ sigma_s,
                                      const double* __restrict__ phi, const double* __restrict__ phi_prev,
                                      const double* __restrict__ q, T* __restrict__ out) {
-    const long ns = (long)nx + 63;
-    const long per = (long)((ny + 63) / 64) * ns * 64;
     const long nc = (long)nx * ny;
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)(c / nx);
-        T v[4];
+        double f[4];
         for (int n = 0; n < 4; ++n) {
-            double f = phi ? phi[c * 4 + n] : 0.0;
-            if (phi_prev) f -= phi_prev[c * 4 + n];
-            v[n] = T((sigma_s[c] * f + (q ? q[c] : 0.0)) * 0.07957747154594766788);  // 1 / 4pi
+            f[n] = phi ? phi[c * 4 + n] : 0.0;
+            if (phi_prev) f[n] -= phi_prev[c * 4 + n];
         }
-        for (int qd = 0; qd < 4; ++qd) {
-            const int il = (qd & 1) ? nx - 1 - i : i;
-            const int jl = (qd & 2) ? ny - 1 - j : j;
-            const int l = jl & 63;
-            T* o = out + (qd * per + ((long)(jl >> 6) * ns + il + l) * 64 + l) * 4;
-            for (int n = 0; n < 4; ++n) o[n] = v[n];
+        put_source_skew2d<T>(nx, ny, c, sigma_s[c], q ? q[c] : 0.0, f, out);
+    }
+}
+
+// 2D source iteration: the DSA's final update phi_out = phi_SI + P x fused
+// with the next iteration's FP64 sweep source from phi_out (one kernel and
+// one launch fewer between the solve and the next sweep)
+__global__ void scatter_source_skew2d_kernel(int nx, int ny, const int* __restrict__ slot_of_cell,
+                                             const double* __restrict__ phi_si, const double* __restrict__ x,
+                                             const double* __restrict__ sigma_s, const double* __restrict__ q,
+                                             double* __restrict__ phi_out, double* __restrict__ out) {
+    const long nc = (long)nx * ny;
+    for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+        const int s = slot_of_cell[c];
+        double f[4];
+        for (int n = 0; n < 4; ++n) {
+            f[n] = phi_si[c * 4 + n];
+            if (s >= 0) f[n] += x[(long)s * 4 + n];
+            phi_out[c * 4 + n] = f[n];
         }
+        put_source_skew2d<double>(nx, ny, c, sigma_s[c], q ? q[c] : 0.0, f, out);
     }
 }
 
@@ -1118,6 +1148,15 @@ hipError_t launch_source_skew2d(int nx, int ny, const double* sigma_s, const dou
     const int blocks = (int)std::min<long>((nc + 255) / 256, 65536);
     hipLaunchKernelGGL(source_skew2d_kernel<T>, dim3(blocks), dim3(256), 0, st, nx, ny, sigma_s, phi, phi_prev, q,
                        out);
+    return hipGetLastError();
+}
+hipError_t launch_scatter_source_skew2d(int nx, int ny, const int* slot_of_cell, const double* phi_si,
+                                       const double* x, const double* sigma_s, const double* q, double* phi_out,
+                                       double* out, hipStream_t st) {
+    const long nc = (long)nx * ny;
+    const int blocks = (int)std::min<long>((nc + 255) / 256, 65536);
+    hipLaunchKernelGGL(scatter_source_skew2d_kernel, dim3(blocks), dim3(256), 0, st, nx, ny, slot_of_cell, phi_si,
+                       x, sigma_s, q, phi_out, out);
     return hipGetLastError();
 }
 template hipError_t launch_source_skew2d<double>(int, int, const double*, const double*, const double*,
