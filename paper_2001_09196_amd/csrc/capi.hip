@@ -980,7 +980,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     dg.nthick = nthick;
     const long nf = (long)nthick * c->nn;
     c->nparts = std::max(1, std::min((nthick + 255) / 256, 1024));
-    if ((rc = c->binv.ensure((size_t)std::max(nthick, 1) * c->nn * c->nn)) || (rc = c->cx.ensure(nf)) ||
+    if ((rc = c->binv.ensure((size_t)std::max(nthick, 1) * bj_entries_of(c->nn))) || (rc = c->cx.ensure(nf)) ||
         (rc = c->cr.ensure(nf)) || (rc = c->cz.ensure(nf)) || (rc = c->cp.ensure(nf)) || (rc = c->cp1.ensure(nf)) ||
         (rc = c->cq.ensure(nf)) || (rc = c->nbr.ensure((size_t)std::max(nthick, 1) * 2 * dim)) ||
         (rc = c->parta.ensure(3 * c->nparts)) || (rc = c->partb.ensure(3 * c->nparts)) ||

@@ -393,8 +393,13 @@ __global__ void block_jacobi_kernel(DsaGeom g, const int* __restrict__ thick_cel
                 }
             }
         }
+        // the inverse of a symmetric block is symmetric: its upper triangle,
+        // row by row, with the two rounded copies of each off-diagonal entry
+        // averaged
+        int k = 0;
         for (int r = 0; r < NN; ++r)
-            for (int c = 0; c < NN; ++c) binv[(long)(r * NN + c) * g.nthick + s] = Inv[r][c];
+            for (int c = r; c < NN; ++c, ++k)
+                binv[(long)k * g.nthick + s] = c == r ? Inv[r][r] : 0.5 * (Inv[r][c] + Inv[c][r]);
     }
 }
 
@@ -462,19 +467,33 @@ __device__ __forceinline__ double reduce_parts(const double* __restrict__ part, 
     return block_reduce(v, sh);
 }
 
+// z = B r for a symmetric block B given by its upper triangle, row by row
+// (bj_entries<NN>() values); get(k) returns entry k
+template <int NN, typename Get>
+__device__ __forceinline__ void sym_apply(Get get, const double r[NN], double z[NN]) {
+#pragma unroll
+    for (int a = 0; a < NN; ++a) z[a] = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < NN; ++a) {
+#pragma unroll
+        for (int b = a; b < NN; ++b, ++k) {
+            const double v = get(k);
+            z[a] = fma(v, r[b], z[a]);
+            if (b != a) z[b] = fma(v, r[a], z[b]);
+        }
+    }
+}
+
 template <int NN>
 __device__ __forceinline__ void bj_apply(const double* __restrict__ binv, long bj_stride, int s, const double r[NN],
                                          double z[NN]) {
-    // element-major storage: entry (a, b) of the blocks of all thick cells is
-    // contiguous, so consecutive lanes (cells) read consecutive words
+    // element-major storage: entry k of the blocks of all thick cells is
+    // contiguous, so consecutive lanes (cells) read consecutive words; only
+    // the upper triangle is stored (the inverse of the symmetric block is
+    // symmetric), 36 of 64 words per cell in 3D
     const long n = bj_stride;
-#pragma unroll
-    for (int a = 0; a < NN; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int b = 0; b < NN; ++b) v = fma(binv[(long)(a * NN + b) * n + s], r[b], v);
-        z[a] = v;
-    }
+    sym_apply<NN>([&](int k) { return binv[(long)k * n + s]; }, r, z);
 }
 
 // right-hand side of thick slot s: b = coef M (phi_si - phi_old)
@@ -744,7 +763,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
     // partials, whose barriers also order memory accesses, so that the loads
     // overlap it (the C2 thick set has one cell per thread); in 2D the
     // block inverse too.
-    constexpr int NB = NN == 4 ? NN * NN : 1;
+    constexpr int NB = NN == 4 ? bj_entries<NN>() : 1;
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
     double x0[NN], p0[NN], q0[NN], r0[NN], b0[NB];
@@ -794,13 +813,7 @@ __global__ void __launch_bounds__(256) cg_update_kernel(DsaGeom g, const double*
         if constexpr (BJ) {
             if constexpr (NN == 4) {
                 if (pre) {
-#pragma unroll
-                    for (int i = 0; i < NN; ++i) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int j = 0; j < NN; ++j) v = fma(b0[i * NN + j], rv[j], v);
-                        zv[i] = v;
-                    }
+                    sym_apply<NN>([&](int k) { return b0[k]; }, rv, zv);
                 } else {
                     bj_apply<NN>(binv, g.nthick, t, rv, zv);
                 }

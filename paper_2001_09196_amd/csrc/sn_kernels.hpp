@@ -111,6 +111,14 @@ hipError_t launch_thick_flags(long nc, const double* sigma_s, double eta, int* f
 hipError_t launch_thick_scan(int nblk, int* block_sums, int* total, hipStream_t st);
 hipError_t launch_thick_scatter(long nc, const int* flags, const int* block_sums, int* slot_of_cell,
                                 int* thick_cell, hipStream_t st);
+// words per thick cell of the stored block-Jacobi inverse (upper triangle)
+template <int NN>
+constexpr int bj_entries() {
+    return NN * (NN + 1) / 2;
+}
+inline int bj_entries_of(int nn) {
+    return nn * (nn + 1) / 2;
+}
 hipError_t launch_block_jacobi(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
                                const double* sigma_t, const double* sigma_s, double* binv, hipStream_t st);
 
