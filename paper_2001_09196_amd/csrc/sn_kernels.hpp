@@ -42,7 +42,10 @@ inline long sink_elems(const SweepGeom&) { return 1; }
 // (workspace [nclasses][ncells][8]) receives each octant's share of phi, then
 // phi = (accumulate ? phi : 0) + sum over the octants in a fixed order.
 // ref != nullptr: residual partial sums as in launch_moment, part[3][octant_sum_blocks(ncells)]
-inline int octant_sum_blocks(long nc) { return (int)std::min<long>((nc * 8 + 255) / 256, 65536); }
+// (at most 4096 blocks: the residual's partial sums are reduced afterwards by
+// one workgroup, and 3 x 65536 of them made that reduction the tail of the
+// DSA's first kernel at 128^3)
+inline int octant_sum_blocks(long nc) { return (int)std::min<long>((nc * 8 + 255) / 256, 4096); }
 template <typename T>
 hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
                                const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
