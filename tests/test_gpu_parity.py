@@ -374,3 +374,25 @@ def test_kernel_timing_modes():
             assert kt["sweep_count"] >= 3 and kt["sweep_ms"] > 0.0
             assert (kt["dsa_count"] == 0) == sweeps_only
         assert lib().sn_set_kernel_timing(ctx.handle, 3) != 0
+
+
+def test_si_fused_source_not_reused_across_calls():
+    """2D FP64 source iteration lets the DSA's final update write the next
+    sweep's source.  That source must not outlive the call: after the caller
+    changes phi in place, a sweep of the same buffer uses the new values."""
+    from paper_2001_09196_amd import sn_source_iterate, sn_sweep
+    p = random_problem(2, 37, 41, 1, order=4, seed=91)
+    say("SI fused source, then an in-place change of phi")
+    with context(p) as ctx:
+        qd = dev(p.q)  # the same q buffer for both calls, as the fused source records it
+        phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+        sn_source_iterate(ctx, qd, None, phi, tol=0.0, max_it=3, use_dsa=True, cg_rtol=1e-10, cg_maxit=500)
+        phi.mul_(0.5)
+        torch.cuda.synchronize()
+        phi_host = phi.cpu().numpy()
+        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device="cuda")
+        sn_sweep(ctx, phi, qd, None, False, 0, psi)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy()
+    ref = oracle.sweep(p, phi_host, p.q, inflow=None, transpose=False)
+    assert rel_max(got, ref) <= 1e-12
