@@ -111,8 +111,11 @@ void orc_cell_mass(int dim, const double h[3], double *M) {
 /* Cell matrix of the upwind-DG transport operator for direction om
  * (eq. Tmat1 at eps = 1 on one Cartesian Q1 cell):
  *   A = |mu| Mz (x) My (x) G_x + |eta| Mz (x) G_y (x) Mx
- *     + |xi| G_z (x) My (x) Mx + sigma_t Mz (x) My (x) Mx.            */
-void orc_cell_matrix(int dim, const double h[3], const double om[3], double sigma_t, double *A) {
+ *     + sigma_t Mz (x) My (x) Mx + |xi| G_z (x) My (x) Mx,
+ * summed in that order.  The first two terms (P), the mass (Mm) and the
+ * z term (Z) do not depend on the cell, so a sweep forms them once per
+ * direction and each cell adds sigma_t Mm: A = (P + sigma_t Mm) + Z. */
+static void cell_matrix_parts(int dim, const double h[3], const double om[3], double *P, double *Mm, double *Z) {
     double mx[2][2], my[2][2], mz[2][2], gx[2][2], gy[2][2], gz[2][2];
     mass1(h[0], mx);
     mass1(h[1], my);
@@ -123,12 +126,27 @@ void orc_cell_matrix(int dim, const double h[3], const double om[3], double sigm
     int nn = dim == 2 ? 4 : 8;
     for (int n = 0; n < nn; ++n)
         for (int np = 0; np < nn; ++np) {
-            double v = fabs(om[0]) * kron3(dim, gx, my, mz, n, np)
-                     + fabs(om[1]) * kron3(dim, mx, gy, mz, n, np)
-                     + sigma_t * kron3(dim, mx, my, mz, n, np);
-            if (dim == 3) v += fabs(om[2]) * kron3(dim, mx, my, gz, n, np);
-            A[n * nn + np] = v;
+            P[n * nn + np] = fabs(om[0]) * kron3(dim, gx, my, mz, n, np)
+                           + fabs(om[1]) * kron3(dim, mx, gy, mz, n, np);
+            Mm[n * nn + np] = kron3(dim, mx, my, mz, n, np);
+            Z[n * nn + np] = dim == 3 ? fabs(om[2]) * kron3(dim, mx, my, gz, n, np) : 0.0;
         }
+}
+
+static void cell_matrix_from_parts(int dim, const double *P, const double *Mm, const double *Z, double sigma_t,
+                                   double *A) {
+    int nn = dim == 2 ? 4 : 8;
+    for (int e = 0; e < nn * nn; ++e) {
+        double v = P[e] + sigma_t * Mm[e];
+        if (dim == 3) v += Z[e];
+        A[e] = v;
+    }
+}
+
+void orc_cell_matrix(int dim, const double h[3], const double om[3], double sigma_t, double *A) {
+    double P[64], Mm[64], Z[64];
+    cell_matrix_parts(dim, h, om, P, Mm, Z);
+    cell_matrix_from_parts(dim, P, Mm, Z, sigma_t, A);
 }
 
 /* Solve A x = b in place (b -> x) by LU with partial pivoting. A is destroyed.
@@ -243,6 +261,8 @@ static int sweep_one(const orc_mesh *m, const double om[3], const double *sigma_
         }
     }
     double A[64], rhs[8];
+    double Pd[64], Md[64], Zd[64];
+    cell_matrix_parts(dim, h, om, Pd, Md, Zd);
     for (int kk = 0; kk < n3[2]; ++kk) {
         int k = step[2] > 0 ? kk : n3[2] - 1 - kk;
         if (dim == 2) k = 0;
@@ -278,7 +298,7 @@ static int sweep_one(const orc_mesh *m, const double om[3], const double *sigma_
                     }
                 }
                 double Ak[64];
-                orc_cell_matrix(dim, h, om, sigma_t[c], Ak);
+                cell_matrix_from_parts(dim, Pd, Md, Zd, sigma_t[c], Ak);
                 if (transpose) {
                     for (int r = 0; r < nn; ++r)
                         for (int s2 = 0; s2 < nn; ++s2) A[r * nn + s2] = Ak[s2 * nn + r];
@@ -553,8 +573,11 @@ static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const
     return 0;
 }
 
+/* y = D_ff x, row block by row block (rows are independent, so the rows are
+ * shared out over threads; each row's sum is formed in the same order). */
 static void dsa_apply(const dsa_mat *A, const double *x, double *y) {
     int nn = A->nn;
+#pragma omp parallel for schedule(static)
     for (int s = 0; s < A->nthick; ++s) {
         for (int r = 0; r < nn; ++r) {
             double v = 0.0;
@@ -593,10 +616,12 @@ static int cg_solve(const dsa_mat *A, const double *b, double *x, double rtol, i
         double pq = dot(n, p, q);
         if (!(pq > 0.0)) { rc = 7; break; }
         double alpha = rr / pq;
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
         double rr2 = dot(n, r, r);
         double beta = rr2 / rr;
         rr = rr2;
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
         ++it;
     }
