@@ -70,8 +70,13 @@ def lib():
             L.orc_dsa_dense.restype = ctypes.c_int
             L.orc_source_iterate.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
                                              ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                             ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _ip]
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                             _ip, _ip]
             L.orc_source_iterate.restype = ctypes.c_int
+            L.orc_gmres.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _ip]
+            L.orc_gmres.restype = ctypes.c_int
             L.orc_gradient.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
             L.orc_inflow_size.argtypes = [mp]
             L.orc_inflow_size.restype = ctypes.c_long
@@ -171,8 +176,10 @@ def dsa_dense(p, eta=None, sigma_t=None, sigma_s=None):
 
 
 def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=1e-13, cg_maxit=100000,
-                   transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None):
-    """Returns dict(phi [nc, nn], iters, res_hist, cg_hist, rc)."""
+                   transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None,
+                   dsa_form=0):
+    """Returns dict(phi [nc, nn], iters, res_hist, cg_hist, rc).
+    dsa_form: 0 diagonal heterogeneous DSA (Alg. 2), 1 triangular (Alg. 1)."""
     st = _f64(p.sigma_t if sigma_t is None else sigma_t)
     ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
     qq = _f64(p.q if q is None else q)
@@ -184,10 +191,33 @@ def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=
     rc = lib().orc_source_iterate(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss),
                                   _d(qq), _d(_f64(inflow)), float(p.eta if eta is None else eta),
                                   int(bool(use_dsa)), int(mass_kind), float(tol), int(max_it), float(cg_rtol),
-                                  int(cg_maxit), int(bool(transpose)), _d(phi), _d(res),
+                                  int(cg_maxit), int(bool(transpose)), int(dsa_form), _d(phi), _d(res),
                                   cgh.ctypes.data_as(_ip), ctypes.byref(iters))
     if rc not in (0, 5, 6):
         raise RuntimeError(f"orc_source_iterate failed ({rc})")
+    n = iters.value
+    return {"phi": phi.reshape(p.ncells, p.nn), "iters": n, "res_hist": res[:n], "cg_hist": cgh[:n], "rc": rc}
+
+
+def gmres(p, tol=1e-8, max_it=1000, restart=30, use_dsa=True, dsa_form=0, mass_kind=0, cg_rtol=1e-13,
+          cg_maxit=100000, transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None):
+    """Flexible GMRES(restart) on S phi = b, right-preconditioned by the
+    heterogeneous DSA.  Returns dict(phi, iters, res_hist, cg_hist, rc);
+    an iteration is one application of S (one sweep)."""
+    st = _f64(p.sigma_t if sigma_t is None else sigma_t)
+    ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
+    qq = _f64(p.q if q is None else q)
+    phi = np.zeros(p.ncells * p.nn) if phi0 is None else _f64(phi0).ravel().copy()
+    res = np.zeros(max_it)
+    cgh = np.zeros(max_it, dtype=np.int32)
+    iters = ctypes.c_int(0)
+    m = _mesh(p)
+    rc = lib().orc_gmres(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss), _d(qq),
+                         _d(_f64(inflow)), float(p.eta if eta is None else eta), int(bool(use_dsa)), int(mass_kind),
+                         int(dsa_form), float(tol), int(max_it), int(restart), float(cg_rtol), int(cg_maxit),
+                         int(bool(transpose)), _d(phi), _d(res), cgh.ctypes.data_as(_ip), ctypes.byref(iters))
+    if rc not in (0, 5, 6):
+        raise RuntimeError(f"orc_gmres failed ({rc})")
     n = iters.value
     return {"phi": phi.reshape(p.ncells, p.nn), "iters": n, "res_hist": res[:n], "cg_hist": cgh[:n], "rc": rc}
 

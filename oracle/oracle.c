@@ -34,6 +34,17 @@
  *       sigma_s (mass_kind 0) or sigma_t (mass_kind 1, Sec. 2.2 footnote).
  *   (7) stopping test ||phi_SI - phi||_2 / ||b||_2 <= tol, b = first sweep
  *       from phi = 0 (eq. source0), tested before the DSA step.
+ *   (8) Alg. 1 (triangular heterogeneous DSA) acts on the same residual:
+ *       after the thick update of (6), the thick part of the preconditioned
+ *       residual, phi_bar = [0; (phi_new - phi)_f], is swept once with zero
+ *       external source and vacuum inflow, and the moment of that sweep is
+ *       added to the thin DOFs only (eq. approxS and the identity below it).
+ *   (9) Krylov view (Sec. 2.2): S phi = b with S = I - sum_d w_d L_d^{-1}
+ *       Sigma_s and b = sum_d w_d L_d^{-1} q_d, solved by flexible GMRES(m)
+ *       with the heterogeneous DSA of (6) or (8) as the right preconditioner
+ *       (applied to a vector v as to a residual: v + P_T D_ff^{-1} Sigma_f
+ *       R_T v).  The residual ||b - S phi|| / ||b|| is the same quantity as
+ *       the source-iteration residual of (7).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -723,23 +734,49 @@ int orc_dsa_dense(const orc_mesh *m, int ndirs, const double *omega, const doubl
 
 static double norm2(long n, const double *a) { return sqrt(dot(n, a, a)); }
 
+/* Alg. 1, second step: phi_new restricted to the thin cells gains the moment
+ * of one sweep of phi_bar = [0; (phi_new - phi_old)_f] with zero external
+ * source and vacuum inflow (the thick part of the preconditioned residual
+ * carried into the thin region by a transport update). */
+static int triangular_step(const orc_mesh *m, int ndirs, const double *omega, const double *w,
+                           const double *sigma_t, const double *sigma_s, const long *slot, int transpose,
+                           const double *phi_old, double *phi_new, double *work_bar, double *work_load,
+                           double *work_zeta) {
+    int nn = nnodes(m);
+    long nc = ncells(m);
+    for (long c = 0; c < nc; ++c)
+        for (int n = 0; n < nn; ++n)
+            work_bar[c * nn + n] = slot[c] >= 0 ? phi_new[c * nn + n] - phi_old[c * nn + n] : 0.0;
+    volume_load(m, sigma_s, work_bar, NULL, work_load);
+    int e = transport_update(m, ndirs, omega, w, sigma_t, work_load, NULL, transpose, work_zeta);
+    if (e) return e;
+    for (long c = 0; c < nc; ++c)
+        if (slot[c] < 0)
+            for (int n = 0; n < nn; ++n) phi_new[c * nn + n] += work_zeta[c * nn + n];
+    return 0;
+}
+
 /* phi_inout: initial guess in, last iterate out.  res_hist / cg_hist: [max_it]
- * (may be NULL).  Returns 0 converged, 5 not converged, 6 diverged (non-finite
- * or residual above 1e6 times the first), or an error code. */
+ * (may be NULL).  dsa_form: 0 diagonal (Alg. 2), 1 triangular (Alg. 1).
+ * Returns 0 converged, 5 not converged, 6 diverged (non-finite or residual
+ * above 1e6 times the first), or an error code. */
 int orc_source_iterate(const orc_mesh *m, int ndirs, const double *omega, const double *w,
                        const double *sigma_t, const double *sigma_s, const double *q,
                        const double *inflow, double eta, int use_dsa, int mass_kind, double tol,
-                       int max_it, double cg_rtol, int cg_maxit, int transpose, double *phi_inout,
-                       double *res_hist, int *cg_hist, int *iters_out) {
+                       int max_it, double cg_rtol, int cg_maxit, int transpose, int dsa_form,
+                       double *phi_inout, double *res_hist, int *cg_hist, int *iters_out) {
     int nn = nnodes(m);
     long nc = ncells(m), n = nc * nn;
     double *load = malloc(sizeof(double) * n);
     double *phi_si = malloc(sizeof(double) * n);
-    if (!load || !phi_si) { free(load); free(phi_si); return 3; }
+    double *phi_old = malloc(sizeof(double) * n);
+    double *bar = malloc(sizeof(double) * n);
+    double *zeta = malloc(sizeof(double) * n);
     dsa_mat A;
     memset(&A, 0, sizeof(A));
     long *slot = NULL;
     int rc = 0;
+    if (!load || !phi_si || !phi_old || !bar || !zeta) { rc = 3; goto done; }
     if (use_dsa) {
         rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot);
         if (rc) goto done;
@@ -772,9 +809,15 @@ int orc_source_iterate(const orc_mesh *m, int ndirs, const double *omega, const 
         int cgi = 0;
         if (use_dsa) {
             double crr;
+            memcpy(phi_old, phi_inout, sizeof(double) * n);
             e = dsa_correct_with(m, &A, sigma_t, sigma_s, mass_kind, phi_inout, phi_si, cg_rtol,
                                  cg_maxit, phi_inout, &cgi, &crr);
             if (e) { rc = e; break; }
+            if (dsa_form == 1) {
+                e = triangular_step(m, ndirs, omega, w, sigma_t, sigma_s, slot, transpose, phi_old, phi_inout,
+                                    bar, load, zeta);
+                if (e) { rc = e; break; }
+            }
         } else {
             memcpy(phi_inout, phi_si, sizeof(double) * n);
         }
@@ -788,6 +831,162 @@ done:
     free(slot);
     free(load);
     free(phi_si);
+    free(phi_old);
+    free(bar);
+    free(zeta);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Krylov view: flexible GMRES(m) on S phi = b (eq. schur).            */
+/* ------------------------------------------------------------------ */
+
+/* y = S x = x - sum_d w_d L_d^{-1} (M sigma_s x / 4pi), homogeneous
+ * boundary (the operator of eq. schur). */
+static int schur_apply(const orc_mesh *m, int ndirs, const double *omega, const double *w,
+                       const double *sigma_t, const double *sigma_s, int transpose, const double *x,
+                       double *load, double *y) {
+    long n = ncells(m) * nnodes(m);
+    volume_load(m, sigma_s, x, NULL, load);
+    int e = transport_update(m, ndirs, omega, w, sigma_t, load, NULL, transpose, y);
+    if (e) return e;
+    for (long i = 0; i < n; ++i) y[i] = x[i] - y[i];
+    return 0;
+}
+
+/* z = M^{-1} v: heterogeneous DSA applied to v as to a residual,
+ * z = v + P_T D_ff^{-1} Sigma_f R_T v (Alg. 2), plus for Alg. 1 the thin
+ * update of triangular_step from the thick part of z. */
+static int dsa_precond(const orc_mesh *m, int ndirs, const double *omega, const double *w,
+                       const double *sigma_t, const double *sigma_s, const dsa_mat *A, const long *slot,
+                       int mass_kind, int dsa_form, int transpose, double cg_rtol, int cg_maxit,
+                       const double *v, double *z, double *zero, double *bar, double *load, double *zeta,
+                       int *cg_iters) {
+    long n = ncells(m) * nnodes(m);
+    double crr;
+    for (long i = 0; i < n; ++i) zero[i] = 0.0;
+    int e = dsa_correct_with(m, A, sigma_t, sigma_s, mass_kind, zero, v, cg_rtol, cg_maxit, z, cg_iters, &crr);
+    if (e) return e;
+    if (dsa_form == 1)
+        return triangular_step(m, ndirs, omega, w, sigma_t, sigma_s, slot, transpose, zero, z, bar, load, zeta);
+    return 0;
+}
+
+/* Flexible GMRES(restart) from the initial guess phi_inout, right
+ * preconditioned by the heterogeneous DSA (use_dsa) or not at all.  Modified
+ * Gram-Schmidt Arnoldi, Givens rotations; an iteration is one application
+ * of S (one sweep of every direction).  res_hist[k] = the least-squares
+ * residual estimate |g_{j+1}| / ||b|| after iteration k (at a restart the
+ * true residual is recomputed).  Stops when that estimate is <= tol. */
+int orc_gmres(const orc_mesh *m, int ndirs, const double *omega, const double *w, const double *sigma_t,
+              const double *sigma_s, const double *q, const double *inflow, double eta, int use_dsa,
+              int mass_kind, int dsa_form, double tol, int max_it, int restart, double cg_rtol, int cg_maxit,
+              int transpose, double *phi_inout, double *res_hist, int *cg_hist, int *iters_out) {
+    int nn = nnodes(m);
+    long n = ncells(m) * nn;
+    int mr = restart;
+    if (mr < 1) return 1;
+    double *b = malloc(sizeof(double) * n), *r = malloc(sizeof(double) * n);
+    double *load = malloc(sizeof(double) * n), *wv = malloc(sizeof(double) * n);
+    double *zero = malloc(sizeof(double) * n), *bar = malloc(sizeof(double) * n);
+    double *zeta = malloc(sizeof(double) * n);
+    double *V = malloc(sizeof(double) * n * (mr + 1)), *Z = malloc(sizeof(double) * n * mr);
+    double *H = calloc((size_t)(mr + 1) * mr, sizeof(double));
+    double *cs = malloc(sizeof(double) * mr), *sn = malloc(sizeof(double) * mr);
+    double *g = malloc(sizeof(double) * (mr + 1)), *y = malloc(sizeof(double) * mr);
+    dsa_mat A;
+    memset(&A, 0, sizeof(A));
+    long *slot = NULL;
+    int rc = 0, it = 0;
+    if (!b || !r || !load || !wv || !zero || !bar || !zeta || !V || !Z || !H || !cs || !sn || !g || !y) {
+        rc = 3;
+        goto done;
+    }
+    if (use_dsa && (rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot))) goto done;
+    /* b = sum_d w_d L_d^{-1}(q_d + inflow load) */
+    volume_load(m, sigma_s, NULL, q, load);
+    if ((rc = transport_update(m, ndirs, omega, w, sigma_t, load, inflow, transpose, b))) goto done;
+    double bnorm = norm2(n, b);
+    if (bnorm == 0.0) bnorm = 1.0;
+    rc = 5;
+    while (it < max_it) {
+        /* r = b - S x */
+        int e = schur_apply(m, ndirs, omega, w, sigma_t, sigma_s, transpose, phi_inout, load, r);
+        if (e) { rc = e; break; }
+        for (long i = 0; i < n; ++i) r[i] = b[i] - r[i];
+        double beta = norm2(n, r);
+        if (!isfinite(beta)) { rc = 6; break; }
+        if (beta / bnorm <= tol) { rc = 0; break; }
+        for (long i = 0; i < n; ++i) V[i] = r[i] / beta;
+        for (int k = 0; k <= mr; ++k) g[k] = 0.0;
+        g[0] = beta;
+        int j, done_cycle = 0;
+        for (j = 0; j < mr && it < max_it; ++j) {
+            double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            int cgi = 0;
+            if (use_dsa) {
+                e = dsa_precond(m, ndirs, omega, w, sigma_t, sigma_s, &A, slot, mass_kind, dsa_form, transpose,
+                                cg_rtol, cg_maxit, vj, zj, zero, bar, load, zeta, &cgi);
+                if (e) { rc = e; break; }
+            } else {
+                memcpy(zj, vj, sizeof(double) * n);
+            }
+            e = schur_apply(m, ndirs, omega, w, sigma_t, sigma_s, transpose, zj, load, wv);
+            if (e) { rc = e; break; }
+            for (int i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * n;
+                double h = dot(n, wv, vi);
+                H[(size_t)i * mr + j] = h;
+                for (long k = 0; k < n; ++k) wv[k] -= h * vi[k];
+            }
+            double hn = norm2(n, wv);
+            H[(size_t)(j + 1) * mr + j] = hn;
+            if (hn > 0.0)
+                for (long k = 0; k < n; ++k) V[(size_t)(j + 1) * n + k] = wv[k] / hn;
+            /* previous rotations on the new column, then a new rotation */
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * mr + j], c2 = H[(size_t)(i + 1) * mr + j];
+                H[(size_t)i * mr + j] = cs[i] * a + sn[i] * c2;
+                H[(size_t)(i + 1) * mr + j] = -sn[i] * a + cs[i] * c2;
+            }
+            {
+                double a = H[(size_t)j * mr + j], c2 = H[(size_t)(j + 1) * mr + j];
+                double den = sqrt(a * a + c2 * c2);
+                cs[j] = den > 0.0 ? a / den : 1.0;
+                sn[j] = den > 0.0 ? c2 / den : 0.0;
+                H[(size_t)j * mr + j] = den;
+                H[(size_t)(j + 1) * mr + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+            }
+            double res = fabs(g[j + 1]) / bnorm;
+            if (res_hist) res_hist[it] = res;
+            if (cg_hist) cg_hist[it] = cgi;
+            ++it;
+            if (!isfinite(res)) { rc = 6; done_cycle = 1; ++j; break; }
+            if (res <= tol || hn == 0.0) { done_cycle = 1; ++j; break; }
+        }
+        if (rc != 5 && rc != 6) break;
+        /* x += Z y, with H(0:j, 0:j) y = g(0:j) by back substitution */
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * mr + k] * y[k];
+            y[i] = s / H[(size_t)i * mr + i];
+        }
+        for (int k = 0; k < j; ++k)
+            for (long i = 0; i < n; ++i) phi_inout[i] += y[k] * Z[(size_t)k * n + i];
+        if (rc == 6) break;
+        if (done_cycle) {
+            rc = 0;
+            break;
+        }
+    }
+    if (iters_out) *iters_out = it;
+done:
+    dsa_free(&A);
+    free(slot);
+    free(b); free(r); free(load); free(wv); free(zero); free(bar); free(zeta);
+    free(V); free(Z); free(H); free(cs); free(sn); free(g); free(y);
     return rc;
 }
 
