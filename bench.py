@@ -1,19 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark of S_N source iteration with heterogeneous DSA on one MI355X.
+"""Benchmark of S_N transport sweeps and source iteration with heterogeneous DSA on one MI355X.
 
-Workload (default): 2D 256 x 256 Q1-DG, level-symmetric S8 (40 directions),
-16 x 16-cell tiles seeded void / thin / thick 20 / 50 / 30 %, vacuum
-boundaries, q = 1 on thin tiles; thick threshold eta = 1 (19,712 thick cells).
+Headline workload (c5): 3D 128^3 Q1 upwind-DG, level-symmetric S12 (168
+directions), 16^3-cell tiles seeded void / thin / thick 20 / 50 / 30 %, vacuum
+boundaries, q = 1 on thin tiles.  A step is one FP64 transport sweep of all
+168 directions through the C ABI (sn_sweep: source formation, the tile-plane
+sweep kernels, psi written to HBM); K steps are timed after W warm-up steps,
+and `value` is the sweep grind time, wall time per step divided by
+cells x directions.  The roofline is that of the sweep kernels (HIP events on
+the library's stream), with the algorithmic bytes of a psi-writing sweep.
 
-A step is one source iteration through the C ABI: transport sweep of all 40
-directions, FP64 scalar-flux moment, residual, heterogeneous DSA (SIP on the
-thick cells, block-Jacobi PCG to 1e-2) and update.  K steps are timed from
-phi = 0 after W warm-up steps.  `value` is the grind time of one whole step in
-ns per (cell x direction), FP64 sweep.  Also reported: the same for the FP32
-sweep form, sweep-only grind times, time to a 1e-8 residual for both forms,
-the FP32 form's error against the FP64 forms and the CPU oracle, the sweep
-kernel's roofline fraction (HIP events on the library's stream), the CPU
-oracle's time on the same workload, and the 3D 128^3 S12 sweep grind time.
+The other figures of the metric (sweep grind FP32 vs FP64, time to a 1e-8
+residual, FP32 forms against the FP64 solution and the oracle) and of the
+method's forms (triangular DSA, GMRES, preconditioners, adjoint) go into the
+same JSON line, per workload c1..c5 (and c2s, c2 with pure-scatterer thick
+tiles).  The CPU oracle is timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -28,11 +29,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "sweep grind time ns/(cell·dir) + time-to-1e-8, FP32 vs FP64 sweep, 1 MI355X"
-# relative tolerance of the thick-region CG inside source iteration: on c2 the
-# source-iteration count (45 to 1e-8) is the same for 1e-1 .. 1e-4, so the
-# diffusion correction is solved to 1e-2 rather than over-solved
+# relative tolerance of the thick-region CG inside source iteration for the
+# timing runs: on c2 the source-iteration count (45 to 1e-8) is the same for
+# 1e-1 .. 1e-4, so the correction is solved to 1e-2 rather than over-solved
+# (the paper's inner tolerance, 1e-4, is reported beside it on c2 and c5)
 CG_RTOL = 1e-2
 HBM_PEAK_GBS = 8000.0
+GOLD = os.path.join(ROOT, "tests", "golden")
 
 
 def log(*a):
@@ -47,9 +50,9 @@ def sweep_bytes_per_call(nc, ndirs, nn, s):
 
 
 def traffic_from_profiles(kernel_key):
-    """HBM bytes per launch measured with rocprofv3 counters, if the summary in
+    """HBM bytes per sweep measured with rocprofv3 counters, if the summary in
     profiles/ was taken on the current kernel source (else None)."""
-    from paper_2001_09196_amd.profile_summary import kernel_source_sha
+    from profile_summary import kernel_source_sha
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -57,9 +60,7 @@ def traffic_from_profiles(kernel_key):
         with open(path) as f:
             data = json.load(f)
         ent = data.get(kernel_key)
-        if not ent:
-            return None
-        if ent.get("kernel_src_sha256") != kernel_source_sha():
+        if not ent or ent.get("kernel_src_sha256") != kernel_source_sha():
             return None
         return float(ent["bytes_per_launch"])
     except Exception:
@@ -83,39 +84,191 @@ def copy_probe():
     log(f"copy probe: 3 x {COPY_PROBE_BYTES} bytes")
 
 
-def sweeps_only(name, prec_name, n):
-    """n sweeps of one workload from a seeded random phi (counter passes)."""
+class Workload:
+    """One seeded configuration on the device with its context."""
+
+    def __init__(self, name):
+        import torch
+
+        import sninputs
+        from paper_2001_09196_amd import Context
+        self.torch = torch
+        self.dev = torch.device("cuda:0")
+        self.p = p = sninputs.config(name)
+        self.name = name
+        self.nc, self.D, self.nn = p.ncells, p.ndirs, p.nn
+        self.cd = self.nc * self.D
+        t = lambda a: torch.tensor(a, dtype=torch.float64, device=self.dev)
+        self.q = t(p.q)
+        self.ctx = Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta)
+
+    def zeros(self):
+        return self.torch.zeros((self.nc, self.nn), dtype=self.torch.float64, device=self.dev)
+
+    def si(self, phi=None, **kw):
+        from paper_2001_09196_amd import sn_source_iterate
+        phi = self.zeros() if phi is None else phi
+        kw.setdefault("cg_rtol", CG_RTOL)
+        kw.setdefault("cg_maxit", 5000)
+        kw.setdefault("max_it", 3000)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sn_source_iterate(self.ctx, self.q, None, phi, **kw)
+        self.torch.cuda.synchronize()
+        r["wall_s"] = time.perf_counter() - t0
+        return phi, r
+
+    def krylov(self, **kw):
+        from paper_2001_09196_amd import sn_krylov_solve
+        phi = self.zeros()
+        kw.setdefault("cg_rtol", CG_RTOL)
+        kw.setdefault("cg_maxit", 5000)
+        kw.setdefault("max_it", 3000)
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sn_krylov_solve(self.ctx, self.q, None, phi, **kw)
+        self.torch.cuda.synchronize()
+        r["wall_s"] = time.perf_counter() - t0
+        return phi, r
+
+    def close(self):
+        self.ctx.close()
+
+
+def rel(a, b):
+    import torch
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
+def vs_samples(phi, gold):
+    """Relative l2 error of phi at a fixture's sample points, and of its norm."""
+    import torch
+    idx = torch.tensor(gold["sample_index"], dtype=torch.long, device=phi.device)
+    ref = torch.tensor(gold["sample_value"], dtype=torch.float64, device=phi.device)
+    got = phi.reshape(-1)[idx]
+    return {"sample_rel_l2": float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref)),
+            "norm_rel": abs(float(torch.linalg.norm(phi)) - gold["norm2"]) / gold["norm2"]}
+
+
+def load_gold(name):
+    path = os.path.join(GOLD, name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def summary(r):
+    return {"seconds": r["wall_s"], "iters": int(r["iters"]), "rc": int(r["rc"]), "sweeps": int(r.get("sweeps", 0)),
+            "cg_iters_total": int(r["cg_hist"].sum())}
+
+
+def sweep_grind(w, prec, reps, warmup):
+    """Timed sn_sweep calls: wall time per call and the event-timed sweep
+    kernels per call."""
     import torch
 
+    from paper_2001_09196_amd import SN_FP32, SN_FP64, sn_sweep
+    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
+    dt = torch.float64 if prec == SN_FP64 else torch.float32
+    phi0 = torch.rand((w.nc, w.nn), dtype=torch.float64, device=w.dev,
+                      generator=torch.Generator(w.dev).manual_seed(0))
+    psi = torch.empty((w.nc, w.D, w.nn), dtype=dt, device=w.dev)
+    for _ in range(max(warmup, 1)):
+        sn_sweep(w.ctx, phi0, w.q, None, False, prec, psi)
+    sn_set_kernel_timing(w.ctx, True, sweeps_only=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sn_sweep(w.ctx, phi0, w.q, None, False, prec, psi)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    kt = sn_kernel_timing(w.ctx)
+    sn_set_kernel_timing(w.ctx, False)
+    del psi
+    torch.cuda.empty_cache()
+    return wall * 1e3, kt["sweep_ms"] / kt["sweep_count"]
+
+
+def si_step(w, prec, k=4, **kw):
+    """k source iterations from phi = 0 after one untimed call; per step wall
+    time, the event-timed sweep kernels (fused sweep + moment in 3D) and DSA."""
+    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
+    w.si(tol=0.0, max_it=1, prec=prec, **kw)
+    phi = w.zeros()
+    _, r = w.si(phi, tol=0.0, max_it=k, prec=prec, **kw)
+    wall = r["wall_s"] / k
+    sn_set_kernel_timing(w.ctx, True, sweeps_only=True)
+    _, _ = w.si(w.zeros(), tol=0.0, max_it=k, prec=prec, **kw)
+    ks = sn_kernel_timing(w.ctx)
+    sn_set_kernel_timing(w.ctx, True)
+    _, r2 = w.si(w.zeros(), tol=0.0, max_it=k, prec=prec, **kw)
+    kd = sn_kernel_timing(w.ctx)
+    sn_set_kernel_timing(w.ctx, False)
+    return {"ms_per_step": wall * 1e3, "sweep_kernels_ms": ks["sweep_ms"] / max(ks["sweep_count"], 1),
+            "dsa_ms": kd["dsa_ms"] / max(kd["dsa_count"], 1), "cg_iters": r2["cg_hist"].tolist()}
+
+
+def forms_to_tolerance(w, res, gold=None, oracle_phi=None, krylov=True, triangular=True):
+    """Time to 1e-8 from phi = 0 in every form, with errors against the FP64
+    solution and, where available, against the oracle."""
+    from paper_2001_09196_amd import SN_DSA_TRIANGULAR, SN_FP32, SN_FP64
+    w.si(tol=0.0, max_it=1)                                  # workspace
+    phi64, r64 = w.si(tol=1e-8)
+    res["fp64"] = summary(r64)
+    phi32, r32 = w.si(tol=1e-8, prec=SN_FP32, fp32_refine=True)
+    res["fp32_refined"] = summary(r32)
+    res["fp32_refined"]["fp64_sweeps"] = int(r32["fp64_checks"])
+    res["fp32_refined"]["vs_fp64_rel_l2"] = rel(phi32, phi64)
+    res["fp32_refined"]["speedup_vs_fp64"] = r64["wall_s"] / r32["wall_s"]
+    phip, rp = w.si(tol=0.0, max_it=max(60, int(r64["iters"]) + 20), prec=SN_FP32)
+    res["fp32_plain"] = summary(rp)
+    res["fp32_plain"]["residual_floor"] = float(rp["res_hist"].min())
+    res["fp32_plain"]["vs_fp64_rel_l2"] = rel(phip, phi64)
+    forms = {"fp64": phi64, "fp32_refined": phi32, "fp32_plain": phip}
+    if triangular:
+        phit, rt = w.si(tol=1e-8, dsa_form=SN_DSA_TRIANGULAR)
+        res["triangular_dsa_fp64"] = summary(rt)
+        res["triangular_dsa_fp64"]["vs_fp64_rel_l2"] = rel(phit, phi64)
+    if krylov:
+        phik, rk = w.krylov(tol=1e-8, restart=30)
+        res["gmres30_dsa_fp64"] = summary(rk)
+        res["gmres30_dsa_fp64"]["vs_fp64_rel_l2"] = rel(phik, phi64)
+    if gold is not None:
+        for f, phi in forms.items():
+            res[f]["vs_oracle_samples"] = vs_samples(phi, gold)
+    if oracle_phi is not None:
+        for f, phi in forms.items():
+            res[f]["vs_oracle_rel_l2"] = rel(phi, oracle_phi)
+    return phi64
+
+
+def oracle_sweep_sample(p, ndirs_sample):
+    """The oracle's psi-writing sweep of a direction sample over the full mesh
+    (evenly spaced directions, all octants)."""
+    import numpy as np
+
+    import oracle
     import sninputs
-    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_sweep
-    dev = torch.device("cuda:0")
-    p = sninputs.config(name)
-    prec, dt = (SN_FP64, torch.float64) if prec_name == "fp64" else (SN_FP32, torch.float32)
-    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
-    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
-    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
-    phi = torch.rand((p.ncells, p.nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
-    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
-        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=dt, device=dev)
-        for _ in range(n):
-            sn_sweep(ctx, phi, q, None, False, prec, psi)
-        torch.cuda.synchronize()
-    log(f"{n} sweeps of {name} in {prec_name}")
+    sel = np.arange(0, p.ndirs, p.ndirs // ndirs_sample)[:ndirs_sample]
+    p1 = sninputs.Problem(p.name, p.dim, p.nx, p.ny, p.nz, p.h, p.sigma_t, p.sigma_s, p.q,
+                          p.omega[sel].copy(), p.w[sel].copy())
+    phi = np.random.default_rng(0).uniform(0, 1, (p.ncells, p.nn))
+    t0 = time.perf_counter()
+    oracle.sweep(p1, phi, p.q)
+    t = time.perf_counter() - t0
+    return {"ns_per_cell_dir": t / (p.ncells * len(sel)) * 1e9, "directions": int(len(sel)), "seconds": t}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 128^3 S12 sweep measurement")
+    ap.add_argument("--headline-only", action="store_true", help="only the c5 sweep steps (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 2 GiB device copy three times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--sweeps-only", type=int, default=0, metavar="N",
                     help="only run N sweeps of --config in --prec (for rocprofv3 counter passes)")
-    ap.add_argument("--config", default="c2", help="workload of --sweeps-only (c1..c5)")
+    ap.add_argument("--config", default="c5", help="workload of --sweeps-only (c1..c5)")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"), help="sweep precision of --sweeps-only")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -125,140 +278,50 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    if args.sweeps_only:
-        sweeps_only(args.config, args.prec, args.sweeps_only)
-        return
 
     import numpy as np
     import torch
 
-    import sninputs
-    from paper_2001_09196_amd import (SN_FP32, SN_FP64, Context, sn_source_iterate, sn_sweep)
-    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
+    from paper_2001_09196_amd import SN_FP32, SN_FP64, sn_sweep
+    torch.cuda.set_device(0)
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    p = sninputs.config("c2")
-    nc, D, nn = p.ncells, p.ndirs, p.nn
-    cd = nc * D
-    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
-    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
-    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
-    ctx = Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta)
-    log(f"c2: {nc} cells x {D} dirs, {ctx.thick_count} thick cells")
-
-    def run_steps(k, prec, timing=False, sweeps_only=True):
-        phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-        if timing:
-            sn_set_kernel_timing(ctx, True, sweeps_only=sweeps_only)
+    if args.sweeps_only:
+        w = Workload(args.config)
+        prec, dt = (SN_FP64, torch.float64) if args.prec == "fp64" else (SN_FP32, torch.float32)
+        phi = torch.rand((w.nc, w.nn), dtype=torch.float64, device=w.dev,
+                         generator=torch.Generator(w.dev).manual_seed(0))
+        psi = torch.empty((w.nc, w.D, w.nn), dtype=dt, device=w.dev)
+        for _ in range(args.sweeps_only):
+            sn_sweep(w.ctx, phi, w.q, None, False, prec, psi)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
-                              cg_maxit=1000)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kt = None
-        if timing:
-            kt = sn_kernel_timing(ctx)
-            sn_set_kernel_timing(ctx, False)
-        return (t1 - t0), r, kt
+        log(f"{args.sweeps_only} sweeps of {args.config} in {args.prec}")
+        return
 
-    # ---- timed steps, FP64 sweep (the reported value) ----
-    # HIP events bracket the sweep kernel (the roofline's kernel) in every
-    # timed step; each recorded event holds the next kernel back by a few
-    # microseconds, so the DSA's share of the step is timed in a separate
-    # run of the same steps that does not enter the reported value.
-    run_steps(max(args.warmup, 1), SN_FP64)
-    dt64, r64, kt64 = run_steps(args.steps, SN_FP64, timing=True)
-    _, _, kt64_all = run_steps(args.steps, SN_FP64, timing=True, sweeps_only=False)
-    ms_step = dt64 / args.steps * 1e3
-    value = ms_step * 1e6 / cd
-    log(f"fp64 step: {ms_step:.3f} ms = {value:.5f} ns/(cell*dir); CG its {r64['cg_hist'].tolist()}")
-    # ---- same for the FP32 sweep form ----
-    run_steps(max(args.warmup, 1), SN_FP32)
-    dt32, r32, kt32 = run_steps(args.steps, SN_FP32, timing=True)
-    ms_step32 = dt32 / args.steps * 1e3
-    log(f"fp32 step: {ms_step32:.3f} ms")
-
-    # ---- sweep-only grind time (event-timed sweep kernels) ----
-    phi0 = torch.rand((nc, nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
-    grind = {}
-    sweep_ms = {}
-    for name, prec, dt in (("fp64", SN_FP64, torch.float64), ("fp32", SN_FP32, torch.float32)):
-        psi = torch.empty((nc, D, nn), dtype=dt, device=dev)
-        for _ in range(3):
-            sn_sweep(ctx, phi0, q, None, False, prec, psi)
-        reps = 20
-        sn_set_kernel_timing(ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            sn_sweep(ctx, phi0, q, None, False, prec, psi)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kt = sn_kernel_timing(ctx)
-        sn_set_kernel_timing(ctx, False)
-        sweep_ms[name] = kt["sweep_ms"] / kt["sweep_count"]
-        grind[name] = {"sweep_kernel_ns": sweep_ms[name] * 1e6 / cd,
-                       "sn_sweep_call_ns": (t1 - t0) / reps * 1e9 / cd}
-        del psi
-        log(f"sweep {name}: kernel {sweep_ms[name]*1e3:.1f} us, grind {grind[name]['sweep_kernel_ns']:.5f} ns")
-
-    # ---- time to 1e-8 ----
-    def solve(prec, tol=1e-8):
-        best = None
-        for _ in range(3):
-            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = sn_source_iterate(ctx, q, None, phi, tol=tol, max_it=2000, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
-                                  cg_maxit=1000)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-            if best is None or t < best[0]:
-                best = (t, r, phi.clone())
-        return best
-
-    # ---- thick-region preconditioners: block Jacobi against multigrid ----
-    def dsa_compare(precond, k=6):
-        phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
-                          cg_maxit=1000, precond=precond)     # first use builds the hierarchy
-        torch.cuda.synchronize()
-        first = time.perf_counter() - t0
-        phi.zero_()
-        sn_set_kernel_timing(ctx, True)
-        r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
-                              cg_maxit=1000, precond=precond)
-        kt = sn_kernel_timing(ctx)
-        sn_set_kernel_timing(ctx, False)
-        return {"dsa_ms": kt["dsa_ms"] / max(kt["dsa_count"], 1), "cg_iters": r["cg_hist"].tolist(),
-                "first_call_s": first}
-
-    precond_cmp = {"block_jacobi": dsa_compare(0), "multigrid": dsa_compare(1)}
-    log(f"c2 DSA: block Jacobi {precond_cmp['block_jacobi']['dsa_ms']:.3f} ms "
-        f"{precond_cmp['block_jacobi']['cg_iters']}, multigrid {precond_cmp['multigrid']['dsa_ms']:.3f} ms "
-        f"{precond_cmp['multigrid']['cg_iters']}")
-
-    t64, s64, phi64 = solve(SN_FP64)
-    t32, s32, phi32 = solve(SN_FP32)
-    err32_vs64 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
-    log(f"time to 1e-8: fp64 {t64*1e3:.1f} ms ({s64['iters']} it, rc {s64['rc']}), "
-        f"fp32 {t32*1e3:.1f} ms ({s32['iters']} it, rc {s32['rc']}), fp32 vs fp64 {err32_vs64:.2e}")
-
-    # ---- roofline of the dominant kernel (per step) ----
-    sweep_per_step = kt64["sweep_ms"] / max(kt64["sweep_count"], 1)
-    dsa_per_step = kt64_all["dsa_ms"] / max(kt64_all["dsa_count"], 1)
-    bytes_sweep = sweep_bytes_per_call(nc, D, nn, 8)
-    roofline = {"kernel": "sweep2d_kernel<double> (one launch per sweep)", "bound": "hbm",
-                "achieved": bytes_sweep / (sweep_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "algorithmic_bytes_per_launch": bytes_sweep, "avg_launch_ms": sweep_per_step,
-                "traffic": traffic_from_profiles("sweep2d_fp64_c2")}
+    # ---- headline: c5 FP64 psi sweep, K timed steps ----
+    w5 = Workload("c5")
+    log(f"c5: {w5.nc} cells x {w5.D} dirs, {w5.ctx.thick_count} thick cells")
+    wall64, kern64 = sweep_grind(w5, SN_FP64, args.steps, args.warmup)
+    value = wall64 * 1e6 / w5.cd
+    bytes64 = sweep_bytes_per_call(w5.nc, w5.D, w5.nn, 8)
+    roofline = {"kernel": "sweep3d_kernel<double> (one launch per tile-diagonal plane, summed per sweep)",
+                "bound": "hbm", "achieved": bytes64 / (kern64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "algorithmic_bytes_per_sweep": bytes64, "sweep_kernels_ms": kern64,
+                "traffic": traffic_from_profiles("sweep3d_fp64_c5")}
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
-    log(f"per step: sweep {sweep_per_step:.3f} ms, dsa {dsa_per_step:.3f} ms of {ms_step:.3f} ms")
-
+    log(f"c5 fp64 sweep: {wall64:.3f} ms per step ({kern64:.3f} ms in the sweep kernels), "
+        f"{value:.5f} ns/(cell*dir), {roofline['achieved']:.0f} GB/s")
+    wall32, kern32 = sweep_grind(w5, SN_FP32, args.steps, args.warmup)
+    bytes32 = sweep_bytes_per_call(w5.nc, w5.D, w5.nn, 4)
+    c5 = {"workload": "c5: 3D 128^3 Q1-DG, S12 (168 dirs), seeded 16^3 tiles", "cells": w5.nc, "dirs": w5.D,
+          "thick_cells": w5.ctx.thick_count,
+          "sweep_fp64": {"ms": wall64, "kernels_ms": kern64, "grind_ns": value,
+                         "hbm_frac": roofline["frac"]},
+          "sweep_fp32": {"ms": wall32, "kernels_ms": kern32, "grind_ns": wall32 * 1e6 / w5.cd,
+                         "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
+                         "hbm_frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic_from_profiles("sweep3d_fp32_c5"),
+                         "speedup_vs_fp64": wall64 / wall32}}
+    log(f"c5 fp32 sweep: {wall32:.3f} ms ({kern32:.3f} ms kernels)")
     out = {
         "metric": METRIC,
         "value": value,
@@ -266,239 +329,194 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": wall64,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c2: 2D 256x256 Q1 upwind-DG, S8 (40 dirs), seeded 16x16 tiles void/thin/thick "
-                               "20/50/30%, vacuum; one step = sweep + FP64 moment + residual + thick-only DSA "
-                               "(SIP, block-Jacobi PCG rtol 1e-2) + update",
-                   "cells": nc, "dirs": D, "thick_cells": ctx.thick_count, "eta": p.eta},
+        "config": {"workload": "c5: 3D 128^3 Q1 upwind-DG, level-symmetric S12 (168 dirs), seeded 16^3 tiles "
+                               "void/thin/thick 20/50/30%, vacuum, q = 1 on thin tiles; one step = one FP64 "
+                               "transport sweep of all directions writing psi (sn_sweep)",
+                   "cells": w5.nc, "dirs": w5.D, "eta": w5.p.eta},
         "roofline": roofline,
-        "step_breakdown_ms": {"sweep": sweep_per_step, "dsa": dsa_per_step,
-                              "cg_iters_per_dsa": float(np.mean(r64["cg_hist"]))},
-        "fp32_form": {"ms_per_step": ms_step32, "value": ms_step32 * 1e6 / cd, "dtype": "f32 sweep, f64 moment/DSA",
-                      "speedup_vs_fp64_step": ms_step / ms_step32},
-        "sweep_grind_ns": grind,
-        "time_to_1e-8": {"fp64": {"seconds": t64, "iters": s64["iters"], "rc": s64["rc"],
-                                  "cg_iters_total": int(np.sum(s64["cg_hist"]))},
-                         "fp32": {"seconds": t32, "iters": s32["iters"], "rc": s32["rc"],
-                                  "cg_iters_total": int(np.sum(s32["cg_hist"]))},
-                         "fp32_speedup": t64 / t32, "fp32_vs_fp64_rel_l2": err32_vs64},
-        "dsa_preconditioners_c2": precond_cmp,
     }
-    del ctx
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        return
 
-    # ---- pure-scatterer thick tiles (sigma_a = 0): where multigrid matters ----
-    try:
-        out["dsa_preconditioners_c2s"] = pure_scatterer_compare(log)
-    except Exception as e:  # report, do not hide
-        out["dsa_preconditioners_c2s"] = {"error": repr(e)}
+    # ---- c5: source-iteration steps and the solves to 1e-8 ----
+    c5["si_step_fp64"] = si_step(w5, SN_FP64)
+    c5["si_step_fp32_plain"] = si_step(w5, SN_FP32)
+    c5["si_step_fp64"]["grind_ns"] = c5["si_step_fp64"]["ms_per_step"] * 1e6 / w5.cd
+    log(f"c5 SI step: fp64 {c5['si_step_fp64']['ms_per_step']:.2f} ms "
+        f"(fused sweep {c5['si_step_fp64']['sweep_kernels_ms']:.2f}, dsa {c5['si_step_fp64']['dsa_ms']:.2f})")
+    c5["dsa_preconditioners"] = {}
+    for name, pc in (("block_jacobi", 0), ("multigrid", 1)):
+        c5["dsa_preconditioners"][name] = si_step(w5, SN_FP64, precond=pc)
+    c5["dsa_cg_rtol_1e-4"] = si_step(w5, SN_FP64, cg_rtol=1e-4)
+    c5["to_1e-8"] = {}
+    forms_to_tolerance(w5, c5["to_1e-8"], gold=load_gold("c5_phi.json"))
+    log(f"c5 to 1e-8: {json.dumps({k: (v['seconds'], v['iters']) for k, v in c5['to_1e-8'].items()})}")
+    w5.close()
+    del w5
+    torch.cuda.empty_cache()
+    out["c5"] = c5
 
-    # ---- 3D: 128^3, S12 (168 dirs) sweep grind time and HBM fraction ----
-    if not args.no_3d:
-        try:
-            out["sweep3d_c5"] = bench_3d(log)
-        except Exception as e:  # report, do not hide
-            out["sweep3d_c5"] = {"error": repr(e)}
+    # ---- c3 ----
+    w3 = Workload("c3")
+    c3 = {"workload": "c3: 3D 64^3, S8 (80 dirs), seeded 8^3 tiles", "to_1e-8": {}}
+    wl, kl = sweep_grind(w3, SN_FP64, 10, 2)
+    c3["sweep_fp64"] = {"ms": wl, "kernels_ms": kl, "grind_ns": wl * 1e6 / w3.cd}
+    forms_to_tolerance(w3, c3["to_1e-8"], gold=load_gold("c3_phi.json"))
+    w3.close()
+    out["c3"] = c3
 
-    # ---- 3D solves to 1e-8 in both forms (C3, C5) ----
-    if not args.no_3d:
-        try:
-            out["time_to_1e-8_3d"] = bench_to_tolerance_3d(log)
-        except Exception as e:  # report, do not hide
-            out["time_to_1e-8_3d"] = {"error": repr(e)}
-
-    # ---- CPU oracle on the same workload (bounded: one solve to 1e-8) ----
+    # ---- c2 and the pure-scatterer variant ----
+    # (the oracle is used only in the CPU-baseline leg: its timings on the
+    # host cores, and the GPU solutions' errors against it)
     if not args.no_cpu_baseline:
         import oracle
-        nth = oracle.num_threads()
+    w2 = Workload("c2")
+    c2 = {"workload": "c2: 2D 256^2, S8 (40 dirs), seeded 16^2 tiles", "thick_cells": w2.ctx.thick_count}
+    for name, prec in (("fp64", SN_FP64), ("fp32", SN_FP32)):
+        wl, kl = sweep_grind(w2, prec, 20, 3)
+        c2[f"sweep_{name}"] = {"ms": wl, "kernels_ms": kl, "grind_ns": wl * 1e6 / w2.cd}
+    c2["si_step_fp64"] = si_step(w2, SN_FP64, k=20)
+    c2["dsa_preconditioners"] = {n: si_step(w2, SN_FP64, k=6, precond=pc) for n, pc in
+                                 (("block_jacobi", 0), ("multigrid", 1))}
+    c2["dsa_cg_rtol_1e-4"] = si_step(w2, SN_FP64, k=20, cg_rtol=1e-4)
+    ro = None
+    if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        ro = oracle.source_iterate(p, tol=1e-8, max_it=2000, use_dsa=True, cg_rtol=CG_RTOL)
-        tcpu = time.perf_counter() - t0
-        its = ro["iters"]
-        ref = torch.tensor(ro["phi"], dtype=torch.float64, device=dev)
-        e64 = float(torch.linalg.norm(phi64 - ref) / torch.linalg.norm(ref))
-        e32 = float(torch.linalg.norm(phi32 - ref) / torch.linalg.norm(ref))
-        out["cpu_baseline"] = {"value": tcpu / its * 1e9 / cd, "unit": "ns/(cell*dir)", "cores": nth,
+        ro = oracle.source_iterate(w2.p, tol=1e-8, max_it=3000, use_dsa=True, cg_rtol=CG_RTOL)
+        c2["oracle_to_1e-8"] = {"seconds": time.perf_counter() - t0, "iters": ro["iters"],
+                                "threads": oracle.num_threads()}
+    c2["to_1e-8"] = {}
+    forms_to_tolerance(w2, c2["to_1e-8"],
+                       oracle_phi=torch.tensor(ro["phi"], device=w2.dev) if ro is not None else None)
+    w2.close()
+    out["c2"] = c2
+    w2s = Workload("c2s")
+    c2s = {"workload": "c2s: c2 with pure-scatterer thick tiles (sigma_t = sigma_s = 1e3)"}
+    from paper_2001_09196_amd import SN_DSA_TRIANGULAR
+    for name, kw in (("block_jacobi", dict(precond=0)), ("multigrid", dict(precond=1)),
+                     ("multigrid_triangular", dict(precond=1, dsa_form=SN_DSA_TRIANGULAR))):
+        w2s.si(tol=0.0, max_it=1, **kw)
+        _, r = w2s.si(tol=1e-8, **kw)
+        c2s[name] = summary(r)
+    _, rk = w2s.krylov(tol=1e-8, restart=30, precond=1)
+    c2s["gmres30_multigrid"] = summary(rk)
+    w2s.close()
+    out["c2s"] = c2s
+    log(f"c2s: {json.dumps({k: (v['seconds'], v['iters']) for k, v in c2s.items() if isinstance(v, dict)})}")
+
+    # ---- c1: iteration counts of the forms, both DSA masses ----
+    w1 = Workload("c1")
+    c1 = {"workload": "c1: 2D 16^2, S4 (12 dirs), thick block + void"}
+    ref1 = None
+    if not args.no_cpu_baseline:
+        ro1 = oracle.source_iterate(w1.p, tol=1e-13, max_it=3000, use_dsa=True, cg_rtol=1e-13)
+        ref1 = torch.tensor(ro1["phi"], device=w1.dev)
+    for name, kw in (("mass_sigma_s", dict(mass_kind=0)), ("mass_sigma_t", dict(mass_kind=1)),
+                     ("triangular_mass_sigma_s", dict(dsa_form=SN_DSA_TRIANGULAR)),
+                     ("no_dsa", dict(use_dsa=False, max_it=200000))):
+        w1.si(tol=0.0, max_it=1, **{k: v for k, v in kw.items() if k != "max_it"})
+        phi, r = w1.si(tol=1e-8, **kw)
+        c1[name] = summary(r)
+        c1[name]["cg_iters_per_dsa"] = float(r["cg_hist"].mean()) if kw.get("use_dsa", True) else 0.0
+        if ref1 is not None:
+            c1[name]["vs_oracle_rel_l2"] = rel(phi, ref1)
+    phik, rk = w1.krylov(tol=1e-8, restart=30)
+    c1["gmres30_dsa"] = summary(rk)
+    if ref1 is not None:
+        c1["gmres30_dsa"]["vs_oracle_rel_l2"] = rel(phik, ref1)
+    c1["forms"] = {}
+    forms_to_tolerance(w1, c1["forms"], oracle_phi=ref1, krylov=False, triangular=False)
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        ro1b = oracle.source_iterate(w1.p, tol=1e-8, max_it=3000, use_dsa=True, cg_rtol=CG_RTOL)
+        c1["oracle_to_1e-8"] = {"seconds": time.perf_counter() - t0, "iters": ro1b["iters"]}
+    w1.close()
+    out["c1"] = c1
+    log(f"c1: {json.dumps({k: v['iters'] for k, v in c1.items() if isinstance(v, dict) and 'iters' in v})}")
+
+    # ---- c4: adjoint gradient of the corner detector ----
+    out["c4"] = bench_adjoint_c4(log)
+
+    # ---- CPU oracle: bounded samples on the host cores ----
+    if not args.no_cpu_baseline:
+        nth = oracle.num_threads()
+        s5 = oracle_sweep_sample(sninputs_config("c5"), 32)
+        out["cpu_baseline"] = {"value": s5["ns_per_cell_dir"], "unit": "ns/(cell*dir)", "cores": nth,
                                "kind": "oracle",
-                               "sample": f"c2 solve to 1e-8 from phi=0: {its} source iterations "
-                                         f"(+1 sweep for ||b||) in {tcpu:.2f} s; value = time per iteration",
-                               "time_to_1e-8_s": tcpu}
-        out["time_to_1e-8"]["fp64_vs_oracle_rel_l2"] = e64
-        out["time_to_1e-8"]["fp32_vs_oracle_rel_l2"] = e32
-        log(f"oracle: {tcpu:.2f} s for {its} iterations on {nth} threads; gpu fp64 err {e64:.2e}, fp32 {e32:.2e}")
+                               "sample": f"c5 psi-writing sweep of {s5['directions']} of the 168 directions "
+                                         f"(evenly spaced, all octants) over the full 128^3 mesh in "
+                                         f"{s5['seconds']:.2f} s on {nth} threads; value = seconds / (cells x "
+                                         f"directions swept), the unit of `value`",
+                               "grind_ns_by_config": {"c5": s5["ns_per_cell_dir"],
+                                                      "c3": oracle_sweep_sample(sninputs_config("c3"), 8)[
+                                                          "ns_per_cell_dir"],
+                                                      "c2": oracle_sweep_sample(sninputs_config("c2"), 40)[
+                                                          "ns_per_cell_dir"]},
+                               "time_to_1e-8_s": {"c1": c1["oracle_to_1e-8"]["seconds"],
+                                                  "c2": out["c2"].get("oracle_to_1e-8", {}).get("seconds")}}
+        log(f"oracle: c5 sweep sample {s5['seconds']:.2f} s on {nth} threads, {s5['ns_per_cell_dir']:.1f} ns")
     print(json.dumps(out), flush=True)
 
 
-def pure_scatterer_compare(log):
-    """c2s (c2 with sigma_s = sigma_t in the thick tiles): FP64 source iteration
-    to 1e-8 with each thick-region preconditioner."""
-    import torch
-
+def sninputs_config(name):
     import sninputs
-    from paper_2001_09196_amd import SN_FP64, Context, sn_source_iterate
-    dev = torch.device("cuda:0")
-    p = sninputs.config("c2s")
-    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
-    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
-    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
-    res = {"workload": "c2s: c2 with pure-scatterer thick tiles (sigma_t = sigma_s = 1e3)"}
-    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
-        for name, pc in (("block_jacobi", 0), ("multigrid", 1)):
-            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
-                              cg_maxit=5000, precond=pc)      # builds the hierarchy on first use
-            phi.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=2000, use_dsa=True, prec=SN_FP64,
-                                  cg_rtol=CG_RTOL, cg_maxit=5000, precond=pc)
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-            res[name] = {"time_to_1e-8_s": t, "iters": r["iters"], "rc": r["rc"],
-                         "cg_iters_total": int(r["cg_hist"].sum()),
-                         "cg_iters_mean": float(r["cg_hist"].mean())}
-            log(f"c2s {name}: {t*1e3:.1f} ms to 1e-8, {r['iters']} SI iterations, "
-                f"CG {int(r['cg_hist'].sum())} total")
-    return res
+    return sninputs.config(name)
 
 
-def bench_3d(log):
-    import torch
-
-    import sninputs
-    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_sweep
-    from paper_2001_09196_amd.binding import sn_kernel_timing, sn_set_kernel_timing
-    dev = torch.device("cuda:0")
-    p = sninputs.config("c5")
-    nc, D, nn = p.ncells, p.ndirs, p.nn
-    cd = nc * D
-    st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
-    ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
-    q = torch.tensor(p.q, dtype=torch.float64, device=dev)
-    phi0 = torch.rand((nc, nn), dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
-    res = {"workload": "c5: 3D 128^3 Q1-DG, S12 (168 dirs), seeded 16^3 tiles", "cells": nc, "dirs": D}
-    with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
-        for name, prec, dt, s in (("fp32", SN_FP32, torch.float32, 4), ("fp64", SN_FP64, torch.float64, 8)):
-            psi = torch.empty((nc, D, nn), dtype=dt, device=dev)
-            sn_sweep(ctx, phi0, q, None, False, prec, psi)
-            reps = 5
-            sn_set_kernel_timing(ctx, True)
-            for _ in range(reps):
-                sn_sweep(ctx, phi0, q, None, False, prec, psi)
-            kt = sn_kernel_timing(ctx)
-            sn_set_kernel_timing(ctx, False)
-            ms = kt["sweep_ms"] / kt["sweep_count"]
-            b = sweep_bytes_per_call(nc, D, nn, s)
-            res[name] = {"sweep_ms": ms, "grind_ns": ms * 1e6 / cd, "algorithmic_bytes": b,
-                         "achieved_GBs": b / (ms * 1e-3) / 1e9, "hbm_frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "traffic": traffic_from_profiles(f"sweep3d_{name}_c5")}
-            log(f"c5 sweep {name}: {ms:.3f} ms, grind {ms*1e6/cd:.5f} ns, {res[name]['achieved_GBs']:.0f} GB/s")
-            del psi
-            torch.cuda.empty_cache()
-        # source iterations: fused sweep + moment (psi never stored) and DSA
-        from paper_2001_09196_amd import sn_source_iterate
-        for pc_name, pc in (("block_jacobi", 0), ("multigrid", 1)):
-            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-            t0 = time.perf_counter()
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
-                              cg_maxit=2000, precond=pc)
-            torch.cuda.synchronize()
-            first = time.perf_counter() - t0
-            phi.zero_()
-            sn_set_kernel_timing(ctx, True)
-            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=4, use_dsa=True, prec=SN_FP64, cg_rtol=CG_RTOL,
-                                  cg_maxit=2000, precond=pc)
-            kt = sn_kernel_timing(ctx)
-            sn_set_kernel_timing(ctx, False)
-            res.setdefault("dsa_preconditioners", {})[pc_name] = {
-                "dsa_ms": kt["dsa_ms"] / max(kt["dsa_count"], 1), "cg_iters": r["cg_hist"].tolist(),
-                "first_call_s": first}
-            log(f"c5 DSA {pc_name}: {res['dsa_preconditioners'][pc_name]['dsa_ms']:.3f} ms, CG {r['cg_hist'].tolist()}, "
-                f"first call {first:.2f} s")
-            del phi
-        for name, prec in (("fp32", SN_FP32), ("fp64", SN_FP64)):
-            k = 4
-            phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-            sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
-                              cg_maxit=2000)
-            phi.zero_()
-            sn_set_kernel_timing(ctx, True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=k, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
-                                  cg_maxit=2000)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            kt = sn_kernel_timing(ctx)
-            sn_set_kernel_timing(ctx, False)
-            fused = kt["sweep_ms"] / max(kt["sweep_count"], 1)
-            res[name]["si_step_ms"] = (t1 - t0) / k * 1e3
-            res[name]["fused_sweep_moment_ms"] = fused
-            res[name]["fused_grind_ns"] = fused * 1e6 / cd
-            res[name]["dsa_ms"] = kt["dsa_ms"] / max(kt["dsa_count"], 1)
-            res[name]["cg_iters"] = r["cg_hist"].tolist()
-            log(f"c5 SI {name}: step {res[name]['si_step_ms']:.2f} ms, fused sweep+moment {fused:.3f} ms, "
-                f"dsa {res[name]['dsa_ms']:.3f} ms, CG {r['cg_hist'].tolist()}")
-            del phi
-    return res
-
-
-def bench_to_tolerance_3d(log):
-    """C3 and C5 solved to 1e-8 from phi = 0 in both forms (one timed solve
-    each, after a first call that builds the context's workspace): seconds,
-    source iterations, FP32 form against FP64, and for C3 both against the
-    oracle's converged flux at its stored sample points."""
+def bench_adjoint_c4(log):
+    """Forward solve, adjoint solve and per-quadrant contraction for the
+    detector on cells [120,128)^2 of c4 (jittered 128^2, S8), against the
+    oracle's adjoint on the fixture's cells."""
     import numpy as np
     import torch
 
     import sninputs
-    from paper_2001_09196_amd import SN_FP32, SN_FP64, Context, sn_source_iterate
+    from paper_2001_09196_amd.adjoint import Solver, detector_response
+    p = sninputs.config("c4")
     dev = torch.device("cuda:0")
-    gold_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c3_phi.json")
-    out = {}
-    for name in ("c3", "c5"):
-        p = sninputs.config(name)
-        nc, nn = p.ncells, p.nn
-        st = torch.tensor(p.sigma_t, dtype=torch.float64, device=dev)
-        ss = torch.tensor(p.sigma_s, dtype=torch.float64, device=dev)
-        q = torch.tensor(p.q, dtype=torch.float64, device=dev)
-        res = {"workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.ndirs} dirs", "cg_rtol": CG_RTOL}
-        phis = {}
-        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta) as ctx:
-            for form, prec in (("fp64", SN_FP64), ("fp32", SN_FP32)):
-                phi = torch.zeros((nc, nn), dtype=torch.float64, device=dev)
-                sn_source_iterate(ctx, q, None, phi, tol=0.0, max_it=1, use_dsa=True, prec=prec, cg_rtol=CG_RTOL,
-                                  cg_maxit=2000)
-                phi.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                r = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=2000, use_dsa=True, prec=prec,
-                                      cg_rtol=CG_RTOL, cg_maxit=2000)
-                torch.cuda.synchronize()
-                res[form] = {"seconds": time.perf_counter() - t0, "iters": r["iters"], "rc": r["rc"],
-                             "cg_iters_total": int(r["cg_hist"][:r["iters"]].sum())}
-                phis[form] = phi
-                log(f"{name} to 1e-8 {form}: {res[form]['seconds']:.3f} s, {r['iters']} iterations")
-        res["fp32_speedup"] = res["fp64"]["seconds"] / res["fp32"]["seconds"]
-        res["fp32_vs_fp64_rel_l2"] = float(torch.linalg.norm(phis["fp32"] - phis["fp64"]) /
-                                           torch.linalg.norm(phis["fp64"]))
-        if name == "c3" and os.path.exists(gold_path):
-            gold = json.load(open(gold_path))
-            res["oracle_samples"] = (f"{len(gold['sample_index'])} values of the oracle's flux solved to residual "
-                                     f"{gold['res_last']:.1e}; the gap below is the 1e-8 stop of these solves")
-            idx = torch.tensor(gold["sample_index"], dtype=torch.long, device=dev)
-            ref = torch.tensor(gold["sample_value"], dtype=torch.float64, device=dev)
-            for form in ("fp64", "fp32"):
-                got = phis[form].reshape(-1)[idx]
-                res[form]["vs_oracle_samples_rel_l2"] = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
-        out[name] = res
-        del phis
-        torch.cuda.empty_cache()
-    return out
+    r = np.zeros(p.ncells)
+    for j in range(120, 128):
+        for i in range(120, 128):
+            r[j * p.nx + i] = 1.0
+    solver = Solver(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, torch.tensor(p.q, device=dev), eta=p.eta,
+                    tol=6e-14, max_it=600, cg_rtol=1e-6, cg_maxit=20000)
+    res = {"workload": "c4: 2D 128^2, S8, jittered; J = detector on cells [120,128)^2"}
+    for rep in range(2):
+        with np.errstate(divide="ignore"):
+            lt = torch.tensor(np.log(p.sigma_t), dtype=torch.float64, device=dev, requires_grad=True)
+            ls = torch.tensor(np.log(p.sigma_s), dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = detector_response(lt, ls, solver, r=torch.tensor(r, device=dev))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    res.update({"forward_s": t1 - t0, "backward_s": t2 - t1, "J": float(J.detach())})
+    gold = load_gold("c4_adjoint.json")
+    if gold is not None:
+        g = {"t": lt.grad.cpu().numpy(), "s": ls.grad.cpu().numpy()}
+        errs = {}
+        for key in ("t", "s"):
+            worst = 0.0
+            for cells_key, val_key in (("fd_cells", f"g_{key}_fd_cells"), ("sample_cells", f"g_{key}_sample"),
+                                       (f"fd_cells_big_{key}", f"g_{key}_fd_cells_big_{key}")):
+                idx = np.array(gold[cells_key])
+                worst = max(worst, float(np.max(np.abs(g[key][idx] - np.array(gold[val_key])))) /
+                            gold[f"g_{key}_maxabs"])
+            errs[f"g_{key}"] = worst
+        res["vs_oracle_max_err_over_max"] = errs
+        res["J_vs_oracle_rel"] = abs(res["J"] - gold["J"]) / abs(gold["J"])
+    log(f"c4 adjoint: forward {res['forward_s']:.3f} s, backward {res['backward_s']:.3f} s")
+    return res
 
 
 if __name__ == "__main__":

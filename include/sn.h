@@ -142,22 +142,28 @@ typedef struct {
 int sn_dsa_thick_correct(sn_context *ctx, const double *phi_old, const double *phi_si, double *phi_out,
                          const sn_dsa_opts *opts, sn_dsa_stats *stats);
 
+/* forms of the heterogeneous DSA (Section 2.3) */
+#define SN_DSA_DIAGONAL 0      /* Alg. 2: thick-region update only */
+#define SN_DSA_TRIANGULAR 1    /* Alg. 1: Alg. 2, then the thick part of the corrected residual is swept
+                                  once (zero source, vacuum) and its moment added to the thin DOFs */
+
 typedef struct {
     double tol;                /* stop when ||phi_SI - phi|| / ||b|| <= tol, b = sweep of q from phi = 0 */
     int max_it;
     int use_dsa;
-    sn_precision prec;         /* precision of the sweep; moment, residual and DSA are FP64.  With
-                                  SN_FP32, iterations after the first sweep the increment
-                                  sigma_s (phi_i - phi_{i-1}) and add its FP64 moment to phi_SI;
-                                  phi_SI is recomputed by one FP64 sweep when that residual first
-                                  drops below 1e-4 and whenever it meets tol, and the iteration
-                                  stops only on the exact residual (FP64 psi workspace allocated
-                                  on demand) */
+    sn_precision prec;         /* precision of the sweep; moment, residual and DSA are FP64 (see fp32_refine) */
     sn_dsa_opts dsa;
     int transpose;             /* 1: adjoint iteration with L_d^{-T} sweeps */
     double *phi_ckpt;          /* device [ckpt_cap][ncells][nn] or NULL: phi after iteration it goes
                                   to slot it % ckpt_cap, so the last ckpt_cap iterates are kept */
     int ckpt_cap;              /* slots in phi_ckpt; must be >= 1 when phi_ckpt is not NULL */
+    int fp32_refine;           /* SN_FP32 only.  0: plain FP32 form, every sweep FP32 on the full source
+                                  (sigma_s phi + q)/4pi.  1: defect correction: after the first sweep the
+                                  FP32 sweeps act on the increment sigma_s (phi_i - phi_{i-1}) and add their
+                                  FP64 moment to phi_SI; phi_SI is recomputed by one FP64 sweep when that
+                                  residual first drops below 1e-4 and whenever it meets tol, and the
+                                  iteration stops only on the exact residual */
+    int dsa_form;              /* SN_DSA_DIAGONAL or SN_DSA_TRIANGULAR (one extra sweep per iteration) */
 } sn_iter_opts;
 
 typedef struct {
@@ -165,7 +171,8 @@ typedef struct {
     double *res_hist;          /* host [max_it] or NULL: relative residual per iteration */
     int *cg_hist;              /* host [max_it] or NULL: CG iterations per iteration */
     double seconds;            /* wall time of the call */
-    int fp64_checks;           /* FP32 form: number of FP64 verification sweeps */
+    int fp64_checks;           /* FP32 form with fp32_refine: number of FP64 verification sweeps */
+    int sweeps;                /* transport sweeps of all directions performed by the call */
 } sn_iter_stats;
 
 /* Source iteration with optional heterogeneous DSA (eq. DSA_fp):
@@ -183,6 +190,68 @@ typedef struct {
  * last iterate in all three error cases). */
 int sn_source_iterate(sn_context *ctx, const double *q, const double *inflow, double *phi_inout,
                       const sn_iter_opts *opts, sn_iter_stats *stats);
+
+/* Krylov solve of the scalar-flux Schur system (Section 2.2, eq. schur):
+ *   S phi = b,  S = I - sum_d w_d L_d^{-1} Sigma_s,  b = sum_d w_d L_d^{-1}(q_d + inflow load),
+ * by flexible GMRES(restart) (classical Gram-Schmidt applied twice, Givens
+ * rotations on the host), right-preconditioned by the heterogeneous DSA
+ * (use_dsa; dsa_form as in sn_iter_opts) applied to a Krylov vector v as to a
+ * residual, z = v + P_T D_ff^{-1} Sigma_f R_T v (eq. approxD; the DSA's CG
+ * tolerance may vary the preconditioner, hence the flexible form).  An
+ * iteration is one application of S (one FP64 sweep of every direction).
+ * Stops when the least-squares residual ||b - S phi|| / ||b|| <= tol, the
+ * same quantity as the source-iteration residual.
+ * phi_inout: device [ncells][nn], initial guess in, solution out.  stats:
+ * res_hist[k] the residual after iteration k, cg_hist[k] the CG iterations of
+ * its preconditioner.  Workspace: (2 restart + 4) FP64 vectors of ncells*nn.
+ * Waits on the host a few times per iteration (dot products).
+ * Returns OK, NOT_CONVERGED, DIVERGED or CG_BREAKDOWN. */
+#define SN_KRYLOV_MAX_RESTART 200
+typedef struct {
+    double tol;
+    int max_it;                /* iterations (applications of S) in total */
+    int restart;               /* Krylov space size m, 1..SN_KRYLOV_MAX_RESTART (the paper uses 30) */
+    int use_dsa;
+    int dsa_form;
+    sn_dsa_opts dsa;
+    int transpose;             /* 1: the adjoint system with L_d^{-T} sweeps */
+} sn_krylov_opts;
+int sn_krylov_solve(sn_context *ctx, const double *q, const double *inflow, double *phi_inout,
+                    const sn_krylov_opts *opts, sn_iter_stats *stats);
+
+/* Adjoint sources of the two responses (derived from the block system,
+ * eq. system): for J = sum_c r_c int_c phi the adjoint volume source is
+ * q_adj = 4 pi r (device [ncells], given with r); for the partial outflow
+ * current through domain face `face` (2 axis + side, -1 none) the transposed
+ * sweep's boundary data is 1 on that face for every direction leaving
+ * through it and 0 elsewhere (inflow_adj: device [ndirs][nbf], in the layout
+ * of the reversed directions' inflow).  r/q_adj and face/inflow_adj are
+ * given together or not at all. */
+int sn_adjoint_source(sn_context *ctx, const double *r, int face, double *q_adj, double *inflow_adj);
+
+/* Partial outflow current of the solution phi through domain face `face`,
+ *   J = sum_{d: Omega_d.n > 0} w_d (Omega_d.n) int_face psi_d,
+ * psi_d = L_d^{-1}(M (sigma_s phi + q)/4pi + inflow load) regenerated one
+ * octant (3D) or quadrant (2D) at a time, so no angular flux of all
+ * directions is held (workspace ncells * part * nn FP64, part = the largest
+ * octant's direction count rounded up to 4).  *out (host) after a stream
+ * synchronisation; the octants are summed in a fixed order. */
+int sn_face_response(sn_context *ctx, const double *phi, const double *q, const double *inflow, int face,
+                     double *out);
+
+/* Adjoint gradient of a linear response (derived from the block system):
+ *   g_t[c] = -sigma_t,c sum_d w_d psi_adj_d,c^T M_c psi_d,c     (d J / d log sigma_t,c)
+ *   g_s[c] =  sigma_s,c chi_c^T M_c phi_c / 4pi                  (d J / d log sigma_s,c)
+ * with psi_d = L_d^{-1}(M (sigma_s phi + q)/4pi + inflow load) regenerated
+ * from the converged flux phi (the checkpoint of the forward solve) and
+ * psi_adj_d = L_d^{-T}(M (sigma_s chi + q_adj)/4pi + inflow_adj load) from
+ * the converged adjoint flux chi, both one octant (quadrant) at a time: the
+ * peak workspace is two FP64 angular fluxes of one octant, never of all
+ * directions.  q, inflow, q_adj, inflow_adj may be NULL (zero / vacuum).
+ * g_t, g_s: device [ncells] FP64 outputs. */
+int sn_adjoint_gradient(sn_context *ctx, const double *phi, const double *q, const double *inflow,
+                        const double *chi, const double *q_adj, const double *inflow_adj, double *g_t,
+                        double *g_s);
 
 /* Adjoint gradient contraction (derived from the block system, eq. system):
  *   g_t[c] = -sigma_t,c sum_d w_d psi_adj_d,c^T M_c psi_d,c       (d J / d log sigma_t,c)

@@ -17,27 +17,29 @@ Two responses are supported:
     J = sum_{d: Omega_d.n > 0} w_d (Omega_d.n) int_face psi_d (adjoint
     boundary data 1 on that face for the outgoing directions).
 
-The forward solve stores the scalar flux after every source iteration
-(checkpoints); the backward pass regenerates psi from the converged phi with
-one sweep instead of storing psi across iterations.  Every step runs in the
-library's kernels; this module only builds the adjoint inputs and calls the
-C ABI.
+No angular flux of all directions is ever held.  The forward solve keeps
+scalar-flux checkpoints (by default only the last, the converged phi*); the
+face response and the backward contraction regenerate psi_d from phi* and
+psi~_d from chi one octant at a time inside the library
+(sn_face_response, sn_adjoint_gradient), and the adjoint sources come from
+sn_adjoint_source.  This module only allocates the tensors and calls the C
+ABI.
 """
 from __future__ import annotations
-
-import math
 
 import numpy as np
 import torch
 
-from .binding import (SN_FP64, Context, sn_gradient, sn_response, sn_source_iterate, sn_sweep)
+from .binding import (SN_FP64, Context, sn_adjoint_gradient, sn_adjoint_source, sn_face_response, sn_response,
+                      sn_source_iterate)
 
 
 def outgoing_face_inflow(dim, nx, ny, nz, omega, face):
-    """Boundary data for the transposed sweep: 1 on every node of `face`
-    (2*axis + side) for the directions leaving the domain through it, laid
-    out as the inflow of the reversed direction (the face is upwind for
-    -Omega_d exactly when Omega_d leaves through it)."""
+    """Host copy of the transposed sweep's boundary data for the outflow
+    current through `face` (2*axis + side): 1 on every node of that face for
+    the directions leaving through it, laid out as the inflow of the reversed
+    direction.  The library builds the same array on the device
+    (sn_adjoint_source); this copy is for callers that need it on the host."""
     F = 2 if dim == 2 else 4
     sizes = [ny * nz * F, nx * nz * F] + ([nx * ny * F] if dim == 3 else [])
     offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -52,10 +54,13 @@ def outgoing_face_inflow(dim, nx, ny, nz, omega, face):
 
 
 class Solver:
-    """Problem description shared by forward and adjoint solves."""
+    """Problem description shared by forward and adjoint solves.
+
+    ckpt_cap: scalar-flux checkpoints kept per forward solve (the last
+    ckpt_cap iterates; the contraction uses the last one, phi*)."""
 
     def __init__(self, dim, nx, ny, nz, h, omega, w, q, eta=1.0, tol=1e-12, max_it=5000, cg_rtol=1e-12,
-                 cg_maxit=10000, checkpoint=True, ckpt_bytes=8 << 30):
+                 cg_maxit=10000, checkpoint=True, ckpt_cap=1):
         self.dim, self.nx, self.ny, self.nz = dim, nx, ny, nz
         self.h = tuple(h)
         self.omega = np.ascontiguousarray(omega, dtype=np.float64)
@@ -64,9 +69,10 @@ class Solver:
         self.eta = eta
         self.tol, self.max_it, self.cg_rtol, self.cg_maxit = tol, max_it, cg_rtol, cg_maxit
         self.checkpoint = checkpoint
-        self.ckpt_bytes = int(ckpt_bytes)    # device memory for flux checkpoints (last iterates kept)
+        self.ckpt_cap = max(1, int(ckpt_cap))
         self.nn = 4 if dim == 2 else 8
         self.ncells = nx * ny * nz
+        self.memory = {}
 
     def context(self, sigma_t, sigma_s):
         return Context(self.dim, self.nx, self.ny, self.nz, self.h, self.omega, self.w,
@@ -77,8 +83,8 @@ class Solver:
         phi = torch.zeros((self.ncells, self.nn), dtype=torch.float64, device=dev)
         ck = None
         if checkpoint:
-            cap = max(1, min(self.max_it, self.ckpt_bytes // (self.ncells * self.nn * 8)))
-            ck = torch.empty((cap, self.ncells, self.nn), dtype=torch.float64, device=dev)
+            ck = torch.empty((min(self.ckpt_cap, self.max_it), self.ncells, self.nn), dtype=torch.float64,
+                             device=dev)
         r = sn_source_iterate(ctx, q, inflow, phi, tol=self.tol, max_it=self.max_it, use_dsa=True, prec=SN_FP64,
                               cg_rtol=self.cg_rtol, cg_maxit=self.cg_maxit, transpose=transpose, phi_ckpt=ck)
         if r["rc"] != 0:
@@ -88,6 +94,14 @@ class Solver:
             n, cap = r["iters"], ck.shape[0]
             ck = ck[:n] if n <= cap else torch.roll(ck, -(n % cap), dims=0)
         return phi, r, ck
+
+    def memory_report(self, ck):
+        """Bytes held for the gradient, next to what all of psi would take."""
+        flux = self.ncells * self.nn * 8
+        per_octant = -(-len(self.w) // (4 if self.dim == 2 else 8))
+        return {"checkpoint_bytes": 0 if ck is None else int(ck.numel()) * 8, "phi_bytes": flux,
+                "psi_all_directions_bytes": flux * len(self.w),
+                "psi_octant_workspace_bytes": 2 * flux * per_octant}
 
 
 class SnDetector(torch.autograd.Function):
@@ -100,16 +114,17 @@ class SnDetector(torch.autograd.Function):
         ss = torch.exp(log_sigma_s.detach()).to(torch.float64).contiguous()
         ctx = solver.context(st, ss)
         phi, res, ck = solver.solve(ctx, q=solver.q, checkpoint=solver.checkpoint)
-        psi = None
+        # the converged flux is the last checkpoint; the contraction starts from it
+        phi_star = ck[-1] if ck is not None else phi
+        J = 0.0
+        if r is not None:
+            J += sn_response(ctx, r, phi_star)
         if face >= 0:
-            psi = torch.empty((solver.ncells, len(solver.w), solver.nn), dtype=torch.float64, device=phi.device)
-            sn_sweep(ctx, phi, solver.q, None, False, SN_FP64, psi)
-        J = sn_response(ctx, r, phi if r is not None else None, face, psi, SN_FP64)
-        del psi
-        fctx.solver, fctx.face, fctx.ctx = solver, face, ctx
+            J += sn_face_response(ctx, phi_star, solver.q, None, face)
+        solver.memory = solver.memory_report(ck)
+        fctx.solver, fctx.face, fctx.ctx = solver, face, ctx   # the context is freed with fctx
         fctx.forward_iters = res["iters"]
-        fctx.checkpoints = ck
-        fctx.save_for_backward(phi, r if r is not None else torch.empty(0, device=phi.device))
+        fctx.save_for_backward(phi_star, r if r is not None else torch.empty(0, device=phi.device))
         return torch.tensor(J, dtype=torch.float64, device=phi.device)
 
     @staticmethod
@@ -117,22 +132,13 @@ class SnDetector(torch.autograd.Function):
         phi, r = fctx.saved_tensors
         solver, face, ctx = fctx.solver, fctx.face, fctx.ctx
         dev = phi.device
-        q_adj = (4.0 * math.pi) * r if r.numel() else None
-        inflow_adj = None
-        if face >= 0:
-            inflow_adj = torch.tensor(outgoing_face_inflow(solver.dim, solver.nx, solver.ny, solver.nz, solver.omega,
-                                                           face), dtype=torch.float64, device=dev)
+        q_adj = torch.empty(solver.ncells, dtype=torch.float64, device=dev) if r.numel() else None
+        inflow_adj = torch.empty((len(solver.w), ctx.nbf), dtype=torch.float64, device=dev) if face >= 0 else None
+        sn_adjoint_source(ctx, r if r.numel() else None, face, q_adj, inflow_adj)
         chi, _, _ = solver.solve(ctx, q=q_adj, inflow=inflow_adj, transpose=True)
-        D = len(solver.w)
-        psi = torch.empty((solver.ncells, D, solver.nn), dtype=torch.float64, device=dev)
-        sn_sweep(ctx, phi, solver.q, None, False, SN_FP64, psi)          # regenerated from phi*
-        psia = torch.empty_like(psi)
-        sn_sweep(ctx, chi, q_adj, inflow_adj, True, SN_FP64, psia)
         gt = torch.empty(solver.ncells, dtype=torch.float64, device=dev)
         gs = torch.empty_like(gt)
-        sn_gradient(ctx, psi, psia, SN_FP64, phi, chi, gt, gs)
-        del psi, psia
-        ctx.close()
+        sn_adjoint_gradient(ctx, phi, solver.q, None, chi, q_adj, inflow_adj, gt, gs)
         return grad_J * gt, grad_J * gs, None, None, None
 
 

@@ -21,12 +21,14 @@ SN_OK, SN_ERR_INVALID, SN_ERR_UNSUPPORTED, SN_ERR_NOMEM, SN_ERR_HIP = 0, 1, 2, 3
 SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED, SN_ERR_CG_BREAKDOWN = 5, 6, 7
 SN_FP64, SN_FP32 = 0, 1
 SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG = 0, 1
+SN_DSA_DIAGONAL, SN_DSA_TRIANGULAR = 0, 1
+SN_KRYLOV_MAX_RESTART = 200
 
 # every symbol declared in include/sn.h
 EXPORTED = ("sn_context_create", "sn_context_destroy", "sn_inflow_size", "sn_thick_count", "sn_sweep",
-            "sn_scalar_flux", "sn_dsa_thick_correct", "sn_source_iterate", "sn_gradient", "sn_response",
-            "sn_set_kernel_timing",
-            "sn_kernel_timing", "sn_last_error")
+            "sn_scalar_flux", "sn_dsa_thick_correct", "sn_source_iterate", "sn_krylov_solve", "sn_adjoint_source",
+            "sn_face_response", "sn_adjoint_gradient", "sn_gradient", "sn_response",
+            "sn_set_kernel_timing", "sn_kernel_timing", "sn_last_error")
 
 
 class SnError(RuntimeError):
@@ -57,13 +59,20 @@ class sn_dsa_stats(ctypes.Structure):
 class sn_iter_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("use_dsa", ctypes.c_int),
                 ("prec", ctypes.c_int), ("dsa", sn_dsa_opts), ("transpose", ctypes.c_int),
-                ("phi_ckpt", ctypes.c_void_p), ("ckpt_cap", ctypes.c_int)]
+                ("phi_ckpt", ctypes.c_void_p), ("ckpt_cap", ctypes.c_int), ("fp32_refine", ctypes.c_int),
+                ("dsa_form", ctypes.c_int)]
 
 
 class sn_iter_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("res_hist", ctypes.POINTER(ctypes.c_double)),
                 ("cg_hist", ctypes.POINTER(ctypes.c_int)), ("seconds", ctypes.c_double),
-                ("fp64_checks", ctypes.c_int)]
+                ("fp64_checks", ctypes.c_int), ("sweeps", ctypes.c_int)]
+
+
+class sn_krylov_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_it", ctypes.c_int), ("restart", ctypes.c_int),
+                ("use_dsa", ctypes.c_int), ("dsa_form", ctypes.c_int), ("dsa", sn_dsa_opts),
+                ("transpose", ctypes.c_int)]
 
 
 _lib = None
@@ -95,6 +104,14 @@ def lib():
         L.sn_dsa_thick_correct.restype = ip
         L.sn_source_iterate.argtypes = [vp, vp, vp, vp, ctypes.POINTER(sn_iter_opts), ctypes.POINTER(sn_iter_stats)]
         L.sn_source_iterate.restype = ip
+        L.sn_krylov_solve.argtypes = [vp, vp, vp, vp, ctypes.POINTER(sn_krylov_opts), ctypes.POINTER(sn_iter_stats)]
+        L.sn_krylov_solve.restype = ip
+        L.sn_adjoint_source.argtypes = [vp, vp, ip, vp, vp]
+        L.sn_adjoint_source.restype = ip
+        L.sn_face_response.argtypes = [vp, vp, vp, vp, ip, ctypes.POINTER(ctypes.c_double)]
+        L.sn_face_response.restype = ip
+        L.sn_adjoint_gradient.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.sn_adjoint_gradient.restype = ip
         L.sn_gradient.argtypes = [vp, vp, vp, ip, vp, vp, vp, vp]
         L.sn_gradient.restype = ip
         L.sn_response.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(ctypes.c_double)]
@@ -205,24 +222,60 @@ def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, c
     return {"rc": rc, "cg_iters": st.cg_iters, "cg_relres": st.cg_relres, "n_thick_cells": st.n_thick_cells}
 
 
+def _stats(max_it):
+    res = np.zeros(max_it, dtype=np.float64)
+    cgh = np.zeros(max_it, dtype=np.int32)
+    st = sn_iter_stats(0, res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                       cgh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 0.0, 0, 0)
+    return st, res, cgh
+
+
 def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_dsa=True, prec=SN_FP64,
-                      cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None, precond=0):
-    """Returns dict(rc, iters, res_hist, cg_hist, seconds); raises on errors
-    other than NOT_CONVERGED / DIVERGED (which are reported in rc).
+                      cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None, precond=0,
+                      fp32_refine=False, dsa_form=SN_DSA_DIAGONAL):
+    """Returns dict(rc, iters, res_hist, cg_hist, seconds, fp64_checks, sweeps);
+    raises on errors other than NOT_CONVERGED / DIVERGED (reported in rc).
     phi_ckpt: optional device tensor [cap, ncells, nn]; iterate it is kept in
     slot it % cap."""
     o = sn_iter_opts(float(tol), int(max_it), int(bool(use_dsa)), int(prec),
                      sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond)), int(bool(transpose)),
-                     _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0)
-    res = np.zeros(max_it, dtype=np.float64)
-    cgh = np.zeros(max_it, dtype=np.int32)
-    st = sn_iter_stats(0, res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                       cgh.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), 0.0, 0)
+                     _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0, int(bool(fp32_refine)),
+                     int(dsa_form))
+    st, res, cgh = _stats(max_it)
     rc = _check(lib().sn_source_iterate(ctx.handle, _ptr(q), _ptr(inflow), _ptr(phi), ctypes.byref(o),
                                         ctypes.byref(st)), allow=(SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED))
     n = st.iters
     return {"rc": rc, "iters": n, "res_hist": res[:n].copy(), "cg_hist": cgh[:n].copy(), "seconds": st.seconds,
-            "fp64_checks": st.fp64_checks}
+            "fp64_checks": st.fp64_checks, "sweeps": st.sweeps}
+
+
+def sn_krylov_solve(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, restart=30, use_dsa=True,
+                    dsa_form=SN_DSA_DIAGONAL, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, precond=0, transpose=False):
+    """Flexible GMRES(restart) on the scalar-flux Schur system; returns dict
+    as sn_source_iterate (raises on errors other than NOT_CONVERGED / DIVERGED)."""
+    o = sn_krylov_opts(float(tol), int(max_it), int(restart), int(bool(use_dsa)), int(dsa_form),
+                       sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond)), int(bool(transpose)))
+    st, res, cgh = _stats(max_it)
+    rc = _check(lib().sn_krylov_solve(ctx.handle, _ptr(q), _ptr(inflow), _ptr(phi), ctypes.byref(o),
+                                      ctypes.byref(st)), allow=(SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED))
+    n = st.iters
+    return {"rc": rc, "iters": n, "res_hist": res[:n].copy(), "cg_hist": cgh[:n].copy(), "seconds": st.seconds,
+            "sweeps": st.sweeps}
+
+
+def sn_adjoint_source(ctx: Context, r=None, face: int = -1, q_adj=None, inflow_adj=None):
+    _check(lib().sn_adjoint_source(ctx.handle, _ptr(r), int(face), _ptr(q_adj), _ptr(inflow_adj)))
+
+
+def sn_face_response(ctx: Context, phi, q, inflow, face: int) -> float:
+    out = ctypes.c_double()
+    _check(lib().sn_face_response(ctx.handle, _ptr(phi), _ptr(q), _ptr(inflow), int(face), ctypes.byref(out)))
+    return out.value
+
+
+def sn_adjoint_gradient(ctx: Context, phi, q, inflow, chi, q_adj, inflow_adj, g_t, g_s):
+    _check(lib().sn_adjoint_gradient(ctx.handle, _ptr(phi), _ptr(q), _ptr(inflow), _ptr(chi), _ptr(q_adj),
+                                     _ptr(inflow_adj), _ptr(g_t), _ptr(g_s)))
 
 
 def sn_gradient(ctx: Context, psi, psi_adj, prec: int, phi, chi, g_t, g_s):

@@ -135,6 +135,23 @@ struct sn_context {
     };
     FaceKey fkey[2];  // [FP64, FP32]
     bool face_reuse = false;
+    // direction parts for sweeps that keep only some directions' psi (the
+    // adjoint contraction and the face response): 3D one reflection class
+    // (octant) each, 2D one quadrant each; part_dirs[p][l] = global direction
+    // of local index l (-1: unused slot), part_w = [part][part_stride] weights
+    std::vector<SweepPart> parts;
+    std::vector<std::vector<int>> part_dirs;
+    int part_stride = 0;
+    DevBuf<int> order2d_parts, face_out;
+    DevBuf<double> part_w, part_wn, psi_a, psi_b;
+    // triangular DSA (Alg. 1): the iterate before the thick update, the thick
+    // part of the preconditioned residual and its transport update
+    DevBuf<double> phiold, phibar, zeta;
+    // Krylov solve: basis V [m + 1][n], preconditioned basis Z [m][n], work
+    // vectors, the zero vector, dot products and their pinned host copy
+    DevBuf<double> kv, kz, kw, kb, kzero, kdot, kpart;
+    double* kdot_host = nullptr;
+    int sweeps = 0;  // transport sweeps (all directions) since the last reset
     // optional event timing of the sweep kernels and of the DSA solves
     int timing = 0;
     std::vector<hipEvent_t> evpool;
@@ -199,7 +216,7 @@ int ensure_skew(sn_context* ctx, DevBuf<T>& srcskew) {
 template <typename T>
 int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
                int transpose, T* psi, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, DevBuf<T>& sink,
-               const T* sigt, DevBuf<T>& srcskew, const T* sigskew) {
+               const T* sigt, DevBuf<T>& srcskew, const T* sigskew, const SweepPart* part = nullptr) {
     const SweepGeom& g = ctx->sg;
     int rc;
     if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
@@ -226,7 +243,8 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, xf.p, yf.p, zf.p, ctx->tiles.p,
-                           ctx->plane_off.data(), psi, sink.p, ctx->stream));
+                           ctx->plane_off.data(), psi, sink.p, ctx->stream, part));
+    if (!part) ++ctx->sweeps;
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->sweep_ev.emplace_back(e0, e1);
@@ -236,12 +254,13 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
 
 // psi = L^{-1} or L^{-T} of the load of (sigma_s (phi - phi_prev) + q)/4pi plus the inflow
 int do_sweep(sn_context* ctx, const double* phi, const double* phi_prev, const double* q, const double* inflow,
-             int transpose, sn_precision prec, void* psi) {
+             int transpose, sn_precision prec, void* psi, const SweepPart* part = nullptr) {
     if (prec == SN_FP64)
         return sweep_impl<double>(ctx, phi, phi_prev, q, inflow, transpose, (double*)psi, ctx->xf64, ctx->yf64,
-                                  ctx->zf64, ctx->src64, ctx->sink64, ctx->sigt.p, ctx->srcskew64, ctx->sigskew64.p);
+                                  ctx->zf64, ctx->src64, ctx->sink64, ctx->sigt.p, ctx->srcskew64, ctx->sigskew64.p,
+                                  part);
     return sweep_impl<float>(ctx, phi, phi_prev, q, inflow, transpose, (float*)psi, ctx->xf32, ctx->yf32, ctx->zf32,
-                             ctx->src32, ctx->sink32, ctx->sigt32.p, ctx->srcskew32, ctx->sigskew32.p);
+                             ctx->src32, ctx->sink32, ctx->sigt32.p, ctx->srcskew32, ctx->sigskew32.p, part);
 }
 
 // res_ref != nullptr: also the residual partial sums against res_ref into
@@ -276,6 +295,7 @@ int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev
     HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
                                   ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, res_ref, ctx->fpart.p,
                                   ctx->stream));
+    ++ctx->sweeps;
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
         ctx->sweep_ev.emplace_back(e0, e1);
@@ -638,6 +658,44 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     return 0;
 }
 
+// Alg. 1, second step, on a vector phi whose thick update started from
+// phi_old (NULL: zero): phi_thin += (sum_d w_d L_d^{-1} Sigma_s bar)_thin,
+// bar = (phi - phi_old) on the thick cells, zero source and vacuum inflow
+int triangular_step(sn_context* ctx, const double* phi_old, double* phi, int transpose, sn_precision prec) {
+    const long n = ctx->nc * ctx->nn;
+    int rc;
+    if ((rc = ctx->phibar.ensure(n)) || (rc = ctx->zeta.ensure(n))) return rc;
+    HIPCHK(launch_thick_diff(ctx->nc, ctx->nn, ctx->slot.p, phi, phi_old, ctx->phibar.p, ctx->stream));
+    if ((rc = do_sweep_flux(ctx, ctx->phibar.p, nullptr, nullptr, nullptr, transpose, prec, ctx->zeta.p, 0)))
+        return rc;
+    HIPCHK(launch_thin_add(ctx->nc, ctx->nn, ctx->slot.p, ctx->zeta.p, phi, ctx->stream));
+    return 0;
+}
+
+// k dot products V_i . w (i < k) into ctx->kdot (device) and out (host)
+int dots(sn_context* ctx, int k, const double* V, const double* w, double* out) {
+    const long n = ctx->nc * ctx->nn;
+    HIPCHK(launch_multi_dot(n, k, V, w, ctx->kpart.p, ctx->kdot.p, ctx->kdot_host, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < k; ++i) out[i] = ctx->kdot_host[i];
+    return 0;
+}
+
+// Inflow-layout range [f0, f1) of the domain face `face` (2 axis + side)
+void face_range(const sn_mesh& m, int face, long* f0, long* f1) {
+    const int F = m.dim == 2 ? 2 : 4;
+    const long sx = (long)m.ny * m.nz * F, sy = (long)m.nx * m.nz * F, sz = m.dim == 3 ? (long)m.nx * m.ny * F : 0;
+    const int ax = face >> 1;
+    const long off[4] = {0, sx, sx + sy, sx + sy + sz};
+    *f0 = off[ax];
+    *f1 = off[ax + 1];
+}
+
+// Omega_d . n of the outward normal of `face`
+double face_dot(const sn_context* ctx, int face, int d) {
+    return ((face & 1) ? 1.0 : -1.0) * ctx->omega[3 * d + (face >> 1)];
+}
+
 int residual3(sn_context* ctx, const double* a, const double* b, double out[3]) {
     const long n = ctx->nc * ctx->nn;
     HIPCHK(launch_residual(n, a, b, ctx->rpart.p, ctx->nrpart, ctx->res3.p, ctx->stream));
@@ -728,6 +786,23 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->mg_par.release();
     ctx->mg_vnodes.release();
     ctx->mg_nodev.release();
+    ctx->order2d_parts.release();
+    ctx->face_out.release();
+    ctx->part_w.release();
+    ctx->part_wn.release();
+    ctx->psi_a.release();
+    ctx->psi_b.release();
+    ctx->phiold.release();
+    ctx->phibar.release();
+    ctx->zeta.release();
+    ctx->kv.release();
+    ctx->kz.release();
+    ctx->kw.release();
+    ctx->kb.release();
+    ctx->kzero.release();
+    ctx->kdot.release();
+    ctx->kpart.release();
+    if (ctx->kdot_host) (void)hipHostFree(ctx->kdot_host);
     delete ctx;
 }
 
@@ -953,6 +1028,61 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.groups = c->groups.p;
     }
 
+    // direction parts: 3D the reflection classes (local index 4 group + slot),
+    // 2D the quadrants (local index = position in the quadrant's list)
+    {
+        if (dim == 3) {
+            const int gpc = g.groups_per_class;
+            std::vector<int> gr((size_t)g.nclasses * gpc * 6);
+            HIPCHK(hipMemcpy(gr.data(), g.groups, gr.size() * sizeof(int), hipMemcpyDeviceToHost));
+            // the stride is the largest valid local index + 1 (S12: 21 of the
+            // 24 slots of six groups; the empty slots of the last group are
+            // never written, so they need no room)
+            for (int ci = 0; ci < g.nclasses; ++ci) {
+                std::vector<int> ids(4 * gpc, -1);
+                for (int gi = 0; gi < gpc; ++gi)
+                    for (int k = 0; k < 4; ++k) {
+                        ids[4 * gi + k] = gr[((size_t)ci * gpc + gi) * 6 + k];
+                        if (ids[4 * gi + k] >= 0) c->part_stride = std::max(c->part_stride, 4 * gi + k + 1);
+                    }
+                c->parts.push_back(SweepPart{ci, 1, 0, 1, nullptr});
+                c->part_dirs.push_back(ids);
+            }
+            for (auto& pp : c->parts) pp.pstride = c->part_stride;
+            for (auto& ids : c->part_dirs) ids.resize(c->part_stride);
+        } else {
+            std::vector<std::vector<int>> qd(4);
+            for (int d = 0; d < c->ndirs; ++d) qd[c->hdirs[d].rx | (c->hdirs[d].ry << 1)].push_back(d);
+            std::vector<int> flat;
+            for (auto& v : qd) {
+                c->part_stride = std::max(c->part_stride, (int)v.size());
+                flat.insert(flat.end(), v.begin(), v.end());
+            }
+            if ((rc = c->order2d_parts.ensure(std::max<size_t>(flat.size(), 1)))) return rc;
+            HIPCHK(hipMemcpy(c->order2d_parts.p, flat.data(), flat.size() * sizeof(int), hipMemcpyHostToDevice));
+            size_t off = 0;
+            for (auto& v : qd) {
+                if (v.empty()) continue;
+                c->parts.push_back(SweepPart{0, (int)v.size(), 0, 1, c->order2d_parts.p + off});
+                std::vector<int> ids(v);
+                c->part_dirs.push_back(ids);
+                off += v.size();
+            }
+            for (auto& pp : c->parts) pp.pstride = c->part_stride;
+            for (auto& ids : c->part_dirs) ids.resize(c->part_stride, -1);
+        }
+        std::vector<double> pw((size_t)c->parts.size() * c->part_stride, 0.0);
+        for (size_t pi = 0; pi < c->parts.size(); ++pi)
+            for (int l = 0; l < c->part_stride; ++l) {
+                const int d = c->part_dirs[pi][l];
+                if (d >= 0) pw[pi * c->part_stride + l] = quad->w[d];
+            }
+        if ((rc = c->part_w.ensure(pw.size())) || (rc = c->part_wn.ensure(pw.size())) ||
+            (rc = c->face_out.ensure(c->ndirs)))
+            return rc;
+        HIPCHK(hipMemcpy(c->part_w.p, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+
     // thick set
     const int nblk = (int)((nc + 255) / 256);
     if ((rc = c->flags.ensure(nc)) || (rc = c->blocksums.ensure(nblk)) || (rc = c->total.ensure(1)) ||
@@ -1067,6 +1197,9 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     if (o->phi_ckpt && o->ckpt_cap < 1) return fail(SN_ERR_INVALID, "ckpt_cap must be >= 1 with phi_ckpt");
     if (o->prec != SN_FP64 && o->prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
     if (o->use_dsa && bad_dsa_opts(o->dsa)) return fail(SN_ERR_INVALID, "bad DSA options");
+    if (o->fp32_refine != 0 && o->fp32_refine != 1) return fail(SN_ERR_INVALID, "fp32_refine must be 0 or 1");
+    if (o->dsa_form != SN_DSA_DIAGONAL && o->dsa_form != SN_DSA_TRIANGULAR)
+        return fail(SN_ERR_INVALID, "unknown DSA form %d", o->dsa_form);
     // the inflow array is fixed for the whole call: face buffers are filled
     // once per precision (and transpose flag) and reused by later sweeps
     struct FaceReuse {
@@ -1085,11 +1218,20 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     int rc;
     if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->phitmp.ensure(n)) || (rc = ctx->phiprev.ensure(n))) return rc;
     const int tr = o->transpose ? 1 : 0;
+    // FP32 form.  Plain (fp32_refine = 0): every sweep is FP32 on the full
+    // source; moment, residual and DSA stay FP64.  Refined (fp32_refine = 1):
     // FP32 sweeps act on the iterate increment (defect correction): after the
     // first iteration the sweep source is sigma_s (phi_i - phi_{i-1}) / 4pi
     // and its moment is added to the FP64 accumulator phi_SI, so the FP32
     // rounding error scales with the increment instead of with phi.
-    const bool incr = o->prec == SN_FP32;
+    const bool incr = o->prec == SN_FP32 && o->fp32_refine;
+    // triangular heterogeneous DSA (Alg. 1): after the thick update, the thick
+    // part of the preconditioned residual is swept once more (zero source,
+    // vacuum) and the result is added to the thin DOFs
+    const bool tri = o->use_dsa && o->dsa_form == SN_DSA_TRIANGULAR && ctx->nthick > 0;
+    if (tri && ((rc = ctx->phiold.ensure(n)) || (rc = ctx->phibar.ensure(n)) || (rc = ctx->zeta.ensure(n))))
+        return rc;
+    ctx->sweeps = 0;
     if (stats) stats->fp64_checks = 0;
     double bnorm = 1.0, first = -1.0;
     int it = 0;
@@ -1157,12 +1299,21 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
         // (the CG warm-starts from the previous iteration's correction)
         auto update = [&](const double* phi_old, bool with_res) -> int {
             if (o->use_dsa) {
+                const double* pold = phi_old;
+                if (tri && phi_old == phi) {  // the thick update overwrites phi in place
+                    HIPCHK(hipMemcpyAsync(ctx->phiold.p, phi, n * sizeof(double), hipMemcpyDeviceToDevice,
+                                          ctx->stream));
+                    pold = ctx->phiold.p;
+                }
                 sn_dsa_stats ds{};
-                const int e = do_dsa(ctx, phi_old, ctx->phisi.p, phi, &o->dsa, &ds,
-                                     with_res ? ctx->fpart.p : nullptr, res_n, dsa_done > 0, !incr, q);
+                // (2D FP64 diagonal form: the final update also writes the next sweep's source)
+                const int e = do_dsa(ctx, pold, ctx->phisi.p, phi, &o->dsa, &ds,
+                                     with_res ? ctx->fpart.p : nullptr, res_n, dsa_done > 0,
+                                     o->prec == SN_FP64 && !tri, q);
                 ++dsa_done;
                 cgi = ds.cg_iters;
-                return e;
+                if (e) return e;
+                return tri ? triangular_step(ctx, pold, phi, tr, o->prec) : 0;
             }
             if (with_res) {
                 HIPCHK(launch_residual_final(res_n, ctx->fpart.p, ctx->res3.p, ctx->hpin->r3, ctx->stream));
@@ -1214,6 +1365,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     (void)verified;
     if (stats) {
         stats->iters = it;
+        stats->sweeps = ctx->sweeps;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
@@ -1269,6 +1421,243 @@ int sn_gradient(sn_context* ctx, const void* psi, const void* psi_adj, sn_precis
                                       (const float*)psi, (const float*)psi_adj, phi, chi, g_t, g_s, ctx->stream));
     else
         return fail(SN_ERR_INVALID, "unknown precision");
+    return 0;
+}
+
+int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, double* phi, const sn_krylov_opts* o,
+                    sn_iter_stats* stats) {
+    g_err.clear();
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !phi || !o) return fail(SN_ERR_INVALID, "NULL argument");
+    if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
+    if (o->restart < 1 || o->restart > SN_KRYLOV_MAX_RESTART)
+        return fail(SN_ERR_INVALID, "restart must be in 1..%d", SN_KRYLOV_MAX_RESTART);
+    if (o->use_dsa && bad_dsa_opts(o->dsa)) return fail(SN_ERR_INVALID, "bad DSA options");
+    if (o->dsa_form != SN_DSA_DIAGONAL && o->dsa_form != SN_DSA_TRIANGULAR)
+        return fail(SN_ERR_INVALID, "unknown DSA form %d", o->dsa_form);
+    struct FaceReuse {
+        sn_context* c;
+        explicit FaceReuse(sn_context* c_) : c(c_) {
+            c->fkey[0].valid = c->fkey[1].valid = false;
+            c->face_reuse = true;
+            c->src_tok = false;
+        }
+        ~FaceReuse() {
+            c->face_reuse = false;
+            c->src_tok = false;
+        }
+    } face_reuse(ctx);
+    const long n = ctx->nc * ctx->nn;
+    const int m = o->restart, tr = o->transpose ? 1 : 0;
+    const bool dsa = o->use_dsa && ctx->nthick > 0;
+    const bool tri = dsa && o->dsa_form == SN_DSA_TRIANGULAR;
+    int rc;
+    const bool fresh_zero = !ctx->kzero.p;
+    if ((rc = ctx->kv.ensure((size_t)(m + 1) * n)) || (rc = ctx->kw.ensure(n)) || (rc = ctx->kb.ensure(n)) ||
+        (rc = ctx->kzero.ensure(n)) || (rc = ctx->kdot.ensure(SN_KRYLOV_MAX_RESTART + 1)) ||
+        (rc = ctx->kpart.ensure((size_t)(SN_KRYLOV_MAX_RESTART + 1) * krylov_blocks(n))))
+        return rc;
+    if (dsa && (rc = ctx->kz.ensure((size_t)m * n))) return rc;
+    if (fresh_zero) HIPCHK(hipMemsetAsync(ctx->kzero.p, 0, n * sizeof(double), ctx->stream));
+    if (!ctx->kdot_host)
+        HIPCHK(hipHostMalloc((void**)&ctx->kdot_host, (SN_KRYLOV_MAX_RESTART + 2) * sizeof(double),
+                             hipHostMallocDefault));
+    ctx->sweeps = 0;
+    double* V = ctx->kv.p;
+    double* Z = dsa ? ctx->kz.p : ctx->kv.p;
+    double* w = ctx->kw.p;
+    // S x = x - sum_d w_d L_d^{-1} (Sigma_s x) with zero source and vacuum: into w, then w = x - w
+    auto apply_S = [&](const double* x) -> int {
+        int e;
+        if ((e = do_sweep_flux(ctx, x, nullptr, nullptr, nullptr, tr, SN_FP64, w, 0))) return e;
+        HIPCHK(launch_axpby(n, 1.0, x, -1.0, w, ctx->stream));
+        return 0;
+    };
+    // b = sum_d w_d L_d^{-1}(q_d + inflow load)
+    if ((rc = do_sweep_flux(ctx, nullptr, nullptr, q, inflow, tr, SN_FP64, ctx->kb.p, 0))) return rc;
+    double bb;
+    if ((rc = dots(ctx, 1, ctx->kb.p, ctx->kb.p, &bb))) return rc;
+    double bnorm = std::sqrt(bb);
+    if (bnorm == 0.0) bnorm = 1.0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+    int it = 0, status = SN_ERR_NOT_CONVERGED;
+    while (it < o->max_it && status == SN_ERR_NOT_CONVERGED) {
+        // r = b - S x
+        if ((rc = apply_S(phi))) return rc;
+        HIPCHK(launch_axpby(n, 1.0, ctx->kb.p, -1.0, w, ctx->stream));
+        double rr;
+        if ((rc = dots(ctx, 1, w, w, &rr))) return rc;
+        const double beta = std::sqrt(rr);
+        if (!std::isfinite(beta)) {
+            status = fail(SN_ERR_DIVERGED, "Krylov residual is not finite");
+            break;
+        }
+        if (beta / bnorm <= o->tol) {
+            status = SN_OK;
+            break;
+        }
+        HIPCHK(launch_scale(n, 1.0 / beta, w, V, ctx->stream));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool stop = false;
+        for (; j < m && it < o->max_it; ++j) {
+            double* vj = V + (size_t)j * n;
+            double* zj = Z + (size_t)j * n;
+            int cgi = 0;
+            if (dsa) {
+                // the preconditioner applied to v_j as to a residual: z = v + P_T D_ff^{-1} Sigma_f R_T v
+                sn_dsa_stats ds{};
+                if ((rc = do_dsa(ctx, ctx->kzero.p, vj, zj, &o->dsa, &ds))) {
+                    status = rc;
+                    break;
+                }
+                cgi = ds.cg_iters;
+                if (tri && (rc = triangular_step(ctx, nullptr, zj, tr, SN_FP64))) return rc;
+            }
+            if ((rc = apply_S(zj))) return rc;
+            // classical Gram-Schmidt, twice
+            if ((rc = dots(ctx, j + 1, V, w, h.data()))) return rc;
+            HIPCHK(launch_multi_axpy(n, j + 1, V, ctx->kdot.p, -1.0, w, ctx->stream));
+            if ((rc = dots(ctx, j + 1, V, w, h2.data()))) return rc;
+            HIPCHK(launch_multi_axpy(n, j + 1, V, ctx->kdot.p, -1.0, w, ctx->stream));
+            double ww;
+            if ((rc = dots(ctx, 1, w, w, &ww))) return rc;
+            const double hn = std::sqrt(ww);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) HIPCHK(launch_scale(n, 1.0 / hn, w, V + (size_t)(j + 1) * n, ctx->stream));
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+            }
+            {
+                const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+                const double den = std::sqrt(a * a + c2 * c2);
+                cs[j] = den > 0.0 ? a / den : 1.0;
+                sn[j] = den > 0.0 ? c2 / den : 0.0;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+            }
+            const double res = std::fabs(g[j + 1]) / bnorm;
+            if (stats && stats->res_hist) stats->res_hist[it] = res;
+            if (stats && stats->cg_hist) stats->cg_hist[it] = cgi;
+            ++it;
+            if (!std::isfinite(res)) {
+                status = fail(SN_ERR_DIVERGED, "Krylov residual is not finite");
+                ++j;
+                break;
+            }
+            if (res <= o->tol || hn == 0.0) {
+                stop = true;
+                ++j;
+                break;
+            }
+        }
+        if (status == SN_ERR_CG_BREAKDOWN || status == SN_ERR_HIP || status == SN_ERR_NOMEM) break;
+        // x += Z y, H(0:j, 0:j) y = g(0:j)
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * y[k];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        if (j > 0) {
+            for (int i = 0; i < j; ++i) ctx->kdot_host[i] = y[i];
+            HIPCHK(hipMemcpyAsync(ctx->kdot.p, ctx->kdot_host, j * sizeof(double), hipMemcpyHostToDevice,
+                                  ctx->stream));
+            HIPCHK(launch_multi_axpy(n, j, Z, ctx->kdot.p, 1.0, phi, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+        if (status != SN_ERR_NOT_CONVERGED) break;
+        if (stop) status = SN_OK;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (status == SN_ERR_NOT_CONVERGED) fail(status, "not converged in %d iterations", o->max_it);
+    if (stats) {
+        stats->iters = it;
+        stats->sweeps = ctx->sweeps;
+        stats->fp64_checks = 0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+int sn_adjoint_source(sn_context* ctx, const double* r, int face, double* q_adj, double* inflow_adj) {
+    g_err.clear();
+    if (!ctx) return fail(SN_ERR_INVALID, "context is NULL");
+    if (face < -1 || face >= 2 * ctx->mesh.dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * ctx->mesh.dim - 1);
+    if ((r != nullptr) != (q_adj != nullptr)) return fail(SN_ERR_INVALID, "r and q_adj must be given together");
+    if ((face >= 0) != (inflow_adj != nullptr)) return fail(SN_ERR_INVALID, "a face needs inflow_adj (and only then)");
+    if (r) HIPCHK(launch_scale(ctx->nc, 4.0 * kPi, r, q_adj, ctx->stream));
+    if (face >= 0) {
+        std::vector<int> out(ctx->ndirs);
+        for (int d = 0; d < ctx->ndirs; ++d) out[d] = face_dot(ctx, face, d) > 0.0 ? 1 : 0;
+        HIPCHK(hipMemcpy(ctx->face_out.p, out.data(), ctx->ndirs * sizeof(int), hipMemcpyHostToDevice));
+        long f0, f1;
+        face_range(ctx->mesh, face, &f0, &f1);
+        HIPCHK(launch_face_data(ctx->ndirs, ctx->nbf, f0, f1, ctx->face_out.p, inflow_adj, ctx->stream));
+    }
+    return 0;
+}
+
+int sn_face_response(sn_context* ctx, const double* phi, const double* q, const double* inflow, int face,
+                     double* out) {
+    g_err.clear();
+    if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (face < 0 || face >= 2 * ctx->mesh.dim) return fail(SN_ERR_INVALID, "face must be 0..%d", 2 * ctx->mesh.dim - 1);
+    const int S = ctx->part_stride;
+    int rc;
+    if ((rc = ctx->psi_a.ensure((size_t)ctx->nc * S * ctx->nn))) return rc;
+    const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, ctx->mesh.dim == 3 ? ctx->mesh.hz : 1.0};
+    double total = 0.0;
+    for (size_t pi = 0; pi < ctx->parts.size(); ++pi) {
+        std::vector<double> wn(S, 0.0);
+        bool any = false;
+        for (int l = 0; l < S; ++l) {
+            const int d = ctx->part_dirs[pi][l];
+            if (d < 0) continue;
+            const double on = face_dot(ctx, face, d);
+            if (on > 0.0) {
+                wn[l] = ctx->hw[d] * on;
+                any = true;
+            }
+        }
+        if (!any) continue;
+        HIPCHK(hipMemcpy(ctx->part_wn.p + pi * S, wn.data(), S * sizeof(double), hipMemcpyHostToDevice));
+        if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, 0, SN_FP64, ctx->psi_a.p, &ctx->parts[pi]))) return rc;
+        HIPCHK(launch_response<double>(ctx->nc, ctx->nn, ctx->mesh.nx, ctx->mesh.ny, ctx->mesh.nz, h, nullptr, nullptr,
+                                       face, S, ctx->part_wn.p + pi * S, ctx->psi_a.p, ctx->rpart.p, ctx->nrpart,
+                                       ctx->res3.p, ctx->stream));
+        double r3[3];
+        HIPCHK(hipMemcpyAsync(r3, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        total += r3[1];
+    }
+    *out = total;
+    return 0;
+}
+
+int sn_adjoint_gradient(sn_context* ctx, const double* phi, const double* q, const double* inflow, const double* chi,
+                        const double* q_adj, const double* inflow_adj, double* g_t, double* g_s) {
+    g_err.clear();
+    if (!ctx || !phi || !chi || !g_t || !g_s) return fail(SN_ERR_INVALID, "NULL argument");
+    const int S = ctx->part_stride;
+    int rc;
+    if ((rc = ctx->psi_a.ensure((size_t)ctx->nc * S * ctx->nn)) || (rc = ctx->psi_b.ensure((size_t)ctx->nc * S * ctx->nn)))
+        return rc;
+    const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, ctx->mesh.dim == 3 ? ctx->mesh.hz : 1.0};
+    for (size_t pi = 0; pi < ctx->parts.size(); ++pi) {
+        const SweepPart* part = &ctx->parts[pi];
+        // psi_d regenerated from the converged flux; the adjoint psi_d from chi
+        if ((rc = do_sweep(ctx, phi, nullptr, q, inflow, 0, SN_FP64, ctx->psi_a.p, part))) return rc;
+        if ((rc = do_sweep(ctx, chi, nullptr, q_adj, inflow_adj, 1, SN_FP64, ctx->psi_b.p, part))) return rc;
+        HIPCHK(launch_gradient<double>(ctx->nc, ctx->nn, S, ctx->part_w.p + pi * S, h, ctx->sigt.p, ctx->sigs.p,
+                                       ctx->psi_a.p, ctx->psi_b.p, phi, chi, g_t, pi == 0 ? g_s : nullptr, ctx->stream,
+                                       pi > 0));
+    }
     return 0;
 }
 

@@ -186,16 +186,21 @@ __device__ __forceinline__ void apply_mass(const double* h, const double in[NN],
     for (int n = 0; n < NN; ++n) out[n] = t[n];
 }
 
+// psi, psia: [cell][ndirs][NN] for the ndirs directions of w (a part of the
+// quadrature: directions of zero weight are unused slots and are skipped).
+// accumulate: g_t += instead of =; g_s (with phi, chi) is written when given.
 template <typename T, int NN>
 __global__ void gradient_kernel(long nc, int ndirs, const double* __restrict__ w, double hx, double hy, double hz,
                                 const double* __restrict__ sigma_t, const double* __restrict__ sigma_s,
                                 const T* __restrict__ psi, const T* __restrict__ psia,
                                 const double* __restrict__ phi, const double* __restrict__ chi,
-                                double* __restrict__ gt, double* __restrict__ gs) {
+                                double* __restrict__ gt, double* __restrict__ gs, int accumulate) {
     const double h[3] = {hx, hy, hz};
     for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int d = 0; d < ndirs; ++d) {
+            const double wd = w[d];
+            if (wd == 0.0) continue;
             double a[NN], b[NN], mb[NN];
             const T* pa = psia + (c * ndirs + d) * NN;
             const T* pb = psi + (c * ndirs + d) * NN;
@@ -208,31 +213,179 @@ __global__ void gradient_kernel(long nc, int ndirs, const double* __restrict__ w
             double v = 0.0;
 #pragma unroll
             for (int n = 0; n < NN; ++n) v = fma(a[n], mb[n], v);
-            acc = fma(w[d], v, acc);
+            acc = fma(wd, v, acc);
         }
-        gt[c] = -sigma_t[c] * acc;
-        double x[NN], mx[NN];
+        const double g = -sigma_t[c] * acc;
+        gt[c] = accumulate ? gt[c] + g : g;
+        if (gs) {
+            double x[NN], mx[NN];
 #pragma unroll
-        for (int n = 0; n < NN; ++n) x[n] = phi[c * NN + n];
-        apply_mass<NN>(h, x, mx);
-        double v = 0.0;
+            for (int n = 0; n < NN; ++n) x[n] = phi[c * NN + n];
+            apply_mass<NN>(h, x, mx);
+            double v = 0.0;
 #pragma unroll
-        for (int n = 0; n < NN; ++n) v = fma(chi[c * NN + n], mx[n], v);
-        gs[c] = sigma_s[c] * v * kInv4Pi;
+            for (int n = 0; n < NN; ++n) v = fma(chi[c * NN + n], mx[n], v);
+            gs[c] = sigma_s[c] * v * kInv4Pi;
+        }
     }
 }
-
 template <typename T>
 hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const double* h, const double* sigma_t,
                            const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
-                           const double* chi, double* g_t, double* g_s, hipStream_t st) {
+                           const double* chi, double* g_t, double* g_s, hipStream_t st, int accumulate) {
     int blocks = (int)std::min<long>((nc + 255) / 256, 1 << 16);
     if (nn == 4)
         hipLaunchKernelGGL((gradient_kernel<T, 4>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, h[0], h[1], h[2],
-                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s);
+                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s, accumulate);
     else
         hipLaunchKernelGGL((gradient_kernel<T, 8>), dim3(blocks), dim3(256), 0, st, nc, ndirs, w, h[0], h[1], h[2],
-                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s);
+                           sigma_t, sigma_s, psi, psi_adj, phi, chi, g_t, g_s, accumulate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// triangular heterogeneous DSA (Alg. 1): the thick part of the preconditioned
+// residual, and the thin-only accumulation of its transport update
+// ---------------------------------------------------------------------------
+// bar = (a - b) on the nodes of thick cells (slot_of_cell >= 0), 0 elsewhere
+__global__ void thick_diff_kernel(long nc, int nn, const int* __restrict__ slot_of_cell,
+                                  const double* __restrict__ a, const double* __restrict__ b,
+                                  double* __restrict__ bar) {
+    const long n = nc * nn;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const long c = e / nn;
+        bar[e] = slot_of_cell[c] >= 0 ? a[e] - (b ? b[e] : 0.0) : 0.0;
+    }
+}
+// phi += z on the nodes of thin (and void) cells
+__global__ void thin_add_kernel(long nc, int nn, const int* __restrict__ slot_of_cell, const double* __restrict__ z,
+                                double* __restrict__ phi) {
+    const long n = nc * nn;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const long c = e / nn;
+        if (slot_of_cell[c] < 0) phi[e] += z[e];
+    }
+}
+hipError_t launch_thick_diff(long nc, int nn, const int* slot_of_cell, const double* a, const double* b, double* bar,
+                             hipStream_t st) {
+    const int blocks = (int)std::min<long>((nc * nn + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(thick_diff_kernel, dim3(blocks), dim3(256), 0, st, nc, nn, slot_of_cell, a, b, bar);
+    return hipGetLastError();
+}
+hipError_t launch_thin_add(long nc, int nn, const int* slot_of_cell, const double* z, double* phi, hipStream_t st) {
+    const int blocks = (int)std::min<long>((nc * nn + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(thin_add_kernel, dim3(blocks), dim3(256), 0, st, nc, nn, slot_of_cell, z, phi);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint sources of the two responses
+// ---------------------------------------------------------------------------
+// q_adj = 4 pi r (volume detector J = sum_c r_c int_c phi)
+__global__ void scale_kernel(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        y[e] = a * x[e];
+}
+// boundary data of the transposed sweep for the outflow current through a
+// domain face: 1 on that face's slot of the inflow layout for every
+// direction leaving through it (out: 1 or 0 per direction), 0 elsewhere
+__global__ void face_data_kernel(int ndirs, long nbf, long f0, long f1, const int* __restrict__ out,
+                                 double* __restrict__ data) {
+    const long n = (long)ndirs * nbf;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int d = (int)(e / nbf);
+        const long f = e - (long)d * nbf;
+        data[e] = (out[d] && f >= f0 && f < f1) ? 1.0 : 0.0;
+    }
+}
+hipError_t launch_scale(long n, double a, const double* x, double* y, hipStream_t st) {
+    const int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(scale_kernel, dim3(blocks), dim3(256), 0, st, n, a, x, y);
+    return hipGetLastError();
+}
+hipError_t launch_face_data(int ndirs, long nbf, long f0, long f1, const int* out, double* data, hipStream_t st) {
+    const long n = (long)ndirs * nbf;
+    const int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(face_data_kernel, dim3(blocks), dim3(256), 0, st, ndirs, nbf, f0, f1, out, data);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector operations (FP64), reduced in a fixed order
+// ---------------------------------------------------------------------------
+// part[i][blockIdx.x] = block's share of V_i . w for i < k (V: k vectors of
+// length n, stride n); up to KB vectors per pass over w
+constexpr int KB = 8;
+__global__ void __launch_bounds__(256) multi_dot_kernel(long n, int k, const double* __restrict__ V,
+                                                        const double* __restrict__ w, double* __restrict__ part) {
+    __shared__ double sh[48];
+    for (int i0 = 0; i0 < k; i0 += KB) {
+        double acc[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) acc[i] = 0.0;
+        const int nk = min(KB, k - i0);
+        for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+            const double we = w[e];
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                if (i < nk) acc[i] = fma(V[(long)(i0 + i) * n + e], we, acc[i]);
+        }
+        for (int i = 0; i < nk; i += 3) {
+            double a = acc[i], b = i + 1 < nk ? acc[i + 1] : 0.0, c = i + 2 < nk ? acc[i + 2] : 0.0;
+            block_sum3(a, b, c, sh);
+            if (threadIdx.x == 0) {
+                part[(long)(i0 + i) * gridDim.x + blockIdx.x] = a;
+                if (i + 1 < nk) part[(long)(i0 + i + 1) * gridDim.x + blockIdx.x] = b;
+                if (i + 2 < nk) part[(long)(i0 + i + 2) * gridDim.x + blockIdx.x] = c;
+            }
+        }
+    }
+}
+// out[i] = sum over blocks of part[i][.] (one workgroup per i, fixed order);
+// also to pinned host memory when out_host is given
+__global__ void __launch_bounds__(256) multi_dot_final_kernel(int nparts, const double* __restrict__ part,
+                                                              double* __restrict__ out, double* __restrict__ out_host) {
+    __shared__ double sh[48];
+    double a = 0.0, b = 0.0, c = 0.0;
+    const double* pi = part + (long)blockIdx.x * nparts;
+    for (int e = threadIdx.x; e < nparts; e += 256) a += pi[e];
+    block_sum3(a, b, c, sh);
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = a;
+        if (out_host) out_host[blockIdx.x] = a;
+    }
+}
+// w -= sum_i h[i] V_i (i < k)
+__global__ void multi_axpy_kernel(long n, int k, const double* __restrict__ V, const double* __restrict__ h,
+                                  double sign, double* __restrict__ w) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s = fma(h[i], V[(long)i * n + e], s);
+        w[e] = fma(sign, s, w[e]);
+    }
+}
+// y = a x + b y
+__global__ void axpby_kernel(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        y[e] = fma(a, x[e], b * y[e]);
+}
+int krylov_blocks(long n) { return (int)std::min<long>((n + 255) / 256, 1024); }
+hipError_t launch_multi_dot(long n, int k, const double* V, const double* w, double* part, double* out,
+                            double* out_host, hipStream_t st) {
+    const int nb = krylov_blocks(n);
+    hipLaunchKernelGGL(multi_dot_kernel, dim3(nb), dim3(256), 0, st, n, k, V, w, part);
+    hipLaunchKernelGGL(multi_dot_final_kernel, dim3(k), dim3(256), 0, st, nb, part, out, out_host);
+    return hipGetLastError();
+}
+hipError_t launch_multi_axpy(long n, int k, const double* V, const double* h, double sign, double* w,
+                             hipStream_t st) {
+    const int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(blocks), dim3(256), 0, st, n, k, V, h, sign, w);
+    return hipGetLastError();
+}
+hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t st) {
+    const int blocks = (int)std::min<long>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks), dim3(256), 0, st, n, a, x, b, y);
     return hipGetLastError();
 }
 
@@ -324,9 +477,9 @@ template hipError_t launch_moment<float>(long, int, int, const double*, const fl
                                          double*, hipStream_t);
 template hipError_t launch_gradient<double>(long, int, int, const double*, const double*, const double*,
                                             const double*, const double*, const double*, const double*,
-                                            const double*, double*, double*, hipStream_t);
+                                            const double*, double*, double*, hipStream_t, int);
 template hipError_t launch_gradient<float>(long, int, int, const double*, const double*, const double*,
                                            const double*, const float*, const float*, const double*,
-                                           const double*, double*, double*, hipStream_t);
+                                           const double*, double*, double*, hipStream_t, int);
 
 }  // namespace sn

@@ -34,9 +34,19 @@ hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transp
                              T* yf, T* zf, hipStream_t st);
 // 2D: sigt and src are the diagonal-major arrays of launch_skew2d; 3D: per cell.
 // sink: scratch of sink_elems(g) elements (unused)
+// A part of the directions to sweep (nullptr: all of them, psi [cell][ndirs][nn]).
+// 3D: the reflection classes first .. first + count - 1; 2D: the count
+// directions order2d[0 .. count - 1].  psi: [cell][pstride][nn]; local = 0:
+// a direction's global index, local = 1: its position in the part (3D:
+// 4 * group + slot within its class).
+struct SweepPart {
+    int first, count, pstride, local;
+    const int* order2d;
+};
 template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
-                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st);
+                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st,
+                        const SweepPart* part = nullptr);
 inline long sink_elems(const SweepGeom&) { return 1; }
 // 3D fused sweep + moment (source iteration): psi is not stored; phioct
 // (workspace [nclasses][ncells][8]) receives each octant's share of phi, then
@@ -89,10 +99,29 @@ hipError_t launch_residual(long n, const double* a, const double* b, double* par
 // if out_host != nullptr, into pinned host memory
 hipError_t launch_residual_final(int nparts, const double* partials, double* out, double* out_host,
                                  hipStream_t st);
+// gradient contraction over the ndirs directions of psi / psi_adj
+// ([cell][ndirs][nn], weights w, zero weight = unused slot); accumulate:
+// g_t += ...; g_s is written when not NULL
 template <typename T>
 hipError_t launch_gradient(long nc, int nn, int ndirs, const double* w, const double* h, const double* sigma_t,
                            const double* sigma_s, const T* psi, const T* psi_adj, const double* phi,
-                           const double* chi, double* g_t, double* g_s, hipStream_t st);
+                           const double* chi, double* g_t, double* g_s, hipStream_t st, int accumulate = 0);
+// Alg. 1: bar = a - b (b may be NULL) on thick cells, 0 elsewhere; phi += z on thin cells
+hipError_t launch_thick_diff(long nc, int nn, const int* slot_of_cell, const double* a, const double* b, double* bar,
+                             hipStream_t st);
+hipError_t launch_thin_add(long nc, int nn, const int* slot_of_cell, const double* z, double* phi, hipStream_t st);
+// adjoint sources: y = a x; face data [ndirs][nbf] = 1 on [f0, f1) for directions with out[d] != 0
+hipError_t launch_scale(long n, double a, const double* x, double* y, hipStream_t st);
+hipError_t launch_face_data(int ndirs, long nbf, long f0, long f1, const int* out, double* data, hipStream_t st);
+// Krylov vector operations: out[i] = V_i . w (i < k, V: k vectors of n, part:
+// k * krylov_blocks(n) scratch, out_host: pinned copy or NULL);
+// w += sign * sum_i h[i] V_i; y = a x + b y
+int krylov_blocks(long n);
+hipError_t launch_multi_dot(long n, int k, const double* V, const double* w, double* part, double* out,
+                            double* out_host, hipStream_t st);
+hipError_t launch_multi_axpy(long n, int k, const double* V, const double* h, double sign, double* w,
+                             hipStream_t st);
+hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t st);
 
 // out[0] = sum_c r_c int_c phi; out[1] = outflow partial current through `face`
 // (wn[d] = w_d Omega_d.n for outgoing directions, else 0); part: 3*nparts scratch

@@ -475,7 +475,8 @@ __device__ __forceinline__ void sweep2d_wave(int nx, int ny, int ndirs, int d, T
 
 // blockIdx.x: position in dir_order (directions of one quadrant are placed
 // on the same XCDs, whose L2 then holds that quadrant's arrays); one launch
-// per row chunk.  sigskew / srcskew: the diagonal-major arrays of the four
+// per row chunk.  psi: [cell][pstride][4], direction index d (or, with local,
+// the workgroup's position in dir_order).  sigskew / srcskew: the diagonal-major arrays of the four
 // quadrants (skew2d_kernel layout).
 template <typename T>
 __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndirs, const DirInfo* __restrict__ dirs,
@@ -483,9 +484,13 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
                                                        int transpose, const T* __restrict__ sigskew,
                                                        const T* __restrict__ srcskew, const T* __restrict__ xf,
                                                        long xstride, T* __restrict__ ybuf, long ystride, int chunk,
-                                                       int nchunk, int row0, int nrows, T* __restrict__ psi) {
+                                                       int nchunk, int row0, int nrows, T* __restrict__ psi,
+                                                       int pstride, int local) {
     __shared__ __align__(16) Lds2<T> L;
     const int d = dir_order[blockIdx.x];
+    // direction index of this workgroup in psi: the global one, or (local)
+    // its position in dir_order, for a psi holding only those directions
+    const int dpsi = local ? (int)blockIdx.x : d;
     const DirInfo di = dirs[d];
     const int m = (di.rx ^ transpose) | ((di.ry ^ transpose) << 1);
     const T ax = T(di.ax), ay = T(di.ay);
@@ -498,7 +503,7 @@ __global__ void __launch_bounds__(ROWS2D) sweep2d_kernel(int nx, int ny, int ndi
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = (nrows + 63) / 64;
 #define SN_WAVE2(MM, RR) \
-    sweep2d_wave<T, MM, RR>(nx, ny, ndirs, d, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, &L, wave, nw)
+    sweep2d_wave<T, MM, RR>(nx, ny, pstride, dpsi, ax, ay, sq, cq, xfd, yin, yout, row0, nrows, psi, &L, wave, nw)
 #define SN_CASE2(MM)                                      \
     case MM:                                              \
         if (wave == 0) SN_WAVE2(MM, W2_FIRST);            \
@@ -952,6 +957,7 @@ __global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(PSI3D_
 sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const DirInfo* __restrict__ dirs, int transpose,
                                                       const int* __restrict__ groups, int groups_per_class,
+                                                      int cls0, int pstride, int local,
                                                       const T* __restrict__ sigt, const T* __restrict__ src,
                                                       T* __restrict__ xf, long xstride, T* __restrict__ yf,
                                                       long ystride, T* __restrict__ zf, long zstride, int TX,
@@ -964,23 +970,28 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
     const int tile = tiles[blockIdx.x];
     const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
     // reflection of the class, from its first direction (always valid)
-    const int mc = groups[6 * blockIdx.y * groups_per_class];
+    const int cls = cls0 + (int)blockIdx.y;
+    const int mc = groups[6 * cls * groups_per_class];
     const DirInfo dm = dirs[mc];
     const int m = (dm.rx ^ transpose) | ((dm.ry ^ transpose) << 1) | ((dm.rz ^ transpose) << 2);
     if constexpr (staged_tile<T>()) {
         stage_tile<T>(nx, ny, nz, m, I, J, K, TX, sigt, src, &tin);
         __syncthreads();
     }
-    const int grp = blockIdx.y * groups_per_class + wave;
+    const int grp = cls * groups_per_class + wave;
     const int* gi = groups + 6 * grp;
     const int d = gi[lane >> 4];
     const int m0 = gi[0];            // first direction of the group (-1: empty slot)
     if (m0 < 0) return;              // empty group slot: the whole wave leaves
-    // consecutive directions d0 .. d0 + nvalid - 1: psi goes out through the
-    // LDS stage; otherwise (nvalid = 0) every lane stores its own values
-    const int d0 = gi[4], nvalid = gi[4] >= 0 ? gi[5] : 0;
+    // consecutive directions d0 .. d0 + nvalid - 1 of psi: psi goes out
+    // through the LDS stage; otherwise (nvalid = 0) every lane stores its own
+    // values.  With local, psi holds only this class's directions, in group
+    // order (group w, slot k -> 4 w + k), which are always consecutive.
+    const int d0 = local ? 4 * wave : gi[4];
+    const int nvalid = local ? gi[5] : (gi[4] >= 0 ? gi[5] : 0);
     const bool dok = d >= 0;
     const int dd = dok ? d : m0;
+    const int dpsi = local ? 4 * wave + (lane >> 4) : dd;
     const DirInfo di = dirs[dd];
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
     T* xd = xf + dd * xstride;
@@ -988,8 +999,8 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
     T* zd = zf + dd * zstride;
 #define SN_CASE(MM)                                                                                               \
     case MM:                                                                                                      \
-        sweep3d_body<T, MM>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, src, \
-                            xd, yd, zd, psi, d0, nvalid, stage[wave]);                                            \
+        sweep3d_body<T, MM>(nx, ny, nz, pstride, dpsi, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt,   \
+                            src, xd, yd, zd, psi, d0, nvalid, stage[wave]);                                       \
         break;
     switch (m) {
         SN_CASE(0)
@@ -1108,15 +1119,18 @@ hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transp
 
 template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
-                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st) {
+                        T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st,
+                        const SweepPart* part) {
+    const SweepPart all{0, g.dim == 2 ? g.ndirs : g.nclasses, g.ndirs, 0, g.groups};
+    const SweepPart& pp = part ? *part : all;
     if (g.dim == 2) {
         for (int ch = 0; ch < g.nchunk; ++ch) {
             int row0 = ch * ROWS2D;
             int nrows = std::min(ROWS2D, g.ny - row0);
             int nw = (nrows + 63) / 64;
-            hipLaunchKernelGGL(sweep2d_kernel<T>, dim3(g.ndirs), dim3(64 * nw), 0, st, g.nx, g.ny, g.ndirs, dirs,
-                               g.groups, transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0, nrows,
-                               psi);
+            hipLaunchKernelGGL(sweep2d_kernel<T>, dim3(pp.count), dim3(64 * nw), 0, st, g.nx, g.ny, g.ndirs, dirs,
+                               pp.order2d, transpose, sigt, src, xf, g.xstride, yf, g.ystride, ch, g.nchunk, row0,
+                               nrows, psi, pp.pstride, pp.local);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -1124,9 +1138,9 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
     }
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
-        hipLaunchKernelGGL((sweep3d_kernel<T>), dim3(nt, g.nclasses), dim3(64 * g.groups_per_class), 0, st, g.nx,
-                           g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, sigt, src, xf,
-                           g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
+        hipLaunchKernelGGL((sweep3d_kernel<T>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st, g.nx,
+                           g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first, pp.pstride,
+                           pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
                            tiles + plane_off[p], psi);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1203,8 +1217,9 @@ template hipError_t launch_init_faces<float>(const SweepGeom&, const DirInfo*, i
                                              float*, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepGeom&, const DirInfo*, int, const double*, const double*,
                                          double*, double*, double*, const int*, const int*, double*, double*,
-                                         hipStream_t);
+                                         hipStream_t, const SweepPart*);
 template hipError_t launch_sweep<float>(const SweepGeom&, const DirInfo*, int, const float*, const float*, float*,
-                                        float*, float*, const int*, const int*, float*, float*, hipStream_t);
+                                        float*, float*, const int*, const int*, float*, float*, hipStream_t,
+                                        const SweepPart*);
 
 }  // namespace sn

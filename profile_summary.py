@@ -1,15 +1,15 @@
 """Summaries of rocprofv3 output for the sweep kernels.
 
-  python -m paper_2001_09196_amd.profile_summary stats <dir> <out.txt> <command...>
+  python profile_summary.py stats <dir> <out.txt> <command...>
       per-kernel table (calls, average and total duration) from the
       *_kernel_stats.csv of a `rocprofv3 --kernel-trace --stats --output-format csv` run
-  python -m paper_2001_09196_amd.profile_summary traffic <key> <kernel-substring> <fetch_dir> <write_dir>
+  python profile_summary.py traffic <key> <kernel-substring> <fetch_dir> <write_dir>
       <copy_fetch_dir> <copy_write_dir> <copy_bytes> <out.txt> <traffic.json>
       HBM bytes per dispatch of one kernel from FETCH_SIZE and WRITE_SIZE runs (KiB per
       dispatch), each scaled so that a plain copy of copy_bytes reads as copy_bytes; the entry
       of traffic.json records a sha256 of the sweep kernels' source and build flags
       (kernel_source_sha) the counters were taken on.
-  python -m paper_2001_09196_amd.profile_summary traffic_per_call <calls> <key> ... (as traffic)
+  python profile_summary.py traffic_per_call <calls> <key> ... (as traffic)
       the same for kernels launched several times per call: the counters of all
       dispatches summed and divided by the number of calls.
 """
@@ -22,7 +22,7 @@ import json
 import os
 import sys
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2001_09196_amd")
 
 
 def _one(pattern):
