@@ -274,6 +274,22 @@ int sn_gradient(sn_context *ctx, const void *psi, const void *psi_adj, sn_precis
 int sn_response(sn_context *ctx, const double *r, const double *phi, int face, const void *psi,
                 sn_precision prec, double *out);
 
+/* sn_response for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same functional, arguments, kernels and result (bit for bit) as
+ * sn_response, but it allocates nothing.  Its face weights, partial sums and
+ * result live in a fixed scratch array of 16384 doubles (128 KiB) that every
+ * GPU the library runs on holds from the library's load until the process
+ * ends; its device address is looked up once per device when the first
+ * context on that device is created.  Every call on one GPU shares that
+ * array and overwrites it completely, so calls that overlap on one GPU (two
+ * streams or threads at once) race; serialise them.  Needs ndirs + 3 * 1024
+ * + 3 <= 16384 (at most 13309 directions): returns SN_ERR_INVALID beyond it,
+ * SN_ERR_HIP if the scratch address could not be looked up.  *out (host)
+ * after a stream synchronisation. */
+int sn_response_noalloc(sn_context *ctx, const double *r, const double *phi, int face, const void *psi,
+                        sn_precision prec, double *out);
+
 /* Kernel timing for measurement.  enable = 1: every subsequent call records
  * HIP events on the context's stream around the sweep kernels of each sweep
  * (excluding the source and face-initialisation kernels) and around each DSA

@@ -27,7 +27,7 @@ SN_KRYLOV_MAX_RESTART = 200
 # every symbol declared in include/sn.h
 EXPORTED = ("sn_context_create", "sn_context_destroy", "sn_inflow_size", "sn_thick_count", "sn_sweep",
             "sn_scalar_flux", "sn_dsa_thick_correct", "sn_source_iterate", "sn_krylov_solve", "sn_adjoint_source",
-            "sn_face_response", "sn_adjoint_gradient", "sn_gradient", "sn_response",
+            "sn_face_response", "sn_adjoint_gradient", "sn_gradient", "sn_response", "sn_response_noalloc",
             "sn_set_kernel_timing", "sn_kernel_timing", "sn_last_error")
 
 
@@ -116,6 +116,8 @@ def lib():
         L.sn_gradient.restype = ip
         L.sn_response.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(ctypes.c_double)]
         L.sn_response.restype = ip
+        L.sn_response_noalloc.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(ctypes.c_double)]
+        L.sn_response_noalloc.restype = ip
         L.sn_set_kernel_timing.argtypes = [vp, ip]
         L.sn_set_kernel_timing.restype = ip
         dp = ctypes.POINTER(ctypes.c_double)
@@ -286,6 +288,14 @@ def sn_gradient(ctx: Context, psi, psi_adj, prec: int, phi, chi, g_t, g_s):
 def sn_response(ctx: Context, r=None, phi=None, face: int = -1, psi=None, prec: int = SN_FP64) -> float:
     out = ctypes.c_double()
     _check(lib().sn_response(ctx.handle, _ptr(r), _ptr(phi), int(face), _ptr(psi), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def sn_response_noalloc(ctx: Context, r=None, phi=None, face: int = -1, psi=None, prec: int = SN_FP64) -> float:
+    """sn_response without device allocation (fixed scratch, see sn.h)."""
+    out = ctypes.c_double()
+    _check(lib().sn_response_noalloc(ctx.handle, _ptr(r), _ptr(phi), int(face), _ptr(psi), int(prec),
+                                     ctypes.byref(out)))
     return out.value
 
 

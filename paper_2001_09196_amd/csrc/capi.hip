@@ -152,6 +152,10 @@ struct sn_context {
     DevBuf<double> kv, kz, kw, kb, kzero, kdot, kpart;
     double* kdot_host = nullptr;
     int sweeps = 0;  // transport sweeps (all directions) since the last reset
+    // device address of the fixed scratch of the entry points that allocate
+    // nothing on this context's device (NULL if its lookup failed)
+    double* noalloc = nullptr;
+    hipError_t noalloc_err = hipSuccess;
     // optional event timing of the sweep kernels and of the DSA solves
     int timing = 0;
     std::vector<hipEvent_t> evpool;
@@ -1121,6 +1125,9 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     c->nrpart = (int)std::max<long>(1, std::min<long>((nc * c->nn + 255) / 256, 1024));
     if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
     HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(sn_context::HostScalars), hipHostMallocDefault));
+    // once per device (cached across contexts): the address of the fixed
+    // scratch of sn_response_noalloc; a failed lookup disables only that entry
+    c->noalloc_err = noalloc_scratch(&c->noalloc);
     HIPCHK(hipEventCreateWithFlags(&c->res_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->cg_ev, hipEventDisableTiming));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1403,6 +1410,47 @@ int sn_response(sn_context* ctx, const double* r, const double* phi, int face, c
                                       ctx->ndirs, ctx->wn.p, (const float*)psi, ctx->rpart.p, ctx->nrpart,
                                       ctx->res3.p, ctx->stream));
     HIPCHK(hipMemcpyAsync(res, ctx->res3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *out = res[0] + res[1];
+    return 0;
+}
+
+int sn_response_noalloc(sn_context* ctx, const double* r, const double* phi, int face, const void* psi,
+                        sn_precision prec, double* out) {
+    g_err.clear();
+    if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    const int dim = ctx->mesh.dim;
+    if (face < -1 || face >= 2 * dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * dim - 1);
+    if (face >= 0 && !psi) return fail(SN_ERR_INVALID, "psi is needed for a face functional");
+    if ((r == nullptr) != (phi == nullptr)) return fail(SN_ERR_INVALID, "r and phi must be given together");
+    if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision");
+    // scratch layout: [0, nd) face weights, then 3 * nparts partial sums, then the 3 results
+    const long need = (long)ctx->ndirs + 3L * ctx->nrpart + 3;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return fail(SN_ERR_INVALID, "sn_response_noalloc: %d directions need %ld scratch doubles, more than the "
+                    "fixed %ld (at most %ld directions)", ctx->ndirs, need, NOALLOC_SCRATCH_DOUBLES,
+                    NOALLOC_SCRATCH_DOUBLES - 3L * 1024 - 3);
+    if (!ctx->noalloc)
+        return fail(SN_ERR_HIP, "device scratch address unavailable: %s", hipGetErrorString(ctx->noalloc_err));
+    double* wn_d = ctx->noalloc;
+    double* part = wn_d + ctx->ndirs;
+    double* res_d = part + 3L * ctx->nrpart;
+    std::vector<double> wn(ctx->ndirs, 0.0);
+    if (face >= 0)
+        for (int d = 0; d < ctx->ndirs; ++d) {
+            const double on = face_dot(ctx, face, d);
+            wn[d] = on > 0 ? ctx->hw[d] * on : 0.0;
+        }
+    HIPCHK(hipMemcpyAsync(wn_d, wn.data(), ctx->ndirs * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, dim == 3 ? ctx->mesh.hz : 1.0};
+    if (prec == SN_FP64)
+        HIPCHK(launch_response<double>(ctx->nc, ctx->nn, ctx->mesh.nx, ctx->mesh.ny, ctx->mesh.nz, h, r, phi, face,
+                                       ctx->ndirs, wn_d, (const double*)psi, part, ctx->nrpart, res_d, ctx->stream));
+    else
+        HIPCHK(launch_response<float>(ctx->nc, ctx->nn, ctx->mesh.nx, ctx->mesh.ny, ctx->mesh.nz, h, r, phi, face,
+                                      ctx->ndirs, wn_d, (const float*)psi, part, ctx->nrpart, res_d, ctx->stream));
+    double res[3];
+    HIPCHK(hipMemcpyAsync(res, res_d, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     *out = res[0] + res[1];
     return 0;

@@ -130,6 +130,12 @@ hipError_t launch_response(long nc, int nn, int nx, int ny, int nz, const double
                            const double* phi, int face, int ndirs, const double* wn, const T* psi, double* part,
                            int nparts, double* out, hipStream_t st);
 
+// fixed device scratch of the entry points that allocate nothing (noalloc.hip):
+// NOALLOC_SCRATCH_DOUBLES doubles per device, shared by every call on that
+// device; noalloc_scratch returns its device address on the current device
+constexpr long NOALLOC_SCRATCH_DOUBLES = 16384;
+hipError_t noalloc_scratch(double** out);
+
 // heterogeneous DSA (dsa.hip)
 struct DsaGeom {
     int dim, nx, ny, nz, nn;
