@@ -195,11 +195,34 @@ long inflow_size(const sn_mesh* m) {
     return 4L * ((long)m->ny * m->nz + (long)m->nx * m->nz + (long)m->nx * m->ny);
 }
 
+// The sweep's face buffers.  3D: one block per direction holding its x, y
+// and z regions (at 0, yoff and zoff; xstride = ystride = zstride = the block
+// size), all in xf; 2D: x and y in their own buffers.
 template <typename T>
-int init_faces(sn_context* ctx, const double* inflow, int transpose, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf) {
+struct Faces {
+    T *x, *y, *z;
+};
+template <typename T>
+int face_views(sn_context* ctx, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, Faces<T>* f) {
+    const SweepGeom& g = ctx->sg;
+    int rc;
+    if (g.dim == 3) {
+        if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
+        *f = Faces<T>{xf.p, xf.p + g.yoff, xf.p + g.zoff};
+        return 0;
+    }
+    if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
+    if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
+    if ((rc = zf.ensure(1))) return rc;
+    *f = Faces<T>{xf.p, yf.p, zf.p};
+    return 0;
+}
+
+template <typename T>
+int init_faces(sn_context* ctx, const double* inflow, int transpose, const Faces<T>& f) {
     sn_context::FaceKey& k = ctx->fkey[sizeof(T) == 8 ? 0 : 1];
     if (ctx->face_reuse && k.valid && k.inflow == inflow && k.transpose == transpose) return 0;
-    HIPCHK(launch_init_faces<T>(ctx->sg, ctx->dirs.p, transpose, inflow, xf.p, yf.p, zf.p, ctx->stream));
+    HIPCHK(launch_init_faces<T>(ctx->sg, ctx->dirs.p, transpose, inflow, f.x, f.y, f.z, ctx->stream));
     k.inflow = inflow;
     k.transpose = transpose;
     k.valid = true;
@@ -223,9 +246,8 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
                const T* sigt, DevBuf<T>& srcskew, const T* sigskew, const SweepPart* part = nullptr) {
     const SweepGeom& g = ctx->sg;
     int rc;
-    if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
-    if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
-    if ((rc = zf.ensure((size_t)std::max<long>(g.zstride, 1) * g.ndirs))) return rc;
+    Faces<T> f;
+    if ((rc = face_views(ctx, xf, yf, zf, &f))) return rc;
     if ((rc = sink.ensure((size_t)sink_elems(g)))) return rc;
     const T* sweep_src;
     const T* sweep_sig = sigt;
@@ -243,10 +265,10 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
         HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
         sweep_src = src.p;
     }
-    if ((rc = init_faces<T>(ctx, inflow, transpose, xf, yf, zf))) return rc;
+    if ((rc = init_faces<T>(ctx, inflow, transpose, f))) return rc;
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
-    HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, xf.p, yf.p, zf.p, ctx->tiles.p,
+    HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, f.x, f.y, f.z, ctx->tiles.p,
                            ctx->plane_off.data(), psi, sink.p, ctx->stream, part));
     if (!part) ++ctx->sweeps;
     if (ctx->timing) {
@@ -287,16 +309,15 @@ int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev
                       DevBuf<T>& yf, DevBuf<T>& zf, DevBuf<T>& src, const T* sigt, const double* res_ref) {
     const SweepGeom& g = ctx->sg;
     int rc;
-    if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
-    if ((rc = yf.ensure((size_t)g.ystride * g.ndirs))) return rc;
-    if ((rc = zf.ensure((size_t)std::max<long>(g.zstride, 1) * g.ndirs))) return rc;
+    Faces<T> f;
+    if ((rc = face_views(ctx, xf, yf, zf, &f))) return rc;
     if ((rc = src.ensure((size_t)ctx->nc * ctx->nn))) return rc;
     if ((rc = ctx->phioct.ensure((size_t)g.nclasses * ctx->nc * 8))) return rc;
     HIPCHK(launch_source<T>(ctx->nc, ctx->nn, ctx->sigs.p, phi, phi_prev, q, src.p, ctx->stream));
-    if ((rc = init_faces<T>(ctx, inflow, transpose, xf, yf, zf))) return rc;
+    if ((rc = init_faces<T>(ctx, inflow, transpose, f))) return rc;
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
-    HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, xf.p, yf.p, zf.p, ctx->tiles.p,
+    HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, f.x, f.y, f.z, ctx->tiles.p,
                                   ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, res_ref, ctx->fpart.p,
                                   ctx->stream));
     ++ctx->sweeps;
@@ -900,6 +921,7 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.xstride = (long)mesh->ny * 2;
         g.ystride = (long)g.nchunk * mesh->nx * 2;
         g.zstride = 0;
+        g.yoff = g.zoff = 0;
         g.TX = 0;
         g.nTx = g.nTy = g.nTz = 0;
         g.nplanes = 0;
@@ -975,9 +997,10 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
             return fail(SN_ERR_UNSUPPORTED, "more than 1023 sweep tiles along an axis");
         g.nplanes = g.nTx + g.nTy + g.nTz - 2;
         g.nchunk = 0;
-        g.xstride = (long)g.nTx * mesh->nz * mesh->ny * 4;
-        g.ystride = (long)g.nTy * mesh->nz * mesh->nx * 4;
-        g.zstride = (long)g.nTz * mesh->ny * mesh->nx * 4;
+        // a direction's face block: x, y and z regions of every tile row
+        g.yoff = (long)g.nTx * mesh->nz * mesh->ny * 4;
+        g.zoff = g.yoff + (long)g.nTy * mesh->nz * mesh->nx * 4;
+        g.xstride = g.ystride = g.zstride = g.zoff + (long)g.nTz * mesh->ny * mesh->nx * 4;
         std::vector<int> tl;
         c->plane_off.assign(1, 0);
         for (int p = 0; p < g.nplanes; ++p) {
@@ -1030,6 +1053,21 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.nclasses = ncls;
         g.groups_per_class = gpc;
         g.groups = c->groups.p;
+        // the psi sweep without branches around memory operations needs each
+        // direction group consecutive (one face resource per wave) and byte
+        // offsets below 2^31 from a tile's lowest cell and within four
+        // directions' face blocks (FP64 bounds, which cover FP32);
+        // SN_SWEEP_BUF=0 selects the other variant
+        {
+            bool consec = true;
+            for (size_t e = 0; e + 5 < gr.size(); e += 6)
+                if (gr[e + 5] > 0 && gr[e + 4] < 0) consec = false;
+            const double lim = 2147483648.0 - 4096.0;
+            const double psi_span = ((3.0 * mesh->ny + 3.0) * mesh->nx + g.TX) * c->ndirs * 64.0 + 4096.0;
+            const double face_span = 4.0 * (double)g.xstride * 8.0;
+            const char* e = std::getenv("SN_SWEEP_BUF");
+            g.buf = consec && psi_span < lim && face_span < lim && !(e && std::atoi(e) == 0);
+        }
     }
 
     // direction parts: 3D the reflection classes (local index 4 group + slot),

@@ -25,8 +25,13 @@ struct SweepGeom {
                        //     the first id if the valid ids are consecutive (else -1), the valid count;
                        // 2D: device [ndirs] direction of each workgroup (XCD-aware order)
     int nplanes;       // 3D tile-diagonal planes
+    int buf;           // 3D psi sweep: the variant without branches around memory operations (buffer loads
+                       //     and stores with range-checked offsets); needs every direction group consecutive
+                       //     and the byte offsets of one tile's psi and of four directions' face blocks below 2^31
     int nchunk;        // 2D row chunks of at most ROWS2D rows
-    long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements)
+    long xstride, ystride, zstride;  // per-direction face-buffer strides (elements); 3D: all three are the size
+                                     // of a direction's face block, whose y and z regions start at yoff and zoff
+    long yoff, zoff;
 };
 
 template <typename T>

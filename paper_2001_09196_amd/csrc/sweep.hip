@@ -670,6 +670,22 @@ __device__ __forceinline__ void stage_tile(int nx, int ny, int nz, int m, int I,
 
 
 
+// The psi stage of a wave: 16 pencil blocks of four directions x eight values
+// each, a block padded by 16 bytes.  Lane (pencil p, direction k) writes its
+// eight values at p * STAGE_PENCIL + 8 k; unpadded, the blocks of consecutive
+// pencils lie 256 (FP64) or 128 (FP32) bytes apart and the eight lanes of one
+// LDS pass all hit the same four banks (an eight-way conflict on every write;
+// measured at C5: bank-conflict cycles five times the LDS-active cycles).
+// With the padding the eight lanes fall on eight distinct bank groups.
+template <typename T>
+constexpr int stage_pencil() {
+    return 32 + 16 / (int)sizeof(T);
+}
+template <typename T>
+constexpr int stage_elems() {
+    return 16 * stage_pencil<T>();
+}
+
 // FUSED = false: psi is stored.  FUSED = true (source iteration): psi is not
 // stored; every step the lanes' w_d psi (FP64) is summed over the four
 // directions of a pencil (rows_sum8), the 16 pencil sums of each wave go to an
@@ -781,7 +797,7 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                     const int qk = rz ? nz - 1 - qkl : qkl;
                     const long qc0 = ((long)qk * ny + qj) * nx + (rx ? nx - 1 - i0 : i0);
                     wsk[it] = qy + qz;
-                    woff[it] = q * 32 + o * CH;
+                    woff[it] = q * stage_pencil<T>() + o * CH;
                     wp[it] = psi + (qc0 * ndirs + d0) * 8 + o * CH - (long)(qy + qz) * wstride;
                 }
             }
@@ -859,7 +875,7 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 for (int n = 0; n < 8; ++n) acc[n] = wgt * (double)o[n];
             } else if (nvalid > 0) {
                 // staged: this lane's eight values go to LDS slot (pencil, k)
-                lds_t<T>* sp = as_lds(stg) + ((lane & 15) * 4 + (lane >> 4)) * 8;
+                lds_t<T>* sp = as_lds(stg) + (lane & 15) * stage_pencil<T>() + (lane >> 4) * 8;
 #pragma unroll
                 for (int n = 0; n < 8; ++n) sp[n] = o[n];
             } else {
@@ -943,6 +959,301 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3D psi sweep without branches around memory operations
+// ---------------------------------------------------------------------------
+// In sweep3d_body the face loads and every store sit inside per-lane
+// conditions (the lane's cell is inside the tile at this step, it is a face
+// lane, its psi piece is valid).  gfx950 counts loads and stores in one
+// in-order counter (vmcnt), and across such branches the compiler cannot tell
+// how many operations a step issued, so each step waits for all of them
+// (s_waitcnt vmcnt(0)): the face inflow of a step waited for the previous
+// step's psi and face stores to be acknowledged.  Measured at C5 (FP64): the
+// psi sweep takes 8.7 ms with the face loads left out against 15.4 ms with
+// them.  This body issues the same fixed list of memory operations at every
+// step, so the counts are exact and a step waits only for what it uses:
+//   * one 16-byte face piece per lane is loaded two steps ahead: the y and z
+//     face inflow of the wave's four directions for that step (FP64: 64
+//     pieces; FP32: 32, the other lanes idle), then moved through a small LDS
+//     area to the lanes on the tile's y = 0 and z = 0 sides;
+//   * the y and z face outflow of the step goes the opposite way: the lanes on
+//     the tile's far sides put it in the LDS area and every lane stores one
+//     piece;
+//   * psi pieces go out through the LDS stage as in sweep3d_body;
+//   * the x face is loaded before the loop and stored after it.
+// Loads and stores use raw buffer resources with a wave-uniform base and a
+// per-lane byte offset; a lane with nothing to load or store gets the offset
+// kOOB, outside the resource's range, and the hardware's range check turns
+// the load into zeros and drops the store without touching memory.  The
+// faces of a direction are one block (x, y, z regions) so that a single
+// resource from the wave's first direction covers both faces of its four
+// directions; valid offsets stay below 2^31 bytes (checked on the host,
+// SweepGeom::buf), and each wave's directions must be consecutive.
+constexpr unsigned kOOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+struct Piece;  // a 16-byte piece of T values
+template <>
+struct Piece<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Piece<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <typename T>
+using piece_t = typename Piece<T>::type;
+template <typename T>
+using lds_piece_t = __attribute__((address_space(3))) piece_t<T>;
+// aux 2: nontemporal (psi); 0: default caching (face data, read again soon)
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store_piece(__amdgpu_buffer_rsrc_t r, unsigned off, piece_t<T> v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, AUX);
+}
+template <typename T>
+__device__ __forceinline__ piece_t<T> buf_load_piece(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+}
+template <typename T>
+constexpr int face_pieces() {  // 16-byte pieces per four face values
+    return (int)sizeof(T) / 4;
+}
+template <typename T>
+constexpr int face_stage_elems() {  // the face area of a wave: 64 pieces
+    return 64 * 16 / (int)sizeof(T);
+}
+
+// rf: face resource at the wave's first direction's face block (fstride
+// elements per direction; y and z regions at yoff and zoff within a block);
+// xd: this lane's direction's x-face region.  rpsi: psi resource at the
+// tile's lowest cell (cell_base) and the wave's first psi direction.  slots:
+// bit k set when the wave's direction slot k is used.
+template <typename T, int M>
+__device__ __forceinline__ void sweep3d_body_buf(int nx, int ny, int nz, int pstride, unsigned slots, bool dok, T ax,
+                                                 T ay, T az, int I, int J, int K, int TX, int nTx, int nTy, int nTz,
+                                                 const TileIn<T>* tin, const T* __restrict__ sigt,
+                                                 const T* __restrict__ src, T* __restrict__ xd,
+                                                 __amdgpu_buffer_rsrc_t rf, long fstride, long yoff, long zoff,
+                                                 __amdgpu_buffer_rsrc_t rpsi, long cell_base, int nvalid,
+                                                 T* __restrict__ stg, T* __restrict__ fstg) {
+    constexpr int rx = M & 1, ry = (M >> 1) & 1, rz = (M >> 2) & 1;
+    constexpr int sz = (int)sizeof(T);
+    constexpr int CH = 16 / sz;                  // values per 16-byte piece
+    constexpr int NIT = 8 / CH;                  // psi passes for four directions
+    constexpr int NPK = face_pieces<T>();        // pieces per four face values
+    constexpr int NYP = 16 * NPK;                // y-face pieces of a step (z: as many)
+    const int lane = threadIdx.x & 63;
+    const int jy = lane & 3, kz = (lane >> 2) & 3, kd = lane >> 4;
+    const int jl = J * 4 + jy, kl = K * 4 + kz;
+    const bool pen = dok && jl < ny && kl < nz;
+    const int jc = min(jl, ny - 1), kc = min(kl, nz - 1);
+    const int j = ry ? ny - 1 - jc : jc, k = rz ? nz - 1 - kc : kc;
+    const int i0 = I * TX;
+    const int len = min(TX, nx - i0);
+    const int skew = jy + kz;
+    T xin[4], yo[4], zo[4];
+    {
+        const Vec4<T> x = load4(xd + (((long)I * nz + kc) * ny + jc) * 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            xin[t] = x.v[t];
+            yo[t] = T(0);
+            zo[t] = T(0);
+        }
+    }
+    constexpr int cdir = rx ? -1 : 1;
+    const long rowbase = ((long)k * ny + j) * nx;
+    const long c0 = rowbase + (rx ? nx - 1 - i0 : i0);
+    const T* src0 = src + c0 * 8;
+    const T* sig0 = sigt + c0;
+    const lds_t<T>* tsrc = as_lds(&tin->s[0][lane & 15][0]);
+    const lds_t<T>* tsig = as_lds(&tin->sig[0][lane & 15]);
+    // The face piece of this lane: piece q of the y face (q < NYP) or of the
+    // z face, for direction slot fk and side position fq (the kz of a y-face
+    // lane, the jy of a z-face lane), half fh of the four values.  The lane on
+    // the near side that receives it lags the tile's first pencil by fq steps,
+    // the far-side lane that sends it by fq + 3.
+    const bool isy = lane < NYP, isz = !isy && lane < 2 * NYP;
+    const int fqq = isy ? lane : lane - NYP;
+    const int fk = fqq / (4 * NPK), fq = (fqq / NPK) & 3, fh = fqq % NPK;
+    const bool fslot = (isy || isz) && ((slots >> (fk & 3)) & 1u);
+    const bool fin_ok = fslot && (isy ? K * 4 + fq < nz : J * 4 + fq < ny);
+    const bool fout_ok = fslot && (isy ? (J + 1 < nTy && K * 4 + fq < nz) : (K + 1 < nTz && J * 4 + fq < ny));
+    const long frow_in = isy ? yoff + (((long)J * nz + K * 4 + fq) * nx + i0) * 4
+                             : zoff + (((long)K * ny + J * 4 + fq) * nx + i0) * 4;
+    const long frow_out = isy ? yoff + (((long)(J + 1) * nz + K * 4 + fq) * nx + i0) * 4
+                              : zoff + (((long)(K + 1) * ny + J * 4 + fq) * nx + i0) * 4;
+    const unsigned fin0 = (unsigned)(((long)fk * fstride + frow_in + fh * CH) * sz);
+    const unsigned fout0 = (unsigned)(((long)fk * fstride + frow_out + fh * CH) * sz);
+    auto fin_off = [&](int s) {
+        const int ir = s - fq;
+        return (fin_ok && (unsigned)ir < (unsigned)len) ? fin0 + (unsigned)(ir * 4 * sz) : kOOB;
+    };
+    auto fout_off = [&](int s) {
+        const int ir = s - fq - 3;
+        return (fout_ok && (unsigned)ir < (unsigned)len) ? fout0 + (unsigned)(ir * 4 * sz) : kOOB;
+    };
+    // this lane's four y- and z-face values in the face area
+    lds_t<T>* fa = as_lds(fstg);
+    const int ypos = (kd * 4 + kz) * NPK * CH, zpos = (NYP + (kd * 4 + jy) * NPK) * CH;
+    // psi pieces: pass it of the wave writes 16-byte piece it * 64 + lane of
+    // the 16 pencils' blocks of nvalid * 8 values; its byte offset from the
+    // psi resource base at step 0 (32-bit wrap-around arithmetic: at every
+    // step where the piece is written the true offset lies in [0, 2^31)),
+    // moved by wsb per step; wsk: the pencil's skew (huge: no piece)
+    const int wsb = cdir * pstride * 8 * sz;
+    int wsk[NIT], woff[NIT];
+    unsigned wofs[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int id = it * 64 + lane;
+        const int per = nvalid * 8 / CH;
+        wsk[it] = 1 << 29;
+        woff[it] = 0;
+        wofs[it] = 0;
+        if (id < 16 * per) {
+            const int q = id / per, o = id - q * per;
+            const int qy = q & 3, qz = q >> 2;
+            const int qjl = J * 4 + qy, qkl = K * 4 + qz;
+            if (qjl < ny && qkl < nz) {
+                const int qj = ry ? ny - 1 - qjl : qjl;
+                const int qk = rz ? nz - 1 - qkl : qkl;
+                const long qc0 = ((long)qk * ny + qj) * nx + (rx ? nx - 1 - i0 : i0);
+                wsk[it] = qy + qz;
+                woff[it] = q * stage_pencil<T>() + o * CH;
+                wofs[it] = (unsigned)(((qc0 - cell_base) * pstride * 8 + o * CH) * sz - (long)(qy + qz) * wsb);
+            }
+        }
+    }
+    const T ax4 = T(4) * ax, ax2 = T(2) * ax, ay4 = T(4) * ay, ay2 = T(2) * ay, az4 = T(4) * az, az2 = T(2) * az;
+    const int nsteps = len + 6;
+    lds_t<T>* stw = as_lds(stg) + (lane & 15) * stage_pencil<T>() + (lane >> 4) * 8;
+    struct Src {
+        Vec8<T> s;
+        T sig;
+    };
+    auto fetch = [&](int ir, Src& v) {
+        if constexpr (!staged_tile<T>()) {
+            const int irc = min(max(ir, 0), len - 1);
+            v.s = load8(src0 + cdir * irc * 8);
+            v.sig = sig0[cdir * irc];
+        }
+    };
+    // fin: this step's face inflow piece, loaded two steps earlier; refilled
+    // here with the piece of step s + 2
+    auto step = [&](int s, piece_t<T>& fin, Src& use, Src& fill) {
+        const int ir = s - skew;
+        fetch(ir + 1, fill);
+        *reinterpret_cast<lds_piece_t<T>*>(fa + lane * CH) = fin;
+        fin = buf_load_piece<T>(rf, fin_off(s + 2));
+        __builtin_amdgcn_wave_barrier();
+        T yi[4], zi[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            // the moves are made by every lane and only then selected (the
+            // empty asm keeps the compiler from turning the selects into
+            // branches around the moves)
+            T ys = row_shr<1>(yo[t]), zs = row_shr<4>(zo[t]);
+            asm volatile("" : "+v"(ys), "+v"(zs));
+            yi[t] = jy == 0 ? fa[ypos + t] : ys;
+            zi[t] = kz == 0 ? fa[zpos + t] : zs;
+        }
+        const bool active = pen && ir >= 0 && ir < len;
+        const int irl = min(max(ir, 0), len - 1);
+        T g[8], u[8], sg;
+        if constexpr (staged_tile<T>()) {
+            const lds_t<T>* sp = tsrc + irl * (16 * src_pencil<T>());
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g[n] = sp[n ^ M];
+            sg = tsig[irl * 16];
+        } else {
+#pragma unroll
+            for (int n = 0; n < 8; ++n) g[n] = use.s.v[n ^ M];
+            sg = use.sig;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int nx0 = 2 * t;
+            g[nx0] = fma(ax4, xin[t], g[nx0]);
+            g[nx0 + 1] = fma(-ax2, xin[t], g[nx0 + 1]);
+            const int ny0 = (t & 1) + 4 * (t >> 1);
+            g[ny0] = fma(ay4, yi[t], g[ny0]);
+            g[ny0 + 2] = fma(-ay2, yi[t], g[ny0 + 2]);
+            g[t] = fma(az4, zi[t], g[t]);
+            g[t + 4] = fma(-az2, zi[t], g[t + 4]);
+        }
+        cell_solve3(g, ax, ay, az, sg, u);
+        // x inflow: the tile's until the lane's first cell, then each cell's
+        // outflow, held after the last cell for the store after the loop
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            xin[t] = active ? u[2 * t + 1] : xin[t];
+            yo[t] = u[(t & 1) + 2 + 4 * (t >> 1)];
+            zo[t] = u[t + 4];
+        }
+#pragma unroll
+        for (int n = 0; n < 8; ++n) stw[n] = u[n ^ M];
+        // the staged psi of the 16 pencils: LDS operations of one wave execute
+        // in order, so the reads below see this step's writes
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const bool ok = (unsigned)(s - wsk[it]) < (unsigned)len;
+            const piece_t<T> v = *reinterpret_cast<const lds_piece_t<T>*>(as_lds(stg) + woff[it]);
+            buf_store_piece<T, 2>(rpsi, ok ? wofs[it] + (unsigned)(s * wsb) : kOOB, v);
+        }
+        // face outflow: far-side lanes into the face area (after this step's
+        // reads of it), one piece per lane out
+        if (jy == 3) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) fa[ypos + t] = yo[t];
+        }
+        if (kz == 3) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) fa[zpos + t] = zo[t];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const piece_t<T> fo = *reinterpret_cast<const lds_piece_t<T>*>(fa + lane * CH);
+        buf_store_piece<T, 0>(rf, fout_off(s), fo);
+        __builtin_amdgcn_wave_barrier();
+    };
+    Src s0, s1;
+    fetch(-skew, s0);
+    // The pieces of steps 0 and 1, each followed by PAD stores with offset
+    // kOOB (dropped by the range check).  The wait for a piece inside the
+    // loop is set for every way into it, the first turn included, so the
+    // pieces loaded here must be followed by at least as many operations as
+    // in the loop (a step issues NIT psi stores, one face store and, FP32, its
+    // three source loads); otherwise every step would wait for the previous
+    // step's stores.  The scheduling barriers keep this order.
+    constexpr int PAD = NIT + 4;
+    piece_t<T> f0 = buf_load_piece<T>(rf, fin_off(0));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < PAD; ++i) buf_store_piece<T, 0>(rf, kOOB + 16u * i, piece_t<T>{});
+    __builtin_amdgcn_sched_barrier(0);
+    piece_t<T> f1 = buf_load_piece<T>(rf, fin_off(1));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < PAD; ++i) buf_store_piece<T, 0>(rf, kOOB + 16u * (PAD + i), piece_t<T>{});
+    __builtin_amdgcn_sched_barrier(0);
+    // an even number of steps, so that the loop has no exit between its two
+    // steps (such an exit makes the wait at the top of the loop cover every
+    // store again); the extra step, when there is one, has every lane
+    // outside its row and stores nothing
+    const int nsteps2 = (nsteps + 1) & ~1;
+    for (int s = 0; s < nsteps2; s += 2) {
+        step(s, f0, s0, s1);
+        step(s + 1, f1, s1, s0);
+    }
+    if (pen && I + 1 < nTx) store4(xd + (((long)(I + 1) * nz + kl) * ny + jl) * 4, xin[0], xin[1], xin[2], xin[3]);
+}
+
 // blockIdx.x: tile of the plane; blockIdx.y: reflection class; wave w of the
 // block: direction group w of that class (four directions, -1 = unused slot).
 // The waves of a block read the same cells' source and sigma_t, which one
@@ -952,7 +1263,7 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
 // the default schedule for four or more waves; FP64 16.0 -> 15.7 ms against
 // two waves per SIMD.
 constexpr int PSI3D_WAVES = 3;
-template <typename T>
+template <typename T, bool BUF>
 __global__ void __launch_bounds__(384) __attribute__((amdgpu_waves_per_eu(PSI3D_WAVES, PSI3D_WAVES)))
 sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const DirInfo* __restrict__ dirs, int transpose,
@@ -963,9 +1274,11 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       long ystride, T* __restrict__ zf, long zstride, int TX,
                                                       int nTx, int nTy, int nTz, const int* __restrict__ tiles,
                                                       T* __restrict__ psi) {
-    __shared__ __align__(16) T stage[6][16 * 4 * 8];
+    __shared__ __align__(16) T stage[6][stage_elems<T>()];
     __shared__ __align__(16) TileIn<T> tin;
-    const int wave = threadIdx.x >> 6;
+    // (wave-uniform for the compiler, so that the group's values below and
+    // the buffer resources built from them live in scalar registers)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int tile = tiles[blockIdx.x];
     const int I = tile & 1023, J = (tile >> 10) & 1023, K = (tile >> 20) & 1023;
@@ -981,14 +1294,14 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
     const int grp = cls * groups_per_class + wave;
     const int* gi = groups + 6 * grp;
     const int d = gi[lane >> 4];
-    const int m0 = gi[0];            // first direction of the group (-1: empty slot)
+    const int m0 = __builtin_amdgcn_readfirstlane(gi[0]);  // first direction of the group (-1: empty slot)
     if (m0 < 0) return;              // empty group slot: the whole wave leaves
     // consecutive directions d0 .. d0 + nvalid - 1 of psi: psi goes out
     // through the LDS stage; otherwise (nvalid = 0) every lane stores its own
     // values.  With local, psi holds only this class's directions, in group
     // order (group w, slot k -> 4 w + k), which are always consecutive.
-    const int d0 = local ? 4 * wave : gi[4];
-    const int nvalid = local ? gi[5] : (gi[4] >= 0 ? gi[5] : 0);
+    const int d0 = __builtin_amdgcn_readfirstlane(local ? 4 * wave : gi[4]);
+    const int nvalid = __builtin_amdgcn_readfirstlane(local ? gi[5] : (gi[4] >= 0 ? gi[5] : 0));
     const bool dok = d >= 0;
     const int dd = dok ? d : m0;
     const int dpsi = local ? 4 * wave + (lane >> 4) : dd;
@@ -997,6 +1310,43 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
     T* xd = xf + dd * xstride;
     T* yd = yf + dd * ystride;
     T* zd = zf + dd * zstride;
+    if constexpr (BUF) {
+        // wave-uniform resources: the faces from the group's first direction's
+        // face block (the group's directions are consecutive; the y and z
+        // regions of a block start yf - xf and zf - xf elements in), psi from
+        // the tile's lowest cell in memory and the wave's first psi direction
+        __shared__ __align__(16) T fstage[6][face_stage_elems<T>()];
+        const int i0 = I * TX, len = min(TX, nx - i0);
+        const int rxm = m & 1, rym = (m >> 1) & 1, rzm = (m >> 2) & 1;
+        const int jn = min(J * 4 + 4, ny) - J * 4, kn = min(K * 4 + 4, nz) - K * 4;
+        const long imin = rxm ? nx - i0 - len : i0;
+        const long jmin = rym ? ny - J * 4 - jn : J * 4;
+        const long kmin = rzm ? nz - K * 4 - kn : K * 4;
+        const long cell_base = (kmin * ny + jmin) * nx + imin;
+        const __amdgpu_buffer_rsrc_t rf = buf_rsrc(xf + (long)m0 * xstride);
+        const __amdgpu_buffer_rsrc_t rpsi = buf_rsrc(psi + (cell_base * pstride + d0) * 8);
+        const unsigned slots = (unsigned)__builtin_amdgcn_readfirstlane(
+            (gi[0] >= 0 ? 1 : 0) | (gi[1] >= 0 ? 2 : 0) | (gi[2] >= 0 ? 4 : 0) | (gi[3] >= 0 ? 8 : 0));
+        const long yoff = (long)(yf - xf), zoff = (long)(zf - xf);
+#define SN_CASEB(MM)                                                                                               \
+    case MM:                                                                                                       \
+        sweep3d_body_buf<T, MM>(nx, ny, nz, pstride, slots, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, \
+                                src, xd, rf, xstride, yoff, zoff, rpsi, cell_base, nvalid, stage[wave],            \
+                                fstage[wave]);                                                                     \
+        break;
+        switch (m) {
+            SN_CASEB(0)
+            SN_CASEB(1)
+            SN_CASEB(2)
+            SN_CASEB(3)
+            SN_CASEB(4)
+            SN_CASEB(5)
+            SN_CASEB(6)
+            SN_CASEB(7)
+        }
+#undef SN_CASEB
+        return;
+    }
 #define SN_CASE(MM)                                                                                               \
     case MM:                                                                                                      \
         sweep3d_body<T, MM>(nx, ny, nz, pstride, dpsi, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt,   \
@@ -1138,10 +1488,16 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
     }
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
-        hipLaunchKernelGGL((sweep3d_kernel<T>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st, g.nx,
-                           g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first, pp.pstride,
-                           pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
-                           tiles + plane_off[p], psi);
+        if (g.buf)
+            hipLaunchKernelGGL((sweep3d_kernel<T, true>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st,
+                               g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first,
+                               pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX,
+                               g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
+        else
+            hipLaunchKernelGGL((sweep3d_kernel<T, false>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st,
+                               g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first,
+                               pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX,
+                               g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
