@@ -76,6 +76,7 @@ struct sn_context {
     long nbf = 0;
     double eta = 1.0;
     hipStream_t stream = nullptr;
+    StreamSplit split{};  // 3D full sweeps: reflection classes over split.n streams (st[0] = stream)
     std::vector<DirInfo> hdirs;
     std::vector<double> hw, omega;
     DevBuf<double> wn;
@@ -195,9 +196,8 @@ long inflow_size(const sn_mesh* m) {
     return 4L * ((long)m->ny * m->nz + (long)m->nx * m->nz + (long)m->nx * m->ny);
 }
 
-// The sweep's face buffers.  3D: one block per direction holding its x, y
-// and z regions (at 0, yoff and zoff; xstride = ystride = zstride = the block
-// size), all in xf; 2D: x and y in their own buffers.
+// The sweep's face buffers.  3D: x faces per direction in xf, the y/z face
+// slots of every direction group and tile in yf; 2D: x and y per direction.
 template <typename T>
 struct Faces {
     T *x, *y, *z;
@@ -208,7 +208,9 @@ int face_views(sn_context* ctx, DevBuf<T>& xf, DevBuf<T>& yf, DevBuf<T>& zf, Fac
     int rc;
     if (g.dim == 3) {
         if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
-        *f = Faces<T>{xf.p, xf.p + g.yoff, xf.p + g.zoff};
+        if ((rc = yf.ensure((size_t)yz_face_elems(g.nclasses * g.groups_per_class, g.nTx, g.nTy, g.nTz, g.TX))))
+            return rc;
+        *f = Faces<T>{xf.p, yf.p, nullptr};
         return 0;
     }
     if ((rc = xf.ensure((size_t)g.xstride * g.ndirs))) return rc;
@@ -269,7 +271,7 @@ int sweep_impl(sn_context* ctx, const double* phi, const double* phi_prev, const
     size_t e0 = 0, e1 = 0;
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_sweep<T>(g, ctx->dirs.p, transpose, sweep_sig, sweep_src, f.x, f.y, f.z, ctx->tiles.p,
-                           ctx->plane_off.data(), psi, sink.p, ctx->stream, part));
+                           ctx->plane_off.data(), psi, sink.p, ctx->stream, part, &ctx->split));
     if (!part) ++ctx->sweeps;
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
@@ -319,7 +321,7 @@ int sweep_flux3d_impl(sn_context* ctx, const double* phi, const double* phi_prev
     if (ctx->timing && (rc = record_event(ctx, &e0))) return rc;
     HIPCHK(launch_sweep_flux3d<T>(g, ctx->dirs.p, ctx->w.p, transpose, sigt, src.p, f.x, f.y, f.z, ctx->tiles.p,
                                   ctx->plane_off.data(), ctx->phioct.p, phi_out, accumulate, res_ref, ctx->fpart.p,
-                                  ctx->stream));
+                                  ctx->stream, &ctx->split));
     ++ctx->sweeps;
     if (ctx->timing) {
         if ((rc = record_event(ctx, &e1))) return rc;
@@ -748,6 +750,14 @@ void sn_context_destroy(sn_context* ctx) {
     for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
     if (ctx->res_ev) (void)hipEventDestroy(ctx->res_ev);
     if (ctx->cg_ev) (void)hipEventDestroy(ctx->cg_ev);
+    for (int k = 1; k < MAX_SPLIT; ++k) {
+        if (ctx->split.st[k]) {
+            (void)hipStreamSynchronize(ctx->split.st[k]);
+            (void)hipStreamDestroy(ctx->split.st[k]);
+        }
+        if (ctx->split.join[k]) (void)hipEventDestroy(ctx->split.join[k]);
+    }
+    if (ctx->split.fork) (void)hipEventDestroy(ctx->split.fork);
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     ctx->fpart.release();
     ctx->evpool.clear();
@@ -921,7 +931,6 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.xstride = (long)mesh->ny * 2;
         g.ystride = (long)g.nchunk * mesh->nx * 2;
         g.zstride = 0;
-        g.yoff = g.zoff = 0;
         g.TX = 0;
         g.nTx = g.nTy = g.nTz = 0;
         g.nplanes = 0;
@@ -997,10 +1006,8 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
             return fail(SN_ERR_UNSUPPORTED, "more than 1023 sweep tiles along an axis");
         g.nplanes = g.nTx + g.nTy + g.nTz - 2;
         g.nchunk = 0;
-        // a direction's face block: x, y and z regions of every tile row
-        g.yoff = (long)g.nTx * mesh->nz * mesh->ny * 4;
-        g.zoff = g.yoff + (long)g.nTy * mesh->nz * mesh->nx * 4;
-        g.xstride = g.ystride = g.zstride = g.zoff + (long)g.nTz * mesh->ny * mesh->nx * 4;
+        g.xstride = (long)g.nTx * mesh->nz * mesh->ny * 4;  // y and z: tile slots (yz_face_elems)
+        g.ystride = g.zstride = 0;
         std::vector<int> tl;
         c->plane_off.assign(1, 0);
         for (int p = 0; p < g.nplanes; ++p) {
@@ -1054,19 +1061,17 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         g.groups_per_class = gpc;
         g.groups = c->groups.p;
         // the psi sweep without branches around memory operations needs each
-        // direction group consecutive (one face resource per wave) and byte
-        // offsets below 2^31 from a tile's lowest cell and within four
-        // directions' face blocks (FP64 bounds, which cover FP32);
-        // SN_SWEEP_BUF=0 selects the other variant
+        // direction group consecutive (one psi resource per wave) and byte
+        // offsets below 2^31 from a tile's lowest cell (FP64 bounds, which
+        // cover FP32); SN_SWEEP_BUF=0 selects the other variant
         {
             bool consec = true;
             for (size_t e = 0; e + 5 < gr.size(); e += 6)
                 if (gr[e + 5] > 0 && gr[e + 4] < 0) consec = false;
             const double lim = 2147483648.0 - 4096.0;
             const double psi_span = ((3.0 * mesh->ny + 3.0) * mesh->nx + g.TX) * c->ndirs * 64.0 + 4096.0;
-            const double face_span = 4.0 * (double)g.xstride * 8.0;
             const char* e = std::getenv("SN_SWEEP_BUF");
-            g.buf = consec && psi_span < lim && face_span < lim && !(e && std::atoi(e) == 0);
+            g.buf = consec && psi_span < lim && !(e && std::atoi(e) == 0);
         }
     }
 
@@ -1168,6 +1173,21 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
     c->noalloc_err = noalloc_scratch(&c->noalloc);
     HIPCHK(hipEventCreateWithFlags(&c->res_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->cg_ev, hipEventDisableTiming));
+    // 3D: the reflection classes of a full sweep split over up to four streams
+    // of default priority (SN_SWEEP_STREAMS, 1 = the caller's stream only)
+    c->split.n = 1;
+    c->split.st[0] = c->stream;
+    if (dim == 3 && c->sg.nclasses > 1) {
+        int ns = SPLIT_DEFAULT;
+        if (const char* e = std::getenv("SN_SWEEP_STREAMS")) ns = std::atoi(e);
+        ns = std::max(1, std::min(std::min(ns, MAX_SPLIT), c->sg.nclasses));
+        if (ns > 1) HIPCHK(hipEventCreateWithFlags(&c->split.fork, hipEventDisableTiming));
+        for (int k = 1; k < ns; ++k) {
+            HIPCHK(hipStreamCreateWithFlags(&c->split.st[k], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->split.join[k], hipEventDisableTiming));
+        }
+        c->split.n = ns;
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     *out = c.release();
     return SN_OK;

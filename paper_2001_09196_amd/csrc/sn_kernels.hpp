@@ -27,11 +27,10 @@ struct SweepGeom {
     int nplanes;       // 3D tile-diagonal planes
     int buf;           // 3D psi sweep: the variant without branches around memory operations (buffer loads
                        //     and stores with range-checked offsets); needs every direction group consecutive
-                       //     and the byte offsets of one tile's psi and of four directions' face blocks below 2^31
+                       //     and the byte offsets of one tile's psi below 2^31
     int nchunk;        // 2D row chunks of at most ROWS2D rows
-    long xstride, ystride, zstride;  // per-direction face-buffer strides (elements); 3D: all three are the size
-                                     // of a direction's face block, whose y and z regions start at yoff and zoff
-    long yoff, zoff;
+    long xstride, ystride, zstride;  // per-direction face-buffer sizes (elements); 3D: x only (y and z faces
+                                     // are kept in tile slots, yz_face_elems)
 };
 
 template <typename T>
@@ -44,6 +43,36 @@ hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transp
 // directions order2d[0 .. count - 1].  psi: [cell][pstride][nn]; local = 0:
 // a direction's global index, local = 1: its position in the part (3D:
 // 4 * group + slot within its class).
+// 3D y and z face data, in tile slots: for direction group g (class * groups
+// per class + wave) and tile t = (I nTy + J) nTz + K, TX + 3 slots of
+// YZ_SLOT values.  Slot q holds, for the group's four direction slots kd and
+// the four positions kq across the face, the four y-face values (first half,
+// [kd][kq][4]) and z-face values (second half) entering the cell at position
+// q - kq of the tile along x (kq: the kz of a y face, the jy of a z face).
+// The upstream tile writes slot q of its downstream neighbour at step q + 3
+// of its sweep and the tile reads it at step q, so a wave's face data of one
+// step is contiguous.  Faces on the domain boundary (J = 0 for y, K = 0 for z)
+// hold the inflow.  x faces: per direction, [I][kl][jl][4] in the reflected
+// frame.
+constexpr int YZ_SLOT = 128;
+inline long yz_face_elems(int ngroups, int nTx, int nTy, int nTz, int TX) {
+    return (long)ngroups * nTx * nTy * nTz * (TX + 3) * YZ_SLOT;
+}
+
+// Streams over which the reflection classes of a full 3D sweep are split: the
+// classes [k ncls / n, (k + 1) ncls / n) go to st[k], and the plane launches
+// are issued plane by plane across the streams, so that a class group starts
+// its next plane as soon as its own launch is done instead of waiting for the
+// slowest tile of every class.  st[0] is the caller's stream; the others wait
+// for an event recorded on it before the sweep, and it waits for theirs after
+// (classes touch disjoint psi and face data).  n = 1: st[0] only.
+constexpr int MAX_SPLIT = 4;
+constexpr int SPLIT_DEFAULT = 2;
+struct StreamSplit {
+    int n;
+    hipStream_t st[MAX_SPLIT];
+    hipEvent_t fork, join[MAX_SPLIT];
+};
 struct SweepPart {
     int first, count, pstride, local;
     const int* order2d;
@@ -51,7 +80,7 @@ struct SweepPart {
 template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st,
-                        const SweepPart* part = nullptr);
+                        const SweepPart* part = nullptr, const StreamSplit* split = nullptr);
 inline long sink_elems(const SweepGeom&) { return 1; }
 // 3D fused sweep + moment (source iteration): psi is not stored; phioct
 // (workspace [nclasses][ncells][8]) receives each octant's share of phi, then
@@ -65,7 +94,8 @@ template <typename T>
 hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
                                const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
                                const int* plane_off, double* phioct, double* phi, int accumulate,
-                               const double* ref, double* part, hipStream_t st);
+                               const double* ref, double* part, hipStream_t st,
+                               const StreamSplit* split = nullptr);
 // per-cell array [ncells][nn] -> four quadrant diagonal-major arrays
 // [4][ceil(ny / 64)][nx + 63][64][nn] (2D sweep input layout)
 template <typename T>

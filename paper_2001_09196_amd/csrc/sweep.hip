@@ -55,7 +55,7 @@ __global__ void init_faces_kernel(int dim, int nx, int ny, int nz, int ndirs, co
                                   long zstride) {
     const int F = dim == 2 ? 2 : 4;
     const long nxf = (long)ny * nz, nyf = (long)nx * nz, nzf = (long)nx * ny;
-    const long per = (nxf + nyf + (dim == 3 ? nzf : 0));
+    const long per = dim == 3 ? nxf : nxf + nyf;  // 3D: x faces only (y and z: init_yz_faces_kernel)
     long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     long total = per * ndirs;
     for (; idx < total; idx += (long)gridDim.x * blockDim.x) {
@@ -91,6 +91,70 @@ __global__ void init_faces_kernel(int dim, int nx, int ny, int nz, int ndirs, co
                 zf[d * zstride + g * 4 + t] = T(v);
             }
         }
+    }
+}
+
+// The boundary face slots of the 3D y and z faces (yface_slot layout): the y
+// half of every tile with J = 0 and the z half of every tile with K = 0, from
+// the inflow (zero where inflow is null, the direction slot is empty or the
+// position lies outside the tile or the mesh).
+template <typename T>
+__global__ void init_yz_faces_kernel(int nx, int ny, int nz, int TX, int nTx, int nTy, int nTz, int ngroups,
+                                     const int* __restrict__ groups, const DirInfo* __restrict__ dirs, int transpose,
+                                     const double* __restrict__ inflow, long nbf, T* __restrict__ yz) {
+    const long nxf = (long)ny * nz, nyf = (long)nx * nz;
+    const int slots = TX + 3;
+    const long side_y = (long)nTx * nTz, side_z = (long)nTx * nTy;  // boundary tiles per group
+    const long per_group = (side_y + side_z) * slots * 64;
+    const long total = per_group * ngroups;
+    const long ntiles = (long)nTx * nTy * nTz;
+    for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+        const int g = (int)(idx / per_group);
+        long r = idx - (long)g * per_group;
+        const int v = (int)(r & 63);
+        r >>= 6;
+        const int q = (int)(r % slots);
+        const long bt = r / slots;
+        const bool yside = bt < side_y;
+        int I, J, K;
+        if (yside) {
+            I = (int)(bt / nTz);
+            K = (int)(bt % nTz);
+            J = 0;
+        } else {
+            I = (int)((bt - side_y) / nTy);
+            J = (int)((bt - side_y) % nTy);
+            K = 0;
+        }
+        const int kd = v >> 4, kq = (v >> 2) & 3, t = v & 3;
+        const int d = groups[6 * g + kd];
+        const int i0 = I * TX, len = min(TX, nx - i0);
+        const int ir = q - kq;
+        double val = 0.0;
+        if (inflow && d >= 0 && ir >= 0 && ir < len) {
+            const DirInfo di = dirs[d];
+            const int rx = di.rx ^ transpose, ry = di.ry ^ transpose, rz = di.rz ^ transpose;
+            const int il = i0 + ir;
+            const int i = rx ? nx - 1 - il : il;
+            const double* in = inflow + (long)d * nbf;
+            if (yside) {
+                const int kl = K * 4 + kq;
+                if (kl < nz) {
+                    const int k = rz ? nz - 1 - kl : kl;
+                    const int a = (t & 1) ^ rx, c = ((t >> 1) & 1) ^ rz;
+                    val = in[nxf * 4 + ((long)k * nx + i) * 4 + a + 2 * c];
+                }
+            } else {
+                const int jl = J * 4 + kq;
+                if (jl < ny) {
+                    const int j = ry ? ny - 1 - jl : jl;
+                    const int a = (t & 1) ^ rx, b = ((t >> 1) & 1) ^ ry;
+                    val = in[(nxf + nyf) * 4 + ((long)j * nx + i) * 4 + a + 2 * b];
+                }
+            }
+        }
+        const long tl = ((long)I * nTy + J) * nTz + K;
+        yz[(((long)g * ntiles + tl) * slots + q) * YZ_SLOT + (yside ? 0 : YZ_SLOT / 2) + v] = T(val);
     }
 }
 
@@ -697,8 +761,7 @@ template <typename T, int M, bool FUSED = false>
 __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, bool dok, T ax, T ay, T az,
                                              int I, int J, int K, int TX, int nTx, int nTy, int nTz,
                                              const TileIn<T>* tin, const T* __restrict__ sigt,
-                                             const T* __restrict__ src, T* __restrict__ xf, T* __restrict__ yf,
-                                             T* __restrict__ zf,
+                                             const T* __restrict__ src, T* __restrict__ xf, T* __restrict__ yzt,
                                              T* __restrict__ psi, int d0, int nvalid, T* __restrict__ stg,
                                              double wgt = 0.0, double* __restrict__ red = nullptr,
                                              double* __restrict__ phio = nullptr, int nwaves = 0) {
@@ -736,8 +799,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     const long c0 = rowbase + (rx ? nx - 1 - i0 : i0);
     const T* src0 = src + c0 * 8;
     const T* sig0 = sigt + c0;
-    const T* yin0 = yf + (((long)J * nz + kl) * nx + i0) * 4;
-    const T* zin0 = zf + (((long)K * ny + jl) * nx + i0) * 4;
+    // y/z face inflow of the lane's cell at position ir of its pencil: slot
+    // ir + kz (y) or ir + jy (z) of the tile's face slots (yface_slot)
+    const int kd = lane >> 4;
+    const T* yin0 = yzt + kz * YZ_SLOT + (kd * 4 + kz) * 4;
+    const T* zin0 = yzt + jy * YZ_SLOT + YZ_SLOT / 2 + (kd * 4 + jy) * 4;
     // The source, sigma_t and the y/z face inflow of the next cell are loaded
     // one step ahead.  The face values of this tile were written by earlier
     // launches (the upwind tiles) and no tile of this launch writes them, so
@@ -754,11 +820,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             v.sig = tsig[irc * 16];
         }
         if (pen && jy == 0)
-            v.y = load4(yin0 + irc * 4);
+            v.y = load4(yin0 + irc * YZ_SLOT);
         else
             v.y = Vec4<T>{};
         if (pen && kz == 0)
-            v.z = load4(zin0 + irc * 4);
+            v.z = load4(zin0 + irc * YZ_SLOT);
         else
             v.z = Vec4<T>{};
     };
@@ -767,8 +833,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     const bool ystore = pen && jy == 3 && J + 1 < nTy;
     const bool zstore = pen && kz == 3 && K + 1 < nTz;
     const bool xstore = pen && I + 1 < nTx;
-    T* yout0 = yf + (((long)(J + 1) * nz + kl) * nx + i0 - skew) * 4;
-    T* zout0 = zf + (((long)(K + 1) * ny + jl) * nx + i0 - skew) * 4;
+    // outflow at step s into slot s - 3 of the downstream tiles (J + 1: nTz
+    // tiles on, K + 1: the next tile); the pointers are formed at step 0 and
+    // used from step 3 on
+    T* yout0 = yzt + ((long)nTz * (TX + 3) - 3) * YZ_SLOT + (kd * 4 + kz) * 4;
+    T* zout0 = yzt + ((long)(TX + 3) - 3) * YZ_SLOT + YZ_SLOT / 2 + (kd * 4 + jy) * 4;
     T* xout = xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4;
     // psi write-out through the LDS stage (nvalid > 0): pass it of the wave
     // covers the 64 consecutive 16-byte pieces it * 64 + lane of the 16
@@ -883,8 +952,8 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 store4(pp, o[0], o[1], o[2], o[3]);
                 store4(pp + 4, o[4], o[5], o[6], o[7]);
             }
-            if (ystore) store4(yout0 + s * 4, yo[0], yo[1], yo[2], yo[3]);
-            if (zstore) store4(zout0 + s * 4, zo[0], zo[1], zo[2], zo[3]);
+            if (ystore) store4(yout0 + s * YZ_SLOT, yo[0], yo[1], yo[2], yo[3]);
+            if (zstore) store4(zout0 + s * YZ_SLOT, zo[0], zo[1], zo[2], zo[3]);
             if (xstore && ir == len - 1) store4(xout, xin[0], xin[1], xin[2], xin[3]);
         }
         if constexpr (FUSED) {
@@ -1038,8 +1107,8 @@ __device__ __forceinline__ void sweep3d_body_buf(int nx, int ny, int nz, int pst
                                                  T ay, T az, int I, int J, int K, int TX, int nTx, int nTy, int nTz,
                                                  const TileIn<T>* tin, const T* __restrict__ sigt,
                                                  const T* __restrict__ src, T* __restrict__ xd,
-                                                 __amdgpu_buffer_rsrc_t rf, long fstride, long yoff, long zoff,
-                                                 __amdgpu_buffer_rsrc_t rpsi, long cell_base, int nvalid,
+                                                 __amdgpu_buffer_rsrc_t rf, __amdgpu_buffer_rsrc_t rpsi,
+                                                 long cell_base, int nvalid,
                                                  T* __restrict__ stg, T* __restrict__ fstg) {
     constexpr int rx = M & 1, ry = (M >> 1) & 1, rz = (M >> 2) & 1;
     constexpr int sz = (int)sizeof(T);
@@ -1084,19 +1153,20 @@ __device__ __forceinline__ void sweep3d_body_buf(int nx, int ny, int nz, int pst
     const bool fslot = (isy || isz) && ((slots >> (fk & 3)) & 1u);
     const bool fin_ok = fslot && (isy ? K * 4 + fq < nz : J * 4 + fq < ny);
     const bool fout_ok = fslot && (isy ? (J + 1 < nTy && K * 4 + fq < nz) : (K + 1 < nTz && J * 4 + fq < ny));
-    const long frow_in = isy ? yoff + (((long)J * nz + K * 4 + fq) * nx + i0) * 4
-                             : zoff + (((long)K * ny + J * 4 + fq) * nx + i0) * 4;
-    const long frow_out = isy ? yoff + (((long)(J + 1) * nz + K * 4 + fq) * nx + i0) * 4
-                              : zoff + (((long)(K + 1) * ny + J * 4 + fq) * nx + i0) * 4;
-    const unsigned fin0 = (unsigned)(((long)fk * fstride + frow_in + fh * CH) * sz);
-    const unsigned fout0 = (unsigned)(((long)fk * fstride + frow_out + fh * CH) * sz);
+    // Face slots (yface_slot): the receiving lane takes slot s at step s, and
+    // the sending lane writes slot s - 3 of the downstream tile (J + 1: nTz
+    // tiles on, K + 1: the next tile) at step s; piece `lane` of a slot is
+    // this lane's piece.  Offsets in bytes from the tile's first slot.
+    constexpr unsigned SLOTB = YZ_SLOT * sz;
+    const unsigned fin0 = (unsigned)lane * 16u;
+    const unsigned fout0 = (unsigned)((isy ? nTz : 1) * (TX + 3) - 3) * SLOTB + (unsigned)lane * 16u;
     auto fin_off = [&](int s) {
         const int ir = s - fq;
-        return (fin_ok && (unsigned)ir < (unsigned)len) ? fin0 + (unsigned)(ir * 4 * sz) : kOOB;
+        return (fin_ok && (unsigned)ir < (unsigned)len) ? fin0 + (unsigned)s * SLOTB : kOOB;
     };
     auto fout_off = [&](int s) {
         const int ir = s - fq - 3;
-        return (fout_ok && (unsigned)ir < (unsigned)len) ? fout0 + (unsigned)(ir * 4 * sz) : kOOB;
+        return (fout_ok && (unsigned)ir < (unsigned)len) ? fout0 + (unsigned)s * SLOTB : kOOB;
     };
     // this lane's four y- and z-face values in the face area
     lds_t<T>* fa = as_lds(fstg);
@@ -1270,8 +1340,7 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
                                                       const int* __restrict__ groups, int groups_per_class,
                                                       int cls0, int pstride, int local,
                                                       const T* __restrict__ sigt, const T* __restrict__ src,
-                                                      T* __restrict__ xf, long xstride, T* __restrict__ yf,
-                                                      long ystride, T* __restrict__ zf, long zstride, int TX,
+                                                      T* __restrict__ xf, long xstride, T* __restrict__ yz, int TX,
                                                       int nTx, int nTy, int nTz, const int* __restrict__ tiles,
                                                       T* __restrict__ psi) {
     __shared__ __align__(16) T stage[6][stage_elems<T>()];
@@ -1308,13 +1377,12 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
     const DirInfo di = dirs[dd];
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
     T* xd = xf + dd * xstride;
-    T* yd = yf + dd * ystride;
-    T* zd = zf + dd * zstride;
+    // this group's face slots of this tile
+    T* yzt = yz + ((long)grp * nTx * nTy * nTz + ((long)I * nTy + J) * nTz + K) * (TX + 3) * YZ_SLOT;
     if constexpr (BUF) {
-        // wave-uniform resources: the faces from the group's first direction's
-        // face block (the group's directions are consecutive; the y and z
-        // regions of a block start yf - xf and zf - xf elements in), psi from
-        // the tile's lowest cell in memory and the wave's first psi direction
+        // wave-uniform resources: the group's face slots of the tile, psi
+        // from the tile's lowest cell in memory and the wave's first psi
+        // direction
         __shared__ __align__(16) T fstage[6][face_stage_elems<T>()];
         const int i0 = I * TX, len = min(TX, nx - i0);
         const int rxm = m & 1, rym = (m >> 1) & 1, rzm = (m >> 2) & 1;
@@ -1323,15 +1391,14 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
         const long jmin = rym ? ny - J * 4 - jn : J * 4;
         const long kmin = rzm ? nz - K * 4 - kn : K * 4;
         const long cell_base = (kmin * ny + jmin) * nx + imin;
-        const __amdgpu_buffer_rsrc_t rf = buf_rsrc(xf + (long)m0 * xstride);
+        const __amdgpu_buffer_rsrc_t rf = buf_rsrc(yzt);
         const __amdgpu_buffer_rsrc_t rpsi = buf_rsrc(psi + (cell_base * pstride + d0) * 8);
         const unsigned slots = (unsigned)__builtin_amdgcn_readfirstlane(
             (gi[0] >= 0 ? 1 : 0) | (gi[1] >= 0 ? 2 : 0) | (gi[2] >= 0 ? 4 : 0) | (gi[3] >= 0 ? 8 : 0));
-        const long yoff = (long)(yf - xf), zoff = (long)(zf - xf);
 #define SN_CASEB(MM)                                                                                               \
     case MM:                                                                                                       \
         sweep3d_body_buf<T, MM>(nx, ny, nz, pstride, slots, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, \
-                                src, xd, rf, xstride, yoff, zoff, rpsi, cell_base, nvalid, stage[wave],            \
+                                src, xd, rf, rpsi, cell_base, nvalid, stage[wave],                                 \
                                 fstage[wave]);                                                                     \
         break;
         switch (m) {
@@ -1350,7 +1417,7 @@ sweep3d_kernel(int nx, int ny, int nz, int ndirs,
 #define SN_CASE(MM)                                                                                               \
     case MM:                                                                                                      \
         sweep3d_body<T, MM>(nx, ny, nz, pstride, dpsi, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt,   \
-                            src, xd, yd, zd, psi, d0, nvalid, stage[wave]);                                       \
+                            src, xd, yzt, psi, d0, nvalid, stage[wave]);                                          \
         break;
     switch (m) {
         SN_CASE(0)
@@ -1374,19 +1441,20 @@ template <typename T>
 __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int nz, int ndirs,
                                                            const DirInfo* __restrict__ dirs, const double* __restrict__ w,
                                                            int transpose, const int* __restrict__ groups,
-                                                           int groups_per_class, const T* __restrict__ sigt,
+                                                           int groups_per_class, int cls0,
+                                                           const T* __restrict__ sigt,
                                                            const T* __restrict__ src, T* __restrict__ xf, long xstride,
-                                                           T* __restrict__ yf, long ystride, T* __restrict__ zf,
-                                                           long zstride, int TX, int nTx, int nTy, int nTz,
+                                                           T* __restrict__ yz, int TX, int nTx, int nTy, int nTz,
                                                            const int* __restrict__ tiles, double* __restrict__ phioct) {
     __shared__ __align__(16) double red[2 * RF * 6 * 128];
     __shared__ __align__(16) TileIn<T> tin;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int grp = blockIdx.y * groups_per_class + wave;
+    const int cls = cls0 + (int)blockIdx.y;
+    const int grp = cls * groups_per_class + wave;
     const int* gi = groups + 6 * grp;
     const int d = gi[lane >> 4];
-    const int mc = groups[6 * blockIdx.y * groups_per_class];  // first direction of the class (valid)
+    const int mc = groups[6 * cls * groups_per_class];  // first direction of the class (valid)
     const bool dok = d >= 0;
     const int dd = dok ? d : mc;
     const int tile = tiles[blockIdx.x];
@@ -1401,13 +1469,12 @@ __global__ void __launch_bounds__(384) sweep3d_flux_kernel(int nx, int ny, int n
     const T ax = T(di.ax), ay = T(di.ay), az = T(di.az);
     const double wgt = dok ? w[dd] : 0.0;
     T* xd = xf + dd * xstride;
-    T* yd = yf + dd * ystride;
-    T* zd = zf + dd * zstride;
-    double* po = phioct + (long)blockIdx.y * nx * ny * nz * 8;
+    T* yzt = yz + ((long)grp * nTx * nTy * nTz + ((long)I * nTy + J) * nTz + K) * (TX + 3) * YZ_SLOT;
+    double* po = phioct + (long)cls * nx * ny * nz * 8;
 #define SN_CASEF(MM)                                                                                             \
     case MM:                                                                                                     \
         sweep3d_body<T, MM, true>(nx, ny, nz, ndirs, dd, dok, ax, ay, az, I, J, K, TX, nTx, nTy, nTz, &tin, sigt, \
-                                  src, xd, yd, zd, nullptr, -1, 0, nullptr, wgt, red, po, groups_per_class);     \
+                                  src, xd, yzt, nullptr, -1, 0, nullptr, wgt, red, po, groups_per_class);         \
         break;
     switch (m) {
         SN_CASEF(0)
@@ -1456,21 +1523,47 @@ __global__ void __launch_bounds__(256) octant_sum_kernel(long n, int ncls, const
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// the streams st[1..ns) of a split start after the work queued so far on st[0]
+static hipError_t split_fork(const StreamSplit& sp, int ns) {
+    hipError_t e = hipEventRecord(sp.fork, sp.st[0]);
+    for (int k = 1; k < ns && e == hipSuccess; ++k) e = hipStreamWaitEvent(sp.st[k], sp.fork, 0);
+    return e;
+}
+// st[0] continues after the work queued on st[1..ns)
+static hipError_t split_join(const StreamSplit& sp, int ns) {
+    hipError_t e = hipSuccess;
+    for (int k = 1; k < ns && e == hipSuccess; ++k) {
+        e = hipEventRecord(sp.join[k], sp.st[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sp.st[0], sp.join[k], 0);
+    }
+    return e;
+}
+
 template <typename T>
 hipError_t launch_init_faces(const SweepGeom& g, const DirInfo* dirs, int transpose, const double* inflow,
                              T* xf, T* yf, T* zf, hipStream_t st) {
-    long per = (long)g.ny * g.nz + (long)g.nx * g.nz + (g.dim == 3 ? (long)g.nx * g.ny : 0);
+    long per = (long)g.ny * g.nz + (g.dim == 3 ? 0 : (long)g.nx * g.nz);
     long total = per * g.ndirs;
     int blocks = (int)std::min<long>((total + 255) / 256, 65536);
     hipLaunchKernelGGL(init_faces_kernel<T>, dim3(blocks), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz, g.ndirs, dirs,
                        transpose, inflow, g.nbf, xf, g.xstride, yf, g.ystride, zf, g.zstride);
+    if (g.dim == 3) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int ngroups = g.nclasses * g.groups_per_class;
+        const long ny_t = (long)ngroups * ((long)g.nTx * g.nTz + (long)g.nTx * g.nTy) * (g.TX + 3) * 64;
+        const int yb = (int)std::min<long>((ny_t + 255) / 256, 65536);
+        // yf: the y/z face slots
+        hipLaunchKernelGGL(init_yz_faces_kernel<T>, dim3(yb), dim3(256), 0, st, g.nx, g.ny, g.nz, g.TX, g.nTx, g.nTy,
+                           g.nTz, ngroups, g.groups, dirs, transpose, inflow, g.nbf, yf);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, const T* sigt, const T* src, T* xf,
                         T* yf, T* zf, const int* tiles, const int* plane_off, T* psi, T* sink, hipStream_t st,
-                        const SweepPart* part) {
+                        const SweepPart* part, const StreamSplit* split) {
     const SweepPart all{0, g.dim == 2 ? g.ndirs : g.nclasses, g.ndirs, 0, g.groups};
     const SweepPart& pp = part ? *part : all;
     if (g.dim == 2) {
@@ -1486,21 +1579,29 @@ hipError_t launch_sweep(const SweepGeom& g, const DirInfo* dirs, int transpose, 
         }
         return hipSuccess;
     }
+    // a class split over several streams only for full sweeps
+    const int ns = (!part && split) ? std::min(split->n, pp.count) : 1;
+    hipError_t e;
+    if (ns > 1 && (e = split_fork(*split, ns)) != hipSuccess) return e;
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
-        if (g.buf)
-            hipLaunchKernelGGL((sweep3d_kernel<T, true>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st,
-                               g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first,
-                               pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX,
-                               g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
-        else
-            hipLaunchKernelGGL((sweep3d_kernel<T, false>), dim3(nt, pp.count), dim3(64 * g.groups_per_class), 0, st,
-                               g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, pp.first,
-                               pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX,
-                               g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int k = 0; k < ns; ++k) {
+            const int c0 = pp.first + k * pp.count / ns, c1 = pp.first + (k + 1) * pp.count / ns;
+            hipStream_t sk = ns > 1 ? split->st[k] : st;
+            if (g.buf)
+                hipLaunchKernelGGL((sweep3d_kernel<T, true>), dim3(nt, c1 - c0), dim3(64 * g.groups_per_class), 0,
+                                   sk, g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, c0,
+                                   pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.TX,
+                                   g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
+            else
+                hipLaunchKernelGGL((sweep3d_kernel<T, false>), dim3(nt, c1 - c0), dim3(64 * g.groups_per_class), 0,
+                                   sk, g.nx, g.ny, g.nz, g.ndirs, dirs, transpose, g.groups, g.groups_per_class, c0,
+                                   pp.pstride, pp.local, sigt, src, xf, g.xstride, yf, g.TX,
+                                   g.nTx, g.nTy, g.nTz, tiles + plane_off[p], psi);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
+    if (ns > 1) return split_join(*split, ns);
     return hipSuccess;
 }
 
@@ -1540,16 +1641,22 @@ template <typename T>
 hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const double* w, int transpose,
                                const T* sigt, const T* src, T* xf, T* yf, T* zf, const int* tiles,
                                const int* plane_off, double* phioct, double* phi, int accumulate,
-                               const double* ref, double* part, hipStream_t st) {
+                               const double* ref, double* part, hipStream_t st, const StreamSplit* split) {
+    const int ns = split ? std::min(split->n, g.nclasses) : 1;
+    hipError_t e;
+    if (ns > 1 && (e = split_fork(*split, ns)) != hipSuccess) return e;
     for (int p = 0; p < g.nplanes; ++p) {
         int nt = plane_off[p + 1] - plane_off[p];
-        hipLaunchKernelGGL((sweep3d_flux_kernel<T>), dim3(nt, g.nclasses), dim3(64 * g.groups_per_class), 0, st,
-                           g.nx, g.ny, g.nz, g.ndirs, dirs, w, transpose, g.groups, g.groups_per_class, sigt, src,
-                           xf, g.xstride, yf, g.ystride, zf, g.zstride, g.TX, g.nTx, g.nTy, g.nTz,
-                           tiles + plane_off[p], phioct);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int k = 0; k < ns; ++k) {
+            const int c0 = k * g.nclasses / ns, c1 = (k + 1) * g.nclasses / ns;
+            hipLaunchKernelGGL((sweep3d_flux_kernel<T>), dim3(nt, c1 - c0), dim3(64 * g.groups_per_class), 0,
+                               ns > 1 ? split->st[k] : st, g.nx, g.ny, g.nz, g.ndirs, dirs, w, transpose, g.groups,
+                               g.groups_per_class, c0, sigt, src, xf, g.xstride, yf, g.TX,
+                               g.nTx, g.nTy, g.nTz, tiles + plane_off[p], phioct);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
+    if (ns > 1 && (e = split_join(*split, ns)) != hipSuccess) return e;
     const long nc = (long)g.nx * g.ny * g.nz, n = nc * 8;
     const int blocks = octant_sum_blocks(nc);
     if (ref)
@@ -1562,10 +1669,12 @@ hipError_t launch_sweep_flux3d(const SweepGeom& g, const DirInfo* dirs, const do
 }
 template hipError_t launch_sweep_flux3d<double>(const SweepGeom&, const DirInfo*, const double*, int, const double*,
                                                 const double*, double*, double*, double*, const int*, const int*,
-                                                double*, double*, int, const double*, double*, hipStream_t);
+                                                double*, double*, int, const double*, double*, hipStream_t,
+                                                const StreamSplit*);
 template hipError_t launch_sweep_flux3d<float>(const SweepGeom&, const DirInfo*, const double*, int, const float*,
                                                const float*, float*, float*, float*, const int*, const int*,
-                                               double*, double*, int, const double*, double*, hipStream_t);
+                                               double*, double*, int, const double*, double*, hipStream_t,
+                                               const StreamSplit*);
 
 template hipError_t launch_init_faces<double>(const SweepGeom&, const DirInfo*, int, const double*, double*, double*,
                                               double*, hipStream_t);
@@ -1573,9 +1682,9 @@ template hipError_t launch_init_faces<float>(const SweepGeom&, const DirInfo*, i
                                              float*, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepGeom&, const DirInfo*, int, const double*, const double*,
                                          double*, double*, double*, const int*, const int*, double*, double*,
-                                         hipStream_t, const SweepPart*);
+                                         hipStream_t, const SweepPart*, const StreamSplit*);
 template hipError_t launch_sweep<float>(const SweepGeom&, const DirInfo*, int, const float*, const float*, float*,
                                         float*, float*, const int*, const int*, float*, float*, hipStream_t,
-                                        const SweepPart*);
+                                        const SweepPart*, const StreamSplit*);
 
 }  // namespace sn
