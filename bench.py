@@ -414,6 +414,8 @@ def main():
     # ---- c1: iteration counts of the forms, both DSA masses ----
     w1 = Workload("c1")
     c1 = {"workload": "c1: 2D 16^2, S4 (12 dirs), thick block + void"}
+    wl, kl = sweep_grind(w1, SN_FP64, 50, 5)
+    c1["sweep_fp64"] = {"ms": wl, "kernels_ms": kl, "grind_ns": wl * 1e6 / w1.cd}
     ref1 = None
     if not args.no_cpu_baseline:
         ro1 = oracle.source_iterate(w1.p, tol=1e-13, max_it=3000, use_dsa=True, cg_rtol=1e-13)
@@ -443,11 +445,16 @@ def main():
 
     # ---- c4: adjoint gradient of the corner detector ----
     out["c4"] = bench_adjoint_c4(log)
+    w4 = Workload("c4")
+    for name, prec in (("fp64", SN_FP64), ("fp32", SN_FP32)):
+        wl, kl = sweep_grind(w4, prec, 20, 3)
+        out["c4"][f"sweep_{name}"] = {"ms": wl, "kernels_ms": kl, "grind_ns": wl * 1e6 / w4.cd}
+    w4.close()
 
     # ---- CPU oracle: bounded samples on the host cores ----
     if not args.no_cpu_baseline:
         nth = oracle.num_threads()
-        s5 = oracle_sweep_sample(sninputs_config("c5"), 32)
+        s5 = oracle_sweep_sample(sninputs_config("c5"), 168)
         out["cpu_baseline"] = {"value": s5["ns_per_cell_dir"], "unit": "ns/(cell*dir)", "cores": nth,
                                "kind": "oracle",
                                "sample": f"c5 psi-writing sweep of {s5['directions']} of the 168 directions "
@@ -458,6 +465,10 @@ def main():
                                                       "c3": oracle_sweep_sample(sninputs_config("c3"), 8)[
                                                           "ns_per_cell_dir"],
                                                       "c2": oracle_sweep_sample(sninputs_config("c2"), 40)[
+                                                          "ns_per_cell_dir"],
+                                                      "c4": oracle_sweep_sample(sninputs_config("c4"), 40)[
+                                                          "ns_per_cell_dir"],
+                                                      "c1": oracle_sweep_sample(sninputs_config("c1"), 12)[
                                                           "ns_per_cell_dir"]},
                                "time_to_1e-8_s": {"c1": c1["oracle_to_1e-8"]["seconds"],
                                                   "c2": out["c2"].get("oracle_to_1e-8", {}).get("seconds")}}

@@ -12,6 +12,13 @@
   python profile_summary.py traffic_per_call <calls> <key> ... (as traffic)
       the same for kernels launched several times per call: the counters of all
       dispatches summed and divided by the number of calls.
+  python profile_summary.py spans <dir> <kernel-substring> <launches-per-call> <out.txt>
+      appends to out.txt, from the *_kernel_trace.csv of the same run, the time from the
+      first start to the last end of each call's launches of one kernel (the launches of a
+      call may run on several streams at once), their summed durations and the queues used.
+  python profile_summary.py counters <kernel-substring> <out.txt> <dir>[,<dir>...] <command...>
+      every counter of the `rocprofv3 --pmc` runs in the listed directories for one
+      kernel, averaged per dispatch.
 """
 from __future__ import annotations
 
@@ -98,10 +105,50 @@ def traffic(key, kernel, fdir, wdir, cfdir, cwdir, copy_bytes, out, jpath, comma
     json.dump(data, open(jpath, "w"), indent=1)
 
 
+def spans(d, kernel, per_call, out):
+    rows = [r for r in csv.DictReader(open(_one(os.path.join(d, "**", "*kernel_trace.csv"))))
+            if kernel in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    per_call = int(per_call)
+    lines = ["", f"# per call of {kernel} ({per_call} launches each, in launch order)",
+             f"{'call':>5s} {'first start -> last end ms':>27s} {'summed durations ms':>20s} {'queues':>7s}"]
+    for c in range(len(rows) // per_call):
+        g = rows[c * per_call:(c + 1) * per_call]
+        t0 = min(int(r["Start_Timestamp"]) for r in g)
+        t1 = max(int(r["End_Timestamp"]) for r in g)
+        tot = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in g)
+        nq = len({r["Queue_Id"] for r in g})
+        lines.append(f"{c:5d} {(t1 - t0) / 1e6:27.3f} {tot / 1e6:20.3f} {nq:7d}")
+    open(out, "a").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counters(kernel, out, dirs, command):
+    lines = [f"# rocprofv3 counters of {kernel}, averaged per dispatch", f"# commands: {command}",
+             f"# kernel source sha256 {kernel_source_sha()} (sweep.hip, sn_device.hpp, sn_kernels.hpp, build.py)", ""]
+    for d in dirs.split(","):
+        vals, disp = {}, {}
+        for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            c = r["Counter_Name"]
+            vals[c] = vals.get(c, 0.0) + float(r["Counter_Value"])
+            disp.setdefault(c, set()).add(r["Dispatch_Id"])
+        for c in sorted(vals):
+            lines.append(f"{os.path.basename(d.rstrip('/')):10s} {c:36s} {vals[c] / len(disp[c]):16.0f} "
+                         f"per dispatch ({len(disp[c])} dispatches)")
+    open(out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if a and a[0] == "stats":
         stats(a[1], a[2], " ".join(a[3:]))
+    elif a and a[0] == "spans":
+        spans(a[1], a[2], a[3], a[4])
+    elif a and a[0] == "counters":
+        counters(a[1], a[2], a[3], " ".join(a[4:]))
     elif a and a[0] == "traffic":
         traffic(*a[1:10], " ".join(a[10:]))
     elif a and a[0] == "traffic_per_call":

@@ -111,6 +111,28 @@ def test_sweep3d_tile_lengths(tx, prec, monkeypatch):
         assert rel_l2(got["phi"], ref["phi"]) <= 1e-10
 
 
+@pytest.mark.parametrize("variant", ["branching", "one_stream"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep3d_variants(variant, prec, monkeypatch):
+    """The 3D psi sweep's other paths against the oracle: the body with
+    per-lane branches around its memory operations (SN_SWEEP_BUF=0; the
+    library takes it when a tile's psi offsets exceed 2^31 bytes or a
+    direction group is not consecutive), and all reflection classes on the
+    caller's stream (SN_SWEEP_STREAMS=1), with inflow and transposed."""
+    if variant == "branching":
+        monkeypatch.setenv("SN_SWEEP_BUF", "0")
+    else:
+        monkeypatch.setenv("SN_SWEEP_STREAMS", "1")
+    for transpose in (False, True):
+        p = random_problem(3, 70, 19, 11, order=4, seed=90 + prec + 2 * transpose)
+        got, ref = _sweep_case(p, transpose, with_inflow=True, prec=prec)
+        assert rel_max(got, ref) <= (1e-12 if prec == 0 else 2e-5)
+    p = random_problem(3, 40, 9, 7, order=4, seed=95)
+    ref = oracle.source_iterate(p, tol=0.0, max_it=3, use_dsa=True, cg_rtol=1e-13)
+    got = _si_gpu(p, tol=0.0, max_it=3, use_dsa=True, cg_rtol=1e-13, cg_maxit=5000, prec=prec)
+    assert rel_l2(got["phi"], ref["phi"]) <= (1e-10 if prec == 0 else 2e-5)
+
+
 def test_sweep_vacuum_null_inputs():
     from paper_2001_09196_amd import sn_sweep
     p = random_problem(2, 20, 70, 1, seed=4)
