@@ -269,6 +269,7 @@ def main():
     ap.add_argument("--sweeps-only", type=int, default=0, metavar="N",
                     help="only run N sweeps of --config in --prec (for rocprofv3 counter passes)")
     ap.add_argument("--config", default="c5", help="workload of --sweeps-only (c1..c5)")
+    ap.add_argument("--pipe-only", action="store_true", help="only the crooked-pipe scan")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"), help="sweep precision of --sweeps-only")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -284,6 +285,10 @@ def main():
 
     from paper_2001_09196_amd import SN_FP32, SN_FP64, sn_sweep
     torch.cuda.set_device(0)
+
+    if args.pipe_only:
+        print(json.dumps(bench_pipe(log)), flush=True)
+        return
 
     if args.sweeps_only:
         w = Workload(args.config)
@@ -443,6 +448,9 @@ def main():
     out["c1"] = c1
     log(f"c1: {json.dumps({k: v['iters'] for k, v in c1.items() if isinstance(v, dict) and 'iters' in v})}")
 
+    # ---- crooked-pipe stand-in: heterogeneous against full DSA ----
+    out["crooked_pipe"] = bench_pipe(log)
+
     # ---- c4: adjoint gradient of the corner detector ----
     out["c4"] = bench_adjoint_c4(log)
     w4 = Workload("c4")
@@ -479,6 +487,79 @@ def main():
 def sninputs_config(name):
     import sninputs
     return sninputs.config(name)
+
+
+# Table crookedpipe1 (order-2 rows): GMRES(30) iterations to 1e-12 with full DSA (NIP, mNIP) and the
+# heterogeneous DSA (NIP), per problem and c dt ("sa0": sigma_a = 0); context only (other discretisation,
+# DSA inverted exactly, CPU cluster)
+PAPER_PIPE = {1: {"1": (19, 56, 15), "1e3": (31, 120, 25), "1e8": (34, 123, 25), "sa0": (34, 153, 25)},
+              2: {"1": (18, 41, 15), "1e3": (25, 61, 25), "1e8": (25, 64, 25), "sa0": (25, 94, 25)},
+              3: {"1": (16, 41, 13), "1e3": (23, 96, 20), "1e8": (28, 98, 21), "sa0": (24, 128, 21)},
+              4: {"1": (19, 58, 15), "1e3": (26, 132, 22), "1e8": (116, 134, 22), "sa0": (119, 164, 22)},
+              5: {"1": (20, 44, 15), "1e3": (102, 143, 25), "1e8": (134, 147, 25), "sa0": (None, 177, 25)}}
+
+
+def bench_pipe(log, budget_s=150.0):
+    """Crooked-pipe stand-in (Sec. 4.1; geometry of sninputs.pipe_regions at
+    the paper's 0.5-unit cells, S8): iterations of GMRES(30) to 1e-12 (the
+    paper's protocol) and of source iteration to 1e-8 (problems only), with the heterogeneous
+    DSA (eta = 1) and with full DSA (eta = 0, every cell in the diffusion
+    solve), for the five problems of Table problems at c dt = 1, 1e3, 1e8 and
+    without absorption, and the two-region scan of sigma_pipe (everything
+    else 200, c dt = 1000).  Both DSA forms use the sigma_t mass of Alg. 2 and
+    block-Jacobi CG to 1e-10.  "DNC": not converged in the iteration cap."""
+    import dataclasses
+
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import Context, sn_krylov_solve, sn_source_iterate
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    out = {"workload": "crooked-pipe stand-in: 2D 28x20 cells of 0.5, S8 (40 dirs), regions pipe/wall/edge/block "
+                       "with the area shares of the paper's Table problems; q = 1 in the pipe inlet; vacuum",
+           "kmax_gmres": 200, "kmax_si": 600, "problems": {}, "sigma_pipe_scan": {}, "paper_order2": PAPER_PIPE}
+
+    def run(p, si=True):
+        t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+        res = {}
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta) as ctx:
+            q = t(p.q)
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
+            rk = sn_krylov_solve(ctx, q, None, phi, tol=1e-12, max_it=200, restart=30, use_dsa=True,
+                                 cg_rtol=1e-10, cg_maxit=20000, mass_kind=1)
+            res["gmres30_to_1e-12"] = rk["iters"] if rk["rc"] == 0 else "DNC"
+            res["cg_iters_per_dsa_gmres"] = float(np.mean(rk["cg_hist"])) if rk["iters"] else 0.0
+            res["seconds"] = rk["seconds"]
+            if si:
+                phi.zero_()
+                rs = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=600, use_dsa=True, cg_rtol=1e-10,
+                                       cg_maxit=20000, mass_kind=1)
+                res["si_to_1e-8"] = rs["iters"] if rs["rc"] == 0 else "DNC"
+                res["seconds"] += rs["seconds"]
+        return res
+
+    import numpy as np
+    for k in sorted(sninputs.PIPE_PROBLEMS):
+        for label, cdt in (("1", 1.0), ("1e3", 1e3), ("1e8", 1e8), ("sa0", None)):
+            if time.perf_counter() - t_start > budget_s:
+                out["truncated"] = True
+                break
+            base = sninputs.crooked_pipe(k, cdt, cells_per_unit=2)
+            row = {"thick_share": float(base.thick_mask(1.0).mean())}
+            for name, eta in (("het_dsa", 1.0), ("full_dsa", 0.0)):
+                row[name] = run(dataclasses.replace(base, eta=eta))
+            out["problems"][f"#{k} cdt={label}"] = row
+    for sp in (0.0, 1e-3, 0.1, 1.0, 5.0, 10.0, 100.0):
+        if time.perf_counter() - t_start > budget_s:
+            out["truncated"] = True
+            break
+        base = sninputs.crooked_pipe((sp, 200.0, 200.0, 200.0), 1e3, cells_per_unit=2)
+        out["sigma_pipe_scan"][str(sp)] = {name: run(dataclasses.replace(base, eta=eta), si=False)
+                                           for name, eta in (("het_dsa", 1.0), ("full_dsa", 0.0))}
+    out["seconds"] = time.perf_counter() - t_start
+    log(f"crooked pipe: {json.dumps({k: (v['het_dsa']['gmres30_to_1e-12'], v['full_dsa']['gmres30_to_1e-12']) for k, v in out['problems'].items()})}")
+    return out
 
 
 def bench_adjoint_c4(log):

@@ -28,6 +28,7 @@ import numpy as np
 __all__ = [
     "level_symmetric", "Problem", "config", "CONFIG_NAMES", "tile_materials",
     "inflow_size", "unit_inflow_on_face", "patch_source", "fd_cells",
+    "crooked_pipe", "PIPE_PROBLEMS", "pipe_regions",
 ]
 
 # First level cosine of the level-symmetric LQ_N sets.  S4 follows from the
@@ -227,6 +228,67 @@ def config(name: str) -> Problem:
         return Problem(name, 3, n, n, n, (1.0, 1.0, 1.0), st, ss, q, om, w,
                        meta={"tile": tile, "kind": kind})
     raise ValueError(f"unknown config {name!r}")
+
+
+# Scattering cross sections (pipe, wall, edge, block) of the five heterogeneous
+# crooked-pipe problems of Sec. 4.1 (Table problems).
+PIPE_PROBLEMS = {
+    1: (1e-3, 500.0, 1e-4, 100.0),
+    2: (0.1, 200.0, 200.0, 5.0),
+    3: (1e-4, 10.0, 500.0, 0.1),
+    4: (1e-6, 0.1, 100.0, 1000.0),
+    5: (1e-4, 10.0, 500.0, 100.0),
+}
+PIPE_REGIONS = ("pipe", "wall", "edge", "block")
+
+
+def pipe_regions(nx: int, ny: int, h: float) -> np.ndarray:
+    """Region index per cell (0 pipe, 1 wall, 2 edge, 3 block) of a synthetic
+    crooked-pipe geometry on [0, 14] x [0, 10].  The paper's geometry exists
+    only as a figure; this stand-in has its four kinds of region with the area
+    shares implied by its thin/thick percentages at eta = 1 (pipe 32%, wall
+    about 37%, edge 25%, block 7%):
+
+    * pipe: a channel of width 2 entering at x = 0 (y in [1.5, 3.5]), rising
+      at x in [2, 4] to y in [6, 8], crossing to x = 12, falling at x in
+      [10, 12] to y in [2.5, 4.5] and leaving at x = 14 (44 of 140 units^2);
+    * edge: the bands y < 1.25 and y > 8.75 along the bottom and top;
+    * block: the rectangle [5, 9] x [3, 5.5] inside the bend;
+    * wall: the rest.
+    Cell centres decide the region."""
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    reg = np.ones((ny, nx), dtype=np.int8)
+    reg[(Y < 1.25) | (Y > 8.75)] = 2
+    reg[(X > 5.0) & (X < 9.0) & (Y > 3.0) & (Y < 5.5)] = 3
+    inside = lambda x0, x1, y0, y1: (X > x0) & (X < x1) & (Y > y0) & (Y < y1)
+    pipe = (inside(0.0, 4.0, 1.5, 3.5) | inside(2.0, 4.0, 1.5, 8.0) | inside(2.0, 12.0, 6.0, 8.0) |
+            inside(10.0, 12.0, 2.5, 8.0) | inside(10.0, 14.0, 2.5, 4.5))
+    reg[pipe] = 0
+    return reg.ravel()
+
+
+def crooked_pipe(sigmas, cdt: Optional[float], cells_per_unit: int = 8, order: int = 8,
+                 name: str = "pipe") -> Problem:
+    """A crooked-pipe problem (Sec. 4.1): sigma_s piecewise constant over the
+    regions of pipe_regions, sigma_t = sigma_s + 1/cdt (cdt None: no
+    absorption, sigma_t = sigma_s), S_N of the given order in 2D, vacuum
+    boundaries, unit isotropic source in the pipe cells of the inlet unit
+    (x < 1).  sigmas: (pipe, wall, edge, block), or a problem number of
+    PIPE_PROBLEMS."""
+    if isinstance(sigmas, int):
+        sigmas = PIPE_PROBLEMS[sigmas]
+    h = 1.0 / cells_per_unit
+    nx, ny = 14 * cells_per_unit, 10 * cells_per_unit
+    reg = pipe_regions(nx, ny, h)
+    ss = np.asarray(sigmas, dtype=np.float64)[reg]
+    st = ss + (0.0 if cdt is None else 1.0 / cdt)
+    xc = (np.arange(nx * ny) % nx + 0.5) * h
+    q = ((reg == 0) & (xc < 1.0)).astype(np.float64)
+    om, w = level_symmetric(order, 2)
+    return Problem(name, 2, nx, ny, 1, (h, h, h), st, ss, q, om, w,
+                   meta={"regions": reg, "sigmas": tuple(sigmas), "cdt": cdt})
 
 
 def inflow_size(dim: int, nx: int, ny: int, nz: int) -> int:

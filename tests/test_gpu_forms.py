@@ -123,6 +123,36 @@ def test_krylov_vs_oracle(case, use_dsa, form, restart):
     assert abs(rc["iters"] - conv["iters"]) <= 2
 
 
+@pytest.mark.parametrize("k,cdt", [(5, 1e3), (2, 1.0)])
+def test_crooked_pipe_het_and_full_dsa(k, cdt):
+    """The crooked-pipe stand-in of Sec. 4.1 (Table problems #5 and #2, S8,
+    the paper's 0.5-unit cells): three source iterations with the
+    heterogeneous DSA (eta = 1) and with full DSA (eta = 0: every cell in the
+    diffusion solve, defined here since no cell is void), and twelve GMRES
+    iterations with each, all with the CG at 1e-13, against the oracle."""
+    import dataclasses
+
+    from paper_2001_09196_amd import sn_krylov_solve, sn_source_iterate
+    base = sninputs.crooked_pipe(k, cdt, cells_per_unit=2)
+    for eta in (1.0, 0.0):
+        p = dataclasses.replace(base, eta=eta)
+        say(f"crooked pipe #{k} cdt={cdt} eta={eta}")
+        ref = oracle.source_iterate(p, tol=0.0, max_it=3, use_dsa=True, cg_rtol=1e-13)
+        refk = oracle.gmres(p, tol=0.0, max_it=12, restart=30, use_dsa=True, cg_rtol=1e-13)
+        with context(p) as ctx:
+            phi = _zeros(p)
+            r = sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=3, use_dsa=True, cg_rtol=1e-13,
+                                  cg_maxit=100000)
+            e_si = rel_l2(phi.cpu().numpy(), ref["phi"])
+            phi = _zeros(p)
+            rk = sn_krylov_solve(ctx, dev(p.q), None, phi, tol=0.0, max_it=12, restart=30, use_dsa=True,
+                                 cg_rtol=1e-13, cg_maxit=100000)
+            e_k = rel_l2(phi.cpu().numpy(), refk["phi"])
+        say(f"  SI {e_si:.2e} (CG {list(r['cg_hist'])}), GMRES {e_k:.2e}")
+        assert r["iters"] == 3 and rk["iters"] == 12
+        assert e_si <= 1e-10 and e_k <= 1e-9
+
+
 @pytest.mark.parametrize("dim,shape", [(2, (19, 13, 1)), (3, (11, 8, 6))])
 def test_octant_adjoint_vs_full_psi_and_oracle(dim, shape):
     """sn_adjoint_gradient (psi regenerated one octant at a time) against the
