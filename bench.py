@@ -35,6 +35,13 @@ METRIC = "sweep grind time ns/(cell·dir) + time-to-1e-8, FP32 vs FP64 sweep, 1 
 # (the paper's inner tolerance, 1e-4, is reported beside it on c2 and c5)
 CG_RTOL = 1e-2
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# FP64 operations per cell and direction of the 3D sweeps as compiled for gfx950 (FMA counted as two): the
+# fast-diagonalisation cell solve with its one reciprocal, the inflow face terms, and in the fused source-iteration
+# kernel the weighted moment w_d psi and its sum over a wave's four directions.  Counted from the step loop of
+# `hipcc -S` (per two steps: psi kernel 79 FMA, 32 mul, 18 add, 1 rcp per step; fused 158 FMA, 80 mul, 50 add,
+# 2 rcp per two steps).
+SWEEP3D_FLOPS = {"psi": 208, "fused": 224}
 GOLD = os.path.join(ROOT, "tests", "golden")
 
 
@@ -320,7 +327,10 @@ def main():
     c5 = {"workload": "c5: 3D 128^3 Q1-DG, S12 (168 dirs), seeded 16^3 tiles", "cells": w5.nc, "dirs": w5.D,
           "thick_cells": w5.ctx.thick_count,
           "sweep_fp64": {"ms": wall64, "kernels_ms": kern64, "grind_ns": value,
-                         "hbm_frac": roofline["frac"]},
+                         "hbm_frac": roofline["frac"],
+                         "fp64_TFLOPs": SWEEP3D_FLOPS["psi"] * w5.cd / (kern64 * 1e-3) / 1e12,
+                         "fp64_vector_frac": SWEEP3D_FLOPS["psi"] * w5.cd / (kern64 * 1e-3) / 1e12 /
+                         FP64_VECTOR_PEAK_TFLOPS},
           "sweep_fp32": {"ms": wall32, "kernels_ms": kern32, "grind_ns": wall32 * 1e6 / w5.cd,
                          "achieved_GBs": bytes32 / (kern32 * 1e-3) / 1e9,
                          "hbm_frac": bytes32 / (kern32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -354,6 +364,13 @@ def main():
     c5["si_step_fp64"] = si_step(w5, SN_FP64)
     c5["si_step_fp32_plain"] = si_step(w5, SN_FP32)
     c5["si_step_fp64"]["grind_ns"] = c5["si_step_fp64"]["ms_per_step"] * 1e6 / w5.cd
+    # the fused sweep + moment is not HBM-bound: its FP64 work against the vector peak
+    fk = c5["si_step_fp64"]["sweep_kernels_ms"]
+    c5["fused_sweep_fp64_alu"] = {
+        "kernel": "sweep3d_flux_kernel<double>", "bound": "alu", "unit": "TFLOP/s",
+        "flops_per_cell_dir": SWEEP3D_FLOPS["fused"],
+        "achieved": SWEEP3D_FLOPS["fused"] * w5.cd / (fk * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS}
+    c5["fused_sweep_fp64_alu"]["frac"] = c5["fused_sweep_fp64_alu"]["achieved"] / FP64_VECTOR_PEAK_TFLOPS
     log(f"c5 SI step: fp64 {c5['si_step_fp64']['ms_per_step']:.2f} ms "
         f"(fused sweep {c5['si_step_fp64']['sweep_kernels_ms']:.2f}, dsa {c5['si_step_fp64']['dsa_ms']:.2f})")
     c5["dsa_preconditioners"] = {}
