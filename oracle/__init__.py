@@ -64,17 +64,18 @@ def lib():
             L.orc_sweep.restype = ctypes.c_int
             L.orc_moment.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp]
             L.orc_dsa_correct.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
-                                          _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _ip, _dp]
+                                          ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp, _ip, _dp]
             L.orc_dsa_correct.restype = ctypes.c_int
-            L.orc_dsa_dense.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double, _dp, _lp, _ip]
+            L.orc_dsa_dense.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp,
+                                        _lp, _ip]
             L.orc_dsa_dense.restype = ctypes.c_int
             L.orc_source_iterate.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
-                                             ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp,
                                              _ip, _ip]
             L.orc_source_iterate.restype = ctypes.c_int
             L.orc_gmres.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp, _ip, _ip]
             L.orc_gmres.restype = ctypes.c_int
             L.orc_gradient.argtypes = [mp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -140,8 +141,13 @@ def moment(p, psi):
     return phi.reshape(p.ncells, p.nn)
 
 
+# diffusion forms of the DSA (Sec. 3.1): eq. SIP, eq. NIP, and NIP with the
+# penalty of eq. ModifiedF0
+DSA_SIP, DSA_NIP, DSA_MNIP = 0, 1, 2
+
+
 def dsa_correct(p, phi_old, phi_si, eta=None, mass_kind=0, cg_rtol=1e-13, cg_maxit=100000,
-                sigma_t=None, sigma_s=None):
+                sigma_t=None, sigma_s=None, dsa_op=DSA_SIP):
     st = _f64(p.sigma_t if sigma_t is None else sigma_t)
     ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
     out = np.zeros(p.ncells * p.nn)
@@ -149,7 +155,7 @@ def dsa_correct(p, phi_old, phi_si, eta=None, mass_kind=0, cg_rtol=1e-13, cg_max
     rr = ctypes.c_double(0.0)
     m = _mesh(p)
     rc = lib().orc_dsa_correct(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss),
-                               float(p.eta if eta is None else eta), int(mass_kind),
+                               float(p.eta if eta is None else eta), int(mass_kind), int(dsa_op),
                                _d(_f64(phi_old).ravel()), _d(_f64(phi_si).ravel()), float(cg_rtol),
                                int(cg_maxit), _d(out), ctypes.byref(it), ctypes.byref(rr))
     if rc:
@@ -157,7 +163,7 @@ def dsa_correct(p, phi_old, phi_si, eta=None, mass_kind=0, cg_rtol=1e-13, cg_max
     return out.reshape(p.ncells, p.nn), it.value, rr.value
 
 
-def dsa_dense(p, eta=None, sigma_t=None, sigma_s=None):
+def dsa_dense(p, eta=None, sigma_t=None, sigma_s=None, dsa_op=DSA_SIP):
     """Dense D_ff and the thick cell list (small problems only)."""
     st = _f64(p.sigma_t if sigma_t is None else sigma_t)
     ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
@@ -169,7 +175,7 @@ def dsa_dense(p, eta=None, sigma_t=None, sigma_s=None):
     nt = ctypes.c_int(0)
     m = _mesh(p)
     rc = lib().orc_dsa_dense(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss), e,
-                             _d(D), cells.ctypes.data_as(_lp), ctypes.byref(nt))
+                             int(dsa_op), _d(D), cells.ctypes.data_as(_lp), ctypes.byref(nt))
     if rc:
         raise RuntimeError(f"orc_dsa_dense failed ({rc})")
     return D[:nf * nf].reshape(nf, nf), cells[:nt.value]
@@ -177,9 +183,10 @@ def dsa_dense(p, eta=None, sigma_t=None, sigma_s=None):
 
 def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=1e-13, cg_maxit=100000,
                    transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None,
-                   dsa_form=0):
+                   dsa_form=0, dsa_op=DSA_SIP):
     """Returns dict(phi [nc, nn], iters, res_hist, cg_hist, rc).
-    dsa_form: 0 diagonal heterogeneous DSA (Alg. 2), 1 triangular (Alg. 1)."""
+    dsa_form: 0 diagonal heterogeneous DSA (Alg. 2), 1 triangular (Alg. 1);
+    dsa_op: the diffusion form (DSA_SIP by CG, DSA_NIP / DSA_MNIP by GMRES)."""
     st = _f64(p.sigma_t if sigma_t is None else sigma_t)
     ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
     qq = _f64(p.q if q is None else q)
@@ -190,7 +197,8 @@ def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=
     m = _mesh(p)
     rc = lib().orc_source_iterate(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss),
                                   _d(qq), _d(_f64(inflow)), float(p.eta if eta is None else eta),
-                                  int(bool(use_dsa)), int(mass_kind), float(tol), int(max_it), float(cg_rtol),
+                                  int(bool(use_dsa)), int(mass_kind), int(dsa_op), float(tol), int(max_it),
+                                  float(cg_rtol),
                                   int(cg_maxit), int(bool(transpose)), int(dsa_form), _d(phi), _d(res),
                                   cgh.ctypes.data_as(_ip), ctypes.byref(iters))
     if rc not in (0, 5, 6):
@@ -200,7 +208,8 @@ def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=
 
 
 def gmres(p, tol=1e-8, max_it=1000, restart=30, use_dsa=True, dsa_form=0, mass_kind=0, cg_rtol=1e-13,
-          cg_maxit=100000, transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None):
+          cg_maxit=100000, transpose=False, phi0=None, q=None, inflow=None, eta=None, sigma_t=None, sigma_s=None,
+          dsa_op=DSA_SIP):
     """Flexible GMRES(restart) on S phi = b, right-preconditioned by the
     heterogeneous DSA.  Returns dict(phi, iters, res_hist, cg_hist, rc);
     an iteration is one application of S (one sweep)."""
@@ -214,7 +223,8 @@ def gmres(p, tol=1e-8, max_it=1000, restart=30, use_dsa=True, dsa_form=0, mass_k
     m = _mesh(p)
     rc = lib().orc_gmres(ctypes.byref(m), p.ndirs, _d(_f64(p.omega)), _d(_f64(p.w)), _d(st), _d(ss), _d(qq),
                          _d(_f64(inflow)), float(p.eta if eta is None else eta), int(bool(use_dsa)), int(mass_kind),
-                         int(dsa_form), float(tol), int(max_it), int(restart), float(cg_rtol), int(cg_maxit),
+                         int(dsa_op), int(dsa_form), float(tol), int(max_it), int(restart), float(cg_rtol),
+                         int(cg_maxit),
                          int(bool(transpose)), _d(phi), _d(res), cgh.ctypes.data_as(_ip), ctypes.byref(iters))
     if rc not in (0, 5, 6):
         raise RuntimeError(f"orc_gmres failed ({rc})")

@@ -45,6 +45,11 @@
  *       (applied to a vector v as to a residual: v + P_T D_ff^{-1} Sigma_f
  *       R_T v).  The residual ||b - S phi|| / ||b|| is the same quantity as
  *       the source-iteration residual of (7).
+ *   (10) the nonsymmetric forms of Sec. 3.1 (dsa_op): NIP (eq. NIP) drops
+ *       the face term -int [[u]]{D dv/dn} of (5), mNIP also replaces the
+ *       penalty by the modified one of eq. ModifiedF0 (C = 0.1, p = 1, h the
+ *       cell size across the face).  Both take the paper's penalty alone,
+ *       without the 8 D/h floor of (5), and are solved by GMRES instead of CG.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -434,6 +439,7 @@ static int transport_update(const orc_mesh *m, int ndirs, const double *omega, c
  * (s, s) and (s, neighbour slot) for each thick face neighbour. */
 typedef struct {
     int nn, nthick, nb;          /* nb = 1 + 2*dim blocks per row */
+    int op;                      /* 0 SIP, 1 NIP, 2 mNIP (eq. SIP, eq. NIP, eq. ModifiedF0) */
     long *cell;                  /* slot -> cell */
     int *col;                    /* [nthick][nb] neighbour slot or -1 */
     double *blk;                 /* [nthick][nb][nn][nn] */
@@ -457,15 +463,32 @@ static double *blockp(dsa_mat *A, int s, int b) {
     return A->blk + ((size_t)s * A->nb + b) * A->nn * A->nn;
 }
 
-/* Assemble the thick-cell SIP matrix (eq. SIP at eps = 1, principal submatrix).
+/* mNIP penalty factor of one side of a face (eq. ModifiedF0 for linear
+ * elements: c(p) = C p (p+1) with C = 0.1, p = 1), h the cell size across
+ * the face */
+static double mnip_factor(double sigma_t, double h) {
+    double f = 0.2 / (sigma_t * h);
+    return f > 1.0 ? f : 1.0;
+}
+
+/* Assemble the thick-cell diffusion matrix (principal submatrix, Sec. 3.2) of
+ * one of the forms of Sec. 3.1 at eps = 1:
  * Cell terms: D int grad u . grad v + sigma_a int u v, D = 1/(3 sigma_t).
  * Interior face between K- (low) and K+ (high) along axis a, normal +e_a:
- *   -int {D du/dn}[[v]] - int [[u]]{D dv/dn} + kappa int [[u]][[v]],
+ *   SIP (eq. SIP): -int {D du/dn}[[v]] - int [[u]]{D dv/dn} + kappa int [[u]][[v]],
+ *     kappa = max(kappa_0, 8 max(D-, D+)/h);
+ *   NIP (eq. NIP): the term -int [[u]]{D dv/dn} dropped, kappa = kappa_0;
+ *   mNIP: NIP with kappa = kappa_0 (f(sigma_t-) + f(sigma_t+))/2 (eq.
+ *     ModifiedF0: each direction's term weighted by the factor f of its upwind
+ *     side, mnip_factor; half of the weighted sum comes from either side),
+ *     the thin side's sigma_t included;
  *   [[u]] = u- - u+, {D du/dn} = (D- du-/dx_a + D+ du+/dx_a)/2;
  *   rows/columns of a thin cell are dropped (its D never enters).
- * Domain-boundary face of a thick cell: kappa_0 int u v. */
+ * Domain-boundary face of a thick cell: kappa_0 int u v (mNIP: times f of
+ * the cell).  Returns 1 for mNIP with a void (sigma_t = 0) cell next to a
+ * thick one, where eq. ModifiedF0 is undefined. */
 static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const double *w,
-                        const double *sigma_t, const double *sigma_s, double eta, dsa_mat *A,
+                        const double *sigma_t, const double *sigma_s, double eta, int op, dsa_mat *A,
                         long **slot_of_cell_out) {
     int nn = nnodes(m), dim = m->dim, F = nn / 2;
     long nc = ncells(m);
@@ -476,6 +499,7 @@ static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const
     A->nn = nn;
     A->nthick = nthick;
     A->nb = 1 + 2 * dim;
+    A->op = op;
     A->cell = malloc(sizeof(long) * (nthick ? nthick : 1));
     A->col = malloc(sizeof(int) * (size_t)(nthick ? nthick : 1) * A->nb);
     A->blk = calloc((size_t)(nthick ? nthick : 1) * A->nb * nn * nn, sizeof(double));
@@ -530,19 +554,31 @@ static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const
                         /* domain boundary face of a thick cell */
                         long s = cl >= 0 ? sl : sh;
                         int side = cl >= 0 ? 1 : 0;
+                        double kb = k0[ax];
+                        if (op == 2) {
+                            double stc = sigma_t[cl >= 0 ? cl : chh];
+                            if (!(stc > 0.0)) { free(slot); return 1; }
+                            kb *= mnip_factor(stc, h[ax]);
+                        }
                         double *B = blockp(A, (int)s, 0);
                         for (int t = 0; t < F; ++t)
                             for (int tp = 0; tp < F; ++tp)
                                 B[face_node(dim, ax, side, t) * nn + face_node(dim, ax, side, tp)] +=
-                                    k0[ax] * Mf[t * F + tp];
+                                    kb * Mf[t * F + tp];
                         continue;
                     }
                     /* interior face: local DOF vector = [K- (nn) | K+ (nn)] */
                     double Dm = sl >= 0 ? 1.0 / (3.0 * sigma_t[cl]) : 0.0;
                     double Dp = sh >= 0 ? 1.0 / (3.0 * sigma_t[chh]) : 0.0;
                     double kap = k0[ax];
-                    double Dmax = Dm > Dp ? Dm : Dp;
-                    if (8.0 * Dmax / h[ax] > kap) kap = 8.0 * Dmax / h[ax];
+                    if (op == 0) {
+                        double Dmax = Dm > Dp ? Dm : Dp;
+                        if (8.0 * Dmax / h[ax] > kap) kap = 8.0 * Dmax / h[ax];
+                    } else if (op == 2) {
+                        if (!(sigma_t[cl] > 0.0) || !(sigma_t[chh] > 0.0)) { free(slot); return 1; }
+                        kap = k0[ax] * 0.5 * (mnip_factor(sigma_t[cl], h[ax]) + mnip_factor(sigma_t[chh], h[ax]));
+                    }
+                    const double sym = op == 0 ? 1.0 : 0.0;  /* the -int [[u]]{D dv/dn} term */
                     double jump[4][16], avg[4][16];
                     for (int t = 0; t < F; ++t) {
                         for (int q = 0; q < 2 * nn; ++q) jump[t][q] = avg[t][q] = 0.0;
@@ -559,7 +595,7 @@ static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const
                             double v = 0.0;
                             for (int t = 0; t < F; ++t)
                                 for (int tp = 0; tp < F; ++tp)
-                                    v += Mf[t * F + tp] * (-jump[t][r] * avg[tp][q] - avg[t][r] * jump[tp][q] +
+                                    v += Mf[t * F + tp] * (-jump[t][r] * avg[tp][q] - sym * avg[t][r] * jump[tp][q] +
                                                            kap * jump[t][r] * jump[tp][q]);
                             Bf[r][q] = v;
                         }
@@ -642,6 +678,75 @@ static int cg_solve(const dsa_mat *A, const double *b, double *x, double rtol, i
     return rc;
 }
 
+/* Restarted GMRES(50) with modified Gram-Schmidt for the nonsymmetric
+ * forms (NIP, mNIP): zero initial guess, no preconditioner, stops when the
+ * residual estimate drops to rtol ||b|| (the true residual is formed at every
+ * restart and reported). */
+static int gmres_solve(const dsa_mat *A, const double *b, double *x, double rtol, int maxit, int *iters,
+                       double *relres) {
+    const int mk = 50;
+    long n = (long)A->nthick * A->nn;
+    long nn1 = n ? n : 1;
+    double *V = malloc(sizeof(double) * nn1 * (mk + 1));
+    double *wv = malloc(sizeof(double) * nn1);
+    double *H = calloc((size_t)(mk + 1) * mk, sizeof(double));
+    double cs[50], sn[50], g[51], y[50];
+    if (!V || !wv || !H) { free(V); free(wv); free(H); return 3; }
+    for (long i = 0; i < n; ++i) x[i] = 0.0;
+    double bn = sqrt(dot(n, b, b));
+    int it = 0;
+    double rn = bn;
+    if (bn == 0.0) { *iters = 0; *relres = 0.0; free(V); free(wv); free(H); return 0; }
+    while (1) {
+        dsa_apply(A, x, wv);
+        for (long i = 0; i < n; ++i) wv[i] = b[i] - wv[i];
+        rn = sqrt(dot(n, wv, wv));
+        if (rn <= rtol * bn || it >= maxit || !(rn == rn)) break;
+        for (long i = 0; i < n; ++i) V[i] = wv[i] / rn;
+        for (int i = 0; i <= mk; ++i) g[i] = 0.0;
+        g[0] = rn;
+        int j = 0;
+        for (; j < mk && it < maxit; ++j) {
+            double *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+            dsa_apply(A, vj, vn);
+            for (int i = 0; i <= j; ++i) {
+                double hij = dot(n, vn, V + (size_t)i * n);
+                H[i * mk + j] = hij;
+                for (long k = 0; k < n; ++k) vn[k] -= hij * V[(size_t)i * n + k];
+            }
+            double hn = sqrt(dot(n, vn, vn));
+            H[(j + 1) * mk + j] = hn;
+            if (hn > 0.0)
+                for (long k = 0; k < n; ++k) vn[k] /= hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * mk + j], c2 = H[(i + 1) * mk + j];
+                H[i * mk + j] = cs[i] * a + sn[i] * c2;
+                H[(i + 1) * mk + j] = -sn[i] * a + cs[i] * c2;
+            }
+            double a = H[j * mk + j], c2 = H[(j + 1) * mk + j];
+            double den = sqrt(a * a + c2 * c2);
+            cs[j] = den > 0.0 ? a / den : 1.0;
+            sn[j] = den > 0.0 ? c2 / den : 0.0;
+            H[j * mk + j] = den;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            if (fabs(g[j + 1]) <= rtol * bn || hn == 0.0) { ++j; break; }
+        }
+        for (int i = j - 1; i >= 0; --i) {
+            double sum = g[i];
+            for (int k = i + 1; k < j; ++k) sum -= H[i * mk + k] * y[k];
+            y[i] = sum / H[i * mk + i];
+        }
+        for (int i = 0; i < j; ++i)
+            for (long k = 0; k < n; ++k) x[k] += y[i] * V[(size_t)i * n + k];
+    }
+    *iters = it;
+    *relres = rn / bn;
+    free(V); free(wv); free(H);
+    return (rn == rn) ? 0 : 7;
+}
+
 /* Alg. 2 applied to the SI residual:
  *   phi_out = phi_si + P_T D_ff^{-1} Sigma_f R_T (phi_si - phi_old). */
 static int dsa_correct_with(const orc_mesh *m, const dsa_mat *A, const double *sigma_t,
@@ -668,7 +773,8 @@ static int dsa_correct_with(const orc_mesh *m, const dsa_mat *A, const double *s
     }
     int it = 0;
     double rr = 0.0;
-    int rc = cg_solve(A, b, x, cg_rtol, cg_maxit, &it, &rr);
+    int rc = A->op == 0 ? cg_solve(A, b, x, cg_rtol, cg_maxit, &it, &rr)
+                        : gmres_solve(A, b, x, cg_rtol, cg_maxit, &it, &rr);
     if (phi_out != phi_si) memcpy(phi_out, phi_si, sizeof(double) * nc * nn);
     for (int s = 0; s < A->nthick; ++s) {
         long c = A->cell[s];
@@ -682,13 +788,13 @@ static int dsa_correct_with(const orc_mesh *m, const dsa_mat *A, const double *s
 }
 
 int orc_dsa_correct(const orc_mesh *m, int ndirs, const double *omega, const double *w,
-                    const double *sigma_t, const double *sigma_s, double eta, int mass_kind,
+                    const double *sigma_t, const double *sigma_s, double eta, int mass_kind, int dsa_op,
                     const double *phi_old, const double *phi_si, double cg_rtol, int cg_maxit,
                     double *phi_out, int *cg_iters, double *cg_relres) {
     dsa_mat A;
     memset(&A, 0, sizeof(A));
     long *slot = NULL;
-    int rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot);
+    int rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, dsa_op, &A, &slot);
     if (rc) { dsa_free(&A); free(slot); return rc; }
     rc = dsa_correct_with(m, &A, sigma_t, sigma_s, mass_kind, phi_old, phi_si, cg_rtol, cg_maxit,
                           phi_out, cg_iters, cg_relres);
@@ -700,12 +806,12 @@ int orc_dsa_correct(const orc_mesh *m, int ndirs, const double *omega, const dou
 /* Dense copy of D_ff (for small problems): D[(s*nn+r)*nf + cs*nn+q];
  * thick_cells[s] = cell of slot s.  Returns the number of thick cells via *nthick. */
 int orc_dsa_dense(const orc_mesh *m, int ndirs, const double *omega, const double *w,
-                  const double *sigma_t, const double *sigma_s, double eta, double *D,
+                  const double *sigma_t, const double *sigma_s, double eta, int dsa_op, double *D,
                   long *thick_cells, int *nthick) {
     dsa_mat A;
     memset(&A, 0, sizeof(A));
     long *slot = NULL;
-    int rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot);
+    int rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, dsa_op, &A, &slot);
     if (rc) { dsa_free(&A); free(slot); return rc; }
     int nn = A.nn;
     long nf = (long)A.nthick * nn;
@@ -762,7 +868,7 @@ static int triangular_step(const orc_mesh *m, int ndirs, const double *omega, co
  * above 1e6 times the first), or an error code. */
 int orc_source_iterate(const orc_mesh *m, int ndirs, const double *omega, const double *w,
                        const double *sigma_t, const double *sigma_s, const double *q,
-                       const double *inflow, double eta, int use_dsa, int mass_kind, double tol,
+                       const double *inflow, double eta, int use_dsa, int mass_kind, int dsa_op, double tol,
                        int max_it, double cg_rtol, int cg_maxit, int transpose, int dsa_form,
                        double *phi_inout, double *res_hist, int *cg_hist, int *iters_out) {
     int nn = nnodes(m);
@@ -778,7 +884,7 @@ int orc_source_iterate(const orc_mesh *m, int ndirs, const double *omega, const 
     int rc = 0;
     if (!load || !phi_si || !phi_old || !bar || !zeta) { rc = 3; goto done; }
     if (use_dsa) {
-        rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot);
+        rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, dsa_op, &A, &slot);
         if (rc) goto done;
     }
     /* ||b||: the first transport update from phi = 0 */
@@ -880,8 +986,8 @@ static int dsa_precond(const orc_mesh *m, int ndirs, const double *omega, const 
  * true residual is recomputed).  Stops when that estimate is <= tol. */
 int orc_gmres(const orc_mesh *m, int ndirs, const double *omega, const double *w, const double *sigma_t,
               const double *sigma_s, const double *q, const double *inflow, double eta, int use_dsa,
-              int mass_kind, int dsa_form, double tol, int max_it, int restart, double cg_rtol, int cg_maxit,
-              int transpose, double *phi_inout, double *res_hist, int *cg_hist, int *iters_out) {
+              int mass_kind, int dsa_op, int dsa_form, double tol, int max_it, int restart, double cg_rtol,
+              int cg_maxit, int transpose, double *phi_inout, double *res_hist, int *cg_hist, int *iters_out) {
     int nn = nnodes(m);
     long n = ncells(m) * nn;
     int mr = restart;
@@ -902,7 +1008,7 @@ int orc_gmres(const orc_mesh *m, int ndirs, const double *omega, const double *w
         rc = 3;
         goto done;
     }
-    if (use_dsa && (rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, &A, &slot))) goto done;
+    if (use_dsa && (rc = dsa_assemble(m, ndirs, omega, w, sigma_t, sigma_s, eta, dsa_op, &A, &slot))) goto done;
     /* b = sum_d w_d L_d^{-1}(q_d + inflow load) */
     volume_load(m, sigma_s, NULL, q, load);
     if ((rc = transport_update(m, ndirs, omega, w, sigma_t, load, inflow, transpose, b))) goto done;

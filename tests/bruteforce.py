@@ -226,8 +226,16 @@ def block_system(p, q=None, inflow=None, sigma_t=None, sigma_s=None):
     return A, rhs
 
 
-def sip_matrix(p, eta, sigma_t=None, sigma_s=None, ckappa=8.0):
-    """Dense SIP matrix on the thick cells (sigma_s >= eta), pointwise quadrature."""
+def sip_matrix(p, eta, sigma_t=None, sigma_s=None, ckappa=8.0, form="sip"):
+    """Dense diffusion matrix on the thick cells (sigma_s >= eta), pointwise
+    quadrature.  form "sip": eq. SIP with the penalty max(kappa_0, ckappa D/h);
+    "nip": the term -int [[u]]{D dv/dn} left out and the penalty kappa_0;
+    "mnip": "nip" with the penalty of eq. ModifiedF0 (each direction's
+    |Omega.n| weighted by max(0.2 / (sigma_t h), 1) of its upwind cell, so an
+    interior face gets the mean of the two cells' factors and a domain face
+    the cell's own)."""
+    assert form in ("sip", "nip", "mnip")
+    mfac = lambda c, axis: max(0.2 / (st[c] * p.h[axis]), 1.0)
     st = p.sigma_t if sigma_t is None else sigma_t
     ss = p.sigma_s if sigma_s is None else sigma_s
     thick = [c for c in range(p.ncells) if ss[c] >= eta]
@@ -258,11 +266,12 @@ def sip_matrix(p, eta, sigma_t=None, sigma_s=None, ckappa=8.0):
                 if nb is None:
                     if c not in slot:
                         continue
+                    kb = k0[axis] * (mfac(c, axis) if form == "mnip" else 1.0)
                     for x, wq in _face_points(p, ijk, axis, side):
                         vals = [_basis(p, ijk, n, x)[0] for n in range(nn)]
                         for m in range(nn):
                             for n in range(nn):
-                                Dm[dof(c, m), dof(c, n)] += wq * k0[axis] * vals[n] * vals[m]
+                                Dm[dof(c, m), dof(c, n)] += wq * kb * vals[n] * vals[m]
                     continue
                 if side == 0:
                     continue  # interior faces handled once, from the low cell
@@ -272,7 +281,13 @@ def sip_matrix(p, eta, sigma_t=None, sigma_s=None, ckappa=8.0):
                     continue
                 Dmn = 1.0 / (3.0 * st[cm]) if cm in slot else 0.0
                 Dpl = 1.0 / (3.0 * st[cp]) if cp in slot else 0.0
-                kap = max(k0[axis], ckappa * max(Dmn, Dpl) / p.h[axis])
+                if form == "sip":
+                    kap = max(k0[axis], ckappa * max(Dmn, Dpl) / p.h[axis])
+                elif form == "nip":
+                    kap = k0[axis]
+                else:
+                    kap = k0[axis] * 0.5 * (mfac(cm, axis) + mfac(cp, axis))
+                sym = 1.0 if form == "sip" else 0.0
                 for x, wq in _face_points(p, ijm, axis, 1):
                     # functionals over the DOFs of both cells; thin side contributes nothing
                     ent = []
@@ -284,5 +299,5 @@ def sip_matrix(p, eta, sigma_t=None, sigma_s=None, ckappa=8.0):
                             ent.append((dof(cc, n), sgn * v, 0.5 * Dc * g[axis]))
                     for (r, jr, ar) in ent:
                         for (s, js, as_) in ent:
-                            Dm[r, s] += wq * (-jr * as_ - ar * js + kap * jr * js)
+                            Dm[r, s] += wq * (-jr * as_ - sym * ar * js + kap * jr * js)
     return Dm, np.array(thick, dtype=np.int64)

@@ -97,3 +97,111 @@ def test_p15_het_differs_from_restricted_global():
     dh = het[thick] - r[thick]
     dg = glob[thick] - r[thick]
     assert np.linalg.norm(dh - dg) > 1e-3 * np.linalg.norm(dg)
+
+
+# ---------------------------------------------------------------------------
+# the nonsymmetric forms of Sec. 3.1: NIP (eq. NIP) and mNIP (eq. ModifiedF0)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form,op", [("nip", oracle.DSA_NIP), ("mnip", oracle.DSA_MNIP)])
+@pytest.mark.parametrize("dim,n,seed", [(2, 4, 0), (3, 3, 2)])
+def test_n1_nonsymmetric_forms_vs_quadrature(form, op, dim, n, seed):
+    """NIP and mNIP against a pointwise-quadrature assembly with the term
+    -int [[u]]{D dv/dn} left out (void cells made thin: eq. ModifiedF0 needs
+    sigma_t > 0)."""
+    p = _mixed(dim, n, seed)
+    p.sigma_t[p.sigma_t == 0.0] = 0.05
+    D, cells = oracle.dsa_dense(p, dsa_op=op)
+    Dq, cq = bf.sip_matrix(p, p.eta, form=form)
+    assert np.array_equal(cells, cq)
+    assert np.allclose(D, Dq, rtol=1e-12, atol=1e-14 * np.max(np.abs(Dq)))
+    assert not np.allclose(D, D.T, atol=1e-6 * np.max(np.abs(D)))       # really nonsymmetric
+
+
+@pytest.mark.parametrize("dim,n,seed", [(2, 5, 1), (3, 3, 2)])
+def test_n1_structure_of_the_dropped_term(dim, n, seed):
+    """Structure that fixes which term NIP leaves out.  With one and the same
+    penalty kappa_0, SIP = A0 + C + C^T and NIP = A0 + C, with A0 symmetric
+    (volume, mass and penalty terms) and C the consistency term
+    -int {D du/dn}[[v]]; so X = SIP - NIP is C^T and NIP - X^T = A0 must be
+    symmetric, while X itself is not (a dropped term of the wrong sign, or
+    the consistency term dropped in place of the symmetry term, breaks one of
+    the two).  The mNIP and NIP matrices differ by a penalty, which is
+    symmetric."""
+    p = _mixed(dim, n, seed)
+    p.sigma_t[p.sigma_t == 0.0] = 0.05
+    Dn, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_NIP)
+    Ds0, _ = bf.sip_matrix(p, p.eta, form="sip", ckappa=0.0)
+    sc = np.max(np.abs(Dn))
+    X = Ds0 - Dn
+    assert np.max(np.abs(X)) > 1e-3 * sc
+    assert not np.allclose(X, X.T, atol=1e-6 * sc)
+    A0 = Dn - X.T
+    assert np.allclose(A0, A0.T, rtol=0, atol=1e-13 * sc)
+    Dm, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_MNIP)
+    P = Dm - Dn
+    assert np.max(np.abs(P)) > 0
+    assert np.allclose(P, P.T, rtol=0, atol=1e-13 * sc)
+
+
+def test_n1_mnip_refuses_voids():
+    """eq. ModifiedF0 divides by sigma_t: a void next to a thick cell is an error."""
+    p = _mixed(2, 5, 1)
+    assert np.any(p.sigma_t == 0.0)
+    with pytest.raises(RuntimeError):
+        oracle.dsa_dense(p, dsa_op=oracle.DSA_MNIP)
+
+
+def test_n2_mnip_equals_nip_when_thick_enough():
+    """The modified penalty's factor max(0.2 / (sigma_t h), 1) is 1 wherever
+    sigma_t h >= 0.2, so there mNIP is NIP exactly; with thin cells next to
+    thick ones the two differ on those faces only."""
+    p = _mixed(2, 5, 1)
+    keep = p.sigma_t.copy()
+    p.sigma_t[:] = np.maximum(keep, 0.3)
+    p.sigma_s[:] = np.minimum(p.sigma_s, p.sigma_t)
+    Dn, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_NIP)
+    Dm, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_MNIP)
+    assert np.array_equal(Dn, Dm)
+    p.sigma_t[:] = keep
+    p.sigma_t[p.sigma_t == 0.0] = 0.05                 # no voids (eq. ModifiedF0 needs sigma_t > 0)
+    Dn, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_NIP)
+    Dm, _ = oracle.dsa_dense(p, dsa_op=oracle.DSA_MNIP)
+    assert not np.array_equal(Dn, Dm)
+
+
+@pytest.mark.parametrize("op", [oracle.DSA_NIP, oracle.DSA_MNIP])
+def test_n3_gmres_correction_vs_dense(op):
+    """The DSA correction with a nonsymmetric form (GMRES inner solve) against
+    a dense solve of the same assembled operator, both mass kinds."""
+    p = _mixed(2, 6, 3)
+    p.sigma_t[p.sigma_t == 0.0] = 0.05
+    rng = np.random.default_rng(4)
+    phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    D, cells = oracle.dsa_dense(p, dsa_op=op)
+    M = oracle.cell_mass(p.dim, p.h)
+    for mass_kind in (0, 1):
+        out, it, rr = oracle.dsa_correct(p, phi_old, phi_si, mass_kind=mass_kind, dsa_op=op, cg_rtol=1e-14)
+        coef = p.sigma_t if mass_kind == 1 else p.sigma_s
+        b = np.concatenate([coef[c] * (M @ (phi_si[c] - phi_old[c])) for c in cells])
+        x = np.linalg.solve(D, b)
+        ref = phi_si.copy()
+        for s, c in enumerate(cells):
+            ref[c] += x[s * p.nn:(s + 1) * p.nn]
+        assert rr <= 1e-13 and it > 0
+        assert np.max(np.abs(out - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_n4_nonsymmetric_dsa_keeps_fixed_point():
+    """SI accelerated by het-NIP and het-mNIP DSA reaches the fixed point of
+    unaccelerated SI (eq. DSA_fp: the DSA changes only the path), on C1 with
+    its void block replaced by a thin cell so that mNIP is defined."""
+    p = sninputs.config("c1")
+    st = p.sigma_t.copy()
+    st[st == 0.0] = 0.05
+    ref = oracle.source_iterate(p, tol=1e-13, max_it=200000, use_dsa=False, sigma_t=st)
+    assert ref["rc"] == 0
+    for op in (oracle.DSA_NIP, oracle.DSA_MNIP):
+        r = oracle.source_iterate(p, tol=1e-13, max_it=3000, use_dsa=True, dsa_op=op, cg_rtol=1e-13, sigma_t=st)
+        assert r["rc"] == 0 and r["iters"] < ref["iters"] / 20
+        assert np.linalg.norm(r["phi"] - ref["phi"]) <= 1e-10 * np.linalg.norm(ref["phi"])
