@@ -117,14 +117,32 @@ typedef struct {
                                   Jacobi on the DG level, the continuous Q1 space on the vertices of the
                                   thick cells (Galerkin operator), vertex-grid coarsening by two with
                                   (bi/tri)linear interpolation and damped Jacobi, a dense solve on <= 256
-                                  unknowns.  The hierarchy is built on the first use in a context. */
+                                  unknowns.  The hierarchy is built on the first use in a context.
+                                  SIP only. */
+    int diffusion;             /* the diffusion form of Sec. 3.1 whose thick principal submatrix is solved:
+                                  SN_DIFFUSION_SIP (eq. SIP, penalty max(kappa_0, 8 D / h), CG as above);
+                                  SN_DIFFUSION_NIP (eq. NIP: the term -int [[u]]{D dv/dn} dropped, penalty
+                                  kappa_0) or SN_DIFFUSION_MNIP (NIP with the penalty of eq. ModifiedF0:
+                                  kappa_0 times the mean over the face's two cells of max(0.2 / (sigma_t h), 1),
+                                  the thin neighbour's sigma_t included; on a domain face the cell's own
+                                  factor).  The nonsymmetric forms are solved by GMRES(SN_DSA_GMRES_RESTART),
+                                  right-preconditioned by the inverse diagonal cell blocks, zero initial guess,
+                                  to the true residual ||b - D x|| <= cg_rtol ||b|| or cg_maxit iterations;
+                                  precond must be SN_PRECOND_BLOCK_JACOBI.  mNIP with sigma_t = 0 at a thick
+                                  cell or its face neighbour returns SN_ERR_INVALID (the factor divides by
+                                  sigma_t). */
 } sn_dsa_opts;
+
+#define SN_DIFFUSION_SIP 0
+#define SN_DIFFUSION_NIP 1
+#define SN_DIFFUSION_MNIP 2
+#define SN_DSA_GMRES_RESTART 30
 
 #define SN_PRECOND_BLOCK_JACOBI 0
 #define SN_PRECOND_MG 1
 
 typedef struct {
-    int cg_iters;              /* CG iterations of this call */
+    int cg_iters;              /* CG (NIP, mNIP: GMRES) iterations of this call */
     double cg_relres;          /* final ||r|| / ||b|| */
     int n_thick_cells;
 } sn_dsa_stats;

@@ -186,7 +186,8 @@ def source_iterate(p, tol=1e-8, max_it=1000, use_dsa=True, mass_kind=0, cg_rtol=
                    dsa_form=0, dsa_op=DSA_SIP):
     """Returns dict(phi [nc, nn], iters, res_hist, cg_hist, rc).
     dsa_form: 0 diagonal heterogeneous DSA (Alg. 2), 1 triangular (Alg. 1);
-    dsa_op: the diffusion form (DSA_SIP by CG, DSA_NIP / DSA_MNIP by GMRES)."""
+    dsa_op: the diffusion form (DSA_SIP by CG, DSA_NIP / DSA_MNIP by an exact
+    band LU solve; their cg_hist entries are 0)."""
     st = _f64(p.sigma_t if sigma_t is None else sigma_t)
     ss = _f64(p.sigma_s if sigma_s is None else sigma_s)
     qq = _f64(p.q if q is None else q)

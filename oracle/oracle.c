@@ -49,7 +49,11 @@
  *       the face term -int [[u]]{D dv/dn} of (5), mNIP also replaces the
  *       penalty by the modified one of eq. ModifiedF0 (C = 0.1, p = 1, h the
  *       cell size across the face).  Both take the paper's penalty alone,
- *       without the 8 D/h floor of (5), and are solved by GMRES instead of CG.
+ *       without the 8 D/h floor of (5).  D_ff^{-1} is applied exactly for
+ *       them, by a banded LU factorisation with partial pivoting of the
+ *       assembled matrix (factored once per assembly): the correction's plain
+ *       definition, whatever the conditioning of the high-contrast
+ *       full-DSA inputs.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -443,12 +447,19 @@ typedef struct {
     long *cell;                  /* slot -> cell */
     int *col;                    /* [nthick][nb] neighbour slot or -1 */
     double *blk;                 /* [nthick][nb][nn][nn] */
+    /* NIP, mNIP: band LU factors of the whole matrix (n = nthick nn rows),
+     * row i holding columns i - kl .. i + kl + ku at lu[i * ldb + j - i + kl] */
+    double *lu;
+    long *piv;
+    long kl, ku, ldb;
 } dsa_mat;
 
 static void dsa_free(dsa_mat *A) {
     free(A->cell);
     free(A->col);
     free(A->blk);
+    free(A->lu);
+    free(A->piv);
     memset(A, 0, sizeof(*A));
 }
 
@@ -462,6 +473,82 @@ static double kappa0(int ndirs, const double *omega, const double *w, int axis) 
 static double *blockp(dsa_mat *A, int s, int b) {
     return A->blk + ((size_t)s * A->nb + b) * A->nn * A->nn;
 }
+
+/* Band LU with partial pivoting (Gaussian elimination restricted to the
+ * band; the pivot search looks kl rows down, and a row swap widens the upper
+ * band to kl + ku).  Returns 8 for a zero pivot (singular matrix). */
+static int band_factor(dsa_mat *A) {
+    const int nn = A->nn;
+    const long n = (long)A->nthick * nn;
+    long kl = 0, ku = 0;
+    for (int s = 0; s < A->nthick; ++s)
+        for (int b = 0; b < A->nb; ++b) {
+            int c = A->col[s * A->nb + b];
+            if (c < 0) continue;
+            long lo = ((long)s - c) * nn + (nn - 1), hi = ((long)c - s) * nn + (nn - 1);
+            if (lo > kl) kl = lo;
+            if (hi > ku) ku = hi;
+        }
+    A->kl = kl;
+    A->ku = ku;
+    A->ldb = 2 * kl + ku + 1;
+    A->lu = calloc((size_t)(n ? n : 1) * A->ldb, sizeof(double));
+    A->piv = malloc(sizeof(long) * (n ? n : 1));
+    if (!A->lu || !A->piv) return 3;
+#define LU(i, j) A->lu[(size_t)(i) * A->ldb + ((j) - (i) + kl)]
+    for (int s = 0; s < A->nthick; ++s)
+        for (int b = 0; b < A->nb; ++b) {
+            int c = A->col[s * A->nb + b];
+            if (c < 0) continue;
+            const double *B = A->blk + ((size_t)s * A->nb + b) * nn * nn;
+            for (int r = 0; r < nn; ++r)
+                for (int q = 0; q < nn; ++q) LU((long)s * nn + r, (long)c * nn + q) += B[r * nn + q];
+        }
+    for (long k = 0; k < n; ++k) {
+        long last = k + kl < n - 1 ? k + kl : n - 1;
+        long jend = k + kl + ku < n - 1 ? k + kl + ku : n - 1;
+        long p = k;
+        for (long i = k + 1; i <= last; ++i)
+            if (fabs(LU(i, k)) > fabs(LU(p, k))) p = i;
+        A->piv[k] = p;
+        if (LU(p, k) == 0.0) return 8;
+        if (p != k)
+            for (long j = k; j <= jend; ++j) {
+                double t = LU(k, j);
+                LU(k, j) = LU(p, j);
+                LU(p, j) = t;
+            }
+        for (long i = k + 1; i <= last; ++i) {
+            double l = LU(i, k) / LU(k, k);
+            LU(i, k) = l;
+            for (long j = k + 1; j <= jend; ++j) LU(i, j) -= l * LU(k, j);
+        }
+    }
+    return 0;
+}
+
+/* x = D^{-1} b from the band LU factors */
+static void band_solve(const dsa_mat *A, const double *b, double *x) {
+    const long n = (long)A->nthick * A->nn, kl = A->kl, ku = A->ku;
+    for (long i = 0; i < n; ++i) x[i] = b[i];
+    for (long k = 0; k < n; ++k) {
+        long p = A->piv[k];
+        if (p != k) {
+            double t = x[k];
+            x[k] = x[p];
+            x[p] = t;
+        }
+        long last = k + kl < n - 1 ? k + kl : n - 1;
+        for (long i = k + 1; i <= last; ++i) x[i] -= LU(i, k) * x[k];
+    }
+    for (long i = n - 1; i >= 0; --i) {
+        long jend = i + kl + ku < n - 1 ? i + kl + ku : n - 1;
+        double v = x[i];
+        for (long j = i + 1; j <= jend; ++j) v -= LU(i, j) * x[j];
+        x[i] = v / LU(i, i);
+    }
+}
+#undef LU
 
 /* mNIP penalty factor of one side of a face (eq. ModifiedF0 for linear
  * elements: c(p) = C p (p+1) with C = 0.1, p = 1), h the cell size across
@@ -617,6 +704,10 @@ static int dsa_assemble(const orc_mesh *m, int ndirs, const double *omega, const
                 }
     }
     *slot_of_cell_out = slot;
+    if (op != 0) {
+        int rc = band_factor(A);
+        if (rc) return rc;
+    }
     return 0;
 }
 
@@ -678,72 +769,19 @@ static int cg_solve(const dsa_mat *A, const double *b, double *x, double rtol, i
     return rc;
 }
 
-/* Restarted GMRES(50) with modified Gram-Schmidt for the nonsymmetric
- * forms (NIP, mNIP): zero initial guess, no preconditioner, stops when the
- * residual estimate drops to rtol ||b|| (the true residual is formed at every
- * restart and reported). */
-static int gmres_solve(const dsa_mat *A, const double *b, double *x, double rtol, int maxit, int *iters,
-                       double *relres) {
-    const int mk = 50;
+/* The nonsymmetric forms: x = D^{-1} b by the band LU factors; relres is
+ * the true residual ||b - D x|| / ||b|| of the result. */
+static int direct_solve(const dsa_mat *A, const double *b, double *x, int *iters, double *relres) {
     long n = (long)A->nthick * A->nn;
-    long nn1 = n ? n : 1;
-    double *V = malloc(sizeof(double) * nn1 * (mk + 1));
-    double *wv = malloc(sizeof(double) * nn1);
-    double *H = calloc((size_t)(mk + 1) * mk, sizeof(double));
-    double cs[50], sn[50], g[51], y[50];
-    if (!V || !wv || !H) { free(V); free(wv); free(H); return 3; }
-    for (long i = 0; i < n; ++i) x[i] = 0.0;
-    double bn = sqrt(dot(n, b, b));
-    int it = 0;
-    double rn = bn;
-    if (bn == 0.0) { *iters = 0; *relres = 0.0; free(V); free(wv); free(H); return 0; }
-    while (1) {
-        dsa_apply(A, x, wv);
-        for (long i = 0; i < n; ++i) wv[i] = b[i] - wv[i];
-        rn = sqrt(dot(n, wv, wv));
-        if (rn <= rtol * bn || it >= maxit || !(rn == rn)) break;
-        for (long i = 0; i < n; ++i) V[i] = wv[i] / rn;
-        for (int i = 0; i <= mk; ++i) g[i] = 0.0;
-        g[0] = rn;
-        int j = 0;
-        for (; j < mk && it < maxit; ++j) {
-            double *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
-            dsa_apply(A, vj, vn);
-            for (int i = 0; i <= j; ++i) {
-                double hij = dot(n, vn, V + (size_t)i * n);
-                H[i * mk + j] = hij;
-                for (long k = 0; k < n; ++k) vn[k] -= hij * V[(size_t)i * n + k];
-            }
-            double hn = sqrt(dot(n, vn, vn));
-            H[(j + 1) * mk + j] = hn;
-            if (hn > 0.0)
-                for (long k = 0; k < n; ++k) vn[k] /= hn;
-            for (int i = 0; i < j; ++i) {
-                double a = H[i * mk + j], c2 = H[(i + 1) * mk + j];
-                H[i * mk + j] = cs[i] * a + sn[i] * c2;
-                H[(i + 1) * mk + j] = -sn[i] * a + cs[i] * c2;
-            }
-            double a = H[j * mk + j], c2 = H[(j + 1) * mk + j];
-            double den = sqrt(a * a + c2 * c2);
-            cs[j] = den > 0.0 ? a / den : 1.0;
-            sn[j] = den > 0.0 ? c2 / den : 0.0;
-            H[j * mk + j] = den;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++it;
-            if (fabs(g[j + 1]) <= rtol * bn || hn == 0.0) { ++j; break; }
-        }
-        for (int i = j - 1; i >= 0; --i) {
-            double sum = g[i];
-            for (int k = i + 1; k < j; ++k) sum -= H[i * mk + k] * y[k];
-            y[i] = sum / H[i * mk + i];
-        }
-        for (int i = 0; i < j; ++i)
-            for (long k = 0; k < n; ++k) x[k] += y[i] * V[(size_t)i * n + k];
-    }
-    *iters = it;
-    *relres = rn / bn;
-    free(V); free(wv); free(H);
+    double *r = malloc(sizeof(double) * (n ? n : 1));
+    if (!r) return 3;
+    band_solve(A, b, x);
+    dsa_apply(A, x, r);
+    for (long i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    double bn = sqrt(dot(n, b, b)), rn = sqrt(dot(n, r, r));
+    *iters = 0;
+    *relres = bn > 0.0 ? rn / bn : 0.0;
+    free(r);
     return (rn == rn) ? 0 : 7;
 }
 
@@ -774,7 +812,7 @@ static int dsa_correct_with(const orc_mesh *m, const dsa_mat *A, const double *s
     int it = 0;
     double rr = 0.0;
     int rc = A->op == 0 ? cg_solve(A, b, x, cg_rtol, cg_maxit, &it, &rr)
-                        : gmres_solve(A, b, x, cg_rtol, cg_maxit, &it, &rr);
+                        : direct_solve(A, b, x, &it, &rr);
     if (phi_out != phi_si) memcpy(phi_out, phi_si, sizeof(double) * nc * nn);
     for (int s = 0; s < A->nthick; ++s) {
         long c = A->cell[s];

@@ -22,6 +22,8 @@ SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED, SN_ERR_CG_BREAKDOWN = 5, 6, 7
 SN_FP64, SN_FP32 = 0, 1
 SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG = 0, 1
 SN_DSA_DIAGONAL, SN_DSA_TRIANGULAR = 0, 1
+SN_DIFFUSION_SIP, SN_DIFFUSION_NIP, SN_DIFFUSION_MNIP = 0, 1, 2
+SN_DSA_GMRES_RESTART = 30
 SN_KRYLOV_MAX_RESTART = 200
 
 # every symbol declared in include/sn.h
@@ -49,7 +51,7 @@ class sn_quad(ctypes.Structure):
 
 class sn_dsa_opts(ctypes.Structure):
     _fields_ = [("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int), ("mass_kind", ctypes.c_int),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("diffusion", ctypes.c_int)]
 
 
 class sn_dsa_stats(ctypes.Structure):
@@ -215,9 +217,10 @@ def sn_scalar_flux(ctx: Context, psi, prec: int, phi_out):
 
 
 def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0,
-                         precond=0):
-    """precond: SN_PRECOND_BLOCK_JACOBI (0) or SN_PRECOND_MG (1)."""
-    o = sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond))
+                         precond=0, diffusion=SN_DIFFUSION_SIP):
+    """precond: SN_PRECOND_BLOCK_JACOBI (0) or SN_PRECOND_MG (1, SIP only);
+    diffusion: SN_DIFFUSION_SIP / _NIP / _MNIP (the latter two by GMRES)."""
+    o = sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond), int(diffusion))
     st = sn_dsa_stats()
     rc = _check(lib().sn_dsa_thick_correct(ctx.handle, _ptr(phi_old), _ptr(phi_si), _ptr(phi_out), ctypes.byref(o),
                                            ctypes.byref(st)))
@@ -234,14 +237,14 @@ def _stats(max_it):
 
 def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_dsa=True, prec=SN_FP64,
                       cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, transpose=False, phi_ckpt=None, precond=0,
-                      fp32_refine=False, dsa_form=SN_DSA_DIAGONAL):
+                      fp32_refine=False, dsa_form=SN_DSA_DIAGONAL, diffusion=SN_DIFFUSION_SIP):
     """Returns dict(rc, iters, res_hist, cg_hist, seconds, fp64_checks, sweeps);
     raises on errors other than NOT_CONVERGED / DIVERGED (reported in rc).
     phi_ckpt: optional device tensor [cap, ncells, nn]; iterate it is kept in
     slot it % cap."""
     o = sn_iter_opts(float(tol), int(max_it), int(bool(use_dsa)), int(prec),
-                     sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond)), int(bool(transpose)),
-                     _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0, int(bool(fp32_refine)),
+                     sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond), int(diffusion)),
+                     int(bool(transpose)), _ptr(phi_ckpt), int(phi_ckpt.shape[0]) if phi_ckpt is not None else 0, int(bool(fp32_refine)),
                      int(dsa_form))
     st, res, cgh = _stats(max_it)
     rc = _check(lib().sn_source_iterate(ctx.handle, _ptr(q), _ptr(inflow), _ptr(phi), ctypes.byref(o),
@@ -252,11 +255,13 @@ def sn_source_iterate(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, use_d
 
 
 def sn_krylov_solve(ctx: Context, q, inflow, phi, tol=1e-8, max_it=1000, restart=30, use_dsa=True,
-                    dsa_form=SN_DSA_DIAGONAL, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, precond=0, transpose=False):
+                    dsa_form=SN_DSA_DIAGONAL, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0, precond=0, transpose=False,
+                    diffusion=SN_DIFFUSION_SIP):
     """Flexible GMRES(restart) on the scalar-flux Schur system; returns dict
     as sn_source_iterate (raises on errors other than NOT_CONVERGED / DIVERGED)."""
     o = sn_krylov_opts(float(tol), int(max_it), int(restart), int(bool(use_dsa)), int(dsa_form),
-                       sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond)), int(bool(transpose)))
+                       sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond), int(diffusion)),
+                       int(bool(transpose)))
     st, res, cgh = _stats(max_it)
     rc = _check(lib().sn_krylov_solve(ctx.handle, _ptr(q), _ptr(inflow), _ptr(phi), ctypes.byref(o),
                                       ctypes.byref(st)), allow=(SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED))

@@ -152,6 +152,13 @@ struct sn_context {
     // vectors, the zero vector, dot products and their pinned host copy
     DevBuf<double> kv, kz, kw, kb, kzero, kdot, kpart;
     double* kdot_host = nullptr;
+    // GMRES inner solve of the nonsymmetric diffusion forms: full inverse
+    // diagonal blocks of form binvf_op (-1: none yet), basis [restart + 1][nf],
+    // dot products and their pinned copy, the singular-block flag
+    DevBuf<double> binvf, gv, gdot, gpart;
+    DevBuf<int> gbad;
+    double* gdot_host = nullptr;
+    int binvf_op = -1;
     int sweeps = 0;  // transport sweeps (all directions) since the last reset
     // device address of the fixed scratch of the entry points that allocate
     // nothing on this context's device (NULL if its lookup failed)
@@ -544,7 +551,138 @@ int mg_setup(sn_context* c) {
 
 bool bad_dsa_opts(const sn_dsa_opts& o) {
     return !(o.cg_rtol >= 0) || o.cg_maxit < 1 || (o.mass_kind != 0 && o.mass_kind != 1) ||
-           (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG);
+           (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG) ||
+           (o.diffusion != SN_DIFFUSION_SIP && o.diffusion != SN_DIFFUSION_NIP &&
+            o.diffusion != SN_DIFFUSION_MNIP) ||
+           (o.diffusion != SN_DIFFUSION_SIP && o.precond != SN_PRECOND_BLOCK_JACOBI);
+}
+
+// The thick solve D_ff x = b of a nonsymmetric form (NIP, mNIP) by
+// GMRES(SN_DSA_GMRES_RESTART) right-preconditioned by the inverse diagonal
+// blocks B: D B^{-1} u = b from u = 0, x = B^{-1} u into ctx->cx.  Classical
+// Gram-Schmidt twice, each pass one reduction that also yields the squared
+// norm of the vector it orthogonalises (the new vector is formed in its basis
+// slot, V_{j+1}); the norm after the second pass is ||w||^2 - |h2|^2, the
+// second pass's coefficients being tiny.  Each restart starts from the true
+// residual b - D B^{-1} u, the stop test of the last restart.
+int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o, int* iters,
+              double* relres) {
+    const DsaGeom& g = ctx->dg;
+    const long nf = (long)ctx->nthick * ctx->nn;
+    const int m = SN_DSA_GMRES_RESTART, op = o->diffusion;
+    int rc;
+    if ((rc = ctx->binvf.ensure((size_t)ctx->nthick * ctx->nn * ctx->nn)) ||
+        (rc = ctx->gv.ensure((size_t)(m + 1) * nf)) || (rc = ctx->gdot.ensure(m + 2)) ||
+        (rc = ctx->gpart.ensure((size_t)(m + 2) * krylov_blocks(nf))) || (rc = ctx->gbad.ensure(1)))
+        return rc;
+    if (!ctx->gdot_host)
+        HIPCHK(hipHostMalloc((void**)&ctx->gdot_host, (m + 2) * sizeof(double), hipHostMallocDefault));
+    if (ctx->binvf_op != op) {
+        HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+        HIPCHK(launch_block_inverse_full(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p,
+                                         ctx->gbad.p, ctx->stream));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (bad) {
+            ctx->binvf_op = -1;
+            return fail(SN_ERR_INVALID, op == SN_DIFFUSION_MNIP
+                                            ? "mNIP diffusion: sigma_t <= 0 at a thick cell or its neighbour, or a "
+                                              "singular diagonal block"
+                                            : "NIP diffusion: singular diagonal block");
+        }
+        ctx->binvf_op = op;
+    }
+    double* V = ctx->gv.p;
+    double* b = ctx->cr.p;
+    double* u = ctx->cz.p;
+    auto dotk = [&](int k, const double* Vb, const double* w, double* out) -> int {
+        HIPCHK(launch_multi_dot(nf, k, Vb, w, ctx->gpart.p, ctx->gdot.p, ctx->gdot_host, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < k; ++i) out[i] = ctx->gdot_host[i];
+        return 0;
+    };
+    HIPCHK(launch_dsa_rhs_vec(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, b,
+                              ctx->stream));
+    HIPCHK(hipMemsetAsync(u, 0, nf * sizeof(double), ctx->stream));
+    double bb;
+    if ((rc = dotk(1, b, b, &bb))) return rc;
+    const double bnorm = std::sqrt(bb);
+    if (!std::isfinite(bnorm)) return fail(SN_ERR_DIVERGED, "diffusion right-hand side is not finite");
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gg(m + 1), y(m), h(m + 2), h2(m + 2);
+    int it = 0;
+    double beta = bnorm;
+    bool first = true;
+    while (bnorm > 0.0) {
+        if (first) {
+            HIPCHK(hipMemcpyAsync(V, b, nf * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        } else {
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p, u, b, V,
+                                    ctx->stream));
+            double rr;
+            if ((rc = dotk(1, V, V, &rr))) return rc;
+            beta = std::sqrt(rr);
+        }
+        first = false;
+        if (!std::isfinite(beta)) return fail(SN_ERR_DIVERGED, "diffusion GMRES residual is not finite");
+        if (beta <= o->cg_rtol * bnorm || it >= o->cg_maxit) break;
+        HIPCHK(launch_scale(nf, 1.0 / beta, V, V, ctx->stream));
+        std::fill(gg.begin(), gg.end(), 0.0);
+        gg[0] = beta;
+        int j = 0;
+        for (; j < m && it < o->cg_maxit; ++j) {
+            double* vn = V + (size_t)(j + 1) * nf;
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p,
+                                    V + (size_t)j * nf, nullptr, vn, ctx->stream));
+            if ((rc = dotk(j + 2, V, vn, h.data()))) return rc;
+            HIPCHK(launch_multi_axpy(nf, j + 1, V, ctx->gdot.p, -1.0, vn, ctx->stream));
+            if ((rc = dotk(j + 2, V, vn, h2.data()))) return rc;
+            HIPCHK(launch_multi_axpy(nf, j + 1, V, ctx->gdot.p, -1.0, vn, ctx->stream));
+            double hh2 = 0.0;
+            for (int i = 0; i <= j; ++i) hh2 += h2[i] * h2[i];
+            const double hn = std::sqrt(std::max(0.0, h2[j + 1] - hh2));
+            if (!std::isfinite(hn) || !std::isfinite(h[j + 1]))
+                return fail(SN_ERR_DIVERGED, "diffusion GMRES residual is not finite");
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) HIPCHK(launch_scale(nf, 1.0 / hn, vn, vn, ctx->stream));
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+            }
+            const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+            const double den = std::sqrt(a * a + c2 * c2);
+            cs[j] = den > 0.0 ? a / den : 1.0;
+            sn[j] = den > 0.0 ? c2 / den : 0.0;
+            H[(size_t)j * m + j] = den;
+            gg[j + 1] = -sn[j] * gg[j];
+            gg[j] = cs[j] * gg[j];
+            ++it;
+            if (std::fabs(gg[j + 1]) <= o->cg_rtol * bnorm || hn == 0.0) {
+                ++j;
+                break;
+            }
+        }
+        // u += V y, H(0:j, 0:j) y = g(0:j)
+        for (int i = j - 1; i >= 0; --i) {
+            double sum = gg[i];
+            for (int k = i + 1; k < j; ++k) sum -= H[(size_t)i * m + k] * y[k];
+            y[i] = sum / H[(size_t)i * m + i];
+        }
+        if (j > 0) {
+            for (int i = 0; i < j; ++i) ctx->gdot_host[i] = y[i];
+            HIPCHK(hipMemcpyAsync(ctx->gdot.p, ctx->gdot_host, j * sizeof(double), hipMemcpyHostToDevice,
+                                  ctx->stream));
+            HIPCHK(launch_multi_axpy(nf, j, V, ctx->gdot.p, 1.0, u, ctx->stream));
+            // the pinned coefficients must not be overwritten before the copy ran
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
+    }
+    HIPCHK(launch_full_block_apply(g, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
+    *iters = it;
+    *relres = bnorm > 0.0 ? beta / bnorm : 0.0;
+    return 0;
 }
 
 // res_part / res_nparts: source-iteration residual partial sums to reduce in
@@ -590,6 +728,24 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         }
         return 0;
     };
+    if (o->diffusion != SN_DIFFUSION_SIP) {
+        if (res_part) HIPCHK(launch_residual_final(res_nparts, res_part, ctx->res3.p, ctx->hpin->r3, ctx->stream));
+        if (ctx->timing == 1 && (rc = record_event(ctx, &e0))) return rc;
+        int its = 0;
+        double rel = 0.0;
+        if ((rc = dsa_gmres(ctx, phi_old, phi_si, o, &its, &rel))) return rc;
+        if ((rc = scatter())) return rc;
+        if (ctx->timing == 1) {
+            if ((rc = record_event(ctx, &e1))) return rc;
+            ctx->dsa_ev.emplace_back(e0, e1);
+        }
+        if (stats) {
+            stats->cg_iters = its;
+            stats->cg_relres = rel;
+            stats->n_thick_cells = ctx->nthick;
+        }
+        return 0;
+    }
     if (!bj && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
     CgScalars& hs = ctx->hpin->cs;
     auto vcycle = [&]() -> int {
@@ -838,6 +994,7 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->kdot.release();
     ctx->kpart.release();
     if (ctx->kdot_host) (void)hipHostFree(ctx->kdot_host);
+    if (ctx->gdot_host) (void)hipHostFree(ctx->gdot_host);
     delete ctx;
 }
 

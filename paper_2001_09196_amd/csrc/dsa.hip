@@ -15,6 +15,7 @@
 //   ||r|| <= rtol ||b||.  Scalars stay on the device: every dot product is a
 //   fixed-order block reduction whose partials every consumer block re-reduces
 //   in the same order, so results do not depend on scheduling.
+#include "../../include/sn.h"
 #include "sn_kernels.hpp"
 
 namespace sn {
@@ -267,10 +268,22 @@ hipError_t launch_neighbour_table(const DsaGeom& g, const int* thick_cell, const
     return hipGetLastError();
 }
 
+// mNIP penalty factor of one side of a face (eq. ModifiedF0 with linear
+// elements: c(p) = 0.1 p (p + 1) = 0.2), h the cell size across the face
+__device__ __forceinline__ double mnip_factor(double sigma_t, double h) {
+    const double f = 0.2 / (sigma_t * h);
+    return f > 1.0 ? f : 1.0;
+}
+
 // Rows of D_ff u for thick cell `cell` (slot s) with the neighbour values
 // supplied by get(nslot, un) -- the same bilinear form as sip_cell_apply,
-// reading neighbours through the neighbour table.
-template <int NN, typename Get>
+// reading neighbours through the neighbour table.  OP selects the form of
+// Sec. 3.1: SN_DIFFUSION_SIP (eq. SIP), SN_DIFFUSION_NIP (eq. NIP: the term
+// -int [[u]]{D dv/dn} dropped, penalty kappa_0 without the 8 D/h floor) or
+// SN_DIFFUSION_MNIP (NIP with the penalty of eq. ModifiedF0: kappa_0 times the
+// mean of the two sides' factors, the thin side's sigma_t included; on a
+// domain face the cell's own factor).
+template <int NN, int OP = SN_DIFFUSION_SIP, typename Get>
 __device__ __forceinline__ void sip_rows(const DsaGeom& g, int s, long cell, const int* __restrict__ nbr,
                                          const int* __restrict__ thick_cell, const double* __restrict__ sigma_t,
                                          const double* __restrict__ sigma_s, const double uK[NN], Get get,
@@ -316,9 +329,11 @@ __device__ __forceinline__ void sip_rows(const DsaGeom& g, int s, long cell, con
 #pragma unroll
                 for (int o = 0; o < DIM; ++o)
                     if (o != ax) mass_along<NN>(g.h[o], o, t);
+                double kb = g.kappa0[ax];
+                if constexpr (OP == SN_DIFFUSION_MNIP) kb *= mnip_factor(sigma_t[cell], h);
 #pragma unroll
                 for (int n = 0; n < NN; ++n)
-                    if (((n >> ax) & 1) == sd) out[n] = fma(g.kappa0[ax], t[n], out[n]);
+                    if (((n >> ax) & 1) == sd) out[n] = fma(kb, t[n], out[n]);
                 continue;
             }
             double un[NN];
@@ -330,8 +345,14 @@ __device__ __forceinline__ void sip_rows(const DsaGeom& g, int s, long cell, con
                 get(ns, un);
             }
             double kap = g.kappa0[ax];
-            const double Dmax = DK > Dn ? DK : Dn;
-            if (8.0 * Dmax / h > kap) kap = 8.0 * Dmax / h;
+            if constexpr (OP == SN_DIFFUSION_SIP) {
+                const double Dmax = DK > Dn ? DK : Dn;
+                if (8.0 * Dmax / h > kap) kap = 8.0 * Dmax / h;
+            } else if constexpr (OP == SN_DIFFUSION_MNIP) {
+                const long stride = ax == 0 ? 1L : ax == 1 ? (long)g.nx : (long)g.nx * g.ny;
+                const long nb = cell + (sd ? stride : -stride);
+                kap *= 0.5 * (mnip_factor(sigma_t[cell], h) + mnip_factor(sigma_t[nb], h));
+            }
             double J[NN], G[NN];
 #pragma unroll
             for (int n = 0; n < NN; ++n) {
@@ -349,13 +370,19 @@ __device__ __forceinline__ void sip_rows(const DsaGeom& g, int s, long cell, con
                     mass_along<NN>(g.h[o], o, J);
                     mass_along<NN>(g.h[o], o, G);
                 }
-            const double hd = 0.5 * DK / h;
+            if constexpr (OP == SN_DIFFUSION_SIP) {
+                const double hd = 0.5 * DK / h;
 #pragma unroll
-            for (int n = 0; n < NN; ++n) {
-                if (((n >> ax) & 1) == sd) {
-                    out[n] += -G[n] + kap * J[n] - hd * J[n];
-                    out[n ^ st] += hd * J[n];
+                for (int n = 0; n < NN; ++n) {
+                    if (((n >> ax) & 1) == sd) {
+                        out[n] += -G[n] + kap * J[n] - hd * J[n];
+                        out[n ^ st] += hd * J[n];
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int n = 0; n < NN; ++n)
+                    if (((n >> ax) & 1) == sd) out[n] += -G[n] + kap * J[n];
             }
         }
     }
@@ -511,6 +538,207 @@ __device__ __forceinline__ void dsa_rhs_at(const DsaGeom& g, const int* __restri
     for (int o = 0; o < DIM; ++o) mass_along<NN>(g.h[o], o, t);
 #pragma unroll
     for (int n = 0; n < NN; ++n) t[n] *= coef;
+}
+
+// ---------------------------------------------------------------------------
+// the nonsymmetric forms (NIP, mNIP): operator pieces of the GMRES inner solve
+// ---------------------------------------------------------------------------
+// Full inverse of each thick cell's diagonal block (Gauss-Jordan with partial
+// pivoting: the NIP block is not symmetric and need not be definite), stored
+// element-major, entry r NN + c of all cells contiguous.  Sets *bad to 1 for
+// a singular block, and for mNIP when a thick cell or a face neighbour has
+// sigma_t <= 0 (eq. ModifiedF0 divides by it).
+template <int NN, int OP>
+__global__ void __launch_bounds__(128) block_inverse_full_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                                 const int* __restrict__ nbr,
+                                                                 const double* __restrict__ sigma_t,
+                                                                 const double* __restrict__ sigma_s,
+                                                                 double* __restrict__ binv, int* __restrict__ bad) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    auto zero = [](int, double o[NN]) {
+        for (int n = 0; n < NN; ++n) o[n] = 0.0;
+    };
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long cell = thick_cell[s];
+        bool ok = true;
+        if constexpr (OP == SN_DIFFUSION_MNIP) {
+            ok = sigma_t[cell] > 0.0;
+            const long stride[3] = {1, g.nx, (long)g.nx * g.ny};
+            for (int f = 0; f < 2 * DIM; ++f)
+                if (nbr[s * 2 * DIM + f] != -2) ok = ok && sigma_t[cell + ((f & 1) ? stride[f >> 1] : -stride[f >> 1])] > 0.0;
+        }
+        double B[NN][NN], Inv[NN][NN];
+        for (int c = 0; c < NN; ++c) {
+            double e[NN], col[NN];
+            for (int n = 0; n < NN; ++n) e[n] = (n == c) ? 1.0 : 0.0;
+            sip_rows<NN, OP>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, e, zero, col);
+            for (int n = 0; n < NN; ++n) B[n][c] = col[n];
+        }
+        for (int r = 0; r < NN; ++r)
+            for (int c = 0; c < NN; ++c) Inv[r][c] = (r == c) ? 1.0 : 0.0;
+        for (int p = 0; p < NN && ok; ++p) {
+            int piv = p;
+            for (int r = p + 1; r < NN; ++r)
+                if (fabs(B[r][p]) > fabs(B[piv][p])) piv = r;
+            if (!(fabs(B[piv][p]) > 0.0)) {
+                ok = false;
+                break;
+            }
+            if (piv != p)
+                for (int c = 0; c < NN; ++c) {
+                    const double a = B[p][c], b = Inv[p][c];
+                    B[p][c] = B[piv][c];
+                    Inv[p][c] = Inv[piv][c];
+                    B[piv][c] = a;
+                    Inv[piv][c] = b;
+                }
+            const double ip = 1.0 / B[p][p];
+            for (int c = 0; c < NN; ++c) {
+                B[p][c] *= ip;
+                Inv[p][c] *= ip;
+            }
+            for (int r = 0; r < NN; ++r) {
+                if (r == p) continue;
+                const double f = B[r][p];
+                for (int c = 0; c < NN; ++c) {
+                    B[r][c] -= f * B[p][c];
+                    Inv[r][c] -= f * Inv[p][c];
+                }
+            }
+        }
+        if (!ok) *bad = 1;
+        for (int r = 0; r < NN; ++r)
+            for (int c = 0; c < NN; ++c) binv[(long)(r * NN + c) * g.nthick + s] = ok ? Inv[r][c] : 0.0;
+    }
+}
+
+template <int NN>
+__device__ __forceinline__ void full_block_apply(const double* __restrict__ binv, int nthick, int s,
+                                                 const double* __restrict__ v, double z[NN]) {
+    double vv[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) vv[n] = v[(long)s * NN + n];
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < NN; ++c) a = fma(binv[(long)(r * NN + c) * nthick + s], vv[c], a);
+        z[r] = a;
+    }
+}
+
+// w = D_ff B^{-1} v (right-preconditioned operator; the neighbours' B^{-1} v
+// are formed on the fly), or with b given the residual w = b - D_ff B^{-1} v
+template <int NN, int OP>
+__global__ void __launch_bounds__(256) nip_apply_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                        const int* __restrict__ nbr,
+                                                        const double* __restrict__ sigma_t,
+                                                        const double* __restrict__ sigma_s,
+                                                        const double* __restrict__ binv,
+                                                        const double* __restrict__ v, const double* __restrict__ b,
+                                                        double* __restrict__ w) {
+    auto get = [&](int slot, double out[NN]) { full_block_apply<NN>(binv, g.nthick, slot, v, out); };
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
+        double uK[NN], o[NN];
+        get(t, uK);
+        sip_rows<NN, OP>(g, t, thick_cell[t], nbr, thick_cell, sigma_t, sigma_s, uK, get, o);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) {
+            const long e = (long)t * NN + n;
+            w[e] = b ? b[e] - o[n] : o[n];
+        }
+    }
+}
+
+// x = B^{-1} u
+template <int NN>
+__global__ void __launch_bounds__(256) full_block_apply_kernel(int nthick, const double* __restrict__ binv,
+                                                               const double* __restrict__ u,
+                                                               double* __restrict__ x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nthick; t += gridDim.x * blockDim.x) {
+        double z[NN];
+        full_block_apply<NN>(binv, nthick, t, u, z);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) x[(long)t * NN + n] = z[n];
+    }
+}
+
+// b = coef M (phi_si - phi_old) on the thick cells, as a thick vector
+template <int NN>
+__global__ void __launch_bounds__(256) dsa_rhs_vec_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                          const double* __restrict__ sigma_t,
+                                                          const double* __restrict__ sigma_s, int mass_kind,
+                                                          const double* __restrict__ phi_old,
+                                                          const double* __restrict__ phi_si, double* __restrict__ b) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        double t[NN];
+        dsa_rhs_at<NN>(g, thick_cell, sigma_t, sigma_s, mass_kind, phi_old, phi_si, s, t);
+#pragma unroll
+        for (int n = 0; n < NN; ++n) b[(long)s * NN + n] = t[n];
+    }
+}
+
+static int grid_of(int n, int bs) { return std::max(1, std::min((n + bs - 1) / bs, 65536)); }
+
+hipError_t launch_block_inverse_full(const DsaGeom& g, int op, const int* thick_cell, const int* nbr,
+                                     const double* sigma_t, const double* sigma_s, double* binv, int* bad,
+                                     hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 128);
+#define SN_BIF(NN, OP)                                                                                      \
+    hipLaunchKernelGGL((block_inverse_full_kernel<NN, OP>), dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, \
+                       sigma_t, sigma_s, binv, bad)
+    if (g.nn == 4) {
+        if (op == SN_DIFFUSION_MNIP) SN_BIF(4, SN_DIFFUSION_MNIP);
+        else SN_BIF(4, SN_DIFFUSION_NIP);
+    } else {
+        if (op == SN_DIFFUSION_MNIP) SN_BIF(8, SN_DIFFUSION_MNIP);
+        else SN_BIF(8, SN_DIFFUSION_NIP);
+    }
+#undef SN_BIF
+    return hipGetLastError();
+}
+
+hipError_t launch_nip_apply(const DsaGeom& g, int op, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, const double* binv, const double* v, const double* b, double* w,
+                            hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 256);
+#define SN_NA(NN, OP)                                                                                          \
+    hipLaunchKernelGGL((nip_apply_kernel<NN, OP>), dim3(blocks), dim3(256), 0, st, g, thick_cell, nbr, sigma_t, \
+                       sigma_s, binv, v, b, w)
+    if (g.nn == 4) {
+        if (op == SN_DIFFUSION_MNIP) SN_NA(4, SN_DIFFUSION_MNIP);
+        else SN_NA(4, SN_DIFFUSION_NIP);
+    } else {
+        if (op == SN_DIFFUSION_MNIP) SN_NA(8, SN_DIFFUSION_MNIP);
+        else SN_NA(8, SN_DIFFUSION_NIP);
+    }
+#undef SN_NA
+    return hipGetLastError();
+}
+
+hipError_t launch_full_block_apply(const DsaGeom& g, const double* binv, const double* u, double* x, hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 256);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(full_block_apply_kernel<4>, dim3(blocks), dim3(256), 0, st, g.nthick, binv, u, x);
+    else
+        hipLaunchKernelGGL(full_block_apply_kernel<8>, dim3(blocks), dim3(256), 0, st, g.nthick, binv, u, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_dsa_rhs_vec(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
+                              int mass_kind, const double* phi_old, const double* phi_si, double* b, hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 256);
+    if (g.nn == 4)
+        hipLaunchKernelGGL(dsa_rhs_vec_kernel<4>, dim3(blocks), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, b);
+    else
+        hipLaunchKernelGGL(dsa_rhs_vec_kernel<8>, dim3(blocks), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
+                           mass_kind, phi_old, phi_si, b);
+    return hipGetLastError();
 }
 
 // Warm start of the CG from the previous solution x_p (one-dimensional

@@ -282,7 +282,8 @@ hipError_t launch_thin_add(long nc, int nn, const int* slot_of_cell, const doubl
 // adjoint sources of the two responses
 // ---------------------------------------------------------------------------
 // q_adj = 4 pi r (volume detector J = sum_c r_c int_c phi)
-__global__ void scale_kernel(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+// y = a x; y may be x
+__global__ void scale_kernel(long n, double a, const double* x, double* y) {
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         y[e] = a * x[e];
 }

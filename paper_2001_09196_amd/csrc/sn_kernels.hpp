@@ -194,6 +194,20 @@ inline int bj_entries_of(int nn) {
 }
 hipError_t launch_block_jacobi(const DsaGeom& g, const int* thick_cell, const int* slot_of_cell,
                                const double* sigma_t, const double* sigma_s, double* binv, hipStream_t st);
+// nonsymmetric diffusion forms (op = 1 NIP, 2 mNIP): full inverse of the
+// diagonal blocks (nn * nn words per thick cell, element-major; *bad set for
+// a singular block or, with mNIP, sigma_t <= 0 at a thick cell or its
+// neighbour), w = D B^{-1} v or w = b - D B^{-1} v, x = B^{-1} u, and the
+// thick right-hand side b = coef M (phi_si - phi_old)
+hipError_t launch_block_inverse_full(const DsaGeom& g, int op, const int* thick_cell, const int* nbr,
+                                     const double* sigma_t, const double* sigma_s, double* binv, int* bad,
+                                     hipStream_t st);
+hipError_t launch_nip_apply(const DsaGeom& g, int op, const int* thick_cell, const int* nbr, const double* sigma_t,
+                            const double* sigma_s, const double* binv, const double* v, const double* b, double* w,
+                            hipStream_t st);
+hipError_t launch_full_block_apply(const DsaGeom& g, const double* binv, const double* u, double* x, hipStream_t st);
+hipError_t launch_dsa_rhs_vec(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
+                              int mass_kind, const double* phi_old, const double* phi_si, double* b, hipStream_t st);
 
 struct CgScalars {
     double rz[2];   // r.z of the current iterate, slot = iteration parity

@@ -1,0 +1,144 @@
+"""GPU NIP and mNIP diffusion forms (Sec. 3.1, eqs. NIP and ModifiedF0)
+against the oracle, through the C ABI: the thick correction of one DSA step
+(GMRES inner solve on the GPU to a relative residual of 1e-14, an exact band
+LU solve in the oracle), source iterations and outer GMRES iterations with
+het-NIP, full NIP and full mNIP on the crooked-pipe stand-in, and the option
+and input checks of the forms.
+
+Bars: the corrections agree to 1e-10 (max-norm relative: the inner residual
+of 1e-14 times the forms' condition numbers on these inputs, below 1e4),
+iterates to 1e-10 / 1e-9 as for the SIP form.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import sninputs
+from gpu_util import context, dev, rel_l2, rel_max, random_problem, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FORMS = {"nip": (1, oracle.DSA_NIP), "mnip": (2, oracle.DSA_MNIP)}
+
+
+def _zeros(p):
+    return torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (16, 16, 1)), (2, (45, 70, 1)), (3, (14, 11, 9))])
+@pytest.mark.parametrize("form", ["nip", "mnip"])
+@pytest.mark.parametrize("mass_kind", [0, 1])
+def test_nonsymmetric_dsa_parity(dim, shape, form, mass_kind):
+    from paper_2001_09196_amd import sn_dsa_thick_correct
+    diffusion, op = FORMS[form]
+    p = random_problem(dim, *shape, order=4, seed=7 + shape[0])
+    p.sigma_t[p.sigma_t == 0.0] = 0.05          # eq. ModifiedF0 needs sigma_t > 0 next to thick cells
+    rng = np.random.default_rng(8)
+    phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    ref, it_o, rr_o = oracle.dsa_correct(p, phi_old, phi_si, mass_kind=mass_kind, cg_rtol=1e-14, cg_maxit=200000,
+                                         dsa_op=op)
+    say(f"dsa {form} {p.name} mass_kind={mass_kind}: oracle relres {rr_o:.1e}")
+    with context(p) as ctx:
+        out = _zeros(p)
+        st = sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out, cg_rtol=1e-14, cg_maxit=200000,
+                                  mass_kind=mass_kind, diffusion=diffusion)
+        say(f"  GPU {st['cg_iters']} GMRES iterations, relres {st['cg_relres']:.1e}")
+        got = out.cpu().numpy()
+        # a second call on the same context reuses the block inverses
+        out2 = _zeros(p)
+        sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out2, cg_rtol=1e-14, cg_maxit=200000,
+                             mass_kind=mass_kind, diffusion=diffusion)
+        assert torch.equal(out, out2)
+    assert st["cg_relres"] <= 1e-14 and rr_o <= 1e-14
+    assert rel_max(got, ref) <= 1e-10
+    thin = p.sigma_s < p.eta
+    assert np.array_equal(got[thin], phi_si[thin])
+
+
+def test_forms_switch_on_one_context():
+    """SIP, NIP, mNIP and SIP again on one context: each call matches the
+    oracle's correction of its own form (the block inverses follow the form)."""
+    from paper_2001_09196_amd import sn_dsa_thick_correct
+    p = random_problem(2, 30, 20, 1, seed=9, voids=False)
+    rng = np.random.default_rng(1)
+    phi_old = rng.uniform(0, 1, (p.ncells, p.nn))
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    say("dsa forms on one context")
+    with context(p) as ctx:
+        for diffusion, op in ((0, oracle.DSA_SIP), (1, oracle.DSA_NIP), (2, oracle.DSA_MNIP), (0, oracle.DSA_SIP),
+                              (1, oracle.DSA_NIP)):
+            ref, _, _ = oracle.dsa_correct(p, phi_old, phi_si, cg_rtol=1e-14, cg_maxit=200000, dsa_op=op)
+            out = _zeros(p)
+            sn_dsa_thick_correct(ctx, dev(phi_old), dev(phi_si), out, cg_rtol=1e-14, cg_maxit=200000,
+                                 diffusion=diffusion)
+            assert rel_max(out.cpu().numpy(), ref) <= 1e-10, diffusion
+
+
+PIPE_CASES = [(1, 1e3, ("het",)), (4, 1e8, ("het",)), (5, 1e3, ("het", "full")), (2, 1.0, ("het", "full"))]
+
+
+@pytest.mark.parametrize("k,cdt,which", PIPE_CASES)
+def test_crooked_pipe_nonsymmetric_forms(k, cdt, which):
+    """Crooked-pipe stand-in (Sec. 4.1, problems of Table problems, S8, 0.5-unit
+    cells): three source iterations and ten outer GMRES iterations with het-NIP
+    (eta = 1) and, where the block-Jacobi GMRES inner solve reaches 1e-13 in a
+    few thousand iterations (#5, #2), full NIP and full mNIP (eta = 0),
+    against the oracle (exact inner solves)."""
+    from paper_2001_09196_amd import sn_krylov_solve, sn_source_iterate
+    base = sninputs.crooked_pipe(k, cdt, cells_per_unit=2)
+    forms = [("het-NIP", 1.0, 1, oracle.DSA_NIP)]
+    if "full" in which:
+        forms += [("full NIP", 0.0, 1, oracle.DSA_NIP), ("full mNIP", 0.0, 2, oracle.DSA_MNIP)]
+    for name, eta, diffusion, op in forms:
+        p = dataclasses.replace(base, eta=eta)
+        say(f"crooked pipe #{k} cdt={cdt} {name}")
+        ref = oracle.source_iterate(p, tol=0.0, max_it=3, use_dsa=True, mass_kind=1, cg_rtol=1e-13,
+                                    cg_maxit=200000, dsa_op=op)
+        refk = oracle.gmres(p, tol=0.0, max_it=10, restart=30, use_dsa=True, mass_kind=1, cg_rtol=1e-13,
+                            cg_maxit=200000, dsa_op=op)
+        with context(p) as ctx:
+            phi = _zeros(p)
+            r = sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=3, use_dsa=True, mass_kind=1,
+                                  cg_rtol=1e-13, cg_maxit=200000, diffusion=diffusion)
+            e_si = rel_l2(phi.cpu().numpy(), ref["phi"])
+            phi = _zeros(p)
+            rk = sn_krylov_solve(ctx, dev(p.q), None, phi, tol=0.0, max_it=10, restart=30, use_dsa=True,
+                                 mass_kind=1, cg_rtol=1e-13, cg_maxit=200000, diffusion=diffusion)
+            e_k = rel_l2(phi.cpu().numpy(), refk["phi"])
+        say(f"  SI {e_si:.2e} (GMRES {list(r['cg_hist'])}), outer GMRES {e_k:.2e}")
+        assert r["iters"] == 3 and rk["iters"] == 10
+        assert e_si <= 1e-10 and e_k <= 1e-9
+        assert np.allclose(r["res_hist"], ref["res_hist"], rtol=1e-8, atol=0)
+
+
+def test_nonsymmetric_form_errors():
+    from paper_2001_09196_amd import SnError, sn_dsa_thick_correct, sn_source_iterate
+    from paper_2001_09196_amd.binding import SN_ERR_DIVERGED, SN_ERR_INVALID
+    p = random_problem(2, 12, 10, 1, seed=3)             # has voids next to thick cells
+    assert np.any(p.sigma_t == 0.0)
+    say("nonsymmetric form errors")
+    rng = np.random.default_rng(2)
+    phi_si = dev(rng.uniform(0, 1, (p.ncells, p.nn)))
+    with context(p) as ctx:
+        for kw in ({"diffusion": 3}, {"diffusion": -1}, {"diffusion": 1, "precond": 1}):
+            with pytest.raises(SnError) as e:
+                sn_dsa_thick_correct(ctx, _zeros(p), phi_si, _zeros(p), **kw)
+            assert e.value.code == SN_ERR_INVALID, kw
+        with pytest.raises(SnError) as e:
+            sn_source_iterate(ctx, dev(p.q), None, _zeros(p), max_it=2, diffusion=2)
+        assert e.value.code == SN_ERR_INVALID
+        # NIP is defined next to voids (the thin side never enters it)
+        ref, _, _ = oracle.dsa_correct(p, np.zeros((p.ncells, p.nn)), phi_si.cpu().numpy(), cg_rtol=1e-14,
+                                       cg_maxit=200000, dsa_op=oracle.DSA_NIP)
+        out = _zeros(p)
+        sn_dsa_thick_correct(ctx, _zeros(p), phi_si, out, cg_rtol=1e-14, cg_maxit=200000, diffusion=1)
+        assert rel_max(out.cpu().numpy(), ref) <= 1e-10
+        nan = torch.full((p.ncells, p.nn), float("nan"), dtype=torch.float64, device="cuda")
+        with pytest.raises(SnError) as e:
+            sn_dsa_thick_correct(ctx, nan, phi_si, _zeros(p), diffusion=1)
+        assert e.value.code == SN_ERR_DIVERGED
