@@ -516,47 +516,68 @@ PAPER_PIPE = {1: {"1": (19, 56, 15), "1e3": (31, 120, 25), "1e8": (34, 123, 25),
               5: {"1": (20, 44, 15), "1e3": (102, 143, 25), "1e8": (134, 147, 25), "sa0": (None, 177, 25)}}
 
 
-def bench_pipe(log, budget_s=150.0):
+PIPE_COLUMNS = (
+    # name, eta, diffusion form, inner solver, inner tolerance, also source iteration
+    ("het_nip", 1.0, 1, 2, 0.0, True),        # the paper's het-DSA NIP column, exact inner solve
+    ("full_nip", 0.0, 1, 2, 0.0, False),      # the paper's full-DSA NIP column
+    ("full_mnip", 0.0, 2, 2, 0.0, False),     # the paper's full-DSA mNIP column
+    ("het_nip_mg_1e-4", 1.0, 1, 1, 1e-4, False),  # scalable inner solve at the paper's inner tolerance
+    ("het_sip", 1.0, 0, 0, 1e-10, True),      # SIP (eq. SIP), block-Jacobi CG
+    ("full_sip", 0.0, 0, 2, 0.0, False),      # SIP, full DSA, exact inner solve
+)
+PIPE_SCAN_COLUMNS = (("het_nip", 1.0, 1), ("het_mnip", 1.0, 2), ("full_nip", 0.0, 1), ("full_mnip", 0.0, 2))
+
+
+def bench_pipe(log, budget_s=100.0):
     """Crooked-pipe stand-in (Sec. 4.1; geometry of sninputs.pipe_regions at
     the paper's 0.5-unit cells, S8): iterations of GMRES(30) to 1e-12 (the
-    paper's protocol) and of source iteration to 1e-8 (problems only), with the heterogeneous
-    DSA (eta = 1) and with full DSA (eta = 0, every cell in the diffusion
-    solve), for the five problems of Table problems at c dt = 1, 1e3, 1e8 and
-    without absorption, and the two-region scan of sigma_pipe (everything
-    else 200, c dt = 1000).  Both DSA forms use the sigma_t mass of Alg. 2 and
-    block-Jacobi CG to 1e-10.  "DNC": not converged in the iteration cap."""
+    paper's protocol for Table crookedpipe1, flexible since the DSA solve
+    may be inexact) for the five problems of Table problems at c dt = 1, 1e3,
+    1e8 and without absorption, with the DSA forms of PIPE_COLUMNS: het-NIP,
+    full NIP and full mNIP (the paper's three columns) with an exact inner
+    solve (band LU on the device), het-NIP with the SIP-multigrid GMRES inner
+    solve stopped at 1e-4 (the paper's inner tolerance), and SIP het (CG) and
+    full (exact); source iteration to 1e-8 for het-NIP and het-SIP.  Then the
+    two-region scan of sigma_pipe (everything else 200, c dt = 1000) with
+    het/full NIP and mNIP.  All use the sigma_t mass of Alg. 2.  "DNC": not
+    converged in the iteration cap; "n/a": the form is undefined (mNIP next to
+    a void)."""
     import dataclasses
 
+    import numpy as np
     import torch
 
     import sninputs
-    from paper_2001_09196_amd import Context, sn_krylov_solve, sn_source_iterate
+    from paper_2001_09196_amd import Context, SnError, sn_krylov_solve, sn_source_iterate
     dev = torch.device("cuda:0")
     t_start = time.perf_counter()
     out = {"workload": "crooked-pipe stand-in: 2D 28x20 cells of 0.5, S8 (40 dirs), regions pipe/wall/edge/block "
                        "with the area shares of the paper's Table problems; q = 1 in the pipe inlet; vacuum",
-           "kmax_gmres": 200, "kmax_si": 600, "problems": {}, "sigma_pipe_scan": {}, "paper_order2": PAPER_PIPE}
+           "kmax_gmres": 500, "kmax_si": 600, "columns": [c[0] for c in PIPE_COLUMNS], "problems": {},
+           "sigma_pipe_scan": {}, "paper_order2_full_nip_full_mnip_het_nip": PAPER_PIPE}
 
-    def run(p, si=True):
+    def run(p, diffusion, precond, inner_tol, si):
         t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
         res = {}
+        kw = dict(use_dsa=True, mass_kind=1, diffusion=diffusion, precond=precond, cg_rtol=inner_tol,
+                  cg_maxit=20000)
         with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta) as ctx:
             q = t(p.q)
             phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
-            rk = sn_krylov_solve(ctx, q, None, phi, tol=1e-12, max_it=200, restart=30, use_dsa=True,
-                                 cg_rtol=1e-10, cg_maxit=20000, mass_kind=1)
+            try:
+                rk = sn_krylov_solve(ctx, q, None, phi, tol=1e-12, max_it=500, restart=30, **kw)
+            except SnError as e:
+                return {"gmres30_to_1e-12": "n/a", "error": str(e)}
             res["gmres30_to_1e-12"] = rk["iters"] if rk["rc"] == 0 else "DNC"
-            res["cg_iters_per_dsa_gmres"] = float(np.mean(rk["cg_hist"])) if rk["iters"] else 0.0
+            res["inner_iters_per_dsa"] = float(np.mean(rk["cg_hist"])) if rk["iters"] else 0.0
             res["seconds"] = rk["seconds"]
             if si:
                 phi.zero_()
-                rs = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=600, use_dsa=True, cg_rtol=1e-10,
-                                       cg_maxit=20000, mass_kind=1)
+                rs = sn_source_iterate(ctx, q, None, phi, tol=1e-8, max_it=600, **kw)
                 res["si_to_1e-8"] = rs["iters"] if rs["rc"] == 0 else "DNC"
                 res["seconds"] += rs["seconds"]
         return res
 
-    import numpy as np
     for k in sorted(sninputs.PIPE_PROBLEMS):
         for label, cdt in (("1", 1.0), ("1e3", 1e3), ("1e8", 1e8), ("sa0", None)):
             if time.perf_counter() - t_start > budget_s:
@@ -564,18 +585,20 @@ def bench_pipe(log, budget_s=150.0):
                 break
             base = sninputs.crooked_pipe(k, cdt, cells_per_unit=2)
             row = {"thick_share": float(base.thick_mask(1.0).mean())}
-            for name, eta in (("het_dsa", 1.0), ("full_dsa", 0.0)):
-                row[name] = run(dataclasses.replace(base, eta=eta))
+            for name, eta, diffusion, precond, inner_tol, si in PIPE_COLUMNS:
+                row[name] = run(dataclasses.replace(base, eta=eta), diffusion, precond, inner_tol, si)
             out["problems"][f"#{k} cdt={label}"] = row
     for sp in (0.0, 1e-3, 0.1, 1.0, 5.0, 10.0, 100.0):
         if time.perf_counter() - t_start > budget_s:
             out["truncated"] = True
             break
         base = sninputs.crooked_pipe((sp, 200.0, 200.0, 200.0), 1e3, cells_per_unit=2)
-        out["sigma_pipe_scan"][str(sp)] = {name: run(dataclasses.replace(base, eta=eta), si=False)
-                                           for name, eta in (("het_dsa", 1.0), ("full_dsa", 0.0))}
+        out["sigma_pipe_scan"][str(sp)] = {name: run(dataclasses.replace(base, eta=eta), diffusion, 2, 0.0, False)
+                                           for name, eta, diffusion in PIPE_SCAN_COLUMNS}
     out["seconds"] = time.perf_counter() - t_start
-    log(f"crooked pipe: {json.dumps({k: (v['het_dsa']['gmres30_to_1e-12'], v['full_dsa']['gmres30_to_1e-12']) for k, v in out['problems'].items()})}")
+    summary = {k: tuple(v[c]["gmres30_to_1e-12"] for c in ("full_nip", "full_mnip", "het_nip"))
+               for k, v in out["problems"].items()}
+    log(f"crooked pipe (full NIP, full mNIP, het NIP): {json.dumps(summary)}")
     return out
 
 

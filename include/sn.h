@@ -113,12 +113,13 @@ typedef struct {
     int cg_maxit;              /* iteration cap (SN_ERR_NOT_CONVERGED is not raised for it) */
     int mass_kind;             /* 0: Sigma_f = mass of sigma_s; 1: mass of sigma_t (Sec. 2.2) */
     int precond;               /* SN_PRECOND_BLOCK_JACOBI: inverse diagonal cell blocks.
+                                  SN_PRECOND_DIRECT: see below.
                                   SN_PRECOND_MG: one symmetric geometric-multigrid V-cycle -- damped block
                                   Jacobi on the DG level, the continuous Q1 space on the vertices of the
                                   thick cells (Galerkin operator), vertex-grid coarsening by two with
                                   (bi/tri)linear interpolation and damped Jacobi, a dense solve on <= 256
-                                  unknowns.  The hierarchy is built on the first use in a context.
-                                  SIP only. */
+                                  unknowns.  The hierarchy is built on the first use in a context
+                                  (from the SIP operator, whatever the diffusion form). */
     int diffusion;             /* the diffusion form of Sec. 3.1 whose thick principal submatrix is solved:
                                   SN_DIFFUSION_SIP (eq. SIP, penalty max(kappa_0, 8 D / h), CG as above);
                                   SN_DIFFUSION_NIP (eq. NIP: the term -int [[u]]{D dv/dn} dropped, penalty
@@ -126,11 +127,13 @@ typedef struct {
                                   kappa_0 times the mean over the face's two cells of max(0.2 / (sigma_t h), 1),
                                   the thin neighbour's sigma_t included; on a domain face the cell's own
                                   factor).  The nonsymmetric forms are solved by GMRES(SN_DSA_GMRES_RESTART),
-                                  right-preconditioned by the inverse diagonal cell blocks, zero initial guess,
-                                  to the true residual ||b - D x|| <= cg_rtol ||b|| or cg_maxit iterations;
-                                  precond must be SN_PRECOND_BLOCK_JACOBI.  mNIP with sigma_t = 0 at a thick
-                                  cell or its face neighbour returns SN_ERR_INVALID (the factor divides by
-                                  sigma_t). */
+                                  zero initial guess, to the true residual ||b - D x|| <= cg_rtol ||b|| or
+                                  cg_maxit iterations, right-preconditioned by the inverse of the form's own
+                                  diagonal cell blocks (SN_PRECOND_BLOCK_JACOBI) or by one V-cycle of the SIP
+                                  multigrid (SN_PRECOND_MG; effective where SIP and the form are close, as on a
+                                  thick-only set, not for full DSA through thin cells).  A NaN or infinite
+                                  residual returns SN_ERR_DIVERGED.  mNIP with sigma_t = 0 at a thick cell or
+                                  its face neighbour returns SN_ERR_INVALID (the factor divides by sigma_t). */
 } sn_dsa_opts;
 
 #define SN_DIFFUSION_SIP 0
@@ -140,6 +143,13 @@ typedef struct {
 
 #define SN_PRECOND_BLOCK_JACOBI 0
 #define SN_PRECOND_MG 1
+#define SN_PRECOND_DIRECT 2    /* exact solve, any form: band LU with partial pivoting of the thick matrix,
+                                  assembled and factored on the device on the first use of a form in a context
+                                  (one workgroup; milliseconds for a few thousand unknowns), then one band
+                                  solve per call.  Small systems only: nthick nn <= 8192 unknowns and
+                                  kl + ku = 2 (w + 1) nn - 2 <= 1023, w the largest slot distance between
+                                  face-neighbouring thick cells; SN_ERR_UNSUPPORTED beyond.  cg_rtol and
+                                  cg_maxit are not used; stats report 0 iterations. */
 
 typedef struct {
     int cg_iters;              /* CG (NIP, mNIP: GMRES) iterations of this call */

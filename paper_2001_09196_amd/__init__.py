@@ -7,7 +7,8 @@ the CPU: without the built library the binding raises.
 """
 from . import binding  # noqa: F401
 from .binding import (SN_DIFFUSION_MNIP, SN_DIFFUSION_NIP, SN_DIFFUSION_SIP, SN_DSA_DIAGONAL,  # noqa: F401
-                      SN_DSA_TRIANGULAR, SN_FP32, SN_FP64, SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG, Context, SnError, sn_adjoint_gradient, sn_adjoint_source, sn_dsa_thick_correct,
+                      SN_DSA_TRIANGULAR, SN_FP32, SN_FP64, SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_DIRECT,
+                      SN_PRECOND_MG, Context, SnError, sn_adjoint_gradient, sn_adjoint_source, sn_dsa_thick_correct,
                       sn_face_response, sn_gradient, sn_kernel_timing, sn_krylov_solve, sn_response, sn_response_noalloc,
                       sn_scalar_flux,
                       sn_set_kernel_timing, sn_source_iterate, sn_sweep)

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsn.so")
 SN_OK, SN_ERR_INVALID, SN_ERR_UNSUPPORTED, SN_ERR_NOMEM, SN_ERR_HIP = 0, 1, 2, 3, 4
 SN_ERR_NOT_CONVERGED, SN_ERR_DIVERGED, SN_ERR_CG_BREAKDOWN = 5, 6, 7
 SN_FP64, SN_FP32 = 0, 1
-SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG = 0, 1
+SN_PRECOND_BLOCK_JACOBI, SN_PRECOND_MG, SN_PRECOND_DIRECT = 0, 1, 2
 SN_DSA_DIAGONAL, SN_DSA_TRIANGULAR = 0, 1
 SN_DIFFUSION_SIP, SN_DIFFUSION_NIP, SN_DIFFUSION_MNIP = 0, 1, 2
 SN_DSA_GMRES_RESTART = 30
@@ -218,8 +218,9 @@ def sn_scalar_flux(ctx: Context, psi, prec: int, phi_out):
 
 def sn_dsa_thick_correct(ctx: Context, phi_old, phi_si, phi_out, cg_rtol=1e-4, cg_maxit=1000, mass_kind=0,
                          precond=0, diffusion=SN_DIFFUSION_SIP):
-    """precond: SN_PRECOND_BLOCK_JACOBI (0) or SN_PRECOND_MG (1, SIP only);
-    diffusion: SN_DIFFUSION_SIP / _NIP / _MNIP (the latter two by GMRES)."""
+    """precond: SN_PRECOND_BLOCK_JACOBI (0), SN_PRECOND_MG (1) or
+    SN_PRECOND_DIRECT (2, exact band LU for small thick systems);
+    diffusion: SN_DIFFUSION_SIP (CG) / _NIP / _MNIP (GMRES)."""
     o = sn_dsa_opts(float(cg_rtol), int(cg_maxit), int(mass_kind), int(precond), int(diffusion))
     st = sn_dsa_stats()
     rc = _check(lib().sn_dsa_thick_correct(ctx.handle, _ptr(phi_old), _ptr(phi_si), _ptr(phi_out), ctypes.byref(o),

@@ -155,10 +155,14 @@ struct sn_context {
     // GMRES inner solve of the nonsymmetric diffusion forms: full inverse
     // diagonal blocks of form binvf_op (-1: none yet), basis [restart + 1][nf],
     // dot products and their pinned copy, the singular-block flag
-    DevBuf<double> binvf, gv, gdot, gpart;
+    DevBuf<double> binvf, gv, gdot, gpart, gb, gu, gz;
     DevBuf<int> gbad;
     double* gdot_host = nullptr;
     int binvf_op = -1;
+    // exact thick solve: band LU factors of form band_op (-1: none yet)
+    DevBuf<double> band;
+    DevBuf<int> bpiv;
+    int band_op = -1, band_kl = 0, band_ku = 0, band_ldb = 0;
     int sweeps = 0;  // transport sweeps (all directions) since the last reset
     // device address of the fixed scratch of the entry points that allocate
     // nothing on this context's device (NULL if its lookup failed)
@@ -551,32 +555,30 @@ int mg_setup(sn_context* c) {
 
 bool bad_dsa_opts(const sn_dsa_opts& o) {
     return !(o.cg_rtol >= 0) || o.cg_maxit < 1 || (o.mass_kind != 0 && o.mass_kind != 1) ||
-           (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG) ||
+           (o.precond != SN_PRECOND_BLOCK_JACOBI && o.precond != SN_PRECOND_MG &&
+            o.precond != SN_PRECOND_DIRECT) ||
            (o.diffusion != SN_DIFFUSION_SIP && o.diffusion != SN_DIFFUSION_NIP &&
-            o.diffusion != SN_DIFFUSION_MNIP) ||
-           (o.diffusion != SN_DIFFUSION_SIP && o.precond != SN_PRECOND_BLOCK_JACOBI);
+            o.diffusion != SN_DIFFUSION_MNIP);
 }
 
 // The thick solve D_ff x = b of a nonsymmetric form (NIP, mNIP) by
-// GMRES(SN_DSA_GMRES_RESTART) right-preconditioned by the inverse diagonal
-// blocks B: D B^{-1} u = b from u = 0, x = B^{-1} u into ctx->cx.  Classical
+// GMRES(SN_DSA_GMRES_RESTART) right-preconditioned by M: D M^{-1} u = b from
+// u = 0, x = M^{-1} u into ctx->cx.  M^{-1} is the inverse of the form's own
+// diagonal blocks (block Jacobi, fused into the operator kernel), or one
+// V-cycle of the SIP multigrid (a fixed linear map, so the basis of u need
+// not be kept preconditioned).  Classical
 // Gram-Schmidt twice, each pass one reduction that also yields the squared
 // norm of the vector it orthogonalises (the new vector is formed in its basis
 // slot, V_{j+1}); the norm after the second pass is ||w||^2 - |h2|^2, the
 // second pass's coefficients being tiny.  Each restart starts from the true
 // residual b - D B^{-1} u, the stop test of the last restart.
-int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o, int* iters,
-              double* relres) {
+// The full inverse diagonal blocks of a nonsymmetric form, built once per
+// form; also the check that mNIP is defined (sigma_t > 0 at every thick cell
+// and its face neighbours).
+int form_blocks(sn_context* ctx, int op) {
     const DsaGeom& g = ctx->dg;
-    const long nf = (long)ctx->nthick * ctx->nn;
-    const int m = SN_DSA_GMRES_RESTART, op = o->diffusion;
     int rc;
-    if ((rc = ctx->binvf.ensure((size_t)ctx->nthick * ctx->nn * ctx->nn)) ||
-        (rc = ctx->gv.ensure((size_t)(m + 1) * nf)) || (rc = ctx->gdot.ensure(m + 2)) ||
-        (rc = ctx->gpart.ensure((size_t)(m + 2) * krylov_blocks(nf))) || (rc = ctx->gbad.ensure(1)))
-        return rc;
-    if (!ctx->gdot_host)
-        HIPCHK(hipHostMalloc((void**)&ctx->gdot_host, (m + 2) * sizeof(double), hipHostMallocDefault));
+    if ((rc = ctx->binvf.ensure((size_t)ctx->nthick * ctx->nn * ctx->nn)) || (rc = ctx->gbad.ensure(1))) return rc;
     if (ctx->binvf_op != op) {
         HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
         HIPCHK(launch_block_inverse_full(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p,
@@ -593,9 +595,96 @@ int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, cons
         }
         ctx->binvf_op = op;
     }
+    return 0;
+}
+
+// The exact thick solve of any form for small systems: the band LU factors,
+// built on the device once per form (SN_ERR_UNSUPPORTED beyond the solve
+// kernel's limits: nthick nn <= 8192 unknowns, kl + ku < 1024), then
+// x = D^{-1} b into ctx->cx.
+int dsa_direct(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o) {
+    const DsaGeom& g = ctx->dg;
+    const long nf = (long)ctx->nthick * ctx->nn;
+    const int op = o->diffusion;
+    int rc;
+    if (op != SN_DIFFUSION_SIP && (rc = form_blocks(ctx, op))) return rc;
+    if (ctx->band_op != op) {
+        if (nf > kBandSolveMaxN)
+            return fail(SN_ERR_UNSUPPORTED, "direct thick solve: %ld unknowns exceed %ld", nf, kBandSolveMaxN);
+        if ((rc = ctx->gbad.ensure(1))) return rc;
+        HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+        HIPCHK(launch_band_width(g, ctx->nbr.p, ctx->gbad.p, ctx->stream));
+        int wc = 0;
+        HIPCHK(hipMemcpyAsync(&wc, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const int kl = (wc + 1) * ctx->nn - 1, ku = kl;
+        if (kl + ku > kBandMaxWidth)
+            return fail(SN_ERR_UNSUPPORTED, "direct thick solve: band half width %d too large", kl);
+        const int ldb = 2 * kl + ku + 1;
+        if ((rc = ctx->band.ensure((size_t)nf * ldb)) || (rc = ctx->bpiv.ensure(nf)) || (rc = ctx->gb.ensure(nf)))
+            return rc;
+        ctx->band_op = -1;
+        HIPCHK(hipMemsetAsync(ctx->band.p, 0, (size_t)nf * ldb * sizeof(double), ctx->stream));
+        HIPCHK(launch_band_assemble(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, kl, ldb, ctx->band.p,
+                                    ctx->stream));
+        HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+        HIPCHK(launch_band_factor(nf, kl, ku, ldb, ctx->band.p, ctx->bpiv.p, ctx->gbad.p, ctx->stream));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (bad) return fail(SN_ERR_INVALID, "direct thick solve: the diffusion matrix is singular");
+        ctx->band_op = op;
+        ctx->band_kl = kl;
+        ctx->band_ku = ku;
+        ctx->band_ldb = ldb;
+    }
+    HIPCHK(launch_dsa_rhs_vec(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->gb.p,
+                              ctx->stream));
+    HIPCHK(launch_band_solve(nf, ctx->band_kl, ctx->band_ku, ctx->band_ldb, ctx->band.p, ctx->bpiv.p, ctx->gb.p,
+                             ctx->cx.p, ctx->stream));
+    return 0;
+}
+
+int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o, int* iters,
+              double* relres) {
+    const DsaGeom& g = ctx->dg;
+    const long nf = (long)ctx->nthick * ctx->nn;
+    const int m = SN_DSA_GMRES_RESTART, op = o->diffusion;
+    int rc;
+    const bool mg = o->precond == SN_PRECOND_MG;
+    if ((rc = form_blocks(ctx, op))) return rc;
+    if ((rc = ctx->gv.ensure((size_t)(m + 1) * nf)) || (rc = ctx->gdot.ensure(m + 2)) ||
+        (rc = ctx->gpart.ensure((size_t)(m + 2) * krylov_blocks(nf))) || (rc = ctx->gb.ensure(nf)) ||
+        (rc = ctx->gu.ensure(nf)) || (mg && (rc = ctx->gz.ensure(nf))))
+        return rc;
+    if (mg && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
+    if (!ctx->gdot_host)
+        HIPCHK(hipHostMalloc((void**)&ctx->gdot_host, (m + 2) * sizeof(double), hipHostMallocDefault));
     double* V = ctx->gv.p;
-    double* b = ctx->cr.p;
-    double* u = ctx->cz.p;
+    double* b = ctx->gb.p;
+    double* u = ctx->gu.p;
+    // the V-cycle kernels stop early once the CG status says done
+    if (mg) HIPCHK(hipMemsetAsync(ctx->scal.p, 0, sizeof(CgScalars), ctx->stream));
+    // out = M^{-1} v (multigrid only)
+    auto vcycle = [&](const double* v, double* out) -> int {
+        HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, v, ctx->cz0.p,
+                                ctx->cres.p, out, ctx->mg, ctx->mg_lc, ctx->mg_omega0, ctx->partb.p, ctx->nparts,
+                                ctx->scal.p, ctx->stream));
+        return 0;
+    };
+    // w = D M^{-1} v, or b - D M^{-1} v with bb given
+    auto apply = [&](const double* v, const double* bb_, double* w) -> int {
+        int e;
+        if (mg) {
+            if ((e = vcycle(v, ctx->gz.p))) return e;
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, nullptr, ctx->gz.p,
+                                    bb_, w, ctx->stream));
+        } else {
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p, v, bb_,
+                                    w, ctx->stream));
+        }
+        return 0;
+    };
     auto dotk = [&](int k, const double* Vb, const double* w, double* out) -> int {
         HIPCHK(launch_multi_dot(nf, k, Vb, w, ctx->gpart.p, ctx->gdot.p, ctx->gdot_host, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -617,8 +706,7 @@ int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, cons
         if (first) {
             HIPCHK(hipMemcpyAsync(V, b, nf * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         } else {
-            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p, u, b, V,
-                                    ctx->stream));
+            if ((rc = apply(u, b, V))) return rc;
             double rr;
             if ((rc = dotk(1, V, V, &rr))) return rc;
             beta = std::sqrt(rr);
@@ -632,8 +720,7 @@ int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, cons
         int j = 0;
         for (; j < m && it < o->cg_maxit; ++j) {
             double* vn = V + (size_t)(j + 1) * nf;
-            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p,
-                                    V + (size_t)j * nf, nullptr, vn, ctx->stream));
+            if ((rc = apply(V + (size_t)j * nf, nullptr, vn))) return rc;
             if ((rc = dotk(j + 2, V, vn, h.data()))) return rc;
             HIPCHK(launch_multi_axpy(nf, j + 1, V, ctx->gdot.p, -1.0, vn, ctx->stream));
             if ((rc = dotk(j + 2, V, vn, h2.data()))) return rc;
@@ -679,7 +766,11 @@ int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, cons
             HIPCHK(hipStreamSynchronize(ctx->stream));
         }
     }
-    HIPCHK(launch_full_block_apply(g, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
+    if (mg) {
+        if ((rc = vcycle(u, ctx->cx.p))) return rc;
+    } else {
+        HIPCHK(launch_full_block_apply(g, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
+    }
     *iters = it;
     *relres = bnorm > 0.0 ? beta / bnorm : 0.0;
     return 0;
@@ -728,12 +819,18 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
         }
         return 0;
     };
-    if (o->diffusion != SN_DIFFUSION_SIP) {
+    if (o->diffusion != SN_DIFFUSION_SIP || o->precond == SN_PRECOND_DIRECT) {
         if (res_part) HIPCHK(launch_residual_final(res_nparts, res_part, ctx->res3.p, ctx->hpin->r3, ctx->stream));
         if (ctx->timing == 1 && (rc = record_event(ctx, &e0))) return rc;
         int its = 0;
         double rel = 0.0;
-        if ((rc = dsa_gmres(ctx, phi_old, phi_si, o, &its, &rel))) return rc;
+        if (o->precond == SN_PRECOND_DIRECT) {
+            if ((rc = dsa_direct(ctx, phi_old, phi_si, o))) return rc;
+            // the host reads the residual scalars the caller asked for
+            if (res_part) HIPCHK(hipStreamSynchronize(ctx->stream));
+        } else if ((rc = dsa_gmres(ctx, phi_old, phi_si, o, &its, &rel))) {
+            return rc;
+        }
         if ((rc = scatter())) return rc;
         if (ctx->timing == 1) {
             if ((rc = record_event(ctx, &e1))) return rc;
@@ -993,6 +1090,16 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->kzero.release();
     ctx->kdot.release();
     ctx->kpart.release();
+    ctx->binvf.release();
+    ctx->gv.release();
+    ctx->gdot.release();
+    ctx->gpart.release();
+    ctx->gb.release();
+    ctx->gu.release();
+    ctx->gz.release();
+    ctx->gbad.release();
+    ctx->band.release();
+    ctx->bpiv.release();
     if (ctx->kdot_host) (void)hipHostFree(ctx->kdot_host);
     if (ctx->gdot_host) (void)hipHostFree(ctx->gdot_host);
     delete ctx;

@@ -628,7 +628,8 @@ __device__ __forceinline__ void full_block_apply(const double* __restrict__ binv
 }
 
 // w = D_ff B^{-1} v (right-preconditioned operator; the neighbours' B^{-1} v
-// are formed on the fly), or with b given the residual w = b - D_ff B^{-1} v
+// are formed on the fly), or with b given the residual w = b - D_ff B^{-1} v;
+// binv = nullptr: B = I
 template <int NN, int OP>
 __global__ void __launch_bounds__(256) nip_apply_kernel(DsaGeom g, const int* __restrict__ thick_cell,
                                                         const int* __restrict__ nbr,
@@ -637,7 +638,14 @@ __global__ void __launch_bounds__(256) nip_apply_kernel(DsaGeom g, const int* __
                                                         const double* __restrict__ binv,
                                                         const double* __restrict__ v, const double* __restrict__ b,
                                                         double* __restrict__ w) {
-    auto get = [&](int slot, double out[NN]) { full_block_apply<NN>(binv, g.nthick, slot, v, out); };
+    auto get = [&](int slot, double out[NN]) {
+        if (binv) {
+            full_block_apply<NN>(binv, g.nthick, slot, v, out);
+        } else {
+#pragma unroll
+            for (int n = 0; n < NN; ++n) out[n] = v[(long)slot * NN + n];
+        }
+    };
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.nthick; t += gridDim.x * blockDim.x) {
         double uK[NN], o[NN];
         get(t, uK);
@@ -738,6 +746,221 @@ hipError_t launch_dsa_rhs_vec(const DsaGeom& g, const int* thick_cell, const dou
     else
         hipLaunchKernelGGL(dsa_rhs_vec_kernel<8>, dim3(blocks), dim3(256), 0, st, g, thick_cell, sigma_t, sigma_s,
                            mass_kind, phi_old, phi_si, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exact thick solve for small systems: band LU with partial pivoting
+// ---------------------------------------------------------------------------
+// The thick matrix in band storage, row i holding columns i - kl .. i + kl + ku
+// at lu[i ldb + j - i + kl] (the extra kl columns take the fill of the row
+// swaps).  Each thick cell writes its rows: the diagonal block and the blocks
+// of its thick face neighbours, one column at a time, by applying the form
+// to unit vectors.
+template <int NN, int OP>
+__global__ void __launch_bounds__(128) band_assemble_kernel(DsaGeom g, const int* __restrict__ thick_cell,
+                                                            const int* __restrict__ nbr,
+                                                            const double* __restrict__ sigma_t,
+                                                            const double* __restrict__ sigma_s, int kl, int ldb,
+                                                            double* __restrict__ lu) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x) {
+        const long cell = thick_cell[s];
+        for (int f = -1; f < 2 * DIM; ++f) {
+            const int t = f < 0 ? s : nbr[s * 2 * DIM + f];
+            if (t < 0) continue;
+            for (int c = 0; c < NN; ++c) {
+                double uK[NN], col[NN];
+                for (int n = 0; n < NN; ++n) uK[n] = (f < 0 && n == c) ? 1.0 : 0.0;
+                auto unit = [&](int slot, double o[NN]) {
+                    for (int n = 0; n < NN; ++n) o[n] = (f >= 0 && slot == t && n == c) ? 1.0 : 0.0;
+                };
+                sip_rows<NN, OP>(g, s, cell, nbr, thick_cell, sigma_t, sigma_s, uK, unit, col);
+                for (int r = 0; r < NN; ++r) {
+                    const long i = (long)s * NN + r, j = (long)t * NN + c;
+                    lu[i * ldb + (j - i + kl)] = col[r];
+                }
+            }
+        }
+    }
+}
+
+// largest slot distance to a thick face neighbour (the band's half width in cells)
+template <int NN>
+__global__ void __launch_bounds__(256) band_width_kernel(DsaGeom g, const int* __restrict__ nbr, int* __restrict__ w) {
+    constexpr int DIM = NN == 4 ? 2 : 3;
+    int m = 0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.nthick; s += gridDim.x * blockDim.x)
+        for (int f = 0; f < 2 * DIM; ++f) {
+            const int t = nbr[s * 2 * DIM + f];
+            if (t >= 0) m = max(m, abs(t - s));
+        }
+    atomicMax(w, m);
+}
+
+// In-place band LU with partial pivoting by one workgroup: column k's pivot
+// is the entry of largest magnitude among rows k .. k + kl (the first such
+// row on ties); rows k and p are swapped over columns k .. k + kl + ku, the
+// multipliers stored below the diagonal, and the trailing band block updated.
+// The phases of a column are separated by workgroup barriers, which also
+// order the global-memory accesses of the workgroup's waves.  *bad = 1 on a
+// zero pivot (the factorisation then stops).
+constexpr int kBandThreads = 1024;
+__global__ void __launch_bounds__(kBandThreads) band_factor_kernel(long n, int kl, int ku, int ldb,
+                                                                   double* __restrict__ lu, int* __restrict__ piv,
+                                                                   int* __restrict__ bad) {
+    __shared__ double sv[kBandThreads / 64];
+    __shared__ long si[kBandThreads / 64];
+    __shared__ long sp;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    auto at = [&](long i, long j) -> double& { return lu[i * ldb + (j - i + kl)]; };
+    for (long k = 0; k < n; ++k) {
+        const long last = min(n - 1, k + (long)kl), jend = min(n - 1, k + (long)kl + ku);
+        double best = -1.0;
+        long bi = k;
+        for (long i = k + t; i <= last; i += kBandThreads) {
+            const double v = fabs(at(i, k));
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(best, off);
+            const long oi = __shfl_xor(bi, off);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            sv[wv] = best;
+            si[wv] = bi;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double b = sv[0];
+            long p = si[0];
+            for (int q = 1; q < kBandThreads / 64; ++q)
+                if (sv[q] > b || (sv[q] == b && si[q] < p)) {
+                    b = sv[q];
+                    p = si[q];
+                }
+            sp = b > 0.0 ? p : -1;
+            piv[k] = (int)(b > 0.0 ? p : k);
+            if (!(b > 0.0)) *bad = 1;
+        }
+        __syncthreads();
+        const long p = sp;
+        if (p < 0) return;
+        if (p != k)
+            for (long j = k + t; j <= jend; j += kBandThreads) {
+                const double a = at(k, j);
+                at(k, j) = at(p, j);
+                at(p, j) = a;
+            }
+        __syncthreads();
+        const double inv = 1.0 / at(k, k);
+        for (long i = k + 1 + t; i <= last; i += kBandThreads) at(i, k) *= inv;
+        __syncthreads();
+        const long R = last - k, C = jend - k;
+        for (long e = t; e < R * C; e += kBandThreads) {
+            const long i = k + 1 + e / C, j = k + 1 + e % C;
+            at(i, j) = fma(-at(i, k), at(k, j), at(i, j));
+        }
+        __syncthreads();
+    }
+}
+
+// x = D^{-1} b from the band factors by one workgroup, the vector in LDS
+// (n <= kBandMaxN): forward elimination with the row swaps in factorisation
+// order, then back substitution by columns.  Each thread loads its factor
+// entry of the next column ahead of the barrier.
+constexpr int kBandMaxN = 8192;
+__global__ void __launch_bounds__(kBandThreads) band_solve_kernel(long n, int kl, int ku, int ldb,
+                                                                  const double* __restrict__ lu,
+                                                                  const int* __restrict__ piv,
+                                                                  const double* __restrict__ b,
+                                                                  double* __restrict__ x) {
+    __shared__ double xs[kBandMaxN];
+    const int t = threadIdx.x;
+    auto at = [&](long i, long j) { return lu[i * ldb + (j - i + kl)]; };
+    for (long i = t; i < n; i += kBandThreads) xs[i] = b[i];
+    __syncthreads();
+    // forward: rows k + 1 .. k + kl of column k; thread t takes row k + 1 + t
+    // (kl < kBandThreads: one row per thread)
+    double lnext = (1 + t < n && t < kl) ? at(1 + t, 0) : 0.0;
+    for (long k = 0; k < n; ++k) {
+        if (t == 0) {
+            const long p = piv[k];
+            if (p != k) {
+                const double a = xs[k];
+                xs[k] = xs[p];
+                xs[p] = a;
+            }
+        }
+        const double l = lnext;
+        const long i = k + 1 + t;
+        lnext = (i + 1 < n && t < kl) ? at(i + 1, k + 1) : 0.0;
+        __syncthreads();
+        if (t < kl && i < n) xs[i] = fma(-l, xs[k], xs[i]);
+        __syncthreads();
+    }
+    // backward: x_i = xs_i / U_ii, then rows i - kl - ku .. i - 1 of column i
+    const int w = kl + ku;
+    double unext = (n - 2 - t >= 0 && t < w) ? at(n - 2 - t, n - 1) : 0.0;
+    double dnext = at(n - 1, n - 1);
+    for (long i = n - 1; i >= 0; --i) {
+        const double u = unext, d = dnext;
+        const long j = i - 1 - t;
+        unext = (j - 1 >= 0 && t < w && i >= 1) ? at(j - 1, i - 1) : 0.0;
+        dnext = i >= 1 ? at(i - 1, i - 1) : 0.0;
+        const double xi = xs[i] / d;
+        __syncthreads();
+        if (t == 0) xs[i] = xi;
+        if (t < w && j >= 0) xs[j] = fma(-u, xi, xs[j]);
+        __syncthreads();
+    }
+    for (long i = t; i < n; i += kBandThreads) x[i] = xs[i];
+}
+
+hipError_t launch_band_width(const DsaGeom& g, const int* nbr, int* w, hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 256);
+    if (g.nn == 4) hipLaunchKernelGGL(band_width_kernel<4>, dim3(blocks), dim3(256), 0, st, g, nbr, w);
+    else hipLaunchKernelGGL(band_width_kernel<8>, dim3(blocks), dim3(256), 0, st, g, nbr, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_assemble(const DsaGeom& g, int op, const int* thick_cell, const int* nbr,
+                                const double* sigma_t, const double* sigma_s, int kl, int ldb, double* lu,
+                                hipStream_t st) {
+    if (g.nthick == 0) return hipSuccess;
+    const int blocks = grid_of(g.nthick, 128);
+#define SN_BA(NN, OP)                                                                                         \
+    hipLaunchKernelGGL((band_assemble_kernel<NN, OP>), dim3(blocks), dim3(128), 0, st, g, thick_cell, nbr, sigma_t, \
+                       sigma_s, kl, ldb, lu)
+    if (g.nn == 4) {
+        if (op == SN_DIFFUSION_SIP) SN_BA(4, SN_DIFFUSION_SIP);
+        else if (op == SN_DIFFUSION_NIP) SN_BA(4, SN_DIFFUSION_NIP);
+        else SN_BA(4, SN_DIFFUSION_MNIP);
+    } else {
+        if (op == SN_DIFFUSION_SIP) SN_BA(8, SN_DIFFUSION_SIP);
+        else if (op == SN_DIFFUSION_NIP) SN_BA(8, SN_DIFFUSION_NIP);
+        else SN_BA(8, SN_DIFFUSION_MNIP);
+    }
+#undef SN_BA
+    return hipGetLastError();
+}
+
+hipError_t launch_band_factor(long n, int kl, int ku, int ldb, double* lu, int* piv, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(band_factor_kernel, dim3(1), dim3(kBandThreads), 0, st, n, kl, ku, ldb, lu, piv, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_solve(long n, int kl, int ku, int ldb, const double* lu, const int* piv, const double* b,
+                             double* x, hipStream_t st) {
+    hipLaunchKernelGGL(band_solve_kernel, dim3(1), dim3(kBandThreads), 0, st, n, kl, ku, ldb, lu, piv, b, x);
     return hipGetLastError();
 }
 

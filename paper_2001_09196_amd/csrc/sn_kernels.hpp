@@ -197,7 +197,8 @@ hipError_t launch_block_jacobi(const DsaGeom& g, const int* thick_cell, const in
 // nonsymmetric diffusion forms (op = 1 NIP, 2 mNIP): full inverse of the
 // diagonal blocks (nn * nn words per thick cell, element-major; *bad set for
 // a singular block or, with mNIP, sigma_t <= 0 at a thick cell or its
-// neighbour), w = D B^{-1} v or w = b - D B^{-1} v, x = B^{-1} u, and the
+// neighbour), w = D B^{-1} v or w = b - D B^{-1} v (binv = nullptr: B = I),
+// x = B^{-1} u, and the
 // thick right-hand side b = coef M (phi_si - phi_old)
 hipError_t launch_block_inverse_full(const DsaGeom& g, int op, const int* thick_cell, const int* nbr,
                                      const double* sigma_t, const double* sigma_s, double* binv, int* bad,
@@ -206,6 +207,20 @@ hipError_t launch_nip_apply(const DsaGeom& g, int op, const int* thick_cell, con
                             const double* sigma_s, const double* binv, const double* v, const double* b, double* w,
                             hipStream_t st);
 hipError_t launch_full_block_apply(const DsaGeom& g, const double* binv, const double* u, double* x, hipStream_t st);
+// Exact thick solve by band LU (any form): half width in cells into *w
+// (atomic max, zero it first), band assembly (lu zeroed first, row i at
+// lu[i ldb + j - i + kl]), factorisation and solve by one workgroup each.
+// The solve needs n <= 8192 (the vector in LDS) and kl + ku <= 1023 (one
+// row of a column per thread).
+constexpr long kBandSolveMaxN = 8192;
+constexpr int kBandMaxWidth = 1023;
+hipError_t launch_band_width(const DsaGeom& g, const int* nbr, int* w, hipStream_t st);
+hipError_t launch_band_assemble(const DsaGeom& g, int op, const int* thick_cell, const int* nbr,
+                                const double* sigma_t, const double* sigma_s, int kl, int ldb, double* lu,
+                                hipStream_t st);
+hipError_t launch_band_factor(long n, int kl, int ku, int ldb, double* lu, int* piv, int* bad, hipStream_t st);
+hipError_t launch_band_solve(long n, int kl, int ku, int ldb, const double* lu, const int* piv, const double* b,
+                             double* x, hipStream_t st);
 hipError_t launch_dsa_rhs_vec(const DsaGeom& g, const int* thick_cell, const double* sigma_t, const double* sigma_s,
                               int mass_kind, const double* phi_old, const double* phi_si, double* b, hipStream_t st);
 
