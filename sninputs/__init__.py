@@ -109,6 +109,7 @@ class Problem:
     w: np.ndarray            # [D]
     eta: float = 1.0         # thick threshold: a cell is thick iff sigma_s >= eta
     meta: dict = dataclasses.field(default_factory=dict)
+    order: int = 1           # DG order p: Q_p on the (p + 1)^dim Gauss-Lobatto nodes of each cell
 
     @property
     def ncells(self) -> int:
@@ -116,7 +117,7 @@ class Problem:
 
     @property
     def nn(self) -> int:
-        return 4 if self.dim == 2 else 8
+        return (self.order + 1) ** self.dim
 
     @property
     def ndirs(self) -> int:
