@@ -30,6 +30,7 @@ Sec. 4):
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -91,19 +92,25 @@ class Ref1D:
         self.dl1 = np.array([lagrange_deriv(self.nodes, k, 1.0) for k in range(n)])
 
 
+@functools.lru_cache(maxsize=None)
+def ref1d(p):
+    """The Ref1D tables of order p, built once."""
+    return Ref1D(p)
+
+
 def _kron2(Y, X):
     """Matrix of the 2D operator X along x, Y along y, for nodes n = i + np j."""
     return np.kron(Y, X)
 
 
 def cell_mass(p, h):
-    r = Ref1D(p)
+    r = ref1d(p)
     return _kron2(h[1] * r.M, h[0] * r.M)
 
 
 def cell_matrix(p, h, om, sigma_t):
     """Transport matrix of one cell for direction om (2D)."""
-    r = Ref1D(p)
+    r = ref1d(p)
     n = r.np
     B = []
     for a in range(2):
@@ -128,7 +135,7 @@ def sweep_src(prob, src, inflow=None, sigma_t=None):
     (the total isotropic source density), lexicographic upwind order."""
     p = prob.order
     assert prob.dim == 2
-    r = Ref1D(p)
+    r = ref1d(p)
     n = r.np
     nx, ny = prob.nx, prob.ny
     h = prob.h
@@ -200,7 +207,7 @@ def kappa0(prob, axis):
 def dsa_dense(prob, eta=None, form=SIP, sigma_t=None, sigma_s=None):
     """Dense D_ff of the given form on the thick cells, and the thick cell list."""
     p = prob.order
-    r = Ref1D(p)
+    r = ref1d(p)
     n = r.np
     nn = n * n
     nx, ny = prob.nx, prob.ny

@@ -41,7 +41,7 @@ class SnError(RuntimeError):
 
 class sn_mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
-                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double)]
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double), ("order", ctypes.c_int)]
 
 
 class sn_quad(ctypes.Structure):
@@ -158,18 +158,20 @@ class Context:
 
     sigma_t, sigma_s: FP64 device tensors [ncells]; omega [D, 3] and w [D] are
     host arrays.  The context's stream is torch's current stream unless given.
+    order: DG order (1: Q1; 2, 3: Q_p in 2D, a subset of the entry points).
     """
 
-    def __init__(self, dim, nx, ny, nz, h, omega, w, sigma_t, sigma_s, eta=1.0, stream=None):
+    def __init__(self, dim, nx, ny, nz, h, omega, w, sigma_t, sigma_s, eta=1.0, stream=None, order=1):
         import torch
         self.dim, self.nx, self.ny, self.nz = int(dim), int(nx), int(ny), int(nz)
-        self.nn = 4 if self.dim == 2 else 8
+        self.order = int(order)
+        self.nn = (self.order + 1) ** self.dim
         self.ncells = self.nx * self.ny * self.nz
         self._omega = np.ascontiguousarray(omega, dtype=np.float64)
         self._w = np.ascontiguousarray(w, dtype=np.float64)
         self.ndirs = int(self._w.shape[0])
         self.mesh = sn_mesh(self.dim, self.nx, self.ny, self.nz, float(h[0]), float(h[1]),
-                            float(h[2]) if len(h) > 2 else 1.0)
+                            float(h[2]) if len(h) > 2 else 1.0, self.order)
         quad = sn_quad(self.ndirs, self._omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         for t in (sigma_t, sigma_s):

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsn.so")
-SOURCES = ["sweep.hip", "flux.hip", "dsa.hip", "noalloc.hip", "capi.hip"]
+SOURCES = ["sweep.hip", "flux.hip", "dsa.hip", "hp.hip", "noalloc.hip", "capi.hip"]
 HOST_ONLY = {"capi.hip"}  # host code only: no device compilation pass
 # The sweeps issue from one or two waves per SIMD, so their speed depends on how
 # well independent instructions are interleaved in the in-order stream; the

@@ -15,6 +15,7 @@
 
 #include "../../include/sn.h"
 #include "sn_kernels.hpp"
+#include "hp.hpp"
 #include "mg_host.hpp"
 
 using namespace sn;
@@ -159,6 +160,16 @@ struct sn_context {
     DevBuf<int> gbad;
     double* gdot_host = nullptr;
     int binvf_op = -1;
+    // order p >= 2 (2D): the tables, the thick block rows of form hblk_op
+    // (-1: none yet) and their columns, and a copy of dg with the Q1 node
+    // count (for the neighbour-table and band-width kernels, which only use
+    // the dimension)
+    int order = 1;
+    HpTab hp{};
+    DevBuf<double> hblk;
+    DevBuf<int> hcol;
+    int hblk_op = -1;
+    DsaGeom dg4{};
     // exact thick solve: band LU factors of form band_op (-1: none yet)
     DevBuf<double> band;
     DevBuf<int> bpiv;
@@ -199,10 +210,13 @@ int check_mesh(const sn_mesh* m) {
         return fail(SN_ERR_INVALID, "cell widths must be positive and finite");
     long nc = (long)m->nx * m->ny * m->nz;
     if (nc > (1L << 31) - 1) return fail(SN_ERR_UNSUPPORTED, "more than 2^31 - 1 cells");
+    if (m->order < 0 || m->order > 3) return fail(SN_ERR_INVALID, "order must be 0..3 (got %d)", m->order);
+    if (m->order >= 2 && m->dim != 2) return fail(SN_ERR_UNSUPPORTED, "order %d is built for 2D only", m->order);
     return 0;
 }
 
 long inflow_size(const sn_mesh* m) {
+    if (m->order >= 2) return (long)(m->order + 1) * (m->nx + m->ny);
     if (m->dim == 2) return 2L * m->ny + 2L * m->nx;
     return 4L * ((long)m->ny * m->nz + (long)m->nx * m->nz + (long)m->nx * m->ny);
 }
@@ -645,54 +659,29 @@ int dsa_direct(sn_context* ctx, const double* phi_old, const double* phi_si, con
     return 0;
 }
 
-int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o, int* iters,
-              double* relres) {
-    const DsaGeom& g = ctx->dg;
-    const long nf = (long)ctx->nthick * ctx->nn;
-    const int m = SN_DSA_GMRES_RESTART, op = o->diffusion;
+// GMRES(SN_DSA_GMRES_RESTART) on the thick vector (nf values): D M^{-1} u = b
+// from u = 0, b in ctx->gb, u in ctx->gu.  apply(v, bb, w) writes
+// w = D M^{-1} v, or bb - D M^{-1} v when bb is given; finish(u) forms
+// x = M^{-1} u in ctx->cx.  Stops on the true residual of a restart.
+template <typename Apply, typename Finish>
+int gmres_core(sn_context* ctx, long nf, const sn_dsa_opts* o, Apply apply, Finish finish, int* iters,
+               double* relres) {
+    const int m = SN_DSA_GMRES_RESTART;
     int rc;
-    const bool mg = o->precond == SN_PRECOND_MG;
-    if ((rc = form_blocks(ctx, op))) return rc;
     if ((rc = ctx->gv.ensure((size_t)(m + 1) * nf)) || (rc = ctx->gdot.ensure(m + 2)) ||
-        (rc = ctx->gpart.ensure((size_t)(m + 2) * krylov_blocks(nf))) || (rc = ctx->gb.ensure(nf)) ||
-        (rc = ctx->gu.ensure(nf)) || (mg && (rc = ctx->gz.ensure(nf))))
+        (rc = ctx->gpart.ensure((size_t)(m + 2) * krylov_blocks(nf))))
         return rc;
-    if (mg && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
     if (!ctx->gdot_host)
         HIPCHK(hipHostMalloc((void**)&ctx->gdot_host, (m + 2) * sizeof(double), hipHostMallocDefault));
     double* V = ctx->gv.p;
     double* b = ctx->gb.p;
     double* u = ctx->gu.p;
-    // the V-cycle kernels stop early once the CG status says done
-    if (mg) HIPCHK(hipMemsetAsync(ctx->scal.p, 0, sizeof(CgScalars), ctx->stream));
-    // out = M^{-1} v (multigrid only)
-    auto vcycle = [&](const double* v, double* out) -> int {
-        HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, v, ctx->cz0.p,
-                                ctx->cres.p, out, ctx->mg, ctx->mg_lc, ctx->mg_omega0, ctx->partb.p, ctx->nparts,
-                                ctx->scal.p, ctx->stream));
-        return 0;
-    };
-    // w = D M^{-1} v, or b - D M^{-1} v with bb given
-    auto apply = [&](const double* v, const double* bb_, double* w) -> int {
-        int e;
-        if (mg) {
-            if ((e = vcycle(v, ctx->gz.p))) return e;
-            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, nullptr, ctx->gz.p,
-                                    bb_, w, ctx->stream));
-        } else {
-            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p, v, bb_,
-                                    w, ctx->stream));
-        }
-        return 0;
-    };
     auto dotk = [&](int k, const double* Vb, const double* w, double* out) -> int {
         HIPCHK(launch_multi_dot(nf, k, Vb, w, ctx->gpart.p, ctx->gdot.p, ctx->gdot_host, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         for (int i = 0; i < k; ++i) out[i] = ctx->gdot_host[i];
         return 0;
     };
-    HIPCHK(launch_dsa_rhs_vec(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, b,
-                              ctx->stream));
     HIPCHK(hipMemsetAsync(u, 0, nf * sizeof(double), ctx->stream));
     double bb;
     if ((rc = dotk(1, b, b, &bb))) return rc;
@@ -766,14 +755,212 @@ int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, cons
             HIPCHK(hipStreamSynchronize(ctx->stream));
         }
     }
-    if (mg) {
-        if ((rc = vcycle(u, ctx->cx.p))) return rc;
-    } else {
-        HIPCHK(launch_full_block_apply(g, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
-    }
+    if ((rc = finish(u))) return rc;
     *iters = it;
     *relres = bnorm > 0.0 ? beta / bnorm : 0.0;
     return 0;
+}
+
+int dsa_gmres(sn_context* ctx, const double* phi_old, const double* phi_si, const sn_dsa_opts* o, int* iters,
+              double* relres) {
+    const DsaGeom& g = ctx->dg;
+    const long nf = (long)ctx->nthick * ctx->nn;
+    const int op = o->diffusion;
+    int rc;
+    const bool mg = o->precond == SN_PRECOND_MG;
+    if ((rc = form_blocks(ctx, op))) return rc;
+    if ((rc = ctx->gb.ensure(nf)) || (rc = ctx->gu.ensure(nf)) || (mg && (rc = ctx->gz.ensure(nf)))) return rc;
+    if (mg && !ctx->mg_ready && (rc = mg_setup(ctx))) return rc;
+    // the V-cycle kernels stop early once the CG status says done
+    if (mg) HIPCHK(hipMemsetAsync(ctx->scal.p, 0, sizeof(CgScalars), ctx->stream));
+    // out = M^{-1} v (multigrid only)
+    auto vcycle = [&](const double* v, double* out) -> int {
+        HIPCHK(launch_mg_vcycle(g, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binv.p, v, ctx->cz0.p,
+                                ctx->cres.p, out, ctx->mg, ctx->mg_lc, ctx->mg_omega0, ctx->partb.p, ctx->nparts,
+                                ctx->scal.p, ctx->stream));
+        return 0;
+    };
+    auto apply = [&](const double* v, const double* bb_, double* w) -> int {
+        int e;
+        if (mg) {
+            if ((e = vcycle(v, ctx->gz.p))) return e;
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, nullptr, ctx->gz.p,
+                                    bb_, w, ctx->stream));
+        } else {
+            HIPCHK(launch_nip_apply(g, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p, ctx->binvf.p, v, bb_,
+                                    w, ctx->stream));
+        }
+        return 0;
+    };
+    auto finish = [&](const double* u) -> int {
+        if (mg) return vcycle(u, ctx->cx.p);
+        HIPCHK(launch_full_block_apply(g, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
+        return 0;
+    };
+    HIPCHK(launch_dsa_rhs_vec(g, ctx->thick.p, ctx->sigt.p, ctx->sigs.p, o->mass_kind, phi_old, phi_si, ctx->gb.p,
+                              ctx->stream));
+    return gmres_core(ctx, nf, o, apply, finish, iters, relres);
+}
+
+// The thick correction at order p >= 2 (2D): the block rows of the form,
+// assembled once per form (with the full inverse diagonal blocks), then
+// GMRES right-preconditioned by those inverses or the exact band LU
+// (SN_PRECOND_DIRECT, same limits as at order 1); x into ctx->cx, then the
+// scatter phi_out = phi_si + P x.
+int dsa_hp(sn_context* ctx, const double* phi_old, const double* phi_si, double* phi_out, const sn_dsa_opts* o,
+           sn_dsa_stats* stats) {
+    const long n = ctx->nc * ctx->nn;
+    const int nn = ctx->nn, nt = ctx->nthick, op = o->diffusion;
+    const long nf = (long)nt * nn;
+    int its = 0;
+    double rel = 0.0;
+    int rc;
+    if (o->precond == SN_PRECOND_MG)
+        return fail(SN_ERR_UNSUPPORTED, "the multigrid preconditioner is built for order 1 only");
+    if (nt == 0) {
+        if (phi_out != phi_si)
+            HIPCHK(hipMemcpyAsync(phi_out, phi_si, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+        if (ctx->hblk_op != op) {
+            if ((rc = ctx->hblk.ensure((size_t)nt * 5 * nn * nn)) || (rc = ctx->hcol.ensure((size_t)nt * 5)) ||
+                (rc = ctx->binvf.ensure((size_t)nt * nn * nn)) || (rc = ctx->gbad.ensure(1)))
+                return rc;
+            ctx->hblk_op = -1;
+            ctx->band_op = -1;
+            HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+            HIPCHK(launch_hp_assemble(ctx->hp, ctx->dg, op, ctx->thick.p, ctx->nbr.p, ctx->sigt.p, ctx->sigs.p,
+                                      ctx->hblk.p, ctx->hcol.p, ctx->gbad.p, ctx->stream));
+            HIPCHK(launch_hp_block_inverse(nn, nt, ctx->hblk.p, ctx->binvf.p, ctx->gbad.p, ctx->stream));
+            int bad = 0;
+            HIPCHK(hipMemcpyAsync(&bad, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            if (bad)
+                return fail(SN_ERR_INVALID, "order-%d diffusion: sigma_t <= 0 next to a thick cell (mNIP) or a "
+                            "singular diagonal block", ctx->hp.p);
+            ctx->hblk_op = op;
+        }
+        if ((rc = ctx->gb.ensure(nf)) || (rc = ctx->gu.ensure(nf)) || (rc = ctx->gz.ensure(nf))) return rc;
+        HIPCHK(launch_hp_rhs(ctx->hp, nt, ctx->dg.h[0], ctx->dg.h[1], ctx->thick.p, ctx->sigt.p, ctx->sigs.p,
+                             o->mass_kind, phi_old, phi_si, ctx->gb.p, ctx->stream));
+        if (o->precond == SN_PRECOND_DIRECT) {
+            if (ctx->band_op != op) {
+                if (nf > kBandSolveMaxN)
+                    return fail(SN_ERR_UNSUPPORTED, "direct thick solve: %ld unknowns exceed %ld", nf, kBandSolveMaxN);
+                HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+                HIPCHK(launch_band_width(ctx->dg4, ctx->nbr.p, ctx->gbad.p, ctx->stream));
+                int wc = 0;
+                HIPCHK(hipMemcpyAsync(&wc, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+                const int kl = (wc + 1) * nn - 1, ku = kl;
+                if (kl + ku > kBandMaxWidth)
+                    return fail(SN_ERR_UNSUPPORTED, "direct thick solve: band half width %d too large", kl);
+                const int ldb = 2 * kl + ku + 1;
+                if ((rc = ctx->band.ensure((size_t)nf * ldb)) || (rc = ctx->bpiv.ensure(nf))) return rc;
+                HIPCHK(hipMemsetAsync(ctx->band.p, 0, (size_t)nf * ldb * sizeof(double), ctx->stream));
+                HIPCHK(launch_hp_band(nn, nt, ctx->hblk.p, ctx->hcol.p, kl, ldb, ctx->band.p, ctx->stream));
+                HIPCHK(hipMemsetAsync(ctx->gbad.p, 0, sizeof(int), ctx->stream));
+                HIPCHK(launch_band_factor(nf, kl, ku, ldb, ctx->band.p, ctx->bpiv.p, ctx->gbad.p, ctx->stream));
+                int bad = 0;
+                HIPCHK(hipMemcpyAsync(&bad, ctx->gbad.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+                if (bad) return fail(SN_ERR_INVALID, "direct thick solve: the diffusion matrix is singular");
+                ctx->band_op = op;
+                ctx->band_kl = kl;
+                ctx->band_ku = ku;
+                ctx->band_ldb = ldb;
+            }
+            HIPCHK(launch_band_solve(nf, ctx->band_kl, ctx->band_ku, ctx->band_ldb, ctx->band.p, ctx->bpiv.p,
+                                     ctx->gb.p, ctx->cx.p, ctx->stream));
+        } else {
+            auto apply = [&](const double* v, const double* bb_, double* w) -> int {
+                HIPCHK(launch_hp_block_apply(nn, nt, ctx->binvf.p, v, ctx->gz.p, ctx->stream));
+                HIPCHK(launch_hp_spmv(nn, nt, ctx->hblk.p, ctx->hcol.p, ctx->gz.p, bb_, w, ctx->stream));
+                return 0;
+            };
+            auto finish = [&](const double* u) -> int {
+                HIPCHK(launch_hp_block_apply(nn, nt, ctx->binvf.p, u, ctx->cx.p, ctx->stream));
+                return 0;
+            };
+            if ((rc = gmres_core(ctx, nf, o, apply, finish, &its, &rel))) return rc;
+        }
+        HIPCHK(launch_dsa_scatter(ctx->nc, nn, ctx->slot.p, phi_si, ctx->cx.p, phi_out, ctx->stream));
+    }
+    if (stats) {
+        stats->cg_iters = its;
+        stats->cg_relres = rel;
+        stats->n_thick_cells = nt;
+    }
+    return 0;
+}
+
+int residual3(sn_context* ctx, const double* a, const double* b, double out[3]);
+
+// Source iteration at order p >= 2 (eq. DSA_fp; FP64, forward, diagonal
+// DSA): phi_SI = moment of the sweep of (sigma_s phi + q)/4pi, the stop test
+// ||phi_SI - phi|| / ||b|| before the DSA step (b: the moment of the sweep of
+// q from phi = 0), then phi = phi_SI + P_T D_ff^{-1} Sigma_f R_T (phi_SI - phi).
+int si_hp(sn_context* ctx, const double* q, const double* inflow, double* phi, const sn_iter_opts* o,
+          sn_iter_stats* stats, std::chrono::steady_clock::time_point t0) {
+    if (o->prec != SN_FP64 || o->transpose || o->dsa_form != SN_DSA_DIAGONAL || o->phi_ckpt)
+        return fail(SN_ERR_UNSUPPORTED, "order %d: FP64 forward source iteration with the diagonal DSA and no "
+                    "checkpoints only", ctx->order);
+    const long n = ctx->nc * ctx->nn;
+    int rc;
+    if ((rc = ctx->phisi.ensure(n)) || (rc = ctx->psi64.ensure((size_t)n * ctx->ndirs))) return rc;
+    ctx->sweeps = 0;
+    auto sweep_moment = [&](const double* ph, double* out) -> int {
+        HIPCHK(launch_sweep_hp(ctx->hp, ctx->mesh.nx, ctx->mesh.ny, ctx->ndirs, ctx->nbf, ctx->dirs.p, ctx->sigt.p,
+                               ctx->sigs.p, ph, q, inflow, ctx->psi64.p, ctx->stream));
+        HIPCHK(launch_moment_hp(ctx->nc, ctx->ndirs, ctx->nn, ctx->w.p, ctx->psi64.p, out, ctx->stream));
+        ++ctx->sweeps;
+        return 0;
+    };
+    double r3[3];
+    if ((rc = sweep_moment(nullptr, ctx->phisi.p)) || (rc = residual3(ctx, ctx->phisi.p, ctx->phisi.p, r3)))
+        return rc;
+    double bnorm = std::sqrt(r3[1]);
+    if (bnorm == 0.0) bnorm = 1.0;
+    int it = 0, status = SN_ERR_NOT_CONVERGED;
+    double first = -1.0;
+    for (; it < o->max_it;) {
+        if ((rc = sweep_moment(phi, ctx->phisi.p)) || (rc = residual3(ctx, ctx->phisi.p, phi, r3))) {
+            status = rc;
+            break;
+        }
+        const double res = std::sqrt(r3[0]) / bnorm;
+        int gi = 0;
+        if (o->use_dsa) {
+            sn_dsa_stats ds{};
+            if ((rc = dsa_hp(ctx, phi, ctx->phisi.p, phi, &o->dsa, &ds))) {
+                status = rc;
+                break;
+            }
+            gi = ds.cg_iters;
+        } else {
+            HIPCHK(hipMemcpyAsync(phi, ctx->phisi.p, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        if (stats && stats->res_hist) stats->res_hist[it] = res;
+        if (stats && stats->cg_hist) stats->cg_hist[it] = gi;
+        ++it;
+        if (first < 0) first = res;
+        if (!std::isfinite(res) || res > 1e6 * first) {
+            status = fail(SN_ERR_DIVERGED, "source iteration diverged at iteration %d (residual %g)", it - 1, res);
+            break;
+        }
+        if (res <= o->tol) {
+            status = SN_OK;
+            break;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (status == SN_ERR_NOT_CONVERGED) fail(status, "not converged in %d iterations", o->max_it);
+    if (stats) {
+        stats->iters = it;
+        stats->sweeps = ctx->sweeps;
+        stats->fp64_checks = 0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
 }
 
 // res_part / res_nparts: source-iteration residual partial sums to reduce in
@@ -1100,6 +1287,8 @@ void sn_context_destroy(sn_context* ctx) {
     ctx->gbad.release();
     ctx->band.release();
     ctx->bpiv.release();
+    ctx->hblk.release();
+    ctx->hcol.release();
     if (ctx->kdot_host) (void)hipHostFree(ctx->kdot_host);
     if (ctx->gdot_host) (void)hipHostFree(ctx->gdot_host);
     delete ctx;
@@ -1140,7 +1329,10 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         }
     } guard{c};
     c->mesh = *mesh;
-    c->nn = dim == 2 ? 4 : 8;
+    c->order = mesh->order >= 2 ? mesh->order : 1;
+    c->nn = c->order >= 2 ? (c->order + 1) * (c->order + 1) : (dim == 2 ? 4 : 8);
+    if (c->order >= 2 && !hp_tables(c->order, &c->hp))
+        return fail(SN_ERR_UNSUPPORTED, "order %d: eigenbasis of the 1D upwind operator failed its check", c->order);
     c->nc = (long)mesh->nx * mesh->ny * mesh->nz;
     c->ndirs = quad->ndirs;
     c->nbf = inflow_size(mesh);
@@ -1427,8 +1619,11 @@ int sn_context_create(const sn_mesh* mesh, const sn_quad* quad, const double* si
         (rc = c->parta.ensure(3 * c->nparts)) || (rc = c->partb.ensure(3 * c->nparts)) ||
         (rc = c->scal.ensure(1)))
         return rc;
-    HIPCHK(launch_block_jacobi(dg, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, c->binv.p, c->stream));
-    HIPCHK(launch_neighbour_table(dg, c->thick.p, c->slot.p, c->nbr.p, c->stream));
+    c->dg4 = dg;
+    c->dg4.nn = dim == 2 ? 4 : 8;
+    if (c->order == 1)
+        HIPCHK(launch_block_jacobi(dg, c->thick.p, c->slot.p, c->sigt.p, c->sigs.p, c->binv.p, c->stream));
+    HIPCHK(launch_neighbour_table(c->dg4, c->thick.p, c->slot.p, c->nbr.p, c->stream));
     c->nrpart = (int)std::max<long>(1, std::min<long>((nc * c->nn + 255) / 256, 1024));
     if ((rc = c->rpart.ensure(3 * c->nrpart)) || (rc = c->res3.ensure(3))) return rc;
     HIPCHK(hipHostMalloc((void**)&c->hpin, sizeof(sn_context::HostScalars), hipHostMallocDefault));
@@ -1499,6 +1694,14 @@ int sn_sweep(sn_context* ctx, const double* phi, const double* q, const double* 
     g_err.clear();
     if (!ctx || !psi) return fail(SN_ERR_INVALID, "context or psi is NULL");
     if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision %d", (int)prec);
+    if (ctx->order >= 2) {
+        if (transpose || prec != SN_FP64)
+            return fail(SN_ERR_UNSUPPORTED, "order %d: forward FP64 sweeps only", ctx->order);
+        HIPCHK(launch_sweep_hp(ctx->hp, ctx->mesh.nx, ctx->mesh.ny, ctx->ndirs, ctx->nbf, ctx->dirs.p, ctx->sigt.p,
+                               ctx->sigs.p, phi, q, inflow, (double*)psi, ctx->stream));
+        ++ctx->sweeps;
+        return 0;
+    }
     return do_sweep(ctx, phi, nullptr, q, inflow, transpose ? 1 : 0, prec, psi);
 }
 
@@ -1506,6 +1709,11 @@ int sn_scalar_flux(sn_context* ctx, const void* psi, sn_precision prec, double* 
     g_err.clear();
     if (!ctx || !psi || !phi_out) return fail(SN_ERR_INVALID, "NULL argument");
     if (prec != SN_FP64 && prec != SN_FP32) return fail(SN_ERR_INVALID, "unknown precision %d", (int)prec);
+    if (ctx->order >= 2) {
+        if (prec != SN_FP64) return fail(SN_ERR_UNSUPPORTED, "order %d: FP64 psi only", ctx->order);
+        HIPCHK(launch_moment_hp(ctx->nc, ctx->ndirs, ctx->nn, ctx->w.p, (const double*)psi, phi_out, ctx->stream));
+        return 0;
+    }
     return do_moment(ctx, psi, prec, phi_out);
 }
 
@@ -1514,6 +1722,7 @@ int sn_dsa_thick_correct(sn_context* ctx, const double* phi_old, const double* p
     g_err.clear();
     if (!ctx || !phi_old || !phi_si || !phi_out || !opts) return fail(SN_ERR_INVALID, "NULL argument");
     if (bad_dsa_opts(*opts)) return fail(SN_ERR_INVALID, "bad DSA options");
+    if (ctx->order >= 2) return dsa_hp(ctx, phi_old, phi_si, phi_out, opts, stats);
     return do_dsa(ctx, phi_old, phi_si, phi_out, opts, stats);
 }
 
@@ -1529,6 +1738,7 @@ int sn_source_iterate(sn_context* ctx, const double* q, const double* inflow, do
     if (o->fp32_refine != 0 && o->fp32_refine != 1) return fail(SN_ERR_INVALID, "fp32_refine must be 0 or 1");
     if (o->dsa_form != SN_DSA_DIAGONAL && o->dsa_form != SN_DSA_TRIANGULAR)
         return fail(SN_ERR_INVALID, "unknown DSA form %d", o->dsa_form);
+    if (ctx->order >= 2) return si_hp(ctx, q, inflow, phi, o, stats, t0);
     // the inflow array is fixed for the whole call: face buffers are filled
     // once per precision (and transpose flag) and reused by later sweeps
     struct FaceReuse {
@@ -1704,6 +1914,7 @@ int sn_response(sn_context* ctx, const double* r, const double* phi, int face, c
                 double* out) {
     g_err.clear();
     if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     const int dim = ctx->mesh.dim;
     if (face < -1 || face >= 2 * dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * dim - 1);
     if (face >= 0 && !psi) return fail(SN_ERR_INVALID, "psi is needed for a face functional");
@@ -1741,6 +1952,7 @@ int sn_response_noalloc(sn_context* ctx, const double* r, const double* phi, int
                         sn_precision prec, double* out) {
     g_err.clear();
     if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     const int dim = ctx->mesh.dim;
     if (face < -1 || face >= 2 * dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * dim - 1);
     if (face >= 0 && !psi) return fail(SN_ERR_INVALID, "psi is needed for a face functional");
@@ -1782,6 +1994,7 @@ int sn_gradient(sn_context* ctx, const void* psi, const void* psi_adj, sn_precis
                 const double* chi, double* g_t, double* g_s) {
     g_err.clear();
     if (!ctx || !psi || !psi_adj || !phi || !chi || !g_t || !g_s) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     const double h[3] = {ctx->mesh.hx, ctx->mesh.hy, ctx->mesh.dim == 3 ? ctx->mesh.hz : 1.0};
     if (prec == SN_FP64)
         HIPCHK(launch_gradient<double>(ctx->nc, ctx->nn, ctx->ndirs, ctx->w.p, h, ctx->sigt.p, ctx->sigs.p,
@@ -1799,6 +2012,7 @@ int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, doub
     g_err.clear();
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !phi || !o) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
     if (o->restart < 1 || o->restart > SN_KRYLOV_MAX_RESTART)
         return fail(SN_ERR_INVALID, "restart must be in 1..%d", SN_KRYLOV_MAX_RESTART);
@@ -1958,6 +2172,7 @@ int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, doub
 int sn_adjoint_source(sn_context* ctx, const double* r, int face, double* q_adj, double* inflow_adj) {
     g_err.clear();
     if (!ctx) return fail(SN_ERR_INVALID, "context is NULL");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     if (face < -1 || face >= 2 * ctx->mesh.dim) return fail(SN_ERR_INVALID, "face must be -1 or 0..%d", 2 * ctx->mesh.dim - 1);
     if ((r != nullptr) != (q_adj != nullptr)) return fail(SN_ERR_INVALID, "r and q_adj must be given together");
     if ((face >= 0) != (inflow_adj != nullptr)) return fail(SN_ERR_INVALID, "a face needs inflow_adj (and only then)");
@@ -1977,6 +2192,7 @@ int sn_face_response(sn_context* ctx, const double* phi, const double* q, const 
                      double* out) {
     g_err.clear();
     if (!ctx || !out) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     if (face < 0 || face >= 2 * ctx->mesh.dim) return fail(SN_ERR_INVALID, "face must be 0..%d", 2 * ctx->mesh.dim - 1);
     const int S = ctx->part_stride;
     int rc;
@@ -2014,6 +2230,7 @@ int sn_adjoint_gradient(sn_context* ctx, const double* phi, const double* q, con
                         const double* q_adj, const double* inflow_adj, double* g_t, double* g_s) {
     g_err.clear();
     if (!ctx || !phi || !chi || !g_t || !g_s) return fail(SN_ERR_INVALID, "NULL argument");
+    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
     const int S = ctx->part_stride;
     int rc;
     if ((rc = ctx->psi_a.ensure((size_t)ctx->nc * S * ctx->nn)) || (rc = ctx->psi_b.ensure((size_t)ctx->nc * S * ctx->nn)))

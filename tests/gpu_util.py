@@ -25,7 +25,8 @@ def context(p: Problem, eta=None):
     from paper_2001_09196_amd import Context
     st = dev(p.sigma_t, torch.float64)
     ss = dev(p.sigma_s, torch.float64)
-    return Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta if eta is None else eta)
+    return Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, st, ss, eta=p.eta if eta is None else eta,
+                   order=p.order)
 
 
 def random_problem(dim, nx, ny, nz, order=4, seed=0, voids=True, h=(1.0, 0.8, 1.2)):
