@@ -336,3 +336,74 @@ def source_iterate(prob, tol=1e-8, max_it=200, use_dsa=True, mass_kind=0, form=S
             break
         phi = phi_new
     return {"phi": phi, "iters": it, "res_hist": np.array(res)}
+
+
+def gmres(prob, tol=1e-8, max_it=200, restart=30, use_dsa=True, mass_kind=0, form=SIP, eta=None):
+    """Flexible GMRES(restart) on S phi = b (Sec. 2.2; S = I - sum_d w_d L_d^{-1}
+    Sigma_s, b the moment of the sweep of q from phi = 0), right-preconditioned
+    by the heterogeneous DSA applied to a vector v as to a residual,
+    v + P_T D_ff^{-1} Sigma_f R_T v; modified Gram-Schmidt; zero start.  An
+    iteration is one application of S.  Returns dict(phi, iters, res_hist)."""
+    nn = prob.nn
+    N = prob.ncells * nn
+    b = moment(prob, sweep(prob, None, prob.q)).ravel()
+    bn = np.linalg.norm(b)
+    bn = bn if bn > 0 else 1.0
+    A = dsa_dense(prob, eta, form) if use_dsa else None
+    zero = np.zeros((prob.ncells, nn))
+
+    def S(x):
+        return x - moment(prob, sweep(prob, x.reshape(prob.ncells, nn), None)).ravel()
+
+    def M(v):
+        if not use_dsa:
+            return v.copy()
+        return dsa_correct(prob, zero, v.reshape(prob.ncells, nn), eta, mass_kind, form, A).ravel()
+
+    x = np.zeros(N)
+    res = []
+    it = 0
+    while it < max_it:
+        r = b - S(x)
+        beta = np.linalg.norm(r)
+        if beta / bn <= tol:
+            break
+        m = restart
+        V = np.zeros((m + 1, N))
+        Z = np.zeros((m, N))
+        H = np.zeros((m + 1, m))
+        V[0] = r / beta
+        g = np.zeros(m + 1)
+        g[0] = beta
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        j = 0
+        done = False
+        while j < m and it < max_it:
+            Z[j] = M(V[j])
+            w = S(Z[j])
+            for i in range(j + 1):
+                H[i, j] = w @ V[i]
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] > 0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                a, c = H[i, j], H[i + 1, j]
+                H[i, j], H[i + 1, j] = cs[i] * a + sn[i] * c, -sn[i] * a + cs[i] * c
+            den = math.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = (H[j, j] / den, H[j + 1, j] / den) if den > 0 else (1.0, 0.0)
+            H[j, j] = den
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            it += 1
+            j += 1
+            res.append(abs(g[j]) / bn)
+            if res[-1] <= tol:
+                done = True
+                break
+        y = np.linalg.solve(np.triu(H[:j, :j]), g[:j])
+        x = x + Z[:j].T @ y
+        if done:
+            break
+    return {"phi": x.reshape(prob.ncells, nn), "iters": it, "res_hist": np.array(res)}

@@ -2012,7 +2012,8 @@ int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, doub
     g_err.clear();
     auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !phi || !o) return fail(SN_ERR_INVALID, "NULL argument");
-    if (ctx->order >= 2) return fail(SN_ERR_UNSUPPORTED, "built for order 1 only");
+    if (ctx->order >= 2 && (o->transpose || (o->use_dsa && o->dsa_form != SN_DSA_DIAGONAL)))
+        return fail(SN_ERR_UNSUPPORTED, "order %d: forward sweeps with the diagonal DSA only", ctx->order);
     if (!(o->tol >= 0) || o->max_it < 1) return fail(SN_ERR_INVALID, "bad tolerance or iteration limit");
     if (o->restart < 1 || o->restart > SN_KRYLOV_MAX_RESTART)
         return fail(SN_ERR_INVALID, "restart must be in 1..%d", SN_KRYLOV_MAX_RESTART);
@@ -2050,15 +2051,28 @@ int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, doub
     double* V = ctx->kv.p;
     double* Z = dsa ? ctx->kz.p : ctx->kv.p;
     double* w = ctx->kw.p;
+    // the moment of a full sweep from (phi, q, inflow) into out (order p >= 2:
+    // through a psi workspace)
+    if (ctx->order >= 2 && (rc = ctx->psi64.ensure((size_t)n * ctx->ndirs))) return rc;
+    auto sweep_flux = [&](const double* ph, const double* qq, const double* in, double* out) -> int {
+        if (ctx->order >= 2) {
+            HIPCHK(launch_sweep_hp(ctx->hp, ctx->mesh.nx, ctx->mesh.ny, ctx->ndirs, ctx->nbf, ctx->dirs.p,
+                                   ctx->sigt.p, ctx->sigs.p, ph, qq, in, ctx->psi64.p, ctx->stream));
+            HIPCHK(launch_moment_hp(ctx->nc, ctx->ndirs, ctx->nn, ctx->w.p, ctx->psi64.p, out, ctx->stream));
+            ++ctx->sweeps;
+            return 0;
+        }
+        return do_sweep_flux(ctx, ph, nullptr, qq, in, tr, SN_FP64, out, 0);
+    };
     // S x = x - sum_d w_d L_d^{-1} (Sigma_s x) with zero source and vacuum: into w, then w = x - w
     auto apply_S = [&](const double* x) -> int {
         int e;
-        if ((e = do_sweep_flux(ctx, x, nullptr, nullptr, nullptr, tr, SN_FP64, w, 0))) return e;
+        if ((e = sweep_flux(x, nullptr, nullptr, w))) return e;
         HIPCHK(launch_axpby(n, 1.0, x, -1.0, w, ctx->stream));
         return 0;
     };
     // b = sum_d w_d L_d^{-1}(q_d + inflow load)
-    if ((rc = do_sweep_flux(ctx, nullptr, nullptr, q, inflow, tr, SN_FP64, ctx->kb.p, 0))) return rc;
+    if ((rc = sweep_flux(nullptr, q, inflow, ctx->kb.p))) return rc;
     double bb;
     if ((rc = dots(ctx, 1, ctx->kb.p, ctx->kb.p, &bb))) return rc;
     double bnorm = std::sqrt(bb);
@@ -2092,7 +2106,8 @@ int sn_krylov_solve(sn_context* ctx, const double* q, const double* inflow, doub
             if (dsa) {
                 // the preconditioner applied to v_j as to a residual: z = v + P_T D_ff^{-1} Sigma_f R_T v
                 sn_dsa_stats ds{};
-                if ((rc = do_dsa(ctx, ctx->kzero.p, vj, zj, &o->dsa, &ds))) {
+                if ((rc = ctx->order >= 2 ? dsa_hp(ctx, ctx->kzero.p, vj, zj, &o->dsa, &ds)
+                                          : do_dsa(ctx, ctx->kzero.p, vj, zj, &o->dsa, &ds))) {
                     status = rc;
                     break;
                 }

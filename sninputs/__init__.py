@@ -292,6 +292,76 @@ def crooked_pipe(sigmas, cdt: Optional[float], cells_per_unit: int = 8, order: i
                    meta={"regions": reg, "sigmas": tuple(sigmas), "cdt": cdt})
 
 
+# Pseudo-scattering thermal radiative transfer (Sec. 4.2): NIF units
+TRT_A = 137.199          # radiation constant
+TRT_C = 2.9979e4         # speed of light
+TRT_DT = 1e-3            # time step (one long step, about 10% of an implosion)
+# Table hohlraum_materials: (opacity sigma, heat capacity Cv)
+HOHLRAUM_MATERIALS = {"gold": (1e3, 1e5), "helium": (1e-3, 1e-2), "ch": (1e2, 1e3), "hydrogen": (1.0, 1.0)}
+HOHLRAUM_T_COLD = 1e-3   # keV: the initial temperature everywhere
+HOHLRAUM_T_HOT = 0.4     # keV: the laser-heated parts of the gold wall
+
+
+def trt_pseudo_scattering(sigma, cv, T, dt=TRT_DT):
+    """eq. hohlraum_sigma and eq. hohlraum_q: the pseudo-scattering cross
+    section sigma_ps and the gray-body source q_ps of one implicit time step
+    (opacity sigma, which is also the absorption opacity, heat capacity Cv,
+    temperature T, step dt)."""
+    sigma, cv, T = (np.asarray(v, dtype=np.float64) for v in (sigma, cv, T))
+    b = 16.0 * np.pi * TRT_A * TRT_C * T ** 3
+    den = cv / dt + sigma * b
+    sigma_ps = sigma ** 2 * b / den
+    q_ps = sigma * TRT_A * TRT_C * T ** 4 - sigma ** 2 * 16.0 * np.pi * TRT_A ** 2 * TRT_C ** 2 * T ** 7 / den
+    return sigma_ps, q_ps
+
+
+HOHLRAUM_REGIONS = ("gold", "gold_hot", "helium", "ch", "hydrogen")
+
+
+def hohlraum_regions(nx: int, ny: int) -> np.ndarray:
+    """Region index per cell (HOHLRAUM_REGIONS, x fastest) of a synthetic 2D
+    hohlraum on [0, 2] x [0, 1], decided at cell centres: a gold wall 0.06
+    thick along x = 0, 2 and 0.1 thick along y = 0, 1, with laser entrance
+    holes |y - 1/2| < 0.2 in the end walls (helium); on the long walls the
+    inner half of the thickness is laser-heated for x in [0.55, 0.85] and
+    [1.15, 1.45]; helium fill; a capsule of radius 0.25 at the centre, a CH
+    shell over 0.2 < r < 0.25 around hydrogen fuel.  Materials left to right
+    through the middle: gold (hole), helium, CH, hydrogen, CH, helium, gold."""
+    xc = (np.arange(nx) + 0.5) * (2.0 / nx)
+    yc = (np.arange(ny) + 0.5) * (1.0 / ny)
+    X, Y = np.meshgrid(xc, yc)
+    reg = np.full(X.shape, 2, dtype=np.int64)                       # helium
+    endwall = ((X < 0.06) | (X > 1.94)) & ~(np.abs(Y - 0.5) < 0.2)
+    sidewall = (Y < 0.1) | (Y > 0.9)
+    reg[endwall | sidewall] = 0
+    hot = ((Y > 0.05) & (Y < 0.1)) | ((Y > 0.9) & (Y < 0.95))
+    hot &= ((X > 0.55) & (X < 0.85)) | ((X > 1.15) & (X < 1.45))
+    reg[hot] = 1
+    r = np.hypot(X - 1.0, Y - 0.5)
+    reg[(r < 0.25) & (r >= 0.2)] = 3
+    reg[r < 0.2] = 4
+    return reg.ravel()
+
+
+def hohlraum(nx: int, ny: int, sn: int = 8, order: int = 1, name: str = "hohlraum") -> Problem:
+    """The hohlraum stand-in (Sec. 4.2) as a transport problem: sigma_t =
+    sigma, sigma_s = sigma_ps, and the angular source q_ps in every direction
+    (total isotropic density 4 pi q_ps), with sigma_ps and q_ps of
+    trt_pseudo_scattering at the cell's temperature: 0.4 keV in the heated
+    gold, 1e-3 keV elsewhere.  Vacuum boundaries, S_N of the given order,
+    DG order `order`, cells of 2/nx by 1/ny."""
+    reg = hohlraum_regions(nx, ny)
+    mats = [HOHLRAUM_MATERIALS["gold"], HOHLRAUM_MATERIALS["gold"], HOHLRAUM_MATERIALS["helium"],
+            HOHLRAUM_MATERIALS["ch"], HOHLRAUM_MATERIALS["hydrogen"]]
+    sig = np.array([mats[k][0] for k in reg])
+    cv = np.array([mats[k][1] for k in reg])
+    T = np.where(reg == 1, HOHLRAUM_T_HOT, HOHLRAUM_T_COLD)
+    sps, qps = trt_pseudo_scattering(sig, cv, T)
+    om, w = level_symmetric(sn, 2)
+    return Problem(name, 2, nx, ny, 1, (2.0 / nx, 1.0 / ny, 1.0), sig, np.minimum(sps, sig), 4.0 * np.pi * qps,
+                   om, w, order=order, meta={"regions": reg})
+
+
 def inflow_size(dim: int, nx: int, ny: int, nz: int) -> int:
     """Boundary-face nodes per direction in the inflow layout.
 

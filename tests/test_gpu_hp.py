@@ -134,7 +134,8 @@ def test_order_p_refusals():
             lambda: sn_source_iterate(ctx, dev(p.q), None, _zeros(p), max_it=2, transpose=True),
             lambda: sn_source_iterate(ctx, dev(p.q), None, _zeros(p), max_it=2, dsa_form=1),
             lambda: sn_dsa_thick_correct(ctx, _zeros(p), _zeros(p), _zeros(p), precond=1),
-            lambda: sn_krylov_solve(ctx, dev(p.q), None, _zeros(p), max_it=2),
+            lambda: sn_krylov_solve(ctx, dev(p.q), None, _zeros(p), max_it=2, transpose=True),
+            lambda: sn_krylov_solve(ctx, dev(p.q), None, _zeros(p), max_it=2, dsa_form=1),
             lambda: sn_response(ctx, None, _zeros(p), 1, psi, SN_FP64),
         ]
         for k, f in enumerate(cases):
@@ -146,3 +147,50 @@ def test_order_p_refusals():
     with pytest.raises(SnError) as e:
         Context(3, 2, 2, 2, (1.0, 1.0, 1.0), om, w, st, st, order=2)
     assert e.value.code == SN_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("form,precond", [("sip", 0), ("nip", 0), ("nip", 2), ("mnip", 2)])
+def test_krylov(order, form, precond):
+    """Flexible GMRES(8) at order p with the het-DSA of each form, ten
+    iterations (a restart inside) and converged, against the order-p oracle."""
+    from paper_2001_09196_amd import sn_krylov_solve
+    diffusion, op = FORMS[form]
+    p = _problem(10, 8, order, seed=12, voids=False)
+    say(f"hp krylov {p.name} {form} precond={precond}")
+    ref = hp.gmres(p, tol=0.0, max_it=10, restart=8, use_dsa=True, mass_kind=1, form=op)
+    refc = hp.gmres(p, tol=1e-11, max_it=300, restart=8, use_dsa=True, mass_kind=1, form=op)
+    with context(p) as ctx:
+        phi = _zeros(p)
+        r = sn_krylov_solve(ctx, dev(p.q), None, phi, tol=0.0, max_it=10, restart=8, use_dsa=True, mass_kind=1,
+                            cg_rtol=1e-14, cg_maxit=100000, diffusion=diffusion, precond=precond)
+        e10 = rel_max(phi.cpu().numpy(), ref["phi"])
+        assert np.allclose(r["res_hist"], ref["res_hist"], rtol=1e-7, atol=0)
+        phi = _zeros(p)
+        rc = sn_krylov_solve(ctx, dev(p.q), None, phi, tol=1e-11, max_it=300, restart=8, use_dsa=True, mass_kind=1,
+                             cg_rtol=1e-14, cg_maxit=100000, diffusion=diffusion, precond=precond)
+        ec = rel_max(phi.cpu().numpy(), refc["phi"])
+    say(f"  10 iterations: {e10:.1e}; converged in {rc['iters']} (oracle {refc['iters']}): {ec:.1e}")
+    assert r["iters"] == 10 and e10 <= 1e-9
+    assert rc["rc"] == 0 and abs(rc["iters"] - refc["iters"]) <= 1 and ec <= 1e-10
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_hohlraum_stand_in(order):
+    """The pseudo-scattering TRT hohlraum stand-in (Sec. 4.2) at order p, S4,
+    24 x 12 cells: five GMRES iterations with het-NIP (GMRES inner solve) and
+    with full mNIP (direct inner solve) against the order-p oracle."""
+    from paper_2001_09196_amd import sn_krylov_solve
+    import dataclasses
+    base = sninputs.hohlraum(24, 12, sn=4, order=order)
+    for name, eta, diffusion, op, precond in (("het-NIP", 1.0, 1, hp.NIP, 0), ("full mNIP", 0.0, 2, hp.MNIP, 2)):
+        p = dataclasses.replace(base, eta=eta)
+        say(f"hohlraum order {order} {name}")
+        ref = hp.gmres(p, tol=0.0, max_it=5, restart=30, use_dsa=True, mass_kind=1, form=op)
+        with context(p) as ctx:
+            phi = _zeros(p)
+            r = sn_krylov_solve(ctx, dev(p.q), None, phi, tol=0.0, max_it=5, restart=30, use_dsa=True, mass_kind=1,
+                                cg_rtol=1e-14, cg_maxit=100000, diffusion=diffusion, precond=precond)
+            e = rel_max(phi.cpu().numpy(), ref["phi"])
+        say(f"  {e:.1e}")
+        assert r["iters"] == 5 and e <= 1e-9

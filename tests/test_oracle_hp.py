@@ -203,3 +203,27 @@ def test_h6_si_fixed_point(order):
         acc = hp.source_iterate(prob, tol=1e-13, max_it=2000, use_dsa=True, form=form, mass_kind=1)
         assert np.max(np.abs(acc["phi"] - ref)) <= 1e-10 * np.max(np.abs(ref)), form
         assert acc["iters"] < plain["iters"], form
+
+
+def test_h8_gmres_order1_is_the_q1_oracle():
+    """The order-p flexible GMRES at p = 1 against the C oracle's (pinned by
+    G1-G3): the same residual history and iterates, with the SIP DSA."""
+    prob = _prob(6, 5, 1, seed=4, voids=True)
+    for use_dsa in (False, True):
+        a = hp.gmres(prob, tol=0.0, max_it=12, restart=5, use_dsa=use_dsa, mass_kind=1)
+        b = oracle.gmres(prob, tol=0.0, max_it=12, restart=5, use_dsa=use_dsa, mass_kind=1, cg_rtol=1e-15)
+        assert np.allclose(a["res_hist"], b["res_hist"], rtol=1e-8, atol=1e-15)
+        assert np.max(np.abs(a["phi"] - b["phi"])) <= 1e-10 * np.max(np.abs(b["phi"]))
+
+
+@pytest.mark.parametrize("form", [hp.SIP, hp.NIP])
+def test_h8_gmres_fixed_point(form):
+    prob = _prob(3, 2, 2, seed=9, voids=False)
+    A, rhs = bfh.block_system(prob)
+    x = np.linalg.solve(A, rhs)
+    N = prob.ncells * prob.nn
+    ref = x[prob.ndirs * N:].reshape(prob.ncells, prob.nn)
+    r = hp.gmres(prob, tol=1e-13, max_it=200, restart=30, use_dsa=True, mass_kind=1, form=form)
+    assert r["iters"] < 200
+    assert np.max(np.abs(r["phi"] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert np.all(np.diff(r["res_hist"]) <= 1e-15)            # GMRES residuals never grow within a cycle
