@@ -277,6 +277,7 @@ def main():
                     help="only run N sweeps of --config in --prec (for rocprofv3 counter passes)")
     ap.add_argument("--config", default="c5", help="workload of --sweeps-only (c1..c5)")
     ap.add_argument("--pipe-only", action="store_true", help="only the crooked-pipe scan")
+    ap.add_argument("--hp-only", action="store_true", help="only the order-p leg (sweep grind, hohlraum)")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"), help="sweep precision of --sweeps-only")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -295,6 +296,9 @@ def main():
 
     if args.pipe_only:
         print(json.dumps(bench_pipe(log)), flush=True)
+        return
+    if args.hp_only:
+        print(json.dumps(bench_hp(log)), flush=True)
         return
 
     if args.sweeps_only:
@@ -468,6 +472,9 @@ def main():
     # ---- crooked-pipe stand-in: heterogeneous against full DSA ----
     out["crooked_pipe"] = bench_pipe(log)
 
+    # ---- order p = 2, 3: sweep grind and the hohlraum stand-in ----
+    out["higher_order"] = bench_hp(log)
+
     # ---- c4: adjoint gradient of the corner detector ----
     out["c4"] = bench_adjoint_c4(log)
     w4 = Workload("c4")
@@ -599,6 +606,91 @@ def bench_pipe(log, budget_s=100.0):
     summary = {k: tuple(v[c]["gmres30_to_1e-12"] for c in ("full_nip", "full_mnip", "het_nip"))
                for k, v in out["problems"].items()}
     log(f"crooked pipe (full NIP, full mNIP, het NIP): {json.dumps(summary)}")
+    return out
+
+
+# Table hohlraum (order 4, 16-256 cores): fGMRES(30) iterations to 1e-12 and AMG iterations per DSA
+# solve for full DSA with mNIP and the heterogeneous DSA with NIP, and the thick share; context only
+PAPER_HOHLRAUM = {"S4": [(78900, 52, "DNC", 20, 6, 2.3), (315600, 40, "DNC", 23, 8, 2.9),
+                         (1262400, 28, "DNC", 20, 10, 2.5)],
+                  "S8": [(78900, 52, "DNC", 20, 6, 2.3), (315600, 40, "DNC", 23, 7, 2.9),
+                         (1262400, 29, "DNC", 21, 10, 2.5)],
+                  "S12": [(78900, 52, "DNC", 20, 6, 2.3), (315600, 39, "DNC", 23, 7, 2.9),
+                          (1262400, 29, "DNC", 21, 10, 2.5)]}
+
+
+def bench_hp(log, budget_s=90.0):
+    """Upwind DG of order 2 and 3 (2D).  (1) Sweep grind on the 256^2 S8 mesh
+    of C2 (its cross sections), event-timed over 10 sweeps after 2 warm-up
+    sweeps, beside the psi bytes written.  (2) The pseudo-scattering hohlraum
+    stand-in (Sec. 4.2, sninputs.hohlraum) at order 3, S4/S8/S12, 80x40,
+    160x80 and 320x160 cells (51k, 205k, 819k unknowns): fGMRES(30)
+    iterations to 1e-12 with full DSA mNIP (eta = 0) and het-DSA NIP
+    (eta = 1), each DSA solved by block-Jacobi GMRES to 1e-4
+    with at most 250 iterations (the paper's inner protocol with its AMG
+    replaced), the mean inner iterations per DSA solve and the thick share;
+    and unaccelerated GMRES for reference."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import Context, SN_FP64, SnError, sn_krylov_solve, sn_sweep
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    out = {"sweep_c2_mesh": {}, "hohlraum": {}, "paper_hohlraum_dofs_iters_amg_mnip_then_nip_thick": PAPER_HOHLRAUM}
+    base = sninputs.config("c2")
+    for order in (2, 3):
+        p = dataclasses.replace(base, order=order)
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta,
+                     order=order) as ctx:
+            rng = np.random.default_rng(1)
+            phi = t(rng.uniform(0, 1, (p.ncells, p.nn)))
+            q = t(p.q)
+            psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device=dev)
+            for _ in range(2):
+                sn_sweep(ctx, phi, q, None, False, SN_FP64, psi)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                sn_sweep(ctx, phi, q, None, False, SN_FP64, psi)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            cd = p.ncells * p.ndirs
+            out["sweep_c2_mesh"][f"order{order}"] = {
+                "ms": ms, "grind_ns_per_cell_dir": ms * 1e6 / cd, "grind_ns_per_node_dir": ms * 1e6 / (cd * p.nn),
+                "psi_write_GBps": cd * p.nn * 8 / (ms * 1e-3) / 1e9}
+        log(f"order {order} sweep on the C2 mesh: {ms:.3f} ms ({ms * 1e6 / cd:.2f} ns per cell-dir)")
+
+    def run(p, use_dsa):
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta,
+                     order=p.order) as ctx:
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
+            try:
+                r = sn_krylov_solve(ctx, t(p.q), None, phi, tol=1e-12, max_it=500, restart=30, use_dsa=use_dsa,
+                                    mass_kind=1, cg_rtol=1e-4, cg_maxit=250, diffusion=1 if p.eta > 0 else 2)
+            except SnError as e:
+                return {"iters": "n/a", "error": str(e)}
+            return {"iters": r["iters"] if r["rc"] == 0 else "DNC", "seconds": r["seconds"],
+                    "inner_iters_per_dsa": float(np.mean(r["cg_hist"])) if use_dsa and r["iters"] else 0.0}
+
+    for nx, ny in ((80, 40), (160, 80), (320, 160)):
+        for sn in (4, 8, 12):
+            if time.perf_counter() - t_start > budget_s:
+                out["truncated"] = True
+                break
+            hb = sninputs.hohlraum(nx, ny, sn=sn, order=3)
+            row = {"dofs": hb.ncells * hb.nn, "thick_pct": 100.0 * float((hb.sigma_s >= 1.0).mean())}
+            row["full_mnip"] = run(dataclasses.replace(hb, eta=0.0), True)
+            row["het_nip"] = run(dataclasses.replace(hb, eta=1.0), True)
+            row["no_dsa"] = run(hb, False)
+            out["hohlraum"][f"S{sn} {nx}x{ny}"] = row
+            log(f"hohlraum order 3 S{sn} {nx}x{ny}: full mNIP {row['full_mnip']['iters']}, "
+                f"het NIP {row['het_nip']['iters']}, no DSA {row['no_dsa']['iters']}")
+    out["seconds"] = time.perf_counter() - t_start
     return out
 
 
