@@ -194,3 +194,45 @@ def test_hohlraum_stand_in(order):
             e = rel_max(phi.cpu().numpy(), ref["phi"])
         say(f"  {e:.1e}")
         assert r["iters"] == 5 and e <= 1e-9
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("shape", [(1, 17), (17, 1), (1, 1), (33, 2)])
+def test_degenerate_meshes(order, shape):
+    """Meshes one cell wide, a single cell, and a strip two cells high that
+    spans several 16-cell tiles: sweep with inflow, and three SI iterations
+    with the direct DSA solve, against the oracle."""
+    from paper_2001_09196_amd import SN_FP64, sn_source_iterate, sn_sweep
+    p = _problem(*shape, order, seed=sum(shape), voids=False)
+    p.q[:] = 1.0                               # a source in every cell (thick cells have none otherwise)
+    rng = np.random.default_rng(2)
+    phi = rng.uniform(0, 1, (p.ncells, p.nn))
+    inflow = rng.uniform(0, 1, (p.ndirs, hp.inflow_size(order, p.nx, p.ny)))
+    ref = hp.sweep(p, phi, p.q, inflow=inflow)
+    ref3 = hp.source_iterate(p, tol=0.0, max_it=3, use_dsa=True, mass_kind=1, form=hp.NIP)
+    say(f"hp degenerate {p.name}")
+    with context(p) as ctx:
+        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device="cuda")
+        sn_sweep(ctx, dev(phi), dev(p.q), dev(inflow), False, SN_FP64, psi)
+        assert rel_max(psi.cpu().numpy(), ref) <= 1e-12
+        out = _zeros(p)
+        r = sn_source_iterate(ctx, dev(p.q), None, out, tol=0.0, max_it=3, use_dsa=True, mass_kind=1,
+                              diffusion=1, precond=2)
+        assert r["iters"] == ref3["iters"] == 3 and rel_max(out.cpu().numpy(), ref3["phi"]) <= 1e-10
+
+
+def test_no_thick_cells():
+    """eta above every sigma_s: the DSA leaves phi_SI unchanged and SI is plain SI."""
+    from paper_2001_09196_amd import sn_dsa_thick_correct, sn_source_iterate
+    p = _problem(12, 9, 2, seed=4, voids=True)
+    rng = np.random.default_rng(3)
+    phi_si = rng.uniform(0, 1, (p.ncells, p.nn))
+    ref = hp.source_iterate(p, tol=0.0, max_it=4, use_dsa=False)
+    with context(p, eta=math.inf) as ctx:
+        assert ctx.thick_count == 0
+        out = _zeros(p)
+        st = sn_dsa_thick_correct(ctx, _zeros(p), dev(phi_si), out, diffusion=1)
+        assert st["cg_iters"] == 0 and np.array_equal(out.cpu().numpy(), phi_si)
+        phi = _zeros(p)
+        sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=4, use_dsa=True, diffusion=1)
+        assert rel_max(phi.cpu().numpy(), ref["phi"]) <= 1e-12
