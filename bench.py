@@ -505,6 +505,22 @@ def main():
                                "time_to_1e-8_s": {"c1": c1["oracle_to_1e-8"]["seconds"],
                                                   "c2": out["c2"].get("oracle_to_1e-8", {}).get("seconds")}}
         log(f"oracle: c5 sweep sample {s5['seconds']:.2f} s on {nth} threads, {s5['ns_per_cell_dir']:.1f} ns")
+        # the order-p oracle (numpy, one process) on a bounded sample: a 32 x 32
+        # corner of the C2 mesh at orders 2 and 3, all 40 directions
+        import dataclasses
+
+        from oracle import hp as orc_hp
+        c2p = sninputs_config("c2")
+        corner = lambda a: a.reshape(c2p.ny, c2p.nx)[:32, :32].ravel()
+        for order in (2, 3):
+            ps = dataclasses.replace(c2p, nx=32, ny=32, sigma_t=corner(c2p.sigma_t), sigma_s=corner(c2p.sigma_s),
+                                     q=corner(c2p.q), order=order)
+            t0 = time.perf_counter()
+            orc_hp.sweep(ps, None, ps.q)
+            out["cpu_baseline"]["grind_ns_by_config"][f"c2_order{order}"] = \
+                (time.perf_counter() - t0) * 1e9 / (ps.ncells * ps.ndirs)
+        out["cpu_baseline"]["order_p_sample"] = ("oracle/hp.py (numpy, one process) sweep of a 32 x 32 corner of "
+                                                 "the c2 mesh, all 40 directions")
     print(json.dumps(out), flush=True)
 
 
@@ -660,9 +676,19 @@ def bench_hp(log, budget_s=90.0):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 10
             cd = p.ncells * p.ndirs
+            # algorithmic figures per sweep: psi written once (8 B per node and
+            # direction) plus phi and the cell data read once; the
+            # fast-diagonalisation cell solve, 24 (p + 1)^3 flops per cell and
+            # direction (two complex transforms each way, the division)
+            hbm_bytes = cd * p.nn * 8 + p.ncells * (p.nn + 3) * 8
+            flops = 24 * (order + 1) ** 3 * cd
             out["sweep_c2_mesh"][f"order{order}"] = {
                 "ms": ms, "grind_ns_per_cell_dir": ms * 1e6 / cd, "grind_ns_per_node_dir": ms * 1e6 / (cd * p.nn),
-                "psi_write_GBps": cd * p.nn * 8 / (ms * 1e-3) / 1e9}
+                "roofline": {"bound": "latency (the wavefront: 31 tile diagonals x 31 cell diagonals)",
+                             "hbm_GBps": hbm_bytes / (ms * 1e-3) / 1e9, "hbm_frac": hbm_bytes / (ms * 1e-3) / 8e12,
+                             "fp64_TFLOPs": flops / (ms * 1e-3) / 1e12,
+                             "fp64_frac": flops / (ms * 1e-3) / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
+                             "flops_per_cell_dir": 24 * (order + 1) ** 3}}
         log(f"order {order} sweep on the C2 mesh: {ms:.3f} ms ({ms * 1e6 / cd:.2f} ns per cell-dir)")
 
     def run(p, use_dsa):
