@@ -42,6 +42,26 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// A double moved across lanes by DPP (two 32-bit moves): quad_perm CTRL
+// 0x55 a broadcasts lane a of every quad, row_ror CTRL 0x120 + n gives lane l
+// of a 16-lane row the value of lane (l - n) mod 16 of that row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int A>
+__device__ __forceinline__ double quad_bcast(double v) {
+    return dpp_d<0x55 * A>(v);
+}
+template <int M>
+__device__ __forceinline__ double row_rot(double v) {
+    if constexpr (M == 0) return v;
+    else return dpp_d<0x120 + 4 * M>(v);
+}
+
 // entry [k][a] of a 4 x 4 table for a lane-dependent k (compile-time a):
 // selects among the rows without indexing the table by a register
 template <int N>
@@ -64,10 +84,12 @@ __device__ __forceinline__ double vec_pick(const double (&t)[4], int k) {
 // workgroup per (direction, tile), and the launches run in order, so a tile's
 // upwind tiles are complete when it starts.  Inside its tile a workgroup walks
 // the cell diagonals, a barrier between diagonals.  A cell is solved by a
-// group of (p + 1)^2 lanes, lane (i, j) of the group holding node (i, j) of
-// the frame (i along x) through every stage: each transform along an axis
-// gathers the p + 1 values of its line by lane shuffles within the group, and
-// every lane keeps the table rows of its own (i, j) in registers.  Upwind
+// group of 16 lanes, one DPP row, lane 4 j + i holding node (i, j) of the
+// frame (i along x) through every stage (at p = 2 the lanes with i or j = 3
+// pad the 3 x 3 group): a transform along x gathers its line from the lane's
+// quad (quad_perm broadcasts), one along y from the row rotated by 4, 8 and 12
+// lanes (row_ror), all VALU moves, and every lane keeps the table rows of its
+// own (i, j) in registers, those of the y stages in rotation order.  Upwind
 // faces inside the tile come from LDS (written one diagonal earlier, double-
 // buffered by diagonal parity, indexed by the tile-local x position); across a
 // tile edge from psi (an earlier launch), at the domain edge from the inflow.
@@ -83,7 +105,7 @@ __device__ __forceinline__ double vec_pick(const double (&t)[4], int k) {
 // accesses at every step the waits are exact instead of a full drain per step
 // (measured: a wait for every outstanding access before each step's face loads).
 template <int P>
-__global__ void __launch_bounds__(1024) sweep_hp_kernel(HpTab tb, int nx, int ny, int ndirs, long nbf, int TS,
+__global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny, int ndirs, long nbf, int TS,
                                                        int tdiag, int nTx, int nTy,
                                                        const DirInfo* __restrict__ dirs,
                                                        const double* __restrict__ sigt,
@@ -91,12 +113,16 @@ __global__ void __launch_bounds__(1024) sweep_hp_kernel(HpTab tb, int nx, int ny
                                                        const double* __restrict__ phi, const double* __restrict__ q,
                                                        const double* __restrict__ inflow, double* __restrict__ psi) {
     constexpr int N = P + 1, NN = N * N;
-    constexpr int GPW = 64 / NN;  // cell groups per wave
+    constexpr int GPW = 4;  // cell groups per wave: one 16-lane DPP row each, lane 4 j + i
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int gw = min(lane / NN, GPW - 1), r = min(lane - gw * NN, NN - 1);
+    const int gw = lane >> 4, r = lane & 15;
     const int gid = wave * GPW + gw, ngroups = (blockDim.x >> 6) * GPW;
-    const int g0 = gw * NN;
-    const int i0 = r % N, j0 = r / N;
+    // this lane's node; at p = 2 the lanes with i or j = 3 pad the 3 x 3 group:
+    // they use the clamped node for their addresses, add nothing (zero
+    // coefficients) and store the clamped node's value
+    const int i4 = r & 3, j4 = r >> 2;
+    const bool pad = i4 > P || j4 > P;
+    const int i0 = min(i4, P), j0 = min(j4, P);
     const int d = blockIdx.x % ndirs;
     const int It = max(0, tdiag - (nTy - 1)) + (int)(blockIdx.x / ndirs);
     const int Jt = tdiag - It;
@@ -115,6 +141,26 @@ __global__ void __launch_bounds__(1024) sweep_hp_kernel(HpTab tb, int nx, int ny
         v1i[a] = row_pick<N>(tb.Vi, i0, a);
         v2r[a] = row_pick<N>(tb.Vr, j0, a);
         v2i[a] = row_pick<N>(tb.Vi, j0, a);
+    }
+    // the y stages take the line's values by row rotations, the m-th bringing
+    // b = (j4 - m) mod 4, so their coefficients are stored in that order (zero
+    // for the padding b = 3 at p = 2)
+    double w2rr[4], w2ri[4], v2rr[4], v2ri[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double a = 0.0, b = 0.0, c = 0.0, e = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < N; ++bb) {
+            const bool hit = ((j4 - m + 4) & 3) == bb;
+            a = hit ? w2r[bb] : a;
+            b = hit ? w2i[bb] : b;
+            c = hit ? v2r[bb] : c;
+            e = hit ? v2i[bb] : e;
+        }
+        w2rr[m] = a;
+        w2ri[m] = b;
+        v2rr[m] = c;
+        v2ri[m] = e;
     }
     const double zr0 = ax * vec_pick<N>(tb.lr, i0) + ay * vec_pick<N>(tb.lr, j0);
     const double zi0 = ax * vec_pick<N>(tb.li, i0) + ay * vec_pick<N>(tb.li, j0);
@@ -183,47 +229,55 @@ __global__ void __launch_bounds__(1024) sweep_hp_kernel(HpTab tb, int nx, int ny
         const double gx2 = *px2, gy2 = *py2;
         const int ir = x0 + al, jr = y0 + bl;
         const int cur = k & 1, nxt = cur ^ 1;
-        double f = (ss * ph + qq) * kInv4Pi;
+        double f = pad ? 0.0 : (ss * ph + qq) * kInv4Pi;
         const double lx_ = xf[(cur * (TS + 1) + al) * N + j0];
         const double ly_ = yf[(cur * TS + al) * N + i0];
         const double upx = al > 0 ? lx_ : (ir > 0 || inflow ? gx : 0.0);
         const double upy = bl > 0 ? ly_ : (jr > 0 || inflow ? gy : 0.0);
-        f = fma(cx, upx, f);
-        f = fma(cy, upy, f);
-        // along x: T(i0, j0) = sum_a W[i0][a] f(a, j0)
+        f = pad ? 0.0 : fma(cy, upy, fma(cx, upx, f));
+        // along x: T(i, j) = sum_a W[i][a] f(a, j), the quad's lanes a
+        const double fq[4] = {quad_bcast<0>(f), quad_bcast<1>(f), quad_bcast<2>(f), quad_bcast<3>(f)};
         double tr = 0.0, ti = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            const double fa = __shfl(f, g0 + a + N * j0, 64);
-            tr = fma(w1r[a], fa, tr);
-            ti = fma(w1i[a], fa, ti);
+            tr = fma(w1r[a], fq[a], tr);
+            ti = fma(w1i[a], fq[a], ti);
         }
-        // along y: F(i0, j0) = sum_b W[j0][b] T(i0, b)
+        // along y: F(i, j) = sum_b W[j][b] T(i, b), the row rotated by 4 m
+        const double xr[4] = {tr, row_rot<1>(tr), row_rot<2>(tr), row_rot<3>(tr)};
+        const double xi[4] = {ti, row_rot<1>(ti), row_rot<2>(ti), row_rot<3>(ti)};
         double fr = 0.0, fi = 0.0;
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-            const double xr = __shfl(tr, g0 + i0 + N * b, 64), xi = __shfl(ti, g0 + i0 + N * b, 64);
-            fr = fma(w2r[b], xr, fma(-w2i[b], xi, fr));
-            fi = fma(w2r[b], xi, fma(w2i[b], xr, fi));
+        for (int m = 0; m < 4; ++m) {
+            fr = fma(w2rr[m], xr[m], fma(-w2ri[m], xi[m], fr));
+            fi = fma(w2rr[m], xi[m], fma(w2ri[m], xr[m], fi));
         }
         // U = F / (a_x lambda_i0 + a_y lambda_j0 + sigma_t)
         const double zr = zr0 + st, zi = zi0;
         const double inv = 1.0 / (zr * zr + zi * zi);
         const double ur = (fr * zr + fi * zi) * inv, ui = (fi * zr - fr * zi) * inv;
-        // back along x: T2(i0, j0) = sum_k V[i0][k] U(k, j0)
+        // back along x: T2(i, j) = sum_k V[i][k] U(k, j)
+        const double uq[4] = {quad_bcast<0>(ur), quad_bcast<1>(ur), quad_bcast<2>(ur), quad_bcast<3>(ur)};
+        const double vq[4] = {quad_bcast<0>(ui), quad_bcast<1>(ui), quad_bcast<2>(ui), quad_bcast<3>(ui)};
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int kk = 0; kk < N; ++kk) {
-            const double xr = __shfl(ur, g0 + kk + N * j0, 64), xi = __shfl(ui, g0 + kk + N * j0, 64);
-            sr = fma(v1r[kk], xr, fma(-v1i[kk], xi, sr));
-            si = fma(v1r[kk], xi, fma(v1i[kk], xr, si));
+            sr = fma(v1r[kk], uq[kk], fma(-v1i[kk], vq[kk], sr));
+            si = fma(v1r[kk], vq[kk], fma(v1i[kk], uq[kk], si));
         }
-        // back along y: u(i0, j0) = Re sum_l V[j0][l] T2(i0, l)
+        // back along y: u(i, j) = Re sum_l V[j][l] T2(i, l)
+        const double yr[4] = {sr, row_rot<1>(sr), row_rot<2>(sr), row_rot<3>(sr)};
+        const double yi[4] = {si, row_rot<1>(si), row_rot<2>(si), row_rot<3>(si)};
         double u = 0.0;
 #pragma unroll
-        for (int l = 0; l < N; ++l) {
-            const double xr = __shfl(sr, g0 + i0 + N * l, 64), xi = __shfl(si, g0 + i0 + N * l, 64);
-            u = fma(v2r[l], xr, fma(-v2i[l], xi, u));
+        for (int m = 0; m < 4; ++m) u = fma(v2rr[m], yr[m], fma(-v2ri[m], yi[m], u));
+        if constexpr (P == 2) {
+            // padding lanes take the value of their clamped node: lane i = 3 from
+            // lane 2 of its quad, then row j = 3 from row 2 (rotation by 4)
+            const double ux = dpp_d<0xA4>(u);  // quad_perm (0, 1, 2, 2)
+            u = i4 > P ? ux : u;
+            const double uy = row_rot<1>(u);
+            u = j4 > P ? uy : u;
         }
         psi[(c * ndirs + d) * NN + n_self] = u;
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
@@ -499,16 +553,16 @@ hipError_t launch_sweep_hp(const HpTab& tb, int nx, int ny, int ndirs, long nbf,
                            const double* inflow, double* psi, hipStream_t st) {
     // 16 x 16 tiles (smaller meshes: one tile per axis of the mesh's size;
     // SN_HP_TILE in the environment overrides the 16, at most 64).  Measured
-    // on the 256^2 S8 mesh, order 2 / 3: tiles of 8 1.39 / 1.59 ms, 12 1.19 /
-    // 1.64, 16 1.26 / 1.67, 24 1.21 / 1.91, 32 1.32 / 1.98, 64 1.67 / 2.73.
-    // Enough waves for a tile's longest diagonal.
+    // on the 256^2 S8 mesh, order 2 / 3: tiles of 8 1.28 / 1.30 ms, 12 1.27 /
+    // 1.29, 16 1.18 / 1.18, 24 1.42 / 1.63.  Enough waves for a tile's longest
+    // diagonal, at most 8 (longer diagonals are walked in chunks).
     int tile = 16;
     if (const char* e = std::getenv("SN_HP_TILE")) tile = std::max(4, std::min(64, std::atoi(e)));
     const int TS = std::min(tile, std::max(nx, ny));
     const int nTx = (nx + TS - 1) / TS, nTy = (ny + TS - 1) / TS;
     const int n1 = tb.p + 1;
-    const int gpw = 64 / (n1 * n1);
-    const int waves = std::max(1, std::min(16, (std::min(TS, std::min(nx, ny)) + gpw - 1) / gpw));
+    const int gpw = 4;  // cell groups per wave (16-lane groups at both orders)
+    const int waves = std::max(1, std::min(8, (std::min(TS, std::min(nx, ny)) + gpw - 1) / gpw));
     const size_t lds = (size_t)(2 * (TS + 1) + 2 * TS) * n1 * sizeof(double);
     for (int t = 0; t <= nTx + nTy - 2; ++t) {
         const int ntiles = std::min(t, nTx - 1) - std::max(0, t - (nTy - 1)) + 1;
