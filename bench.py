@@ -560,7 +560,9 @@ def bench_pipe(log, budget_s=100.0):
     full NIP and full mNIP (the paper's three columns) with an exact inner
     solve (band LU on the device), het-NIP with the SIP-multigrid GMRES inner
     solve stopped at 1e-4 (the paper's inner tolerance), and SIP het (CG) and
-    full (exact); source iteration to 1e-8 for het-NIP and het-SIP.  Then the
+    full (exact); source iteration to 1e-8 for het-NIP and het-SIP; and the
+    paper's three columns again with order-2 DG (the paper's order), exact
+    inner solves.  Then the
     two-region scan of sigma_pipe (everything else 200, c dt = 1000) with
     het/full NIP and mNIP.  All use the sigma_t mass of Alg. 2.  "DNC": not
     converged in the iteration cap; "n/a": the form is undefined (mNIP next to
@@ -584,7 +586,8 @@ def bench_pipe(log, budget_s=100.0):
         res = {}
         kw = dict(use_dsa=True, mass_kind=1, diffusion=diffusion, precond=precond, cg_rtol=inner_tol,
                   cg_maxit=20000)
-        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta) as ctx:
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta,
+                     order=p.order) as ctx:
             q = t(p.q)
             phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
             try:
@@ -610,6 +613,11 @@ def bench_pipe(log, budget_s=100.0):
             row = {"thick_share": float(base.thick_mask(1.0).mean())}
             for name, eta, diffusion, precond, inner_tol, si in PIPE_COLUMNS:
                 row[name] = run(dataclasses.replace(base, eta=eta), diffusion, precond, inner_tol, si)
+            # the paper's order: the same three columns with order-2 DG, exact inner solves
+            b2 = dataclasses.replace(base, order=2)
+            for name, eta, diffusion in (("order2_full_nip", 0.0, 1), ("order2_full_mnip", 0.0, 2),
+                                         ("order2_het_nip", 1.0, 1)):
+                row[name] = run(dataclasses.replace(b2, eta=eta), diffusion, 2, 0.0, False)
             out["problems"][f"#{k} cdt={label}"] = row
     for sp in (0.0, 1e-3, 0.1, 1.0, 5.0, 10.0, 100.0):
         if time.perf_counter() - t_start > budget_s:
@@ -619,9 +627,10 @@ def bench_pipe(log, budget_s=100.0):
         out["sigma_pipe_scan"][str(sp)] = {name: run(dataclasses.replace(base, eta=eta), diffusion, 2, 0.0, False)
                                            for name, eta, diffusion in PIPE_SCAN_COLUMNS}
     out["seconds"] = time.perf_counter() - t_start
-    summary = {k: tuple(v[c]["gmres30_to_1e-12"] for c in ("full_nip", "full_mnip", "het_nip"))
+    summary = {k: tuple(v[c]["gmres30_to_1e-12"] for c in ("full_nip", "full_mnip", "het_nip", "order2_full_nip",
+                                                             "order2_full_mnip", "order2_het_nip"))
                for k, v in out["problems"].items()}
-    log(f"crooked pipe (full NIP, full mNIP, het NIP): {json.dumps(summary)}")
+    log(f"crooked pipe (full NIP, full mNIP, het NIP; the same at order 2): {json.dumps(summary)}")
     return out
 
 
