@@ -295,7 +295,8 @@ def main():
     torch.cuda.set_device(0)
 
     if args.pipe_only:
-        print(json.dumps(bench_pipe(log)), flush=True)
+        print(json.dumps({"crooked_pipe": bench_pipe(log), "crooked_pipe_refined": bench_pipe_refined(log)}),
+              flush=True)
         return
     if args.hp_only:
         print(json.dumps(bench_hp(log)), flush=True)
@@ -471,6 +472,7 @@ def main():
 
     # ---- crooked-pipe stand-in: heterogeneous against full DSA ----
     out["crooked_pipe"] = bench_pipe(log)
+    out["crooked_pipe_refined"] = bench_pipe_refined(log)
 
     # ---- order p = 2, 3: sweep grind and the hohlraum stand-in ----
     out["higher_order"] = bench_hp(log)
@@ -631,6 +633,73 @@ def bench_pipe(log, budget_s=100.0):
                                                              "order2_full_mnip", "order2_het_nip"))
                for k, v in out["problems"].items()}
     log(f"crooked pipe (full NIP, full mNIP, het NIP; the same at order 2): {json.dumps(summary)}")
+    return out
+
+
+# Table crookedpipe2 (order 2, about 1M DOFs, 256 cores): per (problem, c dt), fGMRES(30) iterations to 1e-12
+# and AMG-GMRES iterations per DSA solve (to 1e-4, at most 250) for full NIP, full mNIP and het NIP; context only
+PAPER_PIPE2 = {1: {"1": (35, "DNC", 39, 14, 15, 7), "1e3": ("DNC", "DNC", 73, 99, 25, 9),
+                   "1e8": ("DNC", "DNC", 71, 145, 25, 9)},
+               2: {"1": (27, "DNC", 23, 8, 17, 45), "1e3": ("DNC", "DNC", 40, 13, 29, 180),
+                   "1e8": ("DNC", "DNC", 40, 12, 29, 180)},
+               3: {"1": (34, "DNC", 29, 10, 13, 29), "1e3": ("DNC", "DNC", 55, 33, 22, 36),
+                   "1e8": ("DNC", "DNC", 55, 42, 22, 36)},
+               4: {"1": (38, "DNC", 42, 10, 13, 9), "1e3": ("DNC", "DNC", 71, 26, 23, 12),
+                   "1e8": ("DNC", "DNC", 73, 43, 23, 12)},
+               5: {"1": (37, "DNC", 30, 10, 14, 30), "1e3": ("DNC", "DNC", 78, 34, 27, 35),
+                   "1e8": ("DNC", "DNC", 75, 41, 27, 35)}}
+
+
+def bench_pipe_refined(log, budget_s=100.0, cells_per_unit=16):
+    """The crooked-pipe stand-in on a refined mesh with inexact DSA solves
+    (the protocol of Table crookedpipe2): order-2 DG, S8, 224x160 cells of
+    1/16 (322,560 DOFs, a quarter of the paper's), problems #1-#5 at
+    c dt = 1, 1e3, 1e8; fGMRES(30) to 1e-12 (at most 500 iterations) with
+    full NIP, full mNIP and het NIP, each DSA solved by block-Jacobi GMRES(30)
+    to 1e-4 with at most 250 iterations (the paper's AMG replaced); the mean
+    inner iterations per DSA solve beside each count."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    import sninputs
+    from paper_2001_09196_amd import Context, SnError, sn_krylov_solve
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    t_start = time.perf_counter()
+    nx, ny = 14 * cells_per_unit, 10 * cells_per_unit
+    out = {"workload": f"crooked-pipe stand-in, order-2 DG: 2D {nx}x{ny} cells of 1/{cells_per_unit}, "
+                       f"{nx * ny * 9} DOFs, S8 (40 dirs)",
+           "outer": "fGMRES(30) to 1e-12, at most 500", "inner": "block-Jacobi GMRES(30) to 1e-4, at most 250",
+           "problems": {}, "paper_nip_amg_mnip_amg_het_amg": PAPER_PIPE2}
+
+    def run(p, diffusion):
+        with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta,
+                     order=p.order) as ctx:
+            phi = torch.zeros((p.ncells, p.nn), dtype=torch.float64, device=dev)
+            try:
+                r = sn_krylov_solve(ctx, t(p.q), None, phi, tol=1e-12, max_it=500, restart=30, use_dsa=True,
+                                    mass_kind=1, cg_rtol=1e-4, cg_maxit=250, diffusion=diffusion, precond=0)
+            except SnError as e:
+                return {"iters": "n/a", "error": str(e)}
+            return {"iters": r["iters"] if r["rc"] == 0 else "DNC", "seconds": r["seconds"],
+                    "inner_iters_per_dsa": float(np.mean(r["cg_hist"])) if r["iters"] else 0.0}
+
+    for label, cdt in (("1", 1.0), ("1e3", 1e3), ("1e8", 1e8)):
+        for k in sorted(sninputs.PIPE_PROBLEMS):
+            if time.perf_counter() - t_start > budget_s:
+                out["truncated"] = True
+                break
+            b = dataclasses.replace(sninputs.crooked_pipe(k, cdt, cells_per_unit=cells_per_unit), order=2)
+            row = {"thick_share": float(b.thick_mask(1.0).mean())}
+            for name, eta, diffusion in (("full_nip", 0.0, 1), ("full_mnip", 0.0, 2), ("het_nip", 1.0, 1)):
+                row[name] = run(dataclasses.replace(b, eta=eta), diffusion)
+            out["problems"][f"#{k} cdt={label}"] = row
+    out["seconds"] = time.perf_counter() - t_start
+    summary = {k: tuple((v[c]["iters"], round(v[c].get("inner_iters_per_dsa", 0.0))) for c in
+                        ("full_nip", "full_mnip", "het_nip")) for k, v in out["problems"].items()}
+    log(f"crooked pipe refined (full NIP, full mNIP, het NIP; [outer, inner per DSA]): {json.dumps(summary)}")
     return out
 
 
