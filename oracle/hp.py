@@ -1,4 +1,4 @@
-"""CPU FP64 oracle of the higher-order path: upwind DG of order p = 1..3 (Q_p)
+"""CPU FP64 oracle of the higher-order path: upwind DG of order p = 1..4 (Q_p)
 in 2D, source iteration and the heterogeneous DSA at that order.
 
 TEST INFRASTRUCTURE ONLY: the independent checker of the GPU library's

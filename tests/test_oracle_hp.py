@@ -1,4 +1,4 @@
-"""Pins of the order-p oracle (oracle/hp.py, 2D Q_p, p = 1..3).
+"""Pins of the order-p oracle (oracle/hp.py, 2D Q_p, p = 1..4).
 
 H1 p = 1 is the Q1 oracle: sweeps and the SIP / NIP / mNIP diffusion matrices
    equal those of the independently pinned C oracle.
@@ -6,7 +6,7 @@ H2 polynomial reproduction: when the exact transport solution is a Q_p
    polynomial (its source Omega.grad psi + sigma_t psi is then in Q_p too,
    and the inflow is its trace), the sweep returns it exactly, for every
    direction sign pattern.
-H3 p = 2, 3 sweeps against the dense solve of a brute-force quadrature
+H3 p = 2, 3, 4 sweeps against the dense solve of a brute-force quadrature
    assembly (tests/bruteforce_hp.py) with boundary inflow.
 H4 particle balance per direction: absorption + net outflow = source + inflow.
 H5 the diffusion matrices (SIP, NIP, mNIP) against the brute-force pointwise
@@ -14,7 +14,9 @@ H5 the diffusion matrices (SIP, NIP, mNIP) against the brute-force pointwise
    positive definite.
 H6 source iteration reaches the fixed point of the dense block system
    (eq. system), with and without DSA (the DSA does not move it, eq. DSA_fp).
-H7 the Gauss-Lobatto nodes and the 1D matrices: closed forms for p = 1, 2.
+H7 the Gauss-Lobatto nodes (closed forms for p = 1..4) and the 1D matrices
+   (closed forms for p = 1, 2; mass, derivative and integration-by-parts
+   identities for p = 1..4).
 """
 import math
 
@@ -43,6 +45,8 @@ def test_h7_nodes_and_reference_matrices():
     assert np.allclose(hp.gll_nodes(1), [0, 1])
     assert np.allclose(hp.gll_nodes(2), [0, 0.5, 1])
     assert np.allclose(hp.gll_nodes(3), [0, (1 - 1 / math.sqrt(5)) / 2, (1 + 1 / math.sqrt(5)) / 2, 1])
+    # p = 4: the interior points of [-1, 1] are 0 and +-sqrt(3/7)
+    assert np.allclose(hp.gll_nodes(4), [0, (1 - math.sqrt(3 / 7)) / 2, 0.5, (1 + math.sqrt(3 / 7)) / 2, 1])
     r1 = hp.Ref1D(1)
     assert np.allclose(r1.M, [[1 / 3, 1 / 6], [1 / 6, 1 / 3]])
     assert np.allclose(r1.D, [[-0.5, 0.5], [-0.5, 0.5]])
@@ -50,7 +54,7 @@ def test_h7_nodes_and_reference_matrices():
     r2 = hp.Ref1D(2)                      # quadratic Lagrange on 0, 1/2, 1 (Simpson-type masses)
     assert np.allclose(r2.M, np.array([[4, 2, -1], [2, 16, 2], [-1, 2, 4]]) / 30)
     assert np.allclose(r2.K, np.array([[7, -8, 1], [-8, 16, -8], [1, -8, 7]]) / 3)
-    for p in (1, 2, 3):
+    for p in (1, 2, 3, 4):
         r = hp.Ref1D(p)
         assert np.allclose(r.M.sum(), 1.0) and np.allclose(r.D.sum(axis=1), 0.0)
         assert np.allclose(r.D + r.D.T, np.outer(np.eye(p + 1)[-1], np.eye(p + 1)[-1]) -
@@ -109,7 +113,7 @@ def _poly_case(order, om_signs):
     return prob, src, inflow, exact
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
 @pytest.mark.parametrize("signs", [(1, 1), (-1, 1), (1, -1), (-1, -1)])
 def test_h2_polynomial_reproduction(order, signs):
     prob, src, inflow, exact = _poly_case(order, signs)
@@ -117,20 +121,27 @@ def test_h2_polynomial_reproduction(order, signs):
     assert np.max(np.abs(psi[:, 0, :] - exact)) <= 1e-12 * np.max(np.abs(exact))
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_h3_sweep_vs_bruteforce(order):
     prob = _prob(3, 2, order, seed=3 + order, voids=True)
     rng = np.random.default_rng(7)
     inflow = rng.uniform(0, 1, (prob.ndirs, hp.inflow_size(order, prob.nx, prob.ny)))
     psi = hp.sweep(prob, None, prob.q, inflow=inflow)
-    for d in range(prob.ndirs):
+    dirs = range(prob.ndirs)
+    if order == 4:
+        # the brute-force assembly takes about a second per direction at
+        # order 4: the first direction of each quadrant
+        sig = [tuple(np.sign(prob.omega[d][:2])) for d in dirs]
+        dirs = [sig.index(sg) for sg in sorted(set(sig))]
+        assert len(dirs) == 4
+    for d in dirs:
         L = bfh.transport_matrix(prob, d)
         f = bfh.load(prob, d, dens=prob.q / (4 * math.pi), inflow=inflow)
         ref = np.linalg.solve(L, f).reshape(prob.ncells, prob.nn)
         assert np.max(np.abs(psi[:, d] - ref)) <= 1e-12 * np.max(np.abs(ref)), d
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_h4_balance(order):
     prob = _prob(4, 3, order, seed=11, voids=True)
     psi = hp.sweep(prob, None, prob.q)
@@ -157,7 +168,7 @@ def test_h4_balance(order):
         assert abs(ab + out - src) <= 1e-12 * src, d
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("form,fname", [(hp.SIP, "sip"), (hp.NIP, "nip"), (hp.MNIP, "mnip")])
 def test_h5_diffusion_vs_bruteforce(order, form, fname):
     prob = _prob(3, 3, order, seed=5, voids=False)
@@ -186,9 +197,9 @@ def test_h5_interior_rows_annihilate_constants():
                 assert np.allclose(y[s * prob.nn:(s + 1) * prob.nn], ref, rtol=1e-11, atol=0), form
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_h6_si_fixed_point(order):
-    prob = _prob(3, 2, order, seed=9, voids=False)
+    prob = _prob(2, 2, order, seed=9, voids=False) if order == 4 else _prob(3, 2, order, seed=9, voids=False)
     thick = prob.sigma_s >= prob.eta
     prob.sigma_t[thick] = 5.0                    # thick (sigma_s >= 1) at scattering ratio 0.8, so that
     prob.sigma_s[thick] = 4.0                    # plain SI converges in about a hundred iterations
