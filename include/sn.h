@@ -61,7 +61,7 @@ typedef struct {
     int nx, ny, nz;            /* cells per axis; nz = 1 in 2D */
     double hx, hy, hz;         /* cell widths; hz ignored in 2D */
     int order;                 /* DG order p (the paper runs 2 and 4 in Sec. 4): 0 or 1 for Q1 (the default,
-                                  every entry point), 2 or 3 for Q_p on the (p + 1)^2 Gauss-Lobatto nodes of
+                                  every entry point), 2, 3 or 4 for Q_p on the (p + 1)^2 Gauss-Lobatto nodes of
                                   each cell, node i + (p + 1) j, 2D only.  At p >= 2 the sweep, the moment,
                                   the DSA correction (any form; GMRES with block Jacobi, or the direct solve)
                                   and source iteration (FP64, forward, diagonal DSA, no checkpoints) are

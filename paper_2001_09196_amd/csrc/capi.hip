@@ -210,7 +210,7 @@ int check_mesh(const sn_mesh* m) {
         return fail(SN_ERR_INVALID, "cell widths must be positive and finite");
     long nc = (long)m->nx * m->ny * m->nz;
     if (nc > (1L << 31) - 1) return fail(SN_ERR_UNSUPPORTED, "more than 2^31 - 1 cells");
-    if (m->order < 0 || m->order > 3) return fail(SN_ERR_INVALID, "order must be 0..3 (got %d)", m->order);
+    if (m->order < 0 || m->order > 4) return fail(SN_ERR_INVALID, "order must be 0..4 (got %d)", m->order);
     if (m->order >= 2 && m->dim != 2) return fail(SN_ERR_UNSUPPORTED, "order %d is built for 2D only", m->order);
     return 0;
 }

@@ -1,4 +1,4 @@
-// Upwind DG of order p = 2, 3 in 2D (Q_p on the Gauss-Lobatto nodes of each
+// Upwind DG of order p = 2, 3, 4 in 2D (Q_p on the Gauss-Lobatto nodes of each
 // cell; Sec. 3.1 at the orders the paper runs in Sec. 4): the sweep with a
 // fast-diagonalisation cell solve, the moment, and the thick diffusion
 // matrices (SIP, NIP, mNIP) assembled as block-sparse rows.
@@ -16,7 +16,8 @@
 // source (sigma_s phi + q) / 4pi plus, for an inflow face, a_axis c0 (x) u_up
 // with c0 = M^{-1} e_0 and u_up the upwind trace (the neighbour's face nodes).
 //
-// The sweep runs in tile planes (sweep_hp_kernel below).
+// The sweep runs in tile planes (sweep_hp_kernel below; sweep_hp_shfl_kernel
+// at p = 4).
 #include <cstdlib>
 
 #include "../../include/sn.h"
@@ -62,17 +63,17 @@ __device__ __forceinline__ double row_rot(double v) {
     else return dpp_d<0x120 + 4 * M>(v);
 }
 
-// entry [k][a] of a 4 x 4 table for a lane-dependent k (compile-time a):
-// selects among the rows without indexing the table by a register
+// entry [k][a] of a table for a lane-dependent k (compile-time a): selects
+// among the rows without indexing the table by a register
 template <int N>
-__device__ __forceinline__ double row_pick(const double (&t)[4][4], int k, int a) {
+__device__ __forceinline__ double row_pick(const double (&t)[kHpMaxN][kHpMaxN], int k, int a) {
     double v = t[0][a];
 #pragma unroll
     for (int kk = 1; kk < N; ++kk) v = k == kk ? t[kk][a] : v;
     return v;
 }
 template <int N>
-__device__ __forceinline__ double vec_pick(const double (&t)[4], int k) {
+__device__ __forceinline__ double vec_pick(const double (&t)[kHpMaxN], int k) {
     double v = t[0];
 #pragma unroll
     for (int kk = 1; kk < N; ++kk) v = k == kk ? t[kk] : v;
@@ -278,6 +279,178 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
             u = i4 > P ? ux : u;
             const double uy = row_rot<1>(u);
             u = j4 > P ? uy : u;
+        }
+        psi[(c * ndirs + d) * NN + n_self] = u;
+        if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
+        if (j0 == P) yf[(nxt * TS + al) * N + i0] = u;
+        if (k2 != k) lds_barrier();
+        k = k2;
+        base = b2;
+        al = al2;
+        bl = bl2;
+        c = c2;
+        st = st2;
+        ss = ss2;
+        qq = q2;
+        ph = ph2;
+        gx = gx2;
+        gy = gy2;
+    }
+}
+
+// The same tile-plane sweep with the transforms done by lane shuffles
+// (ds_bpermute), for p = 4, whose 25 nodes do not fit a 16-lane DPP row.  A
+// cell is solved by a group of (p + 1)^2 lanes, lane g0 + i + (p + 1) j of
+// the wave holding node (i, j) of the frame, two groups per wave; the 14
+// lanes past the second group repeat that group's last lane (same node, same
+// values, same stores).  A transform along x gathers the p + 1 values of the
+// lane's line from lanes g0 + a + (p + 1) j, one along y from lanes
+// g0 + i + (p + 1) b.  The rest (tile planes, LDS faces inside a tile,
+// next-chunk prefetch, uniform global accesses) is as in sweep_hp_kernel.
+template <int P>
+__global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, int ny, int ndirs, long nbf, int TS,
+                                                            int tdiag, int nTx, int nTy,
+                                                            const DirInfo* __restrict__ dirs,
+                                                            const double* __restrict__ sigt,
+                                                            const double* __restrict__ sigs,
+                                                            const double* __restrict__ phi,
+                                                            const double* __restrict__ q,
+                                                            const double* __restrict__ inflow,
+                                                            double* __restrict__ psi) {
+    constexpr int N = P + 1, NN = N * N;
+    constexpr int GPW = 64 / NN;  // cell groups per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gw = min(lane / NN, GPW - 1), r = min(lane - gw * NN, NN - 1);
+    const int gid = wave * GPW + gw, ngroups = (blockDim.x >> 6) * GPW;
+    const int g0 = gw * NN;
+    const int i0 = r % N, j0 = r / N;
+    const int d = blockIdx.x % ndirs;
+    const int It = max(0, tdiag - (nTy - 1)) + (int)(blockIdx.x / ndirs);
+    const int Jt = tdiag - It;
+    const DirInfo di = dirs[d];
+    const double ax = di.ax, ay = di.ay;
+    const int rx = di.rx, ry = di.ry;
+    // this lane's table rows
+    double w1r[N], w1i[N], w2r[N], w2i[N], v1r[N], v1i[N], v2r[N], v2i[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        w1r[a] = row_pick<N>(tb.Wr, i0, a);
+        w1i[a] = row_pick<N>(tb.Wi, i0, a);
+        w2r[a] = row_pick<N>(tb.Wr, j0, a);
+        w2i[a] = row_pick<N>(tb.Wi, j0, a);
+        v1r[a] = row_pick<N>(tb.Vr, i0, a);
+        v1i[a] = row_pick<N>(tb.Vi, i0, a);
+        v2r[a] = row_pick<N>(tb.Vr, j0, a);
+        v2i[a] = row_pick<N>(tb.Vi, j0, a);
+    }
+    const double zr0 = ax * vec_pick<N>(tb.lr, i0) + ay * vec_pick<N>(tb.lr, j0);
+    const double zi0 = ax * vec_pick<N>(tb.li, i0) + ay * vec_pick<N>(tb.li, j0);
+    const double cx = ax * vec_pick<N>(tb.c0, i0), cy = ay * vec_pick<N>(tb.c0, j0);
+    const int ip = refl(i0, rx, P), jp = refl(j0, ry, P);  // this lane's node in the physical numbering
+    const int n_self = ip + N * jp;
+    const int n_upx = refl(P, rx, P) + N * jp;              // the x-upwind neighbour's facing node
+    const int n_upy = ip + N * refl(P, ry, P);              // the y-upwind neighbour's facing node
+    // the tile in frame coordinates
+    const int x0 = It * TS, y0 = Jt * TS;
+    const int lx = min(TS, nx - x0), ly = min(TS, ny - y0);
+    // LDS faces: x [2][TS + 1][N] (the face left of local position a at a), y [2][TS][N]
+    extern __shared__ double lds[];
+    double* xf = lds;
+    double* yf = lds + 2 * (TS + 1) * N;
+    const int kend = lx + ly - 2;
+    auto first_of = [&](int kk) { return max(0, kk - (ly - 1)); };
+    auto last_of = [&](int kk) { return min(kk, lx - 1); };
+    auto cell_of = [&](int kk, int bb, int* irp, int* jrp) {
+        const int a = min(bb + gid, last_of(kk));
+        *irp = a;
+        *jrp = kk - a;
+        const int ir = x0 + a, jr = y0 + (kk - a);
+        const int i = rx ? nx - 1 - ir : ir, j = ry ? ny - 1 - jr : jr;
+        return (long)j * nx + i;
+    };
+    // absent phi or q: read sigma_t instead and scale by zero
+    const double* php = phi ? phi : sigt;
+    const double* qp = q ? q : sigt;
+    const double phs = phi ? 1.0 : 0.0, qs = q ? 1.0 : 0.0;
+    const int phm = phi ? NN : 1, pho = phi ? n_self : 0;
+    // the global upwind values of a cell (tile edge: psi of the upwind tile,
+    // written by an earlier launch; domain edge: the inflow; elsewhere an
+    // unused load of sigma_t)
+    auto face_ptrs = [&](long cc, int a, int b, const double** px, const double** py) {
+        const int ir = x0 + a, jr = y0 + b;
+        const int i = rx ? nx - 1 - ir : ir, j = ry ? ny - 1 - jr : jr;
+        *px = (a == 0 && ir > 0) ? psi + ((cc + (rx ? 1 : -1)) * ndirs + d) * NN + n_upx
+              : (ir == 0 && inflow ? inflow + (long)d * nbf + (long)j * N + jp : sigt + cc);
+        *py = (b == 0 && jr > 0) ? psi + ((cc + (ry ? nx : -nx)) * ndirs + d) * NN + n_upy
+              : (jr == 0 && inflow ? inflow + (long)d * nbf + (long)ny * N + (long)i * N + ip : sigt + cc);
+    };
+    int k = 0, base = 0;
+    int al, bl;  // tile-local frame position
+    long c = cell_of(k, base, &al, &bl);
+    double st = sigt[c], ss = sigs[c], qq = qs * qp[c], ph = phs * php[c * phm + pho];
+    double gx, gy;
+    {
+        const double *px, *py;
+        face_ptrs(c, al, bl, &px, &py);
+        gx = *px;
+        gy = *py;
+    }
+    while (k <= kend) {
+        // the next chunk, and its cell data loaded ahead
+        int k2 = k, b2 = base + ngroups;
+        if (b2 > last_of(k)) {
+            k2 = k + 1;
+            b2 = first_of(k2);
+        }
+        int al2 = al, bl2 = bl;
+        const long c2 = k2 <= kend ? cell_of(k2, b2, &al2, &bl2) : c;
+        const double *px2, *py2;
+        face_ptrs(c2, al2, bl2, &px2, &py2);
+        const double st2 = sigt[c2], ss2 = sigs[c2], q2 = qs * qp[c2], ph2 = phs * php[c2 * phm + pho];
+        const double gx2 = *px2, gy2 = *py2;
+        const int ir = x0 + al, jr = y0 + bl;
+        const int cur = k & 1, nxt = cur ^ 1;
+        double f = (ss * ph + qq) * kInv4Pi;
+        const double lx_ = xf[(cur * (TS + 1) + al) * N + j0];
+        const double ly_ = yf[(cur * TS + al) * N + i0];
+        const double upx = al > 0 ? lx_ : (ir > 0 || inflow ? gx : 0.0);
+        const double upy = bl > 0 ? ly_ : (jr > 0 || inflow ? gy : 0.0);
+        f = fma(cx, upx, f);
+        f = fma(cy, upy, f);
+        // along x: T(i0, j0) = sum_a W[i0][a] f(a, j0)
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const double fa = __shfl(f, g0 + a + N * j0, 64);
+            tr = fma(w1r[a], fa, tr);
+            ti = fma(w1i[a], fa, ti);
+        }
+        // along y: F(i0, j0) = sum_b W[j0][b] T(i0, b)
+        double fr = 0.0, fi = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            const double xr = __shfl(tr, g0 + i0 + N * b, 64), xi = __shfl(ti, g0 + i0 + N * b, 64);
+            fr = fma(w2r[b], xr, fma(-w2i[b], xi, fr));
+            fi = fma(w2r[b], xi, fma(w2i[b], xr, fi));
+        }
+        // U = F / (a_x lambda_i0 + a_y lambda_j0 + sigma_t)
+        const double zr = zr0 + st, zi = zi0;
+        const double inv = 1.0 / (zr * zr + zi * zi);
+        const double ur = (fr * zr + fi * zi) * inv, ui = (fi * zr - fr * zi) * inv;
+        // back along x: T2(i0, j0) = sum_k V[i0][k] U(k, j0)
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) {
+            const double xr = __shfl(ur, g0 + kk + N * j0, 64), xi = __shfl(ui, g0 + kk + N * j0, 64);
+            sr = fma(v1r[kk], xr, fma(-v1i[kk], xi, sr));
+            si = fma(v1r[kk], xi, fma(v1i[kk], xr, si));
+        }
+        // back along y: u(i0, j0) = Re sum_l V[j0][l] T2(i0, l)
+        double u = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            const double xr = __shfl(sr, g0 + i0 + N * l, 64), xi = __shfl(si, g0 + i0 + N * l, 64);
+            u = fma(v2r[l], xr, fma(-v2i[l], xi, u));
         }
         psi[(c * ndirs + d) * NN + n_self] = u;
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
@@ -561,7 +734,8 @@ hipError_t launch_sweep_hp(const HpTab& tb, int nx, int ny, int ndirs, long nbf,
     const int TS = std::min(tile, std::max(nx, ny));
     const int nTx = (nx + TS - 1) / TS, nTy = (ny + TS - 1) / TS;
     const int n1 = tb.p + 1;
-    const int gpw = 4;  // cell groups per wave (16-lane groups at both orders)
+    // cell groups per wave: 16-lane DPP groups at p = 2, 3; two 25-lane groups at p = 4
+    const int gpw = tb.p == 4 ? 64 / (n1 * n1) : 4;
     const int waves = std::max(1, std::min(8, (std::min(TS, std::min(nx, ny)) + gpw - 1) / gpw));
     const size_t lds = (size_t)(2 * (TS + 1) + 2 * TS) * n1 * sizeof(double);
     for (int t = 0; t <= nTx + nTy - 2; ++t) {
@@ -570,9 +744,12 @@ hipError_t launch_sweep_hp(const HpTab& tb, int nx, int ny, int ndirs, long nbf,
         if (tb.p == 2)
             hipLaunchKernelGGL(sweep_hp_kernel<2>, grid, dim3(64 * waves), lds, st, tb, nx, ny, ndirs, nbf, TS, t, nTx,
                                nTy, dirs, sigt, sigs, phi, q, inflow, psi);
-        else
+        else if (tb.p == 3)
             hipLaunchKernelGGL(sweep_hp_kernel<3>, grid, dim3(64 * waves), lds, st, tb, nx, ny, ndirs, nbf, TS, t, nTx,
                                nTy, dirs, sigt, sigs, phi, q, inflow, psi);
+        else
+            hipLaunchKernelGGL(sweep_hp_shfl_kernel<4>, grid, dim3(64 * waves), lds, st, tb, nx, ny, ndirs, nbf, TS, t,
+                               nTx, nTy, dirs, sigt, sigs, phi, q, inflow, psi);
     }
     return hipGetLastError();
 }
@@ -595,10 +772,14 @@ hipError_t launch_hp_assemble(const HpTab& tb, const DsaGeom& g, int op, const i
         if (op == SN_DIFFUSION_SIP) SN_HA(2, SN_DIFFUSION_SIP);
         else if (op == SN_DIFFUSION_NIP) SN_HA(2, SN_DIFFUSION_NIP);
         else SN_HA(2, SN_DIFFUSION_MNIP);
-    } else {
+    } else if (tb.p == 3) {
         if (op == SN_DIFFUSION_SIP) SN_HA(3, SN_DIFFUSION_SIP);
         else if (op == SN_DIFFUSION_NIP) SN_HA(3, SN_DIFFUSION_NIP);
         else SN_HA(3, SN_DIFFUSION_MNIP);
+    } else {
+        if (op == SN_DIFFUSION_SIP) SN_HA(4, SN_DIFFUSION_SIP);
+        else if (op == SN_DIFFUSION_NIP) SN_HA(4, SN_DIFFUSION_NIP);
+        else SN_HA(4, SN_DIFFUSION_MNIP);
     }
 #undef SN_HA
     return hipGetLastError();
@@ -610,8 +791,10 @@ hipError_t launch_hp_spmv(int nn, int nthick, const double* blk, const int* col,
     const int nb = blocks_of((long)nthick * nn, 256);
     if (nn == 9)
         hipLaunchKernelGGL(hp_spmv_kernel<9>, dim3(nb), dim3(256), 0, st, nthick, blk, col, x, b, y);
-    else
+    else if (nn == 16)
         hipLaunchKernelGGL(hp_spmv_kernel<16>, dim3(nb), dim3(256), 0, st, nthick, blk, col, x, b, y);
+    else
+        hipLaunchKernelGGL(hp_spmv_kernel<25>, dim3(nb), dim3(256), 0, st, nthick, blk, col, x, b, y);
     return hipGetLastError();
 }
 
@@ -620,8 +803,10 @@ hipError_t launch_hp_block_inverse(int nn, int nthick, const double* blk, double
     const int nb = blocks_of(nthick, 64);
     if (nn == 9)
         hipLaunchKernelGGL(hp_block_inverse_kernel<9>, dim3(nb), dim3(64), 0, st, nthick, blk, binv, bad);
-    else
+    else if (nn == 16)
         hipLaunchKernelGGL(hp_block_inverse_kernel<16>, dim3(nb), dim3(64), 0, st, nthick, blk, binv, bad);
+    else
+        hipLaunchKernelGGL(hp_block_inverse_kernel<25>, dim3(nb), dim3(64), 0, st, nthick, blk, binv, bad);
     return hipGetLastError();
 }
 
@@ -630,8 +815,10 @@ hipError_t launch_hp_block_apply(int nn, int nthick, const double* binv, const d
     const int nb = blocks_of((long)nthick * nn, 256);
     if (nn == 9)
         hipLaunchKernelGGL(hp_block_apply_kernel<9>, dim3(nb), dim3(256), 0, st, nthick, binv, v, z);
-    else
+    else if (nn == 16)
         hipLaunchKernelGGL(hp_block_apply_kernel<16>, dim3(nb), dim3(256), 0, st, nthick, binv, v, z);
+    else
+        hipLaunchKernelGGL(hp_block_apply_kernel<25>, dim3(nb), dim3(256), 0, st, nthick, binv, v, z);
     return hipGetLastError();
 }
 
@@ -644,8 +831,11 @@ hipError_t launch_hp_rhs(const HpTab& tb, int nthick, double hx, double hy, cons
     if (tb.p == 2)
         hipLaunchKernelGGL(hp_rhs_kernel<2>, dim3(nb), dim3(256), 0, st, tb, nthick, hx, hy, thick_cell, sigma_t,
                            sigma_s, mass_kind, phi_old, phi_si, b);
-    else
+    else if (tb.p == 3)
         hipLaunchKernelGGL(hp_rhs_kernel<3>, dim3(nb), dim3(256), 0, st, tb, nthick, hx, hy, thick_cell, sigma_t,
+                           sigma_s, mass_kind, phi_old, phi_si, b);
+    else
+        hipLaunchKernelGGL(hp_rhs_kernel<4>, dim3(nb), dim3(256), 0, st, tb, nthick, hx, hy, thick_cell, sigma_t,
                            sigma_s, mass_kind, phi_old, phi_si, b);
     return hipGetLastError();
 }
@@ -656,8 +846,10 @@ hipError_t launch_hp_band(int nn, int nthick, const double* blk, const int* col,
     const int nb = blocks_of((long)nthick * nn, 256);
     if (nn == 9)
         hipLaunchKernelGGL(hp_band_kernel<9>, dim3(nb), dim3(256), 0, st, nthick, blk, col, kl, ldb, band);
-    else
+    else if (nn == 16)
         hipLaunchKernelGGL(hp_band_kernel<16>, dim3(nb), dim3(256), 0, st, nthick, blk, col, kl, ldb, band);
+    else
+        hipLaunchKernelGGL(hp_band_kernel<25>, dim3(nb), dim3(256), 0, st, nthick, blk, col, kl, ldb, band);
     return hipGetLastError();
 }
 

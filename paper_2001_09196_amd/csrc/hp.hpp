@@ -1,4 +1,4 @@
-// Order-p (p = 2, 3) 2D path: the constant tables of the discretisation and
+// Order-p (p = 2, 3, 4) 2D path: the constant tables of the discretisation and
 // the launchers of hp.hip.  hp_tables builds the tables on the host from the
 // Gauss-Lobatto nodes (see hp.hip for how the sweep and the diffusion rows
 // use them).
@@ -12,14 +12,15 @@
 
 namespace sn {
 
+constexpr int kHpMaxN = 5;  // nodes per axis at the highest order built (p = 4)
 struct HpTab {
     int p;
-    double lr[4], li[4];            // eigenvalues of G = M^{-1} (D + e0 e0^T)
-    double Vr[4][4], Vi[4][4];      // V[node][k]: eigenvectors in the columns
-    double Wr[4][4], Wi[4][4];      // V^{-1}[k][node]
-    double c0[4];                   // M^{-1} e_0
-    double M[4][4], K[4][4];        // int l_i l_j, int l_i' l_j' on [0, 1]
-    double dl0[4], dl1[4];          // l_i'(0), l_i'(1)
+    double lr[kHpMaxN], li[kHpMaxN];                    // eigenvalues of G = M^{-1} (D + e0 e0^T)
+    double Vr[kHpMaxN][kHpMaxN], Vi[kHpMaxN][kHpMaxN];  // V[node][k]: eigenvectors in the columns
+    double Wr[kHpMaxN][kHpMaxN], Wi[kHpMaxN][kHpMaxN];  // V^{-1}[k][node]
+    double c0[kHpMaxN];                                 // M^{-1} e_0
+    double M[kHpMaxN][kHpMaxN], K[kHpMaxN][kHpMaxN];    // int l_i l_j, int l_i' l_j' on [0, 1]
+    double dl0[kHpMaxN], dl1[kHpMaxN];                  // l_i'(0), l_i'(1)
 };
 
 hipError_t launch_sweep_hp(const HpTab& tb, int nx, int ny, int ndirs, long nbf, const DirInfo* dirs,
@@ -45,9 +46,9 @@ namespace hp_detail {
 
 using cplx = std::complex<double>;
 
-// Solve A x = b (n <= 4, complex) by Gaussian elimination with partial pivoting.
-inline bool csolve(int n, cplx A[4][4], cplx b[4], cplx x[4]) {
-    int perm[4] = {0, 1, 2, 3};
+// Solve A x = b (n <= kHpMaxN, complex) by Gaussian elimination with partial pivoting.
+inline bool csolve(int n, cplx A[kHpMaxN][kHpMaxN], cplx b[kHpMaxN], cplx x[kHpMaxN]) {
+    int perm[kHpMaxN] = {0, 1, 2, 3, 4};
     for (int k = 0; k < n; ++k) {
         int p = k;
         for (int i = k + 1; i < n; ++i)
@@ -93,14 +94,14 @@ inline double dlag(int n, const double* nodes, int k, double x) {
 
 }  // namespace hp_detail
 
-// The tables of order p (2 or 3).  Returns false if the eigenbasis check
+// The tables of order p (2, 3 or 4).  Returns false if the eigenbasis check
 // fails (||G V - V diag(lambda)|| or ||V V^{-1} - I|| above 1e-11).
 inline bool hp_tables(int p, HpTab* tb) {
     using namespace hp_detail;
     const int n = p + 1;
     *tb = HpTab{};
     tb->p = p;
-    double nodes[4];
+    double nodes[kHpMaxN];
     if (p == 2) {
         const double v[3] = {0.0, 0.5, 1.0};
         for (int i = 0; i < 3; ++i) nodes[i] = v[i];
@@ -108,14 +109,18 @@ inline bool hp_tables(int p, HpTab* tb) {
         const double r = 0.5 / std::sqrt(5.0);   // roots of P_3' on [-1, 1] are +-1/sqrt5
         const double v[4] = {0.0, 0.5 - r, 0.5 + r, 1.0};
         for (int i = 0; i < 4; ++i) nodes[i] = v[i];
+    } else if (p == 4) {
+        const double r = 0.5 * std::sqrt(3.0 / 7.0);  // roots of P_4' on [-1, 1] are 0 and +-sqrt(3/7)
+        const double v[5] = {0.0, 0.5 - r, 0.5, 0.5 + r, 1.0};
+        for (int i = 0; i < 5; ++i) nodes[i] = v[i];
     } else {
         return false;
     }
-    // Gauss-Legendre, 5 points on [0, 1] (exact to degree 9 >= 2p)
+    // Gauss-Legendre, 5 points on [0, 1] (exact to degree 9 >= 2p for p <= 4)
     const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831, 0.9061798459386640};
     const double gw[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889, 0.4786286704993665,
                           0.2369268850561891};
-    double D[4][4] = {};
+    double D[kHpMaxN][kHpMaxN] = {};
     for (int g = 0; g < 5; ++g) {
         const double x = 0.5 * (gx[g] + 1.0), w = 0.5 * gw[g];
         for (int i = 0; i < n; ++i)
@@ -132,9 +137,9 @@ inline bool hp_tables(int p, HpTab* tb) {
         tb->dl1[i] = dlag(n, nodes, i, 1.0);
     }
     // G = M^{-1} (D + e0 e0^T), c0 = M^{-1} e0
-    double G[4][4];
+    double G[kHpMaxN][kHpMaxN];
     {
-        cplx A[4][4], b[4], x[4];
+        cplx A[kHpMaxN][kHpMaxN], b[kHpMaxN], x[kHpMaxN];
         for (int col = 0; col <= n; ++col) {
             for (int i = 0; i < n; ++i) {
                 for (int j = 0; j < n; ++j) A[i][j] = tb->M[i][j];
@@ -148,9 +153,9 @@ inline bool hp_tables(int p, HpTab* tb) {
         }
     }
     // characteristic polynomial det(z I - G) = sum_k a[k] z^k (Faddeev-LeVerrier)
-    double a[5] = {};
+    double a[kHpMaxN + 1] = {};
     {
-        double Mk[4][4] = {}, T[4][4];
+        double Mk[kHpMaxN][kHpMaxN] = {}, T[kHpMaxN][kHpMaxN];
         a[n] = 1.0;
         for (int k = 1; k <= n; ++k) {
             // Mk = G M_{k-1} + a[n-k+1] I
@@ -179,7 +184,7 @@ inline bool hp_tables(int p, HpTab* tb) {
         return v;
     };
     // roots: Durand-Kerner from distinct complex starts, then Newton polish
-    cplx z[4];
+    cplx z[kHpMaxN];
     for (int i = 0; i < n; ++i) z[i] = std::pow(cplx(0.4, 0.9), i) * 3.0;
     for (int it = 0; it < 500; ++it) {
         for (int i = 0; i < n; ++i) {
@@ -195,13 +200,13 @@ inline bool hp_tables(int p, HpTab* tb) {
             if (std::abs(dp) > 0.0) z[i] -= poly(z[i]) / dp;
         }
     // eigenvectors by inverse iteration at a slightly shifted eigenvalue
-    cplx V[4][4];
+    cplx V[kHpMaxN][kHpMaxN];
     for (int k = 0; k < n; ++k) {
-        cplx v[4];
+        cplx v[kHpMaxN];
         for (int i = 0; i < n; ++i) v[i] = cplx(1.0 + 0.1 * i, 0.05 * i);
         const cplx mu = z[k] * (1.0 + 1e-9) + 1e-12;
         for (int it = 0; it < 3; ++it) {
-            cplx A[4][4], x[4];
+            cplx A[kHpMaxN][kHpMaxN], x[kHpMaxN];
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) A[i][j] = (i == j ? G[i][j] - mu : cplx(G[i][j]));
             if (!csolve(n, A, v, x)) return false;
@@ -213,9 +218,9 @@ inline bool hp_tables(int p, HpTab* tb) {
         for (int i = 0; i < n; ++i) V[i][k] = v[i];
     }
     // V^{-1} column by column
-    cplx W[4][4];
+    cplx W[kHpMaxN][kHpMaxN];
     for (int col = 0; col < n; ++col) {
-        cplx A[4][4], b[4], x[4];
+        cplx A[kHpMaxN][kHpMaxN], b[kHpMaxN], x[kHpMaxN];
         for (int i = 0; i < n; ++i) {
             for (int j = 0; j < n; ++j) A[i][j] = V[i][j];
             b[i] = i == col ? 1.0 : 0.0;

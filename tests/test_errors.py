@@ -44,7 +44,7 @@ def test_context_create_validation():
         ("NaN width", b.sn_mesh(2, 4, 4, 1, 1.0, float("nan"), 1.0), q, True, 1.0, b.SN_ERR_INVALID),
         ("NULL sigma", good_mesh, q, False, 1.0, b.SN_ERR_INVALID),
         ("NaN eta", good_mesh, q, True, float("nan"), b.SN_ERR_INVALID),
-        ("order 4", b.sn_mesh(2, 4, 4, 1, 1.0, 1.0, 1.0, 4), q, True, 1.0, b.SN_ERR_INVALID),
+        ("order 5", b.sn_mesh(2, 4, 4, 1, 1.0, 1.0, 1.0, 5), q, True, 1.0, b.SN_ERR_INVALID),
         ("order -1", b.sn_mesh(2, 4, 4, 1, 1.0, 1.0, 1.0, -1), q, True, 1.0, b.SN_ERR_INVALID),
         ("order 2 in 3D", b.sn_mesh(3, 4, 4, 4, 1.0, 1.0, 1.0, 2), q, True, 1.0, b.SN_ERR_UNSUPPORTED),
     ]

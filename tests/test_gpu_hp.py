@@ -1,11 +1,15 @@
-"""GPU order-p path (Q_p, p = 2, 3, 2D) against the order-p oracle
+"""GPU order-p path (Q_p, p = 2, 3, 4, 2D) against the order-p oracle
 (oracle/hp.py), through the C ABI: sweeps with voids and boundary inflow,
 the moment, the thick DSA correction of each form (SIP, NIP, mNIP) with the
 GMRES and the direct inner solves, source iterations per iterate and
 converged, and the entry points and options that order p >= 2 refuses.
 
-Bars: a sweep 1e-12 (max-norm relative); the DSA correction 1e-10 with GMRES
-to 1e-14, 1e-11 with the exact solve; SI iterates and converged fluxes 1e-10.
+Bars: a sweep 1e-12 (max-norm relative) at p = 2, 3 and 1e-11 at p = 4; the
+DSA correction 1e-10 with GMRES to 1e-14, 1e-11 with the exact solve; SI
+iterates and converged fluxes 1e-10.  The sweep's cell solve goes through the
+eigenbasis V of the 1D upwind operator in both axes, so its rounding scales
+with cond(V)^2: 54, 641 and 8.1e3 at p = 2, 3, 4 (2-norm, unit columns).  The
+p = 4 bar is the p = 3 bar times that ratio (12.6), rounded up to a decade.
 Shapes span several cell diagonals with ragged extents in both axes.
 """
 import math
@@ -23,6 +27,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FORMS = {"sip": (0, hp.SIP), "nip": (1, hp.NIP), "mnip": (2, hp.MNIP)}
+SWEEP_BAR = {2: 1e-12, 3: 1e-12, 4: 1e-11}   # see the module docstring
 
 
 def _problem(nx, ny, order, sn=4, seed=0, voids=True, h=(0.9, 1.15)):
@@ -40,7 +45,7 @@ def _zeros(p):
     return torch.zeros((p.ncells, p.nn), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("shape,sn", [((13, 7), 4), ((31, 23), 8)])
 def test_sweep_and_moment(order, shape, sn):
     from paper_2001_09196_amd import SN_FP64, sn_scalar_flux, sn_sweep
@@ -61,12 +66,12 @@ def test_sweep_and_moment(order, shape, sn):
         # vacuum and no scattering source
         sn_sweep(ctx, None, dev(p.q), None, False, SN_FP64, psi)
         vac = psi.cpu().numpy()
-    assert rel_max(got, ref) <= 1e-12
-    assert rel_max(mom, hp.moment(p, ref)) <= 1e-12
-    assert rel_max(vac, hp.sweep(p, None, p.q)) <= 1e-12
+    assert rel_max(got, ref) <= SWEEP_BAR[order]
+    assert rel_max(mom, hp.moment(p, ref)) <= SWEEP_BAR[order]
+    assert rel_max(vac, hp.sweep(p, None, p.q)) <= SWEEP_BAR[order]
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("form", ["sip", "nip", "mnip"])
 @pytest.mark.parametrize("precond", [0, 2])
 def test_dsa_correction(order, form, precond):
@@ -90,7 +95,7 @@ def test_dsa_correction(order, form, precond):
     assert np.array_equal(got[thin], phi_si[thin])
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("form", ["sip", "nip"])
 def test_source_iteration(order, form):
     from paper_2001_09196_amd import sn_source_iterate
@@ -116,7 +121,7 @@ def test_source_iteration(order, form):
         phi = _zeros(p)
         r = sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=4, use_dsa=False)
         ref = hp.source_iterate(p, tol=0.0, max_it=4, use_dsa=False)
-        assert rel_max(phi.cpu().numpy(), ref["phi"]) <= 1e-12
+        assert rel_max(phi.cpu().numpy(), ref["phi"]) <= SWEEP_BAR[order]
 
 
 def test_order_p_refusals():
@@ -149,7 +154,7 @@ def test_order_p_refusals():
     assert e.value.code == SN_ERR_UNSUPPORTED
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("form,precond", [("sip", 0), ("nip", 0), ("nip", 2), ("mnip", 2)])
 def test_krylov(order, form, precond):
     """Flexible GMRES(8) at order p with the het-DSA of each form, ten
@@ -175,14 +180,16 @@ def test_krylov(order, form, precond):
     assert rc["rc"] == 0 and abs(rc["iters"] - refc["iters"]) <= 1 and ec <= 1e-10
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_hohlraum_stand_in(order):
     """The pseudo-scattering TRT hohlraum stand-in (Sec. 4.2) at order p, S4,
     24 x 12 cells: five GMRES iterations with het-NIP (GMRES inner solve) and
-    with full mNIP (direct inner solve) against the order-p oracle."""
+    with full mNIP (direct inner solve) against the order-p oracle (16 x 8
+    cells at order 4, where the direct solve's band of 24 x 12 cells exceeds
+    its width limit)."""
     from paper_2001_09196_amd import sn_krylov_solve
     import dataclasses
-    base = sninputs.hohlraum(24, 12, sn=4, order=order)
+    base = sninputs.hohlraum(*((16, 8) if order == 4 else (24, 12)), sn=4, order=order)
     for name, eta, diffusion, op, precond in (("het-NIP", 1.0, 1, hp.NIP, 0), ("full mNIP", 0.0, 2, hp.MNIP, 2)):
         p = dataclasses.replace(base, eta=eta)
         say(f"hohlraum order {order} {name}")
@@ -196,12 +203,13 @@ def test_hohlraum_stand_in(order):
         assert r["iters"] == 5 and e <= 1e-9
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 @pytest.mark.parametrize("shape", [(1, 17), (17, 1), (1, 1), (33, 2)])
 def test_degenerate_meshes(order, shape):
     """Meshes one cell wide, a single cell, and a strip two cells high that
     spans several 16-cell tiles: sweep with inflow, and three SI iterations
-    with the direct DSA solve, against the oracle."""
+    with the direct DSA solve (GMRES where its band is too wide), against the
+    oracle."""
     from paper_2001_09196_amd import SN_FP64, sn_source_iterate, sn_sweep
     p = _problem(*shape, order, seed=sum(shape), voids=False)
     p.q[:] = 1.0                               # a source in every cell (thick cells have none otherwise)
@@ -214,10 +222,13 @@ def test_degenerate_meshes(order, shape):
     with context(p) as ctx:
         psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device="cuda")
         sn_sweep(ctx, dev(phi), dev(p.q), dev(inflow), False, SN_FP64, psi)
-        assert rel_max(psi.cpu().numpy(), ref) <= 1e-12
+        assert rel_max(psi.cpu().numpy(), ref) <= SWEEP_BAR[order]
         out = _zeros(p)
+        # (the 33 x 2 strip's band at order 4 is wider than the direct solve
+        # takes: block-Jacobi GMRES to 1e-14 there)
+        wide = order == 4 and shape == (33, 2)
         r = sn_source_iterate(ctx, dev(p.q), None, out, tol=0.0, max_it=3, use_dsa=True, mass_kind=1,
-                              diffusion=1, precond=2)
+                              diffusion=1, precond=0 if wide else 2, cg_rtol=1e-14, cg_maxit=100000)
         assert r["iters"] == ref3["iters"] == 3 and rel_max(out.cpu().numpy(), ref3["phi"]) <= 1e-10
 
 

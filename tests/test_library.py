@@ -52,6 +52,6 @@ def test_inflow_size_host_logic():
     for dim, nx, ny, nz in ((2, 16, 9, 1), (3, 7, 5, 3), (3, 128, 128, 128)):
         m = binding.sn_mesh(dim, nx, ny, nz, 1.0, 1.0, 1.0)
         assert binding.lib().sn_inflow_size(ctypes.byref(m)) == sninputs.inflow_size(dim, nx, ny, nz)
-    for order in (2, 3):                       # order p: (p + 1) values per boundary face
+    for order in (2, 3, 4):                    # order p: (p + 1) values per boundary face
         m = binding.sn_mesh(2, 16, 9, 1, 1.0, 1.0, 1.0, order)
         assert binding.lib().sn_inflow_size(ctypes.byref(m)) == (order + 1) * (16 + 9)
