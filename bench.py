@@ -541,6 +541,9 @@ PAPER_PIPE = {1: {"1": (19, 56, 15), "1e3": (31, 120, 25), "1e8": (34, 123, 25),
               5: {"1": (20, 44, 15), "1e3": (102, 143, 25), "1e8": (134, 147, 25), "sa0": (None, 177, 25)}}
 
 
+# Table crookedpipe1 rows 21-25 (order 4, sigma_a = 0): full NIP, full mNIP, het NIP per problem; context only
+PAPER_PIPE_ORDER4 = {1: (42, 79, 25), 2: (59, 40, 36), 3: (59, 57, 21), 4: (59, 73, 22), 5: ("DNC", 70, 27)}
+
 PIPE_COLUMNS = (
     # name, eta, diffusion form, inner solver, inner tolerance, also source iteration
     ("het_nip", 1.0, 1, 2, 0.0, True),        # the paper's het-DSA NIP column, exact inner solve
@@ -564,7 +567,7 @@ def bench_pipe(log, budget_s=100.0):
     solve stopped at 1e-4 (the paper's inner tolerance), and SIP het (CG) and
     full (exact); source iteration to 1e-8 for het-NIP and het-SIP; and the
     paper's three columns again with order-2 DG (the paper's order), exact
-    inner solves.  Then the
+    inner solves; the order-4 rows (sigma_a = 0) on cells of 1.  Then the
     two-region scan of sigma_pipe (everything else 200, c dt = 1000) with
     het/full NIP and mNIP.  All use the sigma_t mass of Alg. 2.  "DNC": not
     converged in the iteration cap; "n/a": the form is undefined (mNIP next to
@@ -621,6 +624,17 @@ def bench_pipe(log, budget_s=100.0):
                                          ("order2_het_nip", 1.0, 1)):
                 row[name] = run(dataclasses.replace(b2, eta=eta), diffusion, 2, 0.0, False)
             out["problems"][f"#{k} cdt={label}"] = row
+    # rows 21-25 of the paper's table: order 4, sigma_a = 0, exact inner
+    # solves, on cells of 1 (3500 unknowns: the direct solve's limits)
+    out["order4_sa0_cells_of_1"] = {"paper_full_nip_full_mnip_het_nip": PAPER_PIPE_ORDER4}
+    for k in sorted(sninputs.PIPE_PROBLEMS):
+        if time.perf_counter() - t_start > budget_s:
+            out["truncated"] = True
+            break
+        b4 = dataclasses.replace(sninputs.crooked_pipe(k, None, cells_per_unit=1), order=4)
+        out["order4_sa0_cells_of_1"][f"#{k}"] = {
+            name: run(dataclasses.replace(b4, eta=eta), diffusion, 2, 0.0, False)
+            for name, eta, diffusion in (("full_nip", 0.0, 1), ("full_mnip", 0.0, 2), ("het_nip", 1.0, 1))}
     for sp in (0.0, 1e-3, 0.1, 1.0, 5.0, 10.0, 100.0):
         if time.perf_counter() - t_start > budget_s:
             out["truncated"] = True
@@ -633,6 +647,9 @@ def bench_pipe(log, budget_s=100.0):
                                                              "order2_full_mnip", "order2_het_nip"))
                for k, v in out["problems"].items()}
     log(f"crooked pipe (full NIP, full mNIP, het NIP; the same at order 2): {json.dumps(summary)}")
+    o4 = {k: tuple(v[c]["gmres30_to_1e-12"] for c in ("full_nip", "full_mnip", "het_nip"))
+          for k, v in out["order4_sa0_cells_of_1"].items() if k.startswith("#")}
+    log(f"crooked pipe order 4, sigma_a = 0, cells of 1 (full NIP, full mNIP, het NIP): {json.dumps(o4)}")
     return out
 
 
@@ -713,12 +730,13 @@ PAPER_HOHLRAUM = {"S4": [(78900, 52, "DNC", 20, 6, 2.3), (315600, 40, "DNC", 23,
                           (1262400, 29, "DNC", 21, 10, 2.5)]}
 
 
-def bench_hp(log, budget_s=90.0):
-    """Upwind DG of order 2 and 3 (2D).  (1) Sweep grind on the 256^2 S8 mesh
-    of C2 (its cross sections), event-timed over 10 sweeps after 2 warm-up
-    sweeps, beside the psi bytes written.  (2) The pseudo-scattering hohlraum
-    stand-in (Sec. 4.2, sninputs.hohlraum) at order 3, S4/S8/S12, 80x40,
-    160x80 and 320x160 cells (51k, 205k, 819k unknowns): fGMRES(30)
+def bench_hp(log, budget_s=120.0):
+    """Upwind DG of order 2, 3 and 4 (2D).  (1) Sweep grind on the 256^2 S8
+    mesh of C2 (its cross sections), event-timed over 10 sweeps after 2
+    warm-up sweeps, beside the psi bytes written.  (2) The pseudo-scattering
+    hohlraum stand-in (Sec. 4.2, sninputs.hohlraum) at the paper's order 4,
+    S4/S8/S12, 80x40, 160x80 and 320x160 cells (80k, 320k and 1.28M
+    unknowns, against the paper's 79k, 316k and 1.26M): fGMRES(30)
     iterations to 1e-12 with full DSA mNIP (eta = 0) and het-DSA NIP
     (eta = 1), each DSA solved by block-Jacobi GMRES to 1e-4
     with at most 250 iterations (the paper's inner protocol with its AMG
@@ -736,7 +754,7 @@ def bench_hp(log, budget_s=90.0):
     t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
     out = {"sweep_c2_mesh": {}, "hohlraum": {}, "paper_hohlraum_dofs_iters_amg_mnip_then_nip_thick": PAPER_HOHLRAUM}
     base = sninputs.config("c2")
-    for order in (2, 3):
+    for order in (2, 3, 4):
         p = dataclasses.replace(base, order=order)
         with Context(p.dim, p.nx, p.ny, p.nz, p.h, p.omega, p.w, t(p.sigma_t), t(p.sigma_s), eta=p.eta,
                      order=order) as ctx:
@@ -762,6 +780,7 @@ def bench_hp(log, budget_s=90.0):
             flops = 24 * (order + 1) ** 3 * cd
             out["sweep_c2_mesh"][f"order{order}"] = {
                 "ms": ms, "grind_ns_per_cell_dir": ms * 1e6 / cd, "grind_ns_per_node_dir": ms * 1e6 / (cd * p.nn),
+                "transforms": "DPP row moves" if order < 4 else "lane shuffles (ds_bpermute)",
                 "roofline": {"bound": "latency (the wavefront: 31 tile diagonals x 31 cell diagonals)",
                              "hbm_GBps": hbm_bytes / (ms * 1e-3) / 1e9, "hbm_frac": hbm_bytes / (ms * 1e-3) / 8e12,
                              "fp64_TFLOPs": flops / (ms * 1e-3) / 1e12,
@@ -786,13 +805,13 @@ def bench_hp(log, budget_s=90.0):
             if time.perf_counter() - t_start > budget_s:
                 out["truncated"] = True
                 break
-            hb = sninputs.hohlraum(nx, ny, sn=sn, order=3)
+            hb = sninputs.hohlraum(nx, ny, sn=sn, order=4)
             row = {"dofs": hb.ncells * hb.nn, "thick_pct": 100.0 * float((hb.sigma_s >= 1.0).mean())}
             row["full_mnip"] = run(dataclasses.replace(hb, eta=0.0), True)
             row["het_nip"] = run(dataclasses.replace(hb, eta=1.0), True)
             row["no_dsa"] = run(hb, False)
             out["hohlraum"][f"S{sn} {nx}x{ny}"] = row
-            log(f"hohlraum order 3 S{sn} {nx}x{ny}: full mNIP {row['full_mnip']['iters']}, "
+            log(f"hohlraum order 4 S{sn} {nx}x{ny}: full mNIP {row['full_mnip']['iters']}, "
                 f"het NIP {row['het_nip']['iters']}, no DSA {row['no_dsa']['iters']}")
     out["seconds"] = time.perf_counter() - t_start
     return out
