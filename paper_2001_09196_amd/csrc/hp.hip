@@ -298,15 +298,19 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
     }
 }
 
-// The same tile-plane sweep with the transforms done by lane shuffles
-// (ds_bpermute), for p = 4, whose 25 nodes do not fit a 16-lane DPP row.  A
-// cell is solved by a group of (p + 1)^2 lanes, lane g0 + i + (p + 1) j of
-// the wave holding node (i, j) of the frame, two groups per wave; the 14
-// lanes past the second group repeat that group's last lane (same node, same
-// values, same stores).  A transform along x gathers the p + 1 values of the
-// lane's line from lanes g0 + a + (p + 1) j, one along y from lanes
-// g0 + i + (p + 1) b.  The rest (tile planes, LDS faces inside a tile,
-// next-chunk prefetch, uniform global accesses) is as in sweep_hp_kernel.
+// The same tile-plane sweep for p = 4, whose 25 nodes do not fit a 16-lane
+// DPP row.  A cell is solved by a group of (p + 1)^2 lanes, lane
+// g0 + i + (p + 1) j of the wave holding node (i, j) of the frame, two groups
+// per wave; the 14 lanes past the second group repeat that group's last lane
+// (same node, same values, same stores).  A transform along x gathers the
+// p + 1 values of the lane's line from lanes g0 + a + (p + 1) j, one along y
+// from lanes g0 + i + (p + 1) b, through a 64-slot LDS exchange area of the
+// wave: each lane writes its (complex) value once and reads the p + 1 it
+// needs (one 8- or 16-byte read each, against two to four 4-byte lane
+// permutes per value).  The LDS operations of one wave execute in order, so
+// a stage's write comes after every read of the stage before.  The rest
+// (tile planes, LDS faces inside a tile, next-chunk prefetch, uniform global
+// accesses) is as in sweep_hp_kernel.
 template <int P>
 __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, int ny, int ndirs, long nbf, int TS,
                                                             int tdiag, int nTx, int nTy,
@@ -353,10 +357,13 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
     // the tile in frame coordinates
     const int x0 = It * TS, y0 = Jt * TS;
     const int lx = min(TS, nx - x0), ly = min(TS, ny - y0);
-    // LDS faces: x [2][TS + 1][N] (the face left of local position a at a), y [2][TS][N]
+    // LDS faces: x [2][TS + 1][N] (the face left of local position a at a), y [2][TS][N];
+    // then the exchange areas, 64 complex slots per wave
     extern __shared__ double lds[];
     double* xf = lds;
     double* yf = lds + 2 * (TS + 1) * N;
+    typedef double cx2 __attribute__((ext_vector_type(2)));
+    cx2* xch = reinterpret_cast<cx2*>(lds + (2 * (TS + 1) + 2 * TS) * N) + wave * 64;
     const int kend = lx + ly - 2;
     auto first_of = [&](int kk) { return max(0, kk - (ly - 1)); };
     auto last_of = [&](int kk) { return min(kk, lx - 1); };
@@ -384,6 +391,8 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         *py = (b == 0 && jr > 0) ? psi + ((cc + (ry ? nx : -nx)) * ndirs + d) * NN + n_upy
               : (jr == 0 && inflow ? inflow + (long)d * nbf + (long)ny * N + (long)i * N + ip : sigt + cc);
     };
+    // the line slots of this lane: along x (a, j0) and along y (i0, b)
+    const int sx = g0 + N * j0, sy = g0 + i0;
     int k = 0, base = 0;
     int al, bl;  // tile-local frame position
     long c = cell_of(k, base, &al, &bl);
@@ -418,40 +427,52 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         f = fma(cx, upx, f);
         f = fma(cy, upy, f);
         // along x: T(i0, j0) = sum_a W[i0][a] f(a, j0)
+        xch[lane].x = f;
+        __builtin_amdgcn_wave_barrier();
         double tr = 0.0, ti = 0.0;
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            const double fa = __shfl(f, g0 + a + N * j0, 64);
+            const double fa = xch[sx + a].x;
             tr = fma(w1r[a], fa, tr);
             ti = fma(w1i[a], fa, ti);
         }
+        __builtin_amdgcn_wave_barrier();
         // along y: F(i0, j0) = sum_b W[j0][b] T(i0, b)
+        xch[lane] = cx2{tr, ti};
+        __builtin_amdgcn_wave_barrier();
         double fr = 0.0, fi = 0.0;
 #pragma unroll
         for (int b = 0; b < N; ++b) {
-            const double xr = __shfl(tr, g0 + i0 + N * b, 64), xi = __shfl(ti, g0 + i0 + N * b, 64);
-            fr = fma(w2r[b], xr, fma(-w2i[b], xi, fr));
-            fi = fma(w2r[b], xi, fma(w2i[b], xr, fi));
+            const cx2 t = xch[sy + N * b];
+            fr = fma(w2r[b], t.x, fma(-w2i[b], t.y, fr));
+            fi = fma(w2r[b], t.y, fma(w2i[b], t.x, fi));
         }
+        __builtin_amdgcn_wave_barrier();
         // U = F / (a_x lambda_i0 + a_y lambda_j0 + sigma_t)
         const double zr = zr0 + st, zi = zi0;
         const double inv = 1.0 / (zr * zr + zi * zi);
         const double ur = (fr * zr + fi * zi) * inv, ui = (fi * zr - fr * zi) * inv;
         // back along x: T2(i0, j0) = sum_k V[i0][k] U(k, j0)
+        xch[lane] = cx2{ur, ui};
+        __builtin_amdgcn_wave_barrier();
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int kk = 0; kk < N; ++kk) {
-            const double xr = __shfl(ur, g0 + kk + N * j0, 64), xi = __shfl(ui, g0 + kk + N * j0, 64);
-            sr = fma(v1r[kk], xr, fma(-v1i[kk], xi, sr));
-            si = fma(v1r[kk], xi, fma(v1i[kk], xr, si));
+            const cx2 t = xch[sx + kk];
+            sr = fma(v1r[kk], t.x, fma(-v1i[kk], t.y, sr));
+            si = fma(v1r[kk], t.y, fma(v1i[kk], t.x, si));
         }
+        __builtin_amdgcn_wave_barrier();
         // back along y: u(i0, j0) = Re sum_l V[j0][l] T2(i0, l)
+        xch[lane] = cx2{sr, si};
+        __builtin_amdgcn_wave_barrier();
         double u = 0.0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            const double xr = __shfl(sr, g0 + i0 + N * l, 64), xi = __shfl(si, g0 + i0 + N * l, 64);
-            u = fma(v2r[l], xr, fma(-v2i[l], xi, u));
+            const cx2 t = xch[sy + N * l];
+            u = fma(v2r[l], t.x, fma(-v2i[l], t.y, u));
         }
+        __builtin_amdgcn_wave_barrier();
         psi[(c * ndirs + d) * NN + n_self] = u;
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
         if (j0 == P) yf[(nxt * TS + al) * N + i0] = u;
@@ -737,7 +758,9 @@ hipError_t launch_sweep_hp(const HpTab& tb, int nx, int ny, int ndirs, long nbf,
     // cell groups per wave: 16-lane DPP groups at p = 2, 3; two 25-lane groups at p = 4
     const int gpw = tb.p == 4 ? 64 / (n1 * n1) : 4;
     const int waves = std::max(1, std::min(8, (std::min(TS, std::min(nx, ny)) + gpw - 1) / gpw));
-    const size_t lds = (size_t)(2 * (TS + 1) + 2 * TS) * n1 * sizeof(double);
+    // faces; at p = 4 also the waves' exchange areas (64 complex slots each)
+    const size_t lds = (size_t)(2 * (TS + 1) + 2 * TS) * n1 * sizeof(double) +
+                       (tb.p == 4 ? (size_t)waves * 64 * 2 * sizeof(double) : 0);
     for (int t = 0; t <= nTx + nTy - 2; ++t) {
         const int ntiles = std::min(t, nTx - 1) - std::max(0, t - (nTy - 1)) + 1;
         const dim3 grid((unsigned)(ntiles * ndirs));
