@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--config", default="c5", help="workload of --sweeps-only (c1..c5)")
     ap.add_argument("--pipe-only", action="store_true", help="only the crooked-pipe scan")
     ap.add_argument("--hp-only", action="store_true", help="only the order-p leg (sweep grind, hohlraum)")
+    ap.add_argument("--hp-budget", type=float, default=120.0,
+                    help="seconds for the hohlraum part of the order-p leg (0: the sweep grind only)")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32"), help="sweep precision of --sweeps-only")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -299,7 +301,7 @@ def main():
               flush=True)
         return
     if args.hp_only:
-        print(json.dumps(bench_hp(log)), flush=True)
+        print(json.dumps(bench_hp(log, budget_s=args.hp_budget)), flush=True)
         return
 
     if args.sweeps_only:
