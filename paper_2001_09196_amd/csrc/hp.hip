@@ -308,9 +308,11 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
 // wave: each lane writes its (complex) value once and reads the p + 1 it
 // needs (one 8- or 16-byte read each, against two to four 4-byte lane
 // permutes per value).  The LDS operations of one wave execute in order, so
-// a stage's write comes after every read of the stage before.  The rest
-// (tile planes, LDS faces inside a tile, next-chunk prefetch, uniform global
-// accesses) is as in sweep_hp_kernel.
+// a stage's write comes after every read of the stage before.  Cell data is
+// loaded two chunks ahead (one at p = 2, 3: measured on the 256^2 S8 mesh,
+// two ahead gives 2.70 -> 2.51 ms at p = 4 but 1.17 -> 1.22 ms at p = 3).
+// The rest (tile planes, LDS faces inside a tile, uniform global accesses)
+// is as in sweep_hp_kernel.
 template <int P>
 __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, int ny, int ndirs, long nbf, int TS,
                                                             int tdiag, int nTx, int nTy,
@@ -393,30 +395,48 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
     };
     // the line slots of this lane: along x (a, j0) and along y (i0, b)
     const int sx = g0 + N * j0, sy = g0 + i0;
-    int k = 0, base = 0;
-    int al, bl;  // tile-local frame position
-    long c = cell_of(k, base, &al, &bl);
-    double st = sigt[c], ss = sigs[c], qq = qs * qp[c], ph = phs * php[c * phm + pho];
-    double gx, gy;
-    {
+    // A chunk: its diagonal k, first position, this lane's cell and the data
+    // loaded for it.  Chunks are loaded two ahead of the one being solved
+    // (cell data is read-only here and the upwind psi comes from earlier
+    // launches), so a load has two steps to arrive.  Past the last diagonal a
+    // chunk keeps the previous cell and loads it again.
+    struct Chunk {
+        int k, base, al, bl;
+        long c;
+        double st, ss, qq, ph, gx, gy;
+    };
+    auto load = [&](Chunk& h) {
+        h.st = sigt[h.c];
+        h.ss = sigs[h.c];
+        h.qq = qs * qp[h.c];
+        h.ph = phs * php[h.c * phm + pho];
         const double *px, *py;
-        face_ptrs(c, al, bl, &px, &py);
-        gx = *px;
-        gy = *py;
-    }
-    while (k <= kend) {
-        // the next chunk, and its cell data loaded ahead
-        int k2 = k, b2 = base + ngroups;
-        if (b2 > last_of(k)) {
-            k2 = k + 1;
-            b2 = first_of(k2);
+        face_ptrs(h.c, h.al, h.bl, &px, &py);
+        h.gx = *px;
+        h.gy = *py;
+    };
+    auto advance = [&](const Chunk& h) {
+        Chunk n = h;
+        n.base = h.base + ngroups;
+        if (n.base > last_of(h.k)) {
+            n.k = h.k + 1;
+            n.base = first_of(n.k);
         }
-        int al2 = al, bl2 = bl;
-        const long c2 = k2 <= kend ? cell_of(k2, b2, &al2, &bl2) : c;
-        const double *px2, *py2;
-        face_ptrs(c2, al2, bl2, &px2, &py2);
-        const double st2 = sigt[c2], ss2 = sigs[c2], q2 = qs * qp[c2], ph2 = phs * php[c2 * phm + pho];
-        const double gx2 = *px2, gy2 = *py2;
+        if (n.k <= kend) n.c = cell_of(n.k, n.base, &n.al, &n.bl);
+        load(n);
+        return n;
+    };
+    Chunk C0;
+    C0.k = 0;
+    C0.base = 0;
+    C0.c = cell_of(0, 0, &C0.al, &C0.bl);
+    load(C0);
+    Chunk C1 = advance(C0);
+    while (C0.k <= kend) {
+        const Chunk C2 = advance(C1);
+        const int k = C0.k, al = C0.al, bl = C0.bl;
+        const long c = C0.c;
+        const double st = C0.st, ss = C0.ss, qq = C0.qq, ph = C0.ph, gx = C0.gx, gy = C0.gy;
         const int ir = x0 + al, jr = y0 + bl;
         const int cur = k & 1, nxt = cur ^ 1;
         double f = (ss * ph + qq) * kInv4Pi;
@@ -476,18 +496,9 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         psi[(c * ndirs + d) * NN + n_self] = u;
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
         if (j0 == P) yf[(nxt * TS + al) * N + i0] = u;
-        if (k2 != k) lds_barrier();
-        k = k2;
-        base = b2;
-        al = al2;
-        bl = bl2;
-        c = c2;
-        st = st2;
-        ss = ss2;
-        qq = q2;
-        ph = ph2;
-        gx = gx2;
-        gy = gy2;
+        if (C1.k != k) lds_barrier();
+        C0 = C1;
+        C1 = C2;
     }
 }
 
