@@ -247,3 +247,55 @@ def test_no_thick_cells():
         phi = _zeros(p)
         sn_source_iterate(ctx, dev(p.q), None, phi, tol=0.0, max_it=4, use_dsa=True, diffusion=1)
         assert rel_max(phi.cpu().numpy(), ref["phi"]) <= 1e-12
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_full_size_sweep(order):
+    """The order-p sweep in the benchmarked configuration (the C2 mesh: 256^2,
+    S8, its cross sections with voids and thick tiles, random phi, vacuum).
+    The GPU psi of two sampled directions in opposite quadrants against the
+    oracle's sweep of those directions over the whole mesh (a direction's
+    sweep depends only on phi and q), and particle balance for every
+    direction: absorption + outflow = source (the weak form with v = 1 summed
+    over the cells, exact at any size).  The sampled directions are held to
+    the FP64 parity bar of 1e-10 relative: the tighter small-mesh bars above
+    do not carry over, since the cell solves' rounding accumulates along the
+    upwind path, 512 cells here against about 50 on the small meshes (order 4
+    measured 1.8e-11)."""
+    import dataclasses
+    from paper_2001_09196_amd import SN_FP64, sn_sweep
+    p = dataclasses.replace(sninputs.config("c2"), order=order)
+    rng = np.random.default_rng(17)
+    phi = rng.uniform(0, 1, (p.ncells, p.nn))
+    say(f"hp full size order {order}")
+    with context(p) as ctx:
+        psi = torch.empty((p.ncells, p.ndirs, p.nn), dtype=torch.float64, device="cuda")
+        sn_sweep(ctx, dev(phi), dev(p.q), None, False, SN_FP64, psi)
+        got = psi.cpu().numpy()
+        del psi
+    sg = np.sign(p.omega[:, :2])
+    d1 = int(np.flatnonzero((sg[:, 0] != sg[0, 0]) & (sg[:, 1] != sg[0, 1]))[0])
+    for d in (0, d1):
+        ps = dataclasses.replace(p, omega=p.omega[[d]], w=p.w[[d]])
+        ref = hp.sweep(ps, phi, p.q)[:, 0]
+        e = rel_max(got[:, d], ref)
+        say(f"  direction {d}: {e:.1e}")
+        assert e <= 1e-10, d
+    n = order + 1
+    w1 = hp.ref1d(order).M.sum(axis=0)                   # int of each 1D basis function over [0, 1]
+    hx, hy = p.h[0], p.h[1]
+    wq = np.outer(w1, w1)                                 # [jl, il]
+    src = hp.source(p, phi, p.q).reshape(p.ny, p.nx, n, n)
+    S = hx * hy * float(np.sum(src * wq))
+    st = p.sigma_t.reshape(p.ny, p.nx, 1, 1)
+    worst = 0.0
+    for d in range(p.ndirs):
+        u = got[:, d, :].reshape(p.ny, p.nx, n, n)       # [j, i, jl, il]
+        ab = hx * hy * float(np.sum(st * u * wq))
+        om = p.omega[d]
+        fx = u[:, -1, :, -1] if om[0] > 0 else u[:, 0, :, 0]     # the outflow x face: [j, jl]
+        fy = u[-1, :, -1, :] if om[1] > 0 else u[0, :, 0, :]     # the outflow y face: [i, il]
+        out = abs(om[0]) * hy * float(np.sum(fx * w1)) + abs(om[1]) * hx * float(np.sum(fy * w1))
+        worst = max(worst, abs(ab + out - S) / S)
+    say(f"  balance {worst:.1e}")
+    assert worst <= 1e-11
