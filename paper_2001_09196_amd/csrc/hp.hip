@@ -21,6 +21,7 @@
 #include <cstdlib>
 
 #include "../../include/sn.h"
+#include "sn_device.hpp"
 #include "sn_kernels.hpp"
 #include "hp.hpp"
 
@@ -45,12 +46,15 @@ __device__ __forceinline__ void lds_barrier() {
 
 // A double moved across lanes by DPP (two 32-bit moves): quad_perm CTRL
 // 0x55 a broadcasts lane a of every quad, row_ror CTRL 0x120 + n gives lane l
-// of a 16-lane row the value of lane (l - n) mod 16 of that row.
+// of a 16-lane row the value of lane (l - n) mod 16 of that row.  Every
+// source lane of these patterns exists, so bound_ctrl (zero for a missing
+// source) never applies; set, it spares the move that would otherwise
+// initialise each destination with the old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <int A>
@@ -204,30 +208,41 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
         *py = (b == 0 && jr > 0) ? psi + ((cc + (ry ? nx : -nx)) * ndirs + d) * NN + n_upy
               : (jr == 0 && inflow ? inflow + (long)d * nbf + (long)ny * N + (long)i * N + ip : sigt + cc);
     };
-    int k = 0, base = 0;
-    int al, bl;  // tile-local frame position
-    long c = cell_of(k, base, &al, &bl);
-    double st = sigt[c], ss = sigs[c], qq = qs * qp[c], ph = phs * php[c * phm + pho];
-    double gx, gy;
-    {
-        const double *px, *py;
-        face_ptrs(c, al, bl, &px, &py);
-        gx = *px;
-        gy = *py;
-    }
-    while (k <= kend) {
-        // the next chunk, and its cell data loaded ahead
-        int k2 = k, b2 = base + ngroups;
-        if (b2 > last_of(k)) {
-            k2 = k + 1;
-            b2 = first_of(k2);
+    // A chunk: its diagonal k, first position, this lane's cell and the data
+    // loaded for it, one chunk ahead of the one being solved.  Two chunk
+    // slots alternate (the loop runs two steps per turn), so the loaded data
+    // is used where it was loaded instead of being copied each step.  Past
+    // the last diagonal a chunk keeps the previous cell and loads it again.
+    struct Chunk {
+        int k, base, al, bl;
+        long c;
+        double st, ss, qq, ph, gx, gy;
+    };
+    auto advance = [&](const Chunk& h, Chunk& n) {
+        n.k = h.k;
+        n.base = h.base + ngroups;
+        if (n.base > last_of(h.k)) {
+            n.k = h.k + 1;
+            n.base = first_of(n.k);
         }
-        int al2 = al, bl2 = bl;
-        const long c2 = k2 <= kend ? cell_of(k2, b2, &al2, &bl2) : c;
-        const double *px2, *py2;
-        face_ptrs(c2, al2, bl2, &px2, &py2);
-        const double st2 = sigt[c2], ss2 = sigs[c2], q2 = qs * qp[c2], ph2 = phs * php[c2 * phm + pho];
-        const double gx2 = *px2, gy2 = *py2;
+        n.al = h.al;
+        n.bl = h.bl;
+        n.c = n.k <= kend ? cell_of(n.k, n.base, &n.al, &n.bl) : h.c;
+        n.st = sigt[n.c];
+        n.ss = sigs[n.c];
+        n.qq = qs * qp[n.c];
+        n.ph = phs * php[n.c * phm + pho];
+        const double *px, *py;
+        face_ptrs(n.c, n.al, n.bl, &px, &py);
+        n.gx = *px;
+        n.gy = *py;
+    };
+    // solve chunk C (its data loaded), store, and pass the faces on; Cn is the
+    // chunk after it (a barrier when the diagonal changes)
+    auto solve = [&](const Chunk& C, const Chunk& Cn) {
+        const int k = C.k, al = C.al, bl = C.bl;
+        const long c = C.c;
+        const double st = C.st, ss = C.ss, qq = C.qq, ph = C.ph, gx = C.gx, gy = C.gy;
         const int ir = x0 + al, jr = y0 + bl;
         const int cur = k & 1, nxt = cur ^ 1;
         double f = pad ? 0.0 : (ss * ph + qq) * kInv4Pi;
@@ -255,7 +270,7 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
         }
         // U = F / (a_x lambda_i0 + a_y lambda_j0 + sigma_t)
         const double zr = zr0 + st, zi = zi0;
-        const double inv = 1.0 / (zr * zr + zi * zi);
+        const double inv = rcp(zr * zr + zi * zi);
         const double ur = (fr * zr + fi * zi) * inv, ui = (fi * zr - fr * zi) * inv;
         // back along x: T2(i, j) = sum_k V[i][k] U(k, j)
         const double uq[4] = {quad_bcast<0>(ur), quad_bcast<1>(ur), quad_bcast<2>(ur), quad_bcast<3>(ur)};
@@ -283,18 +298,29 @@ __global__ void __launch_bounds__(512) sweep_hp_kernel(HpTab tb, int nx, int ny,
         psi[(c * ndirs + d) * NN + n_self] = u;
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
         if (j0 == P) yf[(nxt * TS + al) * N + i0] = u;
-        if (k2 != k) lds_barrier();
-        k = k2;
-        base = b2;
-        al = al2;
-        bl = bl2;
-        c = c2;
-        st = st2;
-        ss = ss2;
-        qq = q2;
-        ph = ph2;
-        gx = gx2;
-        gy = gy2;
+        if (Cn.k != k) lds_barrier();
+    };
+    Chunk A, B;
+    A.k = 0;
+    A.base = 0;
+    A.c = cell_of(0, 0, &A.al, &A.bl);
+    {
+        A.st = sigt[A.c];
+        A.ss = sigs[A.c];
+        A.qq = qs * qp[A.c];
+        A.ph = phs * php[A.c * phm + pho];
+        const double *px, *py;
+        face_ptrs(A.c, A.al, A.bl, &px, &py);
+        A.gx = *px;
+        A.gy = *py;
+    }
+    for (;;) {
+        advance(A, B);
+        solve(A, B);
+        if (B.k > kend) break;
+        advance(B, A);
+        solve(B, A);
+        if (A.k > kend) break;
     }
 }
 
