@@ -424,8 +424,10 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
     // A chunk: its diagonal k, first position, this lane's cell and the data
     // loaded for it.  Chunks are loaded two ahead of the one being solved
     // (cell data is read-only here and the upwind psi comes from earlier
-    // launches), so a load has two steps to arrive.  Past the last diagonal a
-    // chunk keeps the previous cell and loads it again.
+    // launches), so a load has two steps to arrive.  Three chunk slots rotate
+    // over a three-step loop, so the loaded data is used where it was loaded.
+    // Past the last diagonal a chunk keeps the previous cell and loads it
+    // again.
     struct Chunk {
         int k, base, al, bl;
         long c;
@@ -441,25 +443,21 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         h.gx = *px;
         h.gy = *py;
     };
-    auto advance = [&](const Chunk& h) {
-        Chunk n = h;
+    auto advance = [&](const Chunk& h, Chunk& n) {
+        n.k = h.k;
         n.base = h.base + ngroups;
         if (n.base > last_of(h.k)) {
             n.k = h.k + 1;
             n.base = first_of(n.k);
         }
-        if (n.k <= kend) n.c = cell_of(n.k, n.base, &n.al, &n.bl);
+        n.al = h.al;
+        n.bl = h.bl;
+        n.c = n.k <= kend ? cell_of(n.k, n.base, &n.al, &n.bl) : h.c;
         load(n);
-        return n;
     };
-    Chunk C0;
-    C0.k = 0;
-    C0.base = 0;
-    C0.c = cell_of(0, 0, &C0.al, &C0.bl);
-    load(C0);
-    Chunk C1 = advance(C0);
-    while (C0.k <= kend) {
-        const Chunk C2 = advance(C1);
+    // solve chunk C0 (its data loaded), store, and pass the faces on; C1 is the
+    // chunk after it (a barrier when the diagonal changes)
+    auto solve = [&](const Chunk& C0, const Chunk& C1) {
         const int k = C0.k, al = C0.al, bl = C0.bl;
         const long c = C0.c;
         const double st = C0.st, ss = C0.ss, qq = C0.qq, ph = C0.ph, gx = C0.gx, gy = C0.gy;
@@ -496,7 +494,7 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         __builtin_amdgcn_wave_barrier();
         // U = F / (a_x lambda_i0 + a_y lambda_j0 + sigma_t)
         const double zr = zr0 + st, zi = zi0;
-        const double inv = 1.0 / (zr * zr + zi * zi);
+        const double inv = rcp(zr * zr + zi * zi);
         const double ur = (fr * zr + fi * zi) * inv, ui = (fi * zr - fr * zi) * inv;
         // back along x: T2(i0, j0) = sum_k V[i0][k] U(k, j0)
         xch[lane] = cx2{ur, ui};
@@ -523,8 +521,23 @@ __global__ void __launch_bounds__(512) sweep_hp_shfl_kernel(HpTab tb, int nx, in
         if (i0 == P) xf[(nxt * (TS + 1) + al + 1) * N + j0] = u;
         if (j0 == P) yf[(nxt * TS + al) * N + i0] = u;
         if (C1.k != k) lds_barrier();
-        C0 = C1;
-        C1 = C2;
+    };
+    Chunk A, B, C;
+    A.k = 0;
+    A.base = 0;
+    A.c = cell_of(0, 0, &A.al, &A.bl);
+    load(A);
+    advance(A, B);
+    for (;;) {
+        advance(B, C);
+        solve(A, B);
+        if (B.k > kend) break;
+        advance(C, A);
+        solve(B, C);
+        if (C.k > kend) break;
+        advance(A, B);
+        solve(C, A);
+        if (A.k > kend) break;
     }
 }
 
