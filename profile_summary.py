@@ -70,11 +70,21 @@ def _per_dispatch(d, counter, kernel, per_call=0):
     return v[len(v) // 2], len(v)   # median over dispatches, KiB
 
 
-def kernel_source_sha() -> str:
+SWEEP_SOURCES = ("csrc/sweep.hip", "csrc/sn_device.hpp", "csrc/sn_kernels.hpp", "build.py")
+HP_SOURCES = ("csrc/hp.hip", "csrc/hp.hpp", "csrc/sn_device.hpp", "csrc/sn_kernels.hpp", "build.py")
+
+
+def sources_of(kernel: str):
+    """The files that decide a kernel's code: the order-p kernels' (hp.hip)
+    or the Q1 sweep kernels' (sweep.hip), with the headers and build flags."""
+    return HP_SOURCES if "_hp" in kernel else SWEEP_SOURCES
+
+
+def kernel_source_sha(files=SWEEP_SOURCES) -> str:
     """sha256 over the files that decide the sweep kernels' code: their
     source, the device header, the launch header and the build flags."""
     h = hashlib.sha256()
-    for rel in ("csrc/sweep.hip", "csrc/sn_device.hpp", "csrc/sn_kernels.hpp", "build.py"):
+    for rel in files:
         h.update(open(os.path.join(HERE, rel), "rb").read())
     return h.hexdigest()
 
@@ -124,8 +134,10 @@ def spans(d, kernel, per_call, out):
 
 
 def counters(kernel, out, dirs, command):
+    files = sources_of(kernel)
+    names = ", ".join(os.path.basename(f) for f in files)
     lines = [f"# rocprofv3 counters of {kernel}, averaged per dispatch", f"# commands: {command}",
-             f"# kernel source sha256 {kernel_source_sha()} (sweep.hip, sn_device.hpp, sn_kernels.hpp, build.py)", ""]
+             f"# kernel source sha256 {kernel_source_sha(files)} ({names})", ""]
     for d in dirs.split(","):
         vals, disp = {}, {}
         for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
