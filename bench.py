@@ -783,7 +783,9 @@ def bench_hp(log, budget_s=120.0):
             out["sweep_c2_mesh"][f"order{order}"] = {
                 "ms": ms, "grind_ns_per_cell_dir": ms * 1e6 / cd, "grind_ns_per_node_dir": ms * 1e6 / (cd * p.nn),
                 "transforms": "DPP row moves" if order < 4 else "lane shuffles (ds_bpermute)",
-                "roofline": {"bound": "latency (the wavefront: 31 tile diagonals x 31 cell diagonals)",
+                "roofline": {"bound": ("VALU issue at one or two waves per SIMD" if order < 4 else
+                                       "dependencies on the LDS line exchanges") +
+                                      " along the wavefront (31 tile diagonals x 31 cell diagonals)",
                              "hbm_GBps": hbm_bytes / (ms * 1e-3) / 1e9, "hbm_frac": hbm_bytes / (ms * 1e-3) / 8e12,
                              "fp64_TFLOPs": flops / (ms * 1e-3) / 1e12,
                              "fp64_frac": flops / (ms * 1e-3) / (FP64_VECTOR_PEAK_TFLOPS * 1e12),
