@@ -1047,7 +1047,13 @@ int do_dsa(sn_context* ctx, const double* phi_old, const double* phi_si, double*
     auto update = [&](int it) -> int {
         HIPCHK(launch_cg_update(g, ctx->binv.p, ctx->cx.p, ctx->cr.p, ctx->cz.p, ctx->cp.p, ctx->cp1.p, ctx->cq.p,
                                 ctx->parta.p, ctx->partb.p, ctx->nparts, ctx->scal.p, &hs, it, bj, ctx->stream));
-        if (!bj) return vcycle();
+        if (!bj) {
+            // the next iteration's stop test before its V-cycle, which is then
+            // skipped when the solve has converged
+            HIPCHK(launch_cg_test(ctx->partb.p, ctx->nparts, ctx->scal.p, &hs, o->cg_rtol, o->cg_maxit, it + 1,
+                                  ctx->stream));
+            return vcycle();
+        }
         return 0;
     };
     // The stop fields of the pinned copy are cleared here, before the solve

@@ -1320,6 +1320,40 @@ hipError_t launch_cg_apply(const DsaGeom& g, const int* thick_cell, const int* n
     return hipGetLastError();
 }
 
+// The stop test of iteration it, ahead of the multigrid V-cycle that would
+// give its z: the same test, on the same partials reduced in the same order,
+// as the apply kernel of iteration it makes first (so the decision is the
+// same), but before the V-cycle, whose kernels and that apply then return at
+// once when it passes.  it >= 1, so ||b||^2 is already in s.
+__global__ void __launch_bounds__(256) cg_test_kernel(const double* __restrict__ part_rr, int nparts, CgScalars* s,
+                                                      CgScalars* s_host, double rtol, int maxit, int it) {
+    if (s->done) return;
+    __shared__ double sh[16];
+    const double rr = reduce_parts(part_rr, nparts, sh);
+    const double bb = s->bb;
+    if (sqrt(rr) <= rtol * sqrt(bb) || it >= maxit || bb == 0.0) {
+        if (threadIdx.x == 0) {
+            s->rr = rr;
+            s->iters = it;
+            s->done = 1;
+            if (s_host) {
+                s_host->bb = bb;
+                s_host->rr = rr;
+                s_host->iters = it;
+                __threadfence_system();  // the fields reach the host before the flag
+                s_host->done = 1;
+            }
+        }
+    }
+}
+
+hipError_t launch_cg_test(const double* part_b, int nparts, CgScalars* s, CgScalars* s_host, double rtol,
+                          int maxit, int it, hipStream_t st) {
+    hipLaunchKernelGGL(cg_test_kernel, dim3(1), dim3(256), 0, st, part_b + nparts, nparts, s, s_host, rtol, maxit,
+                       it);
+    return hipGetLastError();
+}
+
 // update kernel of iteration it (< maxit)
 hipError_t launch_cg_update(const DsaGeom& g, const double* binv, double* x, double* r, double* z, double* p0,
                             double* p1, const double* q, double* part_a, double* part_b, int nparts, CgScalars* s,

@@ -259,6 +259,10 @@ hipError_t launch_cg_apply(const DsaGeom& g, const int* thick_cell, const int* n
 hipError_t launch_cg_update(const DsaGeom& g, const double* binv, double* x, double* r, double* z, double* p0,
                             double* p1, const double* q, double* part_a, double* part_b, int nparts, CgScalars* s,
                             CgScalars* s_host, int it, int bj, hipStream_t st);
+// the stop test of iteration it (>= 1) on the ||r||^2 partials of part_b
+// (from the update of iteration it - 1), made ahead of the multigrid V-cycle
+hipError_t launch_cg_test(const double* part_b, int nparts, CgScalars* s, CgScalars* s_host, double rtol,
+                          int maxit, int it, hipStream_t st);
 
 hipError_t launch_dsa_scatter(long nc, int nn, const int* slot_of_cell, const double* phi_si, const double* x,
                               double* phi_out, hipStream_t st);
