@@ -277,6 +277,8 @@ def main():
                     help="only run N sweeps of --config in --prec (for rocprofv3 counter passes)")
     ap.add_argument("--config", default="c5", help="workload of --sweeps-only (c1..c5)")
     ap.add_argument("--pipe-only", action="store_true", help="only the crooked-pipe scan")
+    ap.add_argument("--pipe-refined-cells", type=int, default=0, metavar="C",
+                    help="only the refined crooked-pipe leg, on cells of 1/C (32: 1.29M DOFs, the paper's size)")
     ap.add_argument("--hp-only", action="store_true", help="only the order-p leg (sweep grind, hohlraum)")
     ap.add_argument("--hp-budget", type=float, default=120.0,
                     help="seconds for the hohlraum part of the order-p leg (0: the sweep grind only)")
@@ -299,6 +301,9 @@ def main():
     if args.pipe_only:
         print(json.dumps({"crooked_pipe": bench_pipe(log), "crooked_pipe_refined": bench_pipe_refined(log)}),
               flush=True)
+        return
+    if args.pipe_refined_cells:
+        print(json.dumps(bench_pipe_refined(log, budget_s=600.0, cells_per_unit=args.pipe_refined_cells)), flush=True)
         return
     if args.hp_only:
         print(json.dumps(bench_hp(log, budget_s=args.hp_budget)), flush=True)
@@ -671,8 +676,9 @@ PAPER_PIPE2 = {1: {"1": (35, "DNC", 39, 14, 15, 7), "1e3": ("DNC", "DNC", 73, 99
 
 def bench_pipe_refined(log, budget_s=100.0, cells_per_unit=16):
     """The crooked-pipe stand-in on a refined mesh with inexact DSA solves
-    (the protocol of Table crookedpipe2): order-2 DG, S8, 224x160 cells of
-    1/16 (322,560 DOFs, a quarter of the paper's), problems #1-#5 at
+    (the protocol of Table crookedpipe2): order-2 DG, S8, by default 224x160
+    cells of 1/16 (322,560 DOFs, a quarter of the paper's; cells_per_unit =
+    32 gives 448x320 cells, 1.29M DOFs), problems #1-#5 at
     c dt = 1, 1e3, 1e8; fGMRES(30) to 1e-12 (at most 500 iterations) with
     full NIP, full mNIP and het NIP, each DSA solved by block-Jacobi GMRES(30)
     to 1e-4 with at most 250 iterations (the paper's AMG replaced); the mean
@@ -715,6 +721,8 @@ def bench_pipe_refined(log, budget_s=100.0, cells_per_unit=16):
             for name, eta, diffusion in (("full_nip", 0.0, 1), ("full_mnip", 0.0, 2), ("het_nip", 1.0, 1)):
                 row[name] = run(dataclasses.replace(b, eta=eta), diffusion)
             out["problems"][f"#{k} cdt={label}"] = row
+            log(f"  refined pipe #{k} cdt={label}: " +
+                ", ".join(f"{c} {row[c]['iters']}" for c in ("full_nip", "full_mnip", "het_nip")))
     out["seconds"] = time.perf_counter() - t_start
     summary = {k: tuple((v[c]["iters"], round(v[c].get("inner_iters_per_dsa", 0.0))) for c in
                         ("full_nip", "full_mnip", "het_nip")) for k, v in out["problems"].items()}
