@@ -807,7 +807,15 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     // The source, sigma_t and the y/z face inflow of the next cell are loaded
     // one step ahead.  The face values of this tile were written by earlier
     // launches (the upwind tiles) and no tile of this launch writes them, so
-    // they can be read at any time.
+    // they can be read at any time.  Every lane loads its face pieces, not
+    // only the lanes on the tile's near sides that use them: yin0 does not
+    // depend on jy nor zin0 on kz, so the other lanes read the same addresses
+    // (no extra traffic), and slot kz + irc (or jy + irc) <= TX + 2 lies in
+    // the tile's TX + 3 slots of its group, which the face buffer holds for
+    // every group slot.  With the loads outside per-lane branches the
+    // compiler counts them exactly instead of draining every access before
+    // each use (C5 fused sweep: FP64 9.32 -> 8.38 ms, FP32 6.03 -> 5.57 ms,
+    // bit-identical).
     auto fetch = [&](int ir, In3<T>& v) {
         const int irc = min(max(ir, 0), len - 1);
         if constexpr (!staged_tile<T>()) {
@@ -819,14 +827,8 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
             for (int n = 0; n < 8; ++n) v.s.v[n] = sp[n];
             v.sig = tsig[irc * 16];
         }
-        if (pen && jy == 0)
-            v.y = load4(yin0 + irc * YZ_SLOT);
-        else
-            v.y = Vec4<T>{};
-        if (pen && kz == 0)
-            v.z = load4(zin0 + irc * YZ_SLOT);
-        else
-            v.z = Vec4<T>{};
+        v.y = load4(yin0 + irc * YZ_SLOT);
+        v.z = load4(zin0 + irc * YZ_SLOT);
     };
     // face outflow of the tile's top pencils (position il = i0 + s - skew at
     // step s) and of the last cell of each pencil
