@@ -757,6 +757,32 @@ constexpr int stage_elems() {
 // barrier, the workgroup adds the waves' sums in wave order and stores the
 // octant's share of phi for those cells (each cell is visited once per
 // octant, so plain stores suffice and the result does not depend on timing).
+// Face stores of the branching body: raw buffer stores from the wave's face
+// slot base, every lane every step; a lane with nothing to store gets offset
+// 0x80000000, outside the resource's range, and the hardware drops its store.
+// With no store inside a per-lane branch the compiler counts the step's
+// memory operations exactly.  The base must be the same for the whole wave
+// (it is read from the first lane).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t face_rsrc(const T* base) {
+    const unsigned long long a = (unsigned long long)base;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((unsigned long long)hi << 32) | lo), 0, 0x7fffffff,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ void face_store4(__amdgpu_buffer_rsrc_t r, unsigned off, T a0, T a1, T a2, T a3) {
+    if constexpr (sizeof(T) == 8) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b128(d2{a0, a1}, r, (int)off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(d2{a2, a3}, r, (int)(off + 16u), 0, 0);
+    } else {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(f4{a0, a1, a2, a3}, r, (int)off, 0, 0);
+    }
+}
+
 template <typename T, int M, bool FUSED = false>
 __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, int d, bool dok, T ax, T ay, T az,
                                              int I, int J, int K, int TX, int nTx, int nTy, int nTz,
@@ -838,8 +864,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
     // outflow at step s into slot s - 3 of the downstream tiles (J + 1: nTz
     // tiles on, K + 1: the next tile); the pointers are formed at step 0 and
     // used from step 3 on
-    T* yout0 = yzt + ((long)nTz * (TX + 3) - 3) * YZ_SLOT + (kd * 4 + kz) * 4;
-    T* zout0 = yzt + ((long)(TX + 3) - 3) * YZ_SLOT + YZ_SLOT / 2 + (kd * 4 + jy) * 4;
+    // (byte offsets from yzt, at most 1023 tiles x 35 slots x 1 KiB: below 2^31)
+    const __amdgpu_buffer_rsrc_t rfz = face_rsrc<T>(yzt);
+    const unsigned yob = (unsigned)((((long)nTz * (TX + 3) - 3) * YZ_SLOT + (kd * 4 + kz) * 4) * sizeof(T));
+    const unsigned zob = (unsigned)(((long)TX * YZ_SLOT + YZ_SLOT / 2 + (kd * 4 + jy) * 4) * sizeof(T));
+    constexpr unsigned kSlotBytes = YZ_SLOT * sizeof(T);
     T* xout = xf + (((long)(I + 1) * nz + kl) * ny + jl) * 4;
     // psi write-out through the LDS stage (nvalid > 0): pass it of the wave
     // covers the 64 consecutive 16-byte pieces it * 64 + lane of the 16
@@ -954,10 +983,11 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                 store4(pp, o[0], o[1], o[2], o[3]);
                 store4(pp + 4, o[4], o[5], o[6], o[7]);
             }
-            if (ystore) store4(yout0 + s * YZ_SLOT, yo[0], yo[1], yo[2], yo[3]);
-            if (zstore) store4(zout0 + s * YZ_SLOT, zo[0], zo[1], zo[2], zo[3]);
-            if (xstore && ir == len - 1) store4(xout, xin[0], xin[1], xin[2], xin[3]);
         }
+        face_store4<T>(rfz, active && ystore ? yob + (unsigned)s * kSlotBytes : 0x80000000u, yo[0], yo[1], yo[2],
+                       yo[3]);
+        face_store4<T>(rfz, active && zstore ? zob + (unsigned)s * kSlotBytes : 0x80000000u, zo[0], zo[1], zo[2],
+                       zo[3]);
         if constexpr (FUSED) {
             const int wave = threadIdx.x >> 6;
             lds_t<double>* rs = as_lds(red) + ((s % (2 * RF)) * nwaves + wave) * 128;
@@ -969,11 +999,19 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                     dvec2{r0, r1};
             }
             if ((s + 1) % RF == 0 || s == nsteps - 1) {
-                __syncthreads();
+                // LDS only: the waves exchange nothing else inside a launch,
+                // and __syncthreads would also wait for every global access
+                // in flight (the face loads and stores) at each batch
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __builtin_amdgcn_s_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                 // the steps sb .. s of this batch: 128 (pencil, node) sums each
                 const int sb = s - s % RF;
                 const int nwork = (s - sb + 1) * 128;
-                for (int id = threadIdx.x; id < nwork; id += blockDim.x) {
+                // (the block is nwaves waves: blockDim.x would be a load from
+                // the dispatch packet, and its wait would drain every access in
+                // flight)
+                for (int id = threadIdx.x; id < nwork; id += nwaves * 64) {
                     const int sj = sb + (id >> 7), q = (id >> 3) & 15, n = id & 7;
                     const lds_t<double>* rq = as_lds(red) + (sj % (2 * RF)) * nwaves * 128 + q * 8 + n;
                     double sum = 0.0;
@@ -1028,6 +1066,8 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
         step(s, s0, s1);
         if (s + 1 < nsteps) step(s + 1, s1, s0);
     }
+    // the x outflow of the pencil's last cell, which xin holds after its row
+    if (xstore) store4(xout, xin[0], xin[1], xin[2], xin[3]);
 }
 
 // ---------------------------------------------------------------------------
