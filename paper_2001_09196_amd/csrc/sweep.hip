@@ -999,9 +999,8 @@ __device__ __forceinline__ void sweep3d_body(int nx, int ny, int nz, int ndirs, 
                     dvec2{r0, r1};
             }
             if ((s + 1) % RF == 0 || s == nsteps - 1) {
-                // LDS only: the waves exchange nothing else inside a launch,
-                // and __syncthreads would also wait for every global access
-                // in flight (the face loads and stores) at each batch
+                // a barrier ordering LDS only: the waves exchange nothing
+                // else inside a launch
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
                 __builtin_amdgcn_s_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
