@@ -35,9 +35,7 @@ __device__ __forceinline__ int refl(int a, int r, int P) { return r ? P - a : a;
 
 // Workgroup barrier that orders LDS only.  The sweep's global stores (psi)
 // are never read back by the workgroup that wrote them inside a launch, so
-// the barrier between cell diagonals need not wait for them (a full
-// __syncthreads waits for every outstanding global access, about a store's
-// round trip per diagonal).
+// the barrier between cell diagonals orders only the LDS faces.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
